@@ -1,0 +1,416 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks an oracle function against something other than itself:
+explicit Kronecker products, closed forms, an independent eigen-algorithm,
+published known-answer vectors, the Jordan-Wigner reduction, trace
+invariants, and eigen-expansions computed with the independent Jacobi solver.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import _native, central, chebyshev, hamiltonian, jordan_wigner, philox, spectral, subspace
+from paper_2011_02107_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+PAULI = {
+    0: np.eye(2),
+    1: np.array([[0.0, 1.0], [1.0, 0.0]]),
+    2: np.array([[0.0, -1j], [1j, 0.0]]),
+    3: np.array([[1.0, 0.0], [0.0, -1.0]]),
+}
+
+
+def kron_term(L, t):
+    """sigma_{L-1} (x) ... (x) sigma_0 for one term (bit i = spin i, little-endian)."""
+    ops = [PAULI[0]] * L
+    ops[int(t["site_a"])] = PAULI[int(t["op_a"])]
+    if int(t["op_b"]):
+        ops[int(t["site_b"])] = PAULI[int(t["op_b"])]
+    M = np.array([[1.0 + 0j]])
+    for site in range(L - 1, -1, -1):
+        M = np.kron(M, ops[site])
+    return t["coeff"] * M
+
+
+def random_terms(L, rng, n):
+    """Random real one- and two-body terms covering every real op pair."""
+    pairs = [(1, 0), (3, 0), (1, 1), (2, 2), (3, 3), (1, 3), (3, 1)]
+    rows = []
+    for _ in range(n):
+        oa, ob = pairs[rng.integers(len(pairs))]
+        sa = int(rng.integers(L))
+        sb = int(rng.integers(L - 1))
+        if sb >= sa:
+            sb += 1
+        if ob == 0:
+            sb = 0
+        rows.append((oa, sa, ob, sb, rng.uniform(-1, 1)))
+    return inputs.make_terms(rows)
+
+
+# ---------------------------------------------------------------- Hamiltonian
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 6])
+def test_dense_h_matches_kronecker(L):
+    rng = np.random.default_rng(L)
+    terms = random_terms(L, rng, 12) if L > 1 else inputs.make_terms([(1, 0, 0, 0, 0.7), (3, 0, 0, 0, -0.2)])
+    H = hamiltonian.dense_h(L, terms)
+    K = sum(kron_term(L, t) for t in terms)
+    assert np.abs(K.imag).max() < 1e-15
+    assert np.abs(H - K.real).max() < 1e-14
+
+
+@pytest.mark.parametrize("builder", ["chain", "glass", "paper_tfim", "paper_sgs"])
+def test_dense_h_kronecker_model_families(builder):
+    L = 5
+    terms = {
+        "chain": inputs.ising_chain(L),
+        "glass": inputs.spin_glass(L, 3),
+        "paper_tfim": inputs.paper_tfim(L, 4),
+        "paper_sgs": inputs.paper_sgs(L, 5),
+    }[builder]
+    H = hamiltonian.dense_h(L, terms)
+    K = sum(kron_term(L, t) for t in terms).real
+    assert np.abs(H - K).max() < 1e-13
+
+
+def test_imaginary_term_rejected():
+    with pytest.raises(ValueError):
+        hamiltonian.term_masks(2, 0, 0, 0)  # single sigma^y
+    with pytest.raises(ValueError):
+        hamiltonian.term_masks(1, 0, 2, 1)  # X Y
+
+
+@pytest.mark.parametrize("L", [4, 7])
+def test_matrix_free_apply_matches_dense(L):
+    rng = np.random.default_rng(10 + L)
+    terms = random_terms(L, rng, 15)
+    X = rng.standard_normal((1 << L, 3))
+    assert np.abs(hamiltonian.apply_h(L, terms, X) - hamiltonian.dense_h(L, terms) @ X).max() < 1e-12
+
+
+@pytest.mark.parametrize("L", [4, 6, 8])
+def test_trace_invariants(L):
+    """tr H = 0 and tr H^2 = D sum c^2 (Pauli strings are traceless and orthogonal);
+    for the chain, tr H^3 / D = 6 (L-1) J hz^2 (only Z_i Z_{i+1} * Z_i * Z_{i+1} = I)."""
+    D = 1 << L
+    for terms in (inputs.ising_chain(L), inputs.spin_glass(L, L)):
+        H = hamiltonian.dense_h(L, terms)
+        assert abs(np.trace(H)) < 1e-10
+        assert abs(np.trace(H @ H) / D - hamiltonian.sum_sq_coeff(terms)) < 1e-10
+    H = hamiltonian.dense_h(L, inputs.ising_chain(L, J=1.0, hx=1.05, hz=0.5))
+    assert abs(np.trace(H @ H @ H) / D - 6 * (L - 1) * 1.0 * 0.5**2) < 1e-9
+
+
+# ---------------------------------------------------------------- eigensolvers
+
+
+def test_syev_vs_jacobi_random():
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 40, 120):
+        A = rng.standard_normal((n, n))
+        A = A + A.T
+        w, Z = _native.syev(A, vectors=True)
+        wj = _native.jacobi(A)
+        assert np.abs(w - wj).max() < 1e-11 * max(1.0, np.abs(w).max())
+        assert np.abs(A @ Z - Z * w).max() < 1e-12 * max(1.0, np.abs(w).max()) * n
+        assert np.abs(Z.T @ Z - np.eye(n)).max() < 1e-13 * n
+
+
+def test_syev_vs_jacobi_hamiltonian():
+    L = 7
+    H = hamiltonian.dense_h(L, inputs.ising_chain(L))
+    assert np.abs(_native.syev(H) - _native.jacobi(H)).max() < 1e-11
+
+
+def test_two_spin_closed_form():
+    for line in open(os.path.join(GOLDEN, "two_spin_chain.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        J, h, *ref = map(float, line.split())
+        w = central.full_spectrum_dense(2, inputs.ising_chain(2, J=J, hx=h, hz=0.0))
+        assert np.abs(w - np.array(ref)).max() < 1e-14
+
+
+def test_degenerate_and_diagonal_inputs():
+    w = _native.syev(np.diag([3.0, -1.0, 3.0, 0.0]))
+    assert np.array_equal(w, np.array([-1.0, 0.0, 3.0, 3.0]))
+    w = _native.syev(np.zeros((3, 3)))
+    assert np.array_equal(w, np.zeros(3))
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 8])
+def test_jordan_wigner_vs_dense_uniform(L):
+    terms = inputs.ising_chain(L, J=1.0, hx=1.05, hz=0.0)
+    w = central.full_spectrum_dense(L, terms)
+    j = jordan_wigner.full_spectrum(np.ones(L - 1), 1.05 * np.ones(L))
+    assert np.abs(w - j).max() < 1e-12
+
+
+def test_jordan_wigner_vs_dense_disordered():
+    L = 7
+    rng = np.random.default_rng(7)
+    J = rng.uniform(-1, 1, L - 1)
+    h = rng.uniform(-1, 1, L)
+    rows = [(3, i, 3, i + 1, J[i]) for i in range(L - 1)] + [(1, i, 0, 0, h[i]) for i in range(L)]
+    w = central.full_spectrum_dense(L, inputs.make_terms(rows))
+    assert np.abs(w - jordan_wigner.full_spectrum(J, h)).max() < 1e-12
+
+
+def test_jordan_wigner_paper_tfim_mapping():
+    """The paper's (1/4) J X X + (1/2) Gamma Z chain equals the Z Z + X form with
+    J -> J/4, h -> Gamma/2 after exchanging x and z."""
+    L = 6
+    terms = inputs.paper_tfim(L, 11)
+    Jb = np.array([t["coeff"] for t in terms if t["op_b"] == 1])
+    g = np.array([t["coeff"] for t in terms if t["op_b"] == 0])
+    w = central.full_spectrum_dense(L, terms)
+    assert np.abs(w - jordan_wigner.full_spectrum(Jb, g)).max() < 1e-12
+
+
+@pytest.mark.parametrize("L", [6, 9])
+def test_spectral_sums(L):
+    terms = inputs.spin_glass(L, 1)
+    w = central.full_spectrum_dense(L, terms)
+    assert abs(w.sum()) < 1e-9
+    assert abs(np.sum(w * w) - (1 << L) * hamiltonian.sum_sq_coeff(terms)) < 1e-8
+
+
+def test_central_selection_ties_and_order():
+    w = np.array([-2.0, -1.0, -0.5, 0.5, 1.0, 3.0])
+    assert np.array_equal(central.select_central(w, 3), np.array([-1.0, -0.5, 0.5]))
+    # odd N: tie |-1| = |1| broken towards the smaller value
+    assert np.array_equal(central.select_central(w, 3)[0], -1.0)
+    assert np.array_equal(central.select_central(np.array([1.0, -1.0, 0.2]), 2), np.array([-1.0, 0.2]))
+
+
+# ---------------------------------------------------------------- Chebyshev
+
+
+def test_cheb_closed_form_vs_recurrence():
+    x = np.concatenate([np.linspace(-1.3, 1.3, 101), [-1.0, 1.0, 0.0]])
+    for k in (0, 1, 2, 5, 17, 40):
+        assert np.abs(chebyshev.cheb_scalar(k, x) - chebyshev.cheb_scalar_recurrence(k, x)).max() < 1e-9 * max(
+            1.0, np.abs(chebyshev.cheb_scalar(k, x)).max()
+        )
+
+
+def test_cheb_bounded_and_product_identity():
+    """|T_k| <= 1 on [-1, 1] (App. A) and T_i T_j = (T_{i+j} + T_{|i-j|}) / 2 (App. C, Eq. shift)."""
+    x = np.linspace(-1, 1, 2001)
+    for k in (3, 4, 5, 100):
+        assert np.abs(chebyshev.cheb_scalar_recurrence(k, x)).max() <= 1.0 + 1e-12
+    for i, j in ((3, 5), (7, 7), (10, 2), (0, 4)):
+        lhs = chebyshev.cheb_scalar(i, x) * chebyshev.cheb_scalar(j, x)
+        rhs = 0.5 * (chebyshev.cheb_scalar(i + j, x) + chebyshev.cheb_scalar(abs(i - j), x))
+        assert np.abs(lhs - rhs).max() < 1e-12
+
+
+def test_filter_gain_matches_exp_semicircle_shape():
+    """Fig. 1 setting (E_max = 1, k a = 24): inside [-a, a] the filter equals
+    (-1)^k cosh(k theta) and ln|T_k(F(x))| stays within ln 2 + k a^3 of
+    2 k sqrt(a^2 - x^2) (Eq. filter); outside the window |T_k(F)| <= 1."""
+    for a in (0.1, 0.05, 0.025):
+        k = int(round(24 / a))
+        x_in = np.linspace(-a, a, 401)[1:-1]
+        g = chebyshev.filter_gain(k, x_in, 1.0, a)
+        theta = np.arccosh(1 + 2 * (a * a - x_in**2) / (1 - a * a))
+        assert np.allclose(g, (-1.0) ** k * np.cosh(k * theta), rtol=1e-9)
+        dev = np.abs(np.log(np.abs(g)) - 2 * k * np.sqrt(a * a - x_in**2))
+        assert dev.max() <= math.log(2) + k * a**3 + 1e-9
+        x_out = np.concatenate([np.linspace(a, 1, 500), -np.linspace(a, 1, 500)])
+        assert np.abs(chebyshev.filter_gain(k, x_out, 1.0, a)).max() <= 1.0 + 1e-9
+
+
+def _jacobi_eigenpairs(L, terms):
+    return _native.jacobi(hamiltonian.dense_h(L, terms), vectors=True)
+
+
+def test_filter_recurrence_matches_eigen_expansion():
+    """T_K(F) psi = sum_j T_K(F(lambda_j)) <phi_j|psi> phi_j (Sec. II.A, Eq. chevo),
+    eigenpairs from the independent Jacobi solver."""
+    L = 6
+    terms = inputs.ising_chain(L)
+    lam, Phi = _jacobi_eigenpairs(L, terms)
+    e_max = 1.01 * np.abs(lam).max()
+    a = 0.8
+    K = 40
+    psi = np.random.default_rng(1).standard_normal((1 << L, 2))
+    got = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, e_max, a, K, normalise=False)
+    ref = Phi @ (chebyshev.filter_gain(K, lam, e_max, a)[:, None] * (Phi.T @ psi))
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+    normed = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, e_max, a, K)
+    assert np.allclose(np.linalg.norm(normed, axis=0), 1.0)
+    assert np.abs(normed - ref / np.linalg.norm(ref, axis=0)).max() < 1e-10
+
+
+def test_sample_orders_even_and_spaced():
+    for a_r in (0.3, 0.05, 0.0071):
+        ks = chebyshev.sample_orders(a_r, 12)
+        assert all(k % 2 == 0 for k in ks)
+        assert all(abs(k - m * math.pi / a_r) <= 2.0 for m, k in enumerate(ks, 1))
+        assert all(k2 > k1 for k1, k2 in zip(ks, ks[1:]))
+
+
+def test_basis_matches_eigen_expansion():
+    """Columns T_k(G) psi_E = sum_j cos(k arccos(lambda_j / E_max)) <phi_j|psi_E> phi_j (Sec. II.B, Eq. chevo2)."""
+    L = 6
+    terms = inputs.ising_chain(L)
+    lam, Phi = _jacobi_eigenpairs(L, terms)
+    e_max = 1.01 * np.abs(lam).max()
+    a = 1.5
+    psi = np.random.default_rng(2).standard_normal((1 << L, 2))
+    V, ks = chebyshev.chebyshev_basis(lambda X: hamiltonian.apply_h(L, terms, X), psi, e_max, a, 3)
+    b = 2
+    assert V.shape == (1 << L, b * 7)
+    coef = Phi.T @ psi
+    orders = [0] + [k for km in ks for k in (km - 1, km)]
+    for p, k in enumerate(orders):
+        ref = Phi @ (np.cos(k * np.arccos(lam / e_max))[:, None] * coef)
+        assert np.abs(V[:, p * b : (p + 1) * b] - ref).max() < 1e-10 * np.abs(psi).max() * max(1, k)
+
+
+def test_overlap_from_moments_product_identity():
+    """App. C: S_ij = <psi|T_x T_y|psi> = (<psi|T_{x+y}|psi> + <psi|T_{|x-y|}|psi>)/2 and
+    P_ij = (<psi|H T_{x+y}|psi> + <psi|H T_{|x-y|}|psi>)/2, from moments alone."""
+    L = 7
+    terms = inputs.spin_glass(L, 2)
+    apply = lambda X: hamiltonian.apply_h(L, terms, X)
+    lam = central.full_spectrum_dense(L, terms)
+    e_max = 1.01 * np.abs(lam).max()
+    psi = np.random.default_rng(3).standard_normal((1 << L, 1))
+    psi /= np.linalg.norm(psi)
+    V, ks = chebyshev.chebyshev_basis(apply, psi, e_max, 2.0, 4)
+    S, P = subspace.project(apply, V)
+    orders = [0] + [k for km in ks for k in (km - 1, km)]
+    kmax = 2 * max(orders)
+    t_prev, t_cur = psi.copy(), apply(psi) / e_max
+    mom_s = [float(psi[:, 0] @ psi[:, 0]), float(psi[:, 0] @ t_cur[:, 0])]
+    hpsi = apply(psi)
+    mom_h = [float(hpsi[:, 0] @ psi[:, 0]), float(hpsi[:, 0] @ t_cur[:, 0])]
+    for _ in range(2, kmax + 1):
+        t_prev, t_cur = t_cur, 2.0 * apply(t_cur) / e_max - t_prev
+        mom_s.append(float(psi[:, 0] @ t_cur[:, 0]))
+        mom_h.append(float(hpsi[:, 0] @ t_cur[:, 0]))
+    for i, x in enumerate(orders):
+        for j, y in enumerate(orders):
+            assert abs(S[i, j] - 0.5 * (mom_s[x + y] + mom_s[abs(x - y)])) < 1e-9
+            assert abs(P[i, j] - 0.5 * (mom_h[x + y] + mom_h[abs(x - y)])) < 1e-8
+
+
+# ---------------------------------------------------------------- subspace diagonalisation
+
+
+def test_rayleigh_ritz_exact_eigenvectors():
+    """With V = a set of exact eigenvectors, S = I and the Ritz values are the eigenvalues."""
+    L = 6
+    terms = inputs.ising_chain(L)
+    lam, Phi = _jacobi_eigenpairs(L, terms)
+    sel = np.arange(20, 31)
+    V = Phi[:, sel]
+    S, P = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
+    assert np.abs(S - np.eye(len(sel))).max() < 1e-12
+    theta, B, r = subspace.rayleigh_ritz(S, P)
+    assert r == len(sel)
+    assert np.abs(theta - lam[sel]).max() < 1e-12
+
+
+def test_rayleigh_ritz_overcomplete_invariant_subspace():
+    """A redundant basis of an invariant subspace (singular S) still gives the exact
+    eigenvalues once the S eigenvalues below epsilon are dropped (App. C)."""
+    L = 6
+    terms = inputs.spin_glass(L, 9)
+    lam, Phi = _jacobi_eigenpairs(L, terms)
+    rng = np.random.default_rng(4)
+    sel = np.arange(25, 37)
+    core = Phi[:, sel] @ rng.standard_normal((len(sel), len(sel)))
+    V = np.concatenate([core, core[:, :5] @ rng.standard_normal((5, 4))], axis=1)
+    S, P = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
+    theta, B, r = subspace.rayleigh_ritz(S, P)
+    assert r == len(sel)
+    assert np.abs(np.sort(theta) - lam[sel]).max() < 1e-10
+    rn, _ = subspace.residual_norms(lambda X: hamiltonian.apply_h(L, terms, X), V, B, theta)
+    assert rn.max() < 1e-9
+
+
+def test_neighbour_gaps():
+    g = subspace.neighbour_gaps(np.array([0.0, 1.0, 3.0, 3.5]))
+    assert np.array_equal(g, np.array([1.0, 1.0, 0.5, 0.5]))
+
+
+# ---------------------------------------------------------------- random numbers
+
+
+def test_philox_known_answers():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        out = philox.philox4x32_10(*v[:6])
+        assert [int(o) for o in out] == v[6:]
+
+
+def test_gaussian_block_statistics():
+    z = philox.gaussian_block(1 << 14, 4, seed=12345)
+    assert z.shape == (1 << 14, 4)
+    assert abs(z.mean()) < 0.03 and abs(z.std() - 1.0) < 0.03
+    # distinct columns and rows are distinct streams
+    assert abs(np.corrcoef(z[:, 0], z[:, 1])[0, 1]) < 0.05
+
+
+# ---------------------------------------------------------------- bounds and density
+
+
+def test_lanczos_bound_is_upper_bound():
+    for L, terms in ((8, inputs.ising_chain(8)), (8, inputs.spin_glass(8, 5)), (9, inputs.paper_sgs(9, 1))):
+        D = 1 << L
+        w = central.full_spectrum_dense(L, terms)
+        norm = max(-w[0], w[-1])
+        al, be = spectral.lanczos(lambda X: hamiltonian.apply_h(L, terms, X), np.random.default_rng(0).standard_normal(D), 60)
+        eb, theta = spectral.lanczos_bound(al, be, hamiltonian.sum_abs_coeff(terms))
+        assert eb >= norm
+        assert eb <= 1.05 * norm
+        assert theta[0] >= w[0] - 1e-9 and theta[-1] <= w[-1] + 1e-9
+
+
+def test_kpm_exact_trace_and_count():
+    """With R = identity the moments are exactly tr T_k(G)/D; the Jackson-damped
+    count over a wide window tracks the exact count (kernel polynomial method)."""
+    L = 8
+    terms = inputs.ising_chain(L)
+    D = 1 << L
+    w = central.full_spectrum_dense(L, terms)
+    e_b = 1.01 * np.abs(w).max()
+    mu = spectral.kpm_moments(lambda X: hamiltonian.apply_h(L, terms, X), np.eye(D), e_b, 64)
+    for k in (0, 1, 7, 30):
+        assert abs(mu[k] - np.mean(chebyshev.cheb_scalar(k, w / e_b))) < 1e-12
+    mu = spectral.kpm_moments(lambda X: hamiltonian.apply_h(L, terms, X), np.eye(D), e_b, 256)
+    for a_r in (0.1, 0.2, 0.4):
+        exact = np.sum(np.abs(w) <= a_r * e_b)
+        assert abs(spectral.kpm_count(mu, D, a_r) - exact) <= 0.08 * exact + 3
+    a_r = spectral.window_for_count(mu, D, 60)
+    assert abs(spectral.kpm_count(mu, D, a_r) - 60) < 1e-6
+
+
+def test_jackson_kernel_limits():
+    g = spectral.jackson(50)
+    assert abs(g[0] - 1.0) < 1e-12
+    assert np.all(np.diff(g) < 0) and g[-1] > 0
+
+
+# ---------------------------------------------------------------- plain definition
+
+
+@pytest.mark.slow
+def test_central_eigenvalues_jw_twin_l12():
+    L, N = 12, 150
+    terms = inputs.ising_chain(L, hz=0.0)
+    got, norm = central.central_eigenvalues(L, terms, N)
+    ref, norm_jw = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
+    assert abs(norm - norm_jw) < 1e-10
+    assert np.abs(got - ref).max() <= 1e-10 * norm
