@@ -1,0 +1,176 @@
+"""Benchmark: central eigenvalues per second of the DACP path on one MI355X.
+
+A step is one dacp_central_eigs call (bound + window, filter, evolution,
+projection, subspace diagonalisation, acceptance) on the chaotic Ising chain
+H = sum Z_i Z_{i+1} + 1.05 sum X_i + 0.5 sum Z_i.  Default workload: L = 20
+(D = 2^20), N = 5000 central eigenvalues.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "central eigenvalues/sec at L=20 (err≤1e-10) + filter HBM GB/s, plain vs tuned"
+WORKLOADS = {
+    "chain_L20_N5000": dict(L=20, N=5000, b=64),
+    "chain_L16_N1000": dict(L=16, N=1000, b=64),
+    "chain_L14_N500": dict(L=14, N=500, b=16),
+    "chain_L10_N100": dict(L=10, N=100, b=4),
+}
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="chain_L20_N5000", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="plain", choices=["plain", "tuned"])
+    ap.add_argument("--kfac", type=float, default=None)
+    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    return ap.parse_args()
+
+
+def opts_for(args, wl):
+    from paper_2011_02107_amd import binding as B
+
+    if args.mode == "plain":
+        o = B.default_opts(b=wl["b"], kfac=18.0, window_ratio=2.2, precision=B.DACP_F64, group=args.group)
+    else:
+        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=1.8, precision=B.DACP_F32, fp64_tail_frac=0.2,
+                           group=args.group)
+    if args.kfac:
+        o.kfac = args.kfac
+    return o
+
+
+def cpu_baseline(wl, rep, steps):
+    """The oracle's matrix-free apply timed on a bounded sample of the same
+    workload (`steps` applies on the L, b block), scaled to the run's total
+    apply count (2K filter + evolution steps x column groups); projection and
+    the subspace solve are not counted (so the CPU figure is optimistic)."""
+    import numpy as np
+
+    from oracle import hamiltonian
+    from paper_2011_02107_amd import inputs
+
+    L, b = wl["L"], rep["b"]
+    terms = inputs.ising_chain(L)
+    X = np.random.default_rng(0).standard_normal((1 << L, b))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X = hamiltonian.apply_h(L, terms, X) / 40.0
+    dt = (time.perf_counter() - t0) / steps
+    applies = 2 * rep["K"] + rep["evol_steps"]
+    total_s = applies * dt
+    return {
+        "value": wl["N"] / total_s,
+        "unit": "eigenvalues/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} oracle matrix-free applies (numpy, L={L}, b={b}) at {dt:.2f} s each, "
+        f"scaled to {applies} applies of the run; projection and subspace solve excluded",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    wl = WORKLOADS[args.workload]
+    L, N = wl["L"], wl["N"]
+    terms = inputs.ising_chain(L)
+    ctx = B.Context(0)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    opts = opts_for(args, wl)
+    # load every kernel once on a tiny problem (not a timed step)
+    small = B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8))
+    B.dacp_central_eigs(ctx, small, 20, B.default_opts(b=4), raise_on_window=False)
+    small.close()
+    for _ in range(args.warmup):
+        B.dacp_central_eigs(ctx, ham, N, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    n_ok = 0
+    for _ in range(args.steps):
+        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
+        reps.append(rep)
+        n_ok += len(eigs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rep = reps[-1]
+    D = 1 << L
+    g = args.group if 0 < args.group < rep["b"] else rep["b"]
+    # evolution kernel: reads T_k and T_{k-1}, writes T_{k+1}: 3 D g 8 algorithmic bytes per launch
+    bytes_per_launch = 3.0 * D * g * 8
+    evol_launch_ms = rep["evol_kernel_ms"] / max(1, rep["evol_launches"])
+    achieved = bytes_per_launch / (evol_launch_ms * 1e-3) / 1e9
+    # filter: 2 launches per order; per order 5 D b s algorithmic bytes (w round trip included)
+    s_bytes = 4 if opts.precision == B.DACP_F32 else 8
+    filter_gbps = 5.0 * D * rep["b"] * s_bytes * rep["K"] / (rep["t_filter_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": n_ok / dt,
+        "unit": "eigenvalues/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if opts.precision == B.DACP_F64 else "f32-filter+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "hamiltonian": "sum Z_i Z_i+1 + 1.05 sum X_i + 0.5 sum Z_i, open chain",
+            "L": L,
+            "N": N,
+            "mode": args.mode,
+            "b": rep["b"],
+            "group": g,
+            "K": rep["K"],
+            "m": rep["m"],
+            "rank": rep["rank"],
+            "evol_steps": rep["evol_steps"],
+            "acceptance": "Kato-Temple residual estimate <= 1e-10 ||H|| (no oracle at this size)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_step<double, *, 2> (evolution recurrence)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "avg_launch_ms": evol_launch_ms,
+            "bytes_per_launch": bytes_per_launch,
+        },
+        "stages_ms": {k: rep[k] for k in ("t_bound_ms", "t_filter_ms", "t_evol_ms", "t_project_ms", "t_gep_ms",
+                                          "t_accept_ms", "t_total_ms")},
+        "filter_algorithmic_GBps": filter_gbps,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, rep, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

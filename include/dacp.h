@@ -1,0 +1,237 @@
+/*
+ * dacp.h -- C ABI of the MI355X (gfx950) DACP central-eigenvalue library.
+ *
+ * DACP (dual application of Chebyshev polynomial, Guan & Zhang): given the
+ * couplings of a spin-1/2 Hamiltonian made of one- and two-body Pauli terms
+ * and a count N, return the N eigenvalues nearest the band centre E = 0
+ * (problem statement: Sec. II opening and Sec. III).  The path is
+ *   bound + window  ->  exp-semicircle filter (Sec. II.A)
+ *   ->  Chebyshev evolution basis (Sec. II.B, App. B)
+ *   ->  projection S, P (Sec. II.C, Eq. gep)
+ *   ->  subspace diagonalisation (App. C)  ->  residual acceptance (Sec. II.C).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns dacp_status (0 = OK, < 0 = error); no exception
+ *     crosses the ABI.  dacp_last_error(ctx) gives a message for the last
+ *     failure on that context.
+ *   - "device" pointers are HIP device memory on the context's device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes; handles (dacp_ctx, dacp_ham) are owned by the library and freed
+ *     by dacp_destroy / dacp_free_hamiltonian.
+ *   - Device work is enqueued on the context's stream.  A call that returns
+ *     host data synchronises that stream before returning; a call that only
+ *     writes device outputs may return before the work completes.
+ *   - On error the outputs are unspecified unless stated otherwise.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - Basis convention: bit i of a state index s is spin i,
+ *     sigma^z |b> = (1 - 2b) |b>.  D = 2^L.
+ *   - Blocks of b states are stored row-major [D][b] with a row stride ld >= b
+ *     (element (s, j) at base[s * ld + j]); all matrices are row-major.
+ */
+#ifndef DACP_H
+#define DACP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DACP_OK = 0,
+  DACP_E_INVALID = -1,     /* bad argument (message says which)                        */
+  DACP_E_NOMEM = -2,       /* device or host allocation failed                         */
+  DACP_E_HIP = -3,         /* a HIP runtime call failed                                */
+  DACP_E_BOUNDS = -4,      /* spectral bound below ||H|| detected (|T_k(G)| grew > 1)  */
+  DACP_E_WINDOW = -5,      /* fewer than N eigenvalues accepted in the window          */
+  DACP_E_NUMERIC = -6,     /* NaN/Inf, or the overlap matrix S lost all rank           */
+  DACP_E_CONVERGENCE = -7  /* the dense eigensolver did not converge                   */
+} dacp_status;
+
+typedef enum { DACP_F64 = 0, DACP_F32 = 1 } dacp_dtype;
+
+/* Pauli operator codes for dacp_term.op_a / op_b. */
+enum { DACP_I = 0, DACP_X = 1, DACP_Y = 2, DACP_Z = 3 };
+
+/* One real term c * sigma^{op_a}_{site_a} sigma^{op_b}_{site_b} (Sec. III: each
+ * Pauli operator or product of two is one function on states).  op_b = DACP_I
+ * for a one-body term (site_b ignored).  A term with an odd number of Y
+ * factors is imaginary and rejected.  16 bytes. */
+typedef struct {
+  uint8_t op_a, op_b;
+  uint16_t site_a, site_b;
+  uint16_t reserved; /* must be 0 */
+  double coeff;
+} dacp_term;
+
+typedef struct dacp_ctx_s *dacp_ctx;
+typedef struct dacp_ham_s *dacp_ham;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (may be NULL for the null stream); it is not owned by the library. */
+dacp_status dacp_create(int device, void *hip_stream, dacp_ctx *out);
+void dacp_destroy(dacp_ctx ctx);
+const char *dacp_last_error(dacp_ctx ctx);
+/* Replace the stream used by later calls on `ctx`. */
+dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream);
+/* Library version string (static storage). */
+const char *dacp_version(void);
+
+/* -------------------------------------------------------------- Hamiltonian */
+
+/* Build device tables for H = sum_t coeff_t P_t from host `terms` (Sec. III,
+ * model definitions).  One-body and two-body terms of any real Pauli type are
+ * accepted.  Equal Pauli strings are merged.  Errors (DACP_E_INVALID):
+ * L outside [1, 30], a site >= L, site_a == site_b in a two-body term, an odd
+ * number of Y, reserved != 0, a non-finite coefficient. */
+dacp_status dacp_build_hamiltonian(dacp_ctx ctx, int L, int n_terms, const dacp_term *terms, dacp_ham *out);
+void dacp_free_hamiltonian(dacp_ham h);
+/* Host query: number of spins, sum |c| (triangle bound on ||H||), sum c^2
+ * (= tr H^2 / D), number of off-diagonal flip groups. */
+dacp_status dacp_ham_info(dacp_ham h, int *L, double *sum_abs, double *sum_sq, int *n_flip_groups);
+
+/* y = H x on [D][b] blocks (device), dtype DACP_F64 or DACP_F32 for both x and
+ * y, row strides ldx, ldy >= b.  x and y must not overlap.  This is the
+ * matrix-free basic step of Sec. II (the paper's tau). */
+dacp_status dacp_apply(dacp_ctx ctx, dacp_ham h, int dtype, int b, const void *x, int64_t ldx, void *y, int64_t ldy);
+
+/* ------------------------------------------------------ bound and density */
+
+/* Spectral bound E_b >= ||H|| (Sec. III: upper-bound estimator for E_max).
+ * `steps`-step Lanczos from device vector v0 (length D, FP64; NULL draws a
+ * seeded Gaussian vector), E_b = safety * max(|theta_max| + r_max,
+ * |theta_min| + r_min) with r the Ritz residual norms |beta_k y_k|, clamped to
+ * sum |c|.  Host outputs: e_bound, theta_min, theta_max (any may be NULL). */
+dacp_status dacp_spectral_bound(dacp_ctx ctx, dacp_ham h, int steps, const double *v0, uint64_t seed, double safety,
+                                double *e_bound, double *theta_min, double *theta_max);
+
+/* Chebyshev moments mu_k = <R, T_k(H / e_bound) R> / <R, R>, k < n_moments
+ * (kernel polynomial estimate of the density of states; Sec. III sets the
+ * window from a density estimate).  R: device [D][nvec] FP64 or NULL for a
+ * seeded Gaussian block.  Uses T_{2k} = 2 T_k^2 - T_0 and
+ * T_{2k+1} = 2 T_{k+1} T_k - T_1 (App. C, Eq. shift).  mu_out: host. */
+dacp_status dacp_dos_moments(dacp_ctx ctx, dacp_ham h, double e_bound, int n_moments, int nvec, const double *R,
+                             uint64_t seed, double *mu_out);
+
+/* Seeded start states: out[s * b + j] ~ N(0,1) from Philox4x32-10 with counter
+ * (s, j, 0, 0) and key (seed_lo, seed_hi); u1, u2 from the top 53 bits of
+ * (r0:r1), (r2:r3) plus half an ulp; z = sqrt(-2 ln u1) cos(2 pi u2).
+ * out: device [D][b] FP64. */
+dacp_status dacp_random_block(dacp_ctx ctx, int64_t D, int b, uint64_t seed, double *out);
+
+/* ---------------------------------------------------------------- filter */
+
+typedef struct {
+  double e_bound;    /* E_max of Eq. F; must be >= ||H||                         */
+  double a;          /* window half-width, 0 < a < e_bound                       */
+  int K;             /* filter order (Sec. II.A uses 18 E_max / a)               */
+  int b;             /* block width (number of start states, Sec. III block filter) */
+  int precision;     /* DACP_F64, or DACP_F32: first K - fp64_tail steps in FP32 */
+  int fp64_tail;     /* FP64 steps after the FP32 part (precision = DACP_F32)    */
+  uint64_t seed;     /* used when `start` is NULL                                */
+} dacp_filter_params;
+
+/* psi_E = T_K(F) psi, F = (H^2 - E_c) / E_0, E_c = (E_b^2 + a^2)/2,
+ * E_0 = (E_b^2 - a^2)/2, every column normalised to 1 (Sec. II.A, Eq. F,
+ * Eq. target).  start: device [D][b] FP64 or NULL (seeded Gaussian).
+ * psi_out: device [D][b] FP64.  With precision DACP_F32 the first
+ * K - fp64_tail steps of the same recurrence run in FP32 (FP32 storage and
+ * accumulation); the pair (T_{k-1}, T_k) is then converted to FP64 and the
+ * last fp64_tail steps run in FP64.  Start and output must not overlap. */
+dacp_status dacp_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, const double *start, double *psi_out);
+
+/* ----------------------------------------------------------------- basis */
+
+typedef struct {
+  double e_bound; /* G = H / e_bound (Sec. II.B, Eq. G2)                       */
+  double a;       /* a_r = a / e_bound                                         */
+  int n;          /* number of sample pairs; basis width m = b (2n + 1)        */
+  int b;          /* block width                                               */
+  int group;      /* evolve columns in groups of this width (0 = all b)        */
+} dacp_basis_params;
+
+/* Chebyshev evolution T_{k+1} = 2 G T_k - T_{k-1} from psi_E (device [D][b]
+ * FP64) up to k_n, storing panels (App. C, Eq. set2)
+ *   panel 0 = psi_E, panel 2m-1 = T_{k_m - 1}(G) psi_E, panel 2m = T_{k_m}(G) psi_E,
+ * k_m = 2 floor(m pi / (2 a_r)), m = 1..n, panel p in columns [p b, p b + b)
+ * of V (device, row-major D x ldv, ldv >= b (2n + 1)).  m_out (host) gets
+ * b (2n + 1).  Returns DACP_E_BOUNDS if the evolved norm exceeds the start
+ * norm by more than 1e-6 relative (|T_k(G)| <= 1 must hold for e_bound >= ||H||). */
+dacp_status dacp_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *V,
+                       int64_t ldv, int *m_out);
+
+/* ------------------------------------------------------------ projection */
+
+/* S = V^T V and P = V^T (H V) (Sec. II.C, Eq. gep) for the first m columns
+ * of V (device, row-major D x ldv).  S, P: device m x m row-major with
+ * leading dimension ld >= m, both triangles written.  FP64 throughout. */
+dacp_status dacp_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
+                         int64_t ld);
+
+/* Generalised eigenproblem P B = S B Lambda by App. C: S = V_s L_s V_s^T,
+ * drop eigenvalues below eps (1e-12 in the paper), U = V~_s L~_s^(-1/2),
+ * H~ = U^T P U, H~ = Y Lambda Y^T, B = U Y.  S and P: device m x m (ld),
+ * read only.  theta_out: host, r ascending Ritz values; B_out: device r x m
+ * row-major (row j = column j of B), may be NULL; r_out: host rank kept. */
+dacp_status dacp_rayleigh_ritz(dacp_ctx ctx, int m, const double *S, const double *P, int64_t ld, double eps,
+                               double *theta_out, double *B_out, int *r_out);
+
+/* Dense symmetric eigen-decomposition on the GPU (Householder
+ * tridiagonalisation, implicit QL): A device n x n (ld), destroyed;
+ * w host ascending; Zrows device n x n (row j = eigenvector j) or NULL. */
+dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
+
+/* C = alpha op(A) op(B) + beta C in FP64 on the matrix cores (row-major;
+ * op(A) is M x K: A stored M x K when transA = 0, K x M when transA = 1;
+ * op(B) is K x N: B stored K x N when transB = 0, N x K when transB = 1). */
+dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc);
+
+/* ------------------------------------------------------------- end to end */
+
+typedef struct {
+  int b;               /* block width (default 64)                                    */
+  int group;           /* evolution column-group width, 0 = b                         */
+  double kfac;         /* K = ceil(kfac * E_b / a) (default 18, Sec. II.A)            */
+  double window_ratio; /* levels wanted in [-a, a] = ceil(window_ratio * N) (2.2)     */
+  double basis_ratio;  /* m = b (2n + 1) ~ basis_ratio * window count (1.5)           */
+  double eps;          /* S eigenvalue cut-off (1e-12, App. C)                        */
+  double tol_rel;      /* accept |error| <= tol_rel * E_b (1e-10)                     */
+  int lanczos_steps;   /* bound estimator steps (80)                                  */
+  int kpm_moments;     /* density moments (256)                                       */
+  int kpm_vectors;     /* random vectors for the density (8)                          */
+  double e_bound;      /* > 0: use this bound and skip Lanczos                        */
+  double a;            /* > 0: use this window and skip the density estimate          */
+  int precision;       /* filter precision: DACP_F64 or DACP_F32                      */
+  double fp64_tail_frac; /* FP64 tail steps = ceil(frac * K) when precision is FP32  */
+  uint64_t seed;       /* start-state seed                                            */
+  int max_retries;     /* window retries on DACP_E_WINDOW (1)                         */
+} dacp_opts;
+
+typedef struct {
+  double e_bound, a, a_r;
+  int K, n, b, m, rank, n_candidates, n_accepted, retries;
+  int64_t evol_steps;       /* recurrence steps of the evolution (per column group) */
+  int64_t evol_launches;    /* evolution kernel launches                            */
+  double t_bound_ms, t_filter_ms, t_evol_ms, t_project_ms, t_gep_ms, t_accept_ms, t_total_ms;
+  double evol_kernel_ms;    /* HIP-event time of the evolution launches only        */
+  double max_err_est;       /* largest accepted error estimate                      */
+} dacp_report;
+
+/* Fill `opts` with the defaults listed above. */
+void dacp_default_opts(dacp_opts *opts);
+
+/* The N eigenvalues of H nearest 0, ascending (host eigs_out[N]); err_out
+ * (host, may be NULL) gets the residual error estimate of each
+ * (Kato-Temple ||r||^2 / gap, or ||r|| when smaller); n_out gets N on success
+ * or, on DACP_E_WINDOW, the number accepted.  report may be NULL. */
+dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
+                              double *err_out, int *n_out, dacp_report *report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DACP_H */

@@ -1,0 +1,337 @@
+"""Thin ctypes binding over libdacp.so (the C ABI declared in include/dacp.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Device buffers are torch tensors on a ROCm device (their data pointers are
+passed through); host outputs come back as numpy arrays.  The binding raises
+if the compiled library is missing -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .inputs import TERM_DTYPE
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdacp.so")
+
+DACP_F64, DACP_F32 = 0, 1
+STATUS = {
+    0: "DACP_OK",
+    -1: "DACP_E_INVALID",
+    -2: "DACP_E_NOMEM",
+    -3: "DACP_E_HIP",
+    -4: "DACP_E_BOUNDS",
+    -5: "DACP_E_WINDOW",
+    -6: "DACP_E_NUMERIC",
+    -7: "DACP_E_CONVERGENCE",
+}
+
+
+class DacpError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class FilterParams(ctypes.Structure):
+    _fields_ = [
+        ("e_bound", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("K", ctypes.c_int),
+        ("b", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("fp64_tail", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class BasisParams(ctypes.Structure):
+    _fields_ = [
+        ("e_bound", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("n", ctypes.c_int),
+        ("b", ctypes.c_int),
+        ("group", ctypes.c_int),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("b", ctypes.c_int),
+        ("group", ctypes.c_int),
+        ("kfac", ctypes.c_double),
+        ("window_ratio", ctypes.c_double),
+        ("basis_ratio", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("tol_rel", ctypes.c_double),
+        ("lanczos_steps", ctypes.c_int),
+        ("kpm_moments", ctypes.c_int),
+        ("kpm_vectors", ctypes.c_int),
+        ("e_bound", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("fp64_tail_frac", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("max_retries", ctypes.c_int),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("e_bound", ctypes.c_double),
+        ("a", ctypes.c_double),
+        ("a_r", ctypes.c_double),
+        ("K", ctypes.c_int),
+        ("n", ctypes.c_int),
+        ("b", ctypes.c_int),
+        ("m", ctypes.c_int),
+        ("rank", ctypes.c_int),
+        ("n_candidates", ctypes.c_int),
+        ("n_accepted", ctypes.c_int),
+        ("retries", ctypes.c_int),
+        ("evol_steps", ctypes.c_int64),
+        ("evol_launches", ctypes.c_int64),
+        ("t_bound_ms", ctypes.c_double),
+        ("t_filter_ms", ctypes.c_double),
+        ("t_evol_ms", ctypes.c_double),
+        ("t_project_ms", ctypes.c_double),
+        ("t_gep_ms", ctypes.c_double),
+        ("t_accept_ms", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double),
+        ("evol_kernel_ms", ctypes.c_double),
+        ("max_err_est", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+# name -> (restype, argtypes); mirrors include/dacp.h
+SIGNATURES = {
+    "dacp_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "dacp_destroy": (None, [_vp]),
+    "dacp_last_error": (ctypes.c_char_p, [_vp]),
+    "dacp_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "dacp_version": (ctypes.c_char_p, []),
+    "dacp_build_hamiltonian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "dacp_free_hamiltonian": (None, [_vp]),
+    "dacp_ham_info": (ctypes.c_int, [_vp, _ip, _dp, _dp, _ip]),
+    "dacp_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _i64, _vp, _i64]),
+    "dacp_spectral_bound": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_uint64, ctypes.c_double, _dp, _dp, _dp]),
+    "dacp_dos_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_uint64, _dp]),
+    "dacp_random_block": (ctypes.c_int, [_vp, _i64, ctypes.c_int, ctypes.c_uint64, _vp]),
+    "dacp_filter": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(FilterParams), _vp, _vp]),
+    "dacp_basis": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(BasisParams), _vp, _vp, _i64, _ip]),
+    "dacp_project": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i64, _vp, _vp, _i64]),
+    "dacp_rayleigh_ritz": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, ctypes.c_double, _dp, _vp, _ip]),
+    "dacp_syev": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _dp, _vp]),
+    "dacp_gemm": (
+        ctypes.c_int,
+        [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _vp, _i64, ctypes.c_double, _vp, _i64],
+    ),
+    "dacp_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "dacp_central_eigs": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)]),
+}
+
+_lib = None
+
+
+def load_library():
+    """Load libdacp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() (there is no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(x):
+    return x.ctypes.data_as(_dp)
+
+
+class Context:
+    """A library context bound to a device and a HIP stream (torch's current one by default)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+
+        self.lib = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = _vp()
+        st = self.lib.dacp_create(int(device), _vp(stream), ctypes.byref(h))
+        if st != 0:
+            raise DacpError(st, "dacp_create failed")
+        self.handle = h
+        self.device = device
+
+    def check(self, st):
+        if st != 0:
+            raise DacpError(st, self.lib.dacp_last_error(self.handle).decode())
+
+    def close(self):
+        if self.handle:
+            self.lib.dacp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    def __init__(self, ctx, handle, L):
+        self.ctx = ctx
+        self.handle = handle
+        self.L = L
+        self.D = 1 << L
+
+    def info(self):
+        L = ctypes.c_int()
+        sa = ctypes.c_double()
+        sq = ctypes.c_double()
+        nf = ctypes.c_int()
+        self.ctx.check(self.ctx.lib.dacp_ham_info(self.handle, ctypes.byref(L), ctypes.byref(sa), ctypes.byref(sq), ctypes.byref(nf)))
+        return {"L": L.value, "sum_abs": sa.value, "sum_sq": sq.value, "n_flip_groups": nf.value}
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.dacp_free_hamiltonian(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dacp_build_hamiltonian(ctx, L, terms):
+    terms = np.ascontiguousarray(np.asarray(terms, dtype=TERM_DTYPE))
+    h = _vp()
+    ctx.check(ctx.lib.dacp_build_hamiltonian(ctx.handle, int(L), len(terms), terms.ctypes.data_as(_vp), ctypes.byref(h)))
+    return Hamiltonian(ctx, h, L)
+
+
+def dacp_apply(ctx, ham, x, y):
+    import torch
+
+    dtype = {torch.float64: DACP_F64, torch.float32: DACP_F32}[x.dtype]
+    assert y.dtype == x.dtype and x.shape == y.shape and x.shape[0] == ham.D
+    b = 1 if x.dim() == 1 else x.shape[1]
+    ctx.check(ctx.lib.dacp_apply(ctx.handle, ham.handle, dtype, b, _ptr(x), b, _ptr(y), b))
+
+
+def dacp_random_block(ctx, D, b, seed, out):
+    ctx.check(ctx.lib.dacp_random_block(ctx.handle, int(D), int(b), int(seed), _ptr(out)))
+
+
+def dacp_spectral_bound(ctx, ham, steps=80, v0=None, seed=0, safety=1.01):
+    eb, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    ctx.check(
+        ctx.lib.dacp_spectral_bound(
+            ctx.handle, ham.handle, int(steps), _ptr(v0), int(seed), float(safety), ctypes.byref(eb), ctypes.byref(lo), ctypes.byref(hi)
+        )
+    )
+    return eb.value, lo.value, hi.value
+
+
+def dacp_dos_moments(ctx, ham, e_bound, n_moments, nvec=8, R=None, seed=0):
+    mu = np.zeros(n_moments)
+    ctx.check(ctx.lib.dacp_dos_moments(ctx.handle, ham.handle, float(e_bound), int(n_moments), int(nvec), _ptr(R), int(seed), _f64(mu)))
+    return mu
+
+
+def dacp_filter(ctx, ham, psi_out, e_bound, a, K, start=None, precision=DACP_F64, fp64_tail=0, seed=0):
+    p = FilterParams(float(e_bound), float(a), int(K), int(psi_out.shape[1]), int(precision), int(fp64_tail), int(seed))
+    ctx.check(ctx.lib.dacp_filter(ctx.handle, ham.handle, ctypes.byref(p), _ptr(start), _ptr(psi_out)))
+
+
+def dacp_basis(ctx, ham, psi_e, V, e_bound, a, n, group=0):
+    b = int(psi_e.shape[1])
+    p = BasisParams(float(e_bound), float(a), int(n), b, int(group))
+    m = ctypes.c_int()
+    ctx.check(ctx.lib.dacp_basis(ctx.handle, ham.handle, ctypes.byref(p), _ptr(psi_e), _ptr(V), int(V.shape[1]), ctypes.byref(m)))
+    return m.value
+
+
+def dacp_project(ctx, ham, V, S, P, m=None):
+    m = int(V.shape[1]) if m is None else int(m)
+    ctx.check(ctx.lib.dacp_project(ctx.handle, ham.handle, m, _ptr(V), int(V.shape[1]), _ptr(S), _ptr(P), int(S.shape[1])))
+
+
+def dacp_rayleigh_ritz(ctx, S, P, eps=1e-12, B_out=None):
+    m = int(S.shape[0])
+    theta = np.zeros(m)
+    r = ctypes.c_int()
+    ctx.check(ctx.lib.dacp_rayleigh_ritz(ctx.handle, m, _ptr(S), _ptr(P), int(S.shape[1]), float(eps), _f64(theta), _ptr(B_out), ctypes.byref(r)))
+    return theta[: r.value], r.value
+
+
+def dacp_syev(ctx, A, Z=None):
+    n = int(A.shape[0])
+    w = np.zeros(n)
+    ctx.check(ctx.lib.dacp_syev(ctx.handle, n, _ptr(A), int(A.shape[1]), _f64(w), _ptr(Z)))
+    return w
+
+
+def dacp_gemm(ctx, transA, transB, A, B, C, alpha=1.0, beta=0.0):
+    M, N = C.shape
+    K = A.shape[0] if transA else A.shape[1]
+    ctx.check(
+        ctx.lib.dacp_gemm(
+            ctx.handle, int(transA), int(transB), M, N, K, float(alpha), _ptr(A), A.shape[1], _ptr(B), B.shape[1], float(beta), _ptr(C), C.shape[1]
+        )
+    )
+
+
+def default_opts(**overrides):
+    o = Opts()
+    load_library().dacp_default_opts(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def dacp_central_eigs(ctx, ham, N, opts=None, raise_on_window=True):
+    """Returns (eigs ascending, error estimates, report dict, status)."""
+    if opts is None:
+        opts = default_opts()
+    eigs = np.zeros(N)
+    errs = np.zeros(N)
+    n_out = ctypes.c_int()
+    rep = Report()
+    st = ctx.lib.dacp_central_eigs(ctx.handle, ham.handle, int(N), ctypes.byref(opts), _f64(eigs), _f64(errs), ctypes.byref(n_out), ctypes.byref(rep))
+    if st != 0 and (raise_on_window or st != -5):
+        ctx.check(st)
+    n = n_out.value if st == 0 else 0
+    return eigs[:n], errs[:n], rep.as_dict(), st

@@ -1,0 +1,1006 @@
+// C ABI and host drivers of the DACP central-eigenvalue path (gfx950).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using dacp::DevBuf;
+using dacp::FlipEntry;
+using dacp::StepArgs;
+
+namespace dacp {
+
+dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+dacp_status hip_err(dacp_ctx ctx, hipError_t e, const char *what) {
+  const dacp_status st = (e == hipErrorOutOfMemory) ? DACP_E_NOMEM : DACP_E_HIP;
+  return set_err(ctx, st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace dacp
+
+using dacp::hip_err;
+using dacp::set_err;
+
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+dacp_status ensure_red(dacp_ctx ctx, size_t partial_elems, size_t out_elems) {
+  if (partial_elems > ctx->red_elems) {
+    if (ctx->red) (void)hipFree(ctx->red);
+    ctx->red = nullptr;
+    DACP_HIP(ctx, hipMalloc(&ctx->red, partial_elems * sizeof(double)));
+    ctx->red_elems = partial_elems;
+  }
+  if (out_elems > ctx->red_out_elems) {
+    if (ctx->red_out) (void)hipFree(ctx->red_out);
+    ctx->red_out = nullptr;
+    DACP_HIP(ctx, hipMalloc(&ctx->red_out, out_elems * sizeof(double)));
+    ctx->red_out_elems = out_elems;
+  }
+  return DACP_OK;
+}
+
+// Per-column dot products x_j . y_j into device memory `dev_out` (b doubles).
+dacp_status coldots_dev(dacp_ctx ctx, const void *x, int64_t ldx, const void *y, int64_t ldy, int dtype, int64_t D,
+                        int b, double *dev_out) {
+  const int nblk = dacp::coldots_blocks(D, b);
+  dacp_status st = ensure_red(ctx, static_cast<size_t>(nblk) * b, b);
+  if (st) return st;
+  DACP_HIP(ctx, dacp::launch_coldots(x, ldx, y, ldy, dtype, D, b, ctx->red, nblk, dev_out, ctx->stream));
+  return DACP_OK;
+}
+
+// Same, result on the host (synchronises).
+dacp_status coldots_host(dacp_ctx ctx, const void *x, int64_t ldx, const void *y, int64_t ldy, int dtype, int64_t D,
+                         int b, double *host_out) {
+  dacp_status st = ensure_red(ctx, static_cast<size_t>(dacp::coldots_blocks(D, b)) * b, b);
+  if (st) return st;
+  st = coldots_dev(ctx, x, ldx, y, ldy, dtype, D, b, ctx->red_out);
+  if (st) return st;
+  DACP_HIP(ctx, hipMemcpyAsync(host_out, ctx->red_out, sizeof(double) * b, hipMemcpyDeviceToHost, ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DACP_OK;
+}
+
+// y = alpha H x + beta u + gamma z (+ FP64 copy into st), columns split in chunks of <= 2048.
+template <typename T>
+dacp_status step(dacp_ctx ctx, dacp_ham h, int b, const T *x, int64_t ldx, T *y, int64_t ldy, T alpha,
+                 const T *u = nullptr, int64_t ldu = 0, T beta = T(0), const T *z = nullptr, int64_t ldz = 0,
+                 T gamma = T(0), double *st = nullptr, int64_t ldst = 0, int role = 0) {
+  const int64_t D = h->D;
+  for (int c0 = 0; c0 < b; c0 += 2048) {
+    const int bc = std::min(2048, b - c0);
+    int log2R = 0;
+    while ((int64_t(2) << log2R) <= D && (int64_t(2) << log2R) * bc <= dacp::kTileElems) ++log2R;
+    const int R = 1 << log2R;
+    StepArgs<T> a;
+    a.x = x + c0;
+    a.ldx = ldx;
+    a.y = y + c0;
+    a.ldy = ldy;
+    a.u = u ? u + c0 : nullptr;
+    a.ldu = ldu;
+    a.z = z ? z + c0 : nullptr;
+    a.ldz = ldz;
+    a.st = st ? st + c0 : nullptr;
+    a.ldst = ldst;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.gamma = gamma;
+    a.diag = std::is_same<T, double>::value ? reinterpret_cast<const T *>(h->d64) : reinterpret_cast<const T *>(h->d32);
+    a.flips = h->flips;
+    a.nflip = static_cast<int>(h->flips_host.size());
+    int nlow = 0;
+    while (nlow < a.nflip && h->flips_host[nlow].xmask < static_cast<uint32_t>(R)) ++nlow;
+    a.nlow = nlow;
+    a.b = bc;
+    a.log2R = log2R;
+    a.ntiles = static_cast<int>(D >> log2R);
+    a.xcd_remap = (a.ntiles % 8 == 0 && a.ntiles >= 64) ? 1 : 0;
+    DACP_HIP(ctx, dacp::launch_step<T>(a, ctx->stream, role));
+  }
+  return DACP_OK;
+}
+
+struct Timer {
+  dacp_ctx ctx;
+  hipEvent_t a, b;
+  explicit Timer(dacp_ctx c) : ctx(c) {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  void start() { (void)hipEventRecord(a, ctx->stream); }
+  double stop_ms() {
+    (void)hipEventRecord(b, ctx->stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+};
+
+// ------------------------------------------------------------- filter core
+// Damped recurrence: with rho = exp(theta_0), theta_0 = arccosh(1 + 2a^2/(E_b^2 - a^2))
+// the growth rate of the band-centre component, the kernels carry
+// T^_k = T_k / rho^k, which obeys T^_{k+1} = (2/rho) F T^_k - (1/rho^2) T^_{k-1};
+// the normalised output is unchanged and FP32 never overflows.
+struct FilterCoefs {
+  double e_c, e_0, rho;
+};
+
+template <typename T>
+dacp_status filter_first(dacp_ctx ctx, dacp_ham h, int b, const FilterCoefs &fc, const T *psi, T *t1, T *w) {
+  dacp_status st = step<T>(ctx, h, b, psi, b, w, b, T(1), nullptr, 0, T(0), nullptr, 0, T(0), nullptr, 0, 1);
+  if (st) return st;
+  return step<T>(ctx, h, b, w, b, t1, b, T(1.0 / (fc.e_0 * fc.rho)), psi, b, T(-fc.e_c / (fc.e_0 * fc.rho)), nullptr, 0,
+                 T(0), nullptr, 0, 1);
+}
+
+// Advance (A = T^_{k-1}, B = T^_k) by `nsteps`; on return B holds the newest.
+template <typename T>
+dacp_status filter_steps(dacp_ctx ctx, dacp_ham h, int b, const FilterCoefs &fc, T *&A, T *&B, T *w, int nsteps) {
+  const T alpha = T(2.0 / (fc.e_0 * fc.rho));
+  const T beta = T(-2.0 * fc.e_c / (fc.e_0 * fc.rho));
+  const T gamma = T(-1.0 / (fc.rho * fc.rho));
+  for (int k = 0; k < nsteps; ++k) {
+    dacp_status st = step<T>(ctx, h, b, B, b, w, b, T(1), nullptr, 0, T(0), nullptr, 0, T(0), nullptr, 0, 1);
+    if (st) return st;
+    st = step<T>(ctx, h, b, w, b, A, b, alpha, B, b, beta, A, b, gamma, nullptr, 0, 1);
+    if (st) return st;
+    std::swap(A, B);
+  }
+  return DACP_OK;
+}
+
+dacp_status normalise_cols(dacp_ctx ctx, double *x, int64_t D, int b) {
+  dacp_status st = ensure_red(ctx, static_cast<size_t>(dacp::coldots_blocks(D, b)) * b, b);
+  if (st) return st;
+  std::vector<double> nrm(b);
+  st = coldots_host(ctx, x, b, x, b, DACP_F64, D, b, nrm.data());
+  if (st) return st;
+  for (int j = 0; j < b; ++j)
+    if (!(nrm[j] > 0.0) || !std::isfinite(nrm[j]))
+      return set_err(ctx, DACP_E_NUMERIC, "filtered column has zero or non-finite norm");
+  DACP_HIP(ctx, dacp::launch_colscale(x, b, D, b, ctx->red_out, ctx->stream));
+  return DACP_OK;
+}
+
+dacp_status run_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, const double *start, double *psi_out) {
+  const int64_t D = h->D;
+  const int b = p->b;
+  if (b < 1 || p->K < 0 || !(p->a > 0.0) || !(p->e_bound > p->a) || !psi_out)
+    return set_err(ctx, DACP_E_INVALID, "filter: need b >= 1, K >= 0, 0 < a < e_bound, psi_out");
+  if (p->precision != DACP_F64 && p->precision != DACP_F32)
+    return set_err(ctx, DACP_E_INVALID, "filter: precision must be DACP_F64 or DACP_F32");
+  const size_t blk = static_cast<size_t>(D) * b;
+  FilterCoefs fc;
+  fc.e_c = 0.5 * (p->e_bound * p->e_bound + p->a * p->a);
+  fc.e_0 = 0.5 * (p->e_bound * p->e_bound - p->a * p->a);
+  fc.rho = std::exp(std::acosh(1.0 + 2.0 * p->a * p->a / (p->e_bound * p->e_bound - p->a * p->a)));
+  DevBuf s0, a64, b64, w64;
+  const double *psi = start;
+  if (!psi) {
+    DACP_HIP(ctx, s0.alloc(blk * sizeof(double)));
+    DACP_HIP(ctx, dacp::launch_philox_gauss(s0.as<double>(), D, b, p->seed, ctx->stream));
+    psi = s0.as<double>();
+  }
+  DACP_HIP(ctx, a64.alloc(blk * sizeof(double)));
+  DACP_HIP(ctx, b64.alloc(blk * sizeof(double)));
+  DACP_HIP(ctx, w64.alloc(blk * sizeof(double)));
+  double *A = a64.as<double>(), *B = b64.as<double>();
+  const int K = p->K;
+  dacp_status st = DACP_OK;
+  if (K == 0) {
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi, b, B, b, D, b, ctx->stream));
+  } else {
+    int tail = (p->precision == DACP_F32) ? std::max(0, std::min(p->fp64_tail, K)) : K;
+    const int n32 = K - tail;  // steps (orders) reached in FP32
+    if (n32 >= 1) {
+      DevBuf a32, b32, w32, p32;
+      DACP_HIP(ctx, a32.alloc(blk * sizeof(float)));
+      DACP_HIP(ctx, b32.alloc(blk * sizeof(float)));
+      DACP_HIP(ctx, w32.alloc(blk * sizeof(float)));
+      DACP_HIP(ctx, p32.alloc(blk * sizeof(float)));
+      DACP_HIP(ctx, dacp::launch_convert_f64_to_f32(psi, b, p32.as<float>(), b, D, b, ctx->stream));
+      float *A32 = a32.as<float>(), *B32 = b32.as<float>();
+      DACP_HIP(ctx, dacp::launch_convert_f64_to_f32(psi, b, A32, b, D, b, ctx->stream));
+      st = filter_first<float>(ctx, h, b, fc, p32.as<float>(), B32, w32.as<float>());
+      if (st) return st;
+      st = filter_steps<float>(ctx, h, b, fc, A32, B32, w32.as<float>(), n32 - 1);
+      if (st) return st;
+      DACP_HIP(ctx, dacp::launch_convert_f32_to_f64(A32, b, A, b, D, b, ctx->stream));
+      DACP_HIP(ctx, dacp::launch_convert_f32_to_f64(B32, b, B, b, D, b, ctx->stream));
+      DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // FP32 buffers are released at scope end
+    } else {
+      DACP_HIP(ctx, dacp::launch_copy_cols(psi, b, A, b, D, b, ctx->stream));
+      st = filter_first<double>(ctx, h, b, fc, psi, B, w64.as<double>());
+      if (st) return st;
+      tail = K - 1;
+    }
+    st = filter_steps<double>(ctx, h, b, fc, A, B, w64.as<double>(), tail);
+    if (st) return st;
+  }
+  st = normalise_cols(ctx, B, D, b);
+  if (st) return st;
+  DACP_HIP(ctx, dacp::launch_copy_cols(B, b, psi_out, b, D, b, ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DACP_OK;
+}
+
+// ------------------------------------------------------------- basis core
+std::vector<int64_t> sample_orders(double a_r, int n) {
+  std::vector<int64_t> ks(n);
+  for (int m = 1; m <= n; ++m) ks[m - 1] = 2 * static_cast<int64_t>(std::floor(m * M_PI / (2.0 * a_r)));
+  return ks;
+}
+
+struct EvolStats {
+  int64_t steps = 0, launches = 0;
+  double kernel_ms = 0.0;
+};
+
+dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *V,
+                      int64_t ldv, int *m_out, EvolStats *stats) {
+  const int64_t D = h->D;
+  const int b = p->b, n = p->n;
+  if (b < 1 || n < 1 || !(p->e_bound > 0.0) || !(p->a > 0.0) || p->a >= p->e_bound || !psi_e || !V)
+    return set_err(ctx, DACP_E_INVALID, "basis: need b >= 1, n >= 1, 0 < a < e_bound, psi_e, V");
+  const int m = b * (2 * n + 1);
+  if (ldv < m) return set_err(ctx, DACP_E_INVALID, "basis: ldv < b (2n + 1)");
+  const double a_r = p->a / p->e_bound;
+  const std::vector<int64_t> ks = sample_orders(a_r, n);
+  std::map<int64_t, int> panel_of;  // order k -> panel index
+  for (int i = 0; i < n; ++i) {
+    panel_of[ks[i] - 1] = 2 * i + 1;
+    panel_of[ks[i]] = 2 * i + 2;
+  }
+  const int64_t kmax = ks.back();
+  const int g = (p->group > 0 && p->group < b) ? p->group : b;
+  DevBuf ba, bb, nrm;
+  DACP_HIP(ctx, ba.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, bb.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, nrm.alloc(static_cast<size_t>(n) * b * sizeof(double)));
+  const double inv_e = 1.0 / p->e_bound;
+  Timer tm(ctx);
+  tm.start();
+  int64_t launches = 0;
+  for (int g0 = 0; g0 < b; g0 += g) {
+    const int gw = std::min(g, b - g0);
+    double *A = ba.as<double>(), *B = bb.as<double>();
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, A, gw, D, gw, ctx->stream));
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, V + g0, ldv, D, gw, ctx->stream));
+    auto store_of = [&](int64_t k) -> double * {
+      auto it = panel_of.find(k);
+      return it == panel_of.end() ? nullptr : V + static_cast<int64_t>(it->second) * b + g0;
+    };
+    dacp_status st =
+        step<double>(ctx, h, gw, A, gw, B, gw, inv_e, nullptr, 0, 0.0, nullptr, 0, 0.0, store_of(1), ldv, 2);
+    if (st) return st;
+    ++launches;
+    for (int64_t k = 1; k < kmax; ++k) {
+      st = step<double>(ctx, h, gw, B, gw, A, gw, 2.0 * inv_e, nullptr, 0, 0.0, A, gw, -1.0, store_of(k + 1), ldv, 2);
+      if (st) return st;
+      ++launches;
+      std::swap(A, B);
+    }
+  }
+  const double evol_ms = tm.stop_ms();
+  // |T_k(G)| <= 1 for e_bound >= ||H||: every stored T_{k_m} column must keep norm <= ||psi_E column||.
+  std::vector<double> n0(b), nk(static_cast<size_t>(n) * b);
+  dacp_status st = coldots_host(ctx, psi_e, b, psi_e, b, DACP_F64, D, b, n0.data());
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    st = coldots_dev(ctx, V + static_cast<int64_t>(2 * i + 2) * b, ldv, V + static_cast<int64_t>(2 * i + 2) * b, ldv,
+                     DACP_F64, D, b, nrm.as<double>() + static_cast<size_t>(i) * b);
+    if (st) return st;
+  }
+  DACP_HIP(ctx, hipMemcpyAsync(nk.data(), nrm.p, sizeof(double) * nk.size(), hipMemcpyDeviceToHost, ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < b; ++j) {
+      const double v = nk[static_cast<size_t>(i) * b + j];
+      if (!std::isfinite(v)) return set_err(ctx, DACP_E_NUMERIC, "basis: non-finite evolved state");
+      if (v > n0[j] * (1.0 + 2e-6))
+        return set_err(ctx, DACP_E_BOUNDS, "basis: |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
+    }
+  if (m_out) *m_out = m;
+  if (stats) {
+    stats->steps = kmax;
+    stats->launches = launches;
+    stats->kernel_ms = evol_ms;
+  }
+  return DACP_OK;
+}
+
+// ------------------------------------------------------------- projection
+dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
+                        int64_t ld) {
+  const int64_t D = h->D;
+  if (m < 1 || ldv < m || ld < m || !V || !S || !P) return set_err(ctx, DACP_E_INVALID, "project: bad sizes/pointers");
+  hipStream_t s = ctx->stream;
+  DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, s));
+  DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
+  const int cw = std::min(m, 512);
+  DevBuf wbuf;
+  DACP_HIP(ctx, wbuf.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
+  double *W = wbuf.as<double>();
+  for (int c0 = 0; c0 < m; c0 += cw) {
+    const int c1 = std::min(m, c0 + cw);
+    const int w = c1 - c0;
+    for (int s0 = c0; s0 < c1; s0 += 64) {
+      const int bw = std::min(64, c1 - s0);
+      dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + (s0 - c0), cw, 1.0);
+      if (st) return st;
+    }
+    DACP_HIP(ctx, dacp::launch_dgemm(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, 0, s));
+  }
+  DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
+  DACP_HIP(ctx, hipStreamSynchronize(s));
+  return DACP_OK;
+}
+
+// ----------------------------------------------------- Rayleigh-Ritz (App. C)
+dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_t ld, double eps,
+                   std::vector<double> &theta, DevBuf *bc_out, int *r_out) {
+  hipStream_t s = ctx->stream;
+  DevBuf awork, zs;
+  DACP_HIP(ctx, awork.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+  DACP_HIP(ctx, zs.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+  DACP_HIP(ctx, hipMemcpy2DAsync(awork.p, m * sizeof(double), S, ld * sizeof(double), m * sizeof(double), m,
+                                 hipMemcpyDeviceToDevice, s));
+  std::vector<double> lam(m);
+  dacp_status st = dacp::gpu_syev(ctx, m, awork.as<double>(), m, lam.data(), zs.as<double>());
+  if (st) return st;
+  int i0 = 0;
+  while (i0 < m && !(lam[i0] > eps)) ++i0;
+  const int r = m - i0;
+  if (r == 0) return set_err(ctx, DACP_E_NUMERIC, "overlap matrix S has no eigenvalue above eps");
+  std::vector<int> perm(r);
+  std::vector<double> scale(r);
+  for (int t = 0; t < r; ++t) {
+    perm[t] = i0 + t;
+    scale[t] = 1.0 / std::sqrt(lam[i0 + t]);
+  }
+  DevBuf dperm, dscale, uc, t1, ht, yc;
+  DACP_HIP(ctx, dperm.alloc(sizeof(int) * r));
+  DACP_HIP(ctx, dscale.alloc(sizeof(double) * r));
+  DACP_HIP(ctx, hipMemcpyAsync(dperm.p, perm.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
+  DACP_HIP(ctx, hipMemcpyAsync(dscale.p, scale.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+  DACP_HIP(ctx, uc.alloc(static_cast<size_t>(r) * m * sizeof(double)));
+  DACP_HIP(ctx, dacp::launch_gather_rows(zs.as<double>(), m, uc.as<double>(), m, dperm.as<int>(), dscale.as<double>(),
+                                         r, m, s));
+  DACP_HIP(ctx, hipStreamSynchronize(s));
+  zs.release();
+  awork.release();
+  // H~ = U^T P U with U = columns of Uc^T:  T1 = Uc P (r x m),  H~ = T1 Uc^T (r x r).
+  DACP_HIP(ctx, t1.alloc(static_cast<size_t>(r) * m * sizeof(double)));
+  DACP_HIP(ctx, dacp::launch_dgemm(0, 0, r, m, m, 1.0, uc.as<double>(), m, P, ld, 0.0, t1.as<double>(), m, 0, s));
+  DACP_HIP(ctx, ht.alloc(static_cast<size_t>(r) * r * sizeof(double)));
+  DACP_HIP(ctx, dacp::launch_dgemm(0, 1, r, r, m, 1.0, t1.as<double>(), m, uc.as<double>(), m, 0.0, ht.as<double>(), r,
+                                   0, s));
+  DACP_HIP(ctx, dacp::launch_symmetrize(ht.as<double>(), r, r, s));
+  DACP_HIP(ctx, hipStreamSynchronize(s));
+  t1.release();
+  theta.assign(r, 0.0);
+  const bool want_b = bc_out != nullptr;
+  if (want_b) DACP_HIP(ctx, yc.alloc(static_cast<size_t>(r) * r * sizeof(double)));
+  st = dacp::gpu_syev(ctx, r, ht.as<double>(), r, theta.data(), want_b ? yc.as<double>() : nullptr);
+  if (st) return st;
+  if (want_b) {
+    // rows of B^T: Bc = Yc Uc  (r x m)
+    DACP_HIP(ctx, bc_out->alloc(static_cast<size_t>(r) * m * sizeof(double)));
+    DACP_HIP(ctx, dacp::launch_dgemm(0, 0, r, m, r, 1.0, yc.as<double>(), r, uc.as<double>(), m, 0.0,
+                                     bc_out->as<double>(), m, 0, s));
+    DACP_HIP(ctx, hipStreamSynchronize(s));
+  }
+  for (double t : theta)
+    if (!std::isfinite(t)) return set_err(ctx, DACP_E_NUMERIC, "non-finite Ritz value");
+  if (r_out) *r_out = r;
+  return DACP_OK;
+}
+
+// ---------------------------------------------------------- Lanczos bound
+dacp_status run_bound(dacp_ctx ctx, dacp_ham h, int steps, const double *v0, uint64_t seed, double safety,
+                      double *e_bound, double *tmin, double *tmax) {
+  const int64_t D = h->D;
+  if (steps < 1) return set_err(ctx, DACP_E_INVALID, "bound: steps >= 1");
+  steps = static_cast<int>(std::min<int64_t>(steps, D));
+  DevBuf bv, bp, bw;
+  DACP_HIP(ctx, bv.alloc(D * sizeof(double)));
+  DACP_HIP(ctx, bp.alloc(D * sizeof(double)));
+  DACP_HIP(ctx, bw.alloc(D * sizeof(double)));
+  double *v = bv.as<double>(), *vp = bp.as<double>(), *w = bw.as<double>();
+  if (v0) DACP_HIP(ctx, hipMemcpyAsync(v, v0, D * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  else DACP_HIP(ctx, dacp::launch_philox_gauss(v, D, 1, seed, ctx->stream));
+  double nv;
+  dacp_status st = coldots_host(ctx, v, 1, v, 1, DACP_F64, D, 1, &nv);
+  if (st) return st;
+  if (!(nv > 0.0)) return set_err(ctx, DACP_E_INVALID, "bound: zero start vector");
+  DACP_HIP(ctx, dacp::launch_axpby(v, v, 0.0, 1.0 / std::sqrt(nv), D, ctx->stream));
+  std::vector<double> al, be;
+  double bprev = 0.0;
+  for (int j = 0; j < steps; ++j) {
+    st = step<double>(ctx, h, 1, v, 1, w, 1, 1.0, j ? vp : nullptr, 1, -bprev);
+    if (st) return st;
+    double alpha;
+    st = coldots_host(ctx, w, 1, v, 1, DACP_F64, D, 1, &alpha);
+    if (st) return st;
+    DACP_HIP(ctx, dacp::launch_axpby(w, v, -alpha, 1.0, D, ctx->stream));
+    double nw;
+    st = coldots_host(ctx, w, 1, w, 1, DACP_F64, D, 1, &nw);
+    if (st) return st;
+    const double beta = std::sqrt(std::max(nw, 0.0));
+    al.push_back(alpha);
+    be.push_back(beta);
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return set_err(ctx, DACP_E_NUMERIC, "bound: non-finite Lanczos");
+    if (beta <= 1e-300 || j + 1 == steps) break;
+    DACP_HIP(ctx, dacp::launch_axpby(w, w, 0.0, 1.0 / beta, D, ctx->stream));
+    double *t = vp;
+    vp = v;
+    v = w;
+    w = t;
+    bprev = beta;
+  }
+  const int k = static_cast<int>(al.size());
+  std::vector<double> th(k), Z(static_cast<size_t>(k) * k);
+  if (!dacp::host_tridiag_eig(al.data(), be.data(), k, th.data(), Z.data()))
+    return set_err(ctx, DACP_E_CONVERGENCE, "bound: tridiagonal eigensolver");
+  const double bk = be.back();
+  const double r_lo = std::fabs(bk * Z[static_cast<size_t>(k - 1) * k + 0]);
+  const double r_hi = std::fabs(bk * Z[static_cast<size_t>(k - 1) * k + (k - 1)]);
+  double eb = safety * std::max(std::fabs(th[k - 1]) + r_hi, std::fabs(th[0]) + r_lo);
+  eb = std::min(eb, h->sum_abs);
+  if (e_bound) *e_bound = eb;
+  if (tmin) *tmin = th[0];
+  if (tmax) *tmax = th[k - 1];
+  return DACP_OK;
+}
+
+// ----------------------------------------------------------- KPM moments
+dacp_status run_moments(dacp_ctx ctx, dacp_ham h, double e_bound, int M, int nvec, const double *R, uint64_t seed,
+                        double *mu) {
+  const int64_t D = h->D;
+  if (M < 1 || nvec < 1 || !(e_bound > 0.0)) return set_err(ctx, DACP_E_INVALID, "moments: bad arguments");
+  const size_t blk = static_cast<size_t>(D) * nvec;
+  DevBuf br, b0, b1;
+  const double *r = R;
+  if (!r) {
+    DACP_HIP(ctx, br.alloc(blk * sizeof(double)));
+    DACP_HIP(ctx, dacp::launch_philox_gauss(br.as<double>(), D, nvec, seed, ctx->stream));
+    r = br.as<double>();
+  }
+  DACP_HIP(ctx, b0.alloc(blk * sizeof(double)));
+  DACP_HIP(ctx, b1.alloc(blk * sizeof(double)));
+  std::vector<double> c(nvec);
+  auto total = [&](const double *x, const double *y, double &out) -> dacp_status {
+    dacp_status st = coldots_host(ctx, x, nvec, y, nvec, DACP_F64, D, nvec, c.data());
+    out = 0.0;
+    for (double v : c) out += v;
+    return st;
+  };
+  double n0;
+  dacp_status st = total(r, r, n0);
+  if (st) return st;
+  mu[0] = 1.0;
+  if (M == 1) return DACP_OK;
+  double *A = b0.as<double>(), *B = b1.as<double>();
+  DACP_HIP(ctx, dacp::launch_copy_cols(r, nvec, A, nvec, D, nvec, ctx->stream));
+  st = step<double>(ctx, h, nvec, A, nvec, B, nvec, 1.0 / e_bound);  // B = T_1 r
+  if (st) return st;
+  double m1;
+  st = total(r, B, m1);
+  if (st) return st;
+  mu[1] = m1 / n0;
+  // A = T_{k-1} r, B = T_k r (k = 1):  mu_{2k} = 2 <T_k r, T_k r> - mu_0,  mu_{2k+1} = 2 <T_{k+1} r, T_k r> - mu_1
+  for (int k = 1; 2 * k < M; ++k) {
+    double tkk;
+    st = total(B, B, tkk);
+    if (st) return st;
+    mu[2 * k] = 2.0 * tkk / n0 - mu[0];
+    if (2 * k + 1 >= M) break;
+    st = step<double>(ctx, h, nvec, B, nvec, A, nvec, 2.0 / e_bound, nullptr, 0, 0.0, A, nvec, -1.0);
+    if (st) return st;
+    std::swap(A, B);  // B = T_{k+1} r, A = T_k r
+    double tk1k;
+    st = total(B, A, tk1k);
+    if (st) return st;
+    mu[2 * k + 1] = 2.0 * tk1k / n0 - mu[1];
+  }
+  return DACP_OK;
+}
+
+// Estimated levels in [-a_r E_b, a_r E_b] from Jackson-damped moments (closed-form integrals).
+double kpm_count(const std::vector<double> &mu, int64_t D, double a_r) {
+  const int M = static_cast<int>(mu.size());
+  const double q = M_PI / (M + 1);
+  const double th = std::acos(a_r);
+  double total = 0.0;
+  for (int k = 0; k < M; ++k) {
+    const double g = ((M - k + 1) * std::cos(q * k) + std::sin(q * k) / std::tan(q)) / (M + 1);
+    if (k == 0) total += g * mu[0] * (M_PI - 2.0 * th) / M_PI;
+    else total += 2.0 * g * mu[k] * (std::sin(k * (M_PI - th)) - std::sin(k * th)) / (k * M_PI);
+  }
+  return static_cast<double>(D) * total;
+}
+
+double window_for_count(const std::vector<double> &mu, int64_t D, double count) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (kpm_count(mu, D, mid) >= count) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+}  // namespace
+
+// =====================================================================  ABI
+
+extern "C" {
+
+const char *dacp_version(void) { return "dacp-mi355x 0.1 (gfx950)"; }
+
+dacp_status dacp_create(int device, void *hip_stream, dacp_ctx *out) {
+  if (!out) return DACP_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DACP_E_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return DACP_E_HIP;
+  dacp_ctx c = new (std::nothrow) dacp_ctx_s();
+  if (!c) return DACP_E_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return DACP_OK;
+}
+
+void dacp_destroy(dacp_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->red) (void)hipFree(ctx->red);
+  if (ctx->red_out) (void)hipFree(ctx->red_out);
+  delete ctx;
+}
+
+const char *dacp_last_error(dacp_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream) {
+  if (!ctx) return DACP_E_INVALID;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return DACP_OK;
+}
+
+dacp_status dacp_build_hamiltonian(dacp_ctx ctx, int L, int n_terms, const dacp_term *terms, dacp_ham *out) {
+  if (!ctx || !out) return DACP_E_INVALID;
+  *out = nullptr;
+  if (L < 1 || L > 30) return set_err(ctx, DACP_E_INVALID, "L must be in [1, 30]");
+  if (n_terms < 0 || (n_terms > 0 && !terms)) return set_err(ctx, DACP_E_INVALID, "bad term list");
+  std::map<uint32_t, double> diag;                              // z-mask -> coefficient
+  std::map<std::pair<uint32_t, uint32_t>, double> flips;        // (x-mask, z-mask) -> coefficient
+  for (int t = 0; t < n_terms; ++t) {
+    const dacp_term &tm = terms[t];
+    if (tm.reserved != 0) return set_err(ctx, DACP_E_INVALID, "term " + std::to_string(t) + ": reserved != 0");
+    if (!std::isfinite(tm.coeff)) return set_err(ctx, DACP_E_INVALID, "term " + std::to_string(t) + ": coefficient");
+    if (tm.op_a > 3 || tm.op_b > 3) return set_err(ctx, DACP_E_INVALID, "term " + std::to_string(t) + ": op code");
+    uint32_t x = 0, z = 0;
+    int ny = 0;
+    const int ops[2] = {tm.op_a, tm.op_b};
+    const int sites[2] = {tm.site_a, tm.site_b};
+    if (tm.op_b != DACP_I && tm.op_a != DACP_I && tm.site_a == tm.site_b)
+      return set_err(ctx, DACP_E_INVALID, "term " + std::to_string(t) + ": two-body term on one site");
+    for (int q = 0; q < 2; ++q) {
+      if (ops[q] == DACP_I) continue;
+      if (sites[q] >= L) return set_err(ctx, DACP_E_INVALID, "term " + std::to_string(t) + ": site >= L");
+      const uint32_t bit = 1u << sites[q];
+      if (ops[q] == DACP_X || ops[q] == DACP_Y) x |= bit;
+      if (ops[q] == DACP_Z || ops[q] == DACP_Y) z |= bit;
+      if (ops[q] == DACP_Y) ++ny;
+    }
+    if (ny % 2) return set_err(ctx, DACP_E_INVALID, "term " + std::to_string(t) + ": odd number of Y (imaginary)");
+    // sigma^y = i sigma^x sigma^z, so a string with ny (even) Y factors carries i^ny = (-1)^(ny/2)
+    const double c = ((ny / 2) % 2 ? -1.0 : 1.0) * tm.coeff;
+    if (x == 0) diag[z] += c;
+    else flips[{x, z}] += c;
+  }
+  dacp_ham h = new (std::nothrow) dacp_ham_s();
+  if (!h) return set_err(ctx, DACP_E_NOMEM, "host allocation");
+  h->ctx = ctx;
+  h->L = L;
+  h->D = int64_t(1) << L;
+  std::vector<uint32_t> dz;
+  std::vector<double> dc;
+  for (auto &kv : diag) {
+    if (kv.second == 0.0) continue;
+    h->sum_abs += std::fabs(kv.second);
+    h->sum_sq += kv.second * kv.second;
+    dz.push_back(kv.first);
+    dc.push_back(kv.second);
+  }
+  for (auto &kv : flips) {
+    if (kv.second == 0.0) continue;
+    h->flips_host.push_back(FlipEntry{kv.first.first, kv.first.second, kv.second});
+    h->sum_abs += std::fabs(kv.second);
+    h->sum_sq += kv.second * kv.second;
+  }
+  std::stable_sort(h->flips_host.begin(), h->flips_host.end(),
+                   [](const FlipEntry &a, const FlipEntry &b) { return a.xmask < b.xmask; });
+  if (h->flips_host.size() > static_cast<size_t>(dacp::kMaxFlips)) {
+    delete h;
+    return set_err(ctx, DACP_E_INVALID, "too many distinct off-diagonal Pauli strings");
+  }
+  auto fail = [&](hipError_t e, const char *what) {
+    dacp_free_hamiltonian(h);
+    return hip_err(ctx, e, what);
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&h->d64, h->D * sizeof(double))) != hipSuccess) return fail(e, "diag alloc");
+  if ((e = hipMalloc(&h->d32, h->D * sizeof(float))) != hipSuccess) return fail(e, "diag alloc");
+  const size_t nf = std::max<size_t>(1, h->flips_host.size());
+  if ((e = hipMalloc(&h->flips, nf * sizeof(FlipEntry))) != hipSuccess) return fail(e, "flip alloc");
+  if (!h->flips_host.empty() &&
+      (e = hipMemcpy(h->flips, h->flips_host.data(), h->flips_host.size() * sizeof(FlipEntry),
+                     hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "flip upload");
+  DevBuf bz, bc;
+  const size_t nd = std::max<size_t>(1, dz.size());
+  if ((e = bz.alloc(nd * sizeof(uint32_t))) != hipSuccess) return fail(e, "diag terms");
+  if ((e = bc.alloc(nd * sizeof(double))) != hipSuccess) return fail(e, "diag terms");
+  if (!dz.empty()) {
+    if ((e = hipMemcpy(bz.p, dz.data(), dz.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "diag upload");
+    if ((e = hipMemcpy(bc.p, dc.data(), dc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e, "diag upload");
+  }
+  if ((e = dacp::launch_diag(bz.as<uint32_t>(), bc.as<double>(), static_cast<int>(dz.size()), h->D, h->d64, h->d32,
+                             ctx->stream)) != hipSuccess)
+    return fail(e, "diag kernel");
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return fail(e, "diag kernel");
+  *out = h;
+  return DACP_OK;
+}
+
+void dacp_free_hamiltonian(dacp_ham h) {
+  if (!h) return;
+  if (h->d64) (void)hipFree(h->d64);
+  if (h->d32) (void)hipFree(h->d32);
+  if (h->flips) (void)hipFree(h->flips);
+  delete h;
+}
+
+dacp_status dacp_ham_info(dacp_ham h, int *L, double *sum_abs, double *sum_sq, int *n_flip_groups) {
+  if (!h) return DACP_E_INVALID;
+  if (L) *L = h->L;
+  if (sum_abs) *sum_abs = h->sum_abs;
+  if (sum_sq) *sum_sq = h->sum_sq;
+  if (n_flip_groups) *n_flip_groups = static_cast<int>(h->flips_host.size());
+  return DACP_OK;
+}
+
+dacp_status dacp_apply(dacp_ctx ctx, dacp_ham h, int dtype, int b, const void *x, int64_t ldx, void *y, int64_t ldy) {
+  if (!ctx || !h || !x || !y || b < 1 || ldx < b || ldy < b) return set_err(ctx, DACP_E_INVALID, "apply: bad args");
+  if (dtype == DACP_F64)
+    return step<double>(ctx, h, b, static_cast<const double *>(x), ldx, static_cast<double *>(y), ldy, 1.0);
+  if (dtype == DACP_F32)
+    return step<float>(ctx, h, b, static_cast<const float *>(x), ldx, static_cast<float *>(y), ldy, 1.0f);
+  return set_err(ctx, DACP_E_INVALID, "apply: dtype");
+}
+
+dacp_status dacp_random_block(dacp_ctx ctx, int64_t D, int b, uint64_t seed, double *out) {
+  if (!ctx || D < 1 || b < 1 || !out) return set_err(ctx, DACP_E_INVALID, "random_block: bad args");
+  DACP_HIP(ctx, dacp::launch_philox_gauss(out, D, b, seed, ctx->stream));
+  return DACP_OK;
+}
+
+dacp_status dacp_spectral_bound(dacp_ctx ctx, dacp_ham h, int steps, const double *v0, uint64_t seed, double safety,
+                                double *e_bound, double *theta_min, double *theta_max) {
+  if (!ctx || !h) return DACP_E_INVALID;
+  return run_bound(ctx, h, steps, v0, seed, safety > 0.0 ? safety : 1.01, e_bound, theta_min, theta_max);
+}
+
+dacp_status dacp_dos_moments(dacp_ctx ctx, dacp_ham h, double e_bound, int n_moments, int nvec, const double *R,
+                             uint64_t seed, double *mu_out) {
+  if (!ctx || !h || !mu_out) return DACP_E_INVALID;
+  return run_moments(ctx, h, e_bound, n_moments, nvec, R, seed, mu_out);
+}
+
+dacp_status dacp_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, const double *start, double *psi_out) {
+  if (!ctx || !h || !p) return DACP_E_INVALID;
+  return run_filter(ctx, h, p, start, psi_out);
+}
+
+dacp_status dacp_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *V,
+                       int64_t ldv, int *m_out) {
+  if (!ctx || !h || !p) return DACP_E_INVALID;
+  return run_basis(ctx, h, p, psi_e, V, ldv, m_out, nullptr);
+}
+
+dacp_status dacp_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
+                         int64_t ld) {
+  if (!ctx || !h) return DACP_E_INVALID;
+  return run_project(ctx, h, m, V, ldv, S, P, ld);
+}
+
+dacp_status dacp_rayleigh_ritz(dacp_ctx ctx, int m, const double *S, const double *P, int64_t ld, double eps,
+                               double *theta_out, double *B_out, int *r_out) {
+  if (!ctx || m < 1 || !S || !P || ld < m || !theta_out) return set_err(ctx, DACP_E_INVALID, "rayleigh_ritz: args");
+  std::vector<double> theta;
+  DevBuf bc;
+  int r = 0;
+  dacp_status st = run_rr(ctx, m, S, P, ld, eps, theta, B_out ? &bc : nullptr, &r);
+  if (st) return st;
+  std::copy(theta.begin(), theta.end(), theta_out);
+  if (B_out) {
+    DACP_HIP(ctx, hipMemcpyAsync(B_out, bc.p, static_cast<size_t>(r) * m * sizeof(double), hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+    DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  if (r_out) *r_out = r;
+  return DACP_OK;
+}
+
+dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows) {
+  if (!ctx || n < 0 || (n > 0 && (!A || !w || ld < n))) return set_err(ctx, DACP_E_INVALID, "syev: args");
+  return dacp::gpu_syev(ctx, n, A, ld, w, Zrows);
+}
+
+dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc) {
+  if (!ctx || M < 0 || N < 0 || K < 0 || !C) return set_err(ctx, DACP_E_INVALID, "gemm: args");
+  DACP_HIP(ctx, dacp::launch_dgemm(transA ? 1 : 0, transB ? 1 : 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 0,
+                                   ctx->stream));
+  return DACP_OK;
+}
+
+void dacp_default_opts(dacp_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->b = 0;
+  o->group = 0;
+  o->kfac = 18.0;
+  o->window_ratio = 2.2;
+  o->basis_ratio = 1.5;
+  o->eps = 1e-12;
+  o->tol_rel = 1e-10;
+  o->lanczos_steps = 80;
+  o->kpm_moments = 256;
+  o->kpm_vectors = 8;
+  o->e_bound = 0.0;
+  o->a = 0.0;
+  o->precision = DACP_F64;
+  o->fp64_tail_frac = 0.2;
+  o->seed = 0;
+  o->max_retries = 1;
+}
+
+dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_in, double *eigs_out,
+                              double *err_out, int *n_out, dacp_report *report) {
+  if (!ctx || !h || !eigs_out) return DACP_E_INVALID;
+  const int64_t D = h->D;
+  if (N < 1 || N > D) return set_err(ctx, DACP_E_INVALID, "central_eigs: need 1 <= N <= 2^L");
+  dacp_opts o;
+  if (opts_in) o = *opts_in;
+  else dacp_default_opts(&o);
+  dacp_report rep;
+  std::memset(&rep, 0, sizeof(rep));
+  const double t_start = now_ms();
+  hipStream_t s = ctx->stream;
+
+  // bound (Sec. III upper-bound estimator)
+  double t0 = now_ms();
+  double e_b = o.e_bound, th_lo = 0.0, th_hi = 0.0;
+  dacp_status st;
+  if (!(e_b > 0.0)) {
+    st = run_bound(ctx, h, o.lanczos_steps > 0 ? o.lanczos_steps : 80, nullptr, o.seed ^ 0x5bd1e995ULL, 1.01, &e_b,
+                   &th_lo, &th_hi);
+    if (st) return st;
+  } else {
+    th_lo = -e_b;
+    th_hi = e_b;
+  }
+  const double norm_est = std::max(std::fabs(th_lo), std::fabs(th_hi));
+  const double tol = o.tol_rel * norm_est;
+  std::vector<double> mu;
+  if (!(o.a > 0.0)) {
+    const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
+    mu.assign(M, 0.0);
+    st = run_moments(ctx, h, e_b, M, o.kpm_vectors > 0 ? o.kpm_vectors : 8, nullptr, o.seed ^ 0x2545f491ULL,
+                     mu.data());
+    if (st) return st;
+  }
+  rep.t_bound_ms = now_ms() - t0;
+  double window_ratio = o.window_ratio > 0.0 ? o.window_ratio : 2.2;
+  int accepted = 0;
+  for (int attempt = 0;; ++attempt) {
+    // window and orders (Sec. II.A, II.B, III)
+    const double n_w = std::min(static_cast<double>(D), std::ceil(window_ratio * N));
+    double a_r = (o.a > 0.0 && attempt == 0) ? o.a / e_b : window_for_count(mu.empty() ? std::vector<double>{1.0} : mu, D, n_w);
+    if (o.a > 0.0 && attempt > 0) a_r = std::min(0.95, (o.a / e_b) * std::pow(1.5, attempt));
+    a_r = std::min(a_r, 0.95);
+    const double a = a_r * e_b;
+    const double kfac = o.kfac > 0.0 ? o.kfac : 18.0;
+    const int K = static_cast<int>(std::ceil(kfac / a_r));
+    int b = o.b;
+    if (b <= 0) {
+      b = 4;
+      while (b < 64 && b * 16 <= n_w) b *= 2;
+    }
+    const double basis_ratio = o.basis_ratio > 0.0 ? o.basis_ratio : 1.5;
+    const int n = std::max(1, static_cast<int>(std::ceil((basis_ratio * n_w / b - 1.0) / 2.0)));
+    const int m = b * (2 * n + 1);
+    rep.e_bound = e_b;
+    rep.a = a;
+    rep.a_r = a_r;
+    rep.K = K;
+    rep.b = b;
+    rep.n = n;
+    rep.m = m;
+    rep.retries = attempt;
+
+    // filter (Sec. II.A)
+    t0 = now_ms();
+    DevBuf psi;
+    DACP_HIP(ctx, psi.alloc(static_cast<size_t>(D) * b * sizeof(double)));
+    dacp_filter_params fp;
+    fp.e_bound = e_b;
+    fp.a = a;
+    fp.K = K;
+    fp.b = b;
+    fp.precision = o.precision;
+    fp.fp64_tail = static_cast<int>(std::ceil(o.fp64_tail_frac * K));
+    fp.seed = o.seed + static_cast<uint64_t>(attempt) * 0x9E3779B97F4A7C15ULL;
+    st = run_filter(ctx, h, &fp, nullptr, psi.as<double>());
+    if (st) return st;
+    rep.t_filter_ms = now_ms() - t0;
+
+    // evolution basis (Sec. II.B, App. B/C)
+    t0 = now_ms();
+    DevBuf vbuf;
+    DACP_HIP(ctx, vbuf.alloc(static_cast<size_t>(D) * m * sizeof(double)));
+    dacp_basis_params bp;
+    bp.e_bound = e_b;
+    bp.a = a;
+    bp.n = n;
+    bp.b = b;
+    bp.group = o.group;
+    EvolStats es;
+    int m_got = 0;
+    st = run_basis(ctx, h, &bp, psi.as<double>(), vbuf.as<double>(), m, &m_got, &es);
+    if (st) return st;
+    psi.release();
+    rep.t_evol_ms = now_ms() - t0;
+    rep.evol_steps = es.steps;
+    rep.evol_launches = es.launches;
+    rep.evol_kernel_ms = es.kernel_ms;
+
+    // projection (Sec. II.C)
+    t0 = now_ms();
+    DevBuf sb, pb;
+    DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+    DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+    st = run_project(ctx, h, m, vbuf.as<double>(), m, sb.as<double>(), pb.as<double>(), m);
+    if (st) return st;
+    rep.t_project_ms = now_ms() - t0;
+
+    // generalised eigenproblem (App. C)
+    t0 = now_ms();
+    std::vector<double> theta;
+    DevBuf bc;
+    int r = 0;
+    st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r);
+    if (st) return st;
+    sb.release();
+    pb.release();
+    rep.rank = r;
+    rep.t_gep_ms = now_ms() - t0;
+
+    // acceptance (Sec. II.C residual check): candidates by |theta|
+    t0 = now_ms();
+    std::vector<int> order(r);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+      const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
+      return ai < aj || (ai == aj && theta[i] < theta[j]);
+    });
+    const int n_sel = std::min(r, N + 16);
+    std::vector<double> gaps(r, INFINITY);
+    for (int i = 0; i < r; ++i) {
+      if (i > 0) gaps[i] = std::min(gaps[i], theta[i] - theta[i - 1]);
+      if (i + 1 < r) gaps[i] = std::min(gaps[i], theta[i + 1] - theta[i]);
+    }
+    std::vector<double> rnorm(n_sel, INFINITY);
+    {
+      const int cw = std::min(n_sel, 512);
+      DevBuf bsel, phi, hphi, dth, dperm;
+      DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
+      DACP_HIP(ctx, phi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
+      DACP_HIP(ctx, hphi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
+      DACP_HIP(ctx, dth.alloc(sizeof(double) * cw));
+      DACP_HIP(ctx, dperm.alloc(sizeof(int) * cw));
+      const int nblk = dacp::coldots_blocks(D, 2 * cw);
+      st = ensure_red(ctx, static_cast<size_t>(nblk) * 2 * cw, 2 * cw);
+      if (st) return st;
+      std::vector<double> out(2 * cw);
+      for (int c0 = 0; c0 < n_sel; c0 += cw) {
+        const int w = std::min(cw, n_sel - c0);
+        std::vector<int> pr(order.begin() + c0, order.begin() + c0 + w);
+        std::vector<double> th(w);
+        for (int i = 0; i < w; ++i) th[i] = theta[pr[i]];
+        DACP_HIP(ctx, hipMemcpyAsync(dperm.p, pr.data(), sizeof(int) * w, hipMemcpyHostToDevice, s));
+        DACP_HIP(ctx, hipMemcpyAsync(dth.p, th.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+        DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, w, m,
+                                               s));
+        // Phi = V B_sel  (D x w)
+        DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, vbuf.as<double>(), m, bsel.as<double>(), m, 0.0,
+                                         phi.as<double>(), w, 0, s));
+        st = step<double>(ctx, h, w, phi.as<double>(), w, hphi.as<double>(), w, 1.0);
+        if (st) return st;
+        DACP_HIP(ctx, dacp::launch_resid(phi.as<double>(), hphi.as<double>(), w, dth.as<double>(), D, w, ctx->red,
+                                         dacp::coldots_blocks(D, 2 * w), ctx->red_out, s));
+        DACP_HIP(ctx, hipMemcpyAsync(out.data(), ctx->red_out, sizeof(double) * 2 * w, hipMemcpyDeviceToHost, s));
+        DACP_HIP(ctx, hipStreamSynchronize(s));
+        for (int i = 0; i < w; ++i) rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
+      }
+    }
+    // contiguous accepted core around 0 (walk outward in |theta|, stop at the first rejection)
+    std::vector<double> est(n_sel);
+    int core = 0;
+    double max_est = 0.0;
+    for (int i = 0; i < n_sel; ++i) {
+      const double g = gaps[order[i]];
+      const double kt = (g > 0.0) ? rnorm[i] * rnorm[i] / g : INFINITY;
+      est[i] = std::min(rnorm[i], kt);
+    }
+    while (core < n_sel && est[core] <= tol && std::fabs(theta[order[core]]) <= a) {
+      max_est = std::max(max_est, est[core]);
+      ++core;
+    }
+    accepted = core;
+    rep.n_candidates = n_sel;
+    rep.n_accepted = core;
+    rep.max_err_est = max_est;
+    rep.t_accept_ms = now_ms() - t0;
+    if (core >= N) {
+      std::vector<std::pair<double, double>> sel;
+      for (int i = 0; i < N; ++i) sel.push_back({theta[order[i]], est[i]});
+      std::sort(sel.begin(), sel.end());
+      for (int i = 0; i < N; ++i) {
+        eigs_out[i] = sel[i].first;
+        if (err_out) err_out[i] = sel[i].second;
+      }
+      if (n_out) *n_out = N;
+      rep.t_total_ms = now_ms() - t_start;
+      if (report) *report = rep;
+      return DACP_OK;
+    }
+    if (attempt >= o.max_retries) break;
+    window_ratio *= 1.5;
+  }
+  if (n_out) *n_out = accepted;
+  rep.t_total_ms = now_ms() - t_start;
+  if (report) *report = rep;
+  return set_err(ctx, DACP_E_WINDOW,
+                 "only " + std::to_string(accepted) + " eigenvalues accepted near 0; widen the window");
+}
+
+}  // extern "C"

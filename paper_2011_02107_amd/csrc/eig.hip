@@ -1,0 +1,398 @@
+// Dense symmetric eigen-decomposition for the subspace problem (App. C):
+// Householder tridiagonalisation on the GPU, implicit symmetric QR with a
+// Wilkinson shift on the host (O(n^2) scalar work), and the QR rotations
+// replayed on the GPU onto the Householder Q.  Eigenvectors are returned as
+// rows (row j = eigenvector j), the layout in which the rotations of one QR
+// sweep stream through memory with every lane owning one column.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace dacp {
+
+// ----------------------------------------------------------- tridiagonalise
+// Step k reduces row k: x = A[k][k+1..n-1], v = x - alpha e1 with
+// alpha = -sign(x0) ||x||, beta = 2 / v^T v; v is written back over x (it is
+// never read again by the reduction) and kept for forming Q.
+__global__ __launch_bounds__(1024) void k_house(double *A, int64_t ld, int n, int k, double *v, double *dd,
+                                                double *ee, double *betas) {
+  __shared__ double red[1024];
+  const int m = n - k - 1;
+  const double *x = A + static_cast<int64_t>(k) * ld + k + 1;
+  double s = 0.0;
+  for (int i = 1 + threadIdx.x; i < m; i += blockDim.x) s += x[i] * x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sigma = red[0];
+  const double x0 = x[0];
+  double beta = 0.0, alpha = x0, v0 = 0.0;
+  if (sigma > 0.0) {
+    const double mu = sqrt(x0 * x0 + sigma);
+    alpha = (x0 >= 0.0) ? -mu : mu;
+    v0 = x0 - alpha;
+    beta = 2.0 / (v0 * v0 + sigma);
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) v[i] = (i == 0) ? v0 : (sigma > 0.0 ? x[i] : 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd[k] = A[static_cast<int64_t>(k) * ld + k];
+    ee[k] = alpha;
+    betas[k] = beta;
+    A[static_cast<int64_t>(k) * ld + k + 1] = v0;
+  }
+}
+
+// p[i] = beta * sum_j A[k+1+i][k+1+j] v[j]; one wave per row.
+__global__ __launch_bounds__(256) void k_symv(const double *A, int64_t ld, int n, int k, const double *v,
+                                              const double *betas, double *p) {
+  const double beta = betas[k];
+  const int m = n - k - 1;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= m || beta == 0.0) return;
+  const double *a = A + static_cast<int64_t>(k + 1 + row) * ld + k + 1;
+  double s = 0.0;
+  for (int j = lane; j < m; j += 64) s += a[j] * v[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) p[row] = beta * s;
+}
+
+// w = p - (beta p^T v / 2) v, in place over p.
+__global__ __launch_bounds__(1024) void k_wvec(double *p, const double *v, const double *betas, int n, int k) {
+  __shared__ double red[1024];
+  const double beta = betas[k];
+  const int m = n - k - 1;
+  if (beta == 0.0) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) s += p[i] * v[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double half = 0.5 * beta * red[0];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) p[i] -= half * v[i];
+}
+
+// A22 -= v w^T + w v^T.
+__global__ __launch_bounds__(256) void k_syr2(double *A, int64_t ld, int n, int k, const double *v, const double *w,
+                                              const double *betas) {
+  if (betas[k] == 0.0) return;
+  const int m = n - k - 1;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= m || i >= m) return;
+  double *a = A + static_cast<int64_t>(k + 1 + i) * ld + k + 1;
+  a[j] -= v[i] * w[j] + w[i] * v[j];
+}
+
+// Q^T <- Q^T P_k on rows i > k: Qc[i] -= beta (Qc[i] . v) v^T, v = A[k][k+1..].
+__global__ __launch_bounds__(256) void k_qupdate(double *Qc, int64_t ldq, const double *A, int64_t ld, int n, int k,
+                                                 const double *betas) {
+  const double beta = betas[k];
+  const int row = k + 1 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n || beta == 0.0) return;
+  const double *v = A + static_cast<int64_t>(k) * ld;
+  double *q = Qc + static_cast<int64_t>(row) * ldq;
+  double s = 0.0;
+  for (int j = k + 1 + lane; j < n; j += 64) s += q[j] * v[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  s *= beta;
+  for (int j = k + 1 + lane; j < n; j += 64) q[j] -= s * v[j];
+}
+
+__global__ void k_set_identity(double *Q, int64_t ldq, int n) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(n) * n) return;
+  const int64_t i = e / n, j = e - i * n;
+  Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
+}
+
+// One implicit-QR sweep on rows p..q of Qc: for k = p..q-1,
+//   Qc[k] <- c Qc[k] - s Qc[k+1],  Qc[k+1] <- s Qc[k] + c Qc[k+1].
+__global__ __launch_bounds__(256) void k_rot_sweep(double *Qc, int64_t ldq, int ncols, int p, int q,
+                                                   const double *cs) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncols) return;
+  double carry = Qc[static_cast<int64_t>(p) * ldq + col];
+  for (int k = p; k < q; ++k) {
+    const double c = cs[2 * (k - p)], s = cs[2 * (k - p) + 1];
+    const double zn = Qc[static_cast<int64_t>(k + 1) * ldq + col];
+    Qc[static_cast<int64_t>(k) * ldq + col] = c * carry - s * zn;
+    carry = s * carry + c * zn;
+  }
+  Qc[static_cast<int64_t>(q) * ldq + col] = carry;
+}
+
+__global__ void k_gather_rows(const double *src, int64_t lds, double *dst, int64_t ldd, const int *perm,
+                              const double *scale, int rows, int cols) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(rows) * cols) return;
+  const int64_t i = e / cols, j = e - i * cols;
+  const double sc = scale ? scale[i] : 1.0;
+  dst[i * ldd + j] = sc * src[static_cast<int64_t>(perm[i]) * lds + j];
+}
+
+// ---------------------------------------------------- host implicit QR
+
+namespace {
+
+struct Sweep {
+  int p, q;
+  size_t off;  // offset (in pairs) into the rotation buffer
+};
+
+// Givens pair for the rotation row_k' = c row_k - s row_{k+1},
+// row_{k+1}' = s row_k + c row_{k+1}: chosen so that c x - s z = r and
+// s x + c z = 0 (Golub & Van Loan's stable formulas).
+inline void givens(double x, double z, double &c, double &s) {
+  if (z == 0.0) {
+    c = 1.0;
+    s = 0.0;
+  } else if (std::fabs(z) > std::fabs(x)) {
+    const double tau = -x / z;
+    s = 1.0 / std::sqrt(1.0 + tau * tau);
+    c = s * tau;
+  } else {
+    const double tau = -z / x;
+    c = 1.0 / std::sqrt(1.0 + tau * tau);
+    s = c * tau;
+  }
+}
+
+// Implicit symmetric QR with a Wilkinson shift (Golub & Van Loan), deflating
+// from the bottom.  d (n), e (n, e[i] couples i and i+1) are overwritten by
+// the eigenvalues (unsorted).  Every sweep over the unreduced block [p, q]
+// calls sink(p, q, cs) with the q - p rotations (c, s) in order k = p..q-1.
+template <typename Sink>
+bool tridiag_qr(std::vector<double> &d, std::vector<double> &e, int n, Sink &&sink) {
+  const double eps = 2.220446049250313e-16;
+  std::vector<double> cs(2 * static_cast<size_t>(n));
+  int q = n - 1;
+  long iters = 0;
+  const long max_iters = 40L * n + 100;
+  while (q > 0) {
+    if (e[q - 1] == 0.0 || std::fabs(e[q - 1]) <= eps * (std::fabs(d[q - 1]) + std::fabs(d[q]))) {
+      e[q - 1] = 0.0;
+      --q;
+      continue;
+    }
+    int p = q - 1;
+    while (p > 0 && !(std::fabs(e[p - 1]) <= eps * (std::fabs(d[p - 1]) + std::fabs(d[p])))) --p;
+    if (p > 0) e[p - 1] = 0.0;
+    if (++iters > max_iters) return false;
+    const double a = d[q - 1], bb = e[q - 1], cc = d[q];
+    const double delta = 0.5 * (a - cc);
+    const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * std::hypot(delta, bb);
+    const double mu = (den != 0.0) ? cc - bb * bb / den : cc;
+    double x = d[p] - mu, z = e[p];
+    for (int k = p; k < q; ++k) {
+      double c, s;
+      givens(x, z, c, s);
+      if (k > p) e[k - 1] = c * x - s * z;
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk - 2.0 * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk + 2.0 * c * s * ek + c * c * dk1;
+      e[k] = c * s * (dk - dk1) + (c * c - s * s) * ek;
+      if (k < q - 1) {
+        x = e[k];
+        z = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      cs[2 * (k - p)] = c;
+      cs[2 * (k - p) + 1] = s;
+    }
+    sink(p, q, cs.data());
+  }
+  return true;
+}
+
+}  // namespace
+
+// Small symmetric tridiagonal eigenproblem on the host (Lanczos matrices):
+// w ascending; Z (n x n row-major, may be null) column j = eigenvector j.
+bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z) {
+  std::vector<double> d(diag, diag + n), e(n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) e[i] = off[i];
+  std::vector<double> Zr;  // rows = eigenvectors while iterating
+  if (Z) {
+    Zr.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Zr[static_cast<size_t>(i) * n + i] = 1.0;
+  }
+  auto sink = [&](int p, int q, const double *cs) {
+    if (!Z) return;
+    for (int col = 0; col < n; ++col) {
+      double carry = Zr[static_cast<size_t>(p) * n + col];
+      for (int k = p; k < q; ++k) {
+        const double c = cs[2 * (k - p)], s = cs[2 * (k - p) + 1];
+        const double zn = Zr[static_cast<size_t>(k + 1) * n + col];
+        Zr[static_cast<size_t>(k) * n + col] = c * carry - s * zn;
+        carry = s * carry + c * zn;
+      }
+      Zr[static_cast<size_t>(q) * n + col] = carry;
+    }
+  };
+  if (!tridiag_qr(d, e, n, sink)) return false;
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int i, int j) { return d[i] < d[j]; });
+  for (int j = 0; j < n; ++j) {
+    w[j] = d[perm[j]];
+    if (Z)
+      for (int i = 0; i < n; ++i) Z[static_cast<size_t>(i) * n + j] = Zr[static_cast<size_t>(perm[j]) * n + i];
+  }
+  return true;
+}
+
+// Eigen-decomposition of the symmetric n x n device matrix A (row-major, ld,
+// destroyed).  w (host) ascending; Zrows (device, n x n, ld n) row j =
+// eigenvector j, or nullptr for eigenvalues only.
+dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows) {
+  hipStream_t st = ctx->stream;
+  if (n <= 0) return DACP_OK;
+  if (n == 1) {
+    DACP_HIP(ctx, hipMemcpyAsync(w, A, sizeof(double), hipMemcpyDeviceToHost, st));
+    DACP_HIP(ctx, hipStreamSynchronize(st));
+    if (Zrows) {
+      const double one = 1.0;
+      DACP_HIP(ctx, hipMemcpyAsync(Zrows, &one, sizeof(double), hipMemcpyHostToDevice, st));
+      DACP_HIP(ctx, hipStreamSynchronize(st));
+    }
+    return DACP_OK;
+  }
+  double *dv = nullptr, *dp = nullptr, *dd = nullptr, *de = nullptr, *db = nullptr;
+  DACP_HIP(ctx, hipMalloc(&dv, sizeof(double) * n));
+  DACP_HIP(ctx, hipMalloc(&dp, sizeof(double) * n));
+  DACP_HIP(ctx, hipMalloc(&dd, sizeof(double) * n));
+  DACP_HIP(ctx, hipMalloc(&de, sizeof(double) * n));
+  DACP_HIP(ctx, hipMalloc(&db, sizeof(double) * n));
+  DACP_HIP(ctx, hipMemsetAsync(db, 0, sizeof(double) * n, st));
+  for (int k = 0; k < n - 2; ++k) {
+    const int m = n - k - 1;
+    hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, st, A, ld, n, k, dv, dd, de, db);
+    hipLaunchKernelGGL(k_symv, dim3((m + 3) / 4), dim3(256), 0, st, A, ld, n, k, dv, db, dp);
+    hipLaunchKernelGGL(k_wvec, dim3(1), dim3(1024), 0, st, dp, dv, db, n, k);
+    hipLaunchKernelGGL(k_syr2, dim3((m + 255) / 256, m), dim3(256), 0, st, A, ld, n, k, dv, dp, db);
+  }
+  DACP_HIP(ctx, hipGetLastError());
+  std::vector<double> d(n), e(n, 0.0);
+  double tail[4];
+  if (n > 2) {
+    DACP_HIP(ctx, hipMemcpyAsync(d.data(), dd, sizeof(double) * (n - 2), hipMemcpyDeviceToHost, st));
+    DACP_HIP(ctx, hipMemcpyAsync(e.data(), de, sizeof(double) * (n - 2), hipMemcpyDeviceToHost, st));
+  }
+  DACP_HIP(ctx, hipMemcpy2DAsync(tail, 2 * sizeof(double), A + static_cast<int64_t>(n - 2) * ld + (n - 2),
+                                 ld * sizeof(double), 2 * sizeof(double), 2, hipMemcpyDeviceToHost, st));
+  DACP_HIP(ctx, hipStreamSynchronize(st));
+  d[n - 2] = tail[0];
+  e[n - 2] = tail[2];
+  d[n - 1] = tail[3];
+  e[n - 1] = 0.0;
+
+  if (Zrows) {
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    hipLaunchKernelGGL(k_set_identity, dim3((nn + 255) / 256), dim3(256), 0, st, Zrows, (int64_t)n, n);
+    for (int k = n - 3; k >= 0; --k) {
+      const int rows = n - k - 1;
+      hipLaunchKernelGGL(k_qupdate, dim3((rows + 3) / 4), dim3(256), 0, st, Zrows, (int64_t)n, A, ld, n, k, db);
+    }
+    DACP_HIP(ctx, hipGetLastError());
+  }
+
+  // QR on the host; rotations batched into pinned memory and replayed on the GPU.
+  const size_t flush_pairs = size_t(1) << 24;
+  const size_t cap_pairs = flush_pairs + static_cast<size_t>(n);
+  std::vector<double> rot;
+  std::vector<Sweep> sweeps;
+  double *pinned = nullptr, *drot = nullptr;
+  dacp_status frc = DACP_OK;
+  if (Zrows) {
+    rot.reserve(2 * cap_pairs);
+    DACP_HIP(ctx, hipMalloc(&drot, cap_pairs * 2 * sizeof(double)));
+    DACP_HIP(ctx, hipHostMalloc(&pinned, cap_pairs * 2 * sizeof(double), hipHostMallocDefault));
+  }
+  auto flush = [&]() {
+    if (sweeps.empty() || frc != DACP_OK) return;
+    hipError_t he = hipStreamSynchronize(st);  // the previous batch no longer reads the buffers
+    if (he == hipSuccess) {
+      std::memcpy(pinned, rot.data(), rot.size() * sizeof(double));
+      he = hipMemcpyAsync(drot, pinned, rot.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    }
+    if (he == hipSuccess) {
+      for (const Sweep &sw : sweeps)
+        hipLaunchKernelGGL(k_rot_sweep, dim3((n + 255) / 256), dim3(256), 0, st, Zrows, (int64_t)n, n, sw.p, sw.q,
+                           drot + 2 * sw.off);
+      he = hipGetLastError();
+    }
+    if (he != hipSuccess) frc = hip_err(ctx, he, "rotation replay");
+    rot.clear();
+    sweeps.clear();
+  };
+  auto sink = [&](int p, int q, const double *cs) {
+    if (!Zrows) return;
+    if (rot.size() / 2 + static_cast<size_t>(q - p) > cap_pairs) flush();
+    sweeps.push_back(Sweep{p, q, rot.size() / 2});
+    rot.insert(rot.end(), cs, cs + 2 * static_cast<size_t>(q - p));
+  };
+  const bool ok = tridiag_qr(d, e, n, sink);
+  if (ok && Zrows) flush();
+  hipError_t he = hipStreamSynchronize(st);
+  if (drot) (void)hipFree(drot);
+  if (pinned) (void)hipHostFree(pinned);
+  (void)hipFree(dv);
+  (void)hipFree(dp);
+  (void)hipFree(dd);
+  (void)hipFree(de);
+  (void)hipFree(db);
+  if (frc != DACP_OK) return frc;
+  if (he != hipSuccess) return hip_err(ctx, he, "eigensolver");
+  dacp_status rc = ok ? DACP_OK : DACP_E_CONVERGENCE;
+  if (rc != DACP_OK) return set_err(ctx, rc, "symmetric QR did not converge");
+
+  // sort ascending, permuting eigenvector rows
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int i, int j) { return d[i] < d[j]; });
+  for (int i = 0; i < n; ++i) w[i] = d[perm[i]];
+  if (Zrows) {
+    double *tmp = nullptr;
+    int *dperm = nullptr;
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    DACP_HIP(ctx, hipMalloc(&tmp, sizeof(double) * nn));
+    DACP_HIP(ctx, hipMalloc(&dperm, sizeof(int) * n));
+    DACP_HIP(ctx, hipMemcpyAsync(dperm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    DACP_HIP(ctx, hipMemcpyAsync(tmp, Zrows, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, st, tmp, (int64_t)n, Zrows, (int64_t)n,
+                       dperm, nullptr, n, n);
+    DACP_HIP(ctx, hipGetLastError());
+    DACP_HIP(ctx, hipStreamSynchronize(st));
+    (void)hipFree(tmp);
+    (void)hipFree(dperm);
+  }
+  return DACP_OK;
+}
+
+hipError_t launch_gather_rows(const double *src, int64_t lds, double *dst, int64_t ldd, const int *perm,
+                              const double *scale, int rows, int cols, hipStream_t s) {
+  const int64_t nn = static_cast<int64_t>(rows) * cols;
+  if (nn == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, s, src, lds, dst, ldd, perm, scale, rows,
+                     cols);
+  return hipGetLastError();
+}
+
+}  // namespace dacp

@@ -1,0 +1,231 @@
+// FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// C = alpha * op(A) * op(B) + beta * C, row-major.  A 256-thread workgroup
+// computes a 128 x 128 tile of C; each of its four 64-lane waves owns a
+// 64 x 64 quadrant held as 4 x 4 MFMA accumulators of 16 x 16.  K advances in
+// slabs of 16 staged through double-buffered LDS (k-major, padded rows).
+// Used for the Gram S = V^T V and P = V^T (H V) (upper triangle only), the
+// subspace transforms of the generalised eigenproblem and the Ritz vectors.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace dacp {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 16, PADD = 4;
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                                                  int64_t lda, const double *B, int64_t ldb, double beta, double *C,
+                                                  int64_t ldc, int upper, int ntn) {
+  __shared__ double As[2][BK][BM + PADD];
+  __shared__ double Bs[2][BK][BN + PADD];
+  int tm, tn;
+  if (upper) {
+    int t = blockIdx.x;
+    tm = 0;
+    while (t >= ntn - tm) {
+      t -= ntn - tm;
+      ++tm;
+    }
+    tn = tm + t;
+  } else {
+    tm = blockIdx.y;
+    tn = blockIdx.x;
+  }
+  const int64_t m0 = static_cast<int64_t>(tm) * BM;
+  const int64_t n0 = static_cast<int64_t>(tn) * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * 64;
+
+  double ra[8], rb[8];
+  auto load_a = [&](int64_t k0) {
+    if (TA) {  // A stored K x M
+      const int kk = tid >> 4, mm = (tid & 15) * 8;
+      const int64_t k = k0 + kk;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t m = m0 + mm + q;
+        ra[q] = (k < K && m < M) ? A[k * lda + m] : 0.0;
+      }
+    } else {  // A stored M x K
+      const int mm = tid >> 1, kk = (tid & 1) * 8;
+      const int64_t m = m0 + mm;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t k = k0 + kk + q;
+        ra[q] = (k < K && m < M) ? A[m * lda + k] : 0.0;
+      }
+    }
+  };
+  auto load_b = [&](int64_t k0) {
+    if (!TB) {  // B stored K x N
+      const int kk = tid >> 4, nn = (tid & 15) * 8;
+      const int64_t k = k0 + kk;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t n = n0 + nn + q;
+        rb[q] = (k < K && n < N) ? B[k * ldb + n] : 0.0;
+      }
+    } else {  // B stored N x K
+      const int nn = tid >> 1, kk = (tid & 1) * 8;
+      const int64_t n = n0 + nn;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t k = k0 + kk + q;
+        rb[q] = (k < K && n < N) ? B[n * ldb + k] : 0.0;
+      }
+    }
+  };
+  auto store_ab = [&](int buf) {
+    if (TA) {
+      const int kk = tid >> 4, mm = (tid & 15) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[buf][kk][mm + q] = ra[q];
+    } else {
+      const int mm = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[buf][kk + q][mm] = ra[q];
+    }
+    if (!TB) {
+      const int kk = tid >> 4, nn = (tid & 15) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Bs[buf][kk][nn + q] = rb[q];
+    } else {
+      const int nn = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Bs[buf][kk + q][nn] = rb[q];
+    }
+  };
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  load_a(0);
+  load_b(0);
+  store_ab(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = static_cast<int>(kt & 1);
+    if (kt + 1 < nk) {
+      load_a((kt + 1) * BK);
+      load_b((kt + 1) * BK);
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_ab(buf ^ 1);
+    __syncthreads();
+  }
+  // Output layout of the 16x16 accumulator: lane l, item r -> row 4 (l / 16) + r, column l % 16.
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t col = n0 + wn + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double v = alpha * acc[i][j][r];
+          if (beta != 0.0) v += beta * C[row * ldc + col];
+          C[row * ldc + col] = v;
+        }
+      }
+}
+
+hipError_t launch_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                        int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc, int upper,
+                        hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tmc = (M + BM - 1) / BM, tnc = (N + BN - 1) / BN;
+  dim3 grid, block(256);
+  if (upper) {
+    if (M != N) return hipErrorInvalidValue;
+    grid = dim3(static_cast<unsigned>(tnc * (tnc + 1) / 2));
+  } else {
+    grid = dim3(static_cast<unsigned>(tnc), static_cast<unsigned>(tmc));
+  }
+  const int ntn = static_cast<int>(tnc);
+#define DACP_GEMM_LAUNCH(a_, b_)                                                                                    \
+  hipLaunchKernelGGL((k_dgemm<a_, b_>), grid, block, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, upper, ntn)
+  if (!transA && !transB) DACP_GEMM_LAUNCH(0, 0);
+  else if (!transA && transB) DACP_GEMM_LAUNCH(0, 1);
+  else if (transA && !transB) DACP_GEMM_LAUNCH(1, 0);
+  else DACP_GEMM_LAUNCH(1, 1);
+#undef DACP_GEMM_LAUNCH
+  return hipGetLastError();
+}
+
+// Copy the upper triangle onto the lower one (tiled through LDS).
+__global__ void k_mirror_upper(double *C, int64_t n, int64_t ldc) {
+  __shared__ double t[32][33];
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;  // source tile (bi, bj) in the upper part
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    t[r][tx] = (i < n && j < n) ? C[i * ldc + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bj * 32 + r, j = bi * 32 + tx;  // destination (row i, col j) = source (j, i)
+    if (i < n && j < n && i > j) C[i * ldc + j] = t[tx][r];
+  }
+}
+
+hipError_t launch_mirror_upper(double *C, int64_t n, int64_t ldc, hipStream_t s) {
+  const unsigned nt = static_cast<unsigned>((n + 31) / 32);
+  hipLaunchKernelGGL(k_mirror_upper, dim3(nt, nt), dim3(32, 8), 0, s, C, n, ldc);
+  return hipGetLastError();
+}
+
+// C <- (C + C^T) / 2, tile pairs handled by the upper tile's workgroup.
+__global__ void k_symmetrize(double *C, int64_t n, int64_t ldc) {
+  __shared__ double tu[32][33], tl[32][33];
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    tu[r][tx] = (i < n && j < n) ? C[i * ldc + j] : 0.0;
+    const int64_t i2 = bj * 32 + r, j2 = bi * 32 + tx;
+    tl[r][tx] = (i2 < n && j2 < n) ? C[i2 * ldc + j2] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = bi * 32 + r, j = bj * 32 + tx;
+    const double v = 0.5 * (tu[r][tx] + tl[tx][r]);
+    if (i < n && j < n) C[i * ldc + j] = v;
+    const int64_t i2 = bj * 32 + r, j2 = bi * 32 + tx;
+    const double v2 = 0.5 * (tl[r][tx] + tu[tx][r]);
+    if (i2 < n && j2 < n && bi != bj) C[i2 * ldc + j2] = v2;
+  }
+}
+
+hipError_t launch_symmetrize(double *C, int64_t n, int64_t ldc, hipStream_t s) {
+  const unsigned nt = static_cast<unsigned>((n + 31) / 32);
+  hipLaunchKernelGGL(k_symmetrize, dim3(nt, nt), dim3(32, 8), 0, s, C, n, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace dacp

@@ -1,0 +1,148 @@
+// Internal declarations of the DACP HIP library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dacp.h"
+
+namespace dacp {
+
+// One off-diagonal group of the Hamiltonian: y[s] += coef * (-1)^popcount((s ^ x) & z) * x[s ^ x].
+struct FlipEntry {
+  uint32_t xmask;
+  uint32_t zmask;
+  double coef;
+};
+
+constexpr int kMaxFlips = 1024;
+constexpr int kApplyThreads = 256;
+constexpr int kTileElems = 8192;  // elements of one LDS tile of the apply kernel
+
+// Arguments of the fused "apply + three-term combine" kernel:
+//   y = alpha * H x + beta * u + gamma * z      (u, z optional; z may alias y)
+//   if st != nullptr: st[s * ldst + j] = y  (FP64 copy, the basis sample store)
+template <typename T>
+struct StepArgs {
+  const T *x;
+  int64_t ldx;
+  T *y;
+  int64_t ldy;
+  const T *u;
+  int64_t ldu;
+  const T *z;
+  int64_t ldz;
+  double *st;
+  int64_t ldst;
+  T alpha, beta, gamma;
+  const T *diag;
+  const FlipEntry *flips;
+  int nflip;
+  int nlow;     // leading flips whose x-mask stays inside one tile
+  int b;        // columns
+  int log2R;    // rows per tile = 2^log2R
+  int ntiles;
+  int xcd_remap;
+};
+
+// Launch helpers (kernels.hip).
+template <typename T>
+hipError_t launch_step(const StepArgs<T> &a, hipStream_t s, int role);
+
+hipError_t launch_diag(const uint32_t *zm, const double *c, int nterm, int64_t D, double *d64, float *d32,
+                       hipStream_t s);
+// partial[blk][j] = sum over a row range of x[s][j] * y[s][j]; out[j] = fixed-order sum of partials.
+hipError_t launch_coldots(const void *x, int64_t ldx, const void *y, int64_t ldy, int dtype, int64_t D, int b,
+                          double *partial, int nblk, double *out, hipStream_t s);
+int coldots_blocks(int64_t D, int b);
+hipError_t launch_colscale(double *x, int64_t ldx, int64_t D, int b, const double *sq_norms, hipStream_t s);
+hipError_t launch_copy_cols(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t D, int b, hipStream_t s);
+hipError_t launch_convert_f64_to_f32(const double *x, int64_t ldx, float *y, int64_t ldy, int64_t D, int b,
+                                     hipStream_t s);
+hipError_t launch_convert_f32_to_f64(const float *x, int64_t ldx, double *y, int64_t ldy, int64_t D, int b,
+                                     hipStream_t s);
+hipError_t launch_philox_gauss(double *out, int64_t D, int b, uint64_t seed, hipStream_t s);
+hipError_t launch_axpby(double *y, const double *x, double a, double bcoef, int64_t n, hipStream_t s);
+// residual: out[2j] = ||hx_j - theta_j x_j||^2 partials, out[2j+1] = ||x_j||^2 partials (2-stage).
+hipError_t launch_resid(const double *x, const double *hx, int64_t ld, const double *theta, int64_t D, int b,
+                        double *partial, int nblk, double *out, hipStream_t s);
+
+// FP64 MFMA GEMM (gemm.hip).  C = alpha op(A) op(B) + beta C, row-major.
+// upper: only output tiles with tile_row <= tile_col (symmetric results).
+hipError_t launch_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                        int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc, int upper,
+                        hipStream_t s);
+hipError_t launch_mirror_upper(double *C, int64_t n, int64_t ldc, hipStream_t s);
+hipError_t launch_symmetrize(double *C, int64_t n, int64_t ldc, hipStream_t s);
+
+hipError_t launch_gather_rows(const double *src, int64_t lds, double *dst, int64_t ldd, const int *perm,
+                              const double *scale, int rows, int cols, hipStream_t s);
+
+// Device allocation owned by a scope.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t nbytes) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = nbytes;
+    return nbytes ? hipMalloc(&p, nbytes) : hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+}  // namespace dacp
+
+struct dacp_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  double *red = nullptr;  // reduction partials
+  size_t red_elems = 0;
+  double *red_out = nullptr;
+  size_t red_out_elems = 0;
+  hipEvent_t ev[8] = {};
+};
+
+struct dacp_ham_s {
+  dacp_ctx ctx = nullptr;
+  int L = 0;
+  int64_t D = 0;
+  double sum_abs = 0.0, sum_sq = 0.0;
+  double *d64 = nullptr;  // diagonal of H, FP64
+  float *d32 = nullptr;   // same in FP32
+  dacp::FlipEntry *flips = nullptr;
+  std::vector<dacp::FlipEntry> flips_host;  // sorted by x-mask
+};
+
+namespace dacp {
+// Error helpers used by the API layer.
+dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg);
+dacp_status hip_err(dacp_ctx ctx, hipError_t e, const char *what);
+// Dense symmetric eigensolver (eig.hip).
+dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
+bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z);
+}  // namespace dacp
+
+#define DACP_HIP(ctx, call)                                  \
+  do {                                                       \
+    hipError_t e_ = (call);                                  \
+    if (e_ != hipSuccess) return dacp::hip_err(ctx, e_, #call); \
+  } while (0)

@@ -1,0 +1,352 @@
+// Streaming kernels of the DACP path on gfx950: the matrix-free Hamiltonian
+// apply fused with the Chebyshev three-term combine, column reductions,
+// start-state generation and small element-wise helpers.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace dacp {
+
+// ---------------------------------------------------------------------------
+// Fused apply + combine.
+//
+// A workgroup owns a tile of R = 2^log2R consecutive rows of the [D][b] block
+// (R * b <= kTileElems elements).  The tile of x is staged in LDS; flips whose
+// x-mask lies below bit log2R stay inside the tile and read LDS, the others
+// read the partner rows s ^ x from global memory (L2 / MALL / HBM).  The
+// diagonal d(s) comes from the precomputed table.  Work-groups are dealt to
+// the 8 XCDs round-robin, so tile ids are remapped to give each XCD one
+// contiguous eighth of the state space: partner rows of all but the top
+// three bits then live in the same XCD's L2 region.
+// ---------------------------------------------------------------------------
+// ROLE only separates kernel symbols for profiling: 0 = plain apply / other,
+// 1 = filter recurrence, 2 = evolution recurrence.
+template <typename T, int EPT, int ROLE>
+__global__ __launch_bounds__(kApplyThreads) void k_step(StepArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+  const int bid = blockIdx.x;
+  int t_id = bid;
+  if (a.xcd_remap) {
+    const int per = a.ntiles >> 3;
+    t_id = (bid & 7) * per + (bid >> 3);
+  }
+  const int b = a.b;
+  const int R = 1 << a.log2R;
+  const int nel = R * b;
+  const int64_t row0 = (int64_t)t_id << a.log2R;
+  for (int e = threadIdx.x; e < nel; e += kApplyThreads) {
+    const int r = e / b;
+    const int j = e - r * b;
+    tile[e] = a.x[(row0 + r) * a.ldx + j];
+  }
+  __syncthreads();
+
+  T acc[EPT];
+  int rr[EPT], jj[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kApplyThreads;
+    const int r = e / b;
+    rr[i] = r;
+    jj[i] = e - r * b;
+    acc[i] = (e < nel) ? a.diag[row0 + r] * tile[e] : T(0);
+  }
+  for (int t = 0; t < a.nlow; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kApplyThreads;
+      if (e < nel) {
+        const uint32_t src = static_cast<uint32_t>(row0 + rr[i]) ^ xm;
+        const T sg = (__popc(src & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[(rr[i] ^ static_cast<int>(xm)) * b + jj[i]];
+      }
+    }
+  }
+  for (int t = a.nlow; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kApplyThreads;
+      if (e < nel) {
+        const uint32_t src = static_cast<uint32_t>(row0 + rr[i]) ^ xm;
+        const T sg = (__popc(src & zm) & 1) ? -c : c;
+        acc[i] += sg * a.x[static_cast<int64_t>(src) * a.ldx + jj[i]];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kApplyThreads;
+    if (e < nel) {
+      const int64_t s = row0 + rr[i];
+      const int j = jj[i];
+      T v = a.alpha * acc[i];
+      if (a.u) v += a.beta * a.u[s * a.ldu + j];
+      if (a.z) v += a.gamma * a.z[s * a.ldz + j];
+      a.y[s * a.ldy + j] = v;
+      if (a.st) a.st[s * a.ldst + j] = static_cast<double>(v);
+    }
+  }
+}
+
+template <typename T, int ROLE>
+hipError_t launch_step_role(const StepArgs<T> &a, hipStream_t s) {
+  const int nel = (1 << a.log2R) * a.b;
+  const int ept = (nel + kApplyThreads - 1) / kApplyThreads;
+  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
+  dim3 grid(a.ntiles), block(kApplyThreads);
+  if (ept <= 1) hipLaunchKernelGGL((k_step<T, 1, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 2) hipLaunchKernelGGL((k_step<T, 2, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 4) hipLaunchKernelGGL((k_step<T, 4, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 8) hipLaunchKernelGGL((k_step<T, 8, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 16) hipLaunchKernelGGL((k_step<T, 16, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 32) hipLaunchKernelGGL((k_step<T, 32, ROLE>), grid, block, lds, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step(const StepArgs<T> &a, hipStream_t s, int role) {
+  if (role == 1) return launch_step_role<T, 1>(a, s);
+  if (role == 2) return launch_step_role<T, 2>(a, s);
+  return launch_step_role<T, 0>(a, s);
+}
+template hipError_t launch_step<double>(const StepArgs<double> &, hipStream_t, int);
+template hipError_t launch_step<float>(const StepArgs<float> &, hipStream_t, int);
+
+// ---------------------------------------------------------------------------
+// Diagonal table d(s) = sum_t c_t (-1)^popcount(s & z_t)  (x-mask-free terms).
+// ---------------------------------------------------------------------------
+__global__ void k_diag(const uint32_t *zm, const double *c, int nterm, int64_t D, double *d64, float *d32) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= D) return;
+  double acc = 0.0;
+  for (int t = 0; t < nterm; ++t) {
+    const double ct = c[t];
+    acc += (__popc(static_cast<uint32_t>(s) & zm[t]) & 1) ? -ct : ct;
+  }
+  d64[s] = acc;
+  d32[s] = static_cast<float>(acc);
+}
+
+hipError_t launch_diag(const uint32_t *zm, const double *c, int nterm, int64_t D, double *d64, float *d32,
+                       hipStream_t s) {
+  const int threads = 256;
+  const int64_t blocks = (D + threads - 1) / threads;
+  hipLaunchKernelGGL(k_diag, dim3(blocks), dim3(threads), 0, s, zm, c, nterm, D, d64, d32);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Column reductions (fixed order, so results are reproducible run to run).
+// ---------------------------------------------------------------------------
+int coldots_blocks(int64_t D, int b) {
+  int64_t nb = (D * static_cast<int64_t>(b)) / 16384;
+  if (nb < 1) nb = 1;
+  if (nb > 1024) nb = 1024;
+  if (nb > D) nb = D;
+  return static_cast<int>(nb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coldots(const T *x, int64_t ldx, const T *y, int64_t ldy, int64_t D, int b,
+                                                 double *partial) {
+  __shared__ double sm[256];
+  const int cpt = b < 256 ? b : 256;
+  const int rstride = 256 / cpt;
+  const int tid = threadIdx.x;
+  const int j0 = tid % cpt;
+  const int r0 = tid / cpt;
+  const int64_t rows_per = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t rbeg = static_cast<int64_t>(blockIdx.x) * rows_per;
+  int64_t rend = rbeg + rows_per;
+  if (rend > D) rend = D;
+  for (int jc = 0; jc < b; jc += cpt) {
+    const int j = jc + j0;
+    double acc = 0.0;
+    if (r0 < rstride && j < b)
+      for (int64_t r = rbeg + r0; r < rend; r += rstride)
+        acc += static_cast<double>(x[r * ldx + j]) * static_cast<double>(y[r * ldy + j]);
+    sm[tid] = acc;
+    __syncthreads();
+    if (r0 == 0 && j < b) {
+      double s = 0.0;
+      for (int q = 0; q < rstride; ++q) s += sm[q * cpt + j0];
+      partial[static_cast<int64_t>(blockIdx.x) * b + j] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_partials(const double *partial, int nblk, int w, double *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= w) return;
+  double s = 0.0;
+  for (int q = 0; q < nblk; ++q) s += partial[static_cast<int64_t>(q) * w + j];
+  out[j] = s;
+}
+
+hipError_t launch_coldots(const void *x, int64_t ldx, const void *y, int64_t ldy, int dtype, int64_t D, int b,
+                          double *partial, int nblk, double *out, hipStream_t s) {
+  if (dtype == DACP_F64)
+    hipLaunchKernelGGL((k_coldots<double>), dim3(nblk), dim3(256), 0, s, static_cast<const double *>(x), ldx,
+                       static_cast<const double *>(y), ldy, D, b, partial);
+  else
+    hipLaunchKernelGGL((k_coldots<float>), dim3(nblk), dim3(256), 0, s, static_cast<const float *>(x), ldx,
+                       static_cast<const float *>(y), ldy, D, b, partial);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((b + 255) / 256), dim3(256), 0, s, partial, nblk, b, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_resid(const double *x, const double *hx, int64_t ld, const double *theta,
+                                               int64_t D, int b, double *partial) {
+  __shared__ double sm[2][256];
+  const int cpt = b < 256 ? b : 256;
+  const int rstride = 256 / cpt;
+  const int tid = threadIdx.x;
+  const int j0 = tid % cpt;
+  const int r0 = tid / cpt;
+  const int64_t rows_per = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t rbeg = static_cast<int64_t>(blockIdx.x) * rows_per;
+  int64_t rend = rbeg + rows_per;
+  if (rend > D) rend = D;
+  for (int jc = 0; jc < b; jc += cpt) {
+    const int j = jc + j0;
+    double ar = 0.0, ax = 0.0;
+    if (r0 < rstride && j < b) {
+      const double th = theta[j];
+      for (int64_t r = rbeg + r0; r < rend; r += rstride) {
+        const double xv = x[r * ld + j];
+        const double rv = hx[r * ld + j] - th * xv;
+        ar += rv * rv;
+        ax += xv * xv;
+      }
+    }
+    sm[0][tid] = ar;
+    sm[1][tid] = ax;
+    __syncthreads();
+    if (r0 == 0 && j < b) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int q = 0; q < rstride; ++q) {
+        s0 += sm[0][q * cpt + j0];
+        s1 += sm[1][q * cpt + j0];
+      }
+      partial[static_cast<int64_t>(blockIdx.x) * 2 * b + 2 * j] = s0;
+      partial[static_cast<int64_t>(blockIdx.x) * 2 * b + 2 * j + 1] = s1;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_resid(const double *x, const double *hx, int64_t ld, const double *theta, int64_t D, int b,
+                        double *partial, int nblk, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(256), 0, s, x, hx, ld, theta, D, b, partial);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((2 * b + 255) / 256), dim3(256), 0, s, partial, nblk, 2 * b, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise helpers on [D][b] blocks.
+// ---------------------------------------------------------------------------
+__global__ void k_colscale(double *x, int64_t ldx, int64_t D, int b, const double *sq) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= D * b) return;
+  const int64_t r = e / b;
+  const int j = static_cast<int>(e - r * b);
+  x[r * ldx + j] *= 1.0 / sqrt(sq[j]);
+}
+
+hipError_t launch_colscale(double *x, int64_t ldx, int64_t D, int b, const double *sq_norms, hipStream_t s) {
+  const int64_t n = D * b;
+  hipLaunchKernelGGL(k_colscale, dim3((n + 255) / 256), dim3(256), 0, s, x, ldx, D, b, sq_norms);
+  return hipGetLastError();
+}
+
+template <typename S, typename Dt>
+__global__ void k_copy_cols(const S *x, int64_t ldx, Dt *y, int64_t ldy, int64_t D, int b) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= D * b) return;
+  const int64_t r = e / b;
+  const int j = static_cast<int>(e - r * b);
+  y[r * ldy + j] = static_cast<Dt>(x[r * ldx + j]);
+}
+
+hipError_t launch_copy_cols(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t D, int b, hipStream_t s) {
+  const int64_t n = D * b;
+  hipLaunchKernelGGL((k_copy_cols<double, double>), dim3((n + 255) / 256), dim3(256), 0, s, x, ldx, y, ldy, D, b);
+  return hipGetLastError();
+}
+hipError_t launch_convert_f64_to_f32(const double *x, int64_t ldx, float *y, int64_t ldy, int64_t D, int b,
+                                     hipStream_t s) {
+  const int64_t n = D * b;
+  hipLaunchKernelGGL((k_copy_cols<double, float>), dim3((n + 255) / 256), dim3(256), 0, s, x, ldx, y, ldy, D, b);
+  return hipGetLastError();
+}
+hipError_t launch_convert_f32_to_f64(const float *x, int64_t ldx, double *y, int64_t ldy, int64_t D, int b,
+                                     hipStream_t s) {
+  const int64_t n = D * b;
+  hipLaunchKernelGGL((k_copy_cols<float, double>), dim3((n + 255) / 256), dim3(256), 0, s, x, ldx, y, ldy, D, b);
+  return hipGetLastError();
+}
+
+__global__ void k_axpby(double *y, const double *x, double a, double bcoef, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + bcoef * y[i];
+}
+
+hipError_t launch_axpby(double *y, const double *x, double a, double bcoef, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, s, y, x, a, bcoef, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Start states: Philox4x32-10 (Salmon et al., SC'11) + Box-Muller.
+// ---------------------------------------------------------------------------
+__device__ inline void philox_round(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3, uint32_t k0,
+                                    uint32_t k1) {
+  const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+  const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+  const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+  const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+  const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+  c0 = n0;
+  c1 = lo1;
+  c2 = n2;
+  c3 = lo0;
+}
+
+__global__ void k_philox_gauss(double *out, int64_t D, int b, uint32_t k0, uint32_t k1) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= D * b) return;
+  const int64_t s = e / b;
+  const int j = static_cast<int>(e - s * b);
+  uint32_t c0 = static_cast<uint32_t>(s), c1 = static_cast<uint32_t>(j), c2 = 0, c3 = 0;
+  uint32_t kk0 = k0, kk1 = k1;
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      kk0 += 0x9E3779B9u;
+      kk1 += 0xBB67AE85u;
+    }
+    philox_round(c0, c1, c2, c3, kk0, kk1);
+  }
+  const uint64_t a = (static_cast<uint64_t>(c0) << 32) | c1;
+  const uint64_t c = (static_cast<uint64_t>(c2) << 32) | c3;
+  const double u1 = (static_cast<double>(a >> 11) + 0.5) * 0x1.0p-53;
+  const double u2 = (static_cast<double>(c >> 11) + 0.5) * 0x1.0p-53;
+  out[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+hipError_t launch_philox_gauss(double *out, int64_t D, int b, uint64_t seed, hipStream_t s) {
+  const int64_t n = D * b;
+  hipLaunchKernelGGL(k_philox_gauss, dim3((n + 255) / 256), dim3(256), 0, s, out, D, b,
+                     static_cast<uint32_t>(seed & 0xFFFFFFFFu), static_cast<uint32_t>(seed >> 32));
+  return hipGetLastError();
+}
+
+}  // namespace dacp

@@ -1,0 +1,350 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, on MI355X.
+
+Tolerances (derived in the module docstring of each group):
+  * apply (FP64): each output element is a sum of <= L + 2 products of
+    O(1) magnitudes, evaluated in a different order than the oracle, so the
+    difference is a few ulp of sum |c| * max|x|: 1e-14 relative to that scale.
+  * apply (FP32): the same sum in FP32 (unit roundoff 6e-8): 1e-6 relative.
+  * recurrences: T_k(G) is bounded by 1, rounding accumulates at most
+    linearly in k (Chebyshev recurrence stability), so 1e-15 * k relative to
+    max|psi| (1e-12 floor); the filter output is normalised and dominated by
+    its amplified window components: 1e-10 absolute on unit columns.
+  * Gram / projection: 2 D terms of magnitude <= 1 summed in FP64 with a
+    different blocking: 1e-13 * D relative to max |S|.
+  * central eigenvalues: the target |delta lambda| <= 1e-10 ||H||, with
+    counts matching exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import central, chebyshev, hamiltonian, jordan_wigner, philox, spectral, subspace  # noqa: E402
+from oracle import _native  # noqa: E402
+from paper_2011_02107_amd import binding as B  # noqa: E402
+from paper_2011_02107_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def random_real_terms(L, seed, n):
+    rng = np.random.default_rng(seed)
+    pairs = [(1, 0), (3, 0), (1, 1), (2, 2), (3, 3), (1, 3), (3, 1), (2, 2)]
+    rows = []
+    for _ in range(n):
+        oa, ob = pairs[rng.integers(len(pairs))]
+        sa = int(rng.integers(L))
+        sb = int(rng.integers(L - 1))
+        if sb >= sa:
+            sb += 1
+        if ob == 0:
+            sb = 0
+        rows.append((oa, sa, ob, sb, rng.uniform(-1, 1)))
+    return inputs.make_terms(rows)
+
+
+# ------------------------------------------------------------------ GEMM
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (37, 129, 70), (128, 128, 16), (300, 257, 513)])
+def test_dgemm_mfma_parity(ctx, ta, tb, M, N, K):
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    Bm = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    ref = 0.5 * (A.T if ta else A) @ (Bm.T if tb else Bm) - 2.0 * C0
+    dC = to_dev(C0)
+    B.dacp_gemm(ctx, ta, tb, to_dev(A), to_dev(Bm), dC, alpha=0.5, beta=-2.0)
+    assert np.abs(host(dC) - ref).max() < 1e-13 * max(1.0, np.abs(ref).max()) * math.sqrt(K)
+
+
+def test_mfma_output_layout_single_tile(ctx):
+    """One 16x16x4 product with distinct entries pins the accumulator lane layout."""
+    A = np.arange(16 * 4, dtype=np.float64).reshape(16, 4) / 7.0
+    Bm = np.arange(4 * 16, dtype=np.float64).reshape(4, 16) / 11.0 - 2.0
+    dC = to_dev(np.zeros((16, 16)))
+    B.dacp_gemm(ctx, 0, 0, to_dev(A), to_dev(Bm), dC)
+    assert np.abs(host(dC) - A @ Bm).max() < 1e-13
+
+
+# ------------------------------------------------------------------ apply
+
+
+@pytest.mark.parametrize(
+    "L,b,which",
+    [(1, 1, "chain"), (3, 2, "chain"), (8, 4, "chain"), (10, 64, "chain"), (12, 8, "glass"), (9, 5, "random"),
+     (11, 3, "paper_sgs"), (13, 1, "glass"), (14, 16, "chain")],
+)
+def test_apply_f64_parity(ctx, L, b, which):
+    terms = {
+        "chain": inputs.ising_chain(L),
+        "glass": inputs.spin_glass(L, L),
+        "random": random_real_terms(L, L, 25),
+        "paper_sgs": inputs.paper_sgs(L, 3),
+    }[which]
+    X = np.random.default_rng(L + b).standard_normal((1 << L, b))
+    ref = hamiltonian.apply_h(L, terms, X)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    dy = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    B.dacp_apply(ctx, ham, to_dev(X), dy)
+    scale = hamiltonian.sum_abs_coeff(terms) * np.abs(X).max()
+    assert np.abs(host(dy) - ref).max() <= 1e-14 * scale
+
+
+def test_apply_f32_parity(ctx):
+    L, b = 12, 32
+    terms = inputs.ising_chain(L)
+    X = np.random.default_rng(5).standard_normal((1 << L, b)).astype(np.float32)
+    ref = hamiltonian.apply_h(L, terms, X.astype(np.float64))
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    dy = torch.empty((1 << L, b), dtype=torch.float32, device=DEV)
+    B.dacp_apply(ctx, ham, to_dev(X, torch.float32), dy)
+    scale = hamiltonian.sum_abs_coeff(terms) * np.abs(X).max()
+    assert np.abs(host(dy).astype(np.float64) - ref).max() <= 1e-6 * scale
+
+
+def test_hamiltonian_info_and_validation(ctx):
+    L = 6
+    terms = inputs.spin_glass(L, 1)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    info = ham.info()
+    assert info["L"] == L and info["n_flip_groups"] == L
+    assert abs(info["sum_abs"] - hamiltonian.sum_abs_coeff(terms)) < 1e-12
+    assert abs(info["sum_sq"] - hamiltonian.sum_sq_coeff(terms)) < 1e-12
+    for bad in (
+        inputs.make_terms([(2, 0, 0, 0, 1.0)]),  # single Y: imaginary
+        inputs.make_terms([(1, 7, 0, 0, 1.0)]),  # site >= L
+        inputs.make_terms([(3, 2, 3, 2, 1.0)]),  # two-body on one site
+    ):
+        with pytest.raises(B.DacpError) as ei:
+            B.dacp_build_hamiltonian(ctx, L, bad)
+        assert ei.value.status == -1
+
+
+# ------------------------------------------------------------------ random start states
+
+
+def test_philox_block_matches_oracle(ctx):
+    D, b, seed = 4096, 8, 0x1234_5678_9ABC
+    out = torch.empty((D, b), dtype=torch.float64, device=DEV)
+    B.dacp_random_block(ctx, D, b, seed, out)
+    ref = philox.gaussian_block(D, b, seed)
+    assert np.abs(host(out) - ref).max() < 1e-13
+
+
+# ------------------------------------------------------------------ bound and density
+
+
+def test_spectral_bound_parity_and_validity(ctx):
+    L = 10
+    terms = inputs.ising_chain(L)
+    v0 = np.random.default_rng(3).standard_normal(1 << L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eb, tlo, thi = B.dacp_spectral_bound(ctx, ham, 60, v0=to_dev(v0))
+    al, be = spectral.lanczos(lambda X: hamiltonian.apply_h(L, terms, X), v0, 60)
+    eb_ref, theta = spectral.lanczos_bound(al, be, hamiltonian.sum_abs_coeff(terms))
+    assert abs(tlo - theta[0]) < 1e-9 and abs(thi - theta[-1]) < 1e-9
+    assert abs(eb - eb_ref) < 1e-6 * eb_ref
+    w = central.full_spectrum_dense(L, terms)
+    assert eb >= max(-w[0], w[-1])
+
+
+def test_dos_moments_parity(ctx):
+    L, nvec, M = 11, 4, 64
+    terms = inputs.spin_glass(L, 2)
+    R = np.random.default_rng(4).standard_normal((1 << L, nvec))
+    eb = 1.02 * np.abs(central.full_spectrum_dense(L, terms)).max()
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    mu = B.dacp_dos_moments(ctx, ham, eb, M, nvec, R=to_dev(R))
+    ref = spectral.kpm_moments(lambda X: hamiltonian.apply_h(L, terms, X), R, eb, M)
+    assert np.abs(mu - ref).max() < 1e-11
+
+
+# ------------------------------------------------------------------ filter and basis
+
+
+@pytest.mark.parametrize("L,b,kfac", [(8, 2, 12.0), (10, 4, 18.0)])
+def test_filter_f64_parity(ctx, L, b, kfac):
+    terms = inputs.ising_chain(L)
+    w = central.full_spectrum_dense(L, terms)
+    eb = 1.01 * np.abs(w).max()
+    a = 0.08 * eb
+    K = chebyshev.filter_order(eb, a, kfac)
+    psi = np.random.default_rng(L).standard_normal((1 << L, b))
+    ref = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, K)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    out = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    B.dacp_filter(ctx, ham, out, eb, a, K, start=to_dev(psi))
+    assert np.abs(host(out) - ref).max() < 1e-10
+
+
+def test_filter_f32_with_fp64_tail(ctx):
+    """FP32 recurrence then an FP64 tail: the output stays within FP32-rounding
+    distance of the FP64 oracle filter (window components dominate)."""
+    L, b = 10, 4
+    terms = inputs.ising_chain(L)
+    eb = 1.01 * np.abs(central.full_spectrum_dense(L, terms)).max()
+    a = 0.08 * eb
+    K = chebyshev.filter_order(eb, a, 12.0)
+    psi = np.random.default_rng(1).standard_normal((1 << L, b))
+    ref = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, K)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    out = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    B.dacp_filter(ctx, ham, out, eb, a, K, start=to_dev(psi), precision=B.DACP_F32, fp64_tail=K // 5)
+    err = np.abs(host(out) - ref).max()
+    assert err < 1e-5
+
+
+def test_basis_parity(ctx):
+    L, b, n = 9, 3, 5
+    terms = inputs.spin_glass(L, 7)
+    eb = 1.01 * np.abs(central.full_spectrum_dense(L, terms)).max()
+    a = 0.1 * eb
+    psi = np.random.default_rng(2).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0)
+    ref, ks = chebyshev.chebyshev_basis(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, n)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    m = b * (2 * n + 1)
+    V = torch.zeros((1 << L, m), dtype=torch.float64, device=DEV)
+    got_m = B.dacp_basis(ctx, ham, to_dev(psi), V, eb, a, n)
+    assert got_m == m
+    assert np.abs(host(V) - ref).max() < 1e-15 * max(ks) + 1e-12
+
+
+def test_basis_column_groups_match_full_block(ctx):
+    L, b, n = 10, 8, 3
+    terms = inputs.ising_chain(L)
+    eb = 1.01 * np.abs(central.full_spectrum_dense(L, terms)).max()
+    psi = np.random.default_rng(9).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    m = b * (2 * n + 1)
+    V1 = torch.zeros((1 << L, m), dtype=torch.float64, device=DEV)
+    V2 = torch.zeros_like(V1)
+    B.dacp_basis(ctx, ham, to_dev(psi), V1, eb, 0.2 * eb, n, group=0)
+    B.dacp_basis(ctx, ham, to_dev(psi), V2, eb, 0.2 * eb, n, group=3)
+    assert np.array_equal(host(V1), host(V2))
+
+
+def test_basis_detects_bound_below_norm(ctx):
+    L = 8
+    terms = inputs.ising_chain(L)
+    norm = np.abs(central.full_spectrum_dense(L, terms)).max()
+    psi = np.random.default_rng(0).standard_normal((1 << L, 2))
+    psi /= np.linalg.norm(psi, axis=0)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    V = torch.zeros((1 << L, 2 * 9), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.DacpError) as ei:
+        B.dacp_basis(ctx, ham, to_dev(psi), V, 0.9 * norm, 0.05 * norm, 4)
+    assert ei.value.status == -4
+
+
+# ------------------------------------------------------------------ projection and GEP
+
+
+def test_project_parity(ctx):
+    L, m = 11, 150
+    terms = inputs.spin_glass(L, 4)
+    V = np.random.default_rng(6).standard_normal((1 << L, m)) / math.sqrt(1 << L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    S = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    P = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    B.dacp_project(ctx, ham, to_dev(V), S, P)
+    S_ref, P_ref = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
+    assert np.abs(host(S) - S_ref).max() < 1e-13
+    assert np.abs(host(P) - P_ref).max() < 1e-12
+    assert np.array_equal(host(S), host(S).T) and np.array_equal(host(P), host(P).T)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 130, 400])
+def test_syev_parity(ctx, n):
+    A = np.random.default_rng(n).standard_normal((n, n))
+    A = A + A.T
+    w_ref = _native.syev(A)
+    dA = to_dev(A)
+    Z = torch.zeros((n, n), dtype=torch.float64, device=DEV)
+    w = B.dacp_syev(ctx, dA, Z)
+    assert np.abs(w - w_ref).max() < 1e-12 * max(1.0, np.abs(w_ref).max()) * max(1, n) ** 0.5
+    Zr = host(Z)  # rows are eigenvectors
+    assert np.abs(Zr @ A @ Zr.T - np.diag(w)).max() < 1e-12 * max(1.0, np.abs(w).max()) * n
+    assert np.abs(Zr @ Zr.T - np.eye(n)).max() < 1e-13 * n
+
+
+def test_rayleigh_ritz_parity(ctx):
+    """Same S, P on both sides: the App. C solve gives the same Ritz values."""
+    L = 9
+    terms = inputs.ising_chain(L)
+    lam, Phi = np.linalg.eigh(hamiltonian.dense_h(L, terms))
+    rng = np.random.default_rng(8)
+    sel = np.arange(200, 240)
+    core = Phi[:, sel] @ rng.standard_normal((len(sel), len(sel)))
+    V = np.concatenate([core, core[:, :10] @ rng.standard_normal((10, 6))], axis=1)
+    S, P = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
+    theta_ref, _, r_ref = subspace.rayleigh_ritz(S, P)
+    theta, r = B.dacp_rayleigh_ritz(ctx, to_dev(S), to_dev(P))
+    assert r == r_ref == len(sel)
+    assert np.abs(theta - theta_ref).max() < 1e-10
+    assert np.abs(theta - lam[sel]).max() < 1e-10
+
+
+# ------------------------------------------------------------------ end to end
+
+
+def _check_central(got, ref, norm, N):
+    assert len(got) == N
+    assert np.all(np.diff(got) >= 0)
+    assert np.abs(np.sort(got) - ref).max() <= 1e-10 * norm
+
+
+def test_central_eigs_chain_L10(ctx):
+    """Chaotic Ising chain L = 10, N = 100, block of 4 start states."""
+    L, N = 10, 100
+    terms = inputs.ising_chain(L)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    for seed in (0, 1, 2):
+        opts = B.default_opts(b=4, seed=seed)
+        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
+        _check_central(eigs, ref, norm, N)
+        assert np.all(errs <= 1e-10 * norm)
+
+
+def test_central_eigs_spin_glass_L12(ctx):
+    L, N = 12, 200
+    terms = inputs.spin_glass(L, 0)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=8))
+    _check_central(eigs, ref, norm, N)
+
+
+def test_central_eigs_jw_twin_L14(ctx):
+    """Integrable twin (hz = 0) against the Jordan-Wigner closed form."""
+    L, N = 14, 300
+    terms = inputs.ising_chain(L, hz=0.0)
+    ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=16))
+    _check_central(eigs, ref, norm, N)
