@@ -45,8 +45,8 @@ def opts_for(args, wl):
     if args.mode == "plain":
         o = B.default_opts(b=wl["b"], kfac=18.0, window_ratio=2.2, precision=B.DACP_F64, group=args.group)
     else:
-        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=1.8, precision=B.DACP_F32, fp64_tail_frac=0.2,
-                           group=args.group)
+        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=1.8, basis_ratio=1.25, precision=B.DACP_F32,
+                           fp64_tail_frac=0.2, group=args.group)
     if args.kfac:
         o.kfac = args.kfac
     return o

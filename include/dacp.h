@@ -77,6 +77,12 @@ void dacp_destroy(dacp_ctx ctx);
 const char *dacp_last_error(dacp_ctx ctx);
 /* Replace the stream used by later calls on `ctx`. */
 dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream);
+/* Tile size (elements of the [rows][b] slab one workgroup stages in LDS) of
+ * the apply / recurrence kernel: a power of two in [256, 8192], default 1024.
+ * Chosen by the autotuner.  For Hamiltonians whose off-diagonal Pauli strings
+ * flip one spin each, results are bit-identical for every tile size; with
+ * multi-spin flips the term summation order, hence the rounding, may differ. */
+dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
 /* Library version string (static storage). */
 const char *dacp_version(void);
 
@@ -225,8 +231,11 @@ typedef struct {
 void dacp_default_opts(dacp_opts *opts);
 
 /* The N eigenvalues of H nearest 0, ascending (host eigs_out[N]); err_out
- * (host, may be NULL) gets the residual error estimate of each
- * (Kato-Temple ||r||^2 / gap, or ||r|| when smaller); n_out gets N on success
+ * (host, may be NULL) gets the residual error estimate of each:
+ * min(||r||, ||r||^2 / eta) with r = H phi - theta phi for the Ritz vector phi
+ * and eta the distance from theta to the nearest unaccepted Ritz value or to
+ * the window edge (quadratic residual bound; the residual is orthogonal to the
+ * converged neighbours, which lie in the search space); n_out gets N on success
  * or, on DACP_E_WINDOW, the number accepted.  report may be NULL. */
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report);

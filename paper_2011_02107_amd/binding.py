@@ -119,6 +119,7 @@ SIGNATURES = {
     "dacp_destroy": (None, [_vp]),
     "dacp_last_error": (ctypes.c_char_p, [_vp]),
     "dacp_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "dacp_set_tile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "dacp_version": (ctypes.c_char_p, []),
     "dacp_build_hamiltonian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "dacp_free_hamiltonian": (None, [_vp]),
@@ -193,6 +194,9 @@ class Context:
     def check(self, st):
         if st != 0:
             raise DacpError(st, self.lib.dacp_last_error(self.handle).decode())
+
+    def set_tile(self, tile_elems):
+        self.check(self.lib.dacp_set_tile(self.handle, int(tile_elems)))
 
     def close(self):
         if self.handle:

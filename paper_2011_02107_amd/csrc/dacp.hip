@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -19,6 +22,25 @@ using dacp::StepArgs;
 
 namespace dacp {
 
+bool verbose() {
+  static const bool v = [] {
+    const char *e = std::getenv("DACP_VERBOSE");
+    return e && *e && *e != '0';
+  }();
+  return v;
+}
+
+void vlog(const char *fmt, ...) {
+  if (!verbose()) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fprintf(stderr, "[dacp] ");
+  std::vfprintf(stderr, fmt, ap);
+  std::fprintf(stderr, "\n");
+  std::fflush(stderr);
+  va_end(ap);
+}
+
 dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg) {
   if (ctx) ctx->err = msg;
   return st;
@@ -33,6 +55,8 @@ dacp_status hip_err(dacp_ctx ctx, hipError_t e, const char *what) {
 
 using dacp::hip_err;
 using dacp::set_err;
+using dacp::verbose;
+using dacp::vlog;
 
 namespace {
 
@@ -78,6 +102,29 @@ dacp_status coldots_host(dacp_ctx ctx, const void *x, int64_t ldx, const void *y
   return DACP_OK;
 }
 
+// Flip table ordered for tiles of 2^log2R rows: masks inside the tile (read from LDS), masks
+// entirely above it (partner row = (row0 ^ x) + r), then mixed masks; x-mask order within each.
+dacp_status tile_order(dacp_ctx ctx, dacp_ham h, int log2R) {
+  auto &to = h->by_log2r[log2R];
+  if (to.dev) return DACP_OK;
+  const uint32_t lowmask = (1u << log2R) - 1u;
+  std::vector<FlipEntry> lo, hi, mx;
+  for (const FlipEntry &f : h->flips_host) {
+    if ((f.xmask & ~lowmask) == 0) lo.push_back(f);
+    else if ((f.xmask & lowmask) == 0) hi.push_back(f);
+    else mx.push_back(f);
+  }
+  std::vector<FlipEntry> all(lo);
+  all.insert(all.end(), hi.begin(), hi.end());
+  all.insert(all.end(), mx.begin(), mx.end());
+  DACP_HIP(ctx, hipMalloc(&to.dev, std::max<size_t>(1, all.size()) * sizeof(FlipEntry)));
+  if (!all.empty())
+    DACP_HIP(ctx, hipMemcpy(to.dev, all.data(), all.size() * sizeof(FlipEntry), hipMemcpyHostToDevice));
+  to.nlow = static_cast<int>(lo.size());
+  to.nhigh = static_cast<int>(lo.size() + hi.size());
+  return DACP_OK;
+}
+
 // y = alpha H x + beta u + gamma z (+ FP64 copy into st), columns split in chunks of <= 2048.
 template <typename T>
 dacp_status step(dacp_ctx ctx, dacp_ham h, int b, const T *x, int64_t ldx, T *y, int64_t ldy, T alpha,
@@ -87,7 +134,10 @@ dacp_status step(dacp_ctx ctx, dacp_ham h, int b, const T *x, int64_t ldx, T *y,
   for (int c0 = 0; c0 < b; c0 += 2048) {
     const int bc = std::min(2048, b - c0);
     int log2R = 0;
-    while ((int64_t(2) << log2R) <= D && (int64_t(2) << log2R) * bc <= dacp::kTileElems) ++log2R;
+    // rows per tile: R * bc <= tile, R <= D, and R * ldx * sizeof(T) < 2^31 (32-bit in-tile offsets)
+    while ((int64_t(2) << log2R) <= D && (int64_t(2) << log2R) * bc <= ctx->tile_elems &&
+           (int64_t(2) << log2R) * ldx * static_cast<int64_t>(sizeof(T)) < (int64_t(1) << 31))
+      ++log2R;
     const int R = 1 << log2R;
     StepArgs<T> a;
     a.x = x + c0;
@@ -104,11 +154,12 @@ dacp_status step(dacp_ctx ctx, dacp_ham h, int b, const T *x, int64_t ldx, T *y,
     a.beta = beta;
     a.gamma = gamma;
     a.diag = std::is_same<T, double>::value ? reinterpret_cast<const T *>(h->d64) : reinterpret_cast<const T *>(h->d32);
-    a.flips = h->flips;
+    dacp_status ost = tile_order(ctx, h, log2R);
+    if (ost) return ost;
+    a.flips = h->by_log2r[log2R].dev;
     a.nflip = static_cast<int>(h->flips_host.size());
-    int nlow = 0;
-    while (nlow < a.nflip && h->flips_host[nlow].xmask < static_cast<uint32_t>(R)) ++nlow;
-    a.nlow = nlow;
+    a.nlow = h->by_log2r[log2R].nlow;
+    a.nhigh = h->by_log2r[log2R].nhigh;
     a.b = bc;
     a.log2R = log2R;
     a.ntiles = static_cast<int>(D >> log2R);
@@ -297,11 +348,17 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
         step<double>(ctx, h, gw, A, gw, B, gw, inv_e, nullptr, 0, 0.0, nullptr, 0, 0.0, store_of(1), ldv, 2);
     if (st) return st;
     ++launches;
+    const int64_t report_every = std::max<int64_t>(1, kmax / 8);
     for (int64_t k = 1; k < kmax; ++k) {
       st = step<double>(ctx, h, gw, B, gw, A, gw, 2.0 * inv_e, nullptr, 0, 0.0, A, gw, -1.0, store_of(k + 1), ldv, 2);
       if (st) return st;
       ++launches;
       std::swap(A, B);
+      if (verbose() && k % report_every == 0) {
+        (void)hipStreamSynchronize(ctx->stream);
+        vlog("evolution group %d/%d: step %lld of %lld", g0 / g + 1, (b + g - 1) / g, static_cast<long long>(k),
+             static_cast<long long>(kmax));
+      }
     }
   }
   const double evol_ms = tm.stop_ms();
@@ -585,6 +642,13 @@ void dacp_destroy(dacp_ctx ctx) {
 
 const char *dacp_last_error(dacp_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems) {
+  if (!ctx || tile_elems < 256 || tile_elems > 8192 || (tile_elems & (tile_elems - 1)))
+    return set_err(ctx, DACP_E_INVALID, "tile_elems must be a power of two in [256, 8192]");
+  ctx->tile_elems = tile_elems;
+  return DACP_OK;
+}
+
 dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream) {
   if (!ctx) return DACP_E_INVALID;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
@@ -682,6 +746,8 @@ dacp_status dacp_build_hamiltonian(dacp_ctx ctx, int L, int n_terms, const dacp_
 
 void dacp_free_hamiltonian(dacp_ham h) {
   if (!h) return;
+  for (auto &to : h->by_log2r)
+    if (to.dev) (void)hipFree(to.dev);
   if (h->d64) (void)hipFree(h->d64);
   if (h->d32) (void)hipFree(h->d32);
   if (h->flips) (void)hipFree(h->flips);
@@ -856,6 +922,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     rep.n = n;
     rep.m = m;
     rep.retries = attempt;
+    vlog("params: E_b=%.6g a=%.6g a_r=%.4g K=%d b=%d n=%d m=%d (attempt %d)", e_b, a, a_r, K, b, n, m, attempt);
 
     // filter (Sec. II.A)
     t0 = now_ms();
@@ -872,6 +939,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     st = run_filter(ctx, h, &fp, nullptr, psi.as<double>());
     if (st) return st;
     rep.t_filter_ms = now_ms() - t0;
+    vlog("filter done: %.1f ms", rep.t_filter_ms);
 
     // evolution basis (Sec. II.B, App. B/C)
     t0 = now_ms();
@@ -892,6 +960,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     rep.evol_steps = es.steps;
     rep.evol_launches = es.launches;
     rep.evol_kernel_ms = es.kernel_ms;
+    vlog("evolution done: %.1f ms (%lld launches)", rep.t_evol_ms, static_cast<long long>(es.launches));
 
     // projection (Sec. II.C)
     t0 = now_ms();
@@ -901,6 +970,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     st = run_project(ctx, h, m, vbuf.as<double>(), m, sb.as<double>(), pb.as<double>(), m);
     if (st) return st;
     rep.t_project_ms = now_ms() - t0;
+    vlog("projection done: %.1f ms", rep.t_project_ms);
 
     // generalised eigenproblem (App. C)
     t0 = now_ms();
@@ -913,6 +983,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     pb.release();
     rep.rank = r;
     rep.t_gep_ms = now_ms() - t0;
+    vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
 
     // acceptance (Sec. II.C residual check): candidates by |theta|
     t0 = now_ms();
@@ -922,12 +993,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
       const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
       return ai < aj || (ai == aj && theta[i] < theta[j]);
     });
-    const int n_sel = std::min(r, N + 16);
-    std::vector<double> gaps(r, INFINITY);
-    for (int i = 0; i < r; ++i) {
-      if (i > 0) gaps[i] = std::min(gaps[i], theta[i] - theta[i - 1]);
-      if (i + 1 < r) gaps[i] = std::min(gaps[i], theta[i + 1] - theta[i]);
-    }
+    const int n_sel = std::min(r, N + std::max(64, N / 8));
     std::vector<double> rnorm(n_sel, INFINITY);
     {
       const int cw = std::min(n_sel, 512);
@@ -962,27 +1028,83 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
         for (int i = 0; i < w; ++i) rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
       }
     }
-    // contiguous accepted core around 0 (walk outward in |theta|, stop at the first rejection)
-    std::vector<double> est(n_sel);
-    int core = 0;
-    double max_est = 0.0;
+    // Acceptance.  The Ritz residual r_j is orthogonal to the whole search space, which holds the
+    // converged neighbours of theta_j, so the quadratic residual bound |theta_j - lambda_j| <=
+    // ||r_j||^2 / eta_j uses eta_j = distance from theta_j to the part of the spectrum the subspace does
+    // not resolve: the nearest unaccepted Ritz value, or the window edge (levels beyond a are not
+    // represented).  Start from the candidates whose residual is below a generous cap, iterate to a
+    // fixed point, then keep the contiguous accepted core around 0 (walk outward in |theta|, stop at
+    // the first rejection).  The estimate reported is min(||r||, ||r||^2 / eta).
+    //
+    // A Ritz value whose residual exceeds ten mean level spacings of the window approximates no
+    // eigenvalue near it (a "ghost" built from weakly represented directions of the overcomplete
+    // basis): it is left out of eta and does not stop the core.  Central levels carry the largest
+    // filter amplitude, so a true level there is never that poorly represented.
+    std::vector<char> ok(r, 0), ghost(r, 0);
+    const double cap = 1e-4 * norm_est;
+    const double ghost_thr = 10.0 * (2.0 * a / n_w);
     for (int i = 0; i < n_sel; ++i) {
-      const double g = gaps[order[i]];
-      const double kt = (g > 0.0) ? rnorm[i] * rnorm[i] / g : INFINITY;
-      est[i] = std::min(rnorm[i], kt);
+      ok[order[i]] = rnorm[i] <= cap;
+      ghost[order[i]] = rnorm[i] > ghost_thr;
     }
-    while (core < n_sel && est[core] <= tol && std::fabs(theta[order[core]]) <= a) {
-      max_est = std::max(max_est, est[core]);
-      ++core;
+    int n_ghost = 0;
+    for (int i = 0; i < n_sel; ++i) n_ghost += ghost[order[i]];
+    std::vector<double> est(n_sel, INFINITY);
+    for (int iter = 0; iter < 8; ++iter) {
+      std::vector<double> unc;  // sorted Ritz values not (or no longer) accepted, ghosts excluded
+      for (int i = 0; i < r; ++i)
+        if (!ok[i] && !ghost[i]) unc.push_back(theta[i]);
+      bool changed = false;
+      for (int q = 0; q < n_sel; ++q) {
+        const int j = order[q];
+        if (!ok[j]) continue;
+        double eta = a - std::fabs(theta[j]);
+        auto it = std::lower_bound(unc.begin(), unc.end(), theta[j]);
+        if (it != unc.end()) eta = std::min(eta, *it - theta[j]);
+        if (it != unc.begin()) eta = std::min(eta, theta[j] - *(it - 1));
+        est[q] = (eta > 0.0) ? std::min(rnorm[q], rnorm[q] * rnorm[q] / eta) : rnorm[q];
+        if (!(est[q] <= tol)) {
+          ok[j] = 0;
+          changed = true;
+        }
+      }
+      if (!changed) break;
+    }
+    // walk outward in |theta|: ghosts are skipped, the first other rejection ends the core
+    std::vector<int> core_idx;  // positions q (into order) of the accepted core
+    double max_est = 0.0;
+    for (int q = 0; q < n_sel && std::fabs(theta[order[q]]) <= a; ++q) {
+      const int j = order[q];
+      if (ghost[j]) continue;
+      if (!ok[j]) break;
+      max_est = std::max(max_est, est[q]);
+      core_idx.push_back(q);
+    }
+    const int core = static_cast<int>(core_idx.size());
+    if (verbose()) {
+      int shown = 0;
+      for (int q = 0; q < n_sel && shown < 6; ++q) {
+        if (ok[order[q]] || ghost[order[q]]) continue;
+        const int j = order[q];
+        const double gl = j > 0 ? theta[j] - theta[j - 1] : INFINITY;
+        const double gr = j + 1 < r ? theta[j + 1] - theta[j] : INFINITY;
+        vlog("rejected #%d (|theta| rank %d): theta=%.10g r=%.3g est=%.3g gaps=(%.3g, %.3g) tol=%.3g", shown, q,
+             theta[j], rnorm[q], est[q], gl, gr, tol);
+        ++shown;
+      }
+      int n_ok = 0;
+      for (int q = 0; q < n_sel; ++q) n_ok += ok[order[q]] ? 1 : 0;
+      vlog("accepted (any position) %d of %d candidates; ghosts %d; contiguous core %d", n_ok, n_sel, n_ghost, core);
     }
     accepted = core;
     rep.n_candidates = n_sel;
     rep.n_accepted = core;
     rep.max_err_est = max_est;
     rep.t_accept_ms = now_ms() - t0;
+    vlog("acceptance done: %.1f ms, %d accepted of %d candidates", rep.t_accept_ms, core, n_sel);
     if (core >= N) {
       std::vector<std::pair<double, double>> sel;
-      for (int i = 0; i < N; ++i) sel.push_back({theta[order[i]], est[i]});
+      for (int i = 0; i < N; ++i) sel.push_back({theta[order[core_idx[i]]], est[core_idx[i]]});
       std::sort(sel.begin(), sel.end());
       for (int i = 0; i < N; ++i) {
         eigs_out[i] = sel[i].first;

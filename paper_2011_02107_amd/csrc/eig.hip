@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -122,20 +123,64 @@ __global__ void k_set_identity(double *Q, int64_t ldq, int n) {
   Q[i * ldq + j] = (i == j) ? 1.0 : 0.0;
 }
 
-// One implicit-QR sweep on rows p..q of Qc: for k = p..q-1,
-//   Qc[k] <- c Qc[k] - s Qc[k+1],  Qc[k+1] <- s Qc[k] + c Qc[k+1].
-__global__ __launch_bounds__(256) void k_rot_sweep(double *Qc, int64_t ldq, int ncols, int p, int q,
-                                                   const double *cs) {
-  const int col = blockIdx.x * 256 + threadIdx.x;
+// Replay of implicit-QR sweeps onto the rows of Qc.  Sweep i rotates, for
+// k = p_i..q_i-1:  Qc[k] <- c Qc[k] - s Qc[k+1],  Qc[k+1] <- s Qc[k] + c Qc[k+1].
+//
+// A batch of NSW consecutive sweeps is applied in one pass as a wavefront:
+// at time tau, sweep i applies its rotation k = tau - 2i.  Sweep i+1 touches
+// rows k, k+1 only after sweep i has finished row k+1 (its rotation k+1 ran
+// at tau - 1), and the sweeps active at one tau touch disjoint row pairs.
+// Each lane owns one column and keeps the last W = 2 NSW rows in registers:
+// row tau + 1 is loaded into the slot that row tau + 1 - W (final for every
+// sweep of the batch) is stored from, so each row is read and written once
+// per batch instead of once per sweep.
+constexpr int NSW = 16;
+constexpr int WIN = 2 * NSW;
+
+struct SweepBatch {
+  int p[NSW], q[NSW];
+  int64_t off[NSW];  // offset (in rotation pairs) of each sweep's rotations
+  int count;
+  int rmin, rmax;    // rows touched by the batch
+};
+
+__global__ __launch_bounds__(64) void k_rot_batch(double *Qc, int64_t ldq, int ncols, SweepBatch sb,
+                                                  const double *cs) {
+  const int col = blockIdx.x * 64 + threadIdx.x;
   if (col >= ncols) return;
-  double carry = Qc[static_cast<int64_t>(p) * ldq + col];
-  for (int k = p; k < q; ++k) {
-    const double c = cs[2 * (k - p)], s = cs[2 * (k - p) + 1];
-    const double zn = Qc[static_cast<int64_t>(k + 1) * ldq + col];
-    Qc[static_cast<int64_t>(k) * ldq + col] = c * carry - s * zn;
-    carry = s * carry + c * zn;
+  double *base = Qc + col;
+  double win[WIN];
+#pragma unroll
+  for (int u = 0; u < WIN; ++u) win[u] = 0.0;
+  // tau runs from rmin - 1 (load row rmin) to rmax + WIN - 1 (store row rmax); aligned so that
+  // slot (row mod WIN) is static inside the unrolled body.
+  const int tau_beg = sb.rmin - 1;
+  const int tau_end = sb.rmax + WIN - 1;
+  const int t0_beg = tau_beg - (((tau_beg % WIN) + WIN) % WIN);
+  for (int t0 = t0_beg; t0 <= tau_end; t0 += WIN) {
+#pragma unroll
+    for (int u = 0; u < WIN; ++u) {
+      const int tau = t0 + u;
+      const int slot = (u + 1) % WIN;  // slot of rows tau + 1 and tau + 1 - WIN
+      const int r_out = tau + 1 - WIN;
+      if (r_out >= sb.rmin && r_out <= sb.rmax) base[static_cast<int64_t>(r_out) * ldq] = win[slot];
+      const int r_in = tau + 1;
+      if (r_in >= sb.rmin && r_in <= sb.rmax) win[slot] = base[static_cast<int64_t>(r_in) * ldq];
+#pragma unroll
+      for (int i = 0; i < NSW; ++i) {
+        const int k = tau - 2 * i;
+        if (i < sb.count && k >= sb.p[i] && k < sb.q[i]) {
+          const int64_t o = sb.off[i] + (k - sb.p[i]);
+          const double c = cs[2 * o], s = cs[2 * o + 1];
+          const int sk = ((u - 2 * i) % WIN + WIN) % WIN;
+          const int sk1 = (sk + 1) % WIN;
+          const double xk = win[sk], xk1 = win[sk1];
+          win[sk] = c * xk - s * xk1;
+          win[sk1] = s * xk + c * xk1;
+        }
+      }
+    }
   }
-  Qc[static_cast<int64_t>(q) * ldq + col] = carry;
 }
 
 __global__ void k_gather_rows(const double *src, int64_t lds, double *dst, int64_t ldd, const int *perm,
@@ -261,8 +306,13 @@ bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, d
 // Eigen-decomposition of the symmetric n x n device matrix A (row-major, ld,
 // destroyed).  w (host) ascending; Zrows (device, n x n, ld n) row j =
 // eigenvector j, or nullptr for eigenvalues only.
+static double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows) {
   hipStream_t st = ctx->stream;
+  const double t_begin = wall_ms();
   if (n <= 0) return DACP_OK;
   if (n == 1) {
     DACP_HIP(ctx, hipMemcpyAsync(w, A, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -281,8 +331,13 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   DACP_HIP(ctx, hipMalloc(&de, sizeof(double) * n));
   DACP_HIP(ctx, hipMalloc(&db, sizeof(double) * n));
   DACP_HIP(ctx, hipMemsetAsync(db, 0, sizeof(double) * n, st));
+  const int report_every = std::max(1, n / 4);
   for (int k = 0; k < n - 2; ++k) {
     const int m = n - k - 1;
+    if (verbose() && k > 0 && k % report_every == 0) {
+      (void)hipStreamSynchronize(st);
+      vlog("eigensolver n=%d: tridiagonalised %d columns", n, k);
+    }
     hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, st, A, ld, n, k, dv, dd, de, db);
     hipLaunchKernelGGL(k_symv, dim3((m + 3) / 4), dim3(256), 0, st, A, ld, n, k, dv, db, dp);
     hipLaunchKernelGGL(k_wvec, dim3(1), dim3(1024), 0, st, dp, dv, db, n, k);
@@ -302,6 +357,7 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   e[n - 2] = tail[2];
   d[n - 1] = tail[3];
   e[n - 1] = 0.0;
+  const double t_tri = wall_ms();
 
   if (Zrows) {
     const int64_t nn = static_cast<int64_t>(n) * n;
@@ -311,7 +367,9 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
       hipLaunchKernelGGL(k_qupdate, dim3((rows + 3) / 4), dim3(256), 0, st, Zrows, (int64_t)n, A, ld, n, k, db);
     }
     DACP_HIP(ctx, hipGetLastError());
+    if (verbose()) (void)hipStreamSynchronize(st);
   }
+  const double t_q = wall_ms();
 
   // QR on the host; rotations batched into pinned memory and replayed on the GPU.
   const size_t flush_pairs = size_t(1) << 24;
@@ -333,9 +391,27 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
       he = hipMemcpyAsync(drot, pinned, rot.size() * sizeof(double), hipMemcpyHostToDevice, st);
     }
     if (he == hipSuccess) {
-      for (const Sweep &sw : sweeps)
-        hipLaunchKernelGGL(k_rot_sweep, dim3((n + 255) / 256), dim3(256), 0, st, Zrows, (int64_t)n, n, sw.p, sw.q,
-                           drot + 2 * sw.off);
+      for (size_t s0 = 0; s0 < sweeps.size(); s0 += NSW) {
+        SweepBatch sb;
+        sb.count = static_cast<int>(std::min<size_t>(NSW, sweeps.size() - s0));
+        sb.rmin = n;
+        sb.rmax = -1;
+        for (int i = 0; i < NSW; ++i) {
+          if (i < sb.count) {
+            const Sweep &sw = sweeps[s0 + i];
+            sb.p[i] = sw.p;
+            sb.q[i] = sw.q;
+            sb.off[i] = static_cast<int64_t>(sw.off);
+            sb.rmin = std::min(sb.rmin, sw.p);
+            sb.rmax = std::max(sb.rmax, sw.q);
+          } else {
+            sb.p[i] = 0;
+            sb.q[i] = 0;
+            sb.off[i] = 0;
+          }
+        }
+        hipLaunchKernelGGL(k_rot_batch, dim3((n + 63) / 64), dim3(64), 0, st, Zrows, (int64_t)n, n, sb, drot);
+      }
       he = hipGetLastError();
     }
     if (he != hipSuccess) frc = hip_err(ctx, he, "rotation replay");
@@ -348,7 +424,10 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
     sweeps.push_back(Sweep{p, q, rot.size() / 2});
     rot.insert(rot.end(), cs, cs + 2 * static_cast<size_t>(q - p));
   };
+  vlog("eigensolver n=%d: tridiagonal form ready, QR iteration%s", n, Zrows ? " with vectors" : "");
   const bool ok = tridiag_qr(d, e, n, sink);
+  const double t_qr = wall_ms();
+  vlog("eigensolver n=%d: QR done", n);
   if (ok && Zrows) flush();
   hipError_t he = hipStreamSynchronize(st);
   if (drot) (void)hipFree(drot);
@@ -358,6 +437,9 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   (void)hipFree(dd);
   (void)hipFree(de);
   (void)hipFree(db);
+  const double t_replay = wall_ms();
+  vlog("eigensolver n=%d timing: tridiagonalise %.0f ms, form Q %.0f ms, QR (host, overlapping replay) %.0f ms, "
+       "replay tail %.0f ms", n, t_tri - t_begin, t_q - t_tri, t_qr - t_q, t_replay - t_qr);
   if (frc != DACP_OK) return frc;
   if (he != hipSuccess) return hip_err(ctx, he, "eigensolver");
   dacp_status rc = ok ? DACP_OK : DACP_E_CONVERGENCE;

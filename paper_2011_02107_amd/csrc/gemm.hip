@@ -136,14 +136,15 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
     if (kt + 1 < nk) store_ab(buf ^ 1);
     __syncthreads();
   }
-  // Output layout of the 16x16 accumulator: lane l, item r -> row 4 (l / 16) + r, column l % 16.
+  // Output layout of the f64 16x16 accumulator (measured on gfx950): lane l,
+  // item r -> row (l / 16) + 4 r, column l % 16.
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
         const int64_t col = n0 + wn + j * 16 + (lane & 15);
         if (row < M && col < N) {
           double v = alpha * acc[i][j][r];

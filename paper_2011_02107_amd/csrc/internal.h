@@ -20,7 +20,7 @@ struct FlipEntry {
 
 constexpr int kMaxFlips = 1024;
 constexpr int kApplyThreads = 256;
-constexpr int kTileElems = 8192;  // elements of one LDS tile of the apply kernel
+constexpr int kTileElemsDefault = 1024;  // default elements of one LDS tile of the apply kernel
 
 // Arguments of the fused "apply + three-term combine" kernel:
 //   y = alpha * H x + beta * u + gamma * z      (u, z optional; z may alias y)
@@ -39,9 +39,10 @@ struct StepArgs {
   int64_t ldst;
   T alpha, beta, gamma;
   const T *diag;
-  const FlipEntry *flips;
+  const FlipEntry *flips;  // ordered: in-tile masks, masks above the tile, mixed masks
   int nflip;
-  int nlow;     // leading flips whose x-mask stays inside one tile
+  int nlow;     // flips whose x-mask stays inside one tile (LDS)
+  int nhigh;    // end of the flips whose x-mask lies entirely above the tile
   int b;        // columns
   int log2R;    // rows per tile = 2^log2R
   int ntiles;
@@ -118,7 +119,7 @@ struct dacp_ctx_s {
   size_t red_elems = 0;
   double *red_out = nullptr;
   size_t red_out_elems = 0;
-  hipEvent_t ev[8] = {};
+  int tile_elems = dacp::kTileElemsDefault;  // apply-kernel tile size (elements), power of two in [256, 8192]
 };
 
 struct dacp_ham_s {
@@ -130,12 +131,20 @@ struct dacp_ham_s {
   float *d32 = nullptr;   // same in FP32
   dacp::FlipEntry *flips = nullptr;
   std::vector<dacp::FlipEntry> flips_host;  // sorted by x-mask
+  struct TileOrder {
+    dacp::FlipEntry *dev = nullptr;
+    int nlow = 0, nhigh = 0;
+  };
+  TileOrder by_log2r[31];  // flip table ordered for a tile of 2^log2R rows (built on first use)
 };
 
 namespace dacp {
 // Error helpers used by the API layer.
 dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg);
 dacp_status hip_err(dacp_ctx ctx, hipError_t e, const char *what);
+// Progress lines on stderr when the environment variable DACP_VERBOSE is set.
+bool verbose();
+void vlog(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 // Dense symmetric eigensolver (eig.hip).
 dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
 bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z);

@@ -11,7 +11,7 @@ namespace dacp {
 // Fused apply + combine.
 //
 // A workgroup owns a tile of R = 2^log2R consecutive rows of the [D][b] block
-// (R * b <= kTileElems elements).  The tile of x is staged in LDS; flips whose
+// (R * b <= tile elements, 1024 by default).  The tile of x is staged in LDS; flips whose
 // x-mask lies below bit log2R stay inside the tile and read LDS, the others
 // read the partner rows s ^ x from global memory (L2 / MALL / HBM).  The
 // diagonal d(s) comes from the precomputed table.  Work-groups are dealt to
@@ -21,6 +21,14 @@ namespace dacp {
 // ---------------------------------------------------------------------------
 // ROLE only separates kernel symbols for profiling: 0 = plain apply / other,
 // 1 = filter recurrence, 2 = evolution recurrence.
+//
+// Every thread owns EPT elements e = tid + i * 256 of the tile.  Elements past
+// the tile end (only when R * b is not a multiple of 256) are clamped to the
+// last element for loading and skipped when storing, so every load below is
+// unconditional: the compiler then issues each term's EPT loads back to back
+// and waits once, instead of serialising them behind per-element branches.
+// For a flip whose mask lies above the tile, s ^ x = (row0 ^ x) + r, so the
+// partner address is a wave-uniform base plus the element's own offset.
 template <typename T, int EPT, int ROLE>
 __global__ __launch_bounds__(kApplyThreads) void k_step(StepArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
@@ -32,53 +40,120 @@ __global__ __launch_bounds__(kApplyThreads) void k_step(StepArgs<T> a) {
     t_id = (bid & 7) * per + (bid >> 3);
   }
   const int b = a.b;
-  const int R = 1 << a.log2R;
-  const int nel = R * b;
-  const int64_t row0 = (int64_t)t_id << a.log2R;
-  for (int e = threadIdx.x; e < nel; e += kApplyThreads) {
-    const int r = e / b;
-    const int j = e - r * b;
-    tile[e] = a.x[(row0 + r) * a.ldx + j];
-  }
-  __syncthreads();
+  const int nel = (1 << a.log2R) * b;
+  const uint32_t row0 = static_cast<uint32_t>(t_id) << a.log2R;
+  const int64_t ldx = a.ldx;
 
-  T acc[EPT];
   int rr[EPT], jj[EPT];
+  uint32_t off[EPT];  // byte offset of the element inside any tile-shaped slab (fits 32 bits, checked on the host)
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    int e = threadIdx.x + i * kApplyThreads;
+    e = e < nel ? e : nel - 1;
+    rr[i] = e / b;
+    jj[i] = e - rr[i] * b;
+    off[i] = static_cast<uint32_t>((static_cast<int64_t>(rr[i]) * ldx + jj[i]) * static_cast<int64_t>(sizeof(T)));
+  }
+  T own[EPT], dg[EPT];
+  {
+    const char *xb = reinterpret_cast<const char *>(a.x + static_cast<int64_t>(row0) * ldx);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) own[i] = *reinterpret_cast<const T *>(xb + off[i]);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) dg[i] = a.diag[row0 + rr[i]];
+  }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = threadIdx.x + i * kApplyThreads;
-    const int r = e / b;
-    rr[i] = r;
-    jj[i] = e - r * b;
-    acc[i] = (e < nel) ? a.diag[row0 + r] * tile[e] : T(0);
+    if (e < nel) tile[e] = own[i];
   }
+  T acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = dg[i] * own[i];
+  __syncthreads();
+
   for (int t = 0; t < a.nlow; ++t) {
     const uint32_t xm = a.flips[t].xmask;
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kApplyThreads;
-      if (e < nel) {
-        const uint32_t src = static_cast<uint32_t>(row0 + rr[i]) ^ xm;
-        const T sg = (__popc(src & zm) & 1) ? -c : c;
-        acc[i] += sg * tile[(rr[i] ^ static_cast<int>(xm)) * b + jj[i]];
+      const uint32_t src = (row0 + static_cast<uint32_t>(rr[i])) ^ xm;
+      const T sg = (__popc(src & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[(rr[i] ^ static_cast<int>(xm)) * b + jj[i]];
+    }
+  }
+  // High flips, UNR terms at a time so that UNR * EPT loads are in flight per wave.
+  constexpr int UNR = 4;
+  int t = a.nlow;
+  for (; t + UNR <= a.nhigh; t += UNR) {
+    T g[UNR][EPT];
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) {
+      const char *xp = reinterpret_cast<const char *>(a.x + static_cast<int64_t>(row0 ^ a.flips[t + q].xmask) * ldx);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) g[q][i] = *reinterpret_cast<const T *>(xp + off[i]);
+    }
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) {
+      const uint32_t pbase = row0 ^ a.flips[t + q].xmask;
+      const uint32_t zm = a.flips[t + q].zmask;
+      const T c = static_cast<T>(a.flips[t + q].coef);
+      if (zm == 0) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) acc[i] += c * g[q][i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+          const T sg = (__popc((pbase + static_cast<uint32_t>(rr[i])) & zm) & 1) ? -c : c;
+          acc[i] += sg * g[q][i];
+        }
       }
     }
   }
-  for (int t = a.nlow; t < a.nflip; ++t) {
+  for (; t < a.nhigh; ++t) {
     const uint32_t xm = a.flips[t].xmask;
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
+    const uint32_t pbase = row0 ^ xm;
+    const char *xp = reinterpret_cast<const char *>(a.x + static_cast<int64_t>(pbase) * ldx);
+    T g[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) g[i] = *reinterpret_cast<const T *>(xp + off[i]);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kApplyThreads;
-      if (e < nel) {
-        const uint32_t src = static_cast<uint32_t>(row0 + rr[i]) ^ xm;
-        const T sg = (__popc(src & zm) & 1) ? -c : c;
-        acc[i] += sg * a.x[static_cast<int64_t>(src) * a.ldx + jj[i]];
-      }
+      const T sg = (__popc((pbase + static_cast<uint32_t>(rr[i])) & zm) & 1) ? -c : c;
+      acc[i] += sg * g[i];
     }
+  }
+  // Masks with bits both inside and above the tile: partner row (row0 ^ x_hi) + (r ^ x_lo).
+  const uint32_t lowmask = (1u << a.log2R) - 1u;
+  for (; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const uint32_t xlo = xm & lowmask;
+    const uint32_t pbase = row0 ^ (xm & ~lowmask);
+    const T *xp = a.x + static_cast<int64_t>(pbase) * ldx;
+    T g[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) g[i] = xp[static_cast<int64_t>(rr[i] ^ static_cast<int>(xlo)) * ldx + jj[i]];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const uint32_t src = pbase + (static_cast<uint32_t>(rr[i]) ^ xlo);
+      const T sg = (__popc(src & zm) & 1) ? -c : c;
+      acc[i] += sg * g[i];
+    }
+  }
+
+  T uv[EPT], zv[EPT];
+  if (a.u) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) uv[i] = a.u[static_cast<int64_t>(row0 + rr[i]) * a.ldu + jj[i]];
+  }
+  if (a.z) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) zv[i] = a.z[static_cast<int64_t>(row0 + rr[i]) * a.ldz + jj[i]];
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
@@ -87,8 +162,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_step(StepArgs<T> a) {
       const int64_t s = row0 + rr[i];
       const int j = jj[i];
       T v = a.alpha * acc[i];
-      if (a.u) v += a.beta * a.u[s * a.ldu + j];
-      if (a.z) v += a.gamma * a.z[s * a.ldz + j];
+      if (a.u) v += a.beta * uv[i];
+      if (a.z) v += a.gamma * zv[i];
       a.y[s * a.ldy + j] = v;
       if (a.st) a.st[s * a.ldst + j] = static_cast<double>(v);
     }

@@ -99,11 +99,11 @@ def test_mfma_output_layout_single_tile(ctx):
 )
 def test_apply_f64_parity(ctx, L, b, which):
     terms = {
-        "chain": inputs.ising_chain(L),
-        "glass": inputs.spin_glass(L, L),
-        "random": random_real_terms(L, L, 25),
-        "paper_sgs": inputs.paper_sgs(L, 3),
-    }[which]
+        "chain": lambda: inputs.ising_chain(L),
+        "glass": lambda: inputs.spin_glass(L, L),
+        "random": lambda: random_real_terms(L, L, 25),
+        "paper_sgs": lambda: inputs.paper_sgs(L, 3),
+    }[which]()
     X = np.random.default_rng(L + b).standard_normal((1 << L, b))
     ref = hamiltonian.apply_h(L, terms, X)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
