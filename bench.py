@@ -117,8 +117,9 @@ def main():
     dt = time.perf_counter() - t0
     rep = reps[-1]
     D = 1 << L
-    g = args.group if 0 < args.group < rep["b"] else rep["b"]
-    # evolution kernel: reads T_k and T_{k-1}, writes T_{k+1}: 3 D g 8 algorithmic bytes per launch
+    g = rep["evol_group"]
+    # one evolution step of a column group reads T_k and T_{k-1} and writes T_{k+1}:
+    # 3 D g 8 algorithmic bytes per step (one step = the low-bit and the high-bit pass at L >= 15)
     bytes_per_launch = 3.0 * D * g * 8
     evol_launch_ms = rep["evol_kernel_ms"] / max(1, rep["evol_launches"])
     achieved = bytes_per_launch / (evol_launch_ms * 1e-3) / 1e9

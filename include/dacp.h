@@ -83,6 +83,18 @@ dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream);
  * flip one spin each, results are bit-identical for every tile size; with
  * multi-spin flips the term summation order, hence the rounding, may differ. */
 dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
+/* Set a tuning knob of the recurrence kernels (the autotuner's interface):
+ *   "tile"        single-pass apply tile, elements (same as dacp_set_tile)
+ *   "pass_tile"   tile of the two-pass / fused recurrence kernels, elements,
+ *                 power of two in [512, 16384] (default 4096; the fused kernels use <= 8192)
+ *   "two_pass_L"  smallest L using the two-pass kernels (0 disables; default 15)
+ *   "fused"       1 = alternating-split fused recurrence in the evolution (default), 0 = off
+ *   "group"       default recurrence column-group width when L >= 15 (power of two, default 4)
+ *   "dc"          dense eigensolver: eigenvectors by divide and conquer for n >= value
+ *                 (default 96; 0 = always implicit QR with replayed rotations)
+ * Results agree for every setting up to the rounding order of each element's sum.
+ * Returns DACP_E_INVALID for an unknown key or a value out of range. */
+dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value);
 /* Library version string (static storage). */
 const char *dacp_version(void);
 
@@ -143,7 +155,8 @@ typedef struct {
 /* psi_E = T_K(F) psi, F = (H^2 - E_c) / E_0, E_c = (E_b^2 + a^2)/2,
  * E_0 = (E_b^2 - a^2)/2, every column normalised to 1 (Sec. II.A, Eq. F,
  * Eq. target).  start: device [D][b] FP64 or NULL (seeded Gaussian).
- * psi_out: device [D][b] FP64.  With precision DACP_F32 the first
+ * psi_out: device [D][b] FP64.  Columns are filtered independently (in groups
+ * of 4 when L >= 15, so the working set stays cache resident).  With precision DACP_F32 the first
  * K - fp64_tail steps of the same recurrence run in FP32 (FP32 storage and
  * accumulation); the pair (T_{k-1}, T_k) is then converted to FP64 and the
  * last fp64_tail steps run in FP64.  Start and output must not overlap. */
@@ -156,7 +169,8 @@ typedef struct {
   double a;       /* a_r = a / e_bound                                         */
   int n;          /* number of sample pairs; basis width m = b (2n + 1)        */
   int b;          /* block width                                               */
-  int group;      /* evolve columns in groups of this width (0 = all b)        */
+  int group;      /* evolve columns in groups of this width (0 = library     */
+                  /* default: 4 when L >= 15 and b > 4, else all b)          */
 } dacp_basis_params;
 
 /* Chebyshev evolution T_{k+1} = 2 G T_k - T_{k-1} from psi_E (device [D][b]
@@ -200,7 +214,7 @@ dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N
 
 typedef struct {
   int b;               /* block width (default 64)                                    */
-  int group;           /* evolution column-group width, 0 = b                         */
+  int group;           /* recurrence column-group width, 0 = library default (above)  */
   double kfac;         /* K = ceil(kfac * E_b / a) (default 18, Sec. II.A)            */
   double window_ratio; /* levels wanted in [-a, a] = ceil(window_ratio * N) (2.2)     */
   double basis_ratio;  /* m = b (2n + 1) ~ basis_ratio * window count (1.5)           */
@@ -225,6 +239,8 @@ typedef struct {
   double t_bound_ms, t_filter_ms, t_evol_ms, t_project_ms, t_gep_ms, t_accept_ms, t_total_ms;
   double evol_kernel_ms;    /* HIP-event time of the evolution launches only        */
   double max_err_est;       /* largest accepted error estimate                      */
+  int evol_group;           /* column-group width the evolution ran with            */
+  int n_ghost;              /* candidates with residual above ten level spacings    */
 } dacp_report;
 
 /* Fill `opts` with the defaults listed above. */

@@ -102,6 +102,8 @@ class Report(ctypes.Structure):
         ("t_total_ms", ctypes.c_double),
         ("evol_kernel_ms", ctypes.c_double),
         ("max_err_est", ctypes.c_double),
+        ("evol_group", ctypes.c_int),
+        ("n_ghost", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -120,6 +122,7 @@ SIGNATURES = {
     "dacp_last_error": (ctypes.c_char_p, [_vp]),
     "dacp_set_stream": (ctypes.c_int, [_vp, _vp]),
     "dacp_set_tile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dacp_tune": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int]),
     "dacp_version": (ctypes.c_char_p, []),
     "dacp_build_hamiltonian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "dacp_free_hamiltonian": (None, [_vp]),
@@ -197,6 +200,9 @@ class Context:
 
     def set_tile(self, tile_elems):
         self.check(self.lib.dacp_set_tile(self.handle, int(tile_elems)))
+
+    def tune(self, key, value):
+        self.check(self.lib.dacp_tune(self.handle, key.encode(), int(value)))
 
     def close(self):
         if self.handle:

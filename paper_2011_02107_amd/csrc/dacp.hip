@@ -125,12 +125,125 @@ dacp_status tile_order(dacp_ctx ctx, dacp_ham h, int log2R) {
   return DACP_OK;
 }
 
+// Flip tables for the two-pass apply split at bit lo_bits.
+dacp_status split_order(dacp_ctx ctx, dacp_ham h, int lo_bits) {
+  auto &so = h->split[lo_bits];
+  if (so.lo) return DACP_OK;
+  const uint32_t lowmask = (1u << lo_bits) - 1u;
+  std::vector<FlipEntry> lo, hi, mx;
+  for (const FlipEntry &f : h->flips_host) {
+    if ((f.xmask & ~lowmask) == 0) lo.push_back(f);
+    else if ((f.xmask & lowmask) == 0) hi.push_back(f);
+    else mx.push_back(f);
+  }
+  hi.insert(hi.end(), mx.begin(), mx.end());
+  DACP_HIP(ctx, hipMalloc(&so.lo, std::max<size_t>(1, lo.size()) * sizeof(FlipEntry)));
+  DACP_HIP(ctx, hipMalloc(&so.hi, std::max<size_t>(1, hi.size()) * sizeof(FlipEntry)));
+  if (!lo.empty()) DACP_HIP(ctx, hipMemcpy(so.lo, lo.data(), lo.size() * sizeof(FlipEntry), hipMemcpyHostToDevice));
+  if (!hi.empty()) DACP_HIP(ctx, hipMemcpy(so.hi, hi.data(), hi.size() * sizeof(FlipEntry), hipMemcpyHostToDevice));
+  so.nlo = static_cast<int>(lo.size());
+  so.nhi = static_cast<int>(hi.size() - mx.size());
+  so.nmix = static_cast<int>(mx.size());
+  return DACP_OK;
+}
+
+// Two-pass apply (low-bit tiles, then high-bit cosets), used when both tiles fit the budget.
+// Returns false (nothing launched) when the shape does not allow it.
+template <typename T>
+bool two_pass_plan(dacp_ctx ctx, dacp_ham h, int b, int &lo_bits, int &W) {
+  if (ctx->two_pass_min_L <= 0 || h->L < ctx->two_pass_min_L) return false;
+  if (b & (b - 1)) return false;  // the pass kernels split elements with shifts
+  const int64_t P = ctx->pass_tile_elems;
+  const int L = h->L;
+  lo_bits = 0;
+  while (lo_bits + 1 < L && (int64_t(2) << lo_bits) * b <= P) ++lo_bits;
+  const int hi_bits = L - lo_bits;
+  if (lo_bits < 1 || hi_bits < 1 || (int64_t(1) << hi_bits) * b > P) return false;
+  if ((int64_t(1) << lo_bits) * b < 1024) return false;  // both kernels need whole 1024-element rounds
+  W = 1;
+  while (W < 8 && (int64_t(2 * W) << hi_bits) * b <= P && 2 * W <= (1 << lo_bits) &&
+         ((1 << lo_bits) / (2 * W)) >= 256)
+    W *= 2;
+  if ((int64_t(W) << hi_bits) * b < 1024) return false;
+  return true;
+}
+
+// Fused alternating-split recurrence plan for a contiguous [D][g] block of FP64:
+// both tiles (2^lo_bits rows and 2^(L - lo_bits) rows of g columns) hold 512..8192 elements,
+// and no flip mask straddles bit lo_bits.
+bool fused_plan(dacp_ctx ctx, dacp_ham h, int g, int &lo_bits) {
+  if (!ctx->fused_rec || ctx->two_pass_min_L <= 0 || h->L < ctx->two_pass_min_L) return false;
+  if (g & (g - 1)) return false;
+  const int L = h->L;
+  const int64_t P = std::min(ctx->pass_tile_elems, 8192);
+  int min_hi = 0;  // smallest high part whose tile still holds 512 elements
+  while ((int64_t(1) << min_hi) * g < 512) ++min_hi;
+  lo_bits = 0;  // largest low part whose tile fits, leaving at least min_hi high bits
+  while (lo_bits + 1 <= L - min_hi && (int64_t(2) << lo_bits) * g <= P) ++lo_bits;
+  const int hi_bits = L - lo_bits;
+  if (lo_bits < 1 || hi_bits < 1) return false;
+  const int64_t nlo = (int64_t(1) << lo_bits) * g, nhi = (int64_t(1) << hi_bits) * g;
+  if (nlo > P || nhi > P || nlo < 512 || nhi < 512) return false;
+  const uint32_t lowmask = (1u << lo_bits) - 1u;
+  for (const FlipEntry &f : h->flips_host)
+    if ((f.xmask & lowmask) && (f.xmask & ~lowmask)) return false;
+  return true;
+}
+
 // y = alpha H x + beta u + gamma z (+ FP64 copy into st), columns split in chunks of <= 2048.
 template <typename T>
 dacp_status step(dacp_ctx ctx, dacp_ham h, int b, const T *x, int64_t ldx, T *y, int64_t ldy, T alpha,
                  const T *u = nullptr, int64_t ldu = 0, T beta = T(0), const T *z = nullptr, int64_t ldz = 0,
                  T gamma = T(0), double *st = nullptr, int64_t ldst = 0, int role = 0) {
   const int64_t D = h->D;
+  int lo_bits = 0, W = 1;
+  if (x != y && two_pass_plan<T>(ctx, h, b, lo_bits, W)) {
+    dacp_status sst = split_order(ctx, h, lo_bits);
+    if (sst) return sst;
+    const auto &so = h->split[lo_bits];
+    StepArgs<T> a;
+    a.x = x;
+    a.ldx = ldx;
+    a.y = y;
+    a.ldy = ldy;
+    a.u = u;
+    a.ldu = ldu;
+    a.z = z;
+    a.ldz = ldz;
+    a.st = nullptr;
+    a.ldst = 0;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.gamma = gamma;
+    a.diag = std::is_same<T, double>::value ? reinterpret_cast<const T *>(h->d64) : reinterpret_cast<const T *>(h->d32);
+    a.flips = so.lo;
+    a.nflip = so.nlo;
+    a.nlow = so.nlo;
+    a.nhigh = so.nlo;
+    a.b = b;
+    a.log2R = lo_bits;
+    a.ntiles = static_cast<int>(D >> lo_bits);
+    a.xcd_remap = 0;
+    DACP_HIP(ctx, dacp::launch_step_lo<T>(a, ctx->stream, role));
+    dacp::HiArgs<T> hb;
+    hb.x = x;
+    hb.ldx = ldx;
+    hb.y = y;
+    hb.ldy = ldy;
+    hb.st = st;
+    hb.ldst = ldst;
+    hb.alpha = alpha;
+    hb.flips = so.hi;
+    hb.nhi = so.nhi;
+    hb.nflip = so.nhi + so.nmix;
+    hb.b = b;
+    hb.lo_bits = lo_bits;
+    hb.hi_bits = h->L - lo_bits;
+    hb.W = W;
+    hb.ntiles = (1 << lo_bits) / W;
+    DACP_HIP(ctx, dacp::launch_step_hi<T>(hb, ctx->stream, role));
+    return DACP_OK;
+  }
   for (int c0 = 0; c0 < b; c0 += 2048) {
     const int bc = std::min(2048, b - c0);
     int log2R = 0;
@@ -236,6 +349,60 @@ dacp_status normalise_cols(dacp_ctx ctx, double *x, int64_t D, int b) {
   return DACP_OK;
 }
 
+// Filter one contiguous [D][g] group of start columns (FP32 part, then FP64 steps); the
+// newest recurrence term ends in `out` (D x g, FP64, not normalised).
+dacp_status filter_group(dacp_ctx ctx, dacp_ham h, int g, const FilterCoefs &fc, int K, int tail_in, int precision,
+                         const double *psi, double *out) {
+  const int64_t D = h->D;
+  const size_t blk = static_cast<size_t>(D) * g;
+  if (K == 0) {
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi, g, out, g, D, g, ctx->stream));
+    return DACP_OK;
+  }
+  DevBuf a64, w64, b64;
+  DACP_HIP(ctx, a64.alloc(blk * sizeof(double)));
+  DACP_HIP(ctx, w64.alloc(blk * sizeof(double)));
+  DACP_HIP(ctx, b64.alloc(blk * sizeof(double)));
+  double *A = a64.as<double>(), *B = b64.as<double>();
+  int tail = (precision == DACP_F32) ? std::max(0, std::min(tail_in, K)) : K;
+  const int n32 = K - tail;  // orders reached in FP32
+  dacp_status st = DACP_OK;
+  if (n32 >= 1) {
+    DevBuf a32, b32, w32, p32;
+    DACP_HIP(ctx, a32.alloc(blk * sizeof(float)));
+    DACP_HIP(ctx, b32.alloc(blk * sizeof(float)));
+    DACP_HIP(ctx, w32.alloc(blk * sizeof(float)));
+    DACP_HIP(ctx, p32.alloc(blk * sizeof(float)));
+    DACP_HIP(ctx, dacp::launch_convert_f64_to_f32(psi, g, p32.as<float>(), g, D, g, ctx->stream));
+    float *A32 = a32.as<float>(), *B32 = b32.as<float>();
+    DACP_HIP(ctx, dacp::launch_convert_f64_to_f32(psi, g, A32, g, D, g, ctx->stream));
+    st = filter_first<float>(ctx, h, g, fc, p32.as<float>(), B32, w32.as<float>());
+    if (st) return st;
+    st = filter_steps<float>(ctx, h, g, fc, A32, B32, w32.as<float>(), n32 - 1);
+    if (st) return st;
+    DACP_HIP(ctx, dacp::launch_convert_f32_to_f64(A32, g, A, g, D, g, ctx->stream));
+    DACP_HIP(ctx, dacp::launch_convert_f32_to_f64(B32, g, B, g, D, g, ctx->stream));
+    DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // FP32 buffers are released at scope end
+  } else {
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi, g, A, g, D, g, ctx->stream));
+    st = filter_first<double>(ctx, h, g, fc, psi, B, w64.as<double>());
+    if (st) return st;
+    tail = K - 1;
+  }
+  st = filter_steps<double>(ctx, h, g, fc, A, B, w64.as<double>(), tail);
+  if (st) return st;
+  DACP_HIP(ctx, dacp::launch_copy_cols(B, g, out, g, D, g, ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return DACP_OK;
+}
+
+// Column-group width for the recurrences: the columns are independent, and a narrow group keeps
+// the recurrence's working set (two or three [D][g] blocks) inside the 256 MB Infinity Cache.
+int recurrence_group(dacp_ctx ctx, dacp_ham h, int b) {
+  if (h->L >= 15 && b > ctx->group_default) return ctx->group_default;
+  return b;
+}
+
 dacp_status run_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, const double *start, double *psi_out) {
   const int64_t D = h->D;
   const int b = p->b;
@@ -243,57 +410,32 @@ dacp_status run_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, co
     return set_err(ctx, DACP_E_INVALID, "filter: need b >= 1, K >= 0, 0 < a < e_bound, psi_out");
   if (p->precision != DACP_F64 && p->precision != DACP_F32)
     return set_err(ctx, DACP_E_INVALID, "filter: precision must be DACP_F64 or DACP_F32");
-  const size_t blk = static_cast<size_t>(D) * b;
   FilterCoefs fc;
   fc.e_c = 0.5 * (p->e_bound * p->e_bound + p->a * p->a);
   fc.e_0 = 0.5 * (p->e_bound * p->e_bound - p->a * p->a);
   fc.rho = std::exp(std::acosh(1.0 + 2.0 * p->a * p->a / (p->e_bound * p->e_bound - p->a * p->a)));
-  DevBuf s0, a64, b64, w64;
+  DevBuf s0;
   const double *psi = start;
   if (!psi) {
-    DACP_HIP(ctx, s0.alloc(blk * sizeof(double)));
+    DACP_HIP(ctx, s0.alloc(static_cast<size_t>(D) * b * sizeof(double)));
     DACP_HIP(ctx, dacp::launch_philox_gauss(s0.as<double>(), D, b, p->seed, ctx->stream));
     psi = s0.as<double>();
   }
-  DACP_HIP(ctx, a64.alloc(blk * sizeof(double)));
-  DACP_HIP(ctx, b64.alloc(blk * sizeof(double)));
-  DACP_HIP(ctx, w64.alloc(blk * sizeof(double)));
-  double *A = a64.as<double>(), *B = b64.as<double>();
-  const int K = p->K;
-  dacp_status st = DACP_OK;
-  if (K == 0) {
-    DACP_HIP(ctx, dacp::launch_copy_cols(psi, b, B, b, D, b, ctx->stream));
-  } else {
-    int tail = (p->precision == DACP_F32) ? std::max(0, std::min(p->fp64_tail, K)) : K;
-    const int n32 = K - tail;  // steps (orders) reached in FP32
-    if (n32 >= 1) {
-      DevBuf a32, b32, w32, p32;
-      DACP_HIP(ctx, a32.alloc(blk * sizeof(float)));
-      DACP_HIP(ctx, b32.alloc(blk * sizeof(float)));
-      DACP_HIP(ctx, w32.alloc(blk * sizeof(float)));
-      DACP_HIP(ctx, p32.alloc(blk * sizeof(float)));
-      DACP_HIP(ctx, dacp::launch_convert_f64_to_f32(psi, b, p32.as<float>(), b, D, b, ctx->stream));
-      float *A32 = a32.as<float>(), *B32 = b32.as<float>();
-      DACP_HIP(ctx, dacp::launch_convert_f64_to_f32(psi, b, A32, b, D, b, ctx->stream));
-      st = filter_first<float>(ctx, h, b, fc, p32.as<float>(), B32, w32.as<float>());
-      if (st) return st;
-      st = filter_steps<float>(ctx, h, b, fc, A32, B32, w32.as<float>(), n32 - 1);
-      if (st) return st;
-      DACP_HIP(ctx, dacp::launch_convert_f32_to_f64(A32, b, A, b, D, b, ctx->stream));
-      DACP_HIP(ctx, dacp::launch_convert_f32_to_f64(B32, b, B, b, D, b, ctx->stream));
-      DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // FP32 buffers are released at scope end
-    } else {
-      DACP_HIP(ctx, dacp::launch_copy_cols(psi, b, A, b, D, b, ctx->stream));
-      st = filter_first<double>(ctx, h, b, fc, psi, B, w64.as<double>());
-      if (st) return st;
-      tail = K - 1;
-    }
-    st = filter_steps<double>(ctx, h, b, fc, A, B, w64.as<double>(), tail);
+  const int g = recurrence_group(ctx, h, b);
+  DevBuf gin, gout;
+  DACP_HIP(ctx, gin.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, gout.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  for (int g0 = 0; g0 < b; g0 += g) {
+    const int gw = std::min(g, b - g0);
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi + g0, b, gin.as<double>(), gw, D, gw, ctx->stream));
+    dacp_status st = filter_group(ctx, h, gw, fc, p->K, p->fp64_tail, p->precision, gin.as<double>(),
+                                  gout.as<double>());
     if (st) return st;
+    DACP_HIP(ctx, dacp::launch_copy_cols(gout.as<double>(), gw, psi_out + g0, b, D, gw, ctx->stream));
+    vlog("filter group %d/%d done", g0 / g + 1, (b + g - 1) / g);
   }
-  st = normalise_cols(ctx, B, D, b);
+  dacp_status st = normalise_cols(ctx, psi_out, D, b);
   if (st) return st;
-  DACP_HIP(ctx, dacp::launch_copy_cols(B, b, psi_out, b, D, b, ctx->stream));
   DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DACP_OK;
 }
@@ -308,6 +450,7 @@ std::vector<int64_t> sample_orders(double a_r, int n) {
 struct EvolStats {
   int64_t steps = 0, launches = 0;
   double kernel_ms = 0.0;
+  int group = 0;
 };
 
 dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *V,
@@ -326,10 +469,11 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
     panel_of[ks[i]] = 2 * i + 2;
   }
   const int64_t kmax = ks.back();
-  const int g = (p->group > 0 && p->group < b) ? p->group : b;
-  DevBuf ba, bb, nrm;
+  const int g = (p->group > 0 && p->group < b) ? p->group : recurrence_group(ctx, h, b);
+  DevBuf ba, bb, nrm, pbuf;
   DACP_HIP(ctx, ba.alloc(static_cast<size_t>(D) * g * sizeof(double)));
   DACP_HIP(ctx, bb.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, pbuf.alloc(static_cast<size_t>(D) * g * sizeof(double)));
   DACP_HIP(ctx, nrm.alloc(static_cast<size_t>(n) * b * sizeof(double)));
   const double inv_e = 1.0 / p->e_bound;
   Timer tm(ctx);
@@ -349,6 +493,73 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
     if (st) return st;
     ++launches;
     const int64_t report_every = std::max<int64_t>(1, kmax / 8);
+    int lo_bits = 0;
+    if (kmax > 1 && fused_plan(ctx, h, gw, lo_bits)) {
+      // P_2 = (2/E)(D + Lo) T_1 - T_0 by the low-bit pass, then alternate high / low fused kernels.
+      st = split_order(ctx, h, lo_bits);
+      if (st) return st;
+      const auto &so = h->split[lo_bits];
+      double *Pp = pbuf.as<double>();
+      {
+        StepArgs<double> sa;
+        std::memset(&sa, 0, sizeof(sa));
+        sa.x = B;
+        sa.ldx = gw;
+        sa.y = Pp;
+        sa.ldy = gw;
+        sa.z = A;
+        sa.ldz = gw;
+        sa.alpha = 2.0 * inv_e;
+        sa.gamma = -1.0;
+        sa.diag = h->d64;
+        sa.flips = so.lo;
+        sa.nflip = so.nlo;
+        sa.nlow = so.nlo;
+        sa.nhigh = so.nlo;
+        sa.b = gw;
+        sa.log2R = lo_bits;
+        sa.ntiles = static_cast<int>(D >> lo_bits);
+        DACP_HIP(ctx, dacp::launch_step_lo<double>(sa, ctx->stream, 2));
+      }
+      dacp::RecArgs<double> ra;
+      std::memset(&ra, 0, sizeof(ra));
+      ra.ld = gw;
+      ra.ldst = ldv;
+      ra.alpha = 2.0 * inv_e;
+      ra.diag = h->d64;
+      ra.b = gw;
+      ra.lo_bits = lo_bits;
+      ra.hi_bits = h->L - lo_bits;
+      ra.p = Pp;
+      for (int64_t k = 1; k < kmax; ++k) {
+        // produce T_{k+1} from T_k (B) and the partial; T_{k+1} overwrites T_{k-1} (A)
+        ra.tcur = B;
+        ra.tnew = A;
+        ra.st = store_of(k + 1);
+        const bool hi_turn = (k % 2) == 1;
+        if (hi_turn) {
+          ra.flips = so.hi;
+          ra.nflip = so.nhi;
+          ra.ntiles = 1 << lo_bits;
+          ra.xcd_remap = (ra.ntiles % 8 == 0) ? 1 : 0;
+          DACP_HIP(ctx, dacp::launch_rec_hi<double>(ra, ctx->stream));
+        } else {
+          ra.flips = so.lo;
+          ra.nflip = so.nlo;
+          ra.ntiles = static_cast<int>(D >> lo_bits);
+          ra.xcd_remap = (ra.ntiles % 8 == 0) ? 1 : 0;
+          DACP_HIP(ctx, dacp::launch_rec_lo<double>(ra, ctx->stream));
+        }
+        ++launches;
+        std::swap(A, B);
+        if (verbose() && k % report_every == 0) {
+          (void)hipStreamSynchronize(ctx->stream);
+          vlog("evolution group %d/%d: step %lld of %lld (fused)", g0 / g + 1, (b + g - 1) / g,
+               static_cast<long long>(k), static_cast<long long>(kmax));
+        }
+      }
+      continue;
+    }
     for (int64_t k = 1; k < kmax; ++k) {
       st = step<double>(ctx, h, gw, B, gw, A, gw, 2.0 * inv_e, nullptr, 0, 0.0, A, gw, -1.0, store_of(k + 1), ldv, 2);
       if (st) return st;
@@ -385,6 +596,7 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
     stats->steps = kmax;
     stats->launches = launches;
     stats->kernel_ms = evol_ms;
+    stats->group = g;
   }
   return DACP_OK;
 }
@@ -649,6 +861,39 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems) {
   return DACP_OK;
 }
 
+dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
+  if (!ctx || !key) return DACP_E_INVALID;
+  const std::string k(key);
+  const bool pow2 = value > 0 && (value & (value - 1)) == 0;
+  if (k == "tile") return dacp_set_tile(ctx, value);
+  if (k == "pass_tile") {
+    if (!pow2 || value < 512 || value > 16384) return set_err(ctx, DACP_E_INVALID, "pass_tile: power of two in [512, 16384]");
+    ctx->pass_tile_elems = value;
+    return DACP_OK;
+  }
+  if (k == "two_pass_L") {
+    if (value < 0 || value > 31) return set_err(ctx, DACP_E_INVALID, "two_pass_L: 0..31");
+    ctx->two_pass_min_L = value;
+    return DACP_OK;
+  }
+  if (k == "fused") {
+    if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "fused: 0 or 1");
+    ctx->fused_rec = value;
+    return DACP_OK;
+  }
+  if (k == "dc") {
+    if (value < 0) return set_err(ctx, DACP_E_INVALID, "dc: smallest size for divide and conquer (0 = never)");
+    ctx->dc_min_n = value;
+    return DACP_OK;
+  }
+  if (k == "group") {
+    if (!pow2 || value > 64) return set_err(ctx, DACP_E_INVALID, "group: power of two <= 64");
+    ctx->group_default = value;
+    return DACP_OK;
+  }
+  return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
+}
+
 dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream) {
   if (!ctx) return DACP_E_INVALID;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
@@ -746,6 +991,10 @@ dacp_status dacp_build_hamiltonian(dacp_ctx ctx, int L, int n_terms, const dacp_
 
 void dacp_free_hamiltonian(dacp_ham h) {
   if (!h) return;
+  for (auto &so : h->split) {
+    if (so.lo) (void)hipFree(so.lo);
+    if (so.hi) (void)hipFree(so.hi);
+  }
   for (auto &to : h->by_log2r)
     if (to.dev) (void)hipFree(to.dev);
   if (h->d64) (void)hipFree(h->d64);
@@ -960,6 +1209,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     rep.evol_steps = es.steps;
     rep.evol_launches = es.launches;
     rep.evol_kernel_ms = es.kernel_ms;
+    rep.evol_group = es.group;
     vlog("evolution done: %.1f ms (%lld launches)", rep.t_evol_ms, static_cast<long long>(es.launches));
 
     // projection (Sec. II.C)
@@ -1100,6 +1350,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     rep.n_candidates = n_sel;
     rep.n_accepted = core;
     rep.max_err_est = max_est;
+    rep.n_ghost = n_ghost;
     rep.t_accept_ms = now_ms() - t0;
     vlog("acceptance done: %.1f ms, %d accepted of %d candidates", rep.t_accept_ms, core, n_sel);
     if (core >= N) {

@@ -49,9 +49,67 @@ struct StepArgs {
   int xcd_remap;
 };
 
+// Arguments of the high-bit pass of the two-pass apply: the tile is the coset
+// {l0 + w + (j << lo_bits) : w < W, j < 2^(L - lo_bits)}, l0 = tile * W, and
+//   y += alpha * sum over flips with every mask bit >= lo_bits (from LDS)
+//      + alpha * sum over mixed-mask flips (partner rows gathered from global)
+// followed by the optional FP64 sample store.
+template <typename T>
+struct HiArgs {
+  const T *x;
+  int64_t ldx;
+  T *y;
+  int64_t ldy;
+  double *st;
+  int64_t ldst;
+  T alpha;
+  const FlipEntry *flips;  // high-range flips, then mixed flips
+  int nhi;
+  int nflip;
+  int b;
+  int lo_bits;
+  int hi_bits;
+  int W;
+  int ntiles;
+};
+
+// Fused alternating-split recurrence kernels for T_{j+1} = alpha H T_j - T_{j-1},
+// H = (D + Lo) + Hi (diagonal and flips below bit lo_bits | flips at or above it).
+// With the partial P holding either alpha (D + Lo) T_j - T_{j-1} ("A first") or
+// alpha Hi T_j - T_{j-1} ("B first"), one kernel completes a step and starts the next:
+//   lo tile kernel:  T_new = P + alpha (D + Lo) T_cur ;  P <- alpha (D + Lo) T_new - T_cur
+//   hi coset kernel: T_new = P + alpha Hi T_cur       ;  P <- alpha Hi T_new - T_cur
+// T_new is written over the buffer of the term before T_cur; P is updated in place.
+template <typename T>
+struct RecArgs {
+  const T *tcur;
+  T *tnew;
+  T *p;
+  double *st;   // optional FP64 copy of T_new (basis sample), row stride ldst
+  int64_t ldst;
+  int64_t ld;   // row stride of tcur, tnew, p (= b)
+  T alpha;
+  const T *diag;
+  const FlipEntry *flips;
+  int nflip;
+  int b;
+  int lo_bits;
+  int hi_bits;
+  int ntiles;
+  int xcd_remap;
+};
+
 // Launch helpers (kernels.hip).
 template <typename T>
+hipError_t launch_rec_lo(const RecArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_rec_hi(const RecArgs<T> &a, hipStream_t s);
+template <typename T>
 hipError_t launch_step(const StepArgs<T> &a, hipStream_t s, int role);
+template <typename T>
+hipError_t launch_step_hi(const HiArgs<T> &a, hipStream_t s, int role);
+template <typename T>
+hipError_t launch_step_lo(const StepArgs<T> &a, hipStream_t s, int role);
 
 hipError_t launch_diag(const uint32_t *zm, const double *c, int nterm, int64_t D, double *d64, float *d32,
                        hipStream_t s);
@@ -120,6 +178,11 @@ struct dacp_ctx_s {
   double *red_out = nullptr;
   size_t red_out_elems = 0;
   int tile_elems = dacp::kTileElemsDefault;  // apply-kernel tile size (elements), power of two in [256, 8192]
+  int two_pass_min_L = 15;    // use the two-pass apply from this L on (0 disables it)
+  int fused_rec = 1;          // alternating-split fused recurrence in the evolution (0 disables it)
+  int pass_tile_elems = 4096;  // elements per LDS tile of the two-pass / fused kernels
+  int group_default = 4;       // recurrence column-group width for L >= 15
+  int dc_min_n = 96;           // eigenvectors by divide and conquer from this size on (0 = never)
 };
 
 struct dacp_ham_s {
@@ -136,6 +199,12 @@ struct dacp_ham_s {
     int nlow = 0, nhigh = 0;
   };
   TileOrder by_log2r[31];  // flip table ordered for a tile of 2^log2R rows (built on first use)
+  struct SplitOrder {
+    dacp::FlipEntry *lo = nullptr;  // flips with every mask bit < lo_bits
+    dacp::FlipEntry *hi = nullptr;  // flips with every mask bit >= lo_bits, then mixed ones
+    int nlo = 0, nhi = 0, nmix = 0;
+  };
+  SplitOrder split[31];  // flip tables for the two-pass apply with lo_bits = index
 };
 
 namespace dacp {
@@ -148,6 +217,7 @@ void vlog(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 // Dense symmetric eigensolver (eig.hip).
 dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
 bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z);
+dacp_status dc_tridiag(dacp_ctx ctx, int n, const double *d, const double *e, double *w, double *Z);
 }  // namespace dacp
 
 #define DACP_HIP(ctx, call)                                  \

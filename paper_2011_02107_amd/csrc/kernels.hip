@@ -196,6 +196,354 @@ template hipError_t launch_step<double>(const StepArgs<double> &, hipStream_t, i
 template hipError_t launch_step<float>(const StepArgs<float> &, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
+// Low-bit pass of the two-pass apply: a tile of 2^log2R consecutive rows in
+// LDS, every flip of the list has its mask below bit log2R, no global gathers:
+//   y = alpha (d x + sum_t c_t sign_t x[s ^ m_t]) + beta u + gamma z.
+// 1024 threads, EPT elements each; b is a power of two (b = 2^lb), so the
+// element -> (row, column) split is a shift and a mask.
+// ---------------------------------------------------------------------------
+template <typename T, int EPT, int ROLE>
+__global__ __launch_bounds__(1024) void k_step_lo(StepArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+  const int lb = __ffs(a.b) - 1;
+  const int nel = (1 << a.log2R) << lb;
+  const uint32_t row0 = static_cast<uint32_t>(blockIdx.x) << a.log2R;
+  const T *xb = a.x + static_cast<int64_t>(row0) * a.ldx;
+  T acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 1024;
+    const int r = e >> lb, j = e & (a.b - 1);
+    const T v = xb[static_cast<int64_t>(r) * a.ldx + j];
+    tile[e] = v;
+    acc[i] = a.diag[row0 + r] * v;
+  }
+  __syncthreads();
+  for (int t = 0; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const int sh = static_cast<int>(xm) << lb;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * 1024;
+      const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[e ^ sh];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 1024;
+    const int64_t r = row0 + (e >> lb);
+    const int j = e & (a.b - 1);
+    T v = a.alpha * acc[i];
+    if (a.u) v += a.beta * a.u[r * a.ldu + j];
+    if (a.z) v += a.gamma * a.z[r * a.ldz + j];
+    a.y[r * a.ldy + j] = v;
+  }
+  (void)nel;
+}
+
+template <typename T, int ROLE>
+hipError_t launch_step_lo_role(const StepArgs<T> &a, hipStream_t s) {
+  const int nel = (1 << a.log2R) * a.b;
+  const int ept = (nel + 1023) / 1024;
+  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
+  dim3 grid(a.ntiles), block(1024);
+  if (ept <= 1) hipLaunchKernelGGL((k_step_lo<T, 1, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 2) hipLaunchKernelGGL((k_step_lo<T, 2, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 4) hipLaunchKernelGGL((k_step_lo<T, 4, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 8) hipLaunchKernelGGL((k_step_lo<T, 8, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 16) hipLaunchKernelGGL((k_step_lo<T, 16, ROLE>), grid, block, lds, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_lo(const StepArgs<T> &a, hipStream_t s, int role) {
+  if (role == 1) return launch_step_lo_role<T, 1>(a, s);
+  if (role == 2) return launch_step_lo_role<T, 2>(a, s);
+  return launch_step_lo_role<T, 0>(a, s);
+}
+template hipError_t launch_step_lo<double>(const StepArgs<double> &, hipStream_t, int);
+template hipError_t launch_step_lo<float>(const StepArgs<float> &, hipStream_t, int);
+
+// ---------------------------------------------------------------------------
+// High-bit pass of the two-pass apply.  1024 threads; element e of the tile is
+// (j, w, col) with col fastest, then w, then j (b = 2^lb, W = 2^lw), so the W
+// adjacent rows of one j form a contiguous W * b run in memory and in LDS.
+// Every flip whose mask lies in the high bits maps j to j ^ (mask >> lo_bits)
+// inside the tile, i.e. e to e ^ ((mask >> lo_bits) << (lw + lb)).
+// ---------------------------------------------------------------------------
+template <typename T, int EPT, int ROLE>
+__global__ __launch_bounds__(1024) void k_step_hi(HiArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+  const int lb = __ffs(a.b) - 1;
+  const int lw = __ffs(a.W) - 1;
+  const uint32_t l0 = static_cast<uint32_t>(blockIdx.x) << lw;
+  const uint32_t lomask_w = (1u << lw) - 1u;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 1024;
+    const uint32_t t = static_cast<uint32_t>(e) >> lb;
+    const uint32_t row = l0 + (t & lomask_w) + ((t >> lw) << a.lo_bits);
+    tile[e] = a.x[static_cast<int64_t>(row) * a.ldx + (e & (a.b - 1))];
+  }
+  T acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = T(0);
+  __syncthreads();
+  for (int t = 0; t < a.nhi; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const int sh = static_cast<int>(xm >> a.lo_bits) << (lw + lb);
+    if (zm == 0) {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 1024) ^ sh];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * 1024;
+        const uint32_t tt = static_cast<uint32_t>(e) >> lb;
+        const uint32_t row = l0 + (tt & lomask_w) + ((tt >> lw) << a.lo_bits);
+        const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[e ^ sh];
+      }
+    }
+  }
+  for (int t = a.nhi; t < a.nflip; ++t) {  // masks with bits in both halves: gather from global
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+#pragma unroll 4
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * 1024;
+      const uint32_t tt = static_cast<uint32_t>(e) >> lb;
+      const uint32_t row = l0 + (tt & lomask_w) + ((tt >> lw) << a.lo_bits);
+      const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * a.x[static_cast<int64_t>(row ^ xm) * a.ldx + (e & (a.b - 1))];
+    }
+  }
+#pragma unroll 8
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 1024;
+    const uint32_t tt = static_cast<uint32_t>(e) >> lb;
+    const int64_t row = l0 + (tt & lomask_w) + ((tt >> lw) << a.lo_bits);
+    const int j = e & (a.b - 1);
+    const T v = a.y[row * a.ldy + j] + a.alpha * acc[i];
+    a.y[row * a.ldy + j] = v;
+    if (a.st) a.st[row * a.ldst + j] = static_cast<double>(v);
+  }
+}
+
+template <typename T, int ROLE>
+hipError_t launch_step_hi_role(const HiArgs<T> &a, hipStream_t s) {
+  const int nel = (a.W << a.hi_bits) * a.b;
+  const int ept = (nel + 1023) / 1024;
+  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
+  dim3 grid(a.ntiles), block(1024);
+  if (ept <= 1) hipLaunchKernelGGL((k_step_hi<T, 1, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 2) hipLaunchKernelGGL((k_step_hi<T, 2, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 4) hipLaunchKernelGGL((k_step_hi<T, 4, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 8) hipLaunchKernelGGL((k_step_hi<T, 8, ROLE>), grid, block, lds, s, a);
+  else if (ept <= 16) hipLaunchKernelGGL((k_step_hi<T, 16, ROLE>), grid, block, lds, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_hi(const HiArgs<T> &a, hipStream_t s, int role) {
+  if (role == 1) return launch_step_hi_role<T, 1>(a, s);
+  if (role == 2) return launch_step_hi_role<T, 2>(a, s);
+  return launch_step_hi_role<T, 0>(a, s);
+}
+template hipError_t launch_step_hi<double>(const HiArgs<double> &, hipStream_t, int);
+template hipError_t launch_step_hi<float>(const HiArgs<float> &, hipStream_t, int);
+
+// ---------------------------------------------------------------------------
+// Fused alternating-split recurrence (see RecArgs).  512 threads, EPT elements
+// each; b = 2^lb.  Both kernels keep T_cur of their own elements in registers,
+// complete T_new from LDS, then stage T_new in LDS to start the next step.
+// ---------------------------------------------------------------------------
+template <typename T, int EPT>
+__global__ __launch_bounds__(512) void k_rec_lo(RecArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+  const int lb = __ffs(a.b) - 1;
+  int bid = blockIdx.x;
+  if (a.xcd_remap) bid = (bid & 7) * (a.ntiles >> 3) + (bid >> 3);
+  const uint32_t row0 = static_cast<uint32_t>(bid) << a.lo_bits;
+  const int64_t base = static_cast<int64_t>(row0) * a.ld;  // tiles are contiguous (ld == b)
+  T cur[EPT], dg[EPT], nw[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 512;
+    cur[i] = a.tcur[base + e];
+    dg[i] = a.diag[row0 + (e >> lb)];
+    nw[i] = a.p[base + e];
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = cur[i];
+  __syncthreads();
+  T acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = dg[i] * cur[i];
+  for (int t = 0; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const int sh = static_cast<int>(xm) << lb;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * 512;
+      const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[e ^ sh];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 512;
+    nw[i] += a.alpha * acc[i];
+    a.tnew[base + e] = nw[i];
+    if (a.st) a.st[static_cast<int64_t>(row0 + (e >> lb)) * a.ldst + (e & (a.b - 1))] = static_cast<double>(nw[i]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = nw[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = dg[i] * nw[i];
+  for (int t = 0; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const int sh = static_cast<int>(xm) << lb;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * 512;
+      const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[e ^ sh];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) a.p[base + threadIdx.x + i * 512] = a.alpha * acc[i] - cur[i];
+}
+
+// Coset tile of the high bits: rows l0 + (j << lo_bits), j < 2^hi_bits (W = 1); element
+// e = (j << lb) | col, so a high flip maps e to e ^ ((mask >> lo_bits) << lb).
+template <typename T, int EPT>
+__global__ __launch_bounds__(512) void k_rec_hi(RecArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+  const int lb = __ffs(a.b) - 1;
+  int bid = blockIdx.x;
+  if (a.xcd_remap) bid = (bid & 7) * (a.ntiles >> 3) + (bid >> 3);
+  const uint32_t l0 = static_cast<uint32_t>(bid);
+  T cur[EPT], nw[EPT];
+  int64_t off[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 512;
+    const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
+    off[i] = static_cast<int64_t>(row) * a.ld + (e & (a.b - 1));
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    cur[i] = a.tcur[off[i]];
+    nw[i] = a.p[off[i]];
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = cur[i];
+  __syncthreads();
+  T acc[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = T(0);
+  for (int t = 0; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const int sh = static_cast<int>(xm >> a.lo_bits) << lb;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * 512;
+      const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
+      const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[e ^ sh];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * 512;
+    nw[i] += a.alpha * acc[i];
+    a.tnew[off[i]] = nw[i];
+    if (a.st) {
+      const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
+      a.st[static_cast<int64_t>(row) * a.ldst + (e & (a.b - 1))] = static_cast<double>(nw[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = nw[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) acc[i] = T(0);
+  for (int t = 0; t < a.nflip; ++t) {
+    const uint32_t xm = a.flips[t].xmask;
+    const uint32_t zm = a.flips[t].zmask;
+    const T c = static_cast<T>(a.flips[t].coef);
+    const int sh = static_cast<int>(xm >> a.lo_bits) << lb;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * 512;
+      const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
+      const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[e ^ sh];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) a.p[off[i]] = a.alpha * acc[i] - cur[i];
+}
+
+template <typename T>
+hipError_t launch_rec_lo(const RecArgs<T> &a, hipStream_t s) {
+  const int nel = (1 << a.lo_bits) * a.b;
+  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
+  dim3 grid(a.ntiles), block(512);
+  switch (nel / 512) {
+    case 1: hipLaunchKernelGGL((k_rec_lo<T, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_rec_lo<T, 2>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_rec_lo<T, 4>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_rec_lo<T, 8>), grid, block, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k_rec_lo<T, 16>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rec_hi(const RecArgs<T> &a, hipStream_t s) {
+  const int nel = (1 << a.hi_bits) * a.b;
+  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
+  dim3 grid(a.ntiles), block(512);
+  switch (nel / 512) {
+    case 1: hipLaunchKernelGGL((k_rec_hi<T, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_rec_hi<T, 2>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_rec_hi<T, 4>), grid, block, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_rec_hi<T, 8>), grid, block, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k_rec_hi<T, 16>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_rec_lo<double>(const RecArgs<double> &, hipStream_t);
+template hipError_t launch_rec_lo<float>(const RecArgs<float> &, hipStream_t);
+template hipError_t launch_rec_hi<double>(const RecArgs<double> &, hipStream_t);
+template hipError_t launch_rec_hi<float>(const RecArgs<float> &, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // Diagonal table d(s) = sum_t c_t (-1)^popcount(s & z_t)  (x-mask-free terms).
 // ---------------------------------------------------------------------------
 __global__ void k_diag(const uint32_t *zm, const double *c, int nterm, int64_t D, double *d64, float *d32) {

@@ -113,6 +113,31 @@ def test_apply_f64_parity(ctx, L, b, which):
     assert np.abs(host(dy) - ref).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize(
+    "L,b,which",
+    [(15, 8, "chain"), (16, 8, "glass"), (15, 4, "random"), (16, 16, "paper_sgs"), (15, 1, "chain"), (16, 2, "paper_sgs")],
+)
+def test_apply_two_pass_parity(ctx, L, b, which):
+    """L >= 15 with a power-of-two width runs the two-pass apply (low-bit tiles, then high-bit
+    cosets, mixed masks gathered); same tolerance as the single-pass kernel."""
+    terms = {
+        "chain": lambda: inputs.ising_chain(L),
+        "glass": lambda: inputs.spin_glass(L, L),
+        "random": lambda: random_real_terms(L, L, 25),
+        "paper_sgs": lambda: inputs.paper_sgs(L, 3),
+    }[which]()
+    X = np.random.default_rng(L * b).standard_normal((1 << L, b))
+    ref = hamiltonian.apply_h(L, terms, X)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    dy = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    B.dacp_apply(ctx, ham, to_dev(X), dy)
+    scale = hamiltonian.sum_abs_coeff(terms) * np.abs(X).max()
+    assert np.abs(host(dy) - ref).max() <= 1e-14 * scale
+    dy32 = torch.empty((1 << L, b), dtype=torch.float32, device=DEV)
+    B.dacp_apply(ctx, ham, to_dev(X, torch.float32), dy32)
+    assert np.abs(host(dy32).astype(np.float64) - ref).max() <= 1e-6 * scale
+
+
 def test_apply_f32_parity(ctx):
     L, b = 12, 32
     terms = inputs.ising_chain(L)
@@ -200,6 +225,21 @@ def test_filter_f64_parity(ctx, L, b, kfac):
     assert np.abs(host(out) - ref).max() < 1e-10
 
 
+def test_filter_grouped_two_pass_parity(ctx):
+    """L = 15, b = 16: the filter runs per column group of 8 with the two-pass apply."""
+    L, b = 15, 16
+    terms = inputs.spin_glass(L, 11)
+    eb = 1.01 * hamiltonian.sum_abs_coeff(terms)
+    a = 0.3 * eb
+    K = chebyshev.filter_order(eb, a, 12.0)
+    psi = np.random.default_rng(6).standard_normal((1 << L, b))
+    ref = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, K)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    out = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    B.dacp_filter(ctx, ham, out, eb, a, K, start=to_dev(psi))
+    assert np.abs(host(out) - ref).max() < 1e-10
+
+
 def test_filter_f32_with_fp64_tail(ctx):
     """FP32 recurrence then an FP64 tail: the output stays within FP32-rounding
     distance of the FP64 oracle filter (window components dominate)."""
@@ -248,6 +288,21 @@ def test_basis_column_groups_match_full_block(ctx):
     assert np.array_equal(host(V1), host(V2))
 
 
+def test_basis_two_pass_groups_match_oracle(ctx):
+    """L = 15 runs the evolution in column groups of 8 with the two-pass apply."""
+    L, b, n = 15, 16, 2
+    terms = inputs.ising_chain(L)
+    eb = 1.01 * (1.723 * L)  # above ||H|| for this chain (checked by the norm guard of dacp_basis)
+    a = 0.3 * eb
+    psi = np.random.default_rng(5).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0)
+    ref, ks = chebyshev.chebyshev_basis(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, n)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    V = torch.zeros((1 << L, b * (2 * n + 1)), dtype=torch.float64, device=DEV)
+    B.dacp_basis(ctx, ham, to_dev(psi), V, eb, a, n)
+    assert np.abs(host(V) - ref).max() < 1e-15 * max(ks) + 1e-12
+
+
 def test_basis_detects_bound_below_norm(ctx):
     L = 8
     terms = inputs.ising_chain(L)
@@ -290,6 +345,46 @@ def test_syev_parity(ctx, n):
     Zr = host(Z)  # rows are eigenvectors
     assert np.abs(Zr @ A @ Zr.T - np.diag(w)).max() < 1e-12 * max(1.0, np.abs(w).max()) * n
     assert np.abs(Zr @ Zr.T - np.eye(n)).max() < 1e-13 * n
+
+
+def _check_eig(ctx, A, tol_scale=1.0):
+    n = A.shape[0]
+    w_ref = _native.syev(A)
+    Z = torch.zeros((n, n), dtype=torch.float64, device=DEV)
+    w = B.dacp_syev(ctx, to_dev(A), Z)
+    scale = max(1.0, np.abs(w_ref).max())
+    assert np.abs(w - w_ref).max() < 1e-12 * scale * max(1, n) ** 0.5 * tol_scale
+    Zr = host(Z)
+    assert np.abs(Zr @ A @ Zr.T - np.diag(w)).max() < 1e-12 * scale * n * tol_scale
+    assert np.abs(Zr @ Zr.T - np.eye(n)).max() < 1e-13 * n
+
+
+@pytest.mark.parametrize("n", [97, 1000, 2047])
+def test_syev_divide_and_conquer_random(ctx, n):
+    A = np.random.default_rng(n).standard_normal((n, n))
+    _check_eig(ctx, A + A.T)
+
+
+def test_syev_divide_and_conquer_deflation_cases(ctx):
+    n = 300
+    rng = np.random.default_rng(1)
+    # diagonal: every z component deflates
+    _check_eig(ctx, np.diag(rng.standard_normal(n)))
+    # repeated eigenvalues: identity plus a rank-two update
+    u = rng.standard_normal((n, 2))
+    _check_eig(ctx, np.eye(n) + u @ u.T)
+    # clustered spectrum from a random orthogonal similarity
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat([-1.0, 0.0, 2.0], n // 3) + 1e-10 * rng.standard_normal(n)
+    _check_eig(ctx, (q * lam) @ q.T)
+
+
+def test_syev_gram_like_psd(ctx):
+    """Overlap-matrix-like input: PSD of rank ~ 2/3 n with a wide spread of eigenvalues."""
+    n, r = 600, 400
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((r, n)) * np.logspace(0, -7, n)[None, :]
+    _check_eig(ctx, X.T @ X)
 
 
 def test_rayleigh_ritz_parity(ctx):
