@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--workload", default="chain_L20_N5000", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="plain", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
+    ap.add_argument("--window-ratio", type=float, default=None)
+    ap.add_argument("--tail", type=float, default=None, help="FP64 tail fraction of the filter (tuned mode)")
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
@@ -45,10 +47,14 @@ def opts_for(args, wl):
     if args.mode == "plain":
         o = B.default_opts(b=wl["b"], kfac=18.0, window_ratio=2.2, precision=B.DACP_F64, group=args.group)
     else:
-        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=1.8, basis_ratio=1.25, precision=B.DACP_F32,
-                           fp64_tail_frac=0.2, group=args.group)
+        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.2, basis_ratio=1.25, precision=B.DACP_F32,
+                           fp64_tail_frac=0.3, group=args.group)
     if args.kfac:
         o.kfac = args.kfac
+    if args.window_ratio:
+        o.window_ratio = args.window_ratio
+    if args.tail is not None:
+        o.fp64_tail_frac = args.tail
     return o
 
 

@@ -89,7 +89,10 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *                 power of two in [512, 16384] (default 4096; the fused kernels use <= 8192)
  *   "two_pass_L"  smallest L using the two-pass kernels (0 disables; default 15)
  *   "fused"       1 = alternating-split fused recurrence in the evolution (default), 0 = off
- *   "group"       default recurrence column-group width when L >= 15 (power of two, default 4)
+ *   "group"       evolution column-group width when L >= 15 (power of two, default 4)
+ *   "filter_group_f64", "filter_group_f32"
+ *                 filter column-group width when L >= 15 for the FP64 / FP32 recurrence
+ *                 (power of two, defaults 8 and 16)
  *   "dc"          dense eigensolver: eigenvectors by divide and conquer for n >= value
  *                 (default 96; 0 = always implicit QR with replayed rotations)
  * Results agree for every setting up to the rounding order of each element's sum.

@@ -421,7 +421,10 @@ dacp_status run_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, co
     DACP_HIP(ctx, dacp::launch_philox_gauss(s0.as<double>(), D, b, p->seed, ctx->stream));
     psi = s0.as<double>();
   }
-  const int g = recurrence_group(ctx, h, b);
+  // the filter moves 5 blocks per order (apply, apply + combine): a wider group than the
+  // evolution's keeps its launches long enough to stream at full rate
+  const int gf = p->precision == DACP_F32 ? ctx->filter_group_f32 : ctx->filter_group_f64;
+  const int g = (h->L >= 15 && b > gf) ? gf : b;
   DevBuf gin, gout;
   DACP_HIP(ctx, gin.alloc(static_cast<size_t>(D) * g * sizeof(double)));
   DACP_HIP(ctx, gout.alloc(static_cast<size_t>(D) * g * sizeof(double)));
@@ -884,6 +887,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
   if (k == "dc") {
     if (value < 0) return set_err(ctx, DACP_E_INVALID, "dc: smallest size for divide and conquer (0 = never)");
     ctx->dc_min_n = value;
+    return DACP_OK;
+  }
+  if (k == "filter_group_f64" || k == "filter_group_f32") {
+    if (!pow2 || value > 64) return set_err(ctx, DACP_E_INVALID, k + ": power of two <= 64");
+    (k == "filter_group_f64" ? ctx->filter_group_f64 : ctx->filter_group_f32) = value;
     return DACP_OK;
   }
   if (k == "group") {

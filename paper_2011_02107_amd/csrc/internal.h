@@ -182,6 +182,8 @@ struct dacp_ctx_s {
   int fused_rec = 1;          // alternating-split fused recurrence in the evolution (0 disables it)
   int pass_tile_elems = 4096;  // elements per LDS tile of the two-pass / fused kernels
   int group_default = 4;       // recurrence column-group width for L >= 15
+  int filter_group_f64 = 8;    // filter column-group width for L >= 15, FP64 recurrence
+  int filter_group_f32 = 16;   // filter column-group width for L >= 15, FP32 recurrence
   int dc_min_n = 96;           // eigenvectors by divide and conquer from this size on (0 = never)
 };
 

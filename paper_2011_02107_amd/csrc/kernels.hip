@@ -76,11 +76,16 @@ __global__ __launch_bounds__(kApplyThreads) void k_step(StepArgs<T> a) {
     const uint32_t xm = a.flips[t].xmask;
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
+    if (zm == 0) {  // X-type term: no sign (wave-uniform branch)
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const uint32_t src = (row0 + static_cast<uint32_t>(rr[i])) ^ xm;
-      const T sg = (__popc(src & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[(rr[i] ^ static_cast<int>(xm)) * b + jj[i]];
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(rr[i] ^ static_cast<int>(xm)) * b + jj[i]];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const uint32_t src = (row0 + static_cast<uint32_t>(rr[i])) ^ xm;
+        const T sg = (__popc(src & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[(rr[i] ^ static_cast<int>(xm)) * b + jj[i]];
+      }
     }
   }
   // High flips, UNR terms at a time so that UNR * EPT loads are in flight per wave.
@@ -225,11 +230,16 @@ __global__ __launch_bounds__(1024) void k_step_lo(StepArgs<T> a) {
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
     const int sh = static_cast<int>(xm) << lb;
+    if (zm == 0) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * 1024;
-      const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[e ^ sh];
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 1024) ^ sh];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * 1024;
+        const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[e ^ sh];
+      }
     }
   }
 #pragma unroll
@@ -396,11 +406,16 @@ __global__ __launch_bounds__(512) void k_rec_lo(RecArgs<T> a) {
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
     const int sh = static_cast<int>(xm) << lb;
+    if (zm == 0) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * 512;
-      const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[e ^ sh];
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * 512;
+        const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[e ^ sh];
+      }
     }
   }
 #pragma unroll
@@ -421,11 +436,16 @@ __global__ __launch_bounds__(512) void k_rec_lo(RecArgs<T> a) {
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
     const int sh = static_cast<int>(xm) << lb;
+    if (zm == 0) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * 512;
-      const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[e ^ sh];
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * 512;
+        const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[e ^ sh];
+      }
     }
   }
 #pragma unroll
@@ -466,12 +486,17 @@ __global__ __launch_bounds__(512) void k_rec_hi(RecArgs<T> a) {
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
     const int sh = static_cast<int>(xm >> a.lo_bits) << lb;
+    if (zm == 0) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * 512;
-      const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
-      const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[e ^ sh];
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * 512;
+        const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
+        const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[e ^ sh];
+      }
     }
   }
 #pragma unroll
@@ -495,12 +520,17 @@ __global__ __launch_bounds__(512) void k_rec_hi(RecArgs<T> a) {
     const uint32_t zm = a.flips[t].zmask;
     const T c = static_cast<T>(a.flips[t].coef);
     const int sh = static_cast<int>(xm >> a.lo_bits) << lb;
+    if (zm == 0) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * 512;
-      const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
-      const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[e ^ sh];
+      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * 512;
+        const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
+        const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
+        acc[i] += sg * tile[e ^ sh];
+      }
     }
   }
 #pragma unroll
