@@ -161,7 +161,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step<double, *, 2> (evolution recurrence)",
+            "kernel": "k_rec_lo / k_rec_hi (fused evolution recurrence, FP64)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

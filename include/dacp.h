@@ -85,11 +85,18 @@ dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream);
 dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
 /* Set a tuning knob of the recurrence kernels (the autotuner's interface):
  *   "tile"        single-pass apply tile, elements (same as dacp_set_tile)
- *   "pass_tile"   tile of the two-pass / fused recurrence kernels, elements,
- *                 power of two in [512, 16384] (default 4096; the fused kernels use <= 8192)
+ *   "pass_tile"   tile of the two-pass apply kernels, elements,
+ *                 power of two in [512, 16384] (default 4096)
  *   "two_pass_L"  smallest L using the two-pass kernels (0 disables; default 15)
  *   "fused"       1 = alternating-split fused recurrence in the evolution (default), 0 = off
- *   "group"       evolution column-group width when L >= 15 (power of two, default 4)
+ *   "rec_tile"    largest tile of the fused recurrence kernels, elements (power of two in
+ *                 [1024, 8192], default 8192)
+ *   "rec_hi_w"    fused recurrence: adjacent rows per high-bit tile (0 = automatic: enough
+ *                 for 128-byte runs; else 1, 2, 4 or 8)
+ *   "rec_threads" fused recurrence: threads per workgroup, 512 or 1024 (default 1024)
+ *   "rec_persist" fused recurrence: 0 = one workgroup per tile (default); n = 1..8 persistent
+ *                 workgroups per compute unit that prefetch their next tile
+ *   "group"       evolution column-group width when L >= 15 (power of two, default 8)
  *   "filter_group_f64", "filter_group_f32"
  *                 filter column-group width when L >= 15 for the FP64 / FP32 recurrence
  *                 (power of two, defaults 8 and 16)

@@ -136,6 +136,14 @@ dacp_status split_order(dacp_ctx ctx, dacp_ham h, int lo_bits) {
     else if ((f.xmask & lowmask) == 0) hi.push_back(f);
     else mx.push_back(f);
   }
+  // sign-free (X-type, z-mask 0) flips first within each pure part: the fused kernels run them
+  // in an unrolled loop without the parity sign
+  auto plain_first = [](std::vector<FlipEntry> &v) {
+    return static_cast<int>(std::stable_partition(v.begin(), v.end(), [](const FlipEntry &f) { return f.zmask == 0; }) -
+                            v.begin());
+  };
+  so.nlo_plain = plain_first(lo);
+  so.nhi_plain = plain_first(hi);
   hi.insert(hi.end(), mx.begin(), mx.end());
   DACP_HIP(ctx, hipMalloc(&so.lo, std::max<size_t>(1, lo.size()) * sizeof(FlipEntry)));
   DACP_HIP(ctx, hipMalloc(&so.hi, std::max<size_t>(1, hi.size()) * sizeof(FlipEntry)));
@@ -168,26 +176,43 @@ bool two_pass_plan(dacp_ctx ctx, dacp_ham h, int b, int &lo_bits, int &W) {
   return true;
 }
 
-// Fused alternating-split recurrence plan for a contiguous [D][g] block of FP64:
-// both tiles (2^lo_bits rows and 2^(L - lo_bits) rows of g columns) hold 512..8192 elements,
-// and no flip mask straddles bit lo_bits.
-bool fused_plan(dacp_ctx ctx, dacp_ham h, int g, int &lo_bits) {
+// Fused alternating-split recurrence plan for a contiguous [D][g] block of FP64.  The low
+// tile (2^lo_bits rows) and the high tile (W adjacent rows x 2^(L - lo_bits) cosets) each hold
+// 2, 4 or 8 16-byte vectors per thread and at most rec_tile elements (64 KB of LDS), the high
+// tile's contiguous runs of W rows fill whole 128-byte lines where possible, and no flip mask
+// straddles bit lo_bits.
+bool fused_plan(dacp_ctx ctx, dacp_ham h, int g, int &lo_bits, int &W) {
   if (!ctx->fused_rec || ctx->two_pass_min_L <= 0 || h->L < ctx->two_pass_min_L) return false;
-  if (g & (g - 1)) return false;
+  if ((g & (g - 1)) || g < 2) return false;
   const int L = h->L;
-  const int64_t P = std::min(ctx->pass_tile_elems, 8192);
-  int min_hi = 0;  // smallest high part whose tile still holds 512 elements
-  while ((int64_t(1) << min_hi) * g < 512) ++min_hi;
-  lo_bits = 0;  // largest low part whose tile fits, leaving at least min_hi high bits
-  while (lo_bits + 1 <= L - min_hi && (int64_t(2) << lo_bits) * g <= P) ++lo_bits;
-  const int hi_bits = L - lo_bits;
-  if (lo_bits < 1 || hi_bits < 1) return false;
-  const int64_t nlo = (int64_t(1) << lo_bits) * g, nhi = (int64_t(1) << hi_bits) * g;
-  if (nlo > P || nhi > P || nlo < 512 || nhi < 512) return false;
-  const uint32_t lowmask = (1u << lo_bits) - 1u;
-  for (const FlipEntry &f : h->flips_host)
-    if ((f.xmask & lowmask) && (f.xmask & ~lowmask)) return false;
-  return true;
+  const int64_t P = std::min<int64_t>(ctx->rec_tile_elems, 8192);
+  const int64_t nt = ctx->rec_threads;
+  auto ok_tile = [&](int64_t nel) {
+    const int64_t per = nel / 2 / nt;  // 16-byte vectors per thread
+    return nel <= P && nel % (2 * nt) == 0 && (per == 1 || per == 2 || per == 4) && nel >= 1024 &&
+           nel <= 16384;
+  };
+  int w0 = ctx->rec_hi_w;
+  if (w0 <= 0) {
+    w0 = 1;
+    while (w0 * g * 8 < 128 && w0 < 8) w0 *= 2;
+  }
+  const uint32_t all = (L >= 32) ? 0xffffffffu : ((1u << L) - 1u);
+  for (W = w0; W >= 1; W /= 2) {
+    for (lo_bits = L - 1; lo_bits >= 1; --lo_bits) {
+      const int hi_bits = L - lo_bits;
+      if ((int64_t(1) << lo_bits) < W) break;
+      const int64_t nlo = (int64_t(1) << lo_bits) * g, nhi = (int64_t(W) << hi_bits) * g;
+      if (!ok_tile(nlo) || !ok_tile(nhi)) continue;
+      const uint32_t lowmask = (1u << lo_bits) - 1u;
+      bool straddle = false;
+      for (const FlipEntry &f : h->flips_host)
+        if ((f.xmask & lowmask) && (f.xmask & ~lowmask & all)) straddle = true;
+      if (straddle) continue;
+      return true;
+    }
+  }
+  return false;
 }
 
 // y = alpha H x + beta u + gamma z (+ FP64 copy into st), columns split in chunks of <= 2048.
@@ -496,8 +521,8 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
     if (st) return st;
     ++launches;
     const int64_t report_every = std::max<int64_t>(1, kmax / 8);
-    int lo_bits = 0;
-    if (kmax > 1 && fused_plan(ctx, h, gw, lo_bits)) {
+    int lo_bits = 0, hw = 1;
+    if (kmax > 1 && fused_plan(ctx, h, gw, lo_bits, hw)) {
       // P_2 = (2/E)(D + Lo) T_1 - T_0 by the low-bit pass, then alternate high / low fused kernels.
       st = split_order(ctx, h, lo_bits);
       if (st) return st;
@@ -533,6 +558,9 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
       ra.b = gw;
       ra.lo_bits = lo_bits;
       ra.hi_bits = h->L - lo_bits;
+      ra.W = hw;
+      ra.threads = ctx->rec_threads;
+      ra.grid = ctx->rec_persist * ctx->num_cus;
       ra.p = Pp;
       for (int64_t k = 1; k < kmax; ++k) {
         // produce T_{k+1} from T_k (B) and the partial; T_{k+1} overwrites T_{k-1} (A)
@@ -543,12 +571,14 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
         if (hi_turn) {
           ra.flips = so.hi;
           ra.nflip = so.nhi;
-          ra.ntiles = 1 << lo_bits;
+          ra.nplain = so.nhi_plain;
+          ra.ntiles = (1 << lo_bits) / hw;
           ra.xcd_remap = (ra.ntiles % 8 == 0) ? 1 : 0;
           DACP_HIP(ctx, dacp::launch_rec_hi<double>(ra, ctx->stream));
         } else {
           ra.flips = so.lo;
           ra.nflip = so.nlo;
+          ra.nplain = so.nlo_plain;
           ra.ntiles = static_cast<int>(D >> lo_bits);
           ra.xcd_remap = (ra.ntiles % 8 == 0) ? 1 : 0;
           DACP_HIP(ctx, dacp::launch_rec_lo<double>(ra, ctx->stream));
@@ -843,6 +873,9 @@ dacp_status dacp_create(int device, void *hip_stream, dacp_ctx *out) {
   if (!c) return DACP_E_NOMEM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->num_cus = cus;
   *out = c;
   return DACP_OK;
 }
@@ -892,6 +925,26 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
   if (k == "filter_group_f64" || k == "filter_group_f32") {
     if (!pow2 || value > 64) return set_err(ctx, DACP_E_INVALID, k + ": power of two <= 64");
     (k == "filter_group_f64" ? ctx->filter_group_f64 : ctx->filter_group_f32) = value;
+    return DACP_OK;
+  }
+  if (k == "rec_hi_w") {
+    if (value != 0 && !(pow2 && value <= 8)) return set_err(ctx, DACP_E_INVALID, "rec_hi_w: 0 (automatic), 1, 2, 4 or 8");
+    ctx->rec_hi_w = value;
+    return DACP_OK;
+  }
+  if (k == "rec_threads") {
+    if (value != 512 && value != 1024) return set_err(ctx, DACP_E_INVALID, "rec_threads: 512 or 1024");
+    ctx->rec_threads = value;
+    return DACP_OK;
+  }
+  if (k == "rec_persist") {
+    if (value < 0 || value > 8) return set_err(ctx, DACP_E_INVALID, "rec_persist: 0..8 workgroups per CU");
+    ctx->rec_persist = value;
+    return DACP_OK;
+  }
+  if (k == "rec_tile") {
+    if (!pow2 || value < 1024 || value > 8192) return set_err(ctx, DACP_E_INVALID, "rec_tile: power of two in [1024, 8192]");
+    ctx->rec_tile_elems = value;
     return DACP_OK;
   }
   if (k == "group") {

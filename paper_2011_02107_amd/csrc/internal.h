@@ -80,6 +80,8 @@ struct HiArgs {
 //   lo tile kernel:  T_new = P + alpha (D + Lo) T_cur ;  P <- alpha (D + Lo) T_new - T_cur
 //   hi coset kernel: T_new = P + alpha Hi T_cur       ;  P <- alpha Hi T_new - T_cur
 // T_new is written over the buffer of the term before T_cur; P is updated in place.
+// The blocks are contiguous [D][b] with b * sizeof(T) a multiple of 16 bytes and
+// D * b * sizeof(T) < 2^35 (32-bit 16-byte-vector offsets).
 template <typename T>
 struct RecArgs {
   const T *tcur;
@@ -90,12 +92,16 @@ struct RecArgs {
   int64_t ld;   // row stride of tcur, tnew, p (= b)
   T alpha;
   const T *diag;
-  const FlipEntry *flips;
+  const FlipEntry *flips;  // read-only while a kernel runs (loaded through the scalar cache)
   int nflip;
+  int nplain;   // flips[0, nplain) have z-mask 0
   int b;
   int lo_bits;
   int hi_bits;
+  int W;        // hi kernel: adjacent rows per coset tile (power of two)
+  int threads;  // 512 or 1024
   int ntiles;
+  int grid;     // > 0 and < ntiles: persistent launch of `grid` workgroups (tiles prefetched)
   int xcd_remap;
 };
 
@@ -181,7 +187,12 @@ struct dacp_ctx_s {
   int two_pass_min_L = 15;    // use the two-pass apply from this L on (0 disables it)
   int fused_rec = 1;          // alternating-split fused recurrence in the evolution (0 disables it)
   int pass_tile_elems = 4096;  // elements per LDS tile of the two-pass / fused kernels
-  int group_default = 4;       // recurrence column-group width for L >= 15
+  int group_default = 8;       // evolution column-group width for L >= 15
+  int rec_hi_w = 0;            // fused recurrence: adjacent rows per high-bit tile (0 = automatic)
+  int rec_threads = 1024;      // fused recurrence: threads per workgroup (512 or 1024)
+  int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
+  int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
+  int num_cus = 256;           // compute units of the device
   int filter_group_f64 = 8;    // filter column-group width for L >= 15, FP64 recurrence
   int filter_group_f32 = 16;   // filter column-group width for L >= 15, FP32 recurrence
   int dc_min_n = 96;           // eigenvectors by divide and conquer from this size on (0 = never)
@@ -205,6 +216,7 @@ struct dacp_ham_s {
     dacp::FlipEntry *lo = nullptr;  // flips with every mask bit < lo_bits
     dacp::FlipEntry *hi = nullptr;  // flips with every mask bit >= lo_bits, then mixed ones
     int nlo = 0, nhi = 0, nmix = 0;
+    int nlo_plain = 0, nhi_plain = 0;  // leading z-mask-free entries of lo / of the pure part of hi
   };
   SplitOrder split[31];  // flip tables for the two-pass apply with lo_bits = index
 };

@@ -374,199 +374,385 @@ template hipError_t launch_step_hi<double>(const HiArgs<double> &, hipStream_t, 
 template hipError_t launch_step_hi<float>(const HiArgs<float> &, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
-// Fused alternating-split recurrence (see RecArgs).  512 threads, EPT elements
-// each; b = 2^lb.  Both kernels keep T_cur of their own elements in registers,
-// complete T_new from LDS, then stage T_new in LDS to start the next step.
+// Fused alternating-split recurrence (see RecArgs).  The blocks are moved as
+// 16-byte vectors (2 doubles / 4 floats of one row; b * sizeof(T) >= 16), so
+// every global access and every LDS read is 16 bytes per lane.  Both kernels
+// keep their vectors of T_cur and P in registers, complete T_new from the LDS
+// copy of T_cur, then stage T_new in LDS to start the next step.
+//   lo kernel: tile = 2^lo_bits consecutive rows (contiguous in memory);
+//   hi kernel: tile = rows l0 + w + (j << lo_bits), w < W, j < 2^hi_bits, so each
+//              j contributes one contiguous run of W * b elements (W chosen on
+//              the host so that a run fills whole 128-byte lines).
+// Vector index v inside a tile: v = ((j << lw) | w) << lbv | cv with 2^lbv
+// vectors per row; a high flip maps j to j ^ (mask >> lo_bits), i.e. v to
+// v ^ ((mask >> lo_bits) << (lw + lbv)); a low flip maps v to v ^ (mask << lbv).
 // ---------------------------------------------------------------------------
-template <typename T, int EPT>
-__global__ __launch_bounds__(512) void k_rec_lo(RecArgs<T> a) {
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2, log2n = 1;
+};
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4, log2n = 2;
+};
+
+// The flip table is not written while a kernel runs, so it is read through the constant
+// address space: uniform scalar loads that do not wait for the kernel's own global stores.
+typedef const __attribute__((address_space(4))) FlipEntry *ConstFlips;
+
+// acc += sum_t c_t sign_t tile[v ^ vs_t] for the flips of one split; vs_t is the mask moved to
+// the vector index (left shift by `shift`, or right shift by -shift for high masks, whose low
+// bits are zero).  Sign-free flips come first and run U at a time, so U * NV LDS reads are in
+// flight per wait; the accumulation order per element is the table order.
+template <typename T, int NT, int NV>
+__device__ __forceinline__ void rec_flips(typename Vec16<T>::type (&acc)[NV], const typename Vec16<T>::type *tile,
+                                          const FlipEntry *flips_g, int nplain, int nflip, int shift,
+                                          const uint32_t (&row)[NV]) {
+  using V = typename Vec16<T>::type;
+  constexpr int U = NV >= 2 ? 2 : 4;
+  const ConstFlips flips = (ConstFlips)flips_g;
+  auto vshift = [shift](uint32_t xm) { return shift >= 0 ? (xm << shift) : (xm >> -shift); };
+  int t = 0;
+  for (; t + U <= nplain; t += U) {
+    uint32_t vs[U];
+    T c[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      vs[q] = vshift(flips[t + q].xmask);
+      c[q] = static_cast<T>(flips[t + q].coef);
+    }
+    V g[U][NV];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) g[q][i] = tile[(threadIdx.x + i * NT) ^ vs[q]];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += c[q] * g[q][i];
+  }
+  for (; t < nplain; ++t) {
+    const uint32_t vs = vshift(flips[t].xmask);
+    const T c = static_cast<T>(flips[t].coef);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += c * tile[(threadIdx.x + i * NT) ^ vs];
+  }
+  for (; t < nflip; ++t) {
+    const uint32_t xm = flips[t].xmask;
+    const uint32_t zm = flips[t].zmask;
+    const T c = static_cast<T>(flips[t].coef);
+    const uint32_t vs = vshift(xm);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const T sg = (__popc((row[i] ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * tile[(threadIdx.x + i * NT) ^ vs];
+    }
+  }
+}
+
+// Waves per SIMD that let two one-tile workgroups share a CU (1024 threads with 2 vectors each,
+// or 512 threads with up to 4); other shapes run one workgroup per CU.
+constexpr int rec_min_waves(int nt, int nv) { return (nt == 1024 && nv <= 2) ? 8 : (nt == 512 && nv <= 4) ? 4 : 1; }
+
+template <typename T>
+__device__ __forceinline__ void store_sample(double *st, int64_t ldst, uint32_t row, uint32_t cv,
+                                             const typename Vec16<T>::type &x) {
+  double *d = st + static_cast<int64_t>(row) * ldst + (static_cast<int64_t>(cv) << Vec16<T>::log2n);
+#pragma unroll
+  for (int q = 0; q < Vec16<T>::n; ++q) d[q] = static_cast<double>(x[q]);
+}
+
+template <typename T, int NT, int NV>
+__global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_lo(RecArgs<T> a) {
+  using V = typename Vec16<T>::type;
   extern __shared__ unsigned char smem_raw[];
-  T *tile = reinterpret_cast<T *>(smem_raw);
-  const int lb = __ffs(a.b) - 1;
+  V *tile = reinterpret_cast<V *>(smem_raw);
+  const int lbv = (__ffs(a.b) - 1) - Vec16<T>::log2n;  // log2(vectors per row)
+  const uint32_t cvmask = (1u << lbv) - 1u;
   int bid = blockIdx.x;
   if (a.xcd_remap) bid = (bid & 7) * (a.ntiles >> 3) + (bid >> 3);
   const uint32_t row0 = static_cast<uint32_t>(bid) << a.lo_bits;
-  const int64_t base = static_cast<int64_t>(row0) * a.ld;  // tiles are contiguous (ld == b)
-  T cur[EPT], dg[EPT], nw[EPT];
+  const uint32_t vbase = row0 << lbv;
+  const V *tc = reinterpret_cast<const V *>(a.tcur) + vbase;
+  V *tn = reinterpret_cast<V *>(a.tnew) + vbase;
+  V *pp = reinterpret_cast<V *>(a.p) + vbase;
+  V cur[NV], nw[NV], acc[NV];
+  T dg[NV];
+  uint32_t row[NV];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * 512;
-    cur[i] = a.tcur[base + e];
-    dg[i] = a.diag[row0 + (e >> lb)];
-    nw[i] = a.p[base + e];
+  for (int i = 0; i < NV; ++i) {
+    const uint32_t v = threadIdx.x + i * NT;
+    row[i] = row0 + (v >> lbv);
+    cur[i] = tc[v];
+    nw[i] = pp[v];
+    dg[i] = a.diag[row[i]];
   }
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = cur[i];
+  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = cur[i];
   __syncthreads();
-  T acc[EPT];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) acc[i] = dg[i] * cur[i];
-  for (int t = 0; t < a.nflip; ++t) {
-    const uint32_t xm = a.flips[t].xmask;
-    const uint32_t zm = a.flips[t].zmask;
-    const T c = static_cast<T>(a.flips[t].coef);
-    const int sh = static_cast<int>(xm) << lb;
-    if (zm == 0) {
+  for (int i = 0; i < NV; ++i) acc[i] = dg[i] * cur[i];
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * 512;
-        const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
-        acc[i] += sg * tile[e ^ sh];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * 512;
+  for (int i = 0; i < NV; ++i) {
+    const uint32_t v = threadIdx.x + i * NT;
     nw[i] += a.alpha * acc[i];
-    a.tnew[base + e] = nw[i];
-    if (a.st) a.st[static_cast<int64_t>(row0 + (e >> lb)) * a.ldst + (e & (a.b - 1))] = static_cast<double>(nw[i]);
+    tn[v] = nw[i];
+    if (a.st) store_sample<T>(a.st, a.ldst, row[i], v & cvmask, nw[i]);
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = nw[i];
+  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = nw[i];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) acc[i] = dg[i] * nw[i];
-  for (int t = 0; t < a.nflip; ++t) {
-    const uint32_t xm = a.flips[t].xmask;
-    const uint32_t zm = a.flips[t].zmask;
-    const T c = static_cast<T>(a.flips[t].coef);
-    const int sh = static_cast<int>(xm) << lb;
-    if (zm == 0) {
+  for (int i = 0; i < NV; ++i) acc[i] = dg[i] * nw[i];
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * 512;
-        const T sg = (__popc(((row0 + static_cast<uint32_t>(e >> lb)) ^ xm) & zm) & 1) ? -c : c;
-        acc[i] += sg * tile[e ^ sh];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) a.p[base + threadIdx.x + i * 512] = a.alpha * acc[i] - cur[i];
+  for (int i = 0; i < NV; ++i) pp[threadIdx.x + i * NT] = a.alpha * acc[i] - cur[i];
 }
 
-// Coset tile of the high bits: rows l0 + (j << lo_bits), j < 2^hi_bits (W = 1); element
-// e = (j << lb) | col, so a high flip maps e to e ^ ((mask >> lo_bits) << lb).
-template <typename T, int EPT>
-__global__ __launch_bounds__(512) void k_rec_hi(RecArgs<T> a) {
+template <typename T, int NT, int NV>
+__global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_hi(RecArgs<T> a) {
+  using V = typename Vec16<T>::type;
   extern __shared__ unsigned char smem_raw[];
-  T *tile = reinterpret_cast<T *>(smem_raw);
-  const int lb = __ffs(a.b) - 1;
+  V *tile = reinterpret_cast<V *>(smem_raw);
+  const int lbv = (__ffs(a.b) - 1) - Vec16<T>::log2n;
+  const int lw = __ffs(a.W) - 1;
+  const uint32_t cvmask = (1u << lbv) - 1u;
+  const uint32_t wmask = static_cast<uint32_t>(a.W) - 1u;
   int bid = blockIdx.x;
   if (a.xcd_remap) bid = (bid & 7) * (a.ntiles >> 3) + (bid >> 3);
-  const uint32_t l0 = static_cast<uint32_t>(bid);
-  T cur[EPT], nw[EPT];
-  int64_t off[EPT];
+  const uint32_t l0 = static_cast<uint32_t>(bid) << lw;
+  const V *tc = reinterpret_cast<const V *>(a.tcur);
+  V *tn = reinterpret_cast<V *>(a.tnew);
+  V *pp = reinterpret_cast<V *>(a.p);
+  V cur[NV], nw[NV], acc[NV];
+  uint32_t row[NV];  // the vector's global offset is (row << lbv) | (v & cvmask)
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * 512;
-    const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
-    off[i] = static_cast<int64_t>(row) * a.ld + (e & (a.b - 1));
+  for (int i = 0; i < NV; ++i) {
+    const uint32_t v = threadIdx.x + i * NT;
+    const uint32_t rv = v >> lbv;
+    row[i] = l0 + (rv & wmask) + ((rv >> lw) << a.lo_bits);
+  }
+  auto off = [&](int i) { return (row[i] << lbv) | ((threadIdx.x + i * NT) & cvmask); };
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    cur[i] = tc[off(i)];
+    nw[i] = pp[off(i)];
   }
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    cur[i] = a.tcur[off[i]];
-    nw[i] = a.p[off[i]];
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = cur[i];
+  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = cur[i];
   __syncthreads();
-  T acc[EPT];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) acc[i] = T(0);
-  for (int t = 0; t < a.nflip; ++t) {
-    const uint32_t xm = a.flips[t].xmask;
-    const uint32_t zm = a.flips[t].zmask;
-    const T c = static_cast<T>(a.flips[t].coef);
-    const int sh = static_cast<int>(xm >> a.lo_bits) << lb;
-    if (zm == 0) {
+  for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
+  // high masks act on j: shift right by lo_bits, then left by lw + lbv
+  const int hs = lw + lbv - a.lo_bits;
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
-    } else {
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * 512;
-        const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
-        const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
-        acc[i] += sg * tile[e ^ sh];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * 512;
+  for (int i = 0; i < NV; ++i) {
     nw[i] += a.alpha * acc[i];
-    a.tnew[off[i]] = nw[i];
-    if (a.st) {
-      const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
-      a.st[static_cast<int64_t>(row) * a.ldst + (e & (a.b - 1))] = static_cast<double>(nw[i]);
-    }
+    tn[off(i)] = nw[i];
+    if (a.st) store_sample<T>(a.st, a.ldst, row[i], (threadIdx.x + i * NT) & cvmask, nw[i]);
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) tile[threadIdx.x + i * 512] = nw[i];
+  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = nw[i];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) acc[i] = T(0);
-  for (int t = 0; t < a.nflip; ++t) {
-    const uint32_t xm = a.flips[t].xmask;
-    const uint32_t zm = a.flips[t].zmask;
-    const T c = static_cast<T>(a.flips[t].coef);
-    const int sh = static_cast<int>(xm >> a.lo_bits) << lb;
-    if (zm == 0) {
+  for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) acc[i] += c * tile[(threadIdx.x + i * 512) ^ sh];
-    } else {
+  for (int i = 0; i < NV; ++i) pp[off(i)] = a.alpha * acc[i] - cur[i];
+}
+
+// Persistent variants: gridDim.x workgroups walk the tiles t = blockIdx.x + k gridDim.x and
+// load tile t + gridDim.x into registers while tile t is in the LDS phase, so a CU keeps its
+// memory pipe busy across the flip loops.
+template <typename T, int NT, int NV>
+__global__ __launch_bounds__(NT) void k_rec_lo_p(RecArgs<T> a) {
+  using V = typename Vec16<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  V *tile = reinterpret_cast<V *>(smem_raw);
+  const int lbv = (__ffs(a.b) - 1) - Vec16<T>::log2n;
+  const uint32_t cvmask = (1u << lbv) - 1u;
+  const int G = gridDim.x;
+  int t = blockIdx.x;
+  V cn[NV], pn[NV];
+  T dn[NV];
+  auto fetch = [&](int tt) {
+    const uint32_t r0 = static_cast<uint32_t>(tt) << a.lo_bits;
+    const uint32_t vb = r0 << lbv;
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + i * 512;
-        const uint32_t row = l0 + (static_cast<uint32_t>(e >> lb) << a.lo_bits);
-        const T sg = (__popc((row ^ xm) & zm) & 1) ? -c : c;
-        acc[i] += sg * tile[e ^ sh];
-      }
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t v = threadIdx.x + i * NT;
+      cn[i] = reinterpret_cast<const V *>(a.tcur)[vb + v];
+      pn[i] = reinterpret_cast<const V *>(a.p)[vb + v];
+      dn[i] = a.diag[r0 + (v >> lbv)];
     }
-  }
+  };
+  if (t < a.ntiles) fetch(t);
+  for (; t < a.ntiles; t += G) {
+    const uint32_t row0 = static_cast<uint32_t>(t) << a.lo_bits;
+    const uint32_t vbase = row0 << lbv;
+    V cur[NV], nw[NV], acc[NV];
+    T dg[NV];
+    uint32_t row[NV];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) a.p[off[i]] = a.alpha * acc[i] - cur[i];
+    for (int i = 0; i < NV; ++i) {
+      cur[i] = cn[i];
+      nw[i] = pn[i];
+      dg[i] = dn[i];
+      row[i] = row0 + ((threadIdx.x + i * NT) >> lbv);
+    }
+    if (t + G < a.ntiles) fetch(t + G);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = cur[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = dg[i] * cur[i];
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
+    V *tn = reinterpret_cast<V *>(a.tnew) + vbase;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t v = threadIdx.x + i * NT;
+      nw[i] += a.alpha * acc[i];
+      tn[v] = nw[i];
+      if (a.st) store_sample<T>(a.st, a.ldst, row[i], v & cvmask, nw[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = nw[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = dg[i] * nw[i];
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
+    V *pp = reinterpret_cast<V *>(a.p) + vbase;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pp[threadIdx.x + i * NT] = a.alpha * acc[i] - cur[i];
+    __syncthreads();  // the next tile overwrites the LDS copy
+  }
+}
+
+template <typename T, int NT, int NV>
+__global__ __launch_bounds__(NT) void k_rec_hi_p(RecArgs<T> a) {
+  using V = typename Vec16<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  V *tile = reinterpret_cast<V *>(smem_raw);
+  const int lbv = (__ffs(a.b) - 1) - Vec16<T>::log2n;
+  const int lw = __ffs(a.W) - 1;
+  const uint32_t cvmask = (1u << lbv) - 1u;
+  const uint32_t wmask = static_cast<uint32_t>(a.W) - 1u;
+  const int hs = lw + lbv - a.lo_bits;
+  const int G = gridDim.x;
+  int t = blockIdx.x;
+  // element offsets relative to the tile's first row l0 = t W (row = l0 + rel)
+  uint32_t rel[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const uint32_t v = threadIdx.x + i * NT;
+    const uint32_t rv = v >> lbv;
+    rel[i] = (rv & wmask) + ((rv >> lw) << a.lo_bits);
+  }
+  V cn[NV], pn[NV];
+  auto fetch = [&](int tt) {
+    const uint32_t l0 = static_cast<uint32_t>(tt) << lw;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t off = ((l0 + rel[i]) << lbv) | ((threadIdx.x + i * NT) & cvmask);
+      cn[i] = reinterpret_cast<const V *>(a.tcur)[off];
+      pn[i] = reinterpret_cast<const V *>(a.p)[off];
+    }
+  };
+  if (t < a.ntiles) fetch(t);
+  for (; t < a.ntiles; t += G) {
+    const uint32_t l0 = static_cast<uint32_t>(t) << lw;
+    V cur[NV], nw[NV], acc[NV];
+    uint32_t row[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      cur[i] = cn[i];
+      nw[i] = pn[i];
+      row[i] = l0 + rel[i];
+    }
+    if (t + G < a.ntiles) fetch(t + G);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = cur[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t cv = (threadIdx.x + i * NT) & cvmask;
+      nw[i] += a.alpha * acc[i];
+      reinterpret_cast<V *>(a.tnew)[(row[i] << lbv) | cv] = nw[i];
+      if (a.st) store_sample<T>(a.st, a.ldst, row[i], cv, nw[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = nw[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const uint32_t cv = (threadIdx.x + i * NT) & cvmask;
+      reinterpret_cast<V *>(a.p)[(row[i] << lbv) | cv] = a.alpha * acc[i] - cur[i];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NT>
+hipError_t launch_rec_nt(const RecArgs<T> &a, int nvec, bool hi, hipStream_t s) {
+  const size_t lds = static_cast<size_t>(nvec) * 16;
+  // (the 1024-thread persistent form with 4 vectors per thread would spill: launch one tile per workgroup)
+  const bool persist = a.grid > 0 && a.grid < a.ntiles && !(NT == 1024 && nvec / NT == 4);
+  dim3 grid(persist ? a.grid : a.ntiles), block(NT);
+#define DACP_REC(nv_)                                                                  \
+  do {                                                                                 \
+    if (persist) {                                                                     \
+      if (hi) hipLaunchKernelGGL((k_rec_hi_p<T, NT, nv_>), grid, block, lds, s, a);   \
+      else hipLaunchKernelGGL((k_rec_lo_p<T, NT, nv_>), grid, block, lds, s, a);      \
+    } else {                                                                           \
+      if (hi) hipLaunchKernelGGL((k_rec_hi<T, NT, nv_>), grid, block, lds, s, a);     \
+      else hipLaunchKernelGGL((k_rec_lo<T, NT, nv_>), grid, block, lds, s, a);        \
+    }                                                                                  \
+  } while (0)
+  switch (nvec / NT) {
+    case 1: DACP_REC(1); break;
+    case 2: DACP_REC(2); break;
+    case 4: DACP_REC(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DACP_REC
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rec(const RecArgs<T> &a, bool hi, hipStream_t s) {
+  const int64_t rows = hi ? (static_cast<int64_t>(a.W) << a.hi_bits) : (int64_t(1) << a.lo_bits);
+  const int64_t nel = rows * a.b;
+  if ((a.b * static_cast<int>(sizeof(T))) % 16 != 0 || nel * static_cast<int64_t>(sizeof(T)) > 65536)
+    return hipErrorInvalidValue;
+  const int nvec = static_cast<int>(nel * sizeof(T) / 16);
+  if (a.threads == 512 && nvec % 512 == 0) return launch_rec_nt<T, 512>(a, nvec, hi, s);
+  if (a.threads == 1024 && nvec % 1024 == 0) return launch_rec_nt<T, 1024>(a, nvec, hi, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_rec_lo(const RecArgs<T> &a, hipStream_t s) {
-  const int nel = (1 << a.lo_bits) * a.b;
-  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
-  dim3 grid(a.ntiles), block(512);
-  switch (nel / 512) {
-    case 1: hipLaunchKernelGGL((k_rec_lo<T, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_rec_lo<T, 2>), grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_rec_lo<T, 4>), grid, block, lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_rec_lo<T, 8>), grid, block, lds, s, a); break;
-    case 16: hipLaunchKernelGGL((k_rec_lo<T, 16>), grid, block, lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return launch_rec<T>(a, false, s);
 }
-
 template <typename T>
 hipError_t launch_rec_hi(const RecArgs<T> &a, hipStream_t s) {
-  const int nel = (1 << a.hi_bits) * a.b;
-  const size_t lds = static_cast<size_t>(nel) * sizeof(T);
-  dim3 grid(a.ntiles), block(512);
-  switch (nel / 512) {
-    case 1: hipLaunchKernelGGL((k_rec_hi<T, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_rec_hi<T, 2>), grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_rec_hi<T, 4>), grid, block, lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_rec_hi<T, 8>), grid, block, lds, s, a); break;
-    case 16: hipLaunchKernelGGL((k_rec_hi<T, 16>), grid, block, lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return launch_rec<T>(a, true, s);
 }
 template hipError_t launch_rec_lo<double>(const RecArgs<double> &, hipStream_t);
 template hipError_t launch_rec_lo<float>(const RecArgs<float> &, hipStream_t);

@@ -303,6 +303,46 @@ def test_basis_two_pass_groups_match_oracle(ctx):
     assert np.abs(host(V) - ref).max() < 1e-15 * max(ks) + 1e-12
 
 
+def _signed_flip_terms(L, seed):
+    """Chain plus X Z and Y Y terms whose x-masks never straddle the middle bits (sign paths of the
+    fused kernels), with a single-spin-flip part that keeps every fused split admissible."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = inputs.X, inputs.Y, inputs.Z
+    rows = [(Y, i, Y, i + 1, rng.uniform(-0.5, 0.5)) for i in (0, 1, L - 3, L - 2)]
+    for _ in range(4):
+        i, j = rng.choice(L, 2, replace=False)
+        rows.append((X, int(i), Z, int(j), rng.uniform(-0.5, 0.5)))
+    return np.concatenate([inputs.ising_chain(L), inputs.make_terms(rows)])
+
+
+@pytest.mark.parametrize("g", [2, 4, 8])
+@pytest.mark.parametrize("threads,hi_w,rec_tile,persist", [(1024, 0, 8192, 0), (512, 0, 8192, 0), (1024, 1, 4096, 0),
+                                                           (512, 2, 4096, 0), (1024, 8, 8192, 0), (1024, 1, 4096, 1),
+                                                           (512, 0, 8192, 2), (1024, 0, 2048, 3)])
+def test_basis_fused_layouts_match_oracle(ctx, g, threads, hi_w, rec_tile, persist):
+    L, b, n = 16, 8, 1
+    terms = _signed_flip_terms(L, 3)
+    eb = 1.05 * hamiltonian.sum_abs_coeff(terms)
+    a = 0.45 * eb
+    psi = np.random.default_rng(11).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0)
+    ref, ks = chebyshev.chebyshev_basis(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, n)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    V = torch.zeros((1 << L, b * (2 * n + 1)), dtype=torch.float64, device=DEV)
+    try:
+        ctx.tune("rec_threads", threads)
+        ctx.tune("rec_hi_w", hi_w)
+        ctx.tune("rec_tile", rec_tile)
+        ctx.tune("rec_persist", persist)
+        B.dacp_basis(ctx, ham, to_dev(psi), V, eb, a, n, group=g)
+    finally:
+        ctx.tune("rec_persist", 0)
+        ctx.tune("rec_threads", 1024)
+        ctx.tune("rec_hi_w", 0)
+        ctx.tune("rec_tile", 8192)
+    assert np.abs(host(V) - ref).max() < 1e-15 * max(ks) + 1e-12
+
+
 def test_basis_detects_bound_below_norm(ctx):
     L = 8
     terms = inputs.ising_chain(L)
