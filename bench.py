@@ -31,13 +31,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="chain_L20_N5000", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="plain", choices=["plain", "tuned"])
+    ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
     ap.add_argument("--window-ratio", type=float, default=None)
     ap.add_argument("--tail", type=float, default=None, help="FP64 tail fraction of the filter (tuned mode)")
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="run only a device copy of known size and a short evolution at the workload's shape "
+                         "(for hardware-counter runs), print one JSON line and exit")
     return ap.parse_args()
 
 
@@ -87,8 +90,41 @@ def cpu_baseline(wl, rep, steps):
     }
 
 
+def profile_kernels(args):
+    """A 256 MiB device copy (read and write byte counts known exactly) followed by 64 steps of the
+    evolution recurrence on one column group at the workload's L, with the same kernels and tiles
+    as a full step.  Used to scale the FETCH_SIZE / WRITE_SIZE counters to algorithmic bytes."""
+    import numpy as np
+    import torch
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    wl = WORKLOADS[args.workload]
+    L = wl["L"]
+    D = 1 << L
+    ctx = B.Context(0)
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L))
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    g = args.group or 8
+    eb = 1.01 * (1.723 * L)  # above the chain norm 1.723 L - 0.73; checked by the evolution norm guard
+    psi = torch.ones((D, g), dtype=torch.float64, device="cuda") / math.sqrt(D)
+    n = 1
+    V = torch.zeros((D, g * (2 * n + 1)), dtype=torch.float64, device="cuda")
+    a_r = math.pi / 64.0  # k_1 = 64 evolution steps
+    B.dacp_basis(ctx, ham, psi, V, eb, a_r * eb, n, group=g)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "evolution_steps": 64, "group": g, "L": L,
+                      "algorithmic_bytes_per_step": 3 * D * g * 8, "e_bound": eb}), flush=True)
+
+
 def main():
     args = parse()
+    if args.profile_kernels:
+        return profile_kernels(args)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)

@@ -19,6 +19,8 @@
 using dacp::DevBuf;
 using dacp::FlipEntry;
 using dacp::StepArgs;
+using dacp::to_device;
+using dacp::to_host;
 
 namespace dacp {
 
@@ -49,6 +51,38 @@ dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg) {
 dacp_status hip_err(dacp_ctx ctx, hipError_t e, const char *what) {
   const dacp_status st = (e == hipErrorOutOfMemory) ? DACP_E_NOMEM : DACP_E_HIP;
   return set_err(ctx, st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+dacp_status to_host(dacp_ctx ctx, void *host, const void *dev, size_t bytes) {
+  if (bytes == 0) return DACP_OK;
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  DACP_HIP(ctx, hipMemcpy(host, dev, bytes, hipMemcpyDeviceToHost));
+  return DACP_OK;
+}
+
+dacp_status to_device(dacp_ctx ctx, void *dev, const void *host, size_t bytes) {
+  if (bytes == 0) return DACP_OK;
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  DACP_HIP(ctx, hipMemcpy(dev, host, bytes, hipMemcpyHostToDevice));
+  return DACP_OK;
+}
+
+dacp_status to_host_2d(dacp_ctx ctx, double *host, const double *dev, int64_t lddev, int64_t rows, int64_t cols) {
+  if (rows <= 0 || cols <= 0) return DACP_OK;
+  DevBuf tmp;
+  DACP_HIP(ctx, tmp.alloc(static_cast<size_t>(rows * cols) * sizeof(double)));
+  DACP_HIP(ctx, launch_copy_cols(dev, lddev, tmp.as<double>(), cols, rows, static_cast<int>(cols), ctx->stream));
+  return to_host(ctx, host, tmp.p, static_cast<size_t>(rows * cols) * sizeof(double));
+}
+
+dacp_status to_device_2d(dacp_ctx ctx, double *dev, int64_t lddev, const double *host, int64_t rows, int64_t cols) {
+  if (rows <= 0 || cols <= 0) return DACP_OK;
+  DevBuf tmp;
+  DACP_HIP(ctx, tmp.alloc(static_cast<size_t>(rows * cols) * sizeof(double)));
+  DACP_TRY(to_device(ctx, tmp.p, host, static_cast<size_t>(rows * cols) * sizeof(double)));
+  DACP_HIP(ctx, launch_copy_cols(tmp.as<double>(), cols, dev, lddev, rows, static_cast<int>(cols), ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // tmp is released on return
+  return DACP_OK;
 }
 
 }  // namespace dacp
@@ -97,7 +131,7 @@ dacp_status coldots_host(dacp_ctx ctx, const void *x, int64_t ldx, const void *y
   if (st) return st;
   st = coldots_dev(ctx, x, ldx, y, ldy, dtype, D, b, ctx->red_out);
   if (st) return st;
-  DACP_HIP(ctx, hipMemcpyAsync(host_out, ctx->red_out, sizeof(double) * b, hipMemcpyDeviceToHost, ctx->stream));
+  DACP_TRY(to_host(ctx, host_out, ctx->red_out, sizeof(double) * b));
   DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return DACP_OK;
 }
@@ -615,7 +649,7 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
                      DACP_F64, D, b, nrm.as<double>() + static_cast<size_t>(i) * b);
     if (st) return st;
   }
-  DACP_HIP(ctx, hipMemcpyAsync(nk.data(), nrm.p, sizeof(double) * nk.size(), hipMemcpyDeviceToHost, ctx->stream));
+  DACP_TRY(to_host(ctx, nk.data(), nrm.p, sizeof(double) * nk.size()));
   DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < b; ++j) {
@@ -668,8 +702,7 @@ dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_
   DevBuf awork, zs;
   DACP_HIP(ctx, awork.alloc(static_cast<size_t>(m) * m * sizeof(double)));
   DACP_HIP(ctx, zs.alloc(static_cast<size_t>(m) * m * sizeof(double)));
-  DACP_HIP(ctx, hipMemcpy2DAsync(awork.p, m * sizeof(double), S, ld * sizeof(double), m * sizeof(double), m,
-                                 hipMemcpyDeviceToDevice, s));
+  DACP_HIP(ctx, dacp::launch_copy_cols(S, ld, awork.as<double>(), m, m, m, s));
   std::vector<double> lam(m);
   dacp_status st = dacp::gpu_syev(ctx, m, awork.as<double>(), m, lam.data(), zs.as<double>());
   if (st) return st;
@@ -686,8 +719,8 @@ dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_
   DevBuf dperm, dscale, uc, t1, ht, yc;
   DACP_HIP(ctx, dperm.alloc(sizeof(int) * r));
   DACP_HIP(ctx, dscale.alloc(sizeof(double) * r));
-  DACP_HIP(ctx, hipMemcpyAsync(dperm.p, perm.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
-  DACP_HIP(ctx, hipMemcpyAsync(dscale.p, scale.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+  DACP_TRY(to_device(ctx, dperm.p, perm.data(), sizeof(int) * r));
+  DACP_TRY(to_device(ctx, dscale.p, scale.data(), sizeof(double) * r));
   DACP_HIP(ctx, uc.alloc(static_cast<size_t>(r) * m * sizeof(double)));
   DACP_HIP(ctx, dacp::launch_gather_rows(zs.as<double>(), m, uc.as<double>(), m, dperm.as<int>(), dscale.as<double>(),
                                          r, m, s));
@@ -1323,8 +1356,8 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
         std::vector<int> pr(order.begin() + c0, order.begin() + c0 + w);
         std::vector<double> th(w);
         for (int i = 0; i < w; ++i) th[i] = theta[pr[i]];
-        DACP_HIP(ctx, hipMemcpyAsync(dperm.p, pr.data(), sizeof(int) * w, hipMemcpyHostToDevice, s));
-        DACP_HIP(ctx, hipMemcpyAsync(dth.p, th.data(), sizeof(double) * w, hipMemcpyHostToDevice, s));
+        DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
+        DACP_TRY(to_device(ctx, dth.p, th.data(), sizeof(double) * w));
         DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, w, m,
                                                s));
         // Phi = V B_sel  (D x w)
@@ -1334,7 +1367,7 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
         if (st) return st;
         DACP_HIP(ctx, dacp::launch_resid(phi.as<double>(), hphi.as<double>(), w, dth.as<double>(), D, w, ctx->red,
                                          dacp::coldots_blocks(D, 2 * w), ctx->red_out, s));
-        DACP_HIP(ctx, hipMemcpyAsync(out.data(), ctx->red_out, sizeof(double) * 2 * w, hipMemcpyDeviceToHost, s));
+        DACP_TRY(to_host(ctx, out.data(), ctx->red_out, sizeof(double) * 2 * w));
         DACP_HIP(ctx, hipStreamSynchronize(s));
         for (int i = 0; i < w; ++i) rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
       }

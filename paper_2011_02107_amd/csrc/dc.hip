@@ -207,10 +207,8 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
   std::vector<double> z(n);
   {
     std::vector<double> col(n);
-    DACP_HIP(ctx, hipMemcpy2DAsync(col.data(), sizeof(double), W.Z + static_cast<int64_t>(lo) * W.n + (m - 1),
-                                   W.n * sizeof(double), sizeof(double), n1, hipMemcpyDeviceToHost, st));
-    DACP_HIP(ctx, hipMemcpy2DAsync(col.data() + n1, sizeof(double), W.Z + static_cast<int64_t>(m) * W.n + m,
-                                   W.n * sizeof(double), sizeof(double), n - n1, hipMemcpyDeviceToHost, st));
+    DACP_TRY(to_host_2d(ctx, col.data(), W.Z + static_cast<int64_t>(lo) * W.n + (m - 1), W.n, n1, 1));
+    DACP_TRY(to_host_2d(ctx, col.data() + n1, W.Z + static_cast<int64_t>(m) * W.n + m, W.n, n - n1, 1));
     DACP_HIP(ctx, hipStreamSynchronize(st));
     for (int i = 0; i < n1; ++i) z[i] = sgn * col[i];
     for (int i = n1; i < n; ++i) z[i] = col[i];
@@ -269,8 +267,8 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
   }
   if (!rot_pq.empty()) {
     const int nr = static_cast<int>(rot_cs.size() / 2);
-    DACP_HIP(ctx, hipMemcpyAsync(W.dpq.p, rot_pq.data(), rot_pq.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    DACP_HIP(ctx, hipMemcpyAsync(W.dcs.p, rot_cs.data(), rot_cs.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    DACP_TRY(to_device(ctx, W.dpq.p, rot_pq.data(), rot_pq.size() * sizeof(int)));
+    DACP_TRY(to_device(ctx, W.dcs.p, rot_cs.data(), rot_cs.size() * sizeof(double)));
     hipLaunchKernelGGL(k_row_rotations, dim3(nblk(n, 64)), dim3(64), 0, st, W.Z, (int64_t)W.n, lo, n,
                        W.dpq.as<int>(), W.dcs.as<double>(), nr);
     DACP_HIP(ctx, hipGetLastError());
@@ -300,8 +298,8 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
       rk[q] = rowid[nd[q]];
     }
     const size_t kk = static_cast<size_t>(k) * k;
-    DACP_HIP(ctx, hipMemcpyAsync(W.dd.p, dk.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-    DACP_HIP(ctx, hipMemcpyAsync(W.dz.p, zk.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+    DACP_TRY(to_device(ctx, W.dd.p, dk.data(), k * sizeof(double)));
+    DACP_TRY(to_device(ctx, W.dz.p, zk.data(), k * sizeof(double)));
     hipLaunchKernelGGL(k_secular, dim3(nblk(k, 64)), dim3(64), 0, st, W.dd.as<double>(), W.dz.as<double>(), k, rho,
                        W.dorg.as<int>(), W.dtau.as<double>());
     hipLaunchKernelGGL(k_zhat, dim3(nblk(k, 64)), dim3(64), 0, st, W.dd.as<double>(), W.dz.as<double>(), k, rho,
@@ -310,7 +308,7 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
                        W.dzh.as<double>(), k, W.dorg.as<int>(), W.dtau.as<double>(), W.dU.as<double>());
     hipLaunchKernelGGL(k_normalise_rows, dim3(k), dim3(256), 0, st, W.dU.as<double>(), k, (int64_t)k, k);
     // old rows of the non-deflated entries (block columns [lo, hi))
-    DACP_HIP(ctx, hipMemcpyAsync(W.drows.p, rk.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+    DACP_TRY(to_device(ctx, W.drows.p, rk.data(), k * sizeof(int)));
     hipLaunchKernelGGL(k_gather_block, dim3(nblk(static_cast<int64_t>(k) * n, 256)), dim3(256), 0, st, W.Z,
                        (int64_t)W.n, W.drows.as<int>(), lo, k, n, W.dA.as<double>(), (int64_t)n);
     // new rows = U * old rows
@@ -319,8 +317,8 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
     DACP_HIP(ctx, hipGetLastError());
     std::vector<int> org(k);
     std::vector<double> tau(k);
-    DACP_HIP(ctx, hipMemcpyAsync(org.data(), W.dorg.p, k * sizeof(int), hipMemcpyDeviceToHost, st));
-    DACP_HIP(ctx, hipMemcpyAsync(tau.data(), W.dtau.p, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    DACP_TRY(to_host(ctx, org.data(), W.dorg.p, k * sizeof(int)));
+    DACP_TRY(to_host(ctx, tau.data(), W.dtau.p, k * sizeof(double)));
     DACP_HIP(ctx, hipStreamSynchronize(st));
     for (int q = 0; q < k; ++q) {
       const double v = dk[org[q]] + tau[q];
@@ -348,7 +346,7 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
     std::vector<int> idx(src_defl);
     idx.insert(idx.end(), dst_defl.begin(), dst_defl.end());
     DACP_HIP(ctx, tmp_idx.alloc(idx.size() * sizeof(int)));
-    DACP_HIP(ctx, hipMemcpyAsync(tmp_idx.p, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DACP_TRY(to_device(ctx, tmp_idx.p, idx.data(), idx.size() * sizeof(int)));
     const int nd2 = static_cast<int>(src_defl.size());
     // stage: gather into contiguous rows, then scatter into dA at dst rows
     DevBuf stage;
@@ -361,18 +359,17 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
     DACP_HIP(ctx, hipGetLastError());
     DACP_HIP(ctx, hipStreamSynchronize(st));
   }
+  std::vector<int> dst_of_q(k);  // read by an async copy: lives until the stream sync below
   if (!src_root.empty()) {
     // dB row q (root q) -> dA row dst; src_root[t] = q
-    std::vector<int> dst_of_q(k);
     for (size_t t = 0; t < src_root.size(); ++t) dst_of_q[src_root[t]] = dst_root[t];
-    DACP_HIP(ctx, hipMemcpyAsync(W.drows.p, dst_of_q.data(), k * sizeof(int), hipMemcpyHostToDevice, st));
+    DACP_TRY(to_device(ctx, W.drows.p, dst_of_q.data(), k * sizeof(int)));
     hipLaunchKernelGGL(k_scatter_block, dim3(nblk(static_cast<int64_t>(k) * n, 256)), dim3(256), 0, st,
                        W.dB.as<double>(), (int64_t)n, W.drows.as<int>(), 0, k, n, W.dA.as<double>(), (int64_t)n);
     DACP_HIP(ctx, hipGetLastError());
   }
   // dA (n x n) -> Z rows lo..hi, columns lo..hi
-  DACP_HIP(ctx, hipMemcpy2DAsync(W.Z + static_cast<int64_t>(lo) * W.n + lo, W.n * sizeof(double), W.dA.p,
-                                 n * sizeof(double), n * sizeof(double), n, hipMemcpyDeviceToDevice, st));
+  DACP_HIP(ctx, launch_copy_cols(W.dA.as<double>(), n, W.Z + static_cast<int64_t>(lo) * W.n + lo, W.n, n, n, st));
   DACP_HIP(ctx, hipStreamSynchronize(st));
   return DACP_OK;
 }
@@ -387,9 +384,7 @@ dacp_status solve(DcWork &W, std::vector<double> &d, std::vector<double> &e, int
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) rows[static_cast<size_t>(j) * n + i] = Zh[static_cast<size_t>(i) * n + j];
     for (int j = 0; j < n; ++j) W.w[lo + j] = w[j];
-    DACP_HIP(W.ctx, hipMemcpy2DAsync(W.Z + static_cast<int64_t>(lo) * W.n + lo, W.n * sizeof(double), rows.data(),
-                                     n * sizeof(double), n * sizeof(double), n, hipMemcpyHostToDevice,
-                                     W.ctx->stream));
+    DACP_TRY(to_device_2d(W.ctx, W.Z + static_cast<int64_t>(lo) * W.n + lo, W.n, rows.data(), n, n));
     DACP_HIP(W.ctx, hipStreamSynchronize(W.ctx->stream));  // `rows` goes out of scope
     return DACP_OK;
   }
@@ -416,11 +411,10 @@ dacp_status solve(DcWork &W, std::vector<double> &d, std::vector<double> &e, int
     }
     DACP_HIP(W.ctx, idx.alloc(n * sizeof(int)));
     DACP_HIP(W.ctx, stage.alloc(static_cast<size_t>(n) * n * sizeof(double)));
-    DACP_HIP(W.ctx, hipMemcpyAsync(idx.p, src.data(), n * sizeof(int), hipMemcpyHostToDevice, W.ctx->stream));
+    DACP_TRY(to_device(W.ctx, idx.p, src.data(), n * sizeof(int)));
     hipLaunchKernelGGL(k_gather_block, dim3(nblk(static_cast<int64_t>(n) * n, 256)), dim3(256), 0, W.ctx->stream,
                        W.Z, (int64_t)W.n, idx.as<int>(), lo, n, n, stage.as<double>(), (int64_t)n);
-    DACP_HIP(W.ctx, hipMemcpy2DAsync(W.Z + static_cast<int64_t>(lo) * W.n + lo, W.n * sizeof(double), stage.p,
-                                     n * sizeof(double), n * sizeof(double), n, hipMemcpyDeviceToDevice,
+    DACP_HIP(W.ctx, launch_copy_cols(stage.as<double>(), n, W.Z + static_cast<int64_t>(lo) * W.n + lo, W.n, n, n,
                                      W.ctx->stream));
     DACP_HIP(W.ctx, hipStreamSynchronize(W.ctx->stream));
     return DACP_OK;
@@ -434,6 +428,9 @@ dacp_status solve(DcWork &W, std::vector<double> &d, std::vector<double> &e, int
 // w (host) ascending; Z (device n x n, ld n): row j = eigenvector j.  Z is zero-filled
 // here (off-block entries of the merged halves must read as zero).
 dacp_status dc_tridiag(dacp_ctx ctx, int n, const double *d_in, const double *e_in, double *w, double *Z) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(d_in[i]) || (i + 1 < n && !std::isfinite(e_in[i])))
+      return set_err(ctx, DACP_E_NUMERIC, "divide and conquer: non-finite tridiagonal entry");
   DACP_HIP(ctx, hipMemsetAsync(Z, 0, static_cast<size_t>(n) * n * sizeof(double), ctx->stream));
   DcWork W;
   W.ctx = ctx;

@@ -315,11 +315,11 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   const double t_begin = wall_ms();
   if (n <= 0) return DACP_OK;
   if (n == 1) {
-    DACP_HIP(ctx, hipMemcpyAsync(w, A, sizeof(double), hipMemcpyDeviceToHost, st));
+    DACP_TRY(to_host(ctx, w, A, sizeof(double)));
     DACP_HIP(ctx, hipStreamSynchronize(st));
     if (Zrows) {
       const double one = 1.0;
-      DACP_HIP(ctx, hipMemcpyAsync(Zrows, &one, sizeof(double), hipMemcpyHostToDevice, st));
+      DACP_TRY(to_device(ctx, Zrows, &one, sizeof(double)));
       DACP_HIP(ctx, hipStreamSynchronize(st));
     }
     return DACP_OK;
@@ -347,11 +347,10 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   std::vector<double> d(n), e(n, 0.0);
   double tail[4];
   if (n > 2) {
-    DACP_HIP(ctx, hipMemcpyAsync(d.data(), dd, sizeof(double) * (n - 2), hipMemcpyDeviceToHost, st));
-    DACP_HIP(ctx, hipMemcpyAsync(e.data(), de, sizeof(double) * (n - 2), hipMemcpyDeviceToHost, st));
+    DACP_TRY(to_host(ctx, d.data(), dd, sizeof(double) * (n - 2)));
+    DACP_TRY(to_host(ctx, e.data(), de, sizeof(double) * (n - 2)));
   }
-  DACP_HIP(ctx, hipMemcpy2DAsync(tail, 2 * sizeof(double), A + static_cast<int64_t>(n - 2) * ld + (n - 2),
-                                 ld * sizeof(double), 2 * sizeof(double), 2, hipMemcpyDeviceToHost, st));
+  DACP_TRY(to_host_2d(ctx, tail, A + static_cast<int64_t>(n - 2) * ld + (n - 2), ld, 2, 2));
   DACP_HIP(ctx, hipStreamSynchronize(st));
   d[n - 2] = tail[0];
   e[n - 2] = tail[2];
@@ -377,6 +376,7 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
     DACP_HIP(ctx, zt.alloc(static_cast<size_t>(n) * n * sizeof(double)));
     DACP_HIP(ctx, qc.alloc(static_cast<size_t>(n) * n * sizeof(double)));
     DACP_HIP(ctx, hipMemcpyAsync(qc.p, Zrows, static_cast<size_t>(n) * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    DACP_HIP(ctx, hipStreamSynchronize(st));  // the Q-formation kernels read db and A
     (void)hipFree(dv);
     (void)hipFree(dp);
     (void)hipFree(dd);
@@ -477,7 +477,7 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
     const int64_t nn = static_cast<int64_t>(n) * n;
     DACP_HIP(ctx, hipMalloc(&tmp, sizeof(double) * nn));
     DACP_HIP(ctx, hipMalloc(&dperm, sizeof(int) * n));
-    DACP_HIP(ctx, hipMemcpyAsync(dperm, perm.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    DACP_TRY(to_device(ctx, dperm, perm.data(), sizeof(int) * n));
     DACP_HIP(ctx, hipMemcpyAsync(tmp, Zrows, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, st, tmp, (int64_t)n, Zrows, (int64_t)n,
                        dperm, nullptr, n, n);

@@ -239,3 +239,21 @@ dacp_status dc_tridiag(dacp_ctx ctx, int n, const double *d, const double *e, do
     hipError_t e_ = (call);                                  \
     if (e_ != hipSuccess) return dacp::hip_err(ctx, e_, #call); \
   } while (0)
+
+#define DACP_TRY(call)                \
+  do {                                \
+    const dacp_status s_ = (call);    \
+    if (s_ != DACP_OK) return s_;     \
+  } while (0)
+
+namespace dacp {
+// Host <-> device copies of host-side bookkeeping (pageable host memory).  Each one waits for
+// the context stream, then copies with a blocking call: the host buffer is complete (to_host)
+// or no longer needed (to_device) on return, and later work on the stream sees the data.
+dacp_status to_host(dacp_ctx ctx, void *host, const void *dev, size_t bytes);
+dacp_status to_device(dacp_ctx ctx, void *dev, const void *host, size_t bytes);
+// rows x cols doubles between a contiguous host array and a device array with row stride lddev
+// (staged through a contiguous device buffer: no pitched runtime copies)
+dacp_status to_host_2d(dacp_ctx ctx, double *host, const double *dev, int64_t lddev, int64_t rows, int64_t cols);
+dacp_status to_device_2d(dacp_ctx ctx, double *dev, int64_t lddev, const double *host, int64_t rows, int64_t cols);
+}  // namespace dacp
