@@ -23,6 +23,11 @@ WORKLOADS = {
     "chain_L10_N100": dict(L=10, N=100, b=4),
 }
 HBM_PEAK_GBPS = 8000.0
+# HBM bytes per evolution launch measured with the FETCH_SIZE and WRITE_SIZE counters (each scaled by
+# its reading on a 256 MiB device copy), for the kernel build and launch shape named by the key:
+# (workload, kernel pair, column group).  Reported as roofline.traffic only for that configuration.
+EVOLUTION_KERNELS = "k_rec_lo/k_rec_hi<double, 1024, 4> v3"
+MEASURED_TRAFFIC = {("chain_L20_N5000", EVOLUTION_KERNELS, 8): 275.17e6}
 
 
 def parse():
@@ -202,7 +207,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC.get((args.workload, EVOLUTION_KERNELS, g)),
             "avg_launch_ms": evol_launch_ms,
             "bytes_per_launch": bytes_per_launch,
         },

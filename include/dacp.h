@@ -166,7 +166,7 @@ typedef struct {
  * E_0 = (E_b^2 - a^2)/2, every column normalised to 1 (Sec. II.A, Eq. F,
  * Eq. target).  start: device [D][b] FP64 or NULL (seeded Gaussian).
  * psi_out: device [D][b] FP64.  Columns are filtered independently (in groups
- * of 4 when L >= 15, so the working set stays cache resident).  With precision DACP_F32 the first
+ * of 8 (FP64) or 16 (FP32) when L >= 15, so the working set stays cache resident).  With precision DACP_F32 the first
  * K - fp64_tail steps of the same recurrence run in FP32 (FP32 storage and
  * accumulation); the pair (T_{k-1}, T_k) is then converted to FP64 and the
  * last fp64_tail steps run in FP64.  Start and output must not overlap. */
@@ -180,7 +180,7 @@ typedef struct {
   int n;          /* number of sample pairs; basis width m = b (2n + 1)        */
   int b;          /* block width                                               */
   int group;      /* evolve columns in groups of this width (0 = library     */
-                  /* default: 4 when L >= 15 and b > 4, else all b)          */
+                  /* default: 8 when L >= 15 and b > 8, else all b)          */
 } dacp_basis_params;
 
 /* Chebyshev evolution T_{k+1} = 2 G T_k - T_{k-1} from psi_E (device [D][b]
@@ -210,8 +210,10 @@ dacp_status dacp_rayleigh_ritz(dacp_ctx ctx, int m, const double *S, const doubl
                                double *theta_out, double *B_out, int *r_out);
 
 /* Dense symmetric eigen-decomposition on the GPU (Householder
- * tridiagonalisation, implicit QL): A device n x n (ld), destroyed;
- * w host ascending; Zrows device n x n (row j = eigenvector j) or NULL. */
+ * tridiagonalisation; eigenvectors of the tridiagonal by divide and conquer
+ * for n >= the "dc" knob (default 96), else implicit QR with the rotations
+ * replayed on the GPU; eigenvalues only: implicit QR): A device n x n (ld),
+ * destroyed; w host ascending; Zrows device n x n (row j = eigenvector j) or NULL. */
 dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
 
 /* C = alpha op(A) op(B) + beta C in FP64 on the matrix cores (row-major;
@@ -229,7 +231,8 @@ typedef struct {
   double window_ratio; /* levels wanted in [-a, a] = ceil(window_ratio * N) (2.2)     */
   double basis_ratio;  /* m = b (2n + 1) ~ basis_ratio * window count (1.5)           */
   double eps;          /* S eigenvalue cut-off (1e-12, App. C)                        */
-  double tol_rel;      /* accept |error| <= tol_rel * E_b (1e-10)                     */
+  double tol_rel;      /* accept |error| <= tol_rel * max(|theta_min|, |theta_max|) of the */
+                       /* bound's Lanczos run, an estimate of ||H|| (1e-10)           */
   int lanczos_steps;   /* bound estimator steps (80)                                  */
   int kpm_moments;     /* density moments (256)                                       */
   int kpm_vectors;     /* random vectors for the density (8)                          */
