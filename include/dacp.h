@@ -96,6 +96,7 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "rec_threads" fused recurrence: threads per workgroup, 512 or 1024 (default 1024)
  *   "rec_persist" fused recurrence: 0 = one workgroup per tile (default); n = 1..8 persistent
  *                 workgroups per compute unit that prefetch their next tile
+ *   "batch_workers" host threads finishing the realisations of dacp_central_eigs_batched (1..64, default 8)
  *   "group"       evolution column-group width when L >= 15 (power of two, default 8)
  *   "filter_group_f64", "filter_group_f32"
  *                 filter column-group width when L >= 15 for the FP64 / FP32 recurrence
@@ -268,6 +269,26 @@ void dacp_default_opts(dacp_opts *opts);
  * or, on DACP_E_WINDOW, the number accepted.  report may be NULL. */
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report);
+
+/* dacp_central_eigs for `count` independent realisations (disorder samples, possibly of
+ * different L, every L <= 14) with the same N and options.  Bounds, densities and windows are
+ * set per realisation; then ONE persistent launch runs the filter and the evolution of every
+ * start column of every realisation: each workgroup keeps one 2^L column on chip (the vector
+ * being applied in LDS, the recurrence terms in registers) and writes only the sampled panels
+ * of its basis (Sec. II.A, II.B on many small problems at once).  Projection, subspace solve
+ * and acceptance follow per realisation, spread over host worker threads with their own
+ * streams.  A realisation whose accepted core falls short is redone alone with a 1.5x wider
+ * window.
+ *   hams[count]              Hamiltonian handles (distinct or repeated)
+ *   eigs_out[count * N]      host; row r = the N values of realisation r, ascending
+ *   err_out[count * N]       host, may be NULL; error estimates as for dacp_central_eigs
+ *   n_out[count]             host; N, or the number accepted for a realisation that fell short
+ *   reports[count]           host, may be NULL; per realisation (t_evol_ms is the time of the
+ *                            shared launch, t_filter_ms is 0: the filter runs inside it)
+ * Returns DACP_E_INVALID for L > 14, DACP_E_BOUNDS if a bound is below ||H||, DACP_E_WINDOW
+ * if some realisation stays short after its retry (the others are still filled in). */
+dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
+                                      double *eigs_out, double *err_out, int *n_out, dacp_report *reports);
 
 #ifdef __cplusplus
 }

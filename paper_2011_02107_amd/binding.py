@@ -142,6 +142,10 @@ SIGNATURES = {
     ),
     "dacp_default_opts": (None, [ctypes.POINTER(Opts)]),
     "dacp_central_eigs": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)]),
+    "dacp_central_eigs_batched": (
+        ctypes.c_int,
+        [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)],
+    ),
 }
 
 _lib = None
@@ -345,3 +349,21 @@ def dacp_central_eigs(ctx, ham, N, opts=None, raise_on_window=True):
         ctx.check(st)
     n = n_out.value if st == 0 else 0
     return eigs[:n], errs[:n], rep.as_dict(), st
+
+
+def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True):
+    """Returns (eigs [count, N], errs [count, N], n_out [count], list of report dicts, status)."""
+    if opts is None:
+        opts = default_opts()
+    count = len(hams)
+    eigs = np.zeros((count, N))
+    errs = np.zeros((count, N))
+    n_out = np.zeros(count, dtype=np.int32)
+    reps = (Report * count)()
+    handles = (_vp * count)(*[h.handle for h in hams])
+    st = ctx.lib.dacp_central_eigs_batched(
+        ctx.handle, count, handles, int(N), ctypes.byref(opts), _f64(eigs), _f64(errs),
+        n_out.ctypes.data_as(_ip), reps)
+    if st != 0 and (raise_on_window or st != -5):
+        ctx.check(st)
+    return eigs, errs, n_out, [r.as_dict() for r in reps], st

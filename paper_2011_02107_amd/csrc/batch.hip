@@ -1,0 +1,334 @@
+// Batched Chebyshev path for many small realisations (L <= 14) in one persistent launch.
+//
+// Workgroup g owns column j of realisation r (descriptor cols[g]) and runs that column's
+// whole recurrence on-chip: the vector being applied sits in LDS (one 2^L-long column,
+// <= 128 KB in FP64), the other recurrence terms in registers (2^L / 1024 elements per
+// thread).  In order it runs
+//   1. the exp-semicircle filter T_K(F) psi (Sec. II.A, Eqs. F, filter) with the damped
+//      recurrence T^_{k+1} = alpha H(H T^_k) + beta T^_k + gamma T^_{k-1}: the first K - tail
+//      orders in FP32 (FP32 storage and accumulation), the last `tail` orders in FP64;
+//   2. column normalisation (a fixed-order workgroup reduction);
+//   3. the Chebyshev evolution T_{k+1} = 2 G T_k - T_{k-1}, G = H / E_b (Sec. II.B), storing
+//      the panels T_{k_m - 1}, T_{k_m} into the realisation's basis V (App. C, Eq. set2) and
+//      checking |T_{k_m}| <= |psi_E| at every sample.
+// Global memory is touched only for the start column, the diagonal table (cached) and the
+// samples.  Every element's flip sum runs in the flip-table order, as in the other kernels.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace dacp {
+
+namespace {
+
+constexpr int kBT = 1024;  // threads per workgroup
+
+typedef const __attribute__((address_space(4))) BatchCol *ConstBatchCols;
+typedef const __attribute__((address_space(4))) FlipEntry *ConstFlipTable;
+typedef const __attribute__((address_space(4))) int *ConstInts;
+
+// Global accesses as a uniform base plus a 32-bit byte offset (every offset here is < 2^32,
+// checked on the host), so the per-element address is one 32-bit register instead of a
+// 64-bit pointer per array kept live across the step loops.
+// threadIdx.x * scale, opaque to loop-invariant code motion: an empty asm statement (no
+// instruction) redefines the value, so the addresses derived from it are formed where they are
+// used instead of being hoisted out of the step loops and held in registers for the whole kernel.
+__device__ __forceinline__ uint32_t tid_off(uint32_t scale) {
+  uint32_t o = threadIdx.x * scale;
+  asm volatile("" : "+v"(o));
+  return o;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T x) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = x;
+}
+
+// v <- H v for this thread's elements s = tid + i * kBT (i < E); lds holds the whole column
+// while the flips are summed.  E = 1 also covers D < kBT (threads with s >= D idle).
+template <typename T, int E>
+__device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, ConstFlipTable flips, int nplain,
+                                              int nflip, uint32_t D) {
+  __syncthreads();  // the previous apply's readers are done with lds
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t s = threadIdx.x + i * kBT;
+    if (E > 1 || s < D) lds[s] = v[i];
+  }
+  __syncthreads();
+  if (E == 1 && threadIdx.x >= D) return;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t o = tid_off(sizeof(T)) + static_cast<uint32_t>(i * kBT * sizeof(T));
+    v[i] *= ld_at(diag, o);
+  }
+  // elements in chunks of at most 4, each chunk running the whole flip list (sign-free flips
+  // first): bounds the loads in flight, and the registers holding them, independently of E
+  constexpr int C = E < 4 ? E : 4;
+#pragma unroll
+  for (int ib = 0; ib < E; ib += C) {
+#pragma nounroll
+    for (int t = 0; t < nplain; ++t) {
+      const uint32_t xm = flips[t].xmask;
+      const T c = static_cast<T>(flips[t].coef);
+#pragma unroll
+      for (int i = ib; i < ib + C; ++i) v[i] += c * lds[(threadIdx.x + i * kBT) ^ xm];
+    }
+#pragma nounroll
+    for (int t = nplain; t < nflip; ++t) {
+      const uint32_t xm = flips[t].xmask;
+      const uint32_t zm = flips[t].zmask;
+      const T c = static_cast<T>(flips[t].coef);
+#pragma unroll
+      for (int i = ib; i < ib + C; ++i) {
+        const uint32_t src = (threadIdx.x + i * kBT) ^ xm;
+        v[i] += ((__popc(src & zm) & 1) ? -c : c) * lds[src];
+      }
+    }
+  }
+}
+
+// Sum over the workgroup in a fixed order (wave shuffles, then the waves in index order).
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kBT / 64; ++w) t += red[w];
+  return t;
+}
+
+template <int E>
+__device__ __forceinline__ double sum_sq(const double (&v)[E], uint32_t D, double *red) {
+  double p = 0.0;
+#pragma unroll
+  for (int i = 0; i < E; ++i)
+    if (E > 1 || threadIdx.x < D) p += v[i] * v[i];
+  return block_sum(p, red);
+}
+
+template <int E>
+__device__ __forceinline__ void store_panel(double *V, int64_t ldv, int64_t col, const double (&v)[E], uint32_t D) {
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t s = tid_off(1u) + static_cast<uint32_t>(i * kBT);
+    if (E > 1 || s < D) st_at(V, (s * static_cast<uint32_t>(ldv) + static_cast<uint32_t>(col)) * 8u, v[i]);
+  }
+}
+
+// Store T_kk when kk is a sample order; at k_m also check |T_{k_m}|^2 <= 1 (unit start column).
+template <int E>
+__device__ __forceinline__ void sample_at(const BatchCol &c, ConstInts ks, int &next, int64_t kk, const double (&T)[E],
+                                          uint32_t D, double *red) {
+  if (next >= c.n_samples) return;
+  const int64_t km = ks[next];
+  if (kk == km - 1) store_panel<E>(c.V, c.ldv, static_cast<int64_t>(2 * next + 1) * c.b, T, D);
+  if (kk == km) {
+    store_panel<E>(c.V, c.ldv, static_cast<int64_t>(2 * next + 2) * c.b, T, D);
+    const double n2 = sum_sq<E>(T, D, red);
+    if (!(n2 <= 1.0 + 2e-6) && threadIdx.x == 0) *c.bound_flag = 1;
+    ++next;
+  }
+}
+
+// A recurrence term held per thread: in registers when a thread holds <= 8 elements (g is then
+// never used and may be null), otherwise in a 2^L-double slice of the column's global scratch,
+// read back only by the thread that wrote it (L2 resident).
+template <int E>
+struct Held {
+  static constexpr bool kRegs = E <= 8;
+  double r[kRegs ? E : 1];
+  double *g;
+  // i: element slot; boff: its byte offset (element index * 8)
+  __device__ __forceinline__ double get(int i, uint32_t boff) const { return kRegs ? r[kRegs ? i : 0] : ld_at(g, boff); }
+  __device__ __forceinline__ void set(int i, uint32_t boff, double x) {
+    if (kRegs) r[kRegs ? i : 0] = x;
+    else st_at(g, boff, x);
+  }
+};
+
+template <int E>
+__device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable flips, ConstInts ks, unsigned char *smem,
+                                           double *red) {
+  const uint32_t D = 1u << c.L;
+  double *lds64 = reinterpret_cast<double *>(smem);
+  float *lds32 = reinterpret_cast<float *>(smem);
+  const bool active = E > 1 || threadIdx.x < D;
+  Held<E> A, Bk;  // T_(k-1); T^_k during an FP64 filter order
+  A.g = c.scratch;
+  Bk.g = c.scratch ? c.scratch + D : nullptr;
+  double v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t s = threadIdx.x + i * kBT;
+    v[i] = active ? ld_at(c.psi0, s * static_cast<uint32_t>(c.ld_psi) * 8u) : 0.0;  // start column
+  }
+
+  // ---- filter: on exit v = T^_K, A = T^_(K-1)
+  int tail = 0;
+  if (c.K == 0) {
+    // psi_E = psi
+  } else if (c.n32 >= 1) {
+    float Af[E], Bf[E], Tf[E];
+    const float fa = static_cast<float>(c.f_alpha), fb = static_cast<float>(c.f_beta);
+    const float fg = static_cast<float>(c.f_gamma);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      Af[i] = static_cast<float>(v[i]);
+      Tf[i] = Af[i];
+    }
+    apply_inplace<float, E>(Tf, lds32, c.d32, flips, c.nplain, c.nflip, D);
+    apply_inplace<float, E>(Tf, lds32, c.d32, flips, c.nplain, c.nflip, D);
+    const float f1a = static_cast<float>(c.f_first_a), f1b = static_cast<float>(c.f_first_b);
+#pragma unroll
+    for (int i = 0; i < E; ++i) Bf[i] = f1a * Tf[i] + f1b * Af[i];
+    for (int k = 1; k < c.n32; ++k) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) Tf[i] = Bf[i];
+      apply_inplace<float, E>(Tf, lds32, c.d32, flips, c.nplain, c.nflip, D);
+      apply_inplace<float, E>(Tf, lds32, c.d32, flips, c.nplain, c.nflip, D);
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const float nb = fa * Tf[i] + fb * Bf[i] + fg * Af[i];
+        Af[i] = Bf[i];
+        Bf[i] = nb;
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        A.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), static_cast<double>(Af[i]));
+        v[i] = static_cast<double>(Bf[i]);
+      }
+    }
+    tail = c.K - c.n32;
+  } else {
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) A.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), v[i]);
+    }
+    apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);
+    apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
+        v[i] = c.f_first_a * v[i] + c.f_first_b * A.get(i, bo);
+      }
+    }
+    tail = c.K - 1;
+  }
+  for (int k = 0; k < tail; ++k) {
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) Bk.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), v[i]);
+    }
+    apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);
+    apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
+        const double b = Bk.get(i, bo);
+        const double nb = c.f_alpha * v[i] + c.f_beta * b + c.f_gamma * A.get(i, bo);
+        A.set(i, bo, b);
+        v[i] = nb;
+      }
+    }
+  }
+
+  // ---- normalise: psi_E = v / |v|
+  {
+    const double inv = 1.0 / sqrt(sum_sq<E>(v, D, red));
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] *= inv;
+  }
+
+  // ---- evolution: A = T_(k-1), v = T_k
+  store_panel<E>(c.V, c.ldv, 0, v, D);
+  int next = 0;
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) A.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), v[i]);
+  }
+  apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] *= c.inv_e;
+  sample_at<E>(c, ks, next, 1, v, D, red);
+  const int64_t kmax = c.n_samples > 0 ? ks[c.n_samples - 1] : 1;
+  const double two_inv_e = 2.0 * c.inv_e;
+  for (int64_t k = 1; k < kmax; ++k) {
+    apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);  // lds keeps T_k
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
+        const double nb = two_inv_e * v[i] - A.get(i, bo);
+        A.set(i, bo, ld_at(lds64, bo));
+        v[i] = nb;
+      }
+    }
+    sample_at<E>(c, ks, next, k + 1, v, D, red);
+  }
+}
+
+__global__ __launch_bounds__(kBT) void k_batch_chebyshev(const BatchCol *cols_g) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[kBT / 64];
+  // field by field through the constant address space (uniform scalar loads)
+  const ConstBatchCols cc = (ConstBatchCols)cols_g + blockIdx.x;
+  BatchCol c;
+  c.flips = cc->flips;
+  c.d64 = cc->d64;
+  c.d32 = cc->d32;
+  c.psi0 = cc->psi0;
+  c.V = cc->V;
+  c.ks = cc->ks;
+  c.bound_flag = cc->bound_flag;
+  c.scratch = cc->scratch;
+  c.ld_psi = cc->ld_psi;
+  c.ldv = cc->ldv;
+  c.f_alpha = cc->f_alpha;
+  c.f_beta = cc->f_beta;
+  c.f_gamma = cc->f_gamma;
+  c.f_first_a = cc->f_first_a;
+  c.f_first_b = cc->f_first_b;
+  c.inv_e = cc->inv_e;
+  c.L = cc->L;
+  c.nflip = cc->nflip;
+  c.nplain = cc->nplain;
+  c.K = cc->K;
+  c.n32 = cc->n32;
+  c.n_samples = cc->n_samples;
+  c.b = cc->b;
+  const ConstFlipTable flips = (ConstFlipTable)c.flips;
+  const ConstInts ks = (ConstInts)c.ks;
+  switch (c.L) {  // elements per thread: 2^L / 1024, at least 1
+    case 14: run_column<16>(c, flips, ks, smem_raw, red); break;
+    case 13: run_column<8>(c, flips, ks, smem_raw, red); break;
+    case 12: run_column<4>(c, flips, ks, smem_raw, red); break;
+    case 11: run_column<2>(c, flips, ks, smem_raw, red); break;
+    default: run_column<1>(c, flips, ks, smem_raw, red); break;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_batch_chebyshev(const BatchCol *cols, int ncols, int max_L, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  if (max_L < 1 || max_L > 14) return hipErrorInvalidValue;
+  const size_t lds = (size_t(1) << max_L) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_chebyshev),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_chebyshev, dim3(ncols), dim3(kBT), lds, s, cols);
+  return hipGetLastError();
+}
+
+}  // namespace dacp

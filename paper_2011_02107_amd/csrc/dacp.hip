@@ -11,6 +11,7 @@
 #include <map>
 #include <numeric>
 #include <type_traits>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -21,6 +22,7 @@ using dacp::FlipEntry;
 using dacp::StepArgs;
 using dacp::to_device;
 using dacp::to_host;
+using dacp::BatchCol;
 
 namespace dacp {
 
@@ -139,6 +141,7 @@ dacp_status coldots_host(dacp_ctx ctx, const void *x, int64_t ldx, const void *y
 // Flip table ordered for tiles of 2^log2R rows: masks inside the tile (read from LDS), masks
 // entirely above it (partner row = (row0 ^ x) + r), then mixed masks; x-mask order within each.
 dacp_status tile_order(dacp_ctx ctx, dacp_ham h, int log2R) {
+  std::lock_guard<std::mutex> lock(h->tables_mu);
   auto &to = h->by_log2r[log2R];
   if (to.dev) return DACP_OK;
   const uint32_t lowmask = (1u << log2R) - 1u;
@@ -161,6 +164,7 @@ dacp_status tile_order(dacp_ctx ctx, dacp_ham h, int log2R) {
 
 // Flip tables for the two-pass apply split at bit lo_bits.
 dacp_status split_order(dacp_ctx ctx, dacp_ham h, int lo_bits) {
+  std::lock_guard<std::mutex> lock(h->tables_mu);
   auto &so = h->split[lo_bits];
   if (so.lo) return DACP_OK;
   const uint32_t lowmask = (1u << lo_bits) - 1u;
@@ -310,7 +314,6 @@ dacp_status step(dacp_ctx ctx, dacp_ham h, int b, const T *x, int64_t ldx, T *y,
     while ((int64_t(2) << log2R) <= D && (int64_t(2) << log2R) * bc <= ctx->tile_elems &&
            (int64_t(2) << log2R) * ldx * static_cast<int64_t>(sizeof(T)) < (int64_t(1) << 31))
       ++log2R;
-    const int R = 1 << log2R;
     StepArgs<T> a;
     a.x = x + c0;
     a.ldx = ldx;
@@ -970,6 +973,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->rec_threads = value;
     return DACP_OK;
   }
+  if (k == "batch_workers") {
+    if (value < 1 || value > 64) return set_err(ctx, DACP_E_INVALID, "batch_workers: 1..64");
+    ctx->batch_workers = value;
+    return DACP_OK;
+  }
   if (k == "rec_persist") {
     if (value < 0 || value > 8) return set_err(ctx, DACP_E_INVALID, "rec_persist: 0..8 workgroups per CU");
     ctx->rec_persist = value;
@@ -1202,6 +1210,198 @@ void dacp_default_opts(dacp_opts *o) {
   o->max_retries = 1;
 }
 
+// Window, orders and basis size of one attempt (Sec. II.A, II.B, III; readings in the header).
+struct Plan {
+  double n_w, a_r, a;
+  int K, b, n, m;
+};
+
+Plan make_plan(const dacp_opts &o, int64_t D, int N, double e_b, const std::vector<double> &mu, double window_ratio,
+               int attempt) {
+  Plan p;
+  p.n_w = std::min(static_cast<double>(D), std::ceil(window_ratio * N));
+  double a_r = (o.a > 0.0 && attempt == 0) ? o.a / e_b
+                                           : window_for_count(mu.empty() ? std::vector<double>{1.0} : mu, D, p.n_w);
+  if (o.a > 0.0 && attempt > 0) a_r = std::min(0.95, (o.a / e_b) * std::pow(1.5, attempt));
+  p.a_r = std::min(a_r, 0.95);
+  p.a = p.a_r * e_b;
+  const double kfac = o.kfac > 0.0 ? o.kfac : 18.0;
+  p.K = static_cast<int>(std::ceil(kfac / p.a_r));
+  p.b = o.b;
+  if (p.b <= 0) {
+    p.b = 4;
+    while (p.b < 64 && p.b * 16 <= p.n_w) p.b *= 2;
+  }
+  const double basis_ratio = o.basis_ratio > 0.0 ? o.basis_ratio : 1.5;
+  p.n = std::max(1, static_cast<int>(std::ceil((basis_ratio * p.n_w / p.b - 1.0) / 2.0)));
+  p.m = p.b * (2 * p.n + 1);
+  return p;
+}
+
+// Projection (Sec. II.C), subspace solve (App. C) and acceptance (Sec. II.C residual check) for
+// one realisation whose basis V (D x m, row stride m) is built.  `accepted` gets the size of the
+// contiguous accepted core; when it reaches N the N values and their estimates are written.
+dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
+                         double norm_est, const double *V, int m, dacp_report &rep, double *eigs_out, double *err_out,
+                         int &accepted) {
+  const int64_t D = h->D;
+  hipStream_t s = ctx->stream;
+  (void)norm_est;
+  // projection (Sec. II.C)
+  double t0 = now_ms();
+  dacp_status st;
+  DevBuf sb, pb;
+  DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+  DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+  st = run_project(ctx, h, m, V, m, sb.as<double>(), pb.as<double>(), m);
+  if (st) return st;
+  rep.t_project_ms = now_ms() - t0;
+  vlog("projection done: %.1f ms", rep.t_project_ms);
+
+  // generalised eigenproblem (App. C)
+  t0 = now_ms();
+  std::vector<double> theta;
+  DevBuf bc;
+  int r = 0;
+  st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r);
+  if (st) return st;
+  sb.release();
+  pb.release();
+  rep.rank = r;
+  rep.t_gep_ms = now_ms() - t0;
+  vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
+
+  // acceptance (Sec. II.C residual check): candidates by |theta|
+  t0 = now_ms();
+  std::vector<int> order(r);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+    const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
+    return ai < aj || (ai == aj && theta[i] < theta[j]);
+  });
+  const int n_sel = std::min(r, N + std::max(64, N / 8));
+  std::vector<double> rnorm(n_sel, INFINITY);
+  {
+    const int cw = std::min(n_sel, 512);
+    DevBuf bsel, phi, hphi, dth, dperm;
+    DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
+    DACP_HIP(ctx, phi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
+    DACP_HIP(ctx, hphi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
+    DACP_HIP(ctx, dth.alloc(sizeof(double) * cw));
+    DACP_HIP(ctx, dperm.alloc(sizeof(int) * cw));
+    const int nblk = dacp::coldots_blocks(D, 2 * cw);
+    st = ensure_red(ctx, static_cast<size_t>(nblk) * 2 * cw, 2 * cw);
+    if (st) return st;
+    std::vector<double> out(2 * cw);
+    for (int c0 = 0; c0 < n_sel; c0 += cw) {
+      const int w = std::min(cw, n_sel - c0);
+      std::vector<int> pr(order.begin() + c0, order.begin() + c0 + w);
+      std::vector<double> th(w);
+      for (int i = 0; i < w; ++i) th[i] = theta[pr[i]];
+      DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
+      DACP_TRY(to_device(ctx, dth.p, th.data(), sizeof(double) * w));
+      DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, w, m,
+                                             s));
+      // Phi = V B_sel  (D x w)
+      DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, V, m, bsel.as<double>(), m, 0.0,
+                                       phi.as<double>(), w, 0, s));
+      st = step<double>(ctx, h, w, phi.as<double>(), w, hphi.as<double>(), w, 1.0);
+      if (st) return st;
+      DACP_HIP(ctx, dacp::launch_resid(phi.as<double>(), hphi.as<double>(), w, dth.as<double>(), D, w, ctx->red,
+                                       dacp::coldots_blocks(D, 2 * w), ctx->red_out, s));
+      DACP_TRY(to_host(ctx, out.data(), ctx->red_out, sizeof(double) * 2 * w));
+      DACP_HIP(ctx, hipStreamSynchronize(s));
+      for (int i = 0; i < w; ++i) rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
+    }
+  }
+  // Acceptance.  The Ritz residual r_j is orthogonal to the whole search space, which holds the
+  // converged neighbours of theta_j, so the quadratic residual bound |theta_j - lambda_j| <=
+  // ||r_j||^2 / eta_j uses eta_j = distance from theta_j to the part of the spectrum the subspace does
+  // not resolve: the nearest unaccepted Ritz value, or the window edge (levels beyond a are not
+  // represented).  Start from the candidates whose residual is below a generous cap, iterate to a
+  // fixed point, then keep the contiguous accepted core around 0 (walk outward in |theta|, stop at
+  // the first rejection).  The estimate reported is min(||r||, ||r||^2 / eta).
+  //
+  // A Ritz value whose residual exceeds ten mean level spacings of the window approximates no
+  // eigenvalue near it (a "ghost" built from weakly represented directions of the overcomplete
+  // basis): it is left out of eta and does not stop the core.  Central levels carry the largest
+  // filter amplitude, so a true level there is never that poorly represented.
+  std::vector<char> ok(r, 0), ghost(r, 0);
+  const double cap = 1e-4 * norm_est;
+  const double ghost_thr = 10.0 * (2.0 * a / n_w);
+  for (int i = 0; i < n_sel; ++i) {
+    ok[order[i]] = rnorm[i] <= cap;
+    ghost[order[i]] = rnorm[i] > ghost_thr;
+  }
+  int n_ghost = 0;
+  for (int i = 0; i < n_sel; ++i) n_ghost += ghost[order[i]];
+  std::vector<double> est(n_sel, INFINITY);
+  for (int iter = 0; iter < 8; ++iter) {
+    std::vector<double> unc;  // sorted Ritz values not (or no longer) accepted, ghosts excluded
+    for (int i = 0; i < r; ++i)
+      if (!ok[i] && !ghost[i]) unc.push_back(theta[i]);
+    bool changed = false;
+    for (int q = 0; q < n_sel; ++q) {
+      const int j = order[q];
+      if (!ok[j]) continue;
+      double eta = a - std::fabs(theta[j]);
+      auto it = std::lower_bound(unc.begin(), unc.end(), theta[j]);
+      if (it != unc.end()) eta = std::min(eta, *it - theta[j]);
+      if (it != unc.begin()) eta = std::min(eta, theta[j] - *(it - 1));
+      est[q] = (eta > 0.0) ? std::min(rnorm[q], rnorm[q] * rnorm[q] / eta) : rnorm[q];
+      if (!(est[q] <= tol)) {
+        ok[j] = 0;
+        changed = true;
+      }
+    }
+    if (!changed) break;
+  }
+  // walk outward in |theta|: ghosts are skipped, the first other rejection ends the core
+  std::vector<int> core_idx;  // positions q (into order) of the accepted core
+  double max_est = 0.0;
+  for (int q = 0; q < n_sel && std::fabs(theta[order[q]]) <= a; ++q) {
+    const int j = order[q];
+    if (ghost[j]) continue;
+    if (!ok[j]) break;
+    max_est = std::max(max_est, est[q]);
+    core_idx.push_back(q);
+  }
+  const int core = static_cast<int>(core_idx.size());
+  if (verbose()) {
+    int shown = 0;
+    for (int q = 0; q < n_sel && shown < 6; ++q) {
+      if (ok[order[q]] || ghost[order[q]]) continue;
+      const int j = order[q];
+      const double gl = j > 0 ? theta[j] - theta[j - 1] : INFINITY;
+      const double gr = j + 1 < r ? theta[j + 1] - theta[j] : INFINITY;
+      vlog("rejected #%d (|theta| rank %d): theta=%.10g r=%.3g est=%.3g gaps=(%.3g, %.3g) tol=%.3g", shown, q,
+           theta[j], rnorm[q], est[q], gl, gr, tol);
+      ++shown;
+    }
+    int n_ok = 0;
+    for (int q = 0; q < n_sel; ++q) n_ok += ok[order[q]] ? 1 : 0;
+    vlog("accepted (any position) %d of %d candidates; ghosts %d; contiguous core %d", n_ok, n_sel, n_ghost, core);
+  }
+  accepted = core;
+  rep.n_candidates = n_sel;
+  rep.n_accepted = core;
+  rep.max_err_est = max_est;
+  rep.n_ghost = n_ghost;
+  rep.t_accept_ms = now_ms() - t0;
+  vlog("acceptance done: %.1f ms, %d accepted of %d candidates", rep.t_accept_ms, core, n_sel);
+  accepted = core;
+  if (core >= N) {
+    std::vector<std::pair<double, double>> sel;
+    for (int i = 0; i < N; ++i) sel.push_back({theta[order[core_idx[i]]], est[core_idx[i]]});
+    std::sort(sel.begin(), sel.end());
+    for (int i = 0; i < N; ++i) {
+      eigs_out[i] = sel[i].first;
+      if (err_out) err_out[i] = sel[i].second;
+    }
+  }
+  return DACP_OK;
+}
+
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_in, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report) {
   if (!ctx || !h || !eigs_out) return DACP_E_INVALID;
@@ -1213,7 +1413,6 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
   dacp_report rep;
   std::memset(&rep, 0, sizeof(rep));
   const double t_start = now_ms();
-  hipStream_t s = ctx->stream;
 
   // bound (Sec. III upper-bound estimator)
   double t0 = now_ms();
@@ -1242,21 +1441,9 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
   int accepted = 0;
   for (int attempt = 0;; ++attempt) {
     // window and orders (Sec. II.A, II.B, III)
-    const double n_w = std::min(static_cast<double>(D), std::ceil(window_ratio * N));
-    double a_r = (o.a > 0.0 && attempt == 0) ? o.a / e_b : window_for_count(mu.empty() ? std::vector<double>{1.0} : mu, D, n_w);
-    if (o.a > 0.0 && attempt > 0) a_r = std::min(0.95, (o.a / e_b) * std::pow(1.5, attempt));
-    a_r = std::min(a_r, 0.95);
-    const double a = a_r * e_b;
-    const double kfac = o.kfac > 0.0 ? o.kfac : 18.0;
-    const int K = static_cast<int>(std::ceil(kfac / a_r));
-    int b = o.b;
-    if (b <= 0) {
-      b = 4;
-      while (b < 64 && b * 16 <= n_w) b *= 2;
-    }
-    const double basis_ratio = o.basis_ratio > 0.0 ? o.basis_ratio : 1.5;
-    const int n = std::max(1, static_cast<int>(std::ceil((basis_ratio * n_w / b - 1.0) / 2.0)));
-    const int m = b * (2 * n + 1);
+    const Plan pl = make_plan(o, D, N, e_b, mu, window_ratio, attempt);
+    const double n_w = pl.n_w, a_r = pl.a_r, a = pl.a;
+    const int K = pl.K, b = pl.b, n = pl.n, m = pl.m;
     rep.e_bound = e_b;
     rep.a = a;
     rep.a_r = a_r;
@@ -1306,155 +1493,9 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     rep.evol_group = es.group;
     vlog("evolution done: %.1f ms (%lld launches)", rep.t_evol_ms, static_cast<long long>(es.launches));
 
-    // projection (Sec. II.C)
-    t0 = now_ms();
-    DevBuf sb, pb;
-    DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
-    DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
-    st = run_project(ctx, h, m, vbuf.as<double>(), m, sb.as<double>(), pb.as<double>(), m);
+    st = finish_basis(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, rep, eigs_out, err_out, accepted);
     if (st) return st;
-    rep.t_project_ms = now_ms() - t0;
-    vlog("projection done: %.1f ms", rep.t_project_ms);
-
-    // generalised eigenproblem (App. C)
-    t0 = now_ms();
-    std::vector<double> theta;
-    DevBuf bc;
-    int r = 0;
-    st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r);
-    if (st) return st;
-    sb.release();
-    pb.release();
-    rep.rank = r;
-    rep.t_gep_ms = now_ms() - t0;
-    vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
-
-    // acceptance (Sec. II.C residual check): candidates by |theta|
-    t0 = now_ms();
-    std::vector<int> order(r);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
-      const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
-      return ai < aj || (ai == aj && theta[i] < theta[j]);
-    });
-    const int n_sel = std::min(r, N + std::max(64, N / 8));
-    std::vector<double> rnorm(n_sel, INFINITY);
-    {
-      const int cw = std::min(n_sel, 512);
-      DevBuf bsel, phi, hphi, dth, dperm;
-      DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
-      DACP_HIP(ctx, phi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
-      DACP_HIP(ctx, hphi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
-      DACP_HIP(ctx, dth.alloc(sizeof(double) * cw));
-      DACP_HIP(ctx, dperm.alloc(sizeof(int) * cw));
-      const int nblk = dacp::coldots_blocks(D, 2 * cw);
-      st = ensure_red(ctx, static_cast<size_t>(nblk) * 2 * cw, 2 * cw);
-      if (st) return st;
-      std::vector<double> out(2 * cw);
-      for (int c0 = 0; c0 < n_sel; c0 += cw) {
-        const int w = std::min(cw, n_sel - c0);
-        std::vector<int> pr(order.begin() + c0, order.begin() + c0 + w);
-        std::vector<double> th(w);
-        for (int i = 0; i < w; ++i) th[i] = theta[pr[i]];
-        DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
-        DACP_TRY(to_device(ctx, dth.p, th.data(), sizeof(double) * w));
-        DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, w, m,
-                                               s));
-        // Phi = V B_sel  (D x w)
-        DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, vbuf.as<double>(), m, bsel.as<double>(), m, 0.0,
-                                         phi.as<double>(), w, 0, s));
-        st = step<double>(ctx, h, w, phi.as<double>(), w, hphi.as<double>(), w, 1.0);
-        if (st) return st;
-        DACP_HIP(ctx, dacp::launch_resid(phi.as<double>(), hphi.as<double>(), w, dth.as<double>(), D, w, ctx->red,
-                                         dacp::coldots_blocks(D, 2 * w), ctx->red_out, s));
-        DACP_TRY(to_host(ctx, out.data(), ctx->red_out, sizeof(double) * 2 * w));
-        DACP_HIP(ctx, hipStreamSynchronize(s));
-        for (int i = 0; i < w; ++i) rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
-      }
-    }
-    // Acceptance.  The Ritz residual r_j is orthogonal to the whole search space, which holds the
-    // converged neighbours of theta_j, so the quadratic residual bound |theta_j - lambda_j| <=
-    // ||r_j||^2 / eta_j uses eta_j = distance from theta_j to the part of the spectrum the subspace does
-    // not resolve: the nearest unaccepted Ritz value, or the window edge (levels beyond a are not
-    // represented).  Start from the candidates whose residual is below a generous cap, iterate to a
-    // fixed point, then keep the contiguous accepted core around 0 (walk outward in |theta|, stop at
-    // the first rejection).  The estimate reported is min(||r||, ||r||^2 / eta).
-    //
-    // A Ritz value whose residual exceeds ten mean level spacings of the window approximates no
-    // eigenvalue near it (a "ghost" built from weakly represented directions of the overcomplete
-    // basis): it is left out of eta and does not stop the core.  Central levels carry the largest
-    // filter amplitude, so a true level there is never that poorly represented.
-    std::vector<char> ok(r, 0), ghost(r, 0);
-    const double cap = 1e-4 * norm_est;
-    const double ghost_thr = 10.0 * (2.0 * a / n_w);
-    for (int i = 0; i < n_sel; ++i) {
-      ok[order[i]] = rnorm[i] <= cap;
-      ghost[order[i]] = rnorm[i] > ghost_thr;
-    }
-    int n_ghost = 0;
-    for (int i = 0; i < n_sel; ++i) n_ghost += ghost[order[i]];
-    std::vector<double> est(n_sel, INFINITY);
-    for (int iter = 0; iter < 8; ++iter) {
-      std::vector<double> unc;  // sorted Ritz values not (or no longer) accepted, ghosts excluded
-      for (int i = 0; i < r; ++i)
-        if (!ok[i] && !ghost[i]) unc.push_back(theta[i]);
-      bool changed = false;
-      for (int q = 0; q < n_sel; ++q) {
-        const int j = order[q];
-        if (!ok[j]) continue;
-        double eta = a - std::fabs(theta[j]);
-        auto it = std::lower_bound(unc.begin(), unc.end(), theta[j]);
-        if (it != unc.end()) eta = std::min(eta, *it - theta[j]);
-        if (it != unc.begin()) eta = std::min(eta, theta[j] - *(it - 1));
-        est[q] = (eta > 0.0) ? std::min(rnorm[q], rnorm[q] * rnorm[q] / eta) : rnorm[q];
-        if (!(est[q] <= tol)) {
-          ok[j] = 0;
-          changed = true;
-        }
-      }
-      if (!changed) break;
-    }
-    // walk outward in |theta|: ghosts are skipped, the first other rejection ends the core
-    std::vector<int> core_idx;  // positions q (into order) of the accepted core
-    double max_est = 0.0;
-    for (int q = 0; q < n_sel && std::fabs(theta[order[q]]) <= a; ++q) {
-      const int j = order[q];
-      if (ghost[j]) continue;
-      if (!ok[j]) break;
-      max_est = std::max(max_est, est[q]);
-      core_idx.push_back(q);
-    }
-    const int core = static_cast<int>(core_idx.size());
-    if (verbose()) {
-      int shown = 0;
-      for (int q = 0; q < n_sel && shown < 6; ++q) {
-        if (ok[order[q]] || ghost[order[q]]) continue;
-        const int j = order[q];
-        const double gl = j > 0 ? theta[j] - theta[j - 1] : INFINITY;
-        const double gr = j + 1 < r ? theta[j + 1] - theta[j] : INFINITY;
-        vlog("rejected #%d (|theta| rank %d): theta=%.10g r=%.3g est=%.3g gaps=(%.3g, %.3g) tol=%.3g", shown, q,
-             theta[j], rnorm[q], est[q], gl, gr, tol);
-        ++shown;
-      }
-      int n_ok = 0;
-      for (int q = 0; q < n_sel; ++q) n_ok += ok[order[q]] ? 1 : 0;
-      vlog("accepted (any position) %d of %d candidates; ghosts %d; contiguous core %d", n_ok, n_sel, n_ghost, core);
-    }
-    accepted = core;
-    rep.n_candidates = n_sel;
-    rep.n_accepted = core;
-    rep.max_err_est = max_est;
-    rep.n_ghost = n_ghost;
-    rep.t_accept_ms = now_ms() - t0;
-    vlog("acceptance done: %.1f ms, %d accepted of %d candidates", rep.t_accept_ms, core, n_sel);
-    if (core >= N) {
-      std::vector<std::pair<double, double>> sel;
-      for (int i = 0; i < N; ++i) sel.push_back({theta[order[core_idx[i]]], est[core_idx[i]]});
-      std::sort(sel.begin(), sel.end());
-      for (int i = 0; i < N; ++i) {
-        eigs_out[i] = sel[i].first;
-        if (err_out) err_out[i] = sel[i].second;
-      }
+    if (accepted >= N) {
       if (n_out) *n_out = N;
       rep.t_total_ms = now_ms() - t_start;
       if (report) *report = rep;
@@ -1468,6 +1509,208 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
   if (report) *report = rep;
   return set_err(ctx, DACP_E_WINDOW,
                  "only " + std::to_string(accepted) + " eigenvalues accepted near 0; widen the window");
+}
+
+
+dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
+                                      double *eigs_out, double *err_out, int *n_out, dacp_report *reports) {
+  if (!ctx || count < 1 || !hams || !eigs_out || !n_out)
+    return set_err(ctx, DACP_E_INVALID, "batched: need ctx, count >= 1, hams, eigs_out, n_out");
+  int max_L = 0;
+  for (int r = 0; r < count; ++r) {
+    if (!hams[r]) return set_err(ctx, DACP_E_INVALID, "batched: null Hamiltonian " + std::to_string(r));
+    if (hams[r]->L > 14)
+      return set_err(ctx, DACP_E_INVALID, "batched: realisation " + std::to_string(r) + " has L > 14 (one column of "
+                                          "2^L FP64 values must fit the 160 KB LDS of a compute unit)");
+    if (N < 1 || N > hams[r]->D) return set_err(ctx, DACP_E_INVALID, "batched: need 1 <= N <= 2^L for every realisation");
+    max_L = std::max(max_L, hams[r]->L);
+  }
+  dacp_opts o;
+  if (opts_in) o = *opts_in;
+  else dacp_default_opts(&o);
+  const double t_start = now_ms();
+  const double window_ratio = o.window_ratio > 0.0 ? o.window_ratio : 2.2;
+  std::vector<dacp_report> rep(count);
+  std::vector<double> norm_est(count), tol(count), e_bs(count);
+  std::vector<Plan> plans(count);
+  // bounds, densities and plans, one realisation after the other (small launches)
+  for (int r = 0; r < count; ++r) {
+    dacp_ham h = hams[r];
+    std::memset(&rep[r], 0, sizeof(dacp_report));
+    const double t0 = now_ms();
+    double e_b = o.e_bound, th_lo = 0.0, th_hi = 0.0;
+    if (!(e_b > 0.0)) {
+      DACP_TRY(run_bound(ctx, h, o.lanczos_steps > 0 ? o.lanczos_steps : 80, nullptr, o.seed ^ 0x5bd1e995ULL, 1.01,
+                         &e_b, &th_lo, &th_hi));
+    } else {
+      th_lo = -e_b;
+      th_hi = e_b;
+    }
+    norm_est[r] = std::max(std::fabs(th_lo), std::fabs(th_hi));
+    tol[r] = o.tol_rel * norm_est[r];
+    e_bs[r] = e_b;
+    std::vector<double> mu;
+    if (!(o.a > 0.0)) {
+      const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
+      mu.assign(M, 0.0);
+      DACP_TRY(run_moments(ctx, h, e_b, M, o.kpm_vectors > 0 ? o.kpm_vectors : 8, nullptr, o.seed ^ 0x2545f491ULL,
+                           mu.data()));
+    }
+    plans[r] = make_plan(o, h->D, N, e_b, mu, window_ratio, 0);
+    const Plan &pl = plans[r];
+    rep[r].e_bound = e_b;
+    rep[r].a = pl.a;
+    rep[r].a_r = pl.a_r;
+    rep[r].K = pl.K;
+    rep[r].b = pl.b;
+    rep[r].n = pl.n;
+    rep[r].m = pl.m;
+    rep[r].evol_group = 1;
+    rep[r].t_bound_ms = now_ms() - t0;
+  }
+
+  // start blocks, bases and the column table of the persistent launch
+  std::vector<DevBuf> psi(count), vb(count), ksd(count), scr(count);
+  DevBuf flags;
+  DACP_HIP(ctx, flags.alloc(sizeof(int) * count));
+  DACP_HIP(ctx, hipMemsetAsync(flags.p, 0, sizeof(int) * count, ctx->stream));
+  std::vector<BatchCol> cols;
+  for (int r = 0; r < count; ++r) {
+    dacp_ham h = hams[r];
+    const Plan &pl = plans[r];
+    const int64_t D = h->D;
+    DACP_HIP(ctx, psi[r].alloc(static_cast<size_t>(D) * pl.b * sizeof(double)));
+    DACP_HIP(ctx, dacp::launch_philox_gauss(psi[r].as<double>(), D, pl.b, o.seed + static_cast<uint64_t>(r) * 0x9E3779B97F4A7C15ULL,
+                                            ctx->stream));
+    DACP_HIP(ctx, vb[r].alloc(static_cast<size_t>(D) * pl.m * sizeof(double)));
+    if (static_cast<double>(D) * pl.m * 8.0 >= 4294967296.0)
+      return set_err(ctx, DACP_E_INVALID, "batched: basis of realisation " + std::to_string(r) + " exceeds 4 GiB");
+    if (h->L == 14) DACP_HIP(ctx, scr[r].alloc(static_cast<size_t>(2 * D) * pl.b * sizeof(double)));
+    DACP_TRY(split_order(ctx, h, h->L));  // every flip in one list, sign-free flips first
+    const auto &so = h->split[h->L];
+    const std::vector<int64_t> ks64 = sample_orders(pl.a_r, pl.n);
+    std::vector<int> ks(ks64.begin(), ks64.end());
+    DACP_HIP(ctx, ksd[r].alloc(sizeof(int) * ks.size()));
+    DACP_TRY(to_device(ctx, ksd[r].p, ks.data(), sizeof(int) * ks.size()));
+    const double e_b = e_bs[r], a = pl.a;
+    const double e_c = 0.5 * (e_b * e_b + a * a), e_0 = 0.5 * (e_b * e_b - a * a);
+    const double rho = std::exp(std::acosh(1.0 + 2.0 * a * a / (e_b * e_b - a * a)));
+    const int tail = (o.precision == DACP_F32) ? std::max(0, std::min(pl.K, static_cast<int>(std::ceil(o.fp64_tail_frac * pl.K)))) : pl.K;
+    for (int j = 0; j < pl.b; ++j) {
+      BatchCol c;
+      std::memset(&c, 0, sizeof(c));
+      c.flips = so.lo;
+      c.nflip = so.nlo;
+      c.nplain = so.nlo_plain;
+      c.scratch = h->L == 14 ? scr[r].as<double>() + static_cast<int64_t>(2 * D) * j : nullptr;
+      if (h->L == 14 && !c.scratch) return set_err(ctx, DACP_E_INVALID, "batched: missing column scratch");
+      c.d64 = h->d64;
+      c.d32 = h->d32;
+      c.psi0 = psi[r].as<double>() + j;
+      c.ld_psi = pl.b;
+      c.V = vb[r].as<double>() + j;
+      c.ldv = pl.m;
+      c.ks = ksd[r].as<int>();
+      c.n_samples = pl.n;
+      c.bound_flag = flags.as<int>() + r;
+      c.f_alpha = 2.0 / (e_0 * rho);
+      c.f_beta = -2.0 * e_c / (e_0 * rho);
+      c.f_gamma = -1.0 / (rho * rho);
+      c.f_first_a = 1.0 / (e_0 * rho);
+      c.f_first_b = -e_c / (e_0 * rho);
+      c.inv_e = 1.0 / e_b;
+      c.L = h->L;
+      c.K = pl.K;
+      c.n32 = pl.K - tail;
+      c.b = pl.b;
+      cols.push_back(c);
+    }
+  }
+  // longest columns first, so the short ones fill in behind them
+  std::stable_sort(cols.begin(), cols.end(), [](const BatchCol &x, const BatchCol &y) {
+    return static_cast<double>(x.K + x.n_samples) * (1 << x.L) > static_cast<double>(y.K + y.n_samples) * (1 << y.L);
+  });
+  DevBuf dcols;
+  DACP_HIP(ctx, dcols.alloc(sizeof(BatchCol) * cols.size()));
+  DACP_TRY(to_device(ctx, dcols.p, cols.data(), sizeof(BatchCol) * cols.size()));
+  const double tb0 = now_ms();
+  DACP_HIP(ctx, dacp::launch_batch_chebyshev(dcols.as<BatchCol>(), static_cast<int>(cols.size()), max_L, ctx->stream));
+  std::vector<int> flag(count);
+  DACP_TRY(to_host(ctx, flag.data(), flags.p, sizeof(int) * count));
+  const double t_batch = now_ms() - tb0;
+  vlog("batched filter + evolution: %d columns of %d realisations in %.1f ms", static_cast<int>(cols.size()), count,
+       t_batch);
+  for (int r = 0; r < count; ++r) {
+    psi[r].release();
+    scr[r].release();
+    rep[r].t_evol_ms = t_batch;
+    if (flag[r])
+      return set_err(ctx, DACP_E_BOUNDS, "batched: realisation " + std::to_string(r) +
+                                             ": |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
+  }
+
+  // projection, subspace solve and acceptance: realisations spread over worker contexts, each
+  // with its own stream, so the small GEMMs and eigen-solves of different realisations overlap
+  const int nw = std::max(1, std::min(count, ctx->batch_workers));
+  std::vector<dacp_ctx_s> wctx(nw);
+  std::vector<dacp_status> wst(count, DACP_OK);
+  std::vector<std::string> werr(count);
+  std::vector<int> acc(count, 0);
+  for (int w = 0; w < nw; ++w) {
+    dacp_ctx_s &c = wctx[w];
+    c.device = ctx->device;
+    c.tile_elems = ctx->tile_elems;
+    c.two_pass_min_L = ctx->two_pass_min_L;
+    c.dc_min_n = ctx->dc_min_n;
+    DACP_HIP(ctx, hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+  }
+  auto worker = [&](int w) {
+    (void)hipSetDevice(ctx->device);
+    for (int r = w; r < count; r += nw) {
+      const Plan &pl = plans[r];
+      wst[r] = finish_basis(&wctx[w], hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
+                            eigs_out + static_cast<int64_t>(r) * N,
+                            err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
+      if (wst[r]) werr[r] = wctx[w].err;
+      vb[r].release();
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);
+  worker(0);
+  for (auto &t : threads) t.join();
+  for (int w = 0; w < nw; ++w) {
+    if (wctx[w].red) (void)hipFree(wctx[w].red);
+    if (wctx[w].red_out) (void)hipFree(wctx[w].red_out);
+    (void)hipStreamDestroy(wctx[w].stream);
+  }
+  for (int r = 0; r < count; ++r)
+    if (wst[r]) return set_err(ctx, wst[r], "batched: realisation " + std::to_string(r) + ": " + werr[r]);
+
+  // realisations whose core fell short: the single-realisation path with a wider window
+  dacp_status worst = DACP_OK;
+  for (int r = 0; r < count; ++r) {
+    n_out[r] = acc[r] >= N ? N : acc[r];
+    if (acc[r] >= N) continue;
+    dacp_opts o2 = o;
+    o2.window_ratio = window_ratio * 1.5;
+    dacp_report r2;
+    int got = 0;
+    const dacp_status st = dacp_central_eigs(ctx, hams[r], N, &o2, eigs_out + static_cast<int64_t>(r) * N,
+                                             err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, &got, &r2);
+    r2.retries += 1;
+    r2.t_bound_ms += rep[r].t_bound_ms;
+    rep[r] = r2;
+    n_out[r] = got;
+    if (st != DACP_OK && worst == DACP_OK) worst = st;
+  }
+  const double total = now_ms() - t_start;
+  for (int r = 0; r < count; ++r) {
+    rep[r].t_total_ms = total;
+    if (reports) reports[r] = rep[r];
+  }
+  if (worst != DACP_OK) return set_err(ctx, worst, "batched: some realisations fell short of N accepted eigenvalues");
+  return DACP_OK;
 }
 
 }  // extern "C"

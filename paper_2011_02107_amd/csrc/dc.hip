@@ -288,7 +288,6 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
   std::vector<Ent> ents;
   for (int j = 0; j < n; ++j)
     if (defl[j]) ents.push_back({ds[j], 0, rowid[j]});
-  dacp_status s2 = DACP_OK;
   if (k > 0) {
     std::vector<double> dk(k), zk(k);
     std::vector<int> rk(k);

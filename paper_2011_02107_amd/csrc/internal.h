@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -105,6 +106,25 @@ struct RecArgs {
   int xcd_remap;
 };
 
+// One column of one realisation for the batched persistent kernel (batch.hip).  Read by the
+// kernel through the scalar cache: the table is not written while the kernel runs.
+struct BatchCol {
+  const FlipEntry *flips;  // the realisation's flip table, sign-free flips first (all applied from LDS)
+  const double *d64;       // diagonal tables
+  const float *d32;
+  const double *psi0;      // start column: psi0[s * ld_psi]
+  double *V;               // the realisation's basis shifted to this column: panel p at V[s * ldv + p * b]
+  const int *ks;           // sample orders k_1 < ... < k_n (device)
+  int *bound_flag;         // set to 1 when |T_k(G) psi_E| > 1 is seen (bound below ||H||)
+  double *scratch;         // 2 x 2^L doubles owned by this column (older recurrence terms at L = 14)
+  int64_t ld_psi, ldv;
+  double f_alpha, f_beta, f_gamma;  // damped filter step coefficients
+  double f_first_a, f_first_b;      // first order: T^_1 = a H (H psi) + b psi
+  double inv_e;                     // 1 / E_b
+  int L, nflip, nplain, K, n32, n_samples, b;  // flips[0, nplain) have z-mask 0
+};
+hipError_t launch_batch_chebyshev(const BatchCol *cols, int ncols, int max_L, hipStream_t s);
+
 // Launch helpers (kernels.hip).
 template <typename T>
 hipError_t launch_rec_lo(const RecArgs<T> &a, hipStream_t s);
@@ -193,6 +213,7 @@ struct dacp_ctx_s {
   int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
   int num_cus = 256;           // compute units of the device
+  int batch_workers = 8;       // host threads (each with its own stream) finishing batched realisations
   int filter_group_f64 = 8;    // filter column-group width for L >= 15, FP64 recurrence
   int filter_group_f32 = 16;   // filter column-group width for L >= 15, FP32 recurrence
   int dc_min_n = 96;           // eigenvectors by divide and conquer from this size on (0 = never)
@@ -207,6 +228,7 @@ struct dacp_ham_s {
   float *d32 = nullptr;   // same in FP32
   dacp::FlipEntry *flips = nullptr;
   std::vector<dacp::FlipEntry> flips_host;  // sorted by x-mask
+  std::mutex tables_mu;                      // guards the lazily built flip orders below
   struct TileOrder {
     dacp::FlipEntry *dev = nullptr;
     int nlow = 0, nhigh = 0;

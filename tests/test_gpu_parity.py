@@ -483,3 +483,49 @@ def test_central_eigs_jw_twin_L14(ctx):
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=16))
     _check_central(eigs, ref, norm, N)
+
+
+# ------------------------------------------------------------------ batched realisations
+
+
+def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
+    """Realisations of different L in one persistent launch, each against its dense oracle."""
+    N = 40
+    specs = [(8, 1), (10, 2), (9, 3), (10, 4), (8, 5)]
+    hams, refs = [], []
+    for L, seed in specs:
+        terms = inputs.spin_glass(L, seed)
+        refs.append(central.central_eigenvalues(L, terms, N))
+        hams.append(B.dacp_build_hamiltonian(ctx, L, terms))
+    for precision in (B.DACP_F64, B.DACP_F32):
+        opts = B.default_opts(b=8, precision=precision, fp64_tail_frac=0.3)
+        eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+        assert st == 0 and np.all(n_out == N)
+        for r, (ref, norm) in enumerate(refs):
+            _check_central(eigs[r], ref, norm, N)
+            assert np.all(errs[r] <= 1e-10 * norm)
+
+
+def test_central_eigs_batched_L14_and_L12(ctx):
+    """L = 14 keeps the older recurrence term in global scratch; checked against the Jordan-Wigner
+    closed form, next to an L = 12 spin glass against the dense oracle."""
+    N = 120
+    L1 = 14
+    ham1 = B.dacp_build_hamiltonian(ctx, L1, inputs.ising_chain(L1, hz=0.0))
+    ref1, norm1 = central.central_eigenvalues_jw(np.ones(L1 - 1), 1.05 * np.ones(L1), N)
+    L2 = 12
+    terms2 = inputs.spin_glass(L2, 7)
+    ref2, norm2 = central.central_eigenvalues(L2, terms2, N)
+    ham2 = B.dacp_build_hamiltonian(ctx, L2, terms2)
+    eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, [ham1, ham2, ham1], N, B.default_opts(b=8))
+    assert st == 0 and np.all(n_out == N)
+    _check_central(eigs[0], ref1, norm1, N)
+    _check_central(eigs[2], ref1, norm1, N)
+    _check_central(eigs[1], ref2, norm2, N)
+
+
+def test_central_eigs_batched_rejects_large_L(ctx):
+    ham = B.dacp_build_hamiltonian(ctx, 15, inputs.ising_chain(15))
+    with pytest.raises(B.DacpError) as ei:
+        B.dacp_central_eigs_batched(ctx, [ham], 10, B.default_opts(b=4))
+    assert ei.value.status == -1
