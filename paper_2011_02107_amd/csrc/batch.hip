@@ -318,6 +318,150 @@ __global__ __launch_bounds__(kBT) void k_batch_chebyshev(const BatchCol *cols_g)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched spectral estimates (the bound and density step of Sec. III for many realisations):
+// workgroup g runs either the Lanczos recurrence of one realisation (kind 0) or the Chebyshev
+// moment recurrence of one random vector of one realisation (kind 1) with the whole column on
+// chip, and writes the scalars the host needs:
+//   kind 0: out[j] = alpha_j, out[steps + j] = beta_j, out[2 steps] = number of steps taken;
+//   kind 1: out[0] = <r, r>, out[1] = <r, T_1 r>, out[2k] = <T_k r, T_k r>,
+//           out[2k + 1] = <T_(k+1) r, T_k r>  (k >= 1, indices below `steps` = M).
+// ---------------------------------------------------------------------------
+template <int E>
+__device__ __forceinline__ double dot_held(const double (&v)[E], const Held<E> &A, uint32_t D, double *red) {
+  double p = 0.0;
+  if (E > 1 || threadIdx.x < D) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) p += v[i] * A.get(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8));
+  }
+  return block_sum(p, red);
+}
+
+template <int E>
+__device__ __forceinline__ void run_spectral(const BatchSpec &c, ConstFlipTable flips, unsigned char *smem,
+                                             double *red) {
+  const uint32_t D = 1u << c.L;
+  double *lds = reinterpret_cast<double *>(smem);
+  const bool active = E > 1 || threadIdx.x < D;
+  Held<E> A;
+  A.g = c.scratch;
+  double v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t s = threadIdx.x + i * kBT;
+    v[i] = active ? ld_at(c.start, s * static_cast<uint32_t>(c.ld) * 8u) : 0.0;
+  }
+  if (c.kind == 0) {
+    // Lanczos: A = v_(j-1), v = v_j, w (in v after the apply) = H v_j - beta_(j-1) v_(j-1)
+    {
+      const double inv = 1.0 / sqrt(sum_sq<E>(v, D, red));
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] *= inv;
+    }
+    double bprev = 0.0;
+    int taken = 0;
+    for (int j = 0; j < c.steps; ++j) {
+      double w[E];
+#pragma unroll
+      for (int i = 0; i < E; ++i) w[i] = v[i];
+      apply_inplace<double, E>(w, lds, c.d64, flips, c.nplain, c.nflip, D);  // lds keeps v_j
+      if (j > 0 && active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) w[i] -= bprev * A.get(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8));
+      }
+      double pa = 0.0;
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) pa += w[i] * v[i];
+      }
+      const double alpha = block_sum(pa, red);
+#pragma unroll
+      for (int i = 0; i < E; ++i) w[i] -= alpha * v[i];
+      const double beta = sqrt(fmax(sum_sq<E>(w, D, red), 0.0));
+      if (threadIdx.x == 0) {
+        c.out[j] = alpha;
+        c.out[c.steps + j] = beta;
+      }
+      taken = j + 1;
+      if (!(beta > 1e-300) || j + 1 == c.steps) break;
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          A.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), v[i]);
+          v[i] = w[i] / beta;
+        }
+      }
+      bprev = beta;
+    }
+    if (threadIdx.x == 0) c.out[2 * c.steps] = static_cast<double>(taken);
+    return;
+  }
+  // Chebyshev moments of one random vector: A = T_(k-1) r, v = T_k r
+  {
+    const double n0 = sum_sq<E>(v, D, red);
+    if (threadIdx.x == 0) c.out[0] = n0;
+  }
+  if (c.steps <= 1) return;
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) A.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), v[i]);
+  }
+  apply_inplace<double, E>(v, lds, c.d64, flips, c.nplain, c.nflip, D);
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] *= c.inv_e;
+  {
+    const double m1 = dot_held<E>(v, A, D, red);
+    if (threadIdx.x == 0) c.out[1] = m1;
+  }
+  const double two_inv_e = 2.0 * c.inv_e;
+  for (int k = 1; 2 * k < c.steps; ++k) {
+    const double tkk = sum_sq<E>(v, D, red);
+    if (threadIdx.x == 0) c.out[2 * k] = tkk;
+    if (2 * k + 1 >= c.steps) break;
+    apply_inplace<double, E>(v, lds, c.d64, flips, c.nplain, c.nflip, D);  // lds keeps T_k r
+    if (active) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
+        const double nb = two_inv_e * v[i] - A.get(i, bo);
+        A.set(i, bo, ld_at(lds, bo));
+        v[i] = nb;
+      }
+    }
+    const double tk1k = dot_held<E>(v, A, D, red);
+    if (threadIdx.x == 0) c.out[2 * k + 1] = tk1k;
+  }
+}
+
+typedef const __attribute__((address_space(4))) BatchSpec *ConstBatchSpecs;
+
+__global__ __launch_bounds__(kBT) void k_batch_spectral(const BatchSpec *specs_g) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[kBT / 64];
+  const ConstBatchSpecs cs = (ConstBatchSpecs)specs_g + blockIdx.x;
+  BatchSpec c;
+  c.flips = cs->flips;
+  c.d64 = cs->d64;
+  c.start = cs->start;
+  c.scratch = cs->scratch;
+  c.out = cs->out;
+  c.ld = cs->ld;
+  c.inv_e = cs->inv_e;
+  c.L = cs->L;
+  c.nflip = cs->nflip;
+  c.nplain = cs->nplain;
+  c.kind = cs->kind;
+  c.steps = cs->steps;
+  const ConstFlipTable flips = (ConstFlipTable)c.flips;
+  switch (c.L) {
+    case 14: run_spectral<16>(c, flips, smem_raw, red); break;
+    case 13: run_spectral<8>(c, flips, smem_raw, red); break;
+    case 12: run_spectral<4>(c, flips, smem_raw, red); break;
+    case 11: run_spectral<2>(c, flips, smem_raw, red); break;
+    default: run_spectral<1>(c, flips, smem_raw, red); break;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_batch_chebyshev(const BatchCol *cols, int ncols, int max_L, hipStream_t s) {
@@ -328,6 +472,17 @@ hipError_t launch_batch_chebyshev(const BatchCol *cols, int ncols, int max_L, hi
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_batch_chebyshev, dim3(ncols), dim3(kBT), lds, s, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_spectral(const BatchSpec *specs, int n, int max_L, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (max_L < 1 || max_L > 14) return hipErrorInvalidValue;
+  const size_t lds = (size_t(1) << max_L) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_spectral),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_spectral, dim3(n), dim3(kBT), lds, s, specs);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ using dacp::StepArgs;
 using dacp::to_device;
 using dacp::to_host;
 using dacp::BatchCol;
+using dacp::BatchSpec;
 
 namespace dacp {
 
@@ -758,6 +759,26 @@ dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_
 }
 
 // ---------------------------------------------------------- Lanczos bound
+// E_b from the Lanczos tridiagonal (alpha, beta): the extreme Ritz values widened by their Ritz
+// residuals |beta_k y_k|, times `safety`, clamped to sum |c| (reading of the Sec. III estimator).
+dacp_status lanczos_bound(dacp_ctx ctx, const std::vector<double> &al, const std::vector<double> &be, double safety,
+                          double sum_abs, double *e_bound, double *tmin, double *tmax) {
+  const int k = static_cast<int>(al.size());
+  if (k < 1 || be.size() != al.size()) return set_err(ctx, DACP_E_NUMERIC, "bound: empty Lanczos run");
+  std::vector<double> th(k), Z(static_cast<size_t>(k) * k);
+  if (!dacp::host_tridiag_eig(al.data(), be.data(), k, th.data(), Z.data()))
+    return set_err(ctx, DACP_E_CONVERGENCE, "bound: tridiagonal eigensolver");
+  const double bk = be.back();
+  const double r_lo = std::fabs(bk * Z[static_cast<size_t>(k - 1) * k + 0]);
+  const double r_hi = std::fabs(bk * Z[static_cast<size_t>(k - 1) * k + (k - 1)]);
+  double eb = safety * std::max(std::fabs(th[k - 1]) + r_hi, std::fabs(th[0]) + r_lo);
+  eb = std::min(eb, sum_abs);
+  if (e_bound) *e_bound = eb;
+  if (tmin) *tmin = th[0];
+  if (tmax) *tmax = th[k - 1];
+  return DACP_OK;
+}
+
 dacp_status run_bound(dacp_ctx ctx, dacp_ham h, int steps, const double *v0, uint64_t seed, double safety,
                       double *e_bound, double *tmin, double *tmax) {
   const int64_t D = h->D;
@@ -799,19 +820,7 @@ dacp_status run_bound(dacp_ctx ctx, dacp_ham h, int steps, const double *v0, uin
     w = t;
     bprev = beta;
   }
-  const int k = static_cast<int>(al.size());
-  std::vector<double> th(k), Z(static_cast<size_t>(k) * k);
-  if (!dacp::host_tridiag_eig(al.data(), be.data(), k, th.data(), Z.data()))
-    return set_err(ctx, DACP_E_CONVERGENCE, "bound: tridiagonal eigensolver");
-  const double bk = be.back();
-  const double r_lo = std::fabs(bk * Z[static_cast<size_t>(k - 1) * k + 0]);
-  const double r_hi = std::fabs(bk * Z[static_cast<size_t>(k - 1) * k + (k - 1)]);
-  double eb = safety * std::max(std::fabs(th[k - 1]) + r_hi, std::fabs(th[0]) + r_lo);
-  eb = std::min(eb, h->sum_abs);
-  if (e_bound) *e_bound = eb;
-  if (tmin) *tmin = th[0];
-  if (tmax) *tmax = th[k - 1];
-  return DACP_OK;
+  return lanczos_bound(ctx, al, be, safety, h->sum_abs, e_bound, tmin, tmax);
 }
 
 // ----------------------------------------------------------- KPM moments
@@ -1533,40 +1542,135 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   std::vector<dacp_report> rep(count);
   std::vector<double> norm_est(count), tol(count), e_bs(count);
   std::vector<Plan> plans(count);
-  // bounds, densities and plans, one realisation after the other (small launches)
-  for (int r = 0; r < count; ++r) {
-    dacp_ham h = hams[r];
-    std::memset(&rep[r], 0, sizeof(dacp_report));
-    const double t0 = now_ms();
-    double e_b = o.e_bound, th_lo = 0.0, th_hi = 0.0;
-    if (!(e_b > 0.0)) {
-      DACP_TRY(run_bound(ctx, h, o.lanczos_steps > 0 ? o.lanczos_steps : 80, nullptr, o.seed ^ 0x5bd1e995ULL, 1.01,
-                         &e_b, &th_lo, &th_hi));
+  // bounds and densities of every realisation: one launch of Lanczos runs, then one launch of
+  // Chebyshev-moment vectors (Sec. III estimators), same start vectors as the single path
+  std::vector<std::vector<double>> mus(count);
+  {
+    const double tb = now_ms();
+    const int steps0 = o.lanczos_steps > 0 ? o.lanczos_steps : 80;
+    const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
+    const int nvec = o.kpm_vectors > 0 ? o.kpm_vectors : 8;
+    std::vector<DevBuf> v0(count), out(count), scr(count), R(count), mout(count), mscr(count);
+    std::vector<BatchSpec> specs;
+    std::vector<int> steps(count);
+    auto base_spec = [&](dacp_ham h, const dacp::SplitOrder_t &so) {
+      BatchSpec c;
+      std::memset(&c, 0, sizeof(c));
+      c.flips = so.lo;
+      c.nflip = so.nlo;
+      c.nplain = so.nlo_plain;
+      c.d64 = h->d64;
+      c.L = h->L;
+      return c;
+    };
+    if (!(o.e_bound > 0.0)) {
+      for (int r = 0; r < count; ++r) {
+        dacp_ham h = hams[r];
+        const int64_t D = h->D;
+        steps[r] = static_cast<int>(std::min<int64_t>(steps0, D));
+        DACP_TRY(split_order(ctx, h, h->L));
+        DACP_HIP(ctx, v0[r].alloc(D * sizeof(double)));
+        DACP_HIP(ctx, dacp::launch_philox_gauss(v0[r].as<double>(), D, 1, o.seed ^ 0x5bd1e995ULL, ctx->stream));
+        DACP_HIP(ctx, out[r].alloc((2 * steps[r] + 1) * sizeof(double)));
+        if (h->L == 14) DACP_HIP(ctx, scr[r].alloc(D * sizeof(double)));
+        BatchSpec c = base_spec(h, h->split[h->L]);
+        c.start = v0[r].as<double>();
+        c.ld = 1;
+        c.scratch = scr[r].as<double>();
+        c.out = out[r].as<double>();
+        c.kind = 0;
+        c.steps = steps[r];
+        specs.push_back(c);
+      }
+      DevBuf dspecs;
+      DACP_HIP(ctx, dspecs.alloc(sizeof(BatchSpec) * specs.size()));
+      DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
+      DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
+                                                ctx->stream));
+      for (int r = 0; r < count; ++r) {
+        std::vector<double> o2(2 * steps[r] + 1);
+        DACP_TRY(to_host(ctx, o2.data(), out[r].p, o2.size() * sizeof(double)));
+        const int k = static_cast<int>(o2[2 * steps[r]]);
+        if (k < 1 || k > steps[r]) return set_err(ctx, DACP_E_NUMERIC, "batched: Lanczos run " + std::to_string(r));
+        std::vector<double> al(o2.begin(), o2.begin() + k), be(o2.begin() + steps[r], o2.begin() + steps[r] + k);
+        for (int j = 0; j < k; ++j)
+          if (!std::isfinite(al[j]) || !std::isfinite(be[j]))
+            return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite Lanczos run " + std::to_string(r));
+        double th_lo = 0.0, th_hi = 0.0;
+        DACP_TRY(lanczos_bound(ctx, al, be, 1.01, hams[r]->sum_abs, &e_bs[r], &th_lo, &th_hi));
+        norm_est[r] = std::max(std::fabs(th_lo), std::fabs(th_hi));
+      }
+      specs.clear();
     } else {
-      th_lo = -e_b;
-      th_hi = e_b;
+      for (int r = 0; r < count; ++r) {
+        e_bs[r] = o.e_bound;
+        norm_est[r] = o.e_bound;
+      }
     }
-    norm_est[r] = std::max(std::fabs(th_lo), std::fabs(th_hi));
-    tol[r] = o.tol_rel * norm_est[r];
-    e_bs[r] = e_b;
-    std::vector<double> mu;
     if (!(o.a > 0.0)) {
-      const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
-      mu.assign(M, 0.0);
-      DACP_TRY(run_moments(ctx, h, e_b, M, o.kpm_vectors > 0 ? o.kpm_vectors : 8, nullptr, o.seed ^ 0x2545f491ULL,
-                           mu.data()));
+      for (int r = 0; r < count; ++r) {
+        dacp_ham h = hams[r];
+        const int64_t D = h->D;
+        DACP_TRY(split_order(ctx, h, h->L));
+        DACP_HIP(ctx, R[r].alloc(static_cast<size_t>(D) * nvec * sizeof(double)));
+        DACP_HIP(ctx, dacp::launch_philox_gauss(R[r].as<double>(), D, nvec, o.seed ^ 0x2545f491ULL, ctx->stream));
+        DACP_HIP(ctx, mout[r].alloc(static_cast<size_t>(M) * nvec * sizeof(double)));
+        if (h->L == 14) DACP_HIP(ctx, mscr[r].alloc(static_cast<size_t>(D) * nvec * sizeof(double)));
+        for (int q = 0; q < nvec; ++q) {
+          BatchSpec c = base_spec(h, h->split[h->L]);
+          c.start = R[r].as<double>() + q;
+          c.ld = nvec;
+          c.scratch = h->L == 14 ? mscr[r].as<double>() + static_cast<int64_t>(D) * q : nullptr;
+          c.out = mout[r].as<double>() + static_cast<int64_t>(M) * q;
+          c.inv_e = 1.0 / e_bs[r];
+          c.kind = 1;
+          c.steps = M;
+          specs.push_back(c);
+        }
+      }
+      DevBuf dspecs;
+      DACP_HIP(ctx, dspecs.alloc(sizeof(BatchSpec) * specs.size()));
+      DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
+      DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
+                                                ctx->stream));
+      for (int r = 0; r < count; ++r) {
+        std::vector<double> mo(static_cast<size_t>(M) * nvec);
+        DACP_TRY(to_host(ctx, mo.data(), mout[r].p, mo.size() * sizeof(double)));
+        auto tot = [&](int idx) {
+          double t = 0.0;
+          for (int q = 0; q < nvec; ++q) t += mo[static_cast<size_t>(q) * M + idx];
+          return t;
+        };
+        std::vector<double> &mu = mus[r];
+        mu.assign(M, 0.0);
+        const double n0 = tot(0);
+        mu[0] = 1.0;
+        if (M > 1) mu[1] = tot(1) / n0;
+        for (int k = 1; 2 * k < M; ++k) {
+          mu[2 * k] = 2.0 * tot(2 * k) / n0 - mu[0];
+          if (2 * k + 1 < M) mu[2 * k + 1] = 2.0 * tot(2 * k + 1) / n0 - mu[1];
+        }
+        for (double x : mu)
+          if (!std::isfinite(x)) return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite moments " + std::to_string(r));
+      }
     }
-    plans[r] = make_plan(o, h->D, N, e_b, mu, window_ratio, 0);
-    const Plan &pl = plans[r];
-    rep[r].e_bound = e_b;
-    rep[r].a = pl.a;
-    rep[r].a_r = pl.a_r;
-    rep[r].K = pl.K;
-    rep[r].b = pl.b;
-    rep[r].n = pl.n;
-    rep[r].m = pl.m;
-    rep[r].evol_group = 1;
-    rep[r].t_bound_ms = now_ms() - t0;
+    const double t_spec = now_ms() - tb;
+    vlog("batched bounds and densities of %d realisations: %.1f ms", count, t_spec);
+    for (int r = 0; r < count; ++r) {
+      std::memset(&rep[r], 0, sizeof(dacp_report));
+      tol[r] = o.tol_rel * norm_est[r];
+      plans[r] = make_plan(o, hams[r]->D, N, e_bs[r], mus[r], window_ratio, 0);
+      const Plan &pl = plans[r];
+      rep[r].e_bound = e_bs[r];
+      rep[r].a = pl.a;
+      rep[r].a_r = pl.a_r;
+      rep[r].K = pl.K;
+      rep[r].b = pl.b;
+      rep[r].n = pl.n;
+      rep[r].m = pl.m;
+      rep[r].evol_group = 1;
+      rep[r].t_bound_ms = t_spec;
+    }
   }
 
   // start blocks, bases and the column table of the persistent launch

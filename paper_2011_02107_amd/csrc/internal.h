@@ -125,6 +125,20 @@ struct BatchCol {
 };
 hipError_t launch_batch_chebyshev(const BatchCol *cols, int ncols, int max_L, hipStream_t s);
 
+// One Lanczos run (kind 0) or one Chebyshev-moment vector (kind 1) of one realisation for the
+// batched spectral kernel (batch.hip); output layout documented there.
+struct BatchSpec {
+  const FlipEntry *flips;  // sign-free flips first
+  const double *d64;
+  const double *start;     // start vector: start[s * ld]
+  double *scratch;         // 2^L doubles at L = 14, else unused
+  double *out;             // kind 0: 2 steps + 1 doubles; kind 1: steps doubles
+  int64_t ld;
+  double inv_e;            // kind 1: 1 / E_b
+  int L, nflip, nplain, kind, steps;
+};
+hipError_t launch_batch_spectral(const BatchSpec *specs, int n, int max_L, hipStream_t s);
+
 // Launch helpers (kernels.hip).
 template <typename T>
 hipError_t launch_rec_lo(const RecArgs<T> &a, hipStream_t s);
@@ -242,6 +256,9 @@ struct dacp_ham_s {
   };
   SplitOrder split[31];  // flip tables for the two-pass apply with lo_bits = index
 };
+namespace dacp {
+typedef dacp_ham_s::SplitOrder SplitOrder_t;
+}  // namespace dacp
 
 namespace dacp {
 // Error helpers used by the API layer.

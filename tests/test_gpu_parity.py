@@ -504,6 +504,9 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
         for r, (ref, norm) in enumerate(refs):
             _check_central(eigs[r], ref, norm, N)
             assert np.all(errs[r] <= 1e-10 * norm)
+            # the batched Lanczos bound equals the single-realisation one up to reduction order
+            eb, _, _ = B.dacp_spectral_bound(ctx, hams[r], steps=80, seed=0x5BD1E995)
+            assert abs(reps[r]["e_bound"] - eb) <= 1e-9 * eb
 
 
 def test_central_eigs_batched_L14_and_L12(ctx):
