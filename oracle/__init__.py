@@ -15,4 +15,5 @@ Modules:
   spectral       -- Lanczos bound, kernel-polynomial moments, window choice
   philox         -- Philox4x32-10 + Box-Muller start states
   central        -- the plain definition: dense full diagonalisation + selection
+  mlp            -- the learned window's regression network: forward, backward, Adam
 """

@@ -414,3 +414,60 @@ def test_central_eigenvalues_jw_twin_l12():
     ref, norm_jw = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
     assert abs(norm - norm_jw) < 1e-10
     assert np.abs(got - ref).max() <= 1e-10 * norm
+
+
+# ------------------------------------------------------------------ learned window network
+
+
+def test_mlp_gradient_matches_central_differences():
+    from oracle import mlp
+
+    n_in, hidden, layers, n_out = 3, 5, 2, 2
+    rng = np.random.default_rng(0)
+    theta = rng.standard_normal(mlp.n_params(n_in, hidden, layers, n_out)) * 0.7
+    X = rng.standard_normal((7, n_in))
+    T = rng.standard_normal((7, n_out))
+    loss, g = mlp.loss_and_grad(theta, X, T, n_in, hidden, layers, n_out)
+    h = 1e-6
+    num = np.zeros_like(theta)
+    for i in range(theta.size):
+        e = np.zeros_like(theta)
+        e[i] = h
+        num[i] = (mlp.loss_and_grad(theta + e, X, T, n_in, hidden, layers, n_out)[0]
+                  - mlp.loss_and_grad(theta - e, X, T, n_in, hidden, layers, n_out)[0]) / (2 * h)
+    assert np.abs(g - num).max() <= 1e-7 * max(1.0, np.abs(num).max())
+
+
+def test_mlp_linear_special_cases():
+    """No hidden layer: least squares, gradient X^T (X W^T + b - T) / n in closed form; a zero
+    input layer makes every hidden tanh output 0, so only the output bias matters."""
+    from oracle import mlp
+
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((9, 4))
+    T = rng.standard_normal((9, 2))
+    W = rng.standard_normal((2, 4))
+    b = rng.standard_normal(2)
+    theta = np.concatenate([W.ravel(), b])
+    loss, g = mlp.loss_and_grad(theta, X, T, 4, 0, 0, 2)
+    R = X @ W.T + b - T
+    assert np.isclose(loss, 0.5 * np.sum(R * R) / 9)
+    assert np.allclose(g, np.concatenate([(R.T @ X / 9).ravel(), R.sum(0) / 9]), atol=1e-14)
+    # zero first layer: the first hidden activations vanish for every input, so every sample
+    # gives the same output, and dL/db_out is the mean residual
+    n = mlp.n_params(4, 6, 2, 2)
+    theta = rng.standard_normal(n)
+    theta[: 6 * 4 + 6] = 0.0
+    y, _ = mlp.forward(theta, X, 4, 6, 2, 2)
+    assert np.allclose(y, y[0][None, :], atol=1e-15)
+    _, g = mlp.loss_and_grad(theta, X, T, 4, 6, 2, 2)
+    assert np.allclose(g[-2:], (y - T).mean(0), atol=1e-14)
+
+
+def test_mlp_adam_first_step_is_signed_lr():
+    """With m = v = 0 the first Adam step moves every parameter by lr * sign(g) (eps aside)."""
+    from oracle import mlp
+
+    g = np.array([0.3, -2.0, 1e-3, -5e-4])
+    th, m, v = mlp.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01, eps=0.0)
+    assert np.allclose(th, -0.01 * np.sign(g), rtol=1e-12)
