@@ -255,6 +255,8 @@ typedef struct {
   double max_err_est;       /* largest accepted error estimate                      */
   int evol_group;           /* column-group width the evolution ran with            */
   int n_ghost;              /* candidates with residual above ten level spacings    */
+  int model_used;           /* dacp_central_eigs_learned: 1 = bound and window from the network */
+  int model_fallback;       /* 1 = the network's window failed and Lanczos / KPM redid the call */
 } dacp_report;
 
 /* Fill `opts` with the defaults listed above. */
@@ -289,6 +291,54 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
  * if some realisation stays short after its retry (the others are still filled in). */
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports);
+
+/* ------------------------------------------------------- learned window */
+
+/* A small regression network (multilayer perceptron: `layers` tanh hidden layers of width
+ * `hidden`, linear output; loss 0.5 mean |y - t|^2) trained and evaluated on the GPU in FP32
+ * by the library's own forward, backward and Adam kernels.  The learned window uses
+ * n_in = DACP_WINDOW_FEATURES inputs and 2 outputs.  Parameters: one flat FP32 vector, layer
+ * by layer, W (n_out x n_in row-major) then b; initial weights Glorot-uniform from `seed`. */
+typedef struct dacp_mlp_s *dacp_mlp;
+dacp_status dacp_mlp_create(dacp_ctx ctx, int n_in, int hidden, int layers, int n_out, uint64_t seed, dacp_mlp *out);
+void dacp_mlp_free(dacp_mlp m);
+/* Copy the parameters out (get, host, may be NULL) and/or in (set, host, may be NULL; resets
+ * the Adam state); n_params (may be NULL) gets their number. */
+dacp_status dacp_mlp_params(dacp_ctx ctx, dacp_mlp m, float *get, const float *set, int *n_params);
+/* Loss and gradient of the network as it stands on n samples X (host n x n_in), T (host
+ * n x n_out), without standardisation; grad (host, n_params, may be NULL). */
+dacp_status dacp_mlp_loss_grad(dacp_ctx ctx, dacp_mlp m, int n, const double *X, const double *T, double *loss,
+                               double *grad);
+/* Adam training on standardised columns (means and deviations fixed by the first call's data
+ * and kept with the network): `epochs` passes in shuffled mini-batches of `batch`, learning
+ * rate lr; final_loss (host, may be NULL) gets the loss of the standardised targets. */
+dacp_status dacp_mlp_train(dacp_ctx ctx, dacp_mlp m, int n, const double *X, const double *Y, int epochs, int batch,
+                           double lr, uint64_t seed, double *final_loss);
+/* Y (host n x n_out) = network(X) in the units of the training targets. */
+dacp_status dacp_mlp_predict(dacp_ctx ctx, dacp_mlp m, int n, const double *X, double *Y);
+
+#define DACP_WINDOW_FEATURES 8
+/* Coupling statistics of H (host, no GPU work): L / 20, log sigma (sigma^2 = sum c^2 = tr H^2 / D),
+ * the diagonal share of sigma^2, its two-body part, the single-spin-flip share, max |c| / sigma,
+ * sum |c| / (sigma sqrt(n_strings)), log(n_strings) / log(L (L + 1) / 2 + 2 L). */
+dacp_status dacp_window_features(dacp_ham h, double *features);
+/* Targets of the learned window from the method's own estimators (Sec. III): per realisation
+ * labels[2 r] = log(E_b / sigma) from the Lanczos bound and labels[2 r + 1] =
+ * log(rho(0) sqrt(2 pi) sigma / D), with rho(0) the kernel-polynomial level density at E = 0
+ * (levels per unit energy, averaged over |E| <= 0.02 E_b).  Realisations with L <= 14 run as one
+ * batched launch per estimator.  opts (may be NULL) supplies the Lanczos steps, moments,
+ * vectors and seed. */
+dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, const dacp_opts *opts, double *labels);
+/* dacp_central_eigs with the bound and the window predicted by `model` (trained on
+ * dacp_window_features -> dacp_window_labels): E_b = (1 + bound_margin) sigma exp(y0), clamped to
+ * sum |c|; a from rho(0) = D exp(y1) / (sqrt(2 pi) sigma) as the half-width holding
+ * ceil(window_ratio N) levels.  If the call then fails with DACP_E_BOUNDS (E_b below ||H||),
+ * DACP_E_NUMERIC (a filter overflow from such a bound) or DACP_E_WINDOW (too few accepted
+ * values), it is redone with the Lanczos / KPM estimates
+ * (report->model_fallback = 1): the method's own estimators are the fallback and the judge. */
+dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, double bound_margin, int N,
+                                      const dacp_opts *opts, double *eigs_out, double *err_out, int *n_out,
+                                      dacp_report *report);
 
 #ifdef __cplusplus
 }

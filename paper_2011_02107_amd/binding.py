@@ -104,6 +104,8 @@ class Report(ctypes.Structure):
         ("max_err_est", ctypes.c_double),
         ("evol_group", ctypes.c_int),
         ("n_ghost", ctypes.c_int),
+        ("model_used", ctypes.c_int),
+        ("model_fallback", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -142,6 +144,21 @@ SIGNATURES = {
     ),
     "dacp_default_opts": (None, [ctypes.POINTER(Opts)]),
     "dacp_central_eigs": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)]),
+    "dacp_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "dacp_mlp_free": (None, [_vp]),
+    "dacp_mlp_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _ip]),
+    "dacp_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp, _dp, _dp]),
+    "dacp_mlp_train": (
+        ctypes.c_int,
+        [_vp, _vp, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, _dp],
+    ),
+    "dacp_mlp_predict": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _dp, _dp]),
+    "dacp_window_features": (ctypes.c_int, [_vp, _dp]),
+    "dacp_window_labels": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(Opts), _dp]),
+    "dacp_central_eigs_learned": (
+        ctypes.c_int,
+        [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)],
+    ),
     "dacp_central_eigs_batched": (
         ctypes.c_int,
         [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)],
@@ -367,3 +384,98 @@ def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True):
     if st != 0 and (raise_on_window or st != -5):
         ctx.check(st)
     return eigs, errs, n_out, [r.as_dict() for r in reps], st
+
+
+WINDOW_FEATURES = 8
+
+
+class Mlp:
+    """Owns a dacp_mlp handle (the learned window's network)."""
+
+    def __init__(self, ctx, n_in=WINDOW_FEATURES, hidden=64, layers=3, n_out=2, seed=0):
+        self.ctx = ctx
+        h = _vp()
+        ctx.check(ctx.lib.dacp_mlp_create(ctx.handle, int(n_in), int(hidden), int(layers), int(n_out), int(seed), ctypes.byref(h)))
+        self.handle = h
+        self.n_in, self.n_out = int(n_in), int(n_out)
+
+    def close(self):
+        if self.handle:
+            self.ctx.lib.dacp_mlp_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dacp_mlp_params(ctx, mlp, set_to=None):
+    """Returns the current parameters (float32); with set_to, loads those first."""
+    n = ctypes.c_int()
+    ctx.check(ctx.lib.dacp_mlp_params(ctx.handle, mlp.handle, None, None, ctypes.byref(n)))
+    if set_to is not None:
+        src = np.ascontiguousarray(set_to, dtype=np.float32)
+        assert src.size == n.value
+        ctx.check(ctx.lib.dacp_mlp_params(ctx.handle, mlp.handle, None, src.ctypes.data_as(_vp), None))
+    out = np.zeros(n.value, dtype=np.float32)
+    ctx.check(ctx.lib.dacp_mlp_params(ctx.handle, mlp.handle, out.ctypes.data_as(_vp), None, None))
+    return out
+
+
+def dacp_mlp_loss_grad(ctx, mlp, X, T):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    n = ctypes.c_int()
+    ctx.check(ctx.lib.dacp_mlp_params(ctx.handle, mlp.handle, None, None, ctypes.byref(n)))
+    grad = np.zeros(n.value)
+    loss = ctypes.c_double()
+    ctx.check(ctx.lib.dacp_mlp_loss_grad(ctx.handle, mlp.handle, X.shape[0], _f64(X), _f64(T), ctypes.byref(loss), _f64(grad)))
+    return loss.value, grad
+
+
+def dacp_mlp_train(ctx, mlp, X, Y, epochs=200, batch=64, lr=1e-3, seed=0):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    loss = ctypes.c_double()
+    ctx.check(ctx.lib.dacp_mlp_train(ctx.handle, mlp.handle, X.shape[0], _f64(X), _f64(Y), int(epochs), int(batch),
+                                     float(lr), int(seed), ctypes.byref(loss)))
+    return loss.value
+
+
+def dacp_mlp_predict(ctx, mlp, X):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Y = np.zeros((X.shape[0], mlp.n_out))
+    ctx.check(ctx.lib.dacp_mlp_predict(ctx.handle, mlp.handle, X.shape[0], _f64(X), _f64(Y)))
+    return Y
+
+
+def dacp_window_features(ctx, ham):
+    f = np.zeros(WINDOW_FEATURES)
+    ctx.check(ctx.lib.dacp_window_features(ham.handle, _f64(f)))
+    return f
+
+
+def dacp_window_labels(ctx, hams, opts=None):
+    count = len(hams)
+    out = np.zeros((count, 2))
+    handles = (_vp * count)(*[h.handle for h in hams])
+    ctx.check(ctx.lib.dacp_window_labels(ctx.handle, count, handles, ctypes.byref(opts) if opts is not None else None, _f64(out)))
+    return out
+
+
+def dacp_central_eigs_learned(ctx, ham, mlp, N, bound_margin=0.05, opts=None, raise_on_window=True):
+    """Returns (eigs ascending, error estimates, report dict, status)."""
+    if opts is None:
+        opts = default_opts()
+    eigs = np.zeros(N)
+    errs = np.zeros(N)
+    n_out = ctypes.c_int()
+    rep = Report()
+    st = ctx.lib.dacp_central_eigs_learned(ctx.handle, ham.handle, mlp.handle, float(bound_margin), int(N), ctypes.byref(opts),
+                                           _f64(eigs), _f64(errs), ctypes.byref(n_out), ctypes.byref(rep))
+    if st != 0 and (raise_on_window or st != -5):
+        ctx.check(st)
+    n = n_out.value if st == 0 else 0
+    return eigs[:n], errs[:n], rep.as_dict(), st

@@ -1052,16 +1052,25 @@ dacp_status dacp_build_hamiltonian(dacp_ctx ctx, int L, int n_terms, const dacp_
   std::vector<double> dc;
   for (auto &kv : diag) {
     if (kv.second == 0.0) continue;
+    const double c2 = kv.second * kv.second;
     h->sum_abs += std::fabs(kv.second);
-    h->sum_sq += kv.second * kv.second;
+    h->sum_sq += c2;
+    h->w_diag += c2;
+    if (__builtin_popcount(kv.first) == 2) h->w_zz += c2;
+    h->max_abs = std::max(h->max_abs, std::fabs(kv.second));
+    ++h->n_strings;
     dz.push_back(kv.first);
     dc.push_back(kv.second);
   }
   for (auto &kv : flips) {
     if (kv.second == 0.0) continue;
+    const double c2 = kv.second * kv.second;
     h->flips_host.push_back(FlipEntry{kv.first.first, kv.first.second, kv.second});
     h->sum_abs += std::fabs(kv.second);
-    h->sum_sq += kv.second * kv.second;
+    h->sum_sq += c2;
+    if (__builtin_popcount(kv.first.first) == 1) h->w_flip1 += c2;
+    h->max_abs = std::max(h->max_abs, std::fabs(kv.second));
+    ++h->n_strings;
   }
   std::stable_sort(h->flips_host.begin(), h->flips_host.end(),
                    [](const FlipEntry &a, const FlipEntry &b) { return a.xmask < b.xmask; });
@@ -1219,6 +1228,7 @@ void dacp_default_opts(dacp_opts *o) {
   o->max_retries = 1;
 }
 
+namespace {
 // Window, orders and basis size of one attempt (Sec. II.A, II.B, III; readings in the header).
 struct Plan {
   double n_w, a_r, a;
@@ -1411,6 +1421,8 @@ dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, do
   return DACP_OK;
 }
 
+}  // namespace
+
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_in, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report) {
   if (!ctx || !h || !eigs_out) return DACP_E_INVALID;
@@ -1521,6 +1533,128 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
 }
 
 
+namespace {
+// Lanczos bounds (e_bs, norm_est) and Chebyshev moments (mus) of many realisations with every
+// L <= 14: one launch of the batched spectral kernel per estimator (Sec. III estimators, the same
+// start vectors as the single-realisation path).  o.e_bound > 0 skips the bounds, o.a > 0 the
+// moments.
+dacp_status batched_estimates(dacp_ctx ctx, int count, const dacp_ham *hams, const dacp_opts &o, int max_L,
+                              std::vector<double> &e_bs, std::vector<double> &norm_est,
+                              std::vector<std::vector<double>> &mus) {
+  e_bs.assign(count, 0.0);
+  norm_est.assign(count, 0.0);
+  mus.assign(count, std::vector<double>());
+  const int steps0 = o.lanczos_steps > 0 ? o.lanczos_steps : 80;
+  const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
+  const int nvec = o.kpm_vectors > 0 ? o.kpm_vectors : 8;
+  std::vector<DevBuf> v0(count), out(count), scr(count), R(count), mout(count), mscr(count);
+  std::vector<BatchSpec> specs;
+  std::vector<int> steps(count);
+  auto base_spec = [&](dacp_ham h, const dacp::SplitOrder_t &so) {
+    BatchSpec c;
+    std::memset(&c, 0, sizeof(c));
+    c.flips = so.lo;
+    c.nflip = so.nlo;
+    c.nplain = so.nlo_plain;
+    c.d64 = h->d64;
+    c.L = h->L;
+    return c;
+  };
+  if (!(o.e_bound > 0.0)) {
+    for (int r = 0; r < count; ++r) {
+      dacp_ham h = hams[r];
+      const int64_t D = h->D;
+      steps[r] = static_cast<int>(std::min<int64_t>(steps0, D));
+      DACP_TRY(split_order(ctx, h, h->L));
+      DACP_HIP(ctx, v0[r].alloc(D * sizeof(double)));
+      DACP_HIP(ctx, dacp::launch_philox_gauss(v0[r].as<double>(), D, 1, o.seed ^ 0x5bd1e995ULL, ctx->stream));
+      DACP_HIP(ctx, out[r].alloc((2 * steps[r] + 1) * sizeof(double)));
+      if (h->L == 14) DACP_HIP(ctx, scr[r].alloc(D * sizeof(double)));
+      BatchSpec c = base_spec(h, h->split[h->L]);
+      c.start = v0[r].as<double>();
+      c.ld = 1;
+      c.scratch = scr[r].as<double>();
+      c.out = out[r].as<double>();
+      c.kind = 0;
+      c.steps = steps[r];
+      specs.push_back(c);
+    }
+    DevBuf dspecs;
+    DACP_HIP(ctx, dspecs.alloc(sizeof(BatchSpec) * specs.size()));
+    DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
+    DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
+                                              ctx->stream));
+    for (int r = 0; r < count; ++r) {
+      std::vector<double> o2(2 * steps[r] + 1);
+      DACP_TRY(to_host(ctx, o2.data(), out[r].p, o2.size() * sizeof(double)));
+      const int k = static_cast<int>(o2[2 * steps[r]]);
+      if (k < 1 || k > steps[r]) return set_err(ctx, DACP_E_NUMERIC, "batched: Lanczos run " + std::to_string(r));
+      std::vector<double> al(o2.begin(), o2.begin() + k), be(o2.begin() + steps[r], o2.begin() + steps[r] + k);
+      for (int j = 0; j < k; ++j)
+        if (!std::isfinite(al[j]) || !std::isfinite(be[j]))
+          return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite Lanczos run " + std::to_string(r));
+      double th_lo = 0.0, th_hi = 0.0;
+      DACP_TRY(lanczos_bound(ctx, al, be, 1.01, hams[r]->sum_abs, &e_bs[r], &th_lo, &th_hi));
+      norm_est[r] = std::max(std::fabs(th_lo), std::fabs(th_hi));
+    }
+    specs.clear();
+  } else {
+    for (int r = 0; r < count; ++r) {
+      e_bs[r] = o.e_bound;
+      norm_est[r] = o.e_bound;
+    }
+  }
+  if (!(o.a > 0.0)) {
+    for (int r = 0; r < count; ++r) {
+      dacp_ham h = hams[r];
+      const int64_t D = h->D;
+      DACP_TRY(split_order(ctx, h, h->L));
+      DACP_HIP(ctx, R[r].alloc(static_cast<size_t>(D) * nvec * sizeof(double)));
+      DACP_HIP(ctx, dacp::launch_philox_gauss(R[r].as<double>(), D, nvec, o.seed ^ 0x2545f491ULL, ctx->stream));
+      DACP_HIP(ctx, mout[r].alloc(static_cast<size_t>(M) * nvec * sizeof(double)));
+      if (h->L == 14) DACP_HIP(ctx, mscr[r].alloc(static_cast<size_t>(D) * nvec * sizeof(double)));
+      for (int q = 0; q < nvec; ++q) {
+        BatchSpec c = base_spec(h, h->split[h->L]);
+        c.start = R[r].as<double>() + q;
+        c.ld = nvec;
+        c.scratch = h->L == 14 ? mscr[r].as<double>() + static_cast<int64_t>(D) * q : nullptr;
+        c.out = mout[r].as<double>() + static_cast<int64_t>(M) * q;
+        c.inv_e = 1.0 / e_bs[r];
+        c.kind = 1;
+        c.steps = M;
+        specs.push_back(c);
+      }
+    }
+    DevBuf dspecs;
+    DACP_HIP(ctx, dspecs.alloc(sizeof(BatchSpec) * specs.size()));
+    DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
+    DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
+                                              ctx->stream));
+    for (int r = 0; r < count; ++r) {
+      std::vector<double> mo(static_cast<size_t>(M) * nvec);
+      DACP_TRY(to_host(ctx, mo.data(), mout[r].p, mo.size() * sizeof(double)));
+      auto tot = [&](int idx) {
+        double t = 0.0;
+        for (int q = 0; q < nvec; ++q) t += mo[static_cast<size_t>(q) * M + idx];
+        return t;
+      };
+      std::vector<double> &mu = mus[r];
+      mu.assign(M, 0.0);
+      const double n0 = tot(0);
+      mu[0] = 1.0;
+      if (M > 1) mu[1] = tot(1) / n0;
+      for (int k = 1; 2 * k < M; ++k) {
+        mu[2 * k] = 2.0 * tot(2 * k) / n0 - mu[0];
+        if (2 * k + 1 < M) mu[2 * k + 1] = 2.0 * tot(2 * k + 1) / n0 - mu[1];
+      }
+      for (double x : mu)
+        if (!std::isfinite(x)) return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite moments " + std::to_string(r));
+    }
+  }
+  return DACP_OK;
+}
+}  // namespace
+
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports) {
   if (!ctx || count < 1 || !hams || !eigs_out || !n_out)
@@ -1547,113 +1681,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   std::vector<std::vector<double>> mus(count);
   {
     const double tb = now_ms();
-    const int steps0 = o.lanczos_steps > 0 ? o.lanczos_steps : 80;
-    const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
-    const int nvec = o.kpm_vectors > 0 ? o.kpm_vectors : 8;
-    std::vector<DevBuf> v0(count), out(count), scr(count), R(count), mout(count), mscr(count);
-    std::vector<BatchSpec> specs;
-    std::vector<int> steps(count);
-    auto base_spec = [&](dacp_ham h, const dacp::SplitOrder_t &so) {
-      BatchSpec c;
-      std::memset(&c, 0, sizeof(c));
-      c.flips = so.lo;
-      c.nflip = so.nlo;
-      c.nplain = so.nlo_plain;
-      c.d64 = h->d64;
-      c.L = h->L;
-      return c;
-    };
-    if (!(o.e_bound > 0.0)) {
-      for (int r = 0; r < count; ++r) {
-        dacp_ham h = hams[r];
-        const int64_t D = h->D;
-        steps[r] = static_cast<int>(std::min<int64_t>(steps0, D));
-        DACP_TRY(split_order(ctx, h, h->L));
-        DACP_HIP(ctx, v0[r].alloc(D * sizeof(double)));
-        DACP_HIP(ctx, dacp::launch_philox_gauss(v0[r].as<double>(), D, 1, o.seed ^ 0x5bd1e995ULL, ctx->stream));
-        DACP_HIP(ctx, out[r].alloc((2 * steps[r] + 1) * sizeof(double)));
-        if (h->L == 14) DACP_HIP(ctx, scr[r].alloc(D * sizeof(double)));
-        BatchSpec c = base_spec(h, h->split[h->L]);
-        c.start = v0[r].as<double>();
-        c.ld = 1;
-        c.scratch = scr[r].as<double>();
-        c.out = out[r].as<double>();
-        c.kind = 0;
-        c.steps = steps[r];
-        specs.push_back(c);
-      }
-      DevBuf dspecs;
-      DACP_HIP(ctx, dspecs.alloc(sizeof(BatchSpec) * specs.size()));
-      DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
-      DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
-                                                ctx->stream));
-      for (int r = 0; r < count; ++r) {
-        std::vector<double> o2(2 * steps[r] + 1);
-        DACP_TRY(to_host(ctx, o2.data(), out[r].p, o2.size() * sizeof(double)));
-        const int k = static_cast<int>(o2[2 * steps[r]]);
-        if (k < 1 || k > steps[r]) return set_err(ctx, DACP_E_NUMERIC, "batched: Lanczos run " + std::to_string(r));
-        std::vector<double> al(o2.begin(), o2.begin() + k), be(o2.begin() + steps[r], o2.begin() + steps[r] + k);
-        for (int j = 0; j < k; ++j)
-          if (!std::isfinite(al[j]) || !std::isfinite(be[j]))
-            return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite Lanczos run " + std::to_string(r));
-        double th_lo = 0.0, th_hi = 0.0;
-        DACP_TRY(lanczos_bound(ctx, al, be, 1.01, hams[r]->sum_abs, &e_bs[r], &th_lo, &th_hi));
-        norm_est[r] = std::max(std::fabs(th_lo), std::fabs(th_hi));
-      }
-      specs.clear();
-    } else {
-      for (int r = 0; r < count; ++r) {
-        e_bs[r] = o.e_bound;
-        norm_est[r] = o.e_bound;
-      }
-    }
-    if (!(o.a > 0.0)) {
-      for (int r = 0; r < count; ++r) {
-        dacp_ham h = hams[r];
-        const int64_t D = h->D;
-        DACP_TRY(split_order(ctx, h, h->L));
-        DACP_HIP(ctx, R[r].alloc(static_cast<size_t>(D) * nvec * sizeof(double)));
-        DACP_HIP(ctx, dacp::launch_philox_gauss(R[r].as<double>(), D, nvec, o.seed ^ 0x2545f491ULL, ctx->stream));
-        DACP_HIP(ctx, mout[r].alloc(static_cast<size_t>(M) * nvec * sizeof(double)));
-        if (h->L == 14) DACP_HIP(ctx, mscr[r].alloc(static_cast<size_t>(D) * nvec * sizeof(double)));
-        for (int q = 0; q < nvec; ++q) {
-          BatchSpec c = base_spec(h, h->split[h->L]);
-          c.start = R[r].as<double>() + q;
-          c.ld = nvec;
-          c.scratch = h->L == 14 ? mscr[r].as<double>() + static_cast<int64_t>(D) * q : nullptr;
-          c.out = mout[r].as<double>() + static_cast<int64_t>(M) * q;
-          c.inv_e = 1.0 / e_bs[r];
-          c.kind = 1;
-          c.steps = M;
-          specs.push_back(c);
-        }
-      }
-      DevBuf dspecs;
-      DACP_HIP(ctx, dspecs.alloc(sizeof(BatchSpec) * specs.size()));
-      DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
-      DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
-                                                ctx->stream));
-      for (int r = 0; r < count; ++r) {
-        std::vector<double> mo(static_cast<size_t>(M) * nvec);
-        DACP_TRY(to_host(ctx, mo.data(), mout[r].p, mo.size() * sizeof(double)));
-        auto tot = [&](int idx) {
-          double t = 0.0;
-          for (int q = 0; q < nvec; ++q) t += mo[static_cast<size_t>(q) * M + idx];
-          return t;
-        };
-        std::vector<double> &mu = mus[r];
-        mu.assign(M, 0.0);
-        const double n0 = tot(0);
-        mu[0] = 1.0;
-        if (M > 1) mu[1] = tot(1) / n0;
-        for (int k = 1; 2 * k < M; ++k) {
-          mu[2 * k] = 2.0 * tot(2 * k) / n0 - mu[0];
-          if (2 * k + 1 < M) mu[2 * k + 1] = 2.0 * tot(2 * k + 1) / n0 - mu[1];
-        }
-        for (double x : mu)
-          if (!std::isfinite(x)) return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite moments " + std::to_string(r));
-      }
-    }
+    DACP_TRY(batched_estimates(ctx, count, hams, o, max_L, e_bs, norm_est, mus));
     const double t_spec = now_ms() - tb;
     vlog("batched bounds and densities of %d realisations: %.1f ms", count, t_spec);
     for (int r = 0; r < count; ++r) {
@@ -1815,6 +1843,111 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   }
   if (worst != DACP_OK) return set_err(ctx, worst, "batched: some realisations fell short of N accepted eigenvalues");
   return DACP_OK;
+}
+
+dacp_status dacp_window_features(dacp_ham h, double *f) {
+  if (!h || !f) return DACP_E_INVALID;
+  const double sig2 = h->sum_sq;
+  if (!(sig2 > 0.0) || h->n_strings < 1) return DACP_E_INVALID;
+  const double sig = std::sqrt(sig2);
+  const double L = h->L;
+  f[0] = L / 20.0;
+  f[1] = std::log(sig);
+  f[2] = h->w_diag / sig2;
+  f[3] = h->w_zz / sig2;
+  f[4] = h->w_flip1 / sig2;
+  f[5] = h->max_abs / sig;
+  f[6] = h->sum_abs / (sig * std::sqrt(static_cast<double>(h->n_strings)));
+  f[7] = std::log(static_cast<double>(h->n_strings)) / std::log(L * (L + 1.0) / 2.0 + 2.0 * L);
+  return DACP_OK;
+}
+
+dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, const dacp_opts *opts, double *labels) {
+  if (!ctx || count < 1 || !hams || !labels) return DACP_E_INVALID;
+  dacp_opts o;
+  if (opts) o = *opts;
+  else dacp_default_opts(&o);
+  o.e_bound = 0.0;  // labels come from the estimators themselves
+  o.a = 0.0;
+  int max_L = 0;
+  for (int r = 0; r < count; ++r) {
+    if (!hams[r] || !(hams[r]->sum_sq > 0.0)) return set_err(ctx, DACP_E_INVALID, "window_labels: bad Hamiltonian");
+    max_L = std::max(max_L, hams[r]->L);
+  }
+  std::vector<double> e_bs(count), norm_est(count);
+  std::vector<std::vector<double>> mus(count);
+  if (max_L <= 14) {
+    DACP_TRY(batched_estimates(ctx, count, hams, o, max_L, e_bs, norm_est, mus));
+  } else {
+    const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
+    for (int r = 0; r < count; ++r) {
+      double lo = 0.0, hi = 0.0;
+      DACP_TRY(run_bound(ctx, hams[r], o.lanczos_steps > 0 ? o.lanczos_steps : 80, nullptr, o.seed ^ 0x5bd1e995ULL, 1.01,
+                         &e_bs[r], &lo, &hi));
+      mus[r].assign(M, 0.0);
+      DACP_TRY(run_moments(ctx, hams[r], e_bs[r], M, o.kpm_vectors > 0 ? o.kpm_vectors : 8, nullptr,
+                           o.seed ^ 0x2545f491ULL, mus[r].data()));
+    }
+  }
+  const double a_r0 = 0.02;
+  for (int r = 0; r < count; ++r) {
+    const double sig = std::sqrt(hams[r]->sum_sq);
+    const double D = static_cast<double>(hams[r]->D);
+    const double rho0 = kpm_count(mus[r], hams[r]->D, a_r0) / (2.0 * a_r0 * e_bs[r]);
+    if (!(rho0 > 0.0)) return set_err(ctx, DACP_E_NUMERIC, "window_labels: no levels near 0 in realisation " + std::to_string(r));
+    labels[2 * r] = std::log(e_bs[r] / sig);
+    labels[2 * r + 1] = std::log(rho0 * std::sqrt(2.0 * M_PI) * sig / D);
+  }
+  return DACP_OK;
+}
+
+dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, double bound_margin, int N,
+                                      const dacp_opts *opts_in, double *eigs_out, double *err_out, int *n_out,
+                                      dacp_report *report) {
+  if (!ctx || !h || !model || !eigs_out || !(bound_margin >= 0.0))
+    return set_err(ctx, DACP_E_INVALID, "central_eigs_learned: need ctx, h, model, eigs_out, bound_margin >= 0");
+  dacp_opts o;
+  if (opts_in) o = *opts_in;
+  else dacp_default_opts(&o);
+  const double t0 = now_ms();
+  double f[DACP_WINDOW_FEATURES], y[2];
+  if (dacp_window_features(h, f) != DACP_OK) return set_err(ctx, DACP_E_INVALID, "central_eigs_learned: features");
+  DACP_TRY(dacp_mlp_predict(ctx, model, 1, f, y));
+  const double sig = std::sqrt(h->sum_sq);
+  const double D = static_cast<double>(h->D);
+  double e_b = std::min((1.0 + bound_margin) * sig * std::exp(y[0]), h->sum_abs);
+  const double rho0 = D * std::exp(y[1]) / (std::sqrt(2.0 * M_PI) * sig);
+  const double n_w = std::min(D, std::ceil((o.window_ratio > 0.0 ? o.window_ratio : 2.2) * N));
+  double a = std::min(0.95 * e_b, n_w / (2.0 * rho0));
+  dacp_opts o2 = o;
+  o2.e_bound = e_b;
+  o2.a = a;
+  o2.tol_rel = o.tol_rel / (1.0 + bound_margin);  // tolerance relative to the unwidened bound
+  const double t_pred = now_ms() - t0;
+  vlog("learned window: E_b=%.6g a=%.6g (prediction %.2f ms)", e_b, a, t_pred);
+  dacp_report r1;
+  std::memset(&r1, 0, sizeof(r1));
+  int got = 0;
+  dacp_status st = (std::isfinite(e_b) && std::isfinite(a) && a > 0.0 && e_b > a)
+                       ? dacp_central_eigs(ctx, h, N, &o2, eigs_out, err_out, &got, &r1)
+                       : DACP_E_WINDOW;
+  r1.model_used = 1;
+  r1.t_bound_ms = t_pred;
+  if (st == DACP_E_BOUNDS || st == DACP_E_WINDOW || st == DACP_E_NUMERIC) {
+    vlog("learned window failed (status %d): Lanczos / KPM fallback", static_cast<int>(st));
+    dacp_report r2;
+    std::memset(&r2, 0, sizeof(r2));
+    st = dacp_central_eigs(ctx, h, N, &o, eigs_out, err_out, &got, &r2);
+    r2.model_used = 1;
+    r2.model_fallback = 1;
+    r2.t_total_ms = now_ms() - t0;
+    r1 = r2;
+  } else {
+    r1.t_total_ms = now_ms() - t0;
+  }
+  if (n_out) *n_out = got;
+  if (report) *report = r1;
+  return st;
 }
 
 }  // extern "C"

@@ -238,6 +238,9 @@ struct dacp_ham_s {
   int L = 0;
   int64_t D = 0;
   double sum_abs = 0.0, sum_sq = 0.0;
+  // coupling statistics of the merged Pauli strings (features of the learned window)
+  double w_diag = 0.0, w_zz = 0.0, w_flip1 = 0.0, max_abs = 0.0;
+  int n_strings = 0;
   double *d64 = nullptr;  // diagonal of H, FP64
   float *d32 = nullptr;   // same in FP32
   dacp::FlipEntry *flips = nullptr;

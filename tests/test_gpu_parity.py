@@ -532,3 +532,126 @@ def test_central_eigs_batched_rejects_large_L(ctx):
     with pytest.raises(B.DacpError) as ei:
         B.dacp_central_eigs_batched(ctx, [ham], 10, B.default_opts(b=4))
     assert ei.value.status == -1
+
+
+# ------------------------------------------------------------------ learned window
+
+
+def _mlp_dims():
+    return B.WINDOW_FEATURES, 64, 3, 2
+
+
+def test_mlp_gradient_matches_oracle(ctx):
+    """FP32 forward/backward kernels against the FP64 oracle network on the same parameters."""
+    from oracle import mlp as omlp
+
+    n_in, hidden, layers, n_out = _mlp_dims()
+    net = B.Mlp(ctx, n_in, hidden, layers, n_out, seed=3)
+    theta = B.dacp_mlp_params(ctx, net).astype(np.float64)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((100, n_in))
+    T = rng.standard_normal((100, n_out))
+    loss, g = B.dacp_mlp_loss_grad(ctx, net, X, T)
+    loss_ref, g_ref = omlp.loss_and_grad(theta, X, T, n_in, hidden, layers, n_out)
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    assert np.abs(g - g_ref).max() <= 1e-3 * np.abs(g_ref).max()
+    # the same on a deeper-than-wide case with a ragged last mini-batch-like size
+    net2 = B.Mlp(ctx, 3, 5, 2, 2, seed=9)
+    th2 = B.dacp_mlp_params(ctx, net2).astype(np.float64)
+    X2, T2 = rng.standard_normal((7, 3)), rng.standard_normal((7, 2))
+    l2, g2 = B.dacp_mlp_loss_grad(ctx, net2, X2, T2)
+    l2r, g2r = omlp.loss_and_grad(th2, X2, T2, 3, 5, 2, 2)
+    assert abs(l2 - l2r) <= 1e-5 * l2r and np.abs(g2 - g2r).max() <= 1e-4 * np.abs(g2r).max()
+
+
+def test_mlp_adam_step_matches_oracle(ctx):
+    """One full-batch epoch = one Adam step on the standardised data."""
+    from oracle import mlp as omlp
+
+    n_in, hidden, layers, n_out = 4, 16, 2, 2
+    net = B.Mlp(ctx, n_in, hidden, layers, n_out, seed=1)
+    theta = B.dacp_mlp_params(ctx, net).astype(np.float64)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((40, n_in)) * 3 + 1
+    Y = rng.standard_normal((40, n_out)) * 2 - 5
+    Xs = (X - X.mean(0)) / X.std(0)
+    Ys = (Y - Y.mean(0)) / Y.std(0)
+    _, g = omlp.loss_and_grad(theta, Xs, Ys, n_in, hidden, layers, n_out)
+    ref, _, _ = omlp.adam_step(theta, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-2)
+    B.dacp_mlp_train(ctx, net, X, Y, epochs=1, batch=40, lr=1e-2)
+    got = B.dacp_mlp_params(ctx, net).astype(np.float64)
+    assert np.abs(got - ref).max() <= 2e-5
+
+
+def test_mlp_learns_a_smooth_map(ctx):
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (600, 8))
+    Y = np.stack([np.sin(2 * X[:, 0]) + 0.5 * X[:, 1] ** 2, X[:, 2] * X[:, 3] - 0.3 * X[:, 4]], axis=1)
+    net = B.Mlp(ctx, seed=0)
+    loss = B.dacp_mlp_train(ctx, net, X[:500], Y[:500], epochs=300, batch=64, lr=3e-3, seed=1)
+    assert loss < 0.02
+    pred = B.dacp_mlp_predict(ctx, net, X[500:])
+    assert np.sqrt(np.mean((pred - Y[500:]) ** 2)) < 0.1
+
+
+def test_window_labels_match_the_estimators(ctx):
+    """Labels equal log(E_b / sigma) of the Lanczos bound and the KPM density near 0, and the
+    density is close to the exact central level density of the dense spectrum."""
+    hams, terms_l = [], []
+    for L, seed in ((9, 1), (10, 2), (11, 3)):
+        t = inputs.spin_glass(L, seed)
+        terms_l.append((L, t))
+        hams.append(B.dacp_build_hamiltonian(ctx, L, t))
+    lab = B.dacp_window_labels(ctx, hams)
+    for (L, t), h, (y0, y1) in zip(terms_l, hams, lab):
+        sig = np.sqrt(hamiltonian.sum_sq_coeff(t))
+        eb, _, _ = B.dacp_spectral_bound(ctx, h, steps=80, seed=0x5BD1E995)
+        assert abs(y0 - np.log(eb / sig)) <= 1e-9
+        ev = central.full_spectrum_dense(L, t)
+        assert eb >= np.abs(ev).max()
+        D = 1 << L
+        half = 0.02 * eb
+        exact = np.sum(np.abs(ev) <= half) / (2 * half)
+        rho = D * np.exp(y1) / (np.sqrt(2 * np.pi) * sig)
+        assert abs(rho - exact) <= 0.25 * exact
+
+
+def _trained_window_model(ctx, seed=0):
+    hams, feats = [], []
+    for L in (8, 9, 10, 11, 12):
+        for s in range(40):
+            h = B.dacp_build_hamiltonian(ctx, L, inputs.spin_glass(L, 1000 + 97 * L + s))
+            hams.append(h)
+            feats.append(B.dacp_window_features(ctx, h))
+    lab = B.dacp_window_labels(ctx, hams)
+    net = B.Mlp(ctx, seed=seed)
+    B.dacp_mlp_train(ctx, net, np.array(feats), lab, epochs=400, batch=64, lr=2e-3, seed=seed)
+    return net
+
+
+def test_central_eigs_learned_matches_dense_oracle(ctx):
+    net = _trained_window_model(ctx)
+    L, N = 12, 150
+    terms = inputs.spin_glass(L, 11)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs_learned(ctx, ham, net, N, bound_margin=0.05, opts=B.default_opts(b=8))
+    assert rep["model_used"] == 1
+    _check_central(eigs, ref, norm, N)
+
+
+def test_central_eigs_learned_falls_back_on_a_bad_model(ctx):
+    """A network that predicts a bound far below ||H||: the evolution's norm guard trips and the
+    Lanczos / KPM path redoes the call, with the same answer."""
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((64, B.WINDOW_FEATURES))
+    Y = np.stack([np.full(64, -3.0), np.zeros(64)], axis=1) + 1e-3 * rng.standard_normal((64, 2))
+    net = B.Mlp(ctx, seed=2)
+    B.dacp_mlp_train(ctx, net, X, Y, epochs=50, batch=64, lr=1e-2)
+    L, N = 10, 60
+    terms = inputs.spin_glass(L, 21)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs_learned(ctx, ham, net, N, bound_margin=0.0, opts=B.default_opts(b=8))
+    assert rep["model_used"] == 1 and rep["model_fallback"] == 1
+    _check_central(eigs, ref, norm, N)
