@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="chain_L20_N5000", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="chain_L20_N5000",
+                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "fp32_tail_table"])
     ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
     ap.add_argument("--window-ratio", type=float, default=None)
@@ -126,10 +127,130 @@ def profile_kernels(args):
                       "algorithmic_bytes_per_step": 3 * D * g * 8, "e_bound": eb}), flush=True)
 
 
+def batch96(args):
+    """96 spin-glass shards (32 each at L = 12, 13, 14, disorder seeds 0..95), N = 200 each:
+    dacp_central_eigs_batched (one persistent launch per stage) against a per-realisation loop
+    of plain FP64 dacp_central_eigs (timed on the first 12 realisations, scaled to 96)."""
+    import numpy as np
+    import torch
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    ctx = B.Context(0)
+    sets = inputs.batched_spin_glass_set()
+    hams = [B.dacp_build_hamiltonian(ctx, L, t) for (L, _, t) in sets]
+    N = 200
+    opts = B.default_opts(b=8, precision=B.DACP_F32, fp64_tail_frac=0.3)
+    B.dacp_central_eigs_batched(ctx, hams[:3], N, opts)  # load the kernels
+    times = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    t0 = time.perf_counter()
+    for h in hams[:12]:
+        B.dacp_central_eigs(ctx, h, N, B.default_opts(b=8))
+    loop = (time.perf_counter() - t0) / 12 * len(hams)
+    print(json.dumps({
+        "metric": "central eigenvalues/s, 96 spin-glass realisations L=12/13/14, N=200 each (batched)",
+        "value": int(n_out.sum()) / dt, "unit": "eigenvalues/s", "realisations_per_s": len(hams) / dt,
+        "s_per_call": dt, "all_reached_N": bool(np.all(n_out == N)),
+        "shared_launch_ms": reps[0]["t_evol_ms"], "bounds_ms": reps[0]["t_bound_ms"],
+        "per_realisation_loop_fp64": {"value": N * len(hams) / loop, "s": loop, "timed": "first 12, scaled"},
+        "speedup_vs_loop": loop / dt, "dtype": "f32-filter+f64", "data": "synthetic"}), flush=True)
+
+
+def glass18_learned(args):
+    """Spin-glass shard L = 18 (disorder seed 0), N = 3000: bound and window from the learned
+    network (trained on Lanczos/KPM labels of 448 realisations, L = 10..16, seeds 1000+) against the
+    Lanczos/KPM estimators; reports times, fallback and whether the predicted window held N."""
+    import numpy as np
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    ctx = B.Context(0)
+    t0 = time.perf_counter()
+    hams, feats = [], []
+    for L in (10, 11, 12, 13, 14, 15, 16):
+        for s_ in range(80 if L <= 14 else 24):
+            h = B.dacp_build_hamiltonian(ctx, L, inputs.spin_glass(L, 1000 + 131 * L + s_))
+            hams.append(h)
+            feats.append(B.dacp_window_features(ctx, h))
+    labels = B.dacp_window_labels(ctx, hams)
+    t_labels = time.perf_counter() - t0
+    net = B.Mlp(ctx, seed=0)
+    t0 = time.perf_counter()
+    loss = B.dacp_mlp_train(ctx, net, np.array(feats), labels, epochs=400, batch=64, lr=2e-3, seed=0)
+    t_train = time.perf_counter() - t0
+    for h in hams:
+        h.close()
+    L, N = 18, 3000
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.spin_glass(L, 0))
+    opts = B.default_opts(b=64)
+    truth = B.dacp_window_labels(ctx, [ham])[0]
+    pred = B.dacp_mlp_predict(ctx, net, B.dacp_window_features(ctx, ham)[None, :])[0]
+    t0 = time.perf_counter()
+    e1, _, r1, _ = B.dacp_central_eigs_learned(ctx, ham, net, N, bound_margin=0.08, opts=opts)
+    t_learned = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e2, _, r2, _ = B.dacp_central_eigs(ctx, ham, N, opts)
+    t_plain = time.perf_counter() - t0
+    print(json.dumps({
+        "metric": "spin glass L=18 N=3000: learned window vs Lanczos/KPM", "unit": "s",
+        "learned_s": t_learned, "lanczos_kpm_s": t_plain,
+        "learned_bound_stage_ms": r1["t_bound_ms"], "lanczos_kpm_bound_stage_ms": r2["t_bound_ms"],
+        "fallback": r1["model_fallback"], "window_held_N": int(r1["model_fallback"] == 0 and r1["retries"] == 0),
+        "m_learned": r1["m"], "m_lanczos_kpm": r2["m"],
+        "label_true": truth.tolist(), "label_pred": pred.tolist(),
+        "max_abs_diff_between_paths": float(np.abs(np.sort(e1) - np.sort(e2)).max()),
+        "train": {"realisations": len(feats), "label_s": t_labels, "train_s": t_train, "final_loss": loss},
+        "data": "synthetic"}), flush=True)
+
+
+def fp32_tail_table(args):
+    """Error of the FP32 filter + FP64 tail against the dense FP64 oracle, per tail fraction
+    (spin glass L = 12, N = 200, b = 8, kfac 12)."""
+    import numpy as np
+
+    from oracle import central
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    ctx = B.Context(0)
+    L, N = 12, 200
+    terms = inputs.spin_glass(L, 0)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    rows = []
+    for prec, frac in ((B.DACP_F64, 1.0), (B.DACP_F32, 0.0), (B.DACP_F32, 0.05), (B.DACP_F32, 0.1),
+                       (B.DACP_F32, 0.2), (B.DACP_F32, 0.3)):
+        o = B.default_opts(b=8, kfac=12.0, precision=prec, fp64_tail_frac=frac, max_retries=0)
+        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o, raise_on_window=False)
+        row = {"filter": "f64" if prec == B.DACP_F64 else "f32", "fp64_tail_frac": frac, "status": st,
+               "accepted_core": rep["n_accepted"], "of_candidates": rep["n_candidates"]}
+        if st == 0:
+            d = np.abs(np.sort(eigs) - ref) / norm
+            row.update({"max_rel_err": float(d.max()), "median_rel_err": float(np.median(d))})
+        rows.append(row)
+    print(json.dumps({"metric": "FP32 filter + FP64 tail vs dense FP64 oracle (glass L=12, N=200)",
+                      "rows": rows, "norm": norm}), flush=True)
+
+
 def main():
     args = parse()
     if args.profile_kernels:
         return profile_kernels(args)
+    if args.workload == "glass_batch96_N200":
+        return batch96(args)
+    if args.workload == "glass_L18_N3000_learned":
+        return glass18_learned(args)
+    if args.workload == "fp32_tail_table":
+        return fp32_tail_table(args)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU design is described in DESIGN.md", file=sys.stderr)

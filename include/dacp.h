@@ -323,14 +323,16 @@ dacp_status dacp_mlp_predict(dacp_ctx ctx, dacp_mlp m, int n, const double *X, d
  * sum |c| / (sigma sqrt(n_strings)), log(n_strings) / log(L (L + 1) / 2 + 2 L). */
 dacp_status dacp_window_features(dacp_ham h, double *features);
 /* Targets of the learned window from the method's own estimators (Sec. III): per realisation
- * labels[2 r] = log(E_b / sigma) from the Lanczos bound and labels[2 r + 1] =
+ * labels[2 r] = log(E_b / (sigma sqrt(2 L ln 2))) from the Lanczos bound (sigma sqrt(2 L ln 2) is
+ * the extreme-value scale of 2^L levels of spread sigma, which keeps the target flat in L) and
+ * labels[2 r + 1] =
  * log(rho(0) sqrt(2 pi) sigma / D), with rho(0) the kernel-polynomial level density at E = 0
  * (levels per unit energy, averaged over |E| <= 0.02 E_b).  Realisations with L <= 14 run as one
- * batched launch per estimator.  opts (may be NULL) supplies the Lanczos steps, moments,
+ * batched launch per estimator, the others one by one.  opts (may be NULL) supplies the Lanczos steps, moments,
  * vectors and seed. */
 dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, const dacp_opts *opts, double *labels);
 /* dacp_central_eigs with the bound and the window predicted by `model` (trained on
- * dacp_window_features -> dacp_window_labels): E_b = (1 + bound_margin) sigma exp(y0), clamped to
+ * dacp_window_features -> dacp_window_labels): E_b = (1 + bound_margin) sigma sqrt(2 L ln 2) exp(y0), clamped to
  * sum |c|; a from rho(0) = D exp(y1) / (sqrt(2 pi) sigma) as the half-width holding
  * ceil(window_ratio N) levels.  If the call then fails with DACP_E_BOUNDS (E_b below ||H||),
  * DACP_E_NUMERIC (a filter overflow from such a bound) or DACP_E_WINDOW (too few accepted

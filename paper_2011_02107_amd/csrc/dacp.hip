@@ -1876,11 +1876,29 @@ dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, co
   }
   std::vector<double> e_bs(count), norm_est(count);
   std::vector<std::vector<double>> mus(count);
-  if (max_L <= 14) {
-    DACP_TRY(batched_estimates(ctx, count, hams, o, max_L, e_bs, norm_est, mus));
-  } else {
+  {
+    // L <= 14 in one batched launch per estimator, the rest one by one
+    std::vector<dacp_ham> small;
+    std::vector<int> where;
+    int ml = 0;
+    for (int r = 0; r < count; ++r)
+      if (hams[r]->L <= 14) {
+        small.push_back(hams[r]);
+        where.push_back(r);
+        ml = std::max(ml, hams[r]->L);
+      }
+    if (!small.empty()) {
+      std::vector<double> eb2, ne2;
+      std::vector<std::vector<double>> mu2;
+      DACP_TRY(batched_estimates(ctx, static_cast<int>(small.size()), small.data(), o, ml, eb2, ne2, mu2));
+      for (size_t q = 0; q < small.size(); ++q) {
+        e_bs[where[q]] = eb2[q];
+        mus[where[q]] = mu2[q];
+      }
+    }
     const int M = o.kpm_moments > 1 ? o.kpm_moments : 256;
     for (int r = 0; r < count; ++r) {
+      if (hams[r]->L <= 14) continue;
       double lo = 0.0, hi = 0.0;
       DACP_TRY(run_bound(ctx, hams[r], o.lanczos_steps > 0 ? o.lanczos_steps : 80, nullptr, o.seed ^ 0x5bd1e995ULL, 1.01,
                          &e_bs[r], &lo, &hi));
@@ -1895,7 +1913,7 @@ dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, co
     const double D = static_cast<double>(hams[r]->D);
     const double rho0 = kpm_count(mus[r], hams[r]->D, a_r0) / (2.0 * a_r0 * e_bs[r]);
     if (!(rho0 > 0.0)) return set_err(ctx, DACP_E_NUMERIC, "window_labels: no levels near 0 in realisation " + std::to_string(r));
-    labels[2 * r] = std::log(e_bs[r] / sig);
+    labels[2 * r] = std::log(e_bs[r] / (sig * std::sqrt(2.0 * hams[r]->L * M_LN2)));
     labels[2 * r + 1] = std::log(rho0 * std::sqrt(2.0 * M_PI) * sig / D);
   }
   return DACP_OK;
@@ -1915,7 +1933,7 @@ dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, 
   DACP_TRY(dacp_mlp_predict(ctx, model, 1, f, y));
   const double sig = std::sqrt(h->sum_sq);
   const double D = static_cast<double>(h->D);
-  double e_b = std::min((1.0 + bound_margin) * sig * std::exp(y[0]), h->sum_abs);
+  double e_b = std::min((1.0 + bound_margin) * sig * std::sqrt(2.0 * h->L * M_LN2) * std::exp(y[0]), h->sum_abs);
   const double rho0 = D * std::exp(y[1]) / (std::sqrt(2.0 * M_PI) * sig);
   const double n_w = std::min(D, std::ceil((o.window_ratio > 0.0 ? o.window_ratio : 2.2) * N));
   double a = std::min(0.95 * e_b, n_w / (2.0 * rho0));

@@ -606,7 +606,7 @@ def test_window_labels_match_the_estimators(ctx):
     for (L, t), h, (y0, y1) in zip(terms_l, hams, lab):
         sig = np.sqrt(hamiltonian.sum_sq_coeff(t))
         eb, _, _ = B.dacp_spectral_bound(ctx, h, steps=80, seed=0x5BD1E995)
-        assert abs(y0 - np.log(eb / sig)) <= 1e-9
+        assert abs(y0 - np.log(eb / (sig * np.sqrt(2 * L * np.log(2))))) <= 1e-9
         ev = central.full_spectrum_dense(L, t)
         assert eb >= np.abs(ev).max()
         D = 1 << L
@@ -645,7 +645,7 @@ def test_central_eigs_learned_falls_back_on_a_bad_model(ctx):
     Lanczos / KPM path redoes the call, with the same answer."""
     rng = np.random.default_rng(0)
     X = rng.standard_normal((64, B.WINDOW_FEATURES))
-    Y = np.stack([np.full(64, -3.0), np.zeros(64)], axis=1) + 1e-3 * rng.standard_normal((64, 2))
+    Y = np.stack([np.full(64, -4.0), np.zeros(64)], axis=1) + 1e-3 * rng.standard_normal((64, 2))
     net = B.Mlp(ctx, seed=2)
     B.dacp_mlp_train(ctx, net, X, Y, epochs=50, batch=64, lr=1e-2)
     L, N = 10, 60
