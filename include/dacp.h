@@ -106,6 +106,8 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  * Results agree for every setting up to the rounding order of each element's sum.
  * Returns DACP_E_INVALID for an unknown key or a value out of range. */
 dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value);
+/* Current value of a tuning knob (same keys as dacp_tune); value: host. */
+dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value);
 /* Library version string (static storage). */
 const char *dacp_version(void);
 
@@ -291,6 +293,14 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
  * if some realisation stays short after its retry (the others are still filled in). */
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports);
+
+/* Autotuner of the evolution recurrence for this Hamiltonian and block width b: times `steps`
+ * evolution steps of one column group for every group width (powers of two up to min(b, 16)),
+ * workgroup size (512, 1024), fused tile (4096, 8192 elements) and high-tile row count
+ * (automatic, 1, 2), at the real state length, and keeps the fastest in ctx (the "group",
+ * "rec_threads", "rec_tile", "rec_hi_w" knobs).  best_group and best_us_per_column_step (host,
+ * may be NULL) get the winner's group width and its time per column and step. */
+dacp_status dacp_autotune(dacp_ctx ctx, dacp_ham h, int b, int steps, int *best_group, double *best_us_per_column_step);
 
 /* ------------------------------------------------------- learned window */
 

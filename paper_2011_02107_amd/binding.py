@@ -125,6 +125,7 @@ SIGNATURES = {
     "dacp_set_stream": (ctypes.c_int, [_vp, _vp]),
     "dacp_set_tile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "dacp_tune": (ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int]),
+    "dacp_tune_get": (ctypes.c_int, [_vp, ctypes.c_char_p, _ip]),
     "dacp_version": (ctypes.c_char_p, []),
     "dacp_build_hamiltonian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "dacp_free_hamiltonian": (None, [_vp]),
@@ -144,6 +145,7 @@ SIGNATURES = {
     ),
     "dacp_default_opts": (None, [ctypes.POINTER(Opts)]),
     "dacp_central_eigs": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)]),
+    "dacp_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _ip, _dp]),
     "dacp_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "dacp_mlp_free": (None, [_vp]),
     "dacp_mlp_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _ip]),
@@ -224,6 +226,11 @@ class Context:
 
     def tune(self, key, value):
         self.check(self.lib.dacp_tune(self.handle, key.encode(), int(value)))
+
+    def tune_get(self, key):
+        v = ctypes.c_int()
+        self.check(self.lib.dacp_tune_get(self.handle, key.encode(), ctypes.byref(v)))
+        return v.value
 
     def close(self):
         if self.handle:
@@ -479,3 +486,11 @@ def dacp_central_eigs_learned(ctx, ham, mlp, N, bound_margin=0.05, opts=None, ra
         ctx.check(st)
     n = n_out.value if st == 0 else 0
     return eigs[:n], errs[:n], rep.as_dict(), st
+
+
+def dacp_autotune(ctx, ham, b=64, steps=64):
+    """Returns (best group width, microseconds per column and step); the context keeps the winner."""
+    g = ctypes.c_int()
+    us = ctypes.c_double()
+    ctx.check(ctx.lib.dacp_autotune(ctx.handle, ham.handle, int(b), int(steps), ctypes.byref(g), ctypes.byref(us)))
+    return g.value, us.value

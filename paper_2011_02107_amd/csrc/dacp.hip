@@ -1005,6 +1005,26 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
   return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
 }
 
+dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
+  if (!ctx || !key || !value) return DACP_E_INVALID;
+  const std::string k(key);
+  if (k == "tile") *value = ctx->tile_elems;
+  else if (k == "pass_tile") *value = ctx->pass_tile_elems;
+  else if (k == "two_pass_L") *value = ctx->two_pass_min_L;
+  else if (k == "fused") *value = ctx->fused_rec;
+  else if (k == "dc") *value = ctx->dc_min_n;
+  else if (k == "group") *value = ctx->group_default;
+  else if (k == "filter_group_f64") *value = ctx->filter_group_f64;
+  else if (k == "filter_group_f32") *value = ctx->filter_group_f32;
+  else if (k == "rec_hi_w") *value = ctx->rec_hi_w;
+  else if (k == "rec_threads") *value = ctx->rec_threads;
+  else if (k == "rec_tile") *value = ctx->rec_tile_elems;
+  else if (k == "rec_persist") *value = ctx->rec_persist;
+  else if (k == "batch_workers") *value = ctx->batch_workers;
+  else return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
+  return DACP_OK;
+}
+
 dacp_status dacp_set_stream(dacp_ctx ctx, void *hip_stream) {
   if (!ctx) return DACP_E_INVALID;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
@@ -1966,6 +1986,75 @@ dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, 
   if (n_out) *n_out = got;
   if (report) *report = r1;
   return st;
+}
+
+dacp_status dacp_autotune(dacp_ctx ctx, dacp_ham h, int b, int steps, int *best_group, double *best_us_per_column_step) {
+  if (!ctx || !h || b < 1 || steps < 4) return set_err(ctx, DACP_E_INVALID, "autotune: need b >= 1, steps >= 4");
+  const int64_t D = h->D;
+  struct Cand {
+    int group, threads, tile, hi_w;
+  };
+  std::vector<Cand> cands;
+  for (int g = 1; g <= std::min(b, 16); g *= 2)
+    for (int th : {512, 1024})
+      for (int tile : {4096, 8192})
+        for (int w : {0, 1, 2}) cands.push_back({g, th, tile, w});
+  const int saved_threads = ctx->rec_threads, saved_tile = ctx->rec_tile_elems, saved_w = ctx->rec_hi_w;
+  // unit start columns; E_b = sum |c| >= ||H||; a_r = pi / steps puts the first sample pair at k = steps
+  DevBuf psi, V;
+  const int gmax = std::min(b, 16);
+  DACP_HIP(ctx, psi.alloc(static_cast<size_t>(D) * gmax * sizeof(double)));
+  DACP_HIP(ctx, V.alloc(static_cast<size_t>(D) * 3 * gmax * sizeof(double)));
+  double best = INFINITY;
+  Cand bc = cands.front();
+  int g_ready = 0;
+  for (const Cand &c : cands) {
+    if (c.group != g_ready) {  // a [D][group] start block for this width
+      DACP_HIP(ctx, dacp::launch_philox_gauss(psi.as<double>(), D, c.group, 12345, ctx->stream));
+      DACP_TRY(normalise_cols(ctx, psi.as<double>(), D, c.group));
+      g_ready = c.group;
+    }
+    ctx->rec_threads = c.threads;
+    ctx->rec_tile_elems = c.tile;
+    ctx->rec_hi_w = c.hi_w;
+    dacp_basis_params bp;
+    bp.e_bound = h->sum_abs;
+    bp.a = h->sum_abs * M_PI / steps;
+    bp.n = 1;
+    bp.b = c.group;
+    bp.group = c.group;
+    if (!(bp.a < bp.e_bound)) continue;
+    EvolStats es;
+    int m = 0;
+    // first call loads the kernels and the flip tables, the second is timed
+    dacp_status st = run_basis(ctx, h, &bp, psi.as<double>(), V.as<double>(), 3 * c.group, &m, &es);
+    if (st == DACP_OK) st = run_basis(ctx, h, &bp, psi.as<double>(), V.as<double>(), 3 * c.group, &m, &es);
+    if (st != DACP_OK || es.steps < 1) {
+      ctx->err.clear();
+      continue;
+    }
+    const double us = es.kernel_ms * 1e3 / (static_cast<double>(es.steps) * c.group);
+    vlog("autotune: group %d threads %d tile %d hi_w %d: %.3f us per column-step", c.group, c.threads, c.tile, c.hi_w,
+         us);
+    if (us < best) {
+      best = us;
+      bc = c;
+    }
+  }
+  // keep the winner
+  if (!std::isfinite(best)) {
+    ctx->rec_threads = saved_threads;
+    ctx->rec_tile_elems = saved_tile;
+    ctx->rec_hi_w = saved_w;
+    return set_err(ctx, DACP_E_NUMERIC, "autotune: no candidate ran");
+  }
+  ctx->group_default = bc.group;
+  ctx->rec_threads = bc.threads;
+  ctx->rec_tile_elems = bc.tile;
+  ctx->rec_hi_w = bc.hi_w;
+  if (best_group) *best_group = bc.group;
+  if (best_us_per_column_step) *best_us_per_column_step = best;
+  return DACP_OK;
 }
 
 }  // extern "C"

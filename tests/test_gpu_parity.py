@@ -655,3 +655,25 @@ def test_central_eigs_learned_falls_back_on_a_bad_model(ctx):
     eigs, errs, rep, st = B.dacp_central_eigs_learned(ctx, ham, net, N, bound_margin=0.0, opts=B.default_opts(b=8))
     assert rep["model_used"] == 1 and rep["model_fallback"] == 1
     _check_central(eigs, ref, norm, N)
+
+
+def test_autotune_keeps_a_working_configuration(ctx):
+    """The autotuner times every evolution configuration at the real shape and keeps the fastest;
+    the basis built with the kept configuration still matches the oracle."""
+    L, b, n = 16, 16, 1
+    terms = inputs.ising_chain(L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    try:
+        g, us = B.dacp_autotune(ctx, ham, b=b, steps=32)
+        assert g in (1, 2, 4, 8, 16) and us > 0
+        eb = 1.01 * (1.723 * L)
+        a = 0.45 * eb
+        psi = np.random.default_rng(3).standard_normal((1 << L, b))
+        psi /= np.linalg.norm(psi, axis=0)
+        ref, ks = chebyshev.chebyshev_basis(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, n)
+        V = torch.zeros((1 << L, b * (2 * n + 1)), dtype=torch.float64, device=DEV)
+        B.dacp_basis(ctx, ham, to_dev(psi), V, eb, a, n)
+        assert np.abs(host(V) - ref).max() < 1e-15 * max(ks) + 1e-12
+    finally:
+        for k, v in (("group", 8), ("rec_threads", 1024), ("rec_tile", 8192), ("rec_hi_w", 0)):
+            ctx.tune(k, v)
