@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
     ap.add_argument("--window-ratio", type=float, default=None)
+    ap.add_argument("--basis-ratio", type=float, default=None)
     ap.add_argument("--tail", type=float, default=None, help="FP64 tail fraction of the filter (tuned mode)")
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -57,12 +58,14 @@ def opts_for(args, wl):
     if args.mode == "plain":
         o = B.default_opts(b=wl["b"], kfac=18.0, window_ratio=2.2, precision=B.DACP_F64, group=args.group)
     else:
-        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.2, basis_ratio=1.25, precision=B.DACP_F32,
+        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.2, basis_ratio=1.1, precision=B.DACP_F32,
                            fp64_tail_frac=0.3, group=args.group)
     if args.kfac:
         o.kfac = args.kfac
     if args.window_ratio:
         o.window_ratio = args.window_ratio
+    if args.basis_ratio:
+        o.basis_ratio = args.basis_ratio
     if args.tail is not None:
         o.fp64_tail_frac = args.tail
     return o

@@ -116,6 +116,78 @@ __global__ __launch_bounds__(256) void k_qupdate(double *Qc, int64_t ldq, const 
   for (int j = k + 1 + lane; j < n; j += 64) q[j] -= s * v[j];
 }
 
+// ---- panel (blocked) tridiagonalisation: the rank-2 updates of a panel of kTB reflectors are
+// deferred and applied to the trailing matrix as two GEMMs at the panel's end.  Within the panel,
+// row k is brought up to date before its reflector is formed, and the matrix-vector product uses
+// the trailing matrix as of the panel start, corrected by the panel's V and W:
+//   p = beta (A v - V (W^T v) - W (V^T v)).
+// V and W are n x kTB row-major (row = global index, column = reflector within the panel).
+constexpr int kTB = 32;
+
+// A[k][c] -= sum_(i<j) V[k][i] W[c][i] + W[k][i] V[c][i]  for c >= k.
+__global__ __launch_bounds__(256) void k_panel_row(double *A, int64_t ld, int n, int k, const double *V,
+                                                   const double *W, int j) {
+  const int c = k + blockIdx.x * 256 + threadIdx.x;
+  if (c >= n || j == 0) return;
+  const double *vk = V + static_cast<int64_t>(k) * kTB, *wk = W + static_cast<int64_t>(k) * kTB;
+  const double *vc = V + static_cast<int64_t>(c) * kTB, *wc = W + static_cast<int64_t>(c) * kTB;
+  double s = 0.0;
+  for (int i = 0; i < j; ++i) s += vk[i] * wc[i] + wk[i] * vc[i];
+  A[static_cast<int64_t>(k) * ld + c] -= s;
+}
+
+// xy[i] = sum_r W[k+1+r][i] v[r], xy[kTB + i] = sum_r V[k+1+r][i] v[r]  (i < j); one block per i.
+__global__ __launch_bounds__(256) void k_panel_dots(const double *V, const double *W, int n, int k, int j,
+                                                    const double *v, double *xy) {
+  __shared__ double red[256];
+  const int i = blockIdx.x % kTB, which = blockIdx.x / kTB;
+  if (i >= j) return;
+  const double *P = which == 0 ? W : V;
+  const int m = n - k - 1;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < m; r += 256) s += P[static_cast<int64_t>(k + 1 + r) * kTB + i] * v[r];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) xy[which * kTB + i] = red[0];
+}
+
+// p[r] -= beta sum_(i<j) (V[k+1+r][i] x_i + W[k+1+r][i] y_i)
+__global__ __launch_bounds__(256) void k_panel_corr(double *p, const double *V, const double *W, int n, int k, int j,
+                                                    const double *xy, const double *betas) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int m = n - k - 1;
+  const double beta = betas[k];
+  if (r >= m || j == 0 || beta == 0.0) return;
+  const double *vr = V + static_cast<int64_t>(k + 1 + r) * kTB, *wr = W + static_cast<int64_t>(k + 1 + r) * kTB;
+  double s = 0.0;
+  for (int i = 0; i < j; ++i) s += vr[i] * xy[i] + wr[i] * xy[kTB + i];
+  p[r] -= beta * s;
+}
+
+// V[:, j] = (0 .. 0, v), W[:, j] = (0 .. 0, w) with v, w starting at global index k + 1.
+__global__ __launch_bounds__(256) void k_panel_store(double *V, double *W, int n, int k, int j, const double *v,
+                                                     const double *w, const double *betas) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= n) return;
+  const bool in = row > k && betas[k] != 0.0;
+  V[static_cast<int64_t>(row) * kTB + j] = in ? v[row - k - 1] : 0.0;
+  W[static_cast<int64_t>(row) * kTB + j] = in ? w[row - k - 1] : 0.0;
+}
+
+// Rows of V^T for reflectors k0 .. k0 + kb - 1: vt[j][c] = v_(k0+j)[c] (stored in A[k0 + j][c] for
+// c > k0 + j), zero elsewhere.
+__global__ void k_build_vt(const double *A, int64_t ld, int n, int k0, int kb, double *vt) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(kb) * n) return;
+  const int j = static_cast<int>(e / n), c = static_cast<int>(e - static_cast<int64_t>(j) * n);
+  const int k = k0 + j;
+  vt[e] = (c > k) ? A[static_cast<int64_t>(k) * ld + c] : 0.0;
+}
+
 __global__ void k_set_identity(double *Q, int64_t ldq, int n) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= static_cast<int64_t>(n) * n) return;
@@ -332,7 +404,47 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   DACP_HIP(ctx, hipMalloc(&db, sizeof(double) * n));
   DACP_HIP(ctx, hipMemsetAsync(db, 0, sizeof(double) * n, st));
   const int report_every = std::max(1, n / 4);
-  for (int k = 0; k < n - 2; ++k) {
+  if (n >= 8 * kTB) {
+    DevBuf pv, pw, pxy;
+    DACP_HIP(ctx, pv.alloc(sizeof(double) * n * kTB));
+    DACP_HIP(ctx, pw.alloc(sizeof(double) * n * kTB));
+    DACP_HIP(ctx, pxy.alloc(sizeof(double) * 2 * kTB));
+    double *V = pv.as<double>(), *W = pw.as<double>();
+    const int nred = n - 2;
+    for (int p0 = 0; p0 < nred; p0 += kTB) {
+      const int nbp = std::min(kTB, nred - p0);
+      if (verbose() && p0 > 0 && (p0 / kTB) % std::max(1, report_every / kTB) == 0) {
+        (void)hipStreamSynchronize(st);
+        vlog("eigensolver n=%d: tridiagonalised %d columns (panels)", n, p0);
+      }
+      for (int j = 0; j < nbp; ++j) {
+        const int k = p0 + j;
+        const int m = n - k - 1;
+        hipLaunchKernelGGL(k_panel_row, dim3((n - k + 255) / 256), dim3(256), 0, st, A, ld, n, k, V, W, j);
+        hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, st, A, ld, n, k, dv, dd, de, db);
+        hipLaunchKernelGGL(k_symv, dim3((m + 3) / 4), dim3(256), 0, st, A, ld, n, k, dv, db, dp);
+        if (j > 0) {
+          hipLaunchKernelGGL(k_panel_dots, dim3(2 * kTB), dim3(256), 0, st, V, W, n, k, j, dv, pxy.as<double>());
+          hipLaunchKernelGGL(k_panel_corr, dim3((m + 255) / 256), dim3(256), 0, st, dp, V, W, n, k, j,
+                             pxy.as<double>(), db);
+        }
+        hipLaunchKernelGGL(k_wvec, dim3(1), dim3(1024), 0, st, dp, dv, db, n, k);
+        hipLaunchKernelGGL(k_panel_store, dim3((n + 255) / 256), dim3(256), 0, st, V, W, n, k, j, dv, dp, db);
+      }
+      // trailing matrix after the panel: A22 -= V W^T + W V^T on rows / columns >= t
+      const int t = p0 + nbp;
+      const int mt = n - t;
+      if (mt > 0) {
+        double *a22 = A + static_cast<int64_t>(t) * ld + t;
+        const double *Vt = V + static_cast<int64_t>(t) * kTB, *Wt = W + static_cast<int64_t>(t) * kTB;
+        DACP_HIP(ctx, launch_dgemm(0, 1, mt, mt, nbp, -1.0, Vt, kTB, Wt, kTB, 1.0, a22, ld, 0, st));
+        DACP_HIP(ctx, launch_dgemm(0, 1, mt, mt, nbp, -1.0, Wt, kTB, Vt, kTB, 1.0, a22, ld, 0, st));
+      }
+    }
+    DACP_HIP(ctx, hipGetLastError());
+    DACP_HIP(ctx, hipStreamSynchronize(st));  // the panel buffers are released at scope end
+  }
+  for (int k = (n >= 8 * kTB) ? n - 2 : 0; k < n - 2; ++k) {
     const int m = n - k - 1;
     if (verbose() && k > 0 && k % report_every == 0) {
       (void)hipStreamSynchronize(st);
@@ -361,9 +473,57 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   if (Zrows) {
     const int64_t nn = static_cast<int64_t>(n) * n;
     hipLaunchKernelGGL(k_set_identity, dim3((nn + 255) / 256), dim3(256), 0, st, Zrows, (int64_t)n, n);
-    for (int k = n - 3; k >= 0; --k) {
-      const int rows = n - k - 1;
-      hipLaunchKernelGGL(k_qupdate, dim3((rows + 3) / 4), dim3(256), 0, st, Zrows, (int64_t)n, A, ld, n, k, db);
+    constexpr int kQB = 64;  // reflectors per compact-WY block
+    if (n >= 4 * kQB) {
+      // Qc <- Qc P_k for k = n-3 .. 0, a block of reflectors at a time (last block first):
+      // P_k0 ... P_(k0+kb-1) = I - V T V^T (T upper triangular, T_jj = beta_j,
+      // T[0:j, j] = -beta_j T[0:j, 0:j] (V[:, 0:j]^T v_j)), so Qc <- Qc - (Qc V) T^T V^T on the rows and
+      // columns after k0 (the others are untouched identity rows / zero columns of V).
+      const int nref = n - 2;
+      std::vector<double> beta(n), g(kQB * kQB), T(kQB * kQB);
+      DACP_TRY(to_host(ctx, beta.data(), db, sizeof(double) * n));
+      DevBuf vt, gd, td, w1, w2;
+      DACP_HIP(ctx, vt.alloc(sizeof(double) * kQB * n));
+      DACP_HIP(ctx, gd.alloc(sizeof(double) * kQB * kQB));
+      DACP_HIP(ctx, td.alloc(sizeof(double) * kQB * kQB));
+      DACP_HIP(ctx, w1.alloc(sizeof(double) * kQB * n));
+      DACP_HIP(ctx, w2.alloc(sizeof(double) * kQB * n));
+      for (int k0 = ((nref - 1) / kQB) * kQB; k0 >= 0; k0 -= kQB) {
+        const int kb = std::min(kQB, nref - k0);
+        const int c0 = k0 + 1, R = n - c0;
+        hipLaunchKernelGGL(k_build_vt, dim3(static_cast<unsigned>((static_cast<int64_t>(kb) * n + 255) / 256)),
+                           dim3(256), 0, st, A, ld, n, k0, kb, vt.as<double>());
+        DACP_HIP(ctx, hipGetLastError());
+        // G = V^T V over the columns after k0
+        DACP_HIP(ctx, launch_dgemm(0, 1, kb, kb, R, 1.0, vt.as<double>() + c0, n, vt.as<double>() + c0, n, 0.0,
+                                   gd.as<double>(), kb, 0, st));
+        DACP_TRY(to_host(ctx, g.data(), gd.p, sizeof(double) * kb * kb));
+        std::fill(T.begin(), T.end(), 0.0);
+        for (int j = 0; j < kb; ++j) {
+          const double bj = beta[k0 + j];
+          for (int i = 0; i < j; ++i) {
+            double acc = 0.0;
+            for (int q = i; q < j; ++q) acc += T[i * kb + q] * g[q * kb + j];
+            T[i * kb + j] = -bj * acc;
+          }
+          T[j * kb + j] = bj;
+        }
+        DACP_TRY(to_device(ctx, td.p, T.data(), sizeof(double) * kb * kb));
+        double *qs = Zrows + static_cast<int64_t>(c0) * n + c0;
+        // W1 = Qc_sub V_sub (R x kb), W2 = W1 T^T, Qc_sub -= W2 V_sub^T
+        DACP_HIP(ctx, launch_dgemm(0, 1, R, kb, R, 1.0, qs, n, vt.as<double>() + c0, n, 0.0, w1.as<double>(), kb, 0,
+                                   st));
+        DACP_HIP(ctx, launch_dgemm(0, 1, R, kb, kb, 1.0, w1.as<double>(), kb, td.as<double>(), kb, 0.0,
+                                   w2.as<double>(), kb, 0, st));
+        DACP_HIP(ctx, launch_dgemm(0, 0, R, R, kb, -1.0, w2.as<double>(), kb, vt.as<double>() + c0, n, 1.0, qs, n,
+                                   0, st));
+      }
+      DACP_HIP(ctx, hipStreamSynchronize(st));  // vt, w1, w2 are released at scope end
+    } else {
+      for (int k = n - 3; k >= 0; --k) {
+        const int rows = n - k - 1;
+        hipLaunchKernelGGL(k_qupdate, dim3((rows + 3) / 4), dim3(256), 0, st, Zrows, (int64_t)n, A, ld, n, k, db);
+      }
     }
     DACP_HIP(ctx, hipGetLastError());
     if (verbose()) (void)hipStreamSynchronize(st);
