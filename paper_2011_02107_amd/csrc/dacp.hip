@@ -678,12 +678,36 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
   const int64_t D = h->D;
   if (m < 1 || ldv < m || ld < m || !V || !S || !P) return set_err(ctx, DACP_E_INVALID, "project: bad sizes/pointers");
   hipStream_t s = ctx->stream;
+  Timer ts(ctx);
+  if (verbose()) ts.start();
   DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, s));
   DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
+  if (verbose()) {
+    const double ms = ts.stop_ms();
+    vlog("projection: S = V^T V (m = %d) %.1f ms, %.1f TFLOP/s (upper tiles)", m, ms,
+         static_cast<double>(D) * m * (m + 128.0) / (ms * 1e-3) / 1e12);
+    ts.start();
+  }
   const int cw = std::min(m, 512);
   DevBuf wbuf;
   DACP_HIP(ctx, wbuf.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
   double *W = wbuf.as<double>();
+  // The early chunks have few output tiles against a K of 2^L: split K so that every chunk
+  // launches at least ~2 workgroups per compute unit.
+  auto splits_for = [&](int rows, int cols) {
+    const int64_t tiles = ((rows + 127) / 128) * static_cast<int64_t>((cols + 127) / 128);
+    int sp = static_cast<int>(std::min<int64_t>(64, (2 * ctx->num_cus + tiles - 1) / tiles));
+    if (D < 64 * 1024) sp = 1;
+    return std::max(1, sp);
+  };
+  size_t work_elems = 0;
+  for (int c0 = 0; c0 < m; c0 += cw) {
+    const int c1 = std::min(m, c0 + cw);
+    const int sp = splits_for(c1, c1 - c0);
+    if (sp > 1) work_elems = std::max(work_elems, static_cast<size_t>(sp) * c1 * (c1 - c0));
+  }
+  DevBuf work;
+  if (work_elems) DACP_HIP(ctx, work.alloc(work_elems * sizeof(double)));
   for (int c0 = 0; c0 < m; c0 += cw) {
     const int c1 = std::min(m, c0 + cw);
     const int w = c1 - c0;
@@ -692,9 +716,15 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
       dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + (s0 - c0), cw, 1.0);
       if (st) return st;
     }
-    DACP_HIP(ctx, dacp::launch_dgemm(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, 0, s));
+    const int sp = splits_for(c1, w);
+    if (sp > 1)
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, sp,
+                                              work.as<double>(), s));
+    else
+      DACP_HIP(ctx, dacp::launch_dgemm(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, 0, s));
   }
   DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
+  if (verbose()) vlog("projection: P = V^T (H V) in chunks %.1f ms", ts.stop_ms());
   DACP_HIP(ctx, hipStreamSynchronize(s));
   return DACP_OK;
 }

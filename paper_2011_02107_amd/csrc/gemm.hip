@@ -16,10 +16,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128, BN = 128, BK = 16, PADD = 4;
 
+// Split K: workgroup z of the grid's third dimension sums k in [z kchunk, (z + 1) kchunk) and,
+// when `work` is set, stores alpha * (its partial tile) to work[z][M][N] for k_splitk_reduce.
 template <int TA, int TB>
 __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A,
                                                   int64_t lda, const double *B, int64_t ldb, double beta, double *C,
-                                                  int64_t ldc, int upper, int ntn) {
+                                                  int64_t ldc, int upper, int ntn, int64_t kchunk, double *work) {
   __shared__ double As[2][BK][BM + PADD];
   __shared__ double Bs[2][BK][BN + PADD];
   int tm, tn;
@@ -43,42 +45,44 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
   const int wm = (wave >> 1) * 64;
   const int wn = (wave & 1) * 64;
 
+  const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
+  const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
   double ra[8], rb[8];
   auto load_a = [&](int64_t k0) {
     if (TA) {  // A stored K x M
       const int kk = tid >> 4, mm = (tid & 15) * 8;
-      const int64_t k = k0 + kk;
+      const int64_t k = kbeg + k0 + kk;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int64_t m = m0 + mm + q;
-        ra[q] = (k < K && m < M) ? A[k * lda + m] : 0.0;
+        ra[q] = (k < kend && m < M) ? A[k * lda + m] : 0.0;
       }
     } else {  // A stored M x K
       const int mm = tid >> 1, kk = (tid & 1) * 8;
       const int64_t m = m0 + mm;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int64_t k = k0 + kk + q;
-        ra[q] = (k < K && m < M) ? A[m * lda + k] : 0.0;
+        const int64_t k = kbeg + k0 + kk + q;
+        ra[q] = (k < kend && m < M) ? A[m * lda + k] : 0.0;
       }
     }
   };
   auto load_b = [&](int64_t k0) {
     if (!TB) {  // B stored K x N
       const int kk = tid >> 4, nn = (tid & 15) * 8;
-      const int64_t k = k0 + kk;
+      const int64_t k = kbeg + k0 + kk;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int64_t n = n0 + nn + q;
-        rb[q] = (k < K && n < N) ? B[k * ldb + n] : 0.0;
+        rb[q] = (k < kend && n < N) ? B[k * ldb + n] : 0.0;
       }
     } else {  // B stored N x K
       const int nn = tid >> 1, kk = (tid & 1) * 8;
       const int64_t n = n0 + nn;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int64_t k = k0 + kk + q;
-        rb[q] = (k < K && n < N) ? B[n * ldb + k] : 0.0;
+        const int64_t k = kbeg + k0 + kk + q;
+        rb[q] = (k < kend && n < N) ? B[n * ldb + k] : 0.0;
       }
     }
   };
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t nk = (K + BK - 1) / BK;
+  const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
   load_a(0);
   load_b(0);
   store_ab(0);
@@ -148,33 +152,69 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
         const int64_t col = n0 + wn + j * 16 + (lane & 15);
         if (row < M && col < N) {
           double v = alpha * acc[i][j][r];
-          if (beta != 0.0) v += beta * C[row * ldc + col];
-          C[row * ldc + col] = v;
+          if (work) {
+            work[static_cast<int64_t>(blockIdx.z) * M * N + row * N + col] = v;
+          } else {
+            if (beta != 0.0) v += beta * C[row * ldc + col];
+            C[row * ldc + col] = v;
+          }
         }
       }
 }
 
-hipError_t launch_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
-                        int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc, int upper,
-                        hipStream_t s) {
+// C = sum_z work[z] + beta C (fixed order over z)
+__global__ void k_splitk_reduce(const double *work, int splits, int64_t M, int64_t N, double beta, double *C,
+                                int64_t ldc) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t row = e / N, col = e - row * N;
+  double v = 0.0;
+  for (int z = 0; z < splits; ++z) v += work[static_cast<int64_t>(z) * M * N + e];
+  if (beta != 0.0) v += beta * C[row * ldc + col];
+  C[row * ldc + col] = v;
+}
+
+hipError_t launch_dgemm_impl(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                             int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                             int upper, int splits, double *work, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tmc = (M + BM - 1) / BM, tnc = (N + BN - 1) / BN;
+  if (splits < 1 || (splits > 1 && (!work || upper))) return hipErrorInvalidValue;
+  const int64_t kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
   dim3 grid, block(256);
   if (upper) {
     if (M != N) return hipErrorInvalidValue;
     grid = dim3(static_cast<unsigned>(tnc * (tnc + 1) / 2));
   } else {
-    grid = dim3(static_cast<unsigned>(tnc), static_cast<unsigned>(tmc));
+    grid = dim3(static_cast<unsigned>(tnc), static_cast<unsigned>(tmc), static_cast<unsigned>(splits));
   }
   const int ntn = static_cast<int>(tnc);
+  double *wk = splits > 1 ? work : nullptr;
 #define DACP_GEMM_LAUNCH(a_, b_)                                                                                    \
-  hipLaunchKernelGGL((k_dgemm<a_, b_>), grid, block, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, upper, ntn)
+  hipLaunchKernelGGL((k_dgemm<a_, b_>), grid, block, 0, s, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, upper, ntn, \
+                     kchunk, wk)
   if (!transA && !transB) DACP_GEMM_LAUNCH(0, 0);
   else if (!transA && transB) DACP_GEMM_LAUNCH(0, 1);
   else if (transA && !transB) DACP_GEMM_LAUNCH(1, 0);
   else DACP_GEMM_LAUNCH(1, 1);
 #undef DACP_GEMM_LAUNCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(static_cast<unsigned>((M * N + 255) / 256)), dim3(256), 0, s, work, splits,
+                     M, N, beta, C, ldc);
   return hipGetLastError();
+}
+
+hipError_t launch_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                        int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc, int upper,
+                        hipStream_t s) {
+  return launch_dgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, upper, 1, nullptr, s);
+}
+
+hipError_t launch_dgemm_splitk(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
+                               int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                               int splits, double *work, hipStream_t s) {
+  return launch_dgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 0, splits, work, s);
 }
 
 // Copy the upper triangle onto the lower one (tiled through LDS).
