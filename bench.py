@@ -26,9 +26,10 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per evolution launch measured with the FETCH_SIZE and WRITE_SIZE counters (each scaled by
 # its reading on a 256 MiB device copy), for the kernel build and launch shape named by the key:
 # (workload, kernel pair, column group).  Reported as roofline.traffic only for that configuration.
-EVOLUTION_KERNELS = "k_rec_lo/k_rec_hi v3"
-# key: (workload, kernel build, group, threads, fused tile, high-tile rows knob)
-MEASURED_TRAFFIC = {("chain_L20_N5000", EVOLUTION_KERNELS, 8, 1024, 8192, 0): 275.17e6}
+EVOLUTION_KERNELS = "k_rec_lo/k_rec_hi v4"
+# key: (workload, kernel build, group, threads, fused tile, high-tile rows knob, XCD tile order knob)
+# (At group 8 and tile 8192 the automatic high-tile rows knob 0 resolves to W = 1: same launch.)
+MEASURED_TRAFFIC = {("chain_L20_N5000", EVOLUTION_KERNELS, 8, 1024, 8192, w, 2): 279.75e6 for w in (0, 1)}
 
 
 def parse():
@@ -331,7 +332,8 @@ def main():
             "evol_steps": rep["evol_steps"],
             "acceptance": "Kato-Temple residual estimate <= 1e-10 ||H|| (no oracle at this size)",
             "autotune": tuned,
-            "evolution_kernel_config": {k: ctx.tune_get(k) for k in ("group", "rec_threads", "rec_tile", "rec_hi_w")},
+            "evolution_kernel_config": {k: ctx.tune_get(k) for k in ("group", "rec_threads", "rec_tile", "rec_hi_w",
+                                                                     "rec_xcd")},
         },
         "roofline": {
             "bound": "hbm",
@@ -341,7 +343,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": MEASURED_TRAFFIC.get((args.workload, EVOLUTION_KERNELS, g, ctx.tune_get("rec_threads"),
-                                             ctx.tune_get("rec_tile"), ctx.tune_get("rec_hi_w"))),
+                                             ctx.tune_get("rec_tile"), ctx.tune_get("rec_hi_w"),
+                                             ctx.tune_get("rec_xcd"))),
             "avg_launch_ms": evol_launch_ms,
             "bytes_per_launch": bytes_per_launch,
         },

@@ -96,6 +96,9 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "rec_threads" fused recurrence: threads per workgroup, 512 or 1024 (default 1024)
  *   "rec_persist" fused recurrence: 0 = one workgroup per tile (default); n = 1..8 persistent
  *                 workgroups per compute unit that prefetch their next tile
+ *   "rec_xcd"     fused recurrence tile order, bit 0 for the low pass and bit 1 for the high
+ *                 pass: set = each of the 8 XCDs takes a contiguous eighth of the tiles, clear =
+ *                 tiles dealt round-robin in launch order (default 2: high pass only)
  *   "batch_workers" host threads finishing the realisations of dacp_central_eigs_batched (1..64, default 8)
  *   "group"       evolution column-group width when L >= 15 (power of two, default 8)
  *   "filter_group_f64", "filter_group_f32"

@@ -223,6 +223,8 @@ bool two_pass_plan(dacp_ctx ctx, dacp_ham h, int b, int &lo_bits, int &W) {
 bool fused_plan(dacp_ctx ctx, dacp_ham h, int g, int &lo_bits, int &W) {
   if (!ctx->fused_rec || ctx->two_pass_min_L <= 0 || h->L < ctx->two_pass_min_L) return false;
   if ((g & (g - 1)) || g < 2) return false;
+  // the kernels address a block with 32-bit byte offsets
+  if (h->D * g * static_cast<int64_t>(sizeof(double)) >= (int64_t(1) << 32)) return false;
   const int L = h->L;
   const int64_t P = std::min<int64_t>(ctx->rec_tile_elems, 8192);
   const int64_t nt = ctx->rec_threads;
@@ -611,14 +613,14 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
           ra.nflip = so.nhi;
           ra.nplain = so.nhi_plain;
           ra.ntiles = (1 << lo_bits) / hw;
-          ra.xcd_remap = (ra.ntiles % 8 == 0) ? 1 : 0;
+          ra.xcd_remap = ((ctx->rec_xcd & 2) && ra.ntiles % 8 == 0) ? 1 : 0;
           DACP_HIP(ctx, dacp::launch_rec_hi<double>(ra, ctx->stream));
         } else {
           ra.flips = so.lo;
           ra.nflip = so.nlo;
           ra.nplain = so.nlo_plain;
           ra.ntiles = static_cast<int>(D >> lo_bits);
-          ra.xcd_remap = (ra.ntiles % 8 == 0) ? 1 : 0;
+          ra.xcd_remap = ((ctx->rec_xcd & 1) && ra.ntiles % 8 == 0) ? 1 : 0;
           DACP_HIP(ctx, dacp::launch_rec_lo<double>(ra, ctx->stream));
         }
         ++launches;
@@ -1017,6 +1019,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->batch_workers = value;
     return DACP_OK;
   }
+  if (k == "rec_xcd") {
+    if (value < 0 || value > 3) return set_err(ctx, DACP_E_INVALID, "rec_xcd: 0..3 (bit 0 low pass, bit 1 high pass)");
+    ctx->rec_xcd = value;
+    return DACP_OK;
+  }
   if (k == "rec_persist") {
     if (value < 0 || value > 8) return set_err(ctx, DACP_E_INVALID, "rec_persist: 0..8 workgroups per CU");
     ctx->rec_persist = value;
@@ -1050,6 +1057,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "rec_threads") *value = ctx->rec_threads;
   else if (k == "rec_tile") *value = ctx->rec_tile_elems;
   else if (k == "rec_persist") *value = ctx->rec_persist;
+  else if (k == "rec_xcd") *value = ctx->rec_xcd;
   else if (k == "batch_workers") *value = ctx->batch_workers;
   else return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
   return DACP_OK;

@@ -24,19 +24,33 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
                                                   int64_t ldc, int upper, int ntn, int64_t kchunk, double *work) {
   __shared__ double As[2][BK][BM + PADD];
   __shared__ double Bs[2][BK][BN + PADD];
-  int tm, tn;
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so workgroup
+  // b = 8 q + x runs on XCD x.  Each XCD takes whole 8 x 8 blocks of output tiles (super-block
+  // s = 8 (q / 64) + x, tile q % 64 inside it): the tiles resident on one XCD at a time share 8 row
+  // panels of op(A) and 8 column panels of op(B) in its L2.  Upper mode enumerates the super-blocks
+  // with block row <= block column and idles the tiles below the diagonal.
+  const int tmc = static_cast<int>((M + BM - 1) / BM);
+  const int sbm = (tmc + 7) / 8, sbn = (ntn + 7) / 8;
+  const int bid = blockIdx.x;
+  const int slot = bid >> 3, x = bid & 7;
+  int sb = (slot >> 6) * 8 + x;
+  const int t64 = slot & 63;
+  int si, sj;
   if (upper) {
-    int t = blockIdx.x;
-    tm = 0;
-    while (t >= ntn - tm) {
-      t -= ntn - tm;
-      ++tm;
+    si = 0;
+    while (si < sbm && sb >= sbn - si) {
+      sb -= sbn - si;
+      ++si;
     }
-    tn = tm + t;
+    if (si >= sbm) return;
+    sj = si + sb;
   } else {
-    tm = blockIdx.y;
-    tn = blockIdx.x;
+    if (sb >= sbm * sbn) return;
+    si = sb / sbn;
+    sj = sb - si * sbn;
   }
+  const int tm = si * 8 + (t64 >> 3), tn = sj * 8 + (t64 & 7);
+  if (tm >= tmc || tn >= ntn || (upper && tm > tn)) return;
   const int64_t m0 = static_cast<int64_t>(tm) * BM;
   const int64_t n0 = static_cast<int64_t>(tn) * BN;
   const int tid = threadIdx.x;
@@ -180,14 +194,14 @@ hipError_t launch_dgemm_impl(int transA, int transB, int64_t M, int64_t N, int64
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tmc = (M + BM - 1) / BM, tnc = (N + BN - 1) / BN;
   if (splits < 1 || (splits > 1 && (!work || upper))) return hipErrorInvalidValue;
+  if (upper && M != N) return hipErrorInvalidValue;
   const int64_t kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
-  dim3 grid, block(256);
-  if (upper) {
-    if (M != N) return hipErrorInvalidValue;
-    grid = dim3(static_cast<unsigned>(tnc * (tnc + 1) / 2));
-  } else {
-    grid = dim3(static_cast<unsigned>(tnc), static_cast<unsigned>(tmc), static_cast<unsigned>(splits));
-  }
+  // super-blocks of 8 x 8 tiles, dealt 8 at a time (one per XCD), 64 workgroups each
+  const int64_t sbm = (tmc + 7) / 8, sbn = (tnc + 7) / 8;
+  const int64_t nsb = upper ? sbn * (sbn + 1) / 2 : sbm * sbn;
+  const int64_t nblocks = 8 * 64 * ((nsb + 7) / 8);
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid(static_cast<unsigned>(nblocks), 1, static_cast<unsigned>(splits)), block(256);
   const int ntn = static_cast<int>(tnc);
   double *wk = splits > 1 ? work : nullptr;
 #define DACP_GEMM_LAUNCH(a_, b_)                                                                                    \

@@ -82,7 +82,7 @@ struct HiArgs {
 //   hi coset kernel: T_new = P + alpha Hi T_cur       ;  P <- alpha Hi T_new - T_cur
 // T_new is written over the buffer of the term before T_cur; P is updated in place.
 // The blocks are contiguous [D][b] with b * sizeof(T) a multiple of 16 bytes and
-// D * b * sizeof(T) < 2^35 (32-bit 16-byte-vector offsets).
+// D * b * sizeof(T) < 2^32 (32-bit byte offsets from the block's base).
 template <typename T>
 struct RecArgs {
   const T *tcur;
@@ -230,6 +230,7 @@ struct dacp_ctx_s {
   int rec_threads = 1024;      // fused recurrence: threads per workgroup (512 or 1024)
   int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
+  int rec_xcd = 2;             // fused recurrence: XCD-contiguous tile order, bit 0 low pass, bit 1 high pass
   int num_cus = 256;           // compute units of the device
   int batch_workers = 8;       // host threads (each with its own stream) finishing batched realisations
   int filter_group_f64 = 8;    // filter column-group width for L >= 15, FP64 recurrence

@@ -404,32 +404,61 @@ struct Vec16<float> {
 // address space: uniform scalar loads that do not wait for the kernel's own global stores.
 typedef const __attribute__((address_space(4))) FlipEntry *ConstFlips;
 
+// Lane index threadIdx.x as an opaque value: expressions built from it are recomputed where they
+// are used instead of being hoisted and kept live across the kernel's phases.
+__device__ __forceinline__ uint32_t lane_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // acc += sum_t c_t sign_t tile[v ^ vs_t] for the flips of one split; vs_t is the mask moved to
 // the vector index (left shift by `shift`, or right shift by -shift for high masks, whose low
-// bits are zero).  Sign-free flips come first and run U at a time, so U * NV LDS reads are in
-// flight per wait; the accumulation order per element is the table order.
-template <typename T, int NT, int NV>
+// bits are zero).  Vector i of the thread is v = tid + i NT, so v ^ vs = (tid ^ (vs mod NT)) +
+// ((i NT) ^ (vs - vs mod NT)): one per-lane index per flip plus a uniform part per i.
+// Sign-free flips come first and run U at a time, so U * NV LDS reads are in flight per wait; the
+// accumulation order per element is the table order.  rowf(i) gives the row of vector i (for
+// the signs of flips with a z-mask).
+template <typename T, int NT, int NV, typename RowF>
 __device__ __forceinline__ void rec_flips(typename Vec16<T>::type (&acc)[NV], const typename Vec16<T>::type *tile,
-                                          const FlipEntry *flips_g, int nplain, int nflip, int shift,
-                                          const uint32_t (&row)[NV]) {
+                                          const FlipEntry *flips_g, int nplain, int nflip, int shift, RowF rowf) {
   using V = typename Vec16<T>::type;
-  constexpr int U = NV >= 2 ? 2 : 4;
+  constexpr int U = (NT == 1024 && NV == 4) ? 1 : NV >= 2 ? 2 : 4;
   const ConstFlips flips = (ConstFlips)flips_g;
   auto vshift = [shift](uint32_t xm) { return shift >= 0 ? (xm << shift) : (xm >> -shift); };
+  auto at = [&](uint32_t lo, uint32_t hi, int i) -> const V & {
+    return tile[lo + ((static_cast<uint32_t>(i) * NT) ^ hi)];
+  };
   int t = 0;
+  if constexpr (U == 1) {
+    // one flip's NV reads per wait; no unrolling, so no second set of loads is kept live
+#pragma unroll 1
+    for (; t < nplain; ++t) {
+      const uint32_t vs = vshift(flips[t].xmask);
+      const T c = static_cast<T>(flips[t].coef);
+      const uint32_t lo = lane_tid() ^ (vs & (NT - 1)), hi = vs & ~uint32_t(NT - 1);
+      V g[NV];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) g[i] = at(lo, hi, i);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += c * g[i];
+    }
+  }
   for (; t + U <= nplain; t += U) {
-    uint32_t vs[U];
+    uint32_t lo[U], hi[U];
     T c[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      vs[q] = vshift(flips[t + q].xmask);
+      const uint32_t vs = vshift(flips[t + q].xmask);
+      lo[q] = threadIdx.x ^ (vs & (NT - 1));
+      hi[q] = vs & ~uint32_t(NT - 1);
       c[q] = static_cast<T>(flips[t + q].coef);
     }
     V g[U][NV];
 #pragma unroll
     for (int q = 0; q < U; ++q)
 #pragma unroll
-      for (int i = 0; i < NV; ++i) g[q][i] = tile[(threadIdx.x + i * NT) ^ vs[q]];
+      for (int i = 0; i < NV; ++i) g[q][i] = at(lo[q], hi[q], i);
 #pragma unroll
     for (int q = 0; q < U; ++q)
 #pragma unroll
@@ -438,25 +467,28 @@ __device__ __forceinline__ void rec_flips(typename Vec16<T>::type (&acc)[NV], co
   for (; t < nplain; ++t) {
     const uint32_t vs = vshift(flips[t].xmask);
     const T c = static_cast<T>(flips[t].coef);
+    const uint32_t lo = threadIdx.x ^ (vs & (NT - 1)), hi = vs & ~uint32_t(NT - 1);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += c * tile[(threadIdx.x + i * NT) ^ vs];
+    for (int i = 0; i < NV; ++i) acc[i] += c * at(lo, hi, i);
   }
+#pragma unroll 1
   for (; t < nflip; ++t) {
     const uint32_t xm = flips[t].xmask;
     const uint32_t zm = flips[t].zmask;
     const T c = static_cast<T>(flips[t].coef);
     const uint32_t vs = vshift(xm);
+    const uint32_t lo = lane_tid() ^ (vs & (NT - 1)), hi = vs & ~uint32_t(NT - 1);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const T sg = (__popc((row[i] ^ xm) & zm) & 1) ? -c : c;
-      acc[i] += sg * tile[(threadIdx.x + i * NT) ^ vs];
+      const T sg = (__popc((rowf(i) ^ xm) & zm) & 1) ? -c : c;
+      acc[i] += sg * at(lo, hi, i);
     }
   }
 }
 
-// Waves per SIMD that let two one-tile workgroups share a CU (1024 threads with 2 vectors each,
-// or 512 threads with up to 4); other shapes run one workgroup per CU.
-constexpr int rec_min_waves(int nt, int nv) { return (nt == 1024 && nv <= 2) ? 8 : (nt == 512 && nv <= 4) ? 4 : 1; }
+// Waves per SIMD that let two one-tile workgroups share a CU (1024 threads with up to 4 vectors
+// each, or 512 threads with up to 4); other shapes run one workgroup per CU.
+constexpr int rec_min_waves(int nt, int nv) { return (nt == 1024 && nv <= 4) ? 8 : (nt == 512 && nv <= 4) ? 4 : 1; }
 
 template <typename T>
 __device__ __forceinline__ void store_sample(double *st, int64_t ldst, uint32_t row, uint32_t cv,
@@ -466,11 +498,27 @@ __device__ __forceinline__ void store_sample(double *st, int64_t ldst, uint32_t 
   for (int q = 0; q < Vec16<T>::n; ++q) d[q] = static_cast<double>(x[q]);
 }
 
+// Both kernels keep three vector sets per thread (T_cur, the accumulator and one flip's loads in
+// flight) and recompute every index from the lane id, so the 1024-thread shape with 4 vectors
+// fits 64 VGPRs and two tiles share a CU: one tile's LDS phase then overlaps the other's loads
+// and stores.  The partial P is loaded only when the first flip sweep is done, and the low pass
+// keeps the tile's diagonal entries in LDS after the vectors (2^lo_bits of them).  Global
+// vector i of a thread sits at a uniform base (one per i) plus the lane's 32-bit byte offset.
+template <typename V>
+__device__ __forceinline__ V *vec_at(V *base, uint32_t vi) {
+  return reinterpret_cast<V *>(reinterpret_cast<char *>(base) + (vi << 4));
+}
+template <typename V>
+__device__ __forceinline__ const V *vec_at(const V *base, uint32_t vi) {
+  return reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + (vi << 4));
+}
+
 template <typename T, int NT, int NV>
 __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_lo(RecArgs<T> a) {
   using V = typename Vec16<T>::type;
   extern __shared__ unsigned char smem_raw[];
   V *tile = reinterpret_cast<V *>(smem_raw);
+  T *dtile = reinterpret_cast<T *>(smem_raw + sizeof(V) * NT * NV);
   const int lbv = (__ffs(a.b) - 1) - Vec16<T>::log2n;  // log2(vectors per row)
   const uint32_t cvmask = (1u << lbv) - 1u;
   int bid = blockIdx.x;
@@ -480,41 +528,50 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_lo(RecArgs<T>
   const V *tc = reinterpret_cast<const V *>(a.tcur) + vbase;
   V *tn = reinterpret_cast<V *>(a.tnew) + vbase;
   V *pp = reinterpret_cast<V *>(a.p) + vbase;
-  V cur[NV], nw[NV], acc[NV];
-  T dg[NV];
-  uint32_t row[NV];
+  auto rowf = [&](int i) { return row0 + ((lane_tid() + static_cast<uint32_t>(i) * NT) >> lbv); };
+  auto dg = [&](int i) { return dtile[(lane_tid() + static_cast<uint32_t>(i) * NT) >> lbv]; };
+  V cur[NV], acc[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const uint32_t v = threadIdx.x + i * NT;
-    row[i] = row0 + (v >> lbv);
-    cur[i] = tc[v];
-    nw[i] = pp[v];
-    dg[i] = a.diag[row[i]];
-  }
+  for (int i = 0; i < NV; ++i) cur[i] = *vec_at(tc + i * NT, lane_tid());
+  const uint32_t nrows = 1u << a.lo_bits;
+  for (uint32_t r = threadIdx.x; r < nrows; r += NT) dtile[r] = a.diag[row0 + r];
 #pragma unroll
   for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = cur[i];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = dg[i] * cur[i];
-  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
+  for (int i = 0; i < NV; ++i) acc[i] = dg(i) * cur[i];
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, rowf);
+  {
+    // all NV loads of P in flight before the first use (no branch between them)
+    V p[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const uint32_t v = threadIdx.x + i * NT;
-    nw[i] += a.alpha * acc[i];
-    tn[v] = nw[i];
-    if (a.st) store_sample<T>(a.st, a.ldst, row[i], v & cvmask, nw[i]);
+    for (int i = 0; i < NV; ++i) p[i] = *vec_at(pp + i * NT, lane_tid());
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      acc[i] = p[i] + a.alpha * acc[i];  // T_new
+      *vec_at(tn + i * NT, lane_tid()) = acc[i];
+    }
+  }
+  if (a.st) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) store_sample<T>(a.st, a.ldst, rowf(i), (lane_tid() + i * NT) & cvmask, acc[i]);
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = nw[i];
+  for (int i = 0; i < NV; ++i) {
+    tile[threadIdx.x + i * NT] = acc[i];
+    acc[i] = dg(i) * acc[i];
+  }
   __syncthreads();
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, rowf);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = dg[i] * nw[i];
-  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
-#pragma unroll
-  for (int i = 0; i < NV; ++i) pp[threadIdx.x + i * NT] = a.alpha * acc[i] - cur[i];
+  for (int i = 0; i < NV; ++i) *vec_at(pp + i * NT, lane_tid()) = a.alpha * acc[i] - cur[i];
 }
 
+// High pass: vector v = tid + i NT of the tile is (j, w, c) = (v >> (lw + lbv), (v >> lbv) & (W - 1),
+// v & (2^lbv - 1)) and lives at global vector ((l0 + w + (j << lo_bits)) << lbv) | c.  With
+// W 2^lbv dividing NT, vector i sits at the offset of vector 0 plus the uniform
+// i (NT >> (lw + lbv)) << (lo_bits + lbv).
 template <typename T, int NT, int NV>
 __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_hi(RecArgs<T> a) {
   using V = typename Vec16<T>::type;
@@ -527,23 +584,23 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_hi(RecArgs<T>
   int bid = blockIdx.x;
   if (a.xcd_remap) bid = (bid & 7) * (a.ntiles >> 3) + (bid >> 3);
   const uint32_t l0 = static_cast<uint32_t>(bid) << lw;
+  const uint32_t istep = static_cast<uint32_t>(NT >> (lw + lbv)) << (a.lo_bits + lbv);
   const V *tc = reinterpret_cast<const V *>(a.tcur);
   V *tn = reinterpret_cast<V *>(a.tnew);
   V *pp = reinterpret_cast<V *>(a.p);
-  V cur[NV], nw[NV], acc[NV];
-  uint32_t row[NV];  // the vector's global offset is (row << lbv) | (v & cvmask)
+  auto rowf = [&](int i) {
+    const uint32_t rv = (lane_tid() + static_cast<uint32_t>(i) * NT) >> lbv;
+    return l0 + (rv & wmask) + ((rv >> lw) << a.lo_bits);
+  };
+  // global vector offset of the lane's vector 0
+  auto off0 = [&]() {
+    const uint32_t t = lane_tid();
+    const uint32_t rv = t >> lbv;
+    return ((l0 + (rv & wmask) + ((rv >> lw) << a.lo_bits)) << lbv) | (t & cvmask);
+  };
+  V cur[NV], acc[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const uint32_t v = threadIdx.x + i * NT;
-    const uint32_t rv = v >> lbv;
-    row[i] = l0 + (rv & wmask) + ((rv >> lw) << a.lo_bits);
-  }
-  auto off = [&](int i) { return (row[i] << lbv) | ((threadIdx.x + i * NT) & cvmask); };
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    cur[i] = tc[off(i)];
-    nw[i] = pp[off(i)];
-  }
+  for (int i = 0; i < NV; ++i) cur[i] = *vec_at(tc + i * istep, off0());
 #pragma unroll
   for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = cur[i];
   __syncthreads();
@@ -551,22 +608,30 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_hi(RecArgs<T>
   for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
   // high masks act on j: shift right by lo_bits, then left by lw + lbv
   const int hs = lw + lbv - a.lo_bits;
-  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, rowf);
+  {
+    V p[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    nw[i] += a.alpha * acc[i];
-    tn[off(i)] = nw[i];
-    if (a.st) store_sample<T>(a.st, a.ldst, row[i], (threadIdx.x + i * NT) & cvmask, nw[i]);
+    for (int i = 0; i < NV; ++i) p[i] = *vec_at(pp + i * istep, off0());
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      acc[i] = p[i] + a.alpha * acc[i];  // T_new
+      *vec_at(tn + i * istep, off0()) = acc[i];
+    }
+  }
+  if (a.st) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) store_sample<T>(a.st, a.ldst, rowf(i), lane_tid() & cvmask, acc[i]);
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = nw[i];
+  for (int i = 0; i < NV; ++i) tile[threadIdx.x + i * NT] = acc[i];
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
-  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
+  rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, rowf);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) pp[off(i)] = a.alpha * acc[i] - cur[i];
+  for (int i = 0; i < NV; ++i) *vec_at(pp + i * istep, off0()) = a.alpha * acc[i] - cur[i];
 }
 
 // Persistent variants: gridDim.x workgroups walk the tiles t = blockIdx.x + k gridDim.x and
@@ -614,7 +679,7 @@ __global__ __launch_bounds__(NT) void k_rec_lo_p(RecArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = dg[i] * cur[i];
-    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, [&](int i) { return row[i]; });
     V *tn = reinterpret_cast<V *>(a.tnew) + vbase;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -629,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_rec_lo_p(RecArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = dg[i] * nw[i];
-    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, row);
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, [&](int i) { return row[i]; });
     V *pp = reinterpret_cast<V *>(a.p) + vbase;
 #pragma unroll
     for (int i = 0; i < NV; ++i) pp[threadIdx.x + i * NT] = a.alpha * acc[i] - cur[i];
@@ -684,7 +749,7 @@ __global__ __launch_bounds__(NT) void k_rec_hi_p(RecArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
-    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, [&](int i) { return row[i]; });
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t cv = (threadIdx.x + i * NT) & cvmask;
@@ -698,7 +763,7 @@ __global__ __launch_bounds__(NT) void k_rec_hi_p(RecArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
-    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, row);
+    rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, [&](int i) { return row[i]; });
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t cv = (threadIdx.x + i * NT) & cvmask;
@@ -708,20 +773,39 @@ __global__ __launch_bounds__(NT) void k_rec_hi_p(RecArgs<T> a) {
   }
 }
 
+// Dynamic LDS above the 64 KiB default must be allowed per kernel; done once per instantiation
+// (function-local statics are initialised once, also under concurrent first calls).
+template <typename T, int NT, int NV>
+hipError_t rec_lo_allow_lds() {
+  static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_rec_lo<T, NT, NV>),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                  static_cast<int>(NT * NV * 16 + 8192 * sizeof(T)));
+  return e;
+}
+
 template <typename T, int NT>
 hipError_t launch_rec_nt(const RecArgs<T> &a, int nvec, bool hi, hipStream_t s) {
-  const size_t lds = static_cast<size_t>(nvec) * 16;
+  // low pass: the vectors, then the tile's 2^lo_bits diagonal entries
+  const size_t rows_lo = size_t(1) << a.lo_bits;
+  const size_t lds_vec = static_cast<size_t>(nvec) * 16;  // persistent forms: vectors only
+  const size_t lds = lds_vec + (hi ? 0 : rows_lo * sizeof(T));
+  if (!hi && rows_lo > 8192) return hipErrorInvalidValue;
   // (the 1024-thread persistent form with 4 vectors per thread would spill: launch one tile per workgroup)
   const bool persist = a.grid > 0 && a.grid < a.ntiles && !(NT == 1024 && nvec / NT == 4);
   dim3 grid(persist ? a.grid : a.ntiles), block(NT);
 #define DACP_REC(nv_)                                                                  \
   do {                                                                                 \
     if (persist) {                                                                     \
-      if (hi) hipLaunchKernelGGL((k_rec_hi_p<T, NT, nv_>), grid, block, lds, s, a);   \
-      else hipLaunchKernelGGL((k_rec_lo_p<T, NT, nv_>), grid, block, lds, s, a);      \
+      if (hi) hipLaunchKernelGGL((k_rec_hi_p<T, NT, nv_>), grid, block, lds_vec, s, a); \
+      else hipLaunchKernelGGL((k_rec_lo_p<T, NT, nv_>), grid, block, lds_vec, s, a);    \
     } else {                                                                           \
-      if (hi) hipLaunchKernelGGL((k_rec_hi<T, NT, nv_>), grid, block, lds, s, a);     \
-      else hipLaunchKernelGGL((k_rec_lo<T, NT, nv_>), grid, block, lds, s, a);        \
+      if (hi) {                                                                        \
+        hipLaunchKernelGGL((k_rec_hi<T, NT, nv_>), grid, block, lds, s, a);           \
+      } else {                                                                         \
+        const hipError_t e = rec_lo_allow_lds<T, NT, nv_>();                           \
+        if (e != hipSuccess) return e;                                                 \
+        hipLaunchKernelGGL((k_rec_lo<T, NT, nv_>), grid, block, lds, s, a);           \
+      }                                                                                \
     }                                                                                  \
   } while (0)
   switch (nvec / NT) {
@@ -741,6 +825,12 @@ hipError_t launch_rec(const RecArgs<T> &a, bool hi, hipStream_t s) {
   if ((a.b * static_cast<int>(sizeof(T))) % 16 != 0 || nel * static_cast<int64_t>(sizeof(T)) > 65536)
     return hipErrorInvalidValue;
   const int nvec = static_cast<int>(nel * sizeof(T) / 16);
+  // 32-bit byte offsets over the whole block (high pass), and W rows of vectors dividing the
+  // thread count (the high pass steps its vectors by a uniform offset)
+  const int64_t D = int64_t(1) << (a.lo_bits + a.hi_bits);
+  if (D * a.b * static_cast<int64_t>(sizeof(T)) >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+  if (hi && static_cast<int64_t>(a.W) * (a.b * static_cast<int64_t>(sizeof(T)) / 16) > a.threads)
+    return hipErrorInvalidValue;
   if (a.threads == 512 && nvec % 512 == 0) return launch_rec_nt<T, 512>(a, nvec, hi, s);
   if (a.threads == 1024 && nvec % 1024 == 0) return launch_rec_nt<T, 1024>(a, nvec, hi, s);
   return hipErrorInvalidValue;

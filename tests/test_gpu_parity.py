@@ -68,7 +68,7 @@ def random_real_terms(L, seed, n):
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (37, 129, 70), (128, 128, 16), (300, 257, 513)])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (37, 129, 70), (128, 128, 16), (300, 257, 513), (1100, 1030, 40)])
 def test_dgemm_mfma_parity(ctx, ta, tb, M, N, K):
     rng = np.random.default_rng(M * 7 + N + K)
     A = rng.standard_normal((K, M) if ta else (M, K))
@@ -370,6 +370,22 @@ def test_project_parity(ctx):
     S_ref, P_ref = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
     assert np.abs(host(S) - S_ref).max() < 1e-13
     assert np.abs(host(P) - P_ref).max() < 1e-12
+    assert np.array_equal(host(S), host(S).T) and np.array_equal(host(P), host(P).T)
+
+
+def test_project_parity_many_tile_blocks(ctx):
+    """m = 1100: 9 x 9 output tiles, so the Gram's upper-triangle walk spans several 8 x 8 tile
+    blocks, including the ragged last block row and column."""
+    L, m = 10, 1100
+    terms = inputs.spin_glass(L, 9)
+    V = np.random.default_rng(9).standard_normal((1 << L, m)) / math.sqrt(1 << L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    S = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    P = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    B.dacp_project(ctx, ham, to_dev(V), S, P)
+    S_ref, P_ref = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
+    assert np.abs(host(S) - S_ref).max() < 1e-13
+    assert np.abs(host(P) - P_ref).max() < 1e-12 * max(1.0, np.abs(P_ref).max())
     assert np.array_equal(host(S), host(S).T) and np.array_equal(host(P), host(P).T)
 
 
