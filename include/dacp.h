@@ -96,6 +96,8 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "rec_threads" fused recurrence: threads per workgroup, 512 or 1024 (default 1024)
  *   "rec_persist" fused recurrence: 0 = one workgroup per tile (default); n = 1..8 persistent
  *                 workgroups per compute unit that prefetch their next tile
+ *   "project_whole" projection: 1 = P = V^T (H V) as one GEMM when the block H V (D x m FP64)
+ *                 fits in free device memory beside V (default), 0 = always in column chunks
  *   "rec_xcd"     fused recurrence tile order, bit 0 for the low pass and bit 1 for the high
  *                 pass: set = each of the 8 XCDs takes a contiguous eighth of the tiles, clear =
  *                 tiles dealt round-robin in launch order (default 2: high pass only)

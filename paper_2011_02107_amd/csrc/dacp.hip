@@ -690,6 +690,28 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
          static_cast<double>(D) * m * (m + 128.0) / (ms * 1e-3) / 1e12);
     ts.start();
   }
+  // With room for the whole block H V (D x m) beside V, P is one upper-triangle GEMM like S;
+  // otherwise it is built in column chunks of 512 against the rows up to each chunk's end.
+  {
+    const size_t whole = static_cast<size_t>(D) * m * sizeof(double);
+    size_t free_b = 0, total_b = 0;
+    DevBuf wall;
+    if (ctx->project_whole && hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > whole + (size_t(4) << 30) &&
+        wall.alloc(whole) == hipSuccess) {
+      double *W = wall.as<double>();
+      for (int s0 = 0; s0 < m; s0 += 64) {
+        const int bw = std::min(64, m - s0);
+        dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + s0, m, 1.0);
+        if (st) return st;
+      }
+      DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, W, m, 0.0, P, ld, 1, s));
+      DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
+      if (verbose()) vlog("projection: P = V^T (H V) in one GEMM %.1f ms", ts.stop_ms());
+      DACP_HIP(ctx, hipStreamSynchronize(s));
+      return DACP_OK;
+    }
+    (void)hipGetLastError();  // a failed allocation here only selects the chunked form
+  }
   const int cw = std::min(m, 512);
   DevBuf wbuf;
   DACP_HIP(ctx, wbuf.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
@@ -1019,6 +1041,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->batch_workers = value;
     return DACP_OK;
   }
+  if (k == "project_whole") {
+    if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "project_whole: 0 or 1");
+    ctx->project_whole = value;
+    return DACP_OK;
+  }
   if (k == "rec_xcd") {
     if (value < 0 || value > 3) return set_err(ctx, DACP_E_INVALID, "rec_xcd: 0..3 (bit 0 low pass, bit 1 high pass)");
     ctx->rec_xcd = value;
@@ -1058,6 +1085,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "rec_tile") *value = ctx->rec_tile_elems;
   else if (k == "rec_persist") *value = ctx->rec_persist;
   else if (k == "rec_xcd") *value = ctx->rec_xcd;
+  else if (k == "project_whole") *value = ctx->project_whole;
   else if (k == "batch_workers") *value = ctx->batch_workers;
   else return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
   return DACP_OK;

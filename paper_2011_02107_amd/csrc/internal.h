@@ -230,6 +230,7 @@ struct dacp_ctx_s {
   int rec_threads = 1024;      // fused recurrence: threads per workgroup (512 or 1024)
   int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
+  int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)
   int rec_xcd = 2;             // fused recurrence: XCD-contiguous tile order, bit 0 low pass, bit 1 high pass
   int num_cus = 256;           // compute units of the device
   int batch_workers = 8;       // host threads (each with its own stream) finishing batched realisations

@@ -390,18 +390,26 @@ def test_project_parity_many_tile_blocks(ctx):
 
 
 def test_project_parity_split_k(ctx):
-    """At D = 2^16 the projection splits K over several workgroup layers (narrow P chunks);
-    two chunks of 512 and 128 columns."""
+    """Column-chunked P at D = 2^16 splits K over several workgroup layers (narrow P chunks);
+    two chunks of 512 and 128 columns.  Then the one-GEMM form of P on the same input."""
     L, m = 16, 640
     terms = inputs.ising_chain(L)
     V = np.random.default_rng(8).standard_normal((1 << L, m)) / math.sqrt(1 << L)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     S = torch.zeros((m, m), dtype=torch.float64, device=DEV)
     P = torch.zeros((m, m), dtype=torch.float64, device=DEV)
-    B.dacp_project(ctx, ham, to_dev(V), S, P)
+    try:
+        ctx.tune("project_whole", 0)
+        B.dacp_project(ctx, ham, to_dev(V), S, P)
+    finally:
+        ctx.tune("project_whole", 1)
     S_ref, P_ref = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
     assert np.abs(host(S) - S_ref).max() < 1e-13
     assert np.abs(host(P) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
+    # the one-GEMM form on the same input
+    P1 = torch.zeros_like(P)
+    B.dacp_project(ctx, ham, to_dev(V), S, P1)
+    assert np.abs(host(P1) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 130, 400])
