@@ -26,10 +26,9 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per evolution launch measured with the FETCH_SIZE and WRITE_SIZE counters (each scaled by
 # its reading on a 256 MiB device copy), for the kernel build and launch shape named by the key:
 # (workload, kernel pair, column group).  Reported as roofline.traffic only for that configuration.
-EVOLUTION_KERNELS = "k_rec_lo/k_rec_hi v4"
+EVOLUTION_KERNELS = "k_rec_lo/k_rec_hi v5"
 # key: (workload, kernel build, group, threads, fused tile, high-tile rows knob, XCD tile order knob)
-# (At group 8 and tile 8192 the automatic high-tile rows knob 0 resolves to W = 1: same launch.)
-MEASURED_TRAFFIC = {("chain_L20_N5000", EVOLUTION_KERNELS, 8, 1024, 8192, w, 2): 279.75e6 for w in (0, 1)}
+MEASURED_TRAFFIC = {("chain_L20_N5000", EVOLUTION_KERNELS, 8, 1024, 8192, 0, 2): 279.67e6}
 
 
 def parse():
@@ -41,10 +40,13 @@ def parse():
                     choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "fp32_tail_table"])
     ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=None, help="start-block seed (default: the library's)")
     ap.add_argument("--window-ratio", type=float, default=None)
     ap.add_argument("--basis-ratio", type=float, default=None)
     ap.add_argument("--tail", type=float, default=None, help="FP64 tail fraction of the filter (tuned mode)")
     ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0, help="start-block width b (default: the workload's)")
+    ap.add_argument("--max-retries", type=int, default=None, help="wider-window retries (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--profile-kernels", action="store_true",
@@ -59,8 +61,16 @@ def opts_for(args, wl):
     if args.mode == "plain":
         o = B.default_opts(b=wl["b"], kfac=18.0, window_ratio=2.2, precision=B.DACP_F64, group=args.group)
     else:
-        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.2, basis_ratio=1.1, precision=B.DACP_F32,
+        # basis 1.2 N_w: at 1.1 - 1.15 a cluster of near-degenerate levels somewhere in the core can
+        # stay unresolved (residuals ~5e-7) on some start blocks and force a retry with a wider window
+        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
                            fp64_tail_frac=0.3, group=args.group)
+    if args.block:
+        o.b = args.block
+    if args.max_retries is not None:
+        o.max_retries = args.max_retries
+    if args.seed is not None:
+        o.seed = args.seed
     if args.kfac:
         o.kfac = args.kfac
     if args.window_ratio:

@@ -74,13 +74,15 @@ struct HiArgs {
   int ntiles;
 };
 
-// Fused alternating-split recurrence kernels for T_{j+1} = alpha H T_j - T_{j-1},
-// H = (D + Lo) + Hi (diagonal and flips below bit lo_bits | flips at or above it).
-// With the partial P holding either alpha (D + Lo) T_j - T_{j-1} ("A first") or
-// alpha Hi T_j - T_{j-1} ("B first"), one kernel completes a step and starts the next:
-//   lo tile kernel:  T_new = P + alpha (D + Lo) T_cur ;  P <- alpha (D + Lo) T_new - T_cur
-//   hi coset kernel: T_new = P + alpha Hi T_cur       ;  P <- alpha Hi T_new - T_cur
-// T_new is written over the buffer of the term before T_cur; P is updated in place.
+// Fused alternating-split kernels for a chain z_{j+1} = c_j H z_j + r_j, with
+// H = (D + Lo) + Hi (diagonal and flips below bit lo_bits | flips at or above it) and r_j a
+// combination of earlier terms.  With the partial P = c_j (other half) z_j + r_j, one kernel
+// completes z_{j+1} with its half X of H and starts the next partial with the same half:
+//   T_new = P + a_fin X T_cur ;  P <- a_start X T_new + b_cur T_cur (+ c_old Old)
+// X = D + Lo for the lo tile kernel and Hi for the hi coset kernel.  The evolution
+// T_{j+1} = 2G T_j - T_{j-1} takes a_fin = a_start = 2/E_b, b_cur = -1 and no Old term; the
+// filter's two applies per order take the coefficients of its recurrence (filter_steps_fused).
+// T_new may be written over the buffer of an earlier term; P is updated in place.
 // The blocks are contiguous [D][b] with b * sizeof(T) a multiple of 16 bytes and
 // D * b * sizeof(T) < 2^32 (32-bit byte offsets from the block's base).
 template <typename T>
@@ -88,10 +90,11 @@ struct RecArgs {
   const T *tcur;
   T *tnew;
   T *p;
+  const T *old;  // optional third block of the new partial (same layout)
   double *st;   // optional FP64 copy of T_new (basis sample), row stride ldst
   int64_t ldst;
   int64_t ld;   // row stride of tcur, tnew, p (= b)
-  T alpha;
+  T a_fin, a_start, b_cur, c_old;
   const T *diag;
   const FlipEntry *flips;  // read-only while a kernel runs (loaded through the scalar cache)
   int nflip;
@@ -235,7 +238,8 @@ struct dacp_ctx_s {
   int num_cus = 256;           // compute units of the device
   int batch_workers = 8;       // host threads (each with its own stream) finishing batched realisations
   int filter_group_f64 = 8;    // filter column-group width for L >= 15, FP64 recurrence
-  int filter_group_f32 = 16;   // filter column-group width for L >= 15, FP32 recurrence
+  int filter_group_f32 = 8;    // filter column-group width for L >= 15, FP32 recurrence (its FP64 tail
+                               // runs on the same groups, and the fused chain needs 8 FP64 columns)
   int dc_min_n = 96;           // eigenvectors by divide and conquer from this size on (0 = never)
 };
 

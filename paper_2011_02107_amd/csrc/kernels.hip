@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_lo(RecArgs<T>
     for (int i = 0; i < NV; ++i) p[i] = *vec_at(pp + i * NT, lane_tid());
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      acc[i] = p[i] + a.alpha * acc[i];  // T_new
+      acc[i] = p[i] + a.a_fin * acc[i];  // T_new
       *vec_at(tn + i * NT, lane_tid()) = acc[i];
     }
   }
@@ -564,8 +564,18 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_lo(RecArgs<T>
   }
   __syncthreads();
   rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, rowf);
+  if (a.old) {
+    const V *od = reinterpret_cast<const V *>(a.old) + vbase;
+    V o[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) *vec_at(pp + i * NT, lane_tid()) = a.alpha * acc[i] - cur[i];
+    for (int i = 0; i < NV; ++i) o[i] = *vec_at(od + i * NT, lane_tid());
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      *vec_at(pp + i * NT, lane_tid()) = (a.a_start * acc[i] + a.b_cur * cur[i]) + a.c_old * o[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) *vec_at(pp + i * NT, lane_tid()) = a.a_start * acc[i] + a.b_cur * cur[i];
+  }
 }
 
 // High pass: vector v = tid + i NT of the tile is (j, w, c) = (v >> (lw + lbv), (v >> lbv) & (W - 1),
@@ -615,7 +625,7 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_hi(RecArgs<T>
     for (int i = 0; i < NV; ++i) p[i] = *vec_at(pp + i * istep, off0());
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      acc[i] = p[i] + a.alpha * acc[i];  // T_new
+      acc[i] = p[i] + a.a_fin * acc[i];  // T_new
       *vec_at(tn + i * istep, off0()) = acc[i];
     }
   }
@@ -630,8 +640,17 @@ __global__ __launch_bounds__(NT, rec_min_waves(NT, NV)) void k_rec_hi(RecArgs<T>
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = V(T(0));
   rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, hs, rowf);
+  if (a.old) {
+    V o[NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) *vec_at(pp + i * istep, off0()) = a.alpha * acc[i] - cur[i];
+    for (int i = 0; i < NV; ++i) o[i] = *vec_at(reinterpret_cast<const V *>(a.old) + i * istep, off0());
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      *vec_at(pp + i * istep, off0()) = (a.a_start * acc[i] + a.b_cur * cur[i]) + a.c_old * o[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) *vec_at(pp + i * istep, off0()) = a.a_start * acc[i] + a.b_cur * cur[i];
+  }
 }
 
 // Persistent variants: gridDim.x workgroups walk the tiles t = blockIdx.x + k gridDim.x and
@@ -684,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_rec_lo_p(RecArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t v = threadIdx.x + i * NT;
-      nw[i] += a.alpha * acc[i];
+      nw[i] += a.a_fin * acc[i];
       tn[v] = nw[i];
       if (a.st) store_sample<T>(a.st, a.ldst, row[i], v & cvmask, nw[i]);
     }
@@ -697,7 +716,12 @@ __global__ __launch_bounds__(NT) void k_rec_lo_p(RecArgs<T> a) {
     rec_flips<T, NT, NV>(acc, tile, a.flips, a.nplain, a.nflip, lbv, [&](int i) { return row[i]; });
     V *pp = reinterpret_cast<V *>(a.p) + vbase;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) pp[threadIdx.x + i * NT] = a.alpha * acc[i] - cur[i];
+    for (int i = 0; i < NV; ++i) {
+      V o = V(T(0));
+      if (a.old) o = reinterpret_cast<const V *>(a.old)[vbase + threadIdx.x + i * NT];
+      pp[threadIdx.x + i * NT] =
+          a.old ? (a.a_start * acc[i] + a.b_cur * cur[i]) + a.c_old * o : a.a_start * acc[i] + a.b_cur * cur[i];
+    }
     __syncthreads();  // the next tile overwrites the LDS copy
   }
 }
@@ -753,7 +777,7 @@ __global__ __launch_bounds__(NT) void k_rec_hi_p(RecArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t cv = (threadIdx.x + i * NT) & cvmask;
-      nw[i] += a.alpha * acc[i];
+      nw[i] += a.a_fin * acc[i];
       reinterpret_cast<V *>(a.tnew)[(row[i] << lbv) | cv] = nw[i];
       if (a.st) store_sample<T>(a.st, a.ldst, row[i], cv, nw[i]);
     }
@@ -767,7 +791,11 @@ __global__ __launch_bounds__(NT) void k_rec_hi_p(RecArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const uint32_t cv = (threadIdx.x + i * NT) & cvmask;
-      reinterpret_cast<V *>(a.p)[(row[i] << lbv) | cv] = a.alpha * acc[i] - cur[i];
+      const uint32_t gv = (row[i] << lbv) | cv;
+      V o = V(T(0));
+      if (a.old) o = reinterpret_cast<const V *>(a.old)[gv];
+      reinterpret_cast<V *>(a.p)[gv] =
+          a.old ? (a.a_start * acc[i] + a.b_cur * cur[i]) + a.c_old * o : a.a_start * acc[i] + a.b_cur * cur[i];
     }
     __syncthreads();
   }

@@ -257,6 +257,52 @@ def test_filter_f32_with_fp64_tail(ctx):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("which", ["chain", "signed"])
+def test_filter_fused_chain_f64_parity(ctx, which):
+    """L = 16, b = 16: the FP64 filter orders run as the fused split chain (groups of 8), including
+    the old-term read of the low kernel; signed flips exercise the z-mask path."""
+    L, b = 16, 16
+    terms = inputs.ising_chain(L) if which == "chain" else _signed_flip_terms(L, 5)
+    eb = 1.02 * hamiltonian.sum_abs_coeff(terms)
+    a = 0.3 * eb
+    K = chebyshev.filter_order(eb, a, 12.0)
+    psi = np.random.default_rng(17).standard_normal((1 << L, b))
+    ref = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, K)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    out = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    B.dacp_filter(ctx, ham, out, eb, a, K, start=to_dev(psi))
+    assert np.abs(host(out) - ref).max() < 1e-10
+    # same orders through the unfused applies
+    out2 = torch.empty_like(out)
+    try:
+        ctx.tune("fused", 0)
+        B.dacp_filter(ctx, ham, out2, eb, a, K, start=to_dev(psi))
+    finally:
+        ctx.tune("fused", 1)
+    assert np.abs(host(out2) - host(out)).max() < 1e-12
+
+
+@pytest.mark.parametrize("g32", [8, 16])
+def test_filter_fused_chain_f32_tail(ctx, g32):
+    """L = 16, b = 16: FP32 orders as the fused chain (float kernels) on groups of 8 or one group of
+    16, then the FP64 tail on the same groups (fused at 8 columns, the single-pass apply at 16)."""
+    L, b = 16, 16
+    terms = _signed_flip_terms(L, 6)
+    eb = 1.02 * hamiltonian.sum_abs_coeff(terms)
+    a = 0.3 * eb
+    K = chebyshev.filter_order(eb, a, 12.0)
+    psi = np.random.default_rng(18).standard_normal((1 << L, b))
+    ref = chebyshev.exp_semicircle_filter(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, K)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    out = torch.empty((1 << L, b), dtype=torch.float64, device=DEV)
+    try:
+        ctx.tune("filter_group_f32", g32)
+        B.dacp_filter(ctx, ham, out, eb, a, K, start=to_dev(psi), precision=B.DACP_F32, fp64_tail=K // 3)
+    finally:
+        ctx.tune("filter_group_f32", 8)
+    assert np.abs(host(out) - ref).max() < 1e-5 * np.abs(ref).max()
+
+
 def test_basis_parity(ctx):
     L, b, n = 9, 3, 5
     terms = inputs.spin_glass(L, 7)
