@@ -3,9 +3,16 @@
 // C = alpha * op(A) * op(B) + beta * C, row-major.  A 256-thread workgroup
 // computes a 128 x 128 tile of C; each of its four 64-lane waves owns a
 // 64 x 64 quadrant held as 4 x 4 MFMA accumulators of 16 x 16.  K advances in
-// slabs of 16 staged through double-buffered LDS (k-major, padded rows).
+// slabs of 16 staged through double-buffered LDS.
 // Used for the Gram S = V^T V and P = V^T (H V) (upper triangle only), the
 // subspace transforms of the generalised eigenproblem and the Ritz vectors.
+//
+// LDS layout.  The 16 x 16 x 4 MFMA takes from lane l the A element (row l % 16, k = l / 16) and
+// the B element (k = l / 16, column l % 16), so over the four k-steps of a slab lane l needs
+// k = l / 16 + 4 s, s = 0..3, of one row.  Each operand tile is stored row-major by m (or n) with
+// the slab's k permuted as kp(k) = 4 (k % 4) + k / 4: those four values are contiguous, and a
+// lane fetches them with two 16-byte LDS reads.  Rows are 18 doubles (144 bytes) apart, so the 16
+// lanes of a read group hit distinct 16-byte bank groups.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -13,8 +20,50 @@
 namespace dacp {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
-constexpr int BM = 128, BN = 128, BK = 16, PADD = 4;
+constexpr int BM = 128, BN = 128, BK = 16, KS = 18;
+
+// Global -> registers -> LDS staging of one 128 x 16 operand slab.  KMAJOR: element (k, x) at
+// src[k * ld + x] (x = m or n contiguous); each thread takes one x and 8 consecutive k and stores
+// pairs (k, k + 4), which are adjacent after the permutation, as 16-byte LDS writes.  Otherwise
+// element (k, x) at src[x * ld + k]; each thread takes one k and 8 rows x.
+template <bool KMAJOR>
+struct Slab {
+  double v[8];
+  // Row q of the thread's 8 starts at a wave-uniform pointer (KMAJOR: k is uniform per wave) or at
+  // a uniform pointer plus one per-lane offset computed once, so the loads need no per-element
+  // 64-bit address registers.
+  __device__ __forceinline__ void load(const double *src, int64_t ld, int64_t x0, int64_t X, int64_t kb, int64_t kend,
+                                       int tid) {
+    if (KMAJOR) {
+      const int x = tid & 127, kk = (tid >> 7) * 8;
+      const bool xin = x0 + x < X;
+      const double *base = src + (kb + kk) * ld + x0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (kb + kk + q < kend && xin) ? base[q * ld + x] : 0.0;
+    } else {
+      const int k = tid & 15, xr = tid >> 4;
+      const bool kin = kb + k < kend;
+      const int64_t off = static_cast<int64_t>(xr) * ld + k;
+      const double *base = src + x0 * ld + kb;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        v[q] = (kin && x0 + xr + 16 * q < X) ? base[static_cast<int64_t>(16 * q) * ld + off] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void store(double (*S)[KS], int tid) const {
+    if (KMAJOR) {
+      const int x = tid & 127, h = tid >> 7;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) *reinterpret_cast<v2d *>(&S[x][4 * c + 2 * h]) = v2d{v[c], v[c + 4]};
+    } else {
+      const int k = tid & 15, kp = 4 * (k & 3) + (k >> 2);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) S[(tid >> 4) + 16 * q][kp] = v[q];
+    }
+  }
+};
 
 // Split K: workgroup z of the grid's third dimension sums k in [z kchunk, (z + 1) kchunk) and,
 // when `work` is set, stores alpha * (its partial tile) to work[z][M][N] for k_splitk_reduce.
@@ -22,8 +71,8 @@ template <int TA, int TB>
 __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A,
                                                   int64_t lda, const double *B, int64_t ldb, double beta, double *C,
                                                   int64_t ldc, int upper, int ntn, int64_t kchunk, double *work) {
-  __shared__ double As[2][BK][BM + PADD];
-  __shared__ double Bs[2][BK][BN + PADD];
+  __shared__ __attribute__((aligned(16))) double As[2][BM][KS];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BN][KS];
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so workgroup
   // b = 8 q + x runs on XCD x.  Each XCD takes whole 8 x 8 blocks of output tiles (super-block
   // s = 8 (q / 64) + x, tile q % 64 inside it): the tiles resident on one XCD at a time share 8 row
@@ -61,65 +110,8 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
 
   const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
-  double ra[8], rb[8];
-  auto load_a = [&](int64_t k0) {
-    if (TA) {  // A stored K x M
-      const int kk = tid >> 4, mm = (tid & 15) * 8;
-      const int64_t k = kbeg + k0 + kk;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t m = m0 + mm + q;
-        ra[q] = (k < kend && m < M) ? A[k * lda + m] : 0.0;
-      }
-    } else {  // A stored M x K
-      const int mm = tid >> 1, kk = (tid & 1) * 8;
-      const int64_t m = m0 + mm;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t k = kbeg + k0 + kk + q;
-        ra[q] = (k < kend && m < M) ? A[m * lda + k] : 0.0;
-      }
-    }
-  };
-  auto load_b = [&](int64_t k0) {
-    if (!TB) {  // B stored K x N
-      const int kk = tid >> 4, nn = (tid & 15) * 8;
-      const int64_t k = kbeg + k0 + kk;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t n = n0 + nn + q;
-        rb[q] = (k < kend && n < N) ? B[k * ldb + n] : 0.0;
-      }
-    } else {  // B stored N x K
-      const int nn = tid >> 1, kk = (tid & 1) * 8;
-      const int64_t n = n0 + nn;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t k = kbeg + k0 + kk + q;
-        rb[q] = (k < kend && n < N) ? B[n * ldb + k] : 0.0;
-      }
-    }
-  };
-  auto store_ab = [&](int buf) {
-    if (TA) {
-      const int kk = tid >> 4, mm = (tid & 15) * 8;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) As[buf][kk][mm + q] = ra[q];
-    } else {
-      const int mm = tid >> 1, kk = (tid & 1) * 8;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) As[buf][kk + q][mm] = ra[q];
-    }
-    if (!TB) {
-      const int kk = tid >> 4, nn = (tid & 15) * 8;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Bs[buf][kk][nn + q] = rb[q];
-    } else {
-      const int nn = tid >> 1, kk = (tid & 1) * 8;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) Bs[buf][kk + q][nn] = rb[q];
-    }
-  };
+  Slab<TA == 1> sa;  // A stored K x M when transposed
+  Slab<TB == 0> sbt;  // B stored K x N when not transposed
 
   v4d acc[4][4];
 #pragma unroll
@@ -128,30 +120,39 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
     for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
   const int64_t nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
-  load_a(0);
-  load_b(0);
-  store_ab(0);
+  sa.load(A, lda, m0, M, kbeg, kend, tid);
+  sbt.load(B, ldb, n0, N, kbeg, kend, tid);
+  sa.store(As[0], tid);
+  sbt.store(Bs[0], tid);
   __syncthreads();
+  const int r = lane & 15, q4 = (lane >> 4) * 4;
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = static_cast<int>(kt & 1);
     if (kt + 1 < nk) {
-      load_a((kt + 1) * BK);
-      load_b((kt + 1) * BK);
+      sa.load(A, lda, m0, M, kbeg + (kt + 1) * BK, kend, tid);
+      sbt.load(B, ldb, n0, N, kbeg + (kt + 1) * BK, kend, tid);
     }
+    // two k-steps per 16-byte read: halves 0 (k-steps 0, 1) and 1 (k-steps 2, 3) of the slab
 #pragma unroll
-    for (int k4 = 0; k4 < BK / 4; ++k4) {
-      const int kr = k4 * 4 + (lane >> 4);
-      double av[4], bv[4];
+    for (int hf = 0; hf < 2; ++hf) {
+      v2d av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+      for (int i = 0; i < 4; ++i) {
+        av[i] = *reinterpret_cast<const v2d *>(&As[buf][wm + i * 16 + r][q4 + 2 * hf]);
+        bv[i] = *reinterpret_cast<const v2d *>(&Bs[buf][wn + i * 16 + r][q4 + 2 * hf]);
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+      for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][s2], bv[j][s2], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) store_ab(buf ^ 1);
+    if (kt + 1 < nk) {
+      sa.store(As[buf ^ 1], tid);
+      sbt.store(Bs[buf ^ 1], tid);
+    }
     __syncthreads();
   }
   // Output layout of the f64 16x16 accumulator (measured on gfx950): lane l,
@@ -161,11 +162,11 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm + i * 16 + (lane >> 4) + 4 * e;
         const int64_t col = n0 + wn + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          double v = alpha * acc[i][j][r];
+          double v = alpha * acc[i][j][e];
           if (work) {
             work[static_cast<int64_t>(blockIdx.z) * M * N + row * N + col] = v;
           } else {
