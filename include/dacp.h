@@ -106,6 +106,8 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "filter_group_f64", "filter_group_f32"
  *                 filter column-group width when L >= 15 for the FP64 / FP32 recurrence
  *                 (power of two, defaults 8 and 8)
+ *   "blocked"     dense eigensolver: panel tridiagonalisation and compact-WY Q formation for
+ *                 n >= value (default 3500, at least 256; 0 = never)
  *   "dc"          dense eigensolver: eigenvectors by divide and conquer for n >= value
  *                 (default 96; 0 = always implicit QR with replayed rotations)
  * Results agree for every setting up to the rounding order of each element's sum.

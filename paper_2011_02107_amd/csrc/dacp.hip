@@ -1149,6 +1149,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->batch_workers = value;
     return DACP_OK;
   }
+  if (k == "blocked") {
+    if (value < 0) return set_err(ctx, DACP_E_INVALID, "blocked: size >= 0 (0 = never)");
+    ctx->blocked_min_n = value;
+    return DACP_OK;
+  }
   if (k == "project_whole") {
     if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "project_whole: 0 or 1");
     ctx->project_whole = value;
@@ -1194,6 +1199,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "rec_persist") *value = ctx->rec_persist;
   else if (k == "rec_xcd") *value = ctx->rec_xcd;
   else if (k == "project_whole") *value = ctx->project_whole;
+  else if (k == "blocked") *value = ctx->blocked_min_n;
   else if (k == "batch_workers") *value = ctx->batch_workers;
   else return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
   return DACP_OK;
@@ -1988,6 +1994,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     c.tile_elems = ctx->tile_elems;
     c.two_pass_min_L = ctx->two_pass_min_L;
     c.dc_min_n = ctx->dc_min_n;
+    c.blocked_min_n = ctx->blocked_min_n;
     DACP_HIP(ctx, hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   }
   auto worker = [&](int w) {

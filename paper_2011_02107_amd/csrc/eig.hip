@@ -404,7 +404,8 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
   DACP_HIP(ctx, hipMalloc(&db, sizeof(double) * n));
   DACP_HIP(ctx, hipMemsetAsync(db, 0, sizeof(double) * n, st));
   const int report_every = std::max(1, n / 4);
-  if (n >= 8 * kTB) {
+  const bool blocked = ctx->blocked_min_n > 0 && n >= std::max(ctx->blocked_min_n, 8 * kTB);
+  if (blocked) {
     DevBuf pv, pw, pxy;
     DACP_HIP(ctx, pv.alloc(sizeof(double) * n * kTB));
     DACP_HIP(ctx, pw.alloc(sizeof(double) * n * kTB));
@@ -444,7 +445,7 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
     DACP_HIP(ctx, hipGetLastError());
     DACP_HIP(ctx, hipStreamSynchronize(st));  // the panel buffers are released at scope end
   }
-  for (int k = (n >= 8 * kTB) ? n - 2 : 0; k < n - 2; ++k) {
+  for (int k = blocked ? n - 2 : 0; k < n - 2; ++k) {
     const int m = n - k - 1;
     if (verbose() && k > 0 && k % report_every == 0) {
       (void)hipStreamSynchronize(st);
@@ -474,7 +475,7 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
     const int64_t nn = static_cast<int64_t>(n) * n;
     hipLaunchKernelGGL(k_set_identity, dim3((nn + 255) / 256), dim3(256), 0, st, Zrows, (int64_t)n, n);
     constexpr int kQB = 64;  // reflectors per compact-WY block
-    if (n >= 4 * kQB) {
+    if (ctx->blocked_min_n > 0 && n >= std::max(ctx->blocked_min_n, 4 * kQB)) {
       // Qc <- Qc P_k for k = n-3 .. 0, a block of reflectors at a time (last block first):
       // P_k0 ... P_(k0+kb-1) = I - V T V^T (T upper triangular, T_jj = beta_j,
       // T[0:j, j] = -beta_j T[0:j, 0:j] (V[:, 0:j]^T v_j)), so Qc <- Qc - (Qc V) T^T V^T on the rows and

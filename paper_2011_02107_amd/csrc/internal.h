@@ -241,6 +241,8 @@ struct dacp_ctx_s {
   int filter_group_f32 = 8;    // filter column-group width for L >= 15, FP32 recurrence (its FP64 tail
                                // runs on the same groups, and the fused chain needs 8 FP64 columns)
   int dc_min_n = 96;           // eigenvectors by divide and conquer from this size on (0 = never)
+  int blocked_min_n = 3500;    // blocked tridiagonalisation and compact-WY Q from this size on (0 = never);
+                               // below it the unblocked form issues fewer launches and is faster
 };
 
 struct dacp_ham_s {

@@ -490,6 +490,18 @@ def test_syev_divide_and_conquer_random(ctx, n):
     _check_eig(ctx, A + A.T)
 
 
+@pytest.mark.parametrize("n", [300, 1000, 2047])
+def test_syev_blocked_tridiagonalisation(ctx, n):
+    """The panel tridiagonalisation and compact-WY Q formation (the default from n = 3500 on)
+    forced at smaller sizes, including a ragged last panel."""
+    A = np.random.default_rng(n + 5).standard_normal((n, n))
+    try:
+        ctx.tune("blocked", 256)
+        _check_eig(ctx, A + A.T)
+    finally:
+        ctx.tune("blocked", 3500)
+
+
 def test_syev_divide_and_conquer_deflation_cases(ctx):
     n = 300
     rng = np.random.default_rng(1)
