@@ -29,6 +29,9 @@ HBM_PEAK_GBPS = 8000.0
 EVOLUTION_KERNELS = "k_rec_lo/k_rec_hi v5"
 # key: (workload, kernel build, group, threads, fused tile, high-tile rows knob, XCD tile order knob)
 MEASURED_TRAFFIC = {("chain_L20_N5000", EVOLUTION_KERNELS, 8, 1024, 8192, 0, 2): 279.67e6}
+# Filter chain: counted bytes per order of one 8-column group (low + high kernel), FP32 and FP64 orders;
+# key: (workload, kernel build, FP32 filter group, FP64 filter group).
+FILTER_TRAFFIC_PER_ORDER = {("chain_L20_N5000", EVOLUTION_KERNELS, 8, 8): {"fp32": 306.3e6, "fp64": 628.0e6}}
 
 
 def parse():
@@ -138,8 +141,13 @@ def profile_kernels(args):
     a_r = math.pi / 64.0  # k_1 = 64 evolution steps
     B.dacp_basis(ctx, ham, psi, V, eb, a_r * eb, n, group=g)
     torch.cuda.synchronize()
+    # the filter chain on one group: 24 FP32 orders, then 8 FP64 orders (fused low/high kernels)
+    fout = torch.empty((D, g), dtype=torch.float64, device="cuda")
+    B.dacp_filter(ctx, ham, fout, eb, 0.05 * eb, 32, start=psi, precision=B.DACP_F32, fp64_tail=8)
+    torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "evolution_steps": 64, "group": g, "L": L,
-                      "algorithmic_bytes_per_step": 3 * D * g * 8, "e_bound": eb}), flush=True)
+                      "algorithmic_bytes_per_step": 3 * D * g * 8, "e_bound": eb,
+                      "filter_orders": {"fp32": 24, "fp64": 8}}), flush=True)
 
 
 def batch96(args):
@@ -312,9 +320,12 @@ def main():
     bytes_per_launch = 3.0 * D * g * 8
     evol_launch_ms = rep["evol_kernel_ms"] / max(1, rep["evol_launches"])
     achieved = bytes_per_launch / (evol_launch_ms * 1e-3) / 1e9
-    # filter: 2 launches per order; per order 5 D b s algorithmic bytes (w round trip included)
-    s_bytes = 4 if opts.precision == B.DACP_F32 else 8
-    filter_gbps = 5.0 * D * rep["b"] * s_bytes * rep["K"] / (rep["t_filter_ms"] * 1e-3) / 1e9
+    # filter: per order 5 D b s algorithmic bytes (w round trip included); s = 4 for the FP32 orders
+    # and 8 for the FP64 tail (all orders FP64 in plain mode)
+    K = rep["K"]
+    k64 = min(K, math.ceil(opts.fp64_tail_frac * K)) if opts.precision == B.DACP_F32 else K
+    filter_bytes = 5.0 * D * rep["b"] * (4 * (K - k64) + 8 * k64)
+    filter_gbps = filter_bytes / (rep["t_filter_ms"] * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": n_ok / dt,
@@ -362,6 +373,14 @@ def main():
                                           "t_accept_ms", "t_total_ms")},
         "filter_algorithmic_GBps": filter_gbps,
     }
+    # counted filter bytes per order (FETCH_SIZE + WRITE_SIZE, fused chain, 8-column groups at L = 20)
+    fb = FILTER_TRAFFIC_PER_ORDER.get((args.workload, EVOLUTION_KERNELS, ctx.tune_get("filter_group_f32"),
+                                       ctx.tune_get("filter_group_f64")))
+    if fb is not None:
+        groups = rep["b"] // 8
+        counted = groups * (fb["fp32"] * (K - k64) + fb["fp64"] * k64)
+        out["filter_counted"] = {"bytes": counted, "GBps": counted / (rep["t_filter_ms"] * 1e-3) / 1e9,
+                                 "bytes_per_order_per_group": fb}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, rep, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)
