@@ -266,6 +266,10 @@ def fp32_tail_table(args):
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form (start columns "
+              "sharded across GPUs, V panels passed around a ring for S and P) is not built", file=sys.stderr)
+        sys.exit(2)
     if args.profile_kernels:
         return profile_kernels(args)
     if args.workload == "glass_batch96_N200":
@@ -274,10 +278,6 @@ def main():
         return glass18_learned(args)
     if args.workload == "fp32_tail_table":
         return fp32_tail_table(args)
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
-        sys.exit(2)
     import numpy as np
     import torch
 
