@@ -354,7 +354,7 @@ dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, co
  * ceil(window_ratio N) levels.  If the call then fails with DACP_E_BOUNDS (E_b below ||H||),
  * DACP_E_NUMERIC (a filter overflow from such a bound) or DACP_E_WINDOW (too few accepted
  * values), it is redone with the Lanczos / KPM estimates
- * (report->model_fallback = 1): the method's own estimators are the fallback and the judge. */
+ * (report->model_fallback = 1): the method's own estimators are both the fallback and the check. */
 dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, double bound_margin, int N,
                                       const dacp_opts *opts, double *eigs_out, double *err_out, int *n_out,
                                       dacp_report *report);
