@@ -101,7 +101,9 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "rec_xcd"     fused recurrence tile order, bit 0 for the low pass and bit 1 for the high
  *                 pass: set = each of the 8 XCDs takes a contiguous eighth of the tiles, clear =
  *                 tiles dealt round-robin in launch order (default 2: high pass only)
- *   "batch_workers" host threads finishing the realisations of dacp_central_eigs_batched (1..64, default 8)
+ *   "batch_workers" host threads finishing the realisations of dacp_central_eigs_batched (1..64, default 16)
+ *   "batch_eig"   dacp_central_eigs_batched: 1 = the finishing threads' dense eigen-decompositions are
+ *                 collected and solved in batched launches (default), 0 = one solver per problem
  *   "group"       evolution column-group width when L >= 15 (power of two, default 8)
  *   "filter_group_f64", "filter_group_f32"
  *                 filter column-group width when L >= 15 for the FP64 / FP32 recurrence
@@ -225,6 +227,16 @@ dacp_status dacp_rayleigh_ritz(dacp_ctx ctx, int m, const double *S, const doubl
  * replayed on the GPU; eigenvalues only: implicit QR): A device n x n (ld),
  * destroyed; w host ascending; Zrows device n x n (row j = eigenvector j) or NULL. */
 dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
+
+/* The same decomposition for `count` matrices in one launch, one workgroup per matrix (App. C's
+ * two eigen-decompositions for many small subspace problems, the batched-realisation path):
+ * Householder tridiagonalisation, implicit symmetric QR with a Wilkinson shift, Householder Q.
+ * n[i] (host): 1 <= n[i] <= 2048.  A[i] (host array of device pointers): symmetric n[i] x n[i],
+ * row-major, ld n[i], destroyed.  w[i] (host array of host pointers): n[i] eigenvalues ascending.
+ * Z[i] (host array of device pointers, entries may be NULL): n[i] x n[i], row j = eigenvector j.
+ * Errors: DACP_E_INVALID (sizes, null pointers), DACP_E_CONVERGENCE (QR did not converge). */
+dacp_status dacp_syev_batched(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                              double *const *Z);
 
 /* C = alpha op(A) op(B) + beta C in FP64 on the matrix cores (row-major;
  * op(A) is M x K: A stored M x K when transA = 0, K x M when transA = 1;

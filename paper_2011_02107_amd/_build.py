@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdacp.so")
-SOURCES = ["kernels.hip", "gemm.hip", "eig.hip", "dc.hip", "batch.hip", "mlp.hip", "dacp.hip"]
+SOURCES = ["kernels.hip", "gemm.hip", "eig.hip", "dc.hip", "batch.hip", "beig.hip", "mlp.hip", "dacp.hip"]
 FLAGS = [
     "-O3",
     "-std=c++17",

@@ -139,6 +139,7 @@ SIGNATURES = {
     "dacp_project": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i64, _vp, _vp, _i64]),
     "dacp_rayleigh_ritz": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, ctypes.c_double, _dp, _vp, _ip]),
     "dacp_syev": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _dp, _vp]),
+    "dacp_syev_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "dacp_gemm": (
         ctypes.c_int,
         [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _vp, _i64, ctypes.c_double, _vp, _i64],
@@ -338,6 +339,19 @@ def dacp_syev(ctx, A, Z=None):
     w = np.zeros(n)
     ctx.check(ctx.lib.dacp_syev(ctx.handle, n, _ptr(A), int(A.shape[1]), _f64(w), _ptr(Z)))
     return w
+
+
+def dacp_syev_batched(ctx, As, Zs=None):
+    """Eigen-decompositions of square device matrices `As` (destroyed) in one launch; returns the
+    list of ascending eigenvalue arrays.  Zs: matching device matrices for the eigenvectors (rows)."""
+    count = len(As)
+    ns = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
+    ws = [np.zeros(int(a.shape[0])) for a in As]
+    a_ptrs = (_vp * count)(*[_ptr(a) for a in As])
+    w_ptrs = (_vp * count)(*[w.ctypes.data_as(_vp) for w in ws])
+    z_ptrs = (_vp * count)(*[(_ptr(z) if z is not None else None) for z in (Zs or [None] * count)])
+    ctx.check(ctx.lib.dacp_syev_batched(ctx.handle, count, ns, a_ptrs, w_ptrs, z_ptrs))
+    return ws
 
 
 def dacp_gemm(ctx, transA, transB, A, B, C, alpha=1.0, beta=0.0):

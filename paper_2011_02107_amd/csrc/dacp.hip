@@ -7,8 +7,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <set>
 #include <numeric>
 #include <type_traits>
@@ -862,15 +865,21 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
 }
 
 // ----------------------------------------------------- Rayleigh-Ritz (App. C)
+// A dense symmetric eigensolver (n, A device n x n destroyed, w host ascending, Zrows device or null).
+typedef std::function<dacp_status(int, double *, double *, double *)> EigFn;
+
 dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_t ld, double eps,
-                   std::vector<double> &theta, DevBuf *bc_out, int *r_out) {
+                   std::vector<double> &theta, DevBuf *bc_out, int *r_out, const EigFn *eig = nullptr) {
+  auto solve = [&](int n, double *A, double *w, double *Z) -> dacp_status {
+    return eig ? (*eig)(n, A, w, Z) : dacp::gpu_syev(ctx, n, A, n, w, Z);
+  };
   hipStream_t s = ctx->stream;
   DevBuf awork, zs;
   DACP_HIP(ctx, awork.alloc(static_cast<size_t>(m) * m * sizeof(double)));
   DACP_HIP(ctx, zs.alloc(static_cast<size_t>(m) * m * sizeof(double)));
   DACP_HIP(ctx, dacp::launch_copy_cols(S, ld, awork.as<double>(), m, m, m, s));
   std::vector<double> lam(m);
-  dacp_status st = dacp::gpu_syev(ctx, m, awork.as<double>(), m, lam.data(), zs.as<double>());
+  dacp_status st = solve(m, awork.as<double>(), lam.data(), zs.as<double>());
   if (st) return st;
   int i0 = 0;
   while (i0 < m && !(lam[i0] > eps)) ++i0;
@@ -905,7 +914,7 @@ dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_
   theta.assign(r, 0.0);
   const bool want_b = bc_out != nullptr;
   if (want_b) DACP_HIP(ctx, yc.alloc(static_cast<size_t>(r) * r * sizeof(double)));
-  st = dacp::gpu_syev(ctx, r, ht.as<double>(), r, theta.data(), want_b ? yc.as<double>() : nullptr);
+  st = solve(r, ht.as<double>(), theta.data(), want_b ? yc.as<double>() : nullptr);
   if (st) return st;
   if (want_b) {
     // rows of B^T: Bc = Yc Uc  (r x m)
@@ -1149,6 +1158,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->batch_workers = value;
     return DACP_OK;
   }
+  if (k == "batch_eig") {
+    if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "batch_eig: 0 or 1");
+    ctx->batch_eig = value;
+    return DACP_OK;
+  }
   if (k == "blocked") {
     if (value < 0) return set_err(ctx, DACP_E_INVALID, "blocked: size >= 0 (0 = never)");
     ctx->blocked_min_n = value;
@@ -1200,6 +1214,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "rec_xcd") *value = ctx->rec_xcd;
   else if (k == "project_whole") *value = ctx->project_whole;
   else if (k == "blocked") *value = ctx->blocked_min_n;
+  else if (k == "batch_eig") *value = ctx->batch_eig;
   else if (k == "batch_workers") *value = ctx->batch_workers;
   else return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
   return DACP_OK;
@@ -1399,6 +1414,15 @@ dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, dou
   return dacp::gpu_syev(ctx, n, A, ld, w, Zrows);
 }
 
+dacp_status dacp_syev_batched(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                              double *const *Z) {
+  if (!ctx || count < 0 || (count > 0 && (!n || !A || !w || !Z))) return set_err(ctx, DACP_E_INVALID, "syev_batched: args");
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 1 || n[i] > dacp::kBatchEigMaxN || !A[i] || !w[i])
+      return set_err(ctx, DACP_E_INVALID, "syev_batched: need 1 <= n <= 2048 and A, w for every matrix");
+  return dacp::batch_syev(ctx, count, n, A, w, Z);
+}
+
 dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc) {
   if (!ctx || M < 0 || N < 0 || K < 0 || !C) return set_err(ctx, DACP_E_INVALID, "gemm: args");
@@ -1462,7 +1486,7 @@ Plan make_plan(const dacp_opts &o, int64_t D, int N, double e_b, const std::vect
 // contiguous accepted core; when it reaches N the N values and their estimates are written.
 dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
                          double norm_est, const double *V, int m, dacp_report &rep, double *eigs_out, double *err_out,
-                         int &accepted) {
+                         int &accepted, const EigFn *eig = nullptr) {
   const int64_t D = h->D;
   hipStream_t s = ctx->stream;
   (void)norm_est;
@@ -1482,7 +1506,7 @@ dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, do
   std::vector<double> theta;
   DevBuf bc;
   int r = 0;
-  st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r);
+  st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r, eig);
   if (st) return st;
   sb.release();
   pb.release();
@@ -1855,6 +1879,62 @@ dacp_status batched_estimates(dacp_ctx ctx, int count, const dacp_ham *hams, con
 }
 }  // namespace
 
+// The dense eigen-decompositions of the workers that finish batched realisations, collected and
+// solved as one batched launch (one workgroup per matrix) once every worker still running waits on
+// one.  Matrices above the batched solver's size limit go through the per-problem solver.
+class EigRendezvous {
+ public:
+  explicit EigRendezvous(int workers) : active_(workers) {}
+  dacp_status solve(dacp_ctx ctx, int n, double *A, double *w, double *Z) {
+    if (n > dacp::kBatchEigMaxN) return dacp::gpu_syev(ctx, n, A, n, w, Z);
+    DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // A was written on this worker's stream
+    std::unique_lock<std::mutex> lk(mu_);
+    Req r{ctx, n, A, w, Z, false, DACP_OK};
+    pending_.push_back(&r);
+    if (static_cast<int>(pending_.size()) == active_) run_locked(ctx);
+    cv_.wait(lk, [&] { return r.done; });
+    return r.st;
+  }
+  // a worker has no further requests
+  void leave(dacp_ctx ctx) {
+    std::unique_lock<std::mutex> lk(mu_);
+    --active_;
+    if (active_ > 0 && !pending_.empty() && static_cast<int>(pending_.size()) == active_) run_locked(ctx);
+  }
+
+ private:
+  struct Req {
+    dacp_ctx ctx;
+    int n;
+    double *A, *w, *Z;
+    bool done;
+    dacp_status st;
+  };
+  void run_locked(dacp_ctx ctx) {
+    const int c = static_cast<int>(pending_.size());
+    std::vector<int> n(c);
+    std::vector<double *> A(c), w(c), Z(c);
+    for (int i = 0; i < c; ++i) {
+      n[i] = pending_[i]->n;
+      A[i] = pending_[i]->A;
+      w[i] = pending_[i]->w;
+      Z[i] = pending_[i]->Z;
+    }
+    const dacp_status st = dacp::batch_syev(ctx, c, n.data(), A.data(), w.data(), Z.data());
+    for (Req *r : pending_) {
+      r->st = st;
+      if (st != DACP_OK && r->ctx != ctx) r->ctx->err = ctx->err;
+      r->done = true;
+    }
+    pending_.clear();
+    cv_.notify_all();
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::vector<Req *> pending_;
+  int active_;
+};
+
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports) {
   if (!ctx || count < 1 || !hams || !eigs_out || !n_out)
@@ -1997,16 +2077,23 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     c.blocked_min_n = ctx->blocked_min_n;
     DACP_HIP(ctx, hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   }
+  EigRendezvous rendezvous(nw);
   auto worker = [&](int w) {
     (void)hipSetDevice(ctx->device);
+    dacp_ctx wc = &wctx[w];
+    const EigFn eig = [&rendezvous, wc](int n, double *A, double *lam, double *Z) {
+      return rendezvous.solve(wc, n, A, lam, Z);
+    };
     for (int r = w; r < count; r += nw) {
       const Plan &pl = plans[r];
-      wst[r] = finish_basis(&wctx[w], hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
+      wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
                             eigs_out + static_cast<int64_t>(r) * N,
-                            err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
+                            err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r],
+                            ctx->batch_eig ? &eig : nullptr);
       if (wst[r]) werr[r] = wctx[w].err;
       vb[r].release();
     }
+    rendezvous.leave(wc);
   };
   std::vector<std::thread> threads;
   for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);

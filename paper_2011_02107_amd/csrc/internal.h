@@ -142,6 +142,21 @@ struct BatchSpec {
 };
 hipError_t launch_batch_spectral(const BatchSpec *specs, int n, int max_L, hipStream_t s);
 
+// One problem of the batched dense eigensolver (beig.hip): A (n x n, ld n) is destroyed; Zr gets
+// the tridiagonal's eigenvectors as rows (unsorted), Q the Householder product, w the eigenvalues
+// (unsorted, w[j] pairs with row j of Zr); beta holds n reflector scalars; status 0 = converged.
+struct BatchEigProblem {
+  double *A;
+  double *Zr;
+  double *Q;
+  double *w;
+  double *beta;
+  int *status;
+  int n;
+};
+constexpr int kBatchEigMaxN = 2048;
+hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s);
+
 // Launch helpers (kernels.hip).
 template <typename T>
 hipError_t launch_rec_lo(const RecArgs<T> &a, hipStream_t s);
@@ -233,10 +248,11 @@ struct dacp_ctx_s {
   int rec_threads = 1024;      // fused recurrence: threads per workgroup (512 or 1024)
   int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
+  int batch_eig = 1;           // batched realisations: dense eigen-decompositions in batched launches
   int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)
   int rec_xcd = 2;             // fused recurrence: XCD-contiguous tile order, bit 0 low pass, bit 1 high pass
   int num_cus = 256;           // compute units of the device
-  int batch_workers = 8;       // host threads (each with its own stream) finishing batched realisations
+  int batch_workers = 16;      // host threads (each with its own stream) finishing batched realisations
   int filter_group_f64 = 8;    // filter column-group width for L >= 15, FP64 recurrence
   int filter_group_f32 = 8;    // filter column-group width for L >= 15, FP32 recurrence (its FP64 tail
                                // runs on the same groups, and the fused chain needs 8 FP64 columns)
@@ -284,6 +300,10 @@ bool verbose();
 void vlog(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 // Dense symmetric eigensolver (eig.hip).
 dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, double *Zrows);
+// Batched form (beig.hip): count matrices A[i] (device, n[i] x n[i], ld n[i], destroyed, n <= 2048)
+// in one launch; w[i] (host) ascending; Zrows[i] (device, n x n, may be null) row j = eigenvector j.
+dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                       double *const *Zrows);
 bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z);
 dacp_status dc_tridiag(dacp_ctx ctx, int n, const double *d, const double *e, double *w, double *Z);
 }  // namespace dacp

@@ -502,6 +502,38 @@ def test_syev_blocked_tridiagonalisation(ctx, n):
         ctx.tune("blocked", 3500)
 
 
+def test_syev_batched_matches_oracle(ctx):
+    """One launch, one workgroup per matrix, mixed sizes (1, 2, 3 and odd sizes up to 700), including a
+    diagonal and a repeated-eigenvalue matrix; eigenvalues against the oracle's eigensolver,
+    eigenvectors through A Z^T = Z^T diag(w) and orthonormality."""
+    rng = np.random.default_rng(21)
+    mats = []
+    for n in (1, 2, 3, 17, 130, 257, 700):
+        X = rng.standard_normal((n, n))
+        mats.append(X + X.T)
+    mats.append(np.diag(rng.standard_normal(40)))
+    u = rng.standard_normal((60, 2))
+    mats.append(np.eye(60) + u @ u.T)
+    As = [to_dev(A) for A in mats]
+    Zs = [torch.zeros(A.shape, dtype=torch.float64, device=DEV) for A in mats]
+    ws = B.dacp_syev_batched(ctx, As, Zs)
+    for A, w, Z in zip(mats, ws, Zs):
+        n = A.shape[0]
+        w_ref = _native.syev(A)
+        scale = max(1.0, np.abs(w_ref).max())
+        assert np.abs(w - w_ref).max() < 1e-12 * scale * max(1, n) ** 0.5
+        Zr = host(Z)
+        assert np.abs(Zr @ A @ Zr.T - np.diag(w)).max() < 1e-12 * scale * n
+        assert np.abs(Zr @ Zr.T - np.eye(n)).max() < 1e-13 * n
+
+
+def test_syev_batched_rejects_large(ctx):
+    A = torch.zeros((2049, 2049), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.DacpError) as ei:
+        B.dacp_syev_batched(ctx, [A])
+    assert ei.value.status == -1
+
+
 def test_syev_divide_and_conquer_deflation_cases(ctx):
     n = 300
     rng = np.random.default_rng(1)
@@ -619,6 +651,29 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
             # the batched Lanczos bound equals the single-realisation one up to reduction order
             eb, _, _ = B.dacp_spectral_bound(ctx, hams[r], steps=80, seed=0x5BD1E995)
             assert abs(reps[r]["e_bound"] - eb) <= 1e-9 * eb
+
+
+def test_central_eigs_batched_per_problem_eigensolver(ctx):
+    """The batched path with the finishing threads' eigen-decompositions solved one by one (knob
+    batch_eig = 0) gives the same eigenvalues as the batched eigensolver path, both at the oracle."""
+    N = 40
+    specs = [(8, 11), (10, 12), (9, 13)]
+    hams, refs = [], []
+    for L, seed in specs:
+        terms = inputs.spin_glass(L, seed)
+        refs.append(central.central_eigenvalues(L, terms, N))
+        hams.append(B.dacp_build_hamiltonian(ctx, L, terms))
+    opts = B.default_opts(b=8)
+    e1, _, n1, _, st1 = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+    try:
+        ctx.tune("batch_eig", 0)
+        e0, _, n0, _, st0 = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+    finally:
+        ctx.tune("batch_eig", 1)
+    assert st0 == 0 and st1 == 0 and np.all(n0 == N) and np.all(n1 == N)
+    for r, (ref, norm) in enumerate(refs):
+        _check_central(e0[r], ref, norm, N)
+        _check_central(e1[r], ref, norm, N)
 
 
 def test_central_eigs_batched_L14_and_L12(ctx):
