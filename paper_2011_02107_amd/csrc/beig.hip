@@ -236,10 +236,11 @@ hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n,
   return hipGetLastError();
 }
 
-// Host side: eigen-decompositions of `count` symmetric matrices A[i] (device, n[i] x n[i], ld n[i],
-// destroyed) in one launch.  w[i] (host) ascending; Zrows[i] (device, n x n) row j = eigenvector j.
-dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
-                       double *const *Zrows) {
+// Host side, first half: one launch over `count` matrices A[i] (device, n[i] x n[i], ld n[i],
+// destroyed); Zr[i], Q[i] (device, n x n) receive the tridiagonal's eigenvectors (rows, unsorted)
+// and the Householder product, w[i] (host) the eigenvalues in the same unsorted order.
+dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
+                           double *const *Q, double *const *w) {
   if (count <= 0) return DACP_OK;
   hipStream_t st = ctx->stream;
   int max_n = 0;
@@ -249,7 +250,7 @@ dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, 
     if (n[i] < 1 || n[i] > kBatchEigMaxN) return set_err(ctx, DACP_E_INVALID, "batch_syev: 1 <= n <= 2048");
     max_n = std::max(max_n, n[i]);
     off[i] = total;
-    total += 2 * static_cast<size_t>(n[i]) * n[i] + 2 * static_cast<size_t>(n[i]);  // Zr, Q, w, beta
+    total += 2 * static_cast<size_t>(n[i]);  // w, beta
   }
   DevBuf work, dprobs, dstat;
   DACP_HIP(ctx, work.alloc(total * sizeof(double)));
@@ -257,13 +258,12 @@ dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, 
   DACP_HIP(ctx, hipMemsetAsync(dstat.p, 0, sizeof(int) * count, st));
   std::vector<BatchEigProblem> probs(count);
   for (int i = 0; i < count; ++i) {
-    const size_t nn = static_cast<size_t>(n[i]) * n[i];
     double *base = work.as<double>() + off[i];
     probs[i].A = A[i];
-    probs[i].Zr = base;
-    probs[i].Q = base + nn;
-    probs[i].w = base + 2 * nn;
-    probs[i].beta = base + 2 * nn + n[i];
+    probs[i].Zr = Zr[i];
+    probs[i].Q = Q[i];
+    probs[i].w = base;
+    probs[i].beta = base + n[i];
     probs[i].status = dstat.as<int>() + i;
     probs[i].n = n[i];
   }
@@ -274,24 +274,57 @@ dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, 
   DACP_TRY(to_host(ctx, status.data(), dstat.p, sizeof(int) * count));
   for (int i = 0; i < count; ++i)
     if (status[i] != 0) return set_err(ctx, DACP_E_CONVERGENCE, "batch_syev: QR iteration did not converge");
-  // ascending order, then the eigenvectors of A as rows of (P Zr) Q^T
-  DevBuf tmp, dperm;
-  DACP_HIP(ctx, tmp.alloc(sizeof(double) * static_cast<size_t>(max_n) * max_n));
-  DACP_HIP(ctx, dperm.alloc(sizeof(int) * max_n));
+  std::vector<double> all(total);
+  DACP_TRY(to_host(ctx, all.data(), work.p, total * sizeof(double)));
+  for (int i = 0; i < count; ++i) std::copy(all.begin() + off[i], all.begin() + off[i] + n[i], w[i]);
+  return DACP_OK;
+}
+
+// Second half, for one matrix on the caller's stream: eigenvalues ascending into w_out and, if
+// Zrows is set, the eigenvectors of A as its rows: Y = Zr Q^T (written over the destroyed A), then
+// the rows of Y in ascending order of the eigenvalues.
+dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr, const double *Q,
+                              double *w_out, double *Zrows) {
+  hipStream_t st = ctx->stream;
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return w_raw[a] < w_raw[b]; });
+  for (int j = 0; j < n; ++j) w_out[j] = w_raw[perm[j]];
+  if (!Zrows) return DACP_OK;
+  DevBuf dperm;
+  DACP_HIP(ctx, dperm.alloc(sizeof(int) * n));
+  DACP_TRY(to_device(ctx, dperm.p, perm.data(), sizeof(int) * n));
+  DACP_HIP(ctx, launch_dgemm(0, 1, n, n, n, 1.0, Zr, n, Q, n, 0.0, A, n, 0, st));
+  DACP_HIP(ctx, launch_gather_rows(A, n, Zrows, n, dperm.as<int>(), nullptr, n, n, st));
+  DACP_HIP(ctx, hipStreamSynchronize(st));  // dperm is released on return
+  return DACP_OK;
+}
+
+// Both halves: eigen-decompositions of `count` symmetric matrices A[i] (device, n[i] x n[i], ld n[i],
+// destroyed) in one launch.  w[i] (host) ascending; Zrows[i] (device, n x n) row j = eigenvector j.
+dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                       double *const *Zrows) {
+  if (count <= 0) return DACP_OK;
+  size_t total = 0;
+  std::vector<size_t> off(count);
   for (int i = 0; i < count; ++i) {
-    const int ni = n[i];
-    std::vector<double> d(ni);
-    DACP_TRY(to_host(ctx, d.data(), probs[i].w, sizeof(double) * ni));
-    std::vector<int> perm(ni);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return d[a] < d[b]; });
-    for (int j = 0; j < ni; ++j) w[i][j] = d[perm[j]];
-    if (!Zrows[i]) continue;
-    DACP_TRY(to_device(ctx, dperm.p, perm.data(), sizeof(int) * ni));
-    DACP_HIP(ctx, launch_gather_rows(probs[i].Zr, ni, tmp.as<double>(), ni, dperm.as<int>(), nullptr, ni, ni, st));
-    DACP_HIP(ctx, launch_dgemm(0, 1, ni, ni, ni, 1.0, tmp.as<double>(), ni, probs[i].Q, ni, 0.0, Zrows[i], ni, 0, st));
-    DACP_HIP(ctx, hipStreamSynchronize(st));  // tmp and dperm are reused by the next problem
+    if (n[i] < 1 || n[i] > kBatchEigMaxN) return set_err(ctx, DACP_E_INVALID, "batch_syev: 1 <= n <= 2048");
+    off[i] = total;
+    total += 2 * static_cast<size_t>(n[i]) * n[i];
   }
+  DevBuf scratch;
+  DACP_HIP(ctx, scratch.alloc(total * sizeof(double)));
+  std::vector<double *> zr(count), q(count), wr(count);
+  std::vector<std::vector<double>> wraw(count);
+  for (int i = 0; i < count; ++i) {
+    zr[i] = scratch.as<double>() + off[i];
+    q[i] = zr[i] + static_cast<size_t>(n[i]) * n[i];
+    wraw[i].resize(n[i]);
+    wr[i] = wraw[i].data();
+  }
+  DACP_TRY(batch_syev_raw(ctx, count, n, A, zr.data(), q.data(), wr.data()));
+  for (int i = 0; i < count; ++i)
+    DACP_TRY(batch_syev_finish(ctx, n[i], wr[i], A[i], zr[i], q[i], w[i], Zrows[i]));
   return DACP_OK;
 }
 

@@ -865,6 +865,55 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
 }
 
 // ----------------------------------------------------- Rayleigh-Ritz (App. C)
+// App. C after the eigen-decomposition of S (lam ascending, zs rows = eigenvectors): drop the
+// eigenvalues at or below eps, U = V~ Lambda~^(-1/2) stored as the rows of uc (r x m), and
+// H~ = U^T P U (r x r, symmetrised) in ht.
+dacp_status rr_reduce(dacp_ctx ctx, int m, const std::vector<double> &lam, const double *zs, const double *P,
+                      int64_t ld, double eps, DevBuf &uc, DevBuf &ht, int *r_out) {
+  hipStream_t s = ctx->stream;
+  int i0 = 0;
+  while (i0 < m && !(lam[i0] > eps)) ++i0;
+  const int r = m - i0;
+  if (r == 0) return set_err(ctx, DACP_E_NUMERIC, "overlap matrix S has no eigenvalue above eps");
+  std::vector<int> perm(r);
+  std::vector<double> scale(r);
+  for (int t = 0; t < r; ++t) {
+    perm[t] = i0 + t;
+    scale[t] = 1.0 / std::sqrt(lam[i0 + t]);
+  }
+  DevBuf dperm, dscale, t1;
+  DACP_HIP(ctx, dperm.alloc(sizeof(int) * r));
+  DACP_HIP(ctx, dscale.alloc(sizeof(double) * r));
+  DACP_TRY(to_device(ctx, dperm.p, perm.data(), sizeof(int) * r));
+  DACP_TRY(to_device(ctx, dscale.p, scale.data(), sizeof(double) * r));
+  DACP_HIP(ctx, uc.alloc(static_cast<size_t>(r) * m * sizeof(double)));
+  DACP_HIP(ctx, dacp::launch_gather_rows(zs, m, uc.as<double>(), m, dperm.as<int>(), dscale.as<double>(), r, m, s));
+  // H~ = U^T P U with U = columns of Uc^T:  T1 = Uc P (r x m),  H~ = T1 Uc^T (r x r).
+  DACP_HIP(ctx, t1.alloc(static_cast<size_t>(r) * m * sizeof(double)));
+  DACP_HIP(ctx, dacp::launch_dgemm(0, 0, r, m, m, 1.0, uc.as<double>(), m, P, ld, 0.0, t1.as<double>(), m, 0, s));
+  DACP_HIP(ctx, ht.alloc(static_cast<size_t>(r) * r * sizeof(double)));
+  DACP_HIP(ctx, dacp::launch_dgemm(0, 1, r, r, m, 1.0, t1.as<double>(), m, uc.as<double>(), m, 0.0, ht.as<double>(), r,
+                                   0, s));
+  DACP_HIP(ctx, dacp::launch_symmetrize(ht.as<double>(), r, r, s));
+  DACP_HIP(ctx, hipStreamSynchronize(s));  // dperm, dscale, t1 are released on return
+  *r_out = r;
+  return DACP_OK;
+}
+
+// App. C after the eigen-decomposition of H~ (theta ascending, yc rows = eigenvectors): the rows of
+// B^T, Bc = Yc Uc (r x m), and a finiteness check of the Ritz values.
+dacp_status rr_back(dacp_ctx ctx, int m, int r, const double *yc, const double *uc, const std::vector<double> &theta,
+                    DevBuf *bc_out) {
+  if (bc_out) {
+    DACP_HIP(ctx, bc_out->alloc(static_cast<size_t>(r) * m * sizeof(double)));
+    DACP_HIP(ctx, dacp::launch_dgemm(0, 0, r, m, r, 1.0, yc, r, uc, m, 0.0, bc_out->as<double>(), m, 0, ctx->stream));
+    DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  for (double t : theta)
+    if (!std::isfinite(t)) return set_err(ctx, DACP_E_NUMERIC, "non-finite Ritz value");
+  return DACP_OK;
+}
+
 // A dense symmetric eigensolver (n, A device n x n destroyed, w host ascending, Zrows device or null).
 typedef std::function<dacp_status(int, double *, double *, double *)> EigFn;
 
@@ -881,50 +930,19 @@ dacp_status run_rr(dacp_ctx ctx, int m, const double *S, const double *P, int64_
   std::vector<double> lam(m);
   dacp_status st = solve(m, awork.as<double>(), lam.data(), zs.as<double>());
   if (st) return st;
-  int i0 = 0;
-  while (i0 < m && !(lam[i0] > eps)) ++i0;
-  const int r = m - i0;
-  if (r == 0) return set_err(ctx, DACP_E_NUMERIC, "overlap matrix S has no eigenvalue above eps");
-  std::vector<int> perm(r);
-  std::vector<double> scale(r);
-  for (int t = 0; t < r; ++t) {
-    perm[t] = i0 + t;
-    scale[t] = 1.0 / std::sqrt(lam[i0 + t]);
-  }
-  DevBuf dperm, dscale, uc, t1, ht, yc;
-  DACP_HIP(ctx, dperm.alloc(sizeof(int) * r));
-  DACP_HIP(ctx, dscale.alloc(sizeof(double) * r));
-  DACP_TRY(to_device(ctx, dperm.p, perm.data(), sizeof(int) * r));
-  DACP_TRY(to_device(ctx, dscale.p, scale.data(), sizeof(double) * r));
-  DACP_HIP(ctx, uc.alloc(static_cast<size_t>(r) * m * sizeof(double)));
-  DACP_HIP(ctx, dacp::launch_gather_rows(zs.as<double>(), m, uc.as<double>(), m, dperm.as<int>(), dscale.as<double>(),
-                                         r, m, s));
-  DACP_HIP(ctx, hipStreamSynchronize(s));
+  DevBuf uc, ht, yc;
+  int r = 0;
+  st = rr_reduce(ctx, m, lam, zs.as<double>(), P, ld, eps, uc, ht, &r);
+  if (st) return st;
   zs.release();
   awork.release();
-  // H~ = U^T P U with U = columns of Uc^T:  T1 = Uc P (r x m),  H~ = T1 Uc^T (r x r).
-  DACP_HIP(ctx, t1.alloc(static_cast<size_t>(r) * m * sizeof(double)));
-  DACP_HIP(ctx, dacp::launch_dgemm(0, 0, r, m, m, 1.0, uc.as<double>(), m, P, ld, 0.0, t1.as<double>(), m, 0, s));
-  DACP_HIP(ctx, ht.alloc(static_cast<size_t>(r) * r * sizeof(double)));
-  DACP_HIP(ctx, dacp::launch_dgemm(0, 1, r, r, m, 1.0, t1.as<double>(), m, uc.as<double>(), m, 0.0, ht.as<double>(), r,
-                                   0, s));
-  DACP_HIP(ctx, dacp::launch_symmetrize(ht.as<double>(), r, r, s));
-  DACP_HIP(ctx, hipStreamSynchronize(s));
-  t1.release();
   theta.assign(r, 0.0);
   const bool want_b = bc_out != nullptr;
   if (want_b) DACP_HIP(ctx, yc.alloc(static_cast<size_t>(r) * r * sizeof(double)));
   st = solve(r, ht.as<double>(), theta.data(), want_b ? yc.as<double>() : nullptr);
   if (st) return st;
-  if (want_b) {
-    // rows of B^T: Bc = Yc Uc  (r x m)
-    DACP_HIP(ctx, bc_out->alloc(static_cast<size_t>(r) * m * sizeof(double)));
-    DACP_HIP(ctx, dacp::launch_dgemm(0, 0, r, m, r, 1.0, yc.as<double>(), r, uc.as<double>(), m, 0.0,
-                                     bc_out->as<double>(), m, 0, s));
-    DACP_HIP(ctx, hipStreamSynchronize(s));
-  }
-  for (double t : theta)
-    if (!std::isfinite(t)) return set_err(ctx, DACP_E_NUMERIC, "non-finite Ritz value");
+  st = rr_back(ctx, m, r, want_b ? yc.as<double>() : nullptr, uc.as<double>(), theta, bc_out);
+  if (st) return st;
   if (r_out) *r_out = r;
   return DACP_OK;
 }
@@ -1484,38 +1502,16 @@ Plan make_plan(const dacp_opts &o, int64_t D, int N, double e_b, const std::vect
 // Projection (Sec. II.C), subspace solve (App. C) and acceptance (Sec. II.C residual check) for
 // one realisation whose basis V (D x m, row stride m) is built.  `accepted` gets the size of the
 // contiguous accepted core; when it reaches N the N values and their estimates are written.
-dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
-                         double norm_est, const double *V, int m, dacp_report &rep, double *eigs_out, double *err_out,
-                         int &accepted, const EigFn *eig = nullptr) {
+// Acceptance (Sec. II.C residual check) of one realisation: Ritz vectors V B for the candidates by
+// |theta|, their residuals, the quadratic residual bound and the contiguous core.  theta ascending
+// (r values), bc the rows of B^T (r x m).
+dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, double tol, double norm_est,
+                         const double *V, int m, int r, const std::vector<double> &theta, const DevBuf &bc,
+                         dacp_report &rep, double *eigs_out, double *err_out, int &accepted) {
   const int64_t D = h->D;
   hipStream_t s = ctx->stream;
-  (void)norm_est;
-  // projection (Sec. II.C)
-  double t0 = now_ms();
   dacp_status st;
-  DevBuf sb, pb;
-  DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
-  DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
-  st = run_project(ctx, h, m, V, m, sb.as<double>(), pb.as<double>(), m);
-  if (st) return st;
-  rep.t_project_ms = now_ms() - t0;
-  vlog("projection done: %.1f ms", rep.t_project_ms);
-
-  // generalised eigenproblem (App. C)
-  t0 = now_ms();
-  std::vector<double> theta;
-  DevBuf bc;
-  int r = 0;
-  st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r, eig);
-  if (st) return st;
-  sb.release();
-  pb.release();
-  rep.rank = r;
-  rep.t_gep_ms = now_ms() - t0;
-  vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
-
-  // acceptance (Sec. II.C residual check): candidates by |theta|
-  t0 = now_ms();
+  double t0 = now_ms();
   std::vector<int> order(r);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
@@ -1643,6 +1639,36 @@ dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, do
     }
   }
   return DACP_OK;
+}
+
+dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
+                         double norm_est, const double *V, int m, dacp_report &rep, double *eigs_out, double *err_out,
+                         int &accepted, const EigFn *eig = nullptr) {
+  // projection (Sec. II.C)
+  double t0 = now_ms();
+  dacp_status st;
+  DevBuf sb, pb;
+  DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+  DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+  st = run_project(ctx, h, m, V, m, sb.as<double>(), pb.as<double>(), m);
+  if (st) return st;
+  rep.t_project_ms = now_ms() - t0;
+  vlog("projection done: %.1f ms", rep.t_project_ms);
+
+  // generalised eigenproblem (App. C)
+  t0 = now_ms();
+  std::vector<double> theta;
+  DevBuf bc;
+  int r = 0;
+  st = run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r, eig);
+  if (st) return st;
+  sb.release();
+  pb.release();
+  rep.rank = r;
+  rep.t_gep_ms = now_ms() - t0;
+  vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
+
+  return accept_stage(ctx, h, N, a, n_w, tol, norm_est, V, m, r, theta, bc, rep, eigs_out, err_out, accepted);
 }
 
 }  // namespace
@@ -1879,60 +1905,100 @@ dacp_status batched_estimates(dacp_ctx ctx, int count, const dacp_ham *hams, con
 }
 }  // namespace
 
-// The dense eigen-decompositions of the workers that finish batched realisations, collected and
-// solved as one batched launch (one workgroup per matrix) once every worker still running waits on
-// one.  Matrices above the batched solver's size limit go through the per-problem solver.
+// The dense eigen-decompositions of the threads that finish batched realisations, solved together:
+// each thread hands in all of its pending problems (possibly none) and waits; once every running
+// thread has arrived the batch's reductions and QR iterations run as one launch (one workgroup per
+// matrix), a new round starts, and each thread then forms its own eigenvectors (a GEMM and a row
+// gather per problem) on its own stream.  Problems above the batched solver's size limit go
+// through the per-problem solver.
 class EigRendezvous {
  public:
+  struct Req {
+    int n;
+    double *A, *w, *Z;
+  };
   explicit EigRendezvous(int workers) : active_(workers) {}
-  dacp_status solve(dacp_ctx ctx, int n, double *A, double *w, double *Z) {
-    if (n > dacp::kBatchEigMaxN) return dacp::gpu_syev(ctx, n, A, n, w, Z);
-    DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // A was written on this worker's stream
-    std::unique_lock<std::mutex> lk(mu_);
-    Req r{ctx, n, A, w, Z, false, DACP_OK};
-    pending_.push_back(&r);
-    if (static_cast<int>(pending_.size()) == active_) run_locked(ctx);
-    cv_.wait(lk, [&] { return r.done; });
-    return r.st;
+  dacp_status solve_many(dacp_ctx ctx, const std::vector<Req> &reqs) {
+    dacp_status big = DACP_OK;
+    Arrival me;
+    me.ctx = ctx;
+    size_t scratch = 0;
+    for (const Req &r : reqs) {
+      if (r.n <= dacp::kBatchEigMaxN) {
+        me.reqs.push_back(r);
+        scratch += 2 * static_cast<size_t>(r.n) * r.n;
+      } else if (big == DACP_OK) {
+        big = dacp::gpu_syev(ctx, r.n, r.A, r.n, r.w, r.Z);
+      }
+    }
+    dacp::DevBuf zq;
+    hipError_t e = zq.alloc(scratch * sizeof(double));
+    size_t off = 0;
+    for (const Req &r : me.reqs) {
+      me.zr.push_back(e == hipSuccess ? zq.as<double>() + off : nullptr);
+      me.q.push_back(e == hipSuccess ? zq.as<double>() + off + static_cast<size_t>(r.n) * r.n : nullptr);
+      me.wraw.emplace_back(r.n);
+      off += 2 * static_cast<size_t>(r.n) * r.n;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // the matrices were written on this stream
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      if (e != hipSuccess) me.reqs.clear();  // still arrive, so that the others are not held up
+      arrived_.push_back(&me);
+      const long gen = generation_;
+      if (static_cast<int>(arrived_.size()) == active_) run_locked(ctx);
+      else cv_.wait(lk, [&] { return generation_ != gen; });
+    }
+    if (e != hipSuccess) return hip_err(ctx, e, "batched eigensolver: scratch or stream");
+    if (me.st != DACP_OK) return me.st;
+    for (size_t i = 0; i < me.reqs.size(); ++i) {
+      const Req &r = me.reqs[i];
+      DACP_TRY(dacp::batch_syev_finish(ctx, r.n, me.wraw[i].data(), r.A, me.zr[i], me.q[i], r.w, r.Z));
+    }
+    return big;
   }
-  // a worker has no further requests
+  // this thread has no further problems
   void leave(dacp_ctx ctx) {
     std::unique_lock<std::mutex> lk(mu_);
     --active_;
-    if (active_ > 0 && !pending_.empty() && static_cast<int>(pending_.size()) == active_) run_locked(ctx);
+    if (active_ > 0 && static_cast<int>(arrived_.size()) == active_) run_locked(ctx);
   }
 
  private:
-  struct Req {
-    dacp_ctx ctx;
-    int n;
-    double *A, *w, *Z;
-    bool done;
-    dacp_status st;
+  struct Arrival {
+    dacp_ctx ctx = nullptr;
+    std::vector<Req> reqs;
+    std::vector<double *> zr, q;
+    std::vector<std::vector<double>> wraw;
+    dacp_status st = DACP_OK;
   };
   void run_locked(dacp_ctx ctx) {
-    const int c = static_cast<int>(pending_.size());
-    std::vector<int> n(c);
-    std::vector<double *> A(c), w(c), Z(c);
-    for (int i = 0; i < c; ++i) {
-      n[i] = pending_[i]->n;
-      A[i] = pending_[i]->A;
-      w[i] = pending_[i]->w;
-      Z[i] = pending_[i]->Z;
+    std::vector<int> n;
+    std::vector<double *> A, zr, q, w;
+    for (Arrival *a : arrived_)
+      for (size_t i = 0; i < a->reqs.size(); ++i) {
+        n.push_back(a->reqs[i].n);
+        A.push_back(a->reqs[i].A);
+        zr.push_back(a->zr[i]);
+        q.push_back(a->q[i]);
+        w.push_back(a->wraw[i].data());
+      }
+    const dacp_status st = n.empty() ? DACP_OK
+                                     : dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(),
+                                                            zr.data(), q.data(), w.data());
+    for (Arrival *a : arrived_) {
+      a->st = st;
+      if (st != DACP_OK && a->ctx != ctx) a->ctx->err = ctx->err;
     }
-    const dacp_status st = dacp::batch_syev(ctx, c, n.data(), A.data(), w.data(), Z.data());
-    for (Req *r : pending_) {
-      r->st = st;
-      if (st != DACP_OK && r->ctx != ctx) r->ctx->err = ctx->err;
-      r->done = true;
-    }
-    pending_.clear();
+    arrived_.clear();
+    ++generation_;
     cv_.notify_all();
   }
   std::mutex mu_;
   std::condition_variable cv_;
-  std::vector<Req *> pending_;
+  std::vector<Arrival *> arrived_;
   int active_;
+  long generation_ = 0;
 };
 
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
@@ -2078,22 +2144,131 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     DACP_HIP(ctx, hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   }
   EigRendezvous rendezvous(nw);
+  // Each thread finishes its realisations r = w, w + nw, ...: with the batched eigensolver, stage by
+  // stage (projection; eig(S) for all of them in the shared launch; U and H~; eig(H~) likewise;
+  // Ritz vectors and acceptance), else one realisation after another.
   auto worker = [&](int w) {
     (void)hipSetDevice(ctx->device);
     dacp_ctx wc = &wctx[w];
-    const EigFn eig = [&rendezvous, wc](int n, double *A, double *lam, double *Z) {
-      return rendezvous.solve(wc, n, A, lam, Z);
+    const double eps = o.eps > 0.0 ? o.eps : 1e-12;
+    if (!ctx->batch_eig) {
+      for (int r = w; r < count; r += nw) {
+        const Plan &pl = plans[r];
+        wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
+                              eigs_out + static_cast<int64_t>(r) * N,
+                              err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
+        if (wst[r]) werr[r] = wc->err;
+        vb[r].release();
+      }
+      rendezvous.leave(wc);
+      return;
+    }
+    struct Fin {
+      DevBuf sb, pb, awork, zs, uc, ht, yc, bc;
+      std::vector<double> lam, theta;
+      int rank = 0;
+      double t0 = 0.0;
     };
-    for (int r = w; r < count; r += nw) {
-      const Plan &pl = plans[r];
-      wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
-                            eigs_out + static_cast<int64_t>(r) * N,
-                            err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r],
-                            ctx->batch_eig ? &eig : nullptr);
-      if (wst[r]) werr[r] = wctx[w].err;
-      vb[r].release();
+    std::vector<int> mine;
+    for (int r = w; r < count; r += nw) mine.push_back(r);
+    std::vector<Fin> F(mine.size());
+    auto fail = [&](int r, dacp_status st) {
+      wst[r] = st;
+      werr[r] = wc->err;
+    };
+    auto alive = [&](int r) { return wst[r] == DACP_OK; };
+    // projection (Sec. II.C), then a copy of S for the eigensolver
+    for (size_t i = 0; i < mine.size(); ++i) {
+      const int r = mine[i];
+      const int m = plans[r].m;
+      Fin &f = F[i];
+      const double t0 = now_ms();
+      hipError_t e = f.sb.alloc(static_cast<size_t>(m) * m * sizeof(double));
+      if (e == hipSuccess) e = f.pb.alloc(static_cast<size_t>(m) * m * sizeof(double));
+      if (e == hipSuccess) e = f.awork.alloc(static_cast<size_t>(m) * m * sizeof(double));
+      if (e == hipSuccess) e = f.zs.alloc(static_cast<size_t>(m) * m * sizeof(double));
+      if (e != hipSuccess) {
+        fail(r, hip_err(wc, e, "batched finish: allocation"));
+        continue;
+      }
+      dacp_status st = run_project(wc, hams[r], m, vb[r].as<double>(), m, f.sb.as<double>(), f.pb.as<double>(), m);
+      if (st == DACP_OK) {
+        e = dacp::launch_copy_cols(f.sb.as<double>(), m, f.awork.as<double>(), m, m, m, wc->stream);
+        if (e != hipSuccess) st = hip_err(wc, e, "batched finish: copy");
+      }
+      if (st) {
+        fail(r, st);
+        continue;
+      }
+      f.lam.assign(m, 0.0);
+      rep[r].t_project_ms = now_ms() - t0;
+      f.t0 = now_ms();
+    }
+    // eig(S) of every realisation in one launch
+    {
+      std::vector<EigRendezvous::Req> reqs;
+      for (size_t i = 0; i < mine.size(); ++i)
+        if (alive(mine[i]))
+          reqs.push_back({plans[mine[i]].m, F[i].awork.as<double>(), F[i].lam.data(), F[i].zs.as<double>()});
+      const dacp_status st = rendezvous.solve_many(wc, reqs);
+      if (st)
+        for (int r : mine)
+          if (alive(r)) fail(r, st);
+    }
+    // U = V~ Lambda~^(-1/2), H~ = U^T P U
+    for (size_t i = 0; i < mine.size(); ++i) {
+      const int r = mine[i];
+      if (!alive(r)) continue;
+      Fin &f = F[i];
+      const int m = plans[r].m;
+      dacp_status st = rr_reduce(wc, m, f.lam, f.zs.as<double>(), f.pb.as<double>(), m, eps, f.uc, f.ht, &f.rank);
+      if (st == DACP_OK) {
+        const hipError_t e = f.yc.alloc(static_cast<size_t>(f.rank) * f.rank * sizeof(double));
+        if (e != hipSuccess) st = hip_err(wc, e, "batched finish: allocation");
+      }
+      if (st) {
+        fail(r, st);
+        continue;
+      }
+      f.sb.release();
+      f.pb.release();
+      f.awork.release();
+      f.zs.release();
+      f.theta.assign(f.rank, 0.0);
+    }
+    // eig(H~) of every realisation in one launch
+    {
+      std::vector<EigRendezvous::Req> reqs;
+      for (size_t i = 0; i < mine.size(); ++i)
+        if (alive(mine[i])) reqs.push_back({F[i].rank, F[i].ht.as<double>(), F[i].theta.data(), F[i].yc.as<double>()});
+      const dacp_status st = rendezvous.solve_many(wc, reqs);
+      if (st)
+        for (int r : mine)
+          if (alive(r)) fail(r, st);
     }
     rendezvous.leave(wc);
+    // B, Ritz vectors and acceptance
+    for (size_t i = 0; i < mine.size(); ++i) {
+      const int r = mine[i];
+      Fin &f = F[i];
+      if (alive(r)) {
+        const Plan &pl = plans[r];
+        dacp_status st = rr_back(wc, pl.m, f.rank, f.yc.as<double>(), f.uc.as<double>(), f.theta, &f.bc);
+        if (st == DACP_OK) {
+          rep[r].rank = f.rank;
+          rep[r].t_gep_ms = now_ms() - f.t0;
+          f.ht.release();
+          f.yc.release();
+          f.uc.release();
+          st = accept_stage(wc, hams[r], N, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, f.rank,
+                            f.theta, f.bc, rep[r], eigs_out + static_cast<int64_t>(r) * N,
+                            err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
+        }
+        if (st) fail(r, st);
+      }
+      for (DevBuf *b : {&f.sb, &f.pb, &f.awork, &f.zs, &f.uc, &f.ht, &f.yc, &f.bc}) b->release();
+      vb[r].release();
+    }
   };
   std::vector<std::thread> threads;
   for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);

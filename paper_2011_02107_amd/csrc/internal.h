@@ -304,6 +304,12 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
 // in one launch; w[i] (host) ascending; Zrows[i] (device, n x n, may be null) row j = eigenvector j.
 dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
                        double *const *Zrows);
+// Its two halves: the launch (Zr, Q device n x n scratch per matrix; w host, unsorted) and, per
+// matrix on the caller's stream, the sort and Zrows = rows of Zr Q^T in ascending order (A reused).
+dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
+                           double *const *Q, double *const *w);
+dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr, const double *Q,
+                              double *w_out, double *Zrows);
 bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z);
 dacp_status dc_tridiag(dacp_ctx ctx, int n, const double *d, const double *e, double *w, double *Z);
 }  // namespace dacp
