@@ -2,9 +2,11 @@
 // matrix).  The per-problem solver of eig.hip issues several kernels per column and is bound by
 // launches at n of a few hundred; here one launch covers every problem of a batch:
 //   1. Householder tridiagonalisation in place (one column per step, the step's vectors in LDS);
-//   2. implicit symmetric QR with a Wilkinson shift on (d, e): thread 0 chases the bulge and
-//      records the sweep's Givens pairs in LDS, then every thread applies them to one column of
-//      Zr (rows = eigenvectors of the tridiagonal, starting from I);
+//   2. implicit symmetric QR with a Wilkinson shift on (d, e), in batches of up to S sweeps:
+//      thread 0 chases the bulges of batch b+1 (the chase carries its running values in
+//      registers) while waves 1.. apply the Givens rotations of batch b to the rows of Zr (rows =
+//      eigenvectors of the tridiagonal, starting from I), one column per thread, all S sweeps in
+//      one pass down the column;
 //   3. Q = H_0 H_1 ... H_(n-3) formed explicitly, one thread per column.
 // The host then sorts the eigenvalues and forms the eigenvectors of A as rows of Zr Q^T.
 #include <hip/hip_runtime.h>
@@ -22,6 +24,10 @@ namespace {
 
 constexpr int kBT = 1024;       // threads per problem
 constexpr int kBWaves = kBT / 64;
+constexpr int kApplyThreads = kBT - 64;  // waves 1.. apply rotations while wave 0 chases
+constexpr int kPrefetch = 8;             // rows of a column loaded ahead of their rotations
+constexpr int kRowBatch = 16;            // rows of a column in flight in the BLAS-2 passes
+constexpr size_t kLdsMax = 160 * 1024;
 
 // Sum over the workgroup, the same value returned to every thread (fixed order: lanes by
 // butterfly, then the waves in index order).  red holds kBWaves doubles.
@@ -53,14 +59,168 @@ __device__ void givens_pair(double x, double z, double &c, double &s) {
   }
 }
 
-// LDS: v, w (n each), cs (2n), d, e (n each), then the reduction slots and control words.
+// The same pair (up to a common sign) through one reciprocal square root when x^2 + z^2 can
+// neither overflow nor underflow: r = sqrt(x^2 + z^2), c = x / r, s = -z / r.
+__device__ void givens_fast(double x, double z, double &c, double &s) {
+  const double m = fmax(fabs(x), fabs(z));
+  if (z != 0.0 && m > 1e-150 && m < 1e150) {
+    const double ir = rsqrt(fma(x, x, z * z));
+    c = x * ir;
+    s = -z * ir;
+  } else {
+    givens_pair(x, z, c, s);
+  }
+}
+
+// One implicit QR sweep with a Wilkinson shift on the unreduced block p..q of (d, e) (Golub and
+// Van Loan's symmetric QR step).  The chase keeps d[k], e[k] and its bulge in registers and reads
+// d[k+2], e[k+2] one rotation ahead; the pairs (c, s) of rotations p..q-1 go to cs.
+__device__ void qr_sweep(double *d, double *e, int p, int q, double *cs) {
+  const double a = d[q - 1], bb = e[q - 1], cq = d[q];
+  const double delta = 0.5 * (a - cq);
+  const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * hypot(delta, bb);
+  const double mu = (den != 0.0) ? cq - bb * bb / den : cq;
+  double dk = d[p], ek = e[p];
+  double dn = d[p + 1], en = (p + 1 < q) ? e[p + 1] : 0.0;
+  double x = dk - mu, z = ek;
+  for (int k = p; k < q; ++k) {
+    const double dn2 = (k + 2 <= q) ? d[k + 2] : 0.0;
+    const double en2 = (k + 2 < q) ? e[k + 2] : 0.0;
+    double c, sn;
+    givens_fast(x, z, c, sn);
+    if (k > p) e[k - 1] = c * x - sn * z;
+    const double c2 = c * c, s2 = sn * sn, csn = c * sn;
+    const double ndk = c2 * dk - 2.0 * csn * ek + s2 * dn;
+    const double ndk1 = s2 * dk + 2.0 * csn * ek + c2 * dn;
+    const double nek = csn * (dk - dn) + (c2 - s2) * ek;
+    d[k] = ndk;
+    cs[2 * (k - p)] = c;
+    cs[2 * (k - p) + 1] = sn;
+    if (k < q - 1) {
+      x = nek;
+      z = -sn * en;
+      dk = ndk1;
+      ek = c * en;
+      dn = dn2;
+      en = en2;
+    } else {
+      d[k + 1] = ndk1;
+      e[k] = nek;
+    }
+  }
+}
+
+// Per-matrix state of the QR phase, held by thread 0.
+struct QrState {
+  int q;
+  long iters, max_iters;
+  bool failed;
+};
+
+// Thread 0: up to S sweeps (deflating from the bottom between them) into batch buffer `cs`
+// (S blocks of n pairs) and its header mt = {count, p_0.., q_0..}.
+template <int S>
+__device__ void chase_batch(QrState &st, double *d, double *e, int n, double *cs, int *mt) {
+  const double eps = 2.220446049250313e-16;
+  int cnt = 0;
+  while (cnt < S && st.q > 0 && !st.failed) {
+    const int q = st.q;
+    if (e[q - 1] == 0.0 || fabs(e[q - 1]) <= eps * (fabs(d[q - 1]) + fabs(d[q]))) {
+      e[q - 1] = 0.0;
+      --st.q;
+      continue;
+    }
+    int p = q - 1;
+    while (p > 0 && !(fabs(e[p - 1]) <= eps * (fabs(d[p - 1]) + fabs(d[p])))) --p;
+    if (p > 0) e[p - 1] = 0.0;
+    if (++st.iters > st.max_iters) {
+      st.failed = true;
+      break;
+    }
+    qr_sweep(d, e, p, q, cs + static_cast<size_t>(cnt) * 2 * n);
+    mt[1 + cnt] = p;
+    mt[1 + S + cnt] = q;
+    ++cnt;
+  }
+  mt[0] = cnt;
+}
+
+// One column of Zr through the batch's sweeps in one pass.  Rotation k of sweep s acts on rows
+// k, k+1 and runs at time t = k + 2s: every rotation that shares a row with it and belongs to an
+// earlier sweep runs at an earlier time, rotations of one time touch disjoint rows, so the result
+// equals applying the sweeps one after another.  At time t the window holds rows t-2(S-1) .. t+1;
+// row t+1 enters (loaded kPrefetch rows ahead) and row t-2(S-1) leaves, finished.
+template <int S>
+__device__ void apply_batch(double *Zr, int n, int col, const double *cs, const int *mt) {
+  const int cnt = mt[0];
+  int ps[S], qs[S];
+  int pmin = n, qmax = -1;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    ps[s] = (s < cnt) ? mt[1 + s] : 0;
+    qs[s] = (s < cnt) ? mt[1 + S + s] : 0;  // empty range for absent sweeps
+    if (s < cnt) {
+      pmin = min(pmin, ps[s]);
+      qmax = max(qmax, qs[s]);
+    }
+  }
+  const int t0 = pmin - 1;
+  const int T = qmax - pmin + 2 * S;  // times t0 .. qmax + 2(S-1)
+  double *zc = Zr + col;
+  double win[2 * S];
+#pragma unroll
+  for (int j = 0; j < 2 * S; ++j) win[j] = 0.0;
+  double pf[kPrefetch];
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int r = pmin + j;
+    pf[j] = (r <= qmax) ? zc[static_cast<int64_t>(r) * n] : 0.0;
+  }
+  for (int base = 0; base < T; base += kPrefetch) {
+    double nx[kPrefetch];
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      const int r = pmin + base + kPrefetch + j;
+      nx[j] = (r <= qmax) ? zc[static_cast<int64_t>(r) * n] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) {
+      if (base + j < T) {
+        const int t = t0 + base + j;
+        win[2 * S - 1] = pf[j];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int k = t - 2 * s;
+          if (k >= ps[s] && k < qs[s]) {
+            const double c = cs[(static_cast<size_t>(s) * n + (k - ps[s])) * 2];
+            const double sn = cs[(static_cast<size_t>(s) * n + (k - ps[s])) * 2 + 1];
+            const double x = win[2 * (S - 1 - s)], y = win[2 * (S - 1 - s) + 1];
+            win[2 * (S - 1 - s)] = c * x - sn * y;
+            win[2 * (S - 1 - s) + 1] = sn * x + c * y;
+          }
+        }
+        const int out = t - 2 * (S - 1);
+        if (out >= pmin && out <= qmax) zc[static_cast<int64_t>(out) * n] = win[0];
+#pragma unroll
+        for (int w = 0; w + 1 < 2 * S; ++w) win[w] = win[w + 1];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPrefetch; ++j) pf[j] = nx[j];
+  }
+}
+
+// LDS: v, w, d, e (n each), the reduction slots, two batch buffers of S x n Givens pairs, then
+// two batch headers of 1 + 2S ints.
+template <int S>
 __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs) {
   extern __shared__ double sm[];
   const BatchEigProblem pb = probs[blockIdx.x];
   const int n = pb.n;
-  double *vsh = sm, *wsh = sm + n, *cs = sm + 2 * n, *d = sm + 4 * n, *e = sm + 5 * n, *red = sm + 6 * n;
-  int *ctl = reinterpret_cast<int *>(red + kBWaves);  // p, q, go
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double *vsh = sm, *wsh = sm + n, *d = sm + 2 * n, *e = sm + 3 * n, *red = sm + 4 * n;
+  double *csb = red + kBWaves;
+  int *meta = reinterpret_cast<int *>(csb + 4 * static_cast<size_t>(S) * n);
+  const int tid = threadIdx.x, wave = tid >> 6;
   double *A = pb.A;
   double *betas = pb.beta;
   if (n == 1) {
@@ -97,14 +257,21 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     __syncthreads();
     if (beta == 0.0) continue;
     double *a22 = A + static_cast<int64_t>(k + 1) * n + k + 1;
-    // p = beta A22 v, one wave per row
-    for (int i = wave; i < m; i += kBWaves) {
-      const double *row = a22 + static_cast<int64_t>(i) * n;
+    // p = beta A22 v as column sums (A22 is symmetric): one thread per column, kRowBatch rows
+    // of loads in flight
+    for (int j = tid; j < m; j += kBT) {
+      const double *cj = a22 + j;
       double t = 0.0;
-      for (int j = lane; j < m; j += 64) t += row[j] * vsh[j];
+      int i = 0;
+      for (; i + kRowBatch <= m; i += kRowBatch) {
+        double a[kRowBatch];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-      if (lane == 0) wsh[i] = beta * t;
+        for (int u = 0; u < kRowBatch; ++u) a[u] = cj[static_cast<int64_t>(i + u) * n];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) t += a[u] * vsh[i + u];
+      }
+      for (; i < m; ++i) t += cj[static_cast<int64_t>(i) * n] * vsh[i];
+      wsh[j] = beta * t;
     }
     __syncthreads();
     // w = p - (beta p^T v / 2) v
@@ -113,11 +280,19 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     const double half = 0.5 * beta * block_sum(pv, red);
     for (int i = tid; i < m; i += kBT) wsh[i] -= half * vsh[i];
     __syncthreads();
-    // A22 -= v w^T + w v^T
-    for (int i = 0; i < m; ++i) {
-      const double vi = vsh[i], wi = wsh[i];
-      double *row = a22 + static_cast<int64_t>(i) * n;
-      for (int j = tid; j < m; j += kBT) row[j] -= vi * wsh[j] + wi * vsh[j];
+    // A22 -= v w^T + w v^T, one thread per column, kRowBatch rows loaded before any is stored
+    for (int j = tid; j < m; j += kBT) {
+      double *cj = a22 + j;
+      const double vj = vsh[j], wj = wsh[j];
+      int i = 0;
+      for (; i + kRowBatch <= m; i += kRowBatch) {
+        double a[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) a[u] = cj[static_cast<int64_t>(i + u) * n];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) cj[static_cast<int64_t>(i + u) * n] = a[u] - (vsh[i + u] * wj + wsh[i + u] * vj);
+      }
+      for (; i < m; ++i) cj[static_cast<int64_t>(i) * n] -= vsh[i] * wj + wsh[i] * vj;
     }
     __syncthreads();
   }
@@ -131,74 +306,27 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
   for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += kBT)
     pb.Zr[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   __syncthreads();
-  // ---- 2. implicit symmetric QR on (d, e): thread 0 steers, everyone rotates Zr's rows p..q
-  int q = n - 1;  // thread 0's working state
-  long iters = 0;
-  const long max_iters = 40L * n + 100;
-  const double eps = 2.220446049250313e-16;
-  while (true) {
-    if (tid == 0) {
-      int go = 0;
-      while (q > 0) {
-        if (e[q - 1] == 0.0 || fabs(e[q - 1]) <= eps * (fabs(d[q - 1]) + fabs(d[q]))) {
-          e[q - 1] = 0.0;
-          --q;
-          continue;
-        }
-        int p = q - 1;
-        while (p > 0 && !(fabs(e[p - 1]) <= eps * (fabs(d[p - 1]) + fabs(d[p])))) --p;
-        if (p > 0) e[p - 1] = 0.0;
-        if (++iters > max_iters) {
-          *pb.status = 1;
-          break;
-        }
-        // Wilkinson shift from the trailing 2 x 2 block, then the bulge chase from p to q
-        const double a = d[q - 1], bb = e[q - 1], cc = d[q];
-        const double delta = 0.5 * (a - cc);
-        const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * hypot(delta, bb);
-        const double mu = (den != 0.0) ? cc - bb * bb / den : cc;
-        double xx = d[p] - mu, zz = e[p];
-        for (int kk = p; kk < q; ++kk) {
-          double c, sn;
-          givens_pair(xx, zz, c, sn);
-          if (kk > p) e[kk - 1] = c * xx - sn * zz;
-          const double dk = d[kk], dk1 = d[kk + 1], ek = e[kk];
-          d[kk] = c * c * dk - 2.0 * c * sn * ek + sn * sn * dk1;
-          d[kk + 1] = sn * sn * dk + 2.0 * c * sn * ek + c * c * dk1;
-          e[kk] = c * sn * (dk - dk1) + (c * c - sn * sn) * ek;
-          if (kk < q - 1) {
-            xx = e[kk];
-            zz = -sn * e[kk + 1];
-            e[kk + 1] = c * e[kk + 1];
-          }
-          cs[2 * (kk - p)] = c;
-          cs[2 * (kk - p) + 1] = sn;
-        }
-        ctl[0] = p;
-        ctl[1] = q;
-        go = 1;
-        break;
-      }
-      ctl[2] = go;
-    }
-    __syncthreads();
-    if (!ctl[2]) break;
-    const int p = ctl[0], qq = ctl[1];
-    for (int col = tid; col < n; col += kBT) {
-      double carry = pb.Zr[static_cast<int64_t>(p) * n + col];
-      for (int kk = p; kk < qq; ++kk) {
-        const double c = cs[2 * (kk - p)], sn = cs[2 * (kk - p) + 1];
-        double *zk1 = pb.Zr + static_cast<int64_t>(kk + 1) * n + col;
-        const double zn = *zk1;
-        pb.Zr[static_cast<int64_t>(kk) * n + col] = c * carry - sn * zn;
-        carry = sn * carry + c * zn;
-      }
-      pb.Zr[static_cast<int64_t>(qq) * n + col] = carry;
+  // ---- 2. implicit symmetric QR, batch b+1 chased while batch b is applied
+  const int hdr = 1 + 2 * S;
+  QrState qs{n - 1, 0, 40L * n + 100, false};  // meaningful in thread 0 only
+  if (tid == 0) chase_batch<S>(qs, d, e, n, csb, meta);
+  __syncthreads();
+  for (int it = 0;; ++it) {
+    const int cur = it & 1;
+    if (meta[cur * hdr] == 0) break;
+    if (wave == 0) {
+      // the chase is one dependent chain: let its wave issue ahead of the applying waves
+      __builtin_amdgcn_s_setprio(3);
+      if (tid == 0) chase_batch<S>(qs, d, e, n, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr);
+      __builtin_amdgcn_s_setprio(0);
+    } else {
+      for (int col = tid - 64; col < n; col += kApplyThreads)
+        apply_batch<S>(pb.Zr, n, col, csb + static_cast<size_t>(cur) * 2 * S * n, meta + cur * hdr);
     }
     __syncthreads();
   }
+  if (tid == 0) *pb.status = qs.failed ? 1 : 0;
   for (int i = tid; i < n; i += kBT) pb.w[i] = d[i];
-  if (tid == 0 && *pb.status != 1) *pb.status = 0;
   // ---- 3. Q = H_0 H_1 ... H_(n-3): apply H_k from k = n-3 down to 0 onto I; H_k touches rows
   // and columns k+1.. only, so columns <= k of the product stay those of I
   for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += kBT)
@@ -212,10 +340,26 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     __syncthreads();
     double *qk = pb.Q + static_cast<int64_t>(k + 1) * n;
     for (int col = k + 1 + tid; col < n; col += kBT) {
+      double *qc = qk + col;
       double t = 0.0;
-      for (int r = 0; r < m; ++r) t += vsh[r] * qk[static_cast<int64_t>(r) * n + col];
+      int r = 0;
+      for (; r + kRowBatch <= m; r += kRowBatch) {
+        double a[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) a[u] = qc[static_cast<int64_t>(r + u) * n];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) t += vsh[r + u] * a[u];
+      }
+      for (; r < m; ++r) t += vsh[r] * qc[static_cast<int64_t>(r) * n];
       t *= beta;
-      for (int r = 0; r < m; ++r) qk[static_cast<int64_t>(r) * n + col] -= t * vsh[r];
+      for (r = 0; r + kRowBatch <= m; r += kRowBatch) {
+        double a[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) a[u] = qc[static_cast<int64_t>(r + u) * n];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) qc[static_cast<int64_t>(r + u) * n] = a[u] - t * vsh[r + u];
+      }
+      for (; r < m; ++r) qc[static_cast<int64_t>(r) * n] -= t * vsh[r];
     }
     __syncthreads();
   }
@@ -223,17 +367,38 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
 
 }  // namespace
 
-size_t batch_syev_lds(int max_n) { return (6 * static_cast<size_t>(max_n) + kBWaves) * sizeof(double) + 4 * sizeof(int); }
+size_t batch_syev_lds_for(int max_n, int S) {
+  return (4 * static_cast<size_t>(max_n) + kBWaves + 4 * static_cast<size_t>(S) * max_n) * sizeof(double) +
+         2 * (1 + 2 * static_cast<size_t>(S)) * sizeof(int);
+}
+
+// Sweeps per batch: the most of 4, 2, 1 whose two Givens buffers fit the LDS beside the rest.
+int batch_syev_sweeps(int max_n) {
+  for (int S : {4, 2})
+    if (batch_syev_lds_for(max_n, S) <= kLdsMax) return S;
+  return 1;
+}
+
+size_t batch_syev_lds(int max_n) { return batch_syev_lds_for(max_n, batch_syev_sweeps(max_n)); }
+
+template <int S>
+static hipError_t launch_batch_syev_s(const BatchEigProblem *probs, int count, int max_n, hipStream_t s) {
+  const size_t lds = batch_syev_lds_for(max_n, S);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_syev<S>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_syev<S>, dim3(count), dim3(kBT), lds, s, probs);
+  return hipGetLastError();
+}
 
 hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (max_n < 1 || max_n > kBatchEigMaxN) return hipErrorInvalidValue;
-  const size_t lds = batch_syev_lds(max_n);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_syev),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_syev, dim3(count), dim3(kBT), lds, s, probs);
-  return hipGetLastError();
+  switch (batch_syev_sweeps(max_n)) {
+    case 4: return launch_batch_syev_s<4>(probs, count, max_n, s);
+    case 2: return launch_batch_syev_s<2>(probs, count, max_n, s);
+    default: return launch_batch_syev_s<1>(probs, count, max_n, s);
+  }
 }
 
 // Host side, first half: one launch over `count` matrices A[i] (device, n[i] x n[i], ld n[i],

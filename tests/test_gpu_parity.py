@@ -527,6 +527,32 @@ def test_syev_batched_matches_oracle(ctx):
         assert np.abs(Zr @ Zr.T - np.eye(n)).max() < 1e-13 * n
 
 
+@pytest.mark.parametrize("sizes", [(1100, 40), (2048,)], ids=["two_sweeps_per_batch", "one_sweep_per_batch"])
+def test_syev_batched_large_sizes(ctx, sizes):
+    """The largest matrix of a launch sets how many QR sweeps share one pass over Zr (fewer at
+    large n, where their Givens buffers fill the LDS); a Gram-like PSD matrix (rank 2/3 n, wide
+    spread of eigenvalues) rides along with the largest."""
+    rng = np.random.default_rng(22)
+    mats = []
+    for n in sizes:
+        X = rng.standard_normal((n, n))
+        mats.append(X + X.T)
+    n0, r = 300, 200
+    X = rng.standard_normal((r, n0)) * np.logspace(0, -7, n0)[None, :]
+    mats.append(X.T @ X)
+    As = [to_dev(A) for A in mats]
+    Zs = [torch.zeros(A.shape, dtype=torch.float64, device=DEV) for A in mats]
+    ws = B.dacp_syev_batched(ctx, As, Zs)
+    for A, w, Z in zip(mats, ws, Zs):
+        n = A.shape[0]
+        w_ref = _native.syev(A)
+        scale = max(1.0, np.abs(w_ref).max())
+        assert np.abs(w - w_ref).max() < 1e-12 * scale * max(1, n) ** 0.5
+        Zr = host(Z)
+        assert np.abs(Zr @ A @ Zr.T - np.diag(w)).max() < 1e-12 * scale * n
+        assert np.abs(Zr @ Zr.T - np.eye(n)).max() < 1e-13 * n
+
+
 def test_syev_batched_rejects_large(ctx):
     A = torch.zeros((2049, 2049), dtype=torch.float64, device=DEV)
     with pytest.raises(B.DacpError) as ei:
