@@ -7,7 +7,8 @@
 //      registers) while waves 1.. apply the Givens rotations of batch b to the rows of Zr (rows =
 //      eigenvectors of the tridiagonal, starting from I), one column per thread, all S sweeps in
 //      one pass down the column;
-//   3. Q = H_0 H_1 ... H_(n-3) formed explicitly, one thread per column.
+//   3. Q = H_0 H_1 ... H_(n-3) formed explicitly, one thread per column, by the applying waves
+//      while thread 0 chases (the columns of Q need no barrier between Householder steps).
 // The host then sorts the eigenvalues and forms the eigenvectors of A as rows of Zr Q^T.
 #include <hip/hip_runtime.h>
 
@@ -27,6 +28,7 @@ constexpr int kBWaves = kBT / 64;
 constexpr int kApplyThreads = kBT - 64;  // waves 1.. apply rotations while wave 0 chases
 constexpr int kPrefetch = 8;             // rows of a column loaded ahead of their rotations
 constexpr int kRowBatch = 16;            // rows of a column in flight in the BLAS-2 passes
+constexpr int kQBatch = 8;               // the same while forming Q beside the rotations
 constexpr size_t kLdsMax = 160 * 1024;
 
 // Sum over the workgroup, the same value returned to every thread (fixed order: lanes by
@@ -60,54 +62,55 @@ __device__ void givens_pair(double x, double z, double &c, double &s) {
 }
 
 // The same pair (up to a common sign) through one reciprocal square root when x^2 + z^2 can
-// neither overflow nor underflow: r = sqrt(x^2 + z^2), c = x / r, s = -z / r.
+// neither overflow nor underflow: r = sqrt(x^2 + z^2), c = x / r, s = -z / r.  The fast form is
+// computed first and the range test only picks the stable one, off the chase's dependent chain.
 __device__ void givens_fast(double x, double z, double &c, double &s) {
-  const double m = fmax(fabs(x), fabs(z));
-  if (z != 0.0 && m > 1e-150 && m < 1e150) {
-    const double ir = rsqrt(fma(x, x, z * z));
-    c = x * ir;
-    s = -z * ir;
-  } else {
-    givens_pair(x, z, c, s);
-  }
+  const double r2 = fma(x, x, z * z);
+  const double ir = rsqrt(r2);
+  c = x * ir;
+  s = -z * ir;
+  if (!(r2 > 1e-290 && r2 < 1e290)) givens_pair(x, z, c, s);
 }
 
 // One implicit QR sweep with a Wilkinson shift on the unreduced block p..q of (d, e) (Golub and
 // Van Loan's symmetric QR step).  The chase keeps d[k], e[k] and its bulge in registers and reads
-// d[k+2], e[k+2] one rotation ahead; the pairs (c, s) of rotations p..q-1 go to cs.
+// d, e two rotations ahead (those reads may run up to two entries past e's end, into the
+// reduction slots: in the workgroup's LDS and unused); the pairs (c, s) of rotations p..q-1 go
+// to cs.
 __device__ void qr_sweep(double *d, double *e, int p, int q, double *cs) {
   const double a = d[q - 1], bb = e[q - 1], cq = d[q];
   const double delta = 0.5 * (a - cq);
   const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * hypot(delta, bb);
   const double mu = (den != 0.0) ? cq - bb * bb / den : cq;
-  double dk = d[p], ek = e[p];
-  double dn = d[p + 1], en = (p + 1 < q) ? e[p + 1] : 0.0;
+  double dk = d[p], ek = e[p], dn = d[p + 1], en = e[p + 1], dn2 = d[p + 2], en2 = e[p + 2];
   double x = dk - mu, z = ek;
-  for (int k = p; k < q; ++k) {
-    const double dn2 = (k + 2 <= q) ? d[k + 2] : 0.0;
-    const double en2 = (k + 2 < q) ? e[k + 2] : 0.0;
-    double c, sn;
+  double c, sn;
+  for (int k = p; k < q - 1; ++k) {
+    const double dn3 = d[k + 3], en3 = e[k + 3];
     givens_fast(x, z, c, sn);
     if (k > p) e[k - 1] = c * x - sn * z;
     const double c2 = c * c, s2 = sn * sn, csn = c * sn;
-    const double ndk = c2 * dk - 2.0 * csn * ek + s2 * dn;
+    d[k] = c2 * dk - 2.0 * csn * ek + s2 * dn;
     const double ndk1 = s2 * dk + 2.0 * csn * ek + c2 * dn;
-    const double nek = csn * (dk - dn) + (c2 - s2) * ek;
-    d[k] = ndk;
+    x = csn * (dk - dn) + (c2 - s2) * ek;
+    z = -sn * en;
     cs[2 * (k - p)] = c;
     cs[2 * (k - p) + 1] = sn;
-    if (k < q - 1) {
-      x = nek;
-      z = -sn * en;
-      dk = ndk1;
-      ek = c * en;
-      dn = dn2;
-      en = en2;
-    } else {
-      d[k + 1] = ndk1;
-      e[k] = nek;
-    }
+    dk = ndk1;
+    ek = c * en;
+    dn = dn2;
+    en = en2;
+    dn2 = dn3;
+    en2 = en3;
   }
+  givens_fast(x, z, c, sn);
+  if (q - 1 > p) e[q - 2] = c * x - sn * z;
+  const double c2 = c * c, s2 = sn * sn, csn = c * sn;
+  d[q - 1] = c2 * dk - 2.0 * csn * ek + s2 * dn;
+  d[q] = s2 * dk + 2.0 * csn * ek + c2 * dn;
+  e[q - 1] = csn * (dk - dn) + (c2 - s2) * ek;
+  cs[2 * (q - 1 - p)] = c;
+  cs[2 * (q - 1 - p) + 1] = sn;
 }
 
 // Per-matrix state of the QR phase, held by thread 0.
@@ -210,8 +213,42 @@ __device__ void apply_batch(double *Zr, int n, int col, const double *cs, const 
   }
 }
 
-// LDS: v, w, d, e (n each), the reduction slots, two batch buffers of S x n Givens pairs, then
-// two batch headers of 1 + 2S ints.
+// Householder step k of forming Q = H_0 H_1 ... H_(n-3) (applied from k = n-3 down to 0 onto I)
+// on the columns of Q that applying thread `a` owns: Q[k+1.., col] -= beta v (v^T Q[k+1.., col]),
+// v from row k of the reduced A.  H_k touches rows and columns k+1.. only, so columns <= k stay
+// those of I.  Every column is independent of the others, so the steps need no barrier.
+__device__ void house_cols(double *Q, const double *A, const double *betas, int n, int k, int a) {
+  const double beta = betas[k];
+  if (beta == 0.0) return;
+  const int m = n - k - 1;
+  const double *v = A + static_cast<int64_t>(k) * n + k + 1;
+  for (int col = a; col < n; col += kApplyThreads) {
+    if (col <= k) continue;
+    double *qc = Q + static_cast<int64_t>(k + 1) * n + col;
+    double t = 0.0;
+    int r = 0;
+    for (; r + kQBatch <= m; r += kQBatch) {
+      double q[kQBatch];
+#pragma unroll
+      for (int u = 0; u < kQBatch; ++u) q[u] = qc[static_cast<int64_t>(r + u) * n];
+#pragma unroll
+      for (int u = 0; u < kQBatch; ++u) t += v[r + u] * q[u];
+    }
+    for (; r < m; ++r) t += v[r] * qc[static_cast<int64_t>(r) * n];
+    t *= beta;
+    for (r = 0; r + kQBatch <= m; r += kQBatch) {
+      double q[kQBatch];
+#pragma unroll
+      for (int u = 0; u < kQBatch; ++u) q[u] = qc[static_cast<int64_t>(r + u) * n];
+#pragma unroll
+      for (int u = 0; u < kQBatch; ++u) qc[static_cast<int64_t>(r + u) * n] = q[u] - t * v[r + u];
+    }
+    for (; r < m; ++r) qc[static_cast<int64_t>(r) * n] -= t * v[r];
+  }
+}
+
+// LDS: v, w, d, e (n each), the reduction slots, two batch buffers of S x n Givens pairs, two
+// batch headers of 1 + 2S ints and the count of finished chases.
 template <int S>
 __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs) {
   extern __shared__ double sm[];
@@ -306,10 +343,21 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
   for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += kBT)
     pb.Zr[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   __syncthreads();
-  // ---- 2. implicit symmetric QR, batch b+1 chased while batch b is applied
+  // ---- 2. implicit symmetric QR, batch b+1 chased while batch b is applied; the applying
+  // threads fill the time the chase takes with the Householder steps that form Q (3.), which
+  // depend on phase 1 only, polling the count of finished chases between steps
   const int hdr = 1 + 2 * S;
+  volatile int *chased = meta + 2 * hdr;
+  const int a = tid - 64;  // applying thread index (waves 1..)
+  int hk = n - 3;          // next Householder step of this thread's Q columns (wave-uniform)
+  if (wave != 0)
+    for (int col = a; col < n; col += kApplyThreads)
+      for (int r = 0; r < n; ++r) pb.Q[static_cast<int64_t>(r) * n + col] = (r == col) ? 1.0 : 0.0;
   QrState qs{n - 1, 0, 40L * n + 100, false};  // meaningful in thread 0 only
-  if (tid == 0) chase_batch<S>(qs, d, e, n, csb, meta);
+  if (tid == 0) {
+    chase_batch<S>(qs, d, e, n, csb, meta);
+    *chased = 0;
+  }
   __syncthreads();
   for (int it = 0;; ++it) {
     const int cur = it & 1;
@@ -317,59 +365,30 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     if (wave == 0) {
       // the chase is one dependent chain: let its wave issue ahead of the applying waves
       __builtin_amdgcn_s_setprio(3);
-      if (tid == 0) chase_batch<S>(qs, d, e, n, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr);
+      if (tid == 0) {
+        chase_batch<S>(qs, d, e, n, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr);
+        *chased = it + 1;
+      }
       __builtin_amdgcn_s_setprio(0);
     } else {
-      for (int col = tid - 64; col < n; col += kApplyThreads)
+      for (int col = a; col < n; col += kApplyThreads)
         apply_batch<S>(pb.Zr, n, col, csb + static_cast<size_t>(cur) * 2 * S * n, meta + cur * hdr);
+      while (hk >= 0 && *chased <= it) house_cols(pb.Q, A, betas, n, hk--, a);
     }
     __syncthreads();
   }
   if (tid == 0) *pb.status = qs.failed ? 1 : 0;
   for (int i = tid; i < n; i += kBT) pb.w[i] = d[i];
-  // ---- 3. Q = H_0 H_1 ... H_(n-3): apply H_k from k = n-3 down to 0 onto I; H_k touches rows
-  // and columns k+1.. only, so columns <= k of the product stay those of I
-  for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += kBT)
-    pb.Q[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    const double beta = betas[k];
-    if (beta == 0.0) continue;
-    const int m = n - k - 1;
-    for (int i = tid; i < m; i += kBT) vsh[i] = A[static_cast<int64_t>(k) * n + k + 1 + i];
-    __syncthreads();
-    double *qk = pb.Q + static_cast<int64_t>(k + 1) * n;
-    for (int col = k + 1 + tid; col < n; col += kBT) {
-      double *qc = qk + col;
-      double t = 0.0;
-      int r = 0;
-      for (; r + kRowBatch <= m; r += kRowBatch) {
-        double a[kRowBatch];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) a[u] = qc[static_cast<int64_t>(r + u) * n];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) t += vsh[r + u] * a[u];
-      }
-      for (; r < m; ++r) t += vsh[r] * qc[static_cast<int64_t>(r) * n];
-      t *= beta;
-      for (r = 0; r + kRowBatch <= m; r += kRowBatch) {
-        double a[kRowBatch];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) a[u] = qc[static_cast<int64_t>(r + u) * n];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) qc[static_cast<int64_t>(r + u) * n] = a[u] - t * vsh[r + u];
-      }
-      for (; r < m; ++r) qc[static_cast<int64_t>(r) * n] -= t * vsh[r];
-    }
-    __syncthreads();
-  }
+  // ---- 3. the Householder steps not yet taken
+  if (wave != 0)
+    while (hk >= 0) house_cols(pb.Q, A, betas, n, hk--, a);
 }
 
 }  // namespace
 
 size_t batch_syev_lds_for(int max_n, int S) {
   return (4 * static_cast<size_t>(max_n) + kBWaves + 4 * static_cast<size_t>(S) * max_n) * sizeof(double) +
-         2 * (1 + 2 * static_cast<size_t>(S)) * sizeof(int);
+         (2 * (1 + 2 * static_cast<size_t>(S)) + 1) * sizeof(int);
 }
 
 // Sweeps per batch: the most of 4, 2, 1 whose two Givens buffers fit the LDS beside the rest.
