@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--max-retries", type=int, default=None, help="wider-window retries (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--profile-gemm", action="store_true",
+                    help="run only the Gram product C = V^T V (V of 2^20 x 4096, FP64 MFMA) three times and "
+                         "print one JSON line (for MFMA counter runs)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run only a device copy of known size and a short evolution at the workload's shape "
                          "(for hardware-counter runs), print one JSON line and exit")
@@ -148,6 +151,30 @@ def profile_kernels(args):
     print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "evolution_steps": 64, "group": g, "L": L,
                       "algorithmic_bytes_per_step": 3 * D * g * 8, "e_bound": eb,
                       "filter_orders": {"fp32": 24, "fp64": 8}}), flush=True)
+
+
+def profile_gemm(args):
+    """The Gram product of the projection, C = V^T V, at D = 2^20 rows and m = 4096 columns (a full
+    square, 2 D m^2 = 3.5e13 flops per call), three calls through the C ABI.  Used for the MFMA
+    counters (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 = flops, SQ_VALU_MFMA_BUSY_CYCLES)."""
+    import torch
+
+    from paper_2011_02107_amd import binding as B
+
+    ctx = B.Context(0)
+    D, m = 1 << 20, 4096
+    g = torch.Generator(device="cuda").manual_seed(3)
+    V = torch.randn(D, m, dtype=torch.float64, device="cuda", generator=g)
+    C = torch.empty(m, m, dtype=torch.float64, device="cuda")
+    rates = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.dacp_gemm(ctx, 1, 0, V, V, C)
+        torch.cuda.synchronize()
+        rates.append(2.0 * D * m * m / (time.perf_counter() - t0) / 1e12)
+    print(json.dumps({"gemm": "C = V^T V", "D": D, "m": m, "flops_per_call": 2 * D * m * m,
+                      "tflops": rates, "peak_tflops": 78.6}), flush=True)
 
 
 def batch96(args):
@@ -272,6 +299,8 @@ def main():
         sys.exit(2)
     if args.profile_kernels:
         return profile_kernels(args)
+    if args.profile_gemm:
+        return profile_gemm(args)
     if args.workload == "glass_batch96_N200":
         return batch96(args)
     if args.workload == "glass_L18_N3000_learned":
