@@ -50,6 +50,96 @@ void vlog(const char *fmt, ...) {
   va_end(ap);
 }
 
+AllocState &alloc_state_tl() {
+  static thread_local AllocState st;
+  return st;
+}
+
+namespace {
+struct CachedBlock {
+  void *p;
+  hipEvent_t ready;  // recorded on the freeing stream
+};
+
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, CachedBlock> blocks;  // by size class
+  std::vector<hipEvent_t> spare;              // events not attached to a block
+  size_t cached = 0;
+};
+
+BlockCache &block_cache(int device) {
+  static BlockCache caches[64];
+  return caches[device & 63];
+}
+
+// Size class: n rounded up to a multiple of a quarter of its leading power of two (256 B at least).
+size_t size_class(size_t n) {
+  size_t top = 256;
+  while (top * 2 <= n) top *= 2;
+  const size_t step = std::max<size_t>(256, top / 4);
+  return (n + step - 1) / step * step;
+}
+}  // namespace
+
+AllocStream::AllocStream(hipStream_t s, int device) : prev(alloc_state_tl()) {
+  AllocState &st = alloc_state_tl();
+  st.on = true;
+  st.s = s;
+  st.device = device;
+}
+
+AllocStream::~AllocStream() { alloc_state_tl() = prev; }
+
+hipError_t pool_alloc(size_t nbytes, hipStream_t s, int device, void **p, size_t *cls) {
+  const size_t c = size_class(nbytes);
+  BlockCache &bc = block_cache(device);
+  {
+    std::unique_lock<std::mutex> lk(bc.mu);
+    auto it = bc.blocks.find(c);
+    if (it != bc.blocks.end()) {
+      const CachedBlock b = it->second;
+      bc.blocks.erase(it);
+      bc.cached -= c;
+      bc.spare.push_back(b.ready);
+      lk.unlock();
+      *p = b.p;
+      *cls = c;
+      // the wait takes the event's state now; the event may be recorded again afterwards
+      return hipStreamWaitEvent(s, b.ready, 0);
+    }
+  }
+  *cls = c;
+  return hipMalloc(p, c);
+}
+
+void pool_free(void *p, size_t cls, int device, hipStream_t s) {
+  BlockCache &bc = block_cache(device);
+  hipEvent_t ev = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(bc.mu);
+    if (bc.cached + cls > kBlockCacheBytes) {
+      ev = nullptr;
+    } else if (!bc.spare.empty()) {
+      ev = bc.spare.back();
+      bc.spare.pop_back();
+    }
+  }
+  if (!ev && bc.cached + cls <= kBlockCacheBytes && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+    ev = nullptr;
+  if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+    if (ev) {
+      std::lock_guard<std::mutex> lk(bc.mu);
+      bc.spare.push_back(ev);
+    }
+    (void)hipFree(p);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(bc.mu);
+  bc.blocks.insert({cls, CachedBlock{p, ev}});
+  bc.cached += cls;
+}
+
 dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg) {
   if (ctx) ctx->err = msg;
   return st;
@@ -2014,6 +2104,8 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     if (N < 1 || N > hams[r]->D) return set_err(ctx, DACP_E_INVALID, "batched: need 1 <= N <= 2^L for every realisation");
     max_L = std::max(max_L, hams[r]->L);
   }
+  // every device buffer of the call, here and in the worker threads, stream-ordered from the pool
+  dacp::AllocStream pooled(ctx->stream, ctx->device);
   dacp_opts o;
   if (opts_in) o = *opts_in;
   else dacp_default_opts(&o);
@@ -2150,6 +2242,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   auto worker = [&](int w) {
     (void)hipSetDevice(ctx->device);
     dacp_ctx wc = &wctx[w];
+    dacp::AllocStream pooled_w(wc->stream, ctx->device);
     const double eps = o.eps > 0.0 ? o.eps : 1e-12;
     if (!ctx->batch_eig) {
       for (int r = w; r < count; r += nw) {

@@ -202,26 +202,79 @@ hipError_t launch_symmetrize(double *C, int64_t n, int64_t ldc, hipStream_t s);
 hipError_t launch_gather_rows(const double *src, int64_t lds, double *dst, int64_t ldd, const int *perm,
                               const double *scale, int rows, int cols, hipStream_t s);
 
+// Cached, stream-ordered allocation for the calling thread.  While an AllocStream is alive on a
+// thread, the DevBufs that thread allocates come from a per-device block cache and the DevBufs it
+// frees go back to it: a freed block carries an event recorded on the freeing thread's stream,
+// and the next user's stream waits on that event before the block is handed out, so reuse is
+// ordered behind every use on the freeing stream.  hipFree synchronises the whole device and
+// hipMalloc maps fresh memory; threads that each drive their own stream would otherwise serialise
+// on them.  The cache keeps freed blocks (rounded up to a size class, at most 1/4 larger) until
+// the process ends, up to kBlockCacheBytes per device; beyond that a freed block is released.
+// A pooled buffer must be used only on its scope's stream, or on other streams whose work the
+// host has waited for before the buffer is freed.
+constexpr size_t kBlockCacheBytes = size_t(32) << 30;
+// The calling thread's allocation scope (on = an AllocStream is alive; s may be the null stream).
+struct AllocState {
+  bool on = false;
+  hipStream_t s = nullptr;
+  int device = 0;
+};
+AllocState &alloc_state_tl();
+struct AllocStream {
+  AllocState prev;
+  AllocStream(hipStream_t s, int device);
+  ~AllocStream();
+  AllocStream(const AllocStream &) = delete;
+  AllocStream &operator=(const AllocStream &) = delete;
+};
+hipError_t pool_alloc(size_t nbytes, hipStream_t s, int device, void **p, size_t *cls);
+void pool_free(void *p, size_t cls, int device, hipStream_t s);
+
 // Device allocation owned by a scope.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  size_t pool_cls = 0;                // size class of a cached block, 0 = plain hipMalloc
+  hipStream_t pool_stream = nullptr;  // stream it was handed out on
+  int pool_device = 0;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
+  ~DevBuf() { release(); }
   hipError_t alloc(size_t nbytes) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
+    release();
     bytes = nbytes;
-    return nbytes ? hipMalloc(&p, nbytes) : hipSuccess;
+    if (!nbytes) return hipSuccess;
+    const AllocState &as = alloc_state_tl();
+    hipError_t e;
+    if (as.on) {
+      e = pool_alloc(nbytes, as.s, as.device, &p, &pool_cls);
+      if (e == hipSuccess) {
+        pool_stream = as.s;
+        pool_device = as.device;
+      }
+    } else {
+      e = hipMalloc(&p, nbytes);
+    }
+    if (e != hipSuccess) {
+      p = nullptr;
+      pool_cls = 0;
+    }
+    return e;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (pool_cls) {
+        const AllocState &as = alloc_state_tl();
+        pool_free(p, pool_cls, pool_device, as.on ? as.s : pool_stream);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     bytes = 0;
+    pool_cls = 0;
+    pool_stream = nullptr;
   }
   template <typename T>
   T *as() const {
