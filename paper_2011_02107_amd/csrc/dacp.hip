@@ -50,6 +50,19 @@ void vlog(const char *fmt, ...) {
   va_end(ap);
 }
 
+// fn(i) for i in [0, count) on up to `threads` host threads (thread t takes i = t, t + threads, ...).
+template <typename F>
+void host_parallel(int count, int threads, F fn) {
+  threads = std::max(1, std::min(threads, count));
+  std::vector<std::thread> ts;
+  for (int t = 1; t < threads; ++t)
+    ts.emplace_back([&, t] {
+      for (int i = t; i < count; i += threads) fn(i);
+    });
+  for (int i = 0; i < count; i += threads) fn(i);
+  for (auto &th : ts) th.join();
+}
+
 AllocState &alloc_state_tl() {
   static thread_local AllocState st;
   return st;
@@ -883,6 +896,34 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
   hipStream_t s = ctx->stream;
   Timer ts(ctx);
   if (verbose()) ts.start();
+  // Few output tiles against a long K (the small subspaces of batched realisations): both products
+  // as full squares with K split over workgroup layers, then the upper triangle mirrored as below.
+  {
+    const int64_t t = (m + 127) / 128;
+    int64_t sp = 1;
+    if (ctx->project_splitk && t * t < ctx->num_cus)
+      sp = std::min<int64_t>({64, (2 * ctx->num_cus + t * t - 1) / (t * t), std::max<int64_t>(1, D / 1024)});
+    if (sp > 1) {
+      DevBuf work, wall;
+      DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * m * m * sizeof(double)));
+      DACP_HIP(ctx, wall.alloc(static_cast<size_t>(D) * m * sizeof(double)));
+      double *W = wall.as<double>();
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, static_cast<int>(sp),
+                                              work.as<double>(), s));
+      DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
+      for (int s0 = 0; s0 < m; s0 += 64) {
+        const int bw = std::min(64, m - s0);
+        dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + s0, m, 1.0);
+        if (st) return st;
+      }
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, W, m, 0.0, P, ld, static_cast<int>(sp),
+                                              work.as<double>(), s));
+      DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
+      if (verbose()) vlog("projection: S and P with K split %d ways (m = %d) %.1f ms", static_cast<int>(sp), m, ts.stop_ms());
+      DACP_HIP(ctx, hipStreamSynchronize(s));
+      return DACP_OK;
+    }
+  }
   DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, s));
   DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
   if (verbose()) {
@@ -1281,6 +1322,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->project_whole = value;
     return DACP_OK;
   }
+  if (k == "project_splitk") {
+    if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "project_splitk: 0 or 1");
+    ctx->project_splitk = value;
+    return DACP_OK;
+  }
   if (k == "rec_xcd") {
     if (value < 0 || value > 3) return set_err(ctx, DACP_E_INVALID, "rec_xcd: 0..3 (bit 0 low pass, bit 1 high pass)");
     ctx->rec_xcd = value;
@@ -1321,6 +1367,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "rec_persist") *value = ctx->rec_persist;
   else if (k == "rec_xcd") *value = ctx->rec_xcd;
   else if (k == "project_whole") *value = ctx->project_whole;
+  else if (k == "project_splitk") *value = ctx->project_splitk;
   else if (k == "blocked") *value = ctx->blocked_min_n;
   else if (k == "batch_eig") *value = ctx->batch_eig;
   else if (k == "batch_workers") *value = ctx->batch_workers;
@@ -1900,6 +1947,7 @@ dacp_status batched_estimates(dacp_ctx ctx, int count, const dacp_ham *hams, con
     c.L = h->L;
     return c;
   };
+  const double tl0 = now_ms();
   if (!(o.e_bound > 0.0)) {
     for (int r = 0; r < count; ++r) {
       dacp_ham h = hams[r];
@@ -1924,19 +1972,32 @@ dacp_status batched_estimates(dacp_ctx ctx, int count, const dacp_ham *hams, con
     DACP_TRY(to_device(ctx, dspecs.p, specs.data(), sizeof(BatchSpec) * specs.size()));
     DACP_HIP(ctx, dacp::launch_batch_spectral(dspecs.as<BatchSpec>(), static_cast<int>(specs.size()), max_L,
                                               ctx->stream));
+    const double tl = now_ms();
+    std::vector<std::vector<double>> outs(count);
     for (int r = 0; r < count; ++r) {
-      std::vector<double> o2(2 * steps[r] + 1);
-      DACP_TRY(to_host(ctx, o2.data(), out[r].p, o2.size() * sizeof(double)));
+      outs[r].resize(2 * steps[r] + 1);
+      DACP_TRY(to_host(ctx, outs[r].data(), out[r].p, outs[r].size() * sizeof(double)));
+    }
+    // the bounds of the realisations on host threads (c = nullptr: no message), then the first
+    // failure again on the context for its message
+    auto bound_one = [&](dacp_ctx c, int r) -> dacp_status {
+      const std::vector<double> &o2 = outs[r];
       const int k = static_cast<int>(o2[2 * steps[r]]);
-      if (k < 1 || k > steps[r]) return set_err(ctx, DACP_E_NUMERIC, "batched: Lanczos run " + std::to_string(r));
+      if (k < 1 || k > steps[r]) return set_err(c, DACP_E_NUMERIC, "batched: Lanczos run " + std::to_string(r));
       std::vector<double> al(o2.begin(), o2.begin() + k), be(o2.begin() + steps[r], o2.begin() + steps[r] + k);
       for (int j = 0; j < k; ++j)
         if (!std::isfinite(al[j]) || !std::isfinite(be[j]))
-          return set_err(ctx, DACP_E_NUMERIC, "batched: non-finite Lanczos run " + std::to_string(r));
+          return set_err(c, DACP_E_NUMERIC, "batched: non-finite Lanczos run " + std::to_string(r));
       double th_lo = 0.0, th_hi = 0.0;
-      DACP_TRY(lanczos_bound(ctx, al, be, 1.01, hams[r]->sum_abs, &e_bs[r], &th_lo, &th_hi));
+      DACP_TRY(lanczos_bound(c, al, be, 1.01, hams[r]->sum_abs, &e_bs[r], &th_lo, &th_hi));
       norm_est[r] = std::max(std::fabs(th_lo), std::fabs(th_hi));
-    }
+      return DACP_OK;
+    };
+    std::vector<dacp_status> bst(count, DACP_OK);
+    dacp::host_parallel(count, ctx->batch_workers, [&](int r) { bst[r] = bound_one(nullptr, r); });
+    for (int r = 0; r < count; ++r)
+      if (bst[r]) return bound_one(ctx, r);
+    vlog("batched Lanczos launch and bounds: %.1f ms (host part %.1f ms)", now_ms() - tl0, now_ms() - tl);
     specs.clear();
   } else {
     for (int r = 0; r < count; ++r) {
@@ -2122,10 +2183,12 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     DACP_TRY(batched_estimates(ctx, count, hams, o, max_L, e_bs, norm_est, mus));
     const double t_spec = now_ms() - tb;
     vlog("batched bounds and densities of %d realisations: %.1f ms", count, t_spec);
+    const double tp = now_ms();
+    dacp::host_parallel(count, ctx->batch_workers,
+                  [&](int r) { plans[r] = make_plan(o, hams[r]->D, N, e_bs[r], mus[r], window_ratio, 0); });
     for (int r = 0; r < count; ++r) {
       std::memset(&rep[r], 0, sizeof(dacp_report));
       tol[r] = o.tol_rel * norm_est[r];
-      plans[r] = make_plan(o, hams[r]->D, N, e_bs[r], mus[r], window_ratio, 0);
       const Plan &pl = plans[r];
       rep[r].e_bound = e_bs[r];
       rep[r].a = pl.a;
@@ -2137,7 +2200,9 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
       rep[r].evol_group = 1;
       rep[r].t_bound_ms = t_spec;
     }
+    vlog("batched plans: %.1f ms", now_ms() - tp);
   }
+  const double t_setup = now_ms();
 
   // start blocks, bases and the column table of the persistent launch
   std::vector<DevBuf> psi(count), vb(count), ksd(count), scr(count);
@@ -2203,6 +2268,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   DevBuf dcols;
   DACP_HIP(ctx, dcols.alloc(sizeof(BatchCol) * cols.size()));
   DACP_TRY(to_device(ctx, dcols.p, cols.data(), sizeof(BatchCol) * cols.size()));
+  vlog("batched start blocks, bases and column table: %.1f ms", now_ms() - t_setup);
   const double tb0 = now_ms();
   DACP_HIP(ctx, dacp::launch_batch_chebyshev(dcols.as<BatchCol>(), static_cast<int>(cols.size()), max_L, ctx->stream));
   std::vector<int> flag(count);

@@ -445,17 +445,26 @@ def test_project_parity_split_k(ctx):
     S = torch.zeros((m, m), dtype=torch.float64, device=DEV)
     P = torch.zeros((m, m), dtype=torch.float64, device=DEV)
     try:
+        ctx.tune("project_splitk", 0)
         ctx.tune("project_whole", 0)
         B.dacp_project(ctx, ham, to_dev(V), S, P)
+        ctx.tune("project_whole", 1)
+        # the one-GEMM form on the same input
+        P1 = torch.zeros_like(P)
+        B.dacp_project(ctx, ham, to_dev(V), S, P1)
     finally:
         ctx.tune("project_whole", 1)
+        ctx.tune("project_splitk", 1)
     S_ref, P_ref = subspace.project(lambda X: hamiltonian.apply_h(L, terms, X), V)
     assert np.abs(host(S) - S_ref).max() < 1e-13
     assert np.abs(host(P) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
-    # the one-GEMM form on the same input
-    P1 = torch.zeros_like(P)
-    B.dacp_project(ctx, ham, to_dev(V), S, P1)
     assert np.abs(host(P1) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
+    # full squares with K split 21 ways (25 output tiles), mirrored
+    S2, P2 = torch.zeros_like(S), torch.zeros_like(P)
+    B.dacp_project(ctx, ham, to_dev(V), S2, P2)
+    assert np.abs(host(S2) - S_ref).max() < 1e-13
+    assert np.abs(host(P2) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
+    assert np.array_equal(host(S2), host(S2).T) and np.array_equal(host(P2), host(P2).T)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 130, 400])
