@@ -72,16 +72,12 @@ __device__ void givens_fast(double x, double z, double &c, double &s) {
   if (!(r2 > 1e-290 && r2 < 1e290)) givens_pair(x, z, c, s);
 }
 
-// One implicit QR sweep with a Wilkinson shift on the unreduced block p..q of (d, e) (Golub and
-// Van Loan's symmetric QR step).  The chase keeps d[k], e[k] and its bulge in registers and reads
+// One implicit QR sweep with shift mu on the unreduced block p..q of (d, e) (Golub and Van Loan's
+// symmetric QR step).  The chase keeps d[k], e[k] and its bulge in registers and reads
 // d, e two rotations ahead (those reads may run up to two entries past e's end, into the
 // reduction slots: in the workgroup's LDS and unused); the pairs (c, s) of rotations p..q-1 go
 // to cs.
-__device__ void qr_sweep(double *d, double *e, int p, int q, double *cs) {
-  const double a = d[q - 1], bb = e[q - 1], cq = d[q];
-  const double delta = 0.5 * (a - cq);
-  const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * hypot(delta, bb);
-  const double mu = (den != 0.0) ? cq - bb * bb / den : cq;
+__device__ void qr_sweep(double *d, double *e, int p, int q, double mu, double *cs) {
   double dk = d[p], ek = e[p], dn = d[p + 1], en = e[p + 1], dn2 = d[p + 2], en2 = e[p + 2];
   double x = dk - mu, z = ek;
   double c, sn;
@@ -113,34 +109,88 @@ __device__ void qr_sweep(double *d, double *e, int p, int q, double *cs) {
   cs[2 * (q - 1 - p) + 1] = sn;
 }
 
+// Eigenvalue j (ascending, 0-based) of the symmetric tridiagonal (d, e) by bisection inside
+// [lo, hi] on the Sturm count: the number of negative pivots of the L D L^T factorisation of
+// T - x I is the number of eigenvalues below x.  A pivot smaller in magnitude than pivmin is
+// replaced by -pivmin.
+__device__ double bisect_eig(const double *d, const double *e, int n, int j, double lo, double hi, double pivmin) {
+  for (int it = 0; it < 128; ++it) {
+    const double x = 0.5 * (lo + hi);
+    if (!(x > lo && x < hi)) break;
+    int cnt = 0;
+    double piv = d[0] - x;
+    if (fabs(piv) < pivmin) piv = -pivmin;
+    cnt += piv < 0.0;
+    for (int i = 1; i < n; ++i) {
+      piv = (d[i] - x) - e[i - 1] * e[i - 1] / piv;
+      if (fabs(piv) < pivmin) piv = -pivmin;
+      cnt += piv < 0.0;
+    }
+    if (cnt > j) hi = x;
+    else lo = x;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Index of the eigenvalue not yet deflated (used[i] == 0) nearest to x in the ascending list lam,
+// or -1 when every one is used.
+__device__ int nearest_unused(const double *lam, const double *used, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if (lam[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  int l = lo - 1, r = lo;
+  while (l >= 0 && used[l] != 0.0) --l;
+  while (r < n && used[r] != 0.0) ++r;
+  if (l < 0) return r < n ? r : -1;
+  if (r >= n) return l;
+  return (x - lam[l] <= lam[r] - x) ? l : r;
+}
+
 // Per-matrix state of the QR phase, held by thread 0.
 struct QrState {
   int q;
   long iters, max_iters;
   bool failed;
+  double small;  // off-diagonals at most this (eps times a bound on the norm) count as zero
 };
 
 // Thread 0: up to S sweeps (deflating from the bottom between them) into batch buffer `cs`
-// (S blocks of n pairs) and its header mt = {count, p_0.., q_0..}.
+// (S blocks of n pairs) and its header mt = {count, p_0.., q_0..}.  lam holds all eigenvalues
+// of the tridiagonal from bisection, ascending; used marks those already deflated.  A sweep
+// shifts by the Wilkinson shift of its block's trailing 2 x 2, or by the nearest eigenvalue not
+// yet deflated when that lies within twice the trailing off-diagonal of it: an exact shift
+// deflates the bottom in about one sweep instead of two.
 template <int S>
-__device__ void chase_batch(QrState &st, double *d, double *e, int n, double *cs, int *mt) {
+__device__ void chase_batch(QrState &st, double *d, double *e, int n, const double *lam, double *used, double *cs,
+                            int *mt) {
   const double eps = 2.220446049250313e-16;
   int cnt = 0;
   while (cnt < S && st.q > 0 && !st.failed) {
     const int q = st.q;
-    if (e[q - 1] == 0.0 || fabs(e[q - 1]) <= eps * (fabs(d[q - 1]) + fabs(d[q]))) {
+    if (fabs(e[q - 1]) <= fmax(st.small, eps * (fabs(d[q - 1]) + fabs(d[q])))) {
       e[q - 1] = 0.0;
+      const int j = nearest_unused(lam, used, n, d[q]);
+      if (j >= 0) used[j] = 1.0;
       --st.q;
       continue;
     }
     int p = q - 1;
-    while (p > 0 && !(fabs(e[p - 1]) <= eps * (fabs(d[p - 1]) + fabs(d[p])))) --p;
+    while (p > 0 && !(fabs(e[p - 1]) <= fmax(st.small, eps * (fabs(d[p - 1]) + fabs(d[p]))))) --p;
     if (p > 0) e[p - 1] = 0.0;
     if (++st.iters > st.max_iters) {
       st.failed = true;
       break;
     }
-    qr_sweep(d, e, p, q, cs + static_cast<size_t>(cnt) * 2 * n);
+    const double a = d[q - 1], bb = e[q - 1], cq = d[q];
+    const double delta = 0.5 * (a - cq);
+    const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * hypot(delta, bb);
+    double mu = (den != 0.0) ? cq - bb * bb / den : cq;
+    const int j = nearest_unused(lam, used, n, mu);
+    if (j >= 0 && fabs(lam[j] - mu) <= 2.0 * fabs(bb)) mu = lam[j];
+    qr_sweep(d, e, p, q, mu, cs + static_cast<size_t>(cnt) * 2 * n);
     mt[1 + cnt] = p;
     mt[1 + S + cnt] = q;
     ++cnt;
@@ -343,6 +393,26 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
   for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += kBT)
     pb.Zr[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   __syncthreads();
+  // ---- eigenvalues of the tridiagonal by bisection, one per thread (the QR shifts): lam in v,
+  // deflation marks in w
+  double tnorm = 0.0;  // Gershgorin bound on the norm of the tridiagonal
+  {
+    double glo = d[0], ghi = d[0], emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+      glo = fmin(glo, d[i] - r);
+      ghi = fmax(ghi, d[i] + r);
+      if (i + 1 < n) emax = fmax(emax, e[i] * e[i]);
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax);
+    const double pad = 2.220446049250313e-16 * fmax(fabs(glo), fabs(ghi)) + pivmin;
+    for (int j = tid; j < n; j += kBT) {
+      vsh[j] = bisect_eig(d, e, n, j, glo - pad, ghi + pad, pivmin);
+      wsh[j] = 0.0;
+    }
+    tnorm = fmax(fabs(glo), fabs(ghi));
+  }
+  __syncthreads();
   // ---- 2. implicit symmetric QR, batch b+1 chased while batch b is applied; the applying
   // threads fill the time the chase takes with the Householder steps that form Q (3.), which
   // depend on phase 1 only, polling the count of finished chases between steps
@@ -353,9 +423,11 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
   if (wave != 0)
     for (int col = a; col < n; col += kApplyThreads)
       for (int r = 0; r < n; ++r) pb.Q[static_cast<int64_t>(r) * n + col] = (r == col) ? 1.0 : 0.0;
-  QrState qs{n - 1, 0, 40L * n + 100, false};  // meaningful in thread 0 only
+  // deflation: an off-diagonal below eps (|d_k| + |d_k+1|) or below eps times the norm bound (a
+  // backward error of that size; eigenvalues near zero then need no relative accuracy)
+  QrState qs{n - 1, 0, 40L * n + 100, false, 2.220446049250313e-16 * tnorm};  // thread 0's
   if (tid == 0) {
-    chase_batch<S>(qs, d, e, n, csb, meta);
+    chase_batch<S>(qs, d, e, n, vsh, wsh, csb, meta);
     *chased = 0;
   }
   __syncthreads();
@@ -366,7 +438,7 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
       // the chase is one dependent chain: let its wave issue ahead of the applying waves
       __builtin_amdgcn_s_setprio(3);
       if (tid == 0) {
-        chase_batch<S>(qs, d, e, n, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr);
+        chase_batch<S>(qs, d, e, n, vsh, wsh, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr);
         *chased = it + 1;
       }
       __builtin_amdgcn_s_setprio(0);
