@@ -29,6 +29,7 @@ constexpr int kApplyThreads = kBT - 64;  // waves 1.. apply rotations while wave
 constexpr int kPrefetch = 8;             // rows of a column loaded ahead of their rotations
 constexpr int kRowBatch = 16;            // rows of a column in flight in the BLAS-2 passes
 constexpr int kQBatch = 8;               // the same while forming Q beside the rotations
+constexpr int kFuseBatch = 8;            // the same in the fused update-and-product pass
 constexpr size_t kLdsMax = 160 * 1024;
 
 // Sum over the workgroup, the same value returned to every thread (fixed order: lanes by
@@ -319,14 +320,25 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     }
     return;
   }
-  // ---- 1. tridiagonalise
+  // ---- 1. tridiagonalise.  Step k applies step k-1's rank-2 update in the same pass over the
+  // trailing block as its own product A22 v (one read and one write of the block per step);
+  // row k gets that update first, since it holds the next Householder vector.
+  double *vp = csb, *wp = csb + n;  // step k-1's v and w (index i = row k + i), in the Givens buffers
+  double *vc = vsh, *wc = wsh;      // step k's (index i = row k + 1 + i)
+  bool have_prev = false;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
-    const double *x = A + static_cast<int64_t>(k) * n + k + 1;
+    double *rowk = A + static_cast<int64_t>(k) * n;
+    if (have_prev) {
+      const double v0p = vp[0], w0p = wp[0];
+      for (int j = k + tid; j < n; j += kBT) rowk[j] -= v0p * wp[j - k] + w0p * vp[j - k];
+      __syncthreads();
+    }
+    const double *x = rowk + k + 1;
+    const double x0 = x[0];  // read before the reduction's barriers: thread 0 overwrites it below
     double s = 0.0;
     for (int i = 1 + tid; i < m; i += kBT) s += x[i] * x[i];
     const double sigma = block_sum(s, red);
-    const double x0 = x[0];
     double alpha = x0, v0 = 0.0, beta = 0.0;
     if (sigma > 0.0) {
       const double mu = sqrt(x0 * x0 + sigma);
@@ -334,59 +346,76 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
       v0 = x0 - alpha;
       beta = 2.0 / (v0 * v0 + sigma);
     }
-    for (int i = tid; i < m; i += kBT) vsh[i] = (i == 0) ? v0 : x[i];
+    for (int i = tid; i < m; i += kBT) vc[i] = (i == 0) ? v0 : x[i];
+    __syncthreads();
     if (tid == 0) {
-      d[k] = A[static_cast<int64_t>(k) * n + k];
+      d[k] = rowk[k];
       e[k] = alpha;
       betas[k] = beta;
-      A[static_cast<int64_t>(k) * n + k + 1] = v0;  // row k keeps v for forming Q
+      rowk[k + 1] = v0;  // row k keeps v for forming Q
     }
-    __syncthreads();
-    if (beta == 0.0) continue;
+    // step k-1's update of A22 and p = beta A22 v as column sums (A22 is symmetric): one thread
+    // per column, kRowBatch rows loaded before any is stored
     double *a22 = A + static_cast<int64_t>(k + 1) * n + k + 1;
-    // p = beta A22 v as column sums (A22 is symmetric): one thread per column, kRowBatch rows
-    // of loads in flight
     for (int j = tid; j < m; j += kBT) {
-      const double *cj = a22 + j;
+      double *cj = a22 + j;
       double t = 0.0;
-      int i = 0;
-      for (; i + kRowBatch <= m; i += kRowBatch) {
-        double a[kRowBatch];
+      if (have_prev) {
+        const double vj = vp[j + 1], wj = wp[j + 1];
+        int i = 0;
+        for (; i + kFuseBatch <= m; i += kFuseBatch) {
+          double a[kFuseBatch];
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) a[u] = cj[static_cast<int64_t>(i + u) * n];
+          for (int u = 0; u < kFuseBatch; ++u) a[u] = cj[static_cast<int64_t>(i + u) * n];
 #pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) t += a[u] * vsh[i + u];
+          for (int u = 0; u < kFuseBatch; ++u) {
+            a[u] -= vp[i + u + 1] * wj + wp[i + u + 1] * vj;
+            cj[static_cast<int64_t>(i + u) * n] = a[u];
+            t += a[u] * vc[i + u];
+          }
+        }
+        for (; i < m; ++i) {
+          const double a = cj[static_cast<int64_t>(i) * n] - (vp[i + 1] * wj + wp[i + 1] * vj);
+          cj[static_cast<int64_t>(i) * n] = a;
+          t += a * vc[i];
+        }
+      } else {
+        int i = 0;
+        for (; i + kRowBatch <= m; i += kRowBatch) {
+          double a[kRowBatch];
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u) a[u] = cj[static_cast<int64_t>(i + u) * n];
+#pragma unroll
+          for (int u = 0; u < kRowBatch; ++u) t += a[u] * vc[i + u];
+        }
+        for (; i < m; ++i) t += cj[static_cast<int64_t>(i) * n] * vc[i];
       }
-      for (; i < m; ++i) t += cj[static_cast<int64_t>(i) * n] * vsh[i];
-      wsh[j] = beta * t;
+      wc[j] = beta * t;
     }
     __syncthreads();
     // w = p - (beta p^T v / 2) v
     double pv = 0.0;
-    for (int i = tid; i < m; i += kBT) pv += wsh[i] * vsh[i];
+    for (int i = tid; i < m; i += kBT) pv += wc[i] * vc[i];
     const double half = 0.5 * beta * block_sum(pv, red);
-    for (int i = tid; i < m; i += kBT) wsh[i] -= half * vsh[i];
+    for (int i = tid; i < m; i += kBT) wc[i] -= half * vc[i];
     __syncthreads();
-    // A22 -= v w^T + w v^T, one thread per column, kRowBatch rows loaded before any is stored
-    for (int j = tid; j < m; j += kBT) {
-      double *cj = a22 + j;
-      const double vj = vsh[j], wj = wsh[j];
-      int i = 0;
-      for (; i + kRowBatch <= m; i += kRowBatch) {
-        double a[kRowBatch];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) a[u] = cj[static_cast<int64_t>(i + u) * n];
-#pragma unroll
-        for (int u = 0; u < kRowBatch; ++u) cj[static_cast<int64_t>(i + u) * n] = a[u] - (vsh[i + u] * wj + wsh[i + u] * vj);
-      }
-      for (; i < m; ++i) cj[static_cast<int64_t>(i) * n] -= vsh[i] * wj + wsh[i] * vj;
-    }
-    __syncthreads();
+    double *t1 = vp, *t2 = wp;
+    vp = vc;
+    wp = wc;
+    vc = t1;
+    wc = t2;
+    have_prev = true;
   }
   if (tid == 0) {
-    d[n - 2] = A[static_cast<int64_t>(n - 2) * n + n - 2];
-    e[n - 2] = A[static_cast<int64_t>(n - 2) * n + n - 1];
-    d[n - 1] = A[static_cast<int64_t>(n - 1) * n + n - 1];
+    double *a2 = A + static_cast<int64_t>(n - 2) * n + n - 2;  // the trailing 2 x 2
+    if (have_prev) {  // the last step's update (its index 0 is row n - 2)
+      a2[0] -= vp[0] * wp[0] + wp[0] * vp[0];
+      a2[1] -= vp[0] * wp[1] + wp[0] * vp[1];
+      a2[n + 1] -= vp[1] * wp[1] + wp[1] * vp[1];
+    }
+    d[n - 2] = a2[0];
+    e[n - 2] = a2[1];
+    d[n - 1] = a2[n + 1];
     e[n - 1] = 0.0;
   }
   // Zr = I
