@@ -98,9 +98,9 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *                 workgroups per compute unit that prefetch their next tile
  *   "project_whole" projection: 1 = P = V^T (H V) as one GEMM when the block H V (D x m FP64)
  *                 fits in free device memory beside V (default), 0 = always in column chunks
- *   "project_splitk" projection: 1 = when the m x m output has fewer 128 x 128 tiles than the GPU
- *                 has compute units, S and P as full squares with K = D split over up to 64
- *                 workgroup layers (each at least 1024 rows), then mirrored (default); 0 = off
+ *   "project_splitk" projection: 1 = when the upper triangle of the m x m output has fewer
+ *                 128 x 128 tiles than the GPU has compute units, S and P with K = D split over up
+ *                 to 64 workgroup layers (each at least 1024 rows), then mirrored (default); 0 = off
  *   "rec_xcd"     fused recurrence tile order, bit 0 for the low pass and bit 1 for the high
  *                 pass: set = each of the 8 XCDs takes a contiguous eighth of the tiles, clear =
  *                 tiles dealt round-robin in launch order (default 2: high pass only)

@@ -897,18 +897,18 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
   Timer ts(ctx);
   if (verbose()) ts.start();
   // Few output tiles against a long K (the small subspaces of batched realisations): both products
-  // as full squares with K split over workgroup layers, then the upper triangle mirrored as below.
+  // as upper-triangle tiles with K split over workgroup layers, then mirrored as below.
   {
-    const int64_t t = (m + 127) / 128;
+    const int64_t t = (m + 127) / 128, tu = t * (t + 1) / 2;
     int64_t sp = 1;
-    if (ctx->project_splitk && t * t < ctx->num_cus)
-      sp = std::min<int64_t>({64, (2 * ctx->num_cus + t * t - 1) / (t * t), std::max<int64_t>(1, D / 1024)});
+    if (ctx->project_splitk && tu < ctx->num_cus)
+      sp = std::min<int64_t>({64, (2 * ctx->num_cus + tu - 1) / tu, std::max<int64_t>(1, D / 1024)});
     if (sp > 1) {
       DevBuf work, wall;
       DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * m * m * sizeof(double)));
       DACP_HIP(ctx, wall.alloc(static_cast<size_t>(D) * m * sizeof(double)));
       double *W = wall.as<double>();
-      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, static_cast<int>(sp),
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, static_cast<int>(sp),
                                               work.as<double>(), s));
       DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
       for (int s0 = 0; s0 < m; s0 += 64) {
@@ -916,7 +916,7 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
         dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + s0, m, 1.0);
         if (st) return st;
       }
-      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, W, m, 0.0, P, ld, static_cast<int>(sp),
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, W, m, 0.0, P, ld, 1, static_cast<int>(sp),
                                               work.as<double>(), s));
       DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
       if (verbose()) vlog("projection: S and P with K split %d ways (m = %d) %.1f ms", static_cast<int>(sp), m, ts.stop_ms());
@@ -984,7 +984,7 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
     }
     const int sp = splits_for(c1, w);
     if (sp > 1)
-      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, sp,
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, 0, sp,
                                               work.as<double>(), s));
     else
       DACP_HIP(ctx, dacp::launch_dgemm(1, 0, c1, w, D, 1.0, V, ldv, W, cw, 0.0, P + c0, ld, 0, s));

@@ -194,7 +194,7 @@ hipError_t launch_dgemm_impl(int transA, int transB, int64_t M, int64_t N, int64
                              int upper, int splits, double *work, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tmc = (M + BM - 1) / BM, tnc = (N + BN - 1) / BN;
-  if (splits < 1 || (splits > 1 && (!work || upper))) return hipErrorInvalidValue;
+  if (splits < 1 || (splits > 1 && !work)) return hipErrorInvalidValue;
   if (upper && M != N) return hipErrorInvalidValue;
   const int64_t kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
   // super-blocks of 8 x 8 tiles, dealt 8 at a time (one per XCD), 64 workgroups each
@@ -226,10 +226,12 @@ hipError_t launch_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K,
   return launch_dgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, upper, 1, nullptr, s);
 }
 
+// With upper set (M == N), only tiles on or above the diagonal are computed and the reduction
+// leaves the tiles below it undefined: the caller mirrors the upper triangle afterwards.
 hipError_t launch_dgemm_splitk(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
                                int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
-                               int splits, double *work, hipStream_t s) {
-  return launch_dgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 0, splits, work, s);
+                               int upper, int splits, double *work, hipStream_t s) {
+  return launch_dgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, upper, splits, work, s);
 }
 
 // Copy the upper triangle onto the lower one (tiled through LDS).

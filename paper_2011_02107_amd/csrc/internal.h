@@ -195,7 +195,7 @@ hipError_t launch_dgemm(int transA, int transB, int64_t M, int64_t N, int64_t K,
 // Same with K split over `splits` workgroup layers; work holds splits * M * N doubles (not upper).
 hipError_t launch_dgemm_splitk(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
                                int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
-                               int splits, double *work, hipStream_t s);
+                               int upper, int splits, double *work, hipStream_t s);
 hipError_t launch_mirror_upper(double *C, int64_t n, int64_t ldc, hipStream_t s);
 hipError_t launch_symmetrize(double *C, int64_t n, int64_t ldc, hipStream_t s);
 

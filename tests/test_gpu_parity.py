@@ -459,7 +459,7 @@ def test_project_parity_split_k(ctx):
     assert np.abs(host(S) - S_ref).max() < 1e-13
     assert np.abs(host(P) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
     assert np.abs(host(P1) - P_ref).max() < 1e-12 * np.abs(P_ref).max()
-    # full squares with K split 21 ways (25 output tiles), mirrored
+    # upper-triangle tiles with K split 35 ways (15 tiles), mirrored
     S2, P2 = torch.zeros_like(S), torch.zeros_like(P)
     B.dacp_project(ctx, ham, to_dev(V), S2, P2)
     assert np.abs(host(S2) - S_ref).max() < 1e-13
