@@ -193,6 +193,8 @@ def batch96(args):
     N = 200
     opts = B.default_opts(b=8, precision=B.DACP_F32, fp64_tail_frac=0.3)
     B.dacp_central_eigs_batched(ctx, hams[:3], N, opts)  # load the kernels
+    for _ in range(args.warmup):  # untimed full calls: the device block cache then holds the call's buffers
+        B.dacp_central_eigs_batched(ctx, hams, N, opts)
     times = []
     for _ in range(max(1, args.steps)):
         torch.cuda.synchronize()
@@ -211,7 +213,8 @@ def batch96(args):
         "s_per_call": dt, "all_reached_N": bool(np.all(n_out == N)),
         "shared_launch_ms": reps[0]["t_evol_ms"], "bounds_ms": reps[0]["t_bound_ms"],
         "per_realisation_loop_fp64": {"value": N * len(hams) / loop, "s": loop, "timed": "first 12, scaled"},
-        "speedup_vs_loop": loop / dt, "dtype": "f32-filter+f64", "data": "synthetic"}), flush=True)
+        "speedup_vs_loop": loop / dt, "steps": max(1, args.steps), "warmup": args.warmup,
+        "dtype": "f32-filter+f64", "data": "synthetic"}), flush=True)
 
 
 def glass18_learned(args):
