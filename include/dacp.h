@@ -311,6 +311,8 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
  *   n_out[count]             host; N, or the number accepted for a realisation that fell short
  *   reports[count]           host, may be NULL; per realisation (t_evol_ms is the time of the
  *                            shared launch, t_filter_ms is 0: the filter runs inside it)
+ * Device buffers of the call come from a per-device block cache that keeps freed blocks (up to
+ * 32 GB) for later calls until the process ends; reuse is ordered by events on the streams.
  * Returns DACP_E_INVALID for L > 14, DACP_E_BOUNDS if a bound is below ||H||, DACP_E_WINDOW
  * if some realisation stays short after its retry (the others are still filled in). */
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
