@@ -711,6 +711,30 @@ def test_central_eigs_batched_per_problem_eigensolver(ctx):
         _check_central(e1[r], ref, norm, N)
 
 
+def test_central_eigs_batched_repeat_reuses_cached_blocks(ctx):
+    """Device buffers of a batched call come from a block cache whose reuse is ordered by stream
+    events: a second identical call (served from the cache, its blocks handed between the worker
+    threads' streams) returns the same values bit for bit, also after a larger call in between
+    (whose first realisations, with the same indices and start blocks, match bit for bit too)."""
+    N = 40
+    specs = [(9, 21), (10, 22), (8, 23), (10, 24)]
+    hams = [B.dacp_build_hamiltonian(ctx, L, inputs.spin_glass(L, seed)) for L, seed in specs]
+    opts = B.default_opts(b=8)
+    e1, r1, n1, _, st1 = B.dacp_central_eigs_batched(ctx, hams[:3], N, opts)
+    e2, r2, n2, _, st2 = B.dacp_central_eigs_batched(ctx, hams[:3], N, opts)
+    big = B.dacp_central_eigs_batched(ctx, hams + hams, N, opts)
+    e3, r3, n3, _, st3 = B.dacp_central_eigs_batched(ctx, hams[:3], N, opts)
+    assert st1 == st2 == st3 == big[4] == 0
+    assert np.all(n1 == N) and np.all(n2 == N) and np.all(n3 == N) and np.all(big[2] == N)
+    assert np.array_equal(e1, e2) and np.array_equal(e1, e3)
+    assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
+    assert np.array_equal(big[0][:3], e1)
+    # realisations 4..6 repeat the Hamiltonians of 0..2 with start blocks of their own index
+    ref, norm = central.central_eigenvalues(10, inputs.spin_glass(10, 22), N)
+    _check_central(e1[1], ref, norm, N)
+    _check_central(big[0][5], ref, norm, N)
+
+
 def test_central_eigs_batched_L14_and_L12(ctx):
     """L = 14 keeps the older recurrence term in global scratch; checked against the Jordan-Wigner
     closed form, next to an L = 12 spin glass against the dense oracle."""
