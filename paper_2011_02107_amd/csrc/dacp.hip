@@ -106,6 +106,7 @@ AllocStream::~AllocStream() { alloc_state_tl() = prev; }
 
 hipError_t pool_alloc(size_t nbytes, hipStream_t s, int device, void **p, size_t *cls) {
   const size_t c = size_class(nbytes);
+  *cls = c;
   BlockCache &bc = block_cache(device);
   {
     std::unique_lock<std::mutex> lk(bc.mu);
@@ -116,41 +117,65 @@ hipError_t pool_alloc(size_t nbytes, hipStream_t s, int device, void **p, size_t
       bc.cached -= c;
       bc.spare.push_back(b.ready);
       lk.unlock();
-      *p = b.p;
-      *cls = c;
       // the wait takes the event's state now; the event may be recorded again afterwards
-      return hipStreamWaitEvent(s, b.ready, 0);
+      const hipError_t e = hipStreamWaitEvent(s, b.ready, 0);
+      if (e != hipSuccess) {
+        (void)hipFree(b.p);  // synchronises the device, so its last use is over
+        return e;
+      }
+      *p = b.p;
+      return hipSuccess;
     }
   }
-  *cls = c;
-  return hipMalloc(p, c);
+  hipError_t e = hipMalloc(p, c);
+  if (e == hipErrorOutOfMemory) {
+    // hand every cached block of the device back to the runtime, then try once more
+    std::vector<void *> held;
+    {
+      std::lock_guard<std::mutex> lk(bc.mu);
+      for (const auto &kv : bc.blocks) {
+        held.push_back(kv.second.p);
+        bc.spare.push_back(kv.second.ready);
+      }
+      bc.blocks.clear();
+      bc.cached = 0;
+    }
+    if (!held.empty()) {
+      (void)hipGetLastError();
+      for (void *q : held) (void)hipFree(q);
+      e = hipMalloc(p, c);
+    }
+  }
+  return e;
 }
 
 void pool_free(void *p, size_t cls, int device, hipStream_t s) {
   BlockCache &bc = block_cache(device);
   hipEvent_t ev = nullptr;
+  bool keep;
   {
     std::lock_guard<std::mutex> lk(bc.mu);
-    if (bc.cached + cls > kBlockCacheBytes) {
-      ev = nullptr;
-    } else if (!bc.spare.empty()) {
-      ev = bc.spare.back();
-      bc.spare.pop_back();
+    keep = bc.cached + cls <= kBlockCacheBytes;
+    if (keep) {
+      bc.cached += cls;  // reserved until the block is filed below or released
+      if (!bc.spare.empty()) {
+        ev = bc.spare.back();
+        bc.spare.pop_back();
+      }
     }
   }
-  if (!ev && bc.cached + cls <= kBlockCacheBytes && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
-    ev = nullptr;
-  if (!ev || hipEventRecord(ev, s) != hipSuccess) {
-    if (ev) {
-      std::lock_guard<std::mutex> lk(bc.mu);
-      bc.spare.push_back(ev);
-    }
-    (void)hipFree(p);
+  if (keep && !ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+  if (keep && ev && hipEventRecord(ev, s) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(bc.mu);
+    bc.blocks.insert({cls, CachedBlock{p, ev}});
     return;
   }
-  std::lock_guard<std::mutex> lk(bc.mu);
-  bc.blocks.insert({cls, CachedBlock{p, ev}});
-  bc.cached += cls;
+  {
+    std::lock_guard<std::mutex> lk(bc.mu);
+    if (keep) bc.cached -= cls;
+    if (ev) bc.spare.push_back(ev);
+  }
+  (void)hipFree(p);
 }
 
 dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg) {
