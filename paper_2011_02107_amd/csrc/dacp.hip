@@ -914,6 +914,44 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
 }
 
 // ------------------------------------------------------------- projection
+// K splits of the projection's small form (1: the shape does not take it): when the upper
+// triangle of the m x m output has fewer 128 x 128 tiles than the GPU has compute units, K = D is
+// split over up to 64 workgroup layers of at least 1024 rows each.
+int64_t project_small_splits(dacp_ctx ctx, int64_t D, int m) {
+  const int64_t t = (m + 127) / 128, tu = t * (t + 1) / 2;
+  if (!ctx->project_splitk || tu >= ctx->num_cus) return 1;
+  return std::min<int64_t>({64, (2 * ctx->num_cus + tu - 1) / tu, std::max<int64_t>(1, D / 1024)});
+}
+
+// One product of the small form, queued on the context's stream without waiting: part 1 is
+// S = V^T V, part 2 is P = V^T (H V).  Upper-triangle tiles with split K, then mirrored.  The
+// scratch buffers are released on return; only stream-ordered reuse makes that safe before the
+// kernels finish (the block cache of an AllocStream scope, or hipFree's device synchronisation).
+dacp_status project_small(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *out, int64_t ld,
+                          int part) {
+  const int64_t D = h->D;
+  hipStream_t s = ctx->stream;
+  const int sp = static_cast<int>(project_small_splits(ctx, D, m));
+  DevBuf work, wall;
+  DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * m * m * sizeof(double)));
+  const double *B = V;
+  int64_t ldb = ldv;
+  if (part == 2) {
+    DACP_HIP(ctx, wall.alloc(static_cast<size_t>(D) * m * sizeof(double)));
+    double *W = wall.as<double>();
+    for (int s0 = 0; s0 < m; s0 += 64) {
+      const int bw = std::min(64, m - s0);
+      dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + s0, m, 1.0);
+      if (st) return st;
+    }
+    B = W;
+    ldb = m;
+  }
+  DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, B, ldb, 0.0, out, ld, 1, sp, work.as<double>(), s));
+  DACP_HIP(ctx, dacp::launch_mirror_upper(out, m, ld, s));
+  return DACP_OK;
+}
+
 dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
                         int64_t ld) {
   const int64_t D = h->D;
@@ -923,31 +961,12 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
   if (verbose()) ts.start();
   // Few output tiles against a long K (the small subspaces of batched realisations): both products
   // as upper-triangle tiles with K split over workgroup layers, then mirrored as below.
-  {
-    const int64_t t = (m + 127) / 128, tu = t * (t + 1) / 2;
-    int64_t sp = 1;
-    if (ctx->project_splitk && tu < ctx->num_cus)
-      sp = std::min<int64_t>({64, (2 * ctx->num_cus + tu - 1) / tu, std::max<int64_t>(1, D / 1024)});
-    if (sp > 1) {
-      DevBuf work, wall;
-      DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * m * m * sizeof(double)));
-      DACP_HIP(ctx, wall.alloc(static_cast<size_t>(D) * m * sizeof(double)));
-      double *W = wall.as<double>();
-      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, static_cast<int>(sp),
-                                              work.as<double>(), s));
-      DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
-      for (int s0 = 0; s0 < m; s0 += 64) {
-        const int bw = std::min(64, m - s0);
-        dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + s0, m, 1.0);
-        if (st) return st;
-      }
-      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, W, m, 0.0, P, ld, 1, static_cast<int>(sp),
-                                              work.as<double>(), s));
-      DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
-      if (verbose()) vlog("projection: S and P with K split %d ways (m = %d) %.1f ms", static_cast<int>(sp), m, ts.stop_ms());
-      DACP_HIP(ctx, hipStreamSynchronize(s));
-      return DACP_OK;
-    }
+  if (project_small_splits(ctx, D, m) > 1) {
+    DACP_TRY(project_small(ctx, h, m, V, ldv, S, ld, 1));
+    DACP_TRY(project_small(ctx, h, m, V, ldv, P, ld, 2));
+    if (verbose()) vlog("projection: S and P with split K (m = %d) %.1f ms", m, ts.stop_ms());
+    DACP_HIP(ctx, hipStreamSynchronize(s));
+    return DACP_OK;
   }
   DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, s));
   DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
@@ -2093,7 +2112,14 @@ class EigRendezvous {
     int n;
     double *A, *w, *Z;
   };
-  explicit EigRendezvous(int workers) : active_(workers) {}
+  explicit EigRendezvous(int workers, int device) : active_(workers), device_(device) {
+    if (hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess) stream_ = nullptr;
+  }
+  ~EigRendezvous() {
+    if (stream_) (void)hipStreamDestroy(stream_);
+  }
+  // The matrices of reqs are complete at the current end of ctx's stream: the round's launch, on
+  // the rendezvous' own stream, waits for that point through an event.
   dacp_status solve_many(dacp_ctx ctx, const std::vector<Req> &reqs) {
     dacp_status big = DACP_OK;
     Arrival me;
@@ -2116,7 +2142,11 @@ class EigRendezvous {
       me.wraw.emplace_back(r.n);
       off += 2 * static_cast<size_t>(r.n) * r.n;
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);  // the matrices were written on this stream
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess && !stream_) e = hipErrorInvalidResourceHandle;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, ctx->stream);
+    if (e == hipSuccess) me.ready = ev;
     {
       std::unique_lock<std::mutex> lk(mu_);
       if (e != hipSuccess) me.reqs.clear();  // still arrive, so that the others are not held up
@@ -2125,7 +2155,8 @@ class EigRendezvous {
       if (static_cast<int>(arrived_.size()) == active_) run_locked(ctx);
       else cv_.wait(lk, [&] { return generation_ != gen; });
     }
-    if (e != hipSuccess) return hip_err(ctx, e, "batched eigensolver: scratch or stream");
+    if (ev) (void)hipEventDestroy(ev);  // the launch's wait on it is enqueued
+    if (e != hipSuccess) return hip_err(ctx, e, "batched eigensolver: scratch, stream or event");
     if (me.st != DACP_OK) return me.st;
     for (size_t i = 0; i < me.reqs.size(); ++i) {
       const Req &r = me.reqs[i];
@@ -2146,6 +2177,7 @@ class EigRendezvous {
     std::vector<Req> reqs;
     std::vector<double *> zr, q;
     std::vector<std::vector<double>> wraw;
+    hipEvent_t ready = nullptr;
     dacp_status st = DACP_OK;
   };
   void run_locked(dacp_ctx ctx) {
@@ -2159,9 +2191,22 @@ class EigRendezvous {
         q.push_back(a->q[i]);
         w.push_back(a->wraw[i].data());
       }
-    const dacp_status st = n.empty() ? DACP_OK
-                                     : dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(),
-                                                            zr.data(), q.data(), w.data());
+    dacp_status st = DACP_OK;
+    if (!n.empty()) {
+      // the launch goes on the rendezvous' own stream, after every arrival's event; the leader's
+      // context lends its error slot, its buffers come from the cache ordered on that stream
+      dacp::AllocStream scope(stream_, device_);
+      const hipStream_t own = ctx->stream;
+      ctx->stream = stream_;
+      for (const Arrival *a : arrived_)
+        if (a->ready && st == DACP_OK) {
+          const hipError_t e = hipStreamWaitEvent(stream_, a->ready, 0);
+          if (e != hipSuccess) st = hip_err(ctx, e, "batched eigensolver: wait");
+        }
+      if (st == DACP_OK)
+        st = dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(), zr.data(), q.data(), w.data());
+      ctx->stream = own;
+    }
     for (Arrival *a : arrived_) {
       a->st = st;
       if (st != DACP_OK && a->ctx != ctx) a->ctx->err = ctx->err;
@@ -2174,6 +2219,8 @@ class EigRendezvous {
   std::condition_variable cv_;
   std::vector<Arrival *> arrived_;
   int active_;
+  int device_;
+  hipStream_t stream_ = nullptr;
   long generation_ = 0;
 };
 
@@ -2326,7 +2373,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     c.blocked_min_n = ctx->blocked_min_n;
     DACP_HIP(ctx, hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   }
-  EigRendezvous rendezvous(nw);
+  EigRendezvous rendezvous(nw, ctx->device);
   // Each thread finishes its realisations r = w, w + nw, ...: with the batched eigensolver, stage by
   // stage (projection; eig(S) for all of them in the shared launch; U and H~; eig(H~) likewise;
   // Ritz vectors and acceptance), else one realisation after another.

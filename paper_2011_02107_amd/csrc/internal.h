@@ -303,7 +303,7 @@ struct dacp_ctx_s {
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
   int batch_eig = 1;           // batched realisations: dense eigen-decompositions in batched launches
   int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)
-  int project_splitk = 1;      // projection: full-square split-K products when the output has few tiles
+  int project_splitk = 1;      // projection: upper-triangle split-K products when the output has few tiles
   int rec_xcd = 2;             // fused recurrence: XCD-contiguous tile order, bit 0 low pass, bit 1 high pass
   int num_cus = 256;           // compute units of the device
   int batch_workers = 16;      // host threads (each with its own stream) finishing batched realisations
