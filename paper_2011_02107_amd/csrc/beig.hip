@@ -1,13 +1,15 @@
 // Batched dense symmetric eigensolver for many small subspace problems (App. C, one workgroup per
 // matrix).  The per-problem solver of eig.hip issues several kernels per column and is bound by
 // launches at n of a few hundred; here one launch covers every problem of a batch:
-//   1. Householder tridiagonalisation in place (one column per step, the step's vectors in LDS);
-//   2. implicit symmetric QR with a Wilkinson shift on (d, e), in batches of up to S sweeps:
-//      thread 0 chases the bulges of batch b+1 (the chase carries its running values in
-//      registers) while waves 1.. apply the Givens rotations of batch b to the rows of Zr (rows =
-//      eigenvectors of the tridiagonal, starting from I), one column per thread, all S sweeps in
-//      one pass down the column;
-//   3. Q = H_0 H_1 ... H_(n-3) formed explicitly, one thread per column, by the applying waves
+//   1. Householder tridiagonalisation in place (one column per step, the step's vectors in LDS;
+//      each step's rank-2 update is applied in the next step's pass over the trailing block);
+//   2. every eigenvalue of the tridiagonal by bisection, one per thread, for the QR shifts;
+//   3. implicit symmetric QR on (d, e), shifted by the nearest eigenvalue not yet deflated (else
+//      Wilkinson's shift), in batches of up to S sweeps: thread 0 chases the bulges of batch b+1
+//      (the chase carries its running values in registers) while waves 1.. apply the Givens
+//      rotations of batch b to the rows of Zr (rows = eigenvectors of the tridiagonal, starting
+//      from I), one column per thread, all S sweeps in one pass down the column;
+//   4. Q = H_0 H_1 ... H_(n-3) formed explicitly, one thread per column, by the applying waves
 //      while thread 0 chases (the columns of Q need no barrier between Householder steps).
 // The host then sorts the eigenvalues and forms the eigenvectors of A as rows of Zr Q^T.
 #include <hip/hip_runtime.h>
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
   for (int64_t idx = tid; idx < static_cast<int64_t>(n) * n; idx += kBT)
     pb.Zr[idx] = (idx / n == idx % n) ? 1.0 : 0.0;
   __syncthreads();
-  // ---- eigenvalues of the tridiagonal by bisection, one per thread (the QR shifts): lam in v,
+  // ---- 2. eigenvalues of the tridiagonal by bisection, one per thread (the QR shifts): lam in v,
   // deflation marks in w
   double tnorm = 0.0;  // Gershgorin bound on the norm of the tridiagonal
   {
@@ -442,8 +444,8 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     tnorm = fmax(fabs(glo), fabs(ghi));
   }
   __syncthreads();
-  // ---- 2. implicit symmetric QR, batch b+1 chased while batch b is applied; the applying
-  // threads fill the time the chase takes with the Householder steps that form Q (3.), which
+  // ---- 3. implicit symmetric QR, batch b+1 chased while batch b is applied; the applying
+  // threads fill the time the chase takes with the Householder steps that form Q (4.), which
   // depend on phase 1 only, polling the count of finished chases between steps
   const int hdr = 1 + 2 * S;
   volatile int *chased = meta + 2 * hdr;
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
   }
   if (tid == 0) *pb.status = qs.failed ? 1 : 0;
   for (int i = tid; i < n; i += kBT) pb.w[i] = d[i];
-  // ---- 3. the Householder steps not yet taken
+  // ---- 4. the Householder steps not yet taken
   if (wave != 0)
     while (hk >= 0) house_cols(pb.Q, A, betas, n, hk--, a);
 }
