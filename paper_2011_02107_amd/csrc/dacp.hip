@@ -2237,7 +2237,18 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     if (N < 1 || N > hams[r]->D) return set_err(ctx, DACP_E_INVALID, "batched: need 1 <= N <= 2^L for every realisation");
     max_L = std::max(max_L, hams[r]->L);
   }
-  // every device buffer of the call, here and in the worker threads, stream-ordered from the pool
+  // the context's device for this thread during the call (the worker threads select it too)
+  struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int d) {
+      if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+      if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceScope() {
+      if (prev >= 0) (void)hipSetDevice(prev);
+    }
+  } device_scope(ctx->device);
+  // every device buffer of the call, here and in the worker threads, from the block cache
   dacp::AllocStream pooled(ctx->stream, ctx->device);
   dacp_opts o;
   if (opts_in) o = *opts_in;
