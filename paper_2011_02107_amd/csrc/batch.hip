@@ -61,16 +61,19 @@ __device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, 
   }
   __syncthreads();
   if (E == 1 && threadIdx.x >= D) return;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const uint32_t o = tid_off(sizeof(T)) + static_cast<uint32_t>(i * kBT * sizeof(T));
-    v[i] *= ld_at(diag, o);
-  }
   // elements in chunks of at most 4, each chunk running the whole flip list (sign-free flips
-  // first): bounds the loads in flight, and the registers holding them, independently of E
+  // first): bounds the loads in flight, and the registers holding them, independently of E.  A
+  // chunk's diagonal entries are loaded first and applied last (to the element's own value, read
+  // back from lds), so their global-load latency runs under the chunk's flips.
   constexpr int C = E < 4 ? E : 4;
 #pragma unroll
   for (int ib = 0; ib < E; ib += C) {
+    T dg[C];
+#pragma unroll
+    for (int i = ib; i < ib + C; ++i) {
+      dg[i - ib] = ld_at(diag, tid_off(sizeof(T)) + static_cast<uint32_t>(i * kBT * sizeof(T)));
+      v[i] = static_cast<T>(0);
+    }
 #pragma nounroll
     for (int t = 0; t < nplain; ++t) {
       const uint32_t xm = flips[t].xmask;
@@ -89,6 +92,8 @@ __device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, 
         v[i] += ((__popc(src & zm) & 1) ? -c : c) * lds[src];
       }
     }
+#pragma unroll
+    for (int i = ib; i < ib + C; ++i) v[i] += dg[i - ib] * lds[threadIdx.x + i * kBT];
   }
 }
 
