@@ -968,7 +968,20 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
     DACP_HIP(ctx, hipStreamSynchronize(s));
     return DACP_OK;
   }
-  DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, V, ldv, 0.0, S, ld, 1, s));
+  // The large form: upper-triangle tiles, K split in two when the scratch fits (twice the work
+  // units: the last round of 8 x 8 tile blocks over the 8 XCDs is then half as long).
+  DevBuf split_work;
+  const int big_splits = (ctx->project_splitk && D >= (int64_t(1) << 18) &&
+                          split_work.alloc(2 * static_cast<size_t>(m) * m * sizeof(double)) == hipSuccess)
+                             ? 2
+                             : 1;
+  (void)hipGetLastError();
+  auto gram_upper = [&](const double *B, int64_t ldb, double *C) -> hipError_t {
+    return big_splits > 1 ? dacp::launch_dgemm_splitk(1, 0, m, m, D, 1.0, V, ldv, B, ldb, 0.0, C, ld, 1, big_splits,
+                                                      split_work.as<double>(), s)
+                          : dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, B, ldb, 0.0, C, ld, 1, s);
+  };
+  DACP_HIP(ctx, gram_upper(V, ldv, S));
   DACP_HIP(ctx, dacp::launch_mirror_upper(S, m, ld, s));
   if (verbose()) {
     const double ms = ts.stop_ms();
@@ -990,7 +1003,7 @@ dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_
         dacp_status st = step<double>(ctx, h, bw, V + s0, ldv, W + s0, m, 1.0);
         if (st) return st;
       }
-      DACP_HIP(ctx, dacp::launch_dgemm(1, 0, m, m, D, 1.0, V, ldv, W, m, 0.0, P, ld, 1, s));
+      DACP_HIP(ctx, gram_upper(W, m, P));
       DACP_HIP(ctx, dacp::launch_mirror_upper(P, m, ld, s));
       if (verbose()) vlog("projection: P = V^T (H V) in one GEMM %.1f ms", ts.stop_ms());
       DACP_HIP(ctx, hipStreamSynchronize(s));
