@@ -48,11 +48,34 @@ __device__ __forceinline__ void st_at(T *base, uint32_t byte_off, T x) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = x;
 }
 
-// v <- H v for this thread's elements s = tid + i * kBT (i < E); lds holds the whole column
-// while the flips are summed.  E = 1 also covers D < kBT (threads with s >= D idle).
+// The flip terms of H for the elements ib .. ib + C - 1 of this thread, added to v from lds (which
+// holds the vector being applied): the sign-free flips first, then the others.
+template <typename T, int E, int C>
+__device__ __forceinline__ void chunk_flips(T (&v)[E], const T *lds, ConstFlipTable flips, int nplain, int nflip,
+                                            int ib) {
+#pragma nounroll
+  for (int t = 0; t < nplain; ++t) {
+    const uint32_t xm = flips[t].xmask;
+    const T c = static_cast<T>(flips[t].coef);
+#pragma unroll
+    for (int i = ib; i < ib + C; ++i) v[i] += c * lds[(threadIdx.x + i * kBT) ^ xm];
+  }
+#pragma nounroll
+  for (int t = nplain; t < nflip; ++t) {
+    const uint32_t xm = flips[t].xmask;
+    const uint32_t zm = flips[t].zmask;
+    const T c = static_cast<T>(flips[t].coef);
+#pragma unroll
+    for (int i = ib; i < ib + C; ++i) {
+      const uint32_t src = (threadIdx.x + i * kBT) ^ xm;
+      v[i] += ((__popc(src & zm) & 1) ? -c : c) * lds[src];
+    }
+  }
+}
+
+// Stores this thread's elements s = tid + i * kBT (i < E) of v into lds between barriers.
 template <typename T, int E>
-__device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, ConstFlipTable flips, int nplain,
-                                              int nflip, uint32_t D) {
+__device__ __forceinline__ void stage_column(const T (&v)[E], T *lds, uint32_t D) {
   __syncthreads();  // the previous apply's readers are done with lds
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -60,11 +83,19 @@ __device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, 
     if (E > 1 || s < D) lds[s] = v[i];
   }
   __syncthreads();
+}
+
+// v <- H v for this thread's elements s = tid + i * kBT (i < E); lds holds the whole column
+// while the flips are summed.  E = 1 also covers D < kBT (threads with s >= D idle).  Elements go
+// in chunks of at most 4, each chunk running the whole flip list: bounds the loads in flight, and
+// the registers holding them, independently of E.  A chunk's diagonal entries are loaded first and
+// applied last (to the element's own value, read back from lds), so their global-load latency runs
+// under the chunk's flips.
+template <typename T, int E>
+__device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, ConstFlipTable flips, int nplain,
+                                              int nflip, uint32_t D) {
+  stage_column<T, E>(v, lds, D);
   if (E == 1 && threadIdx.x >= D) return;
-  // elements in chunks of at most 4, each chunk running the whole flip list (sign-free flips
-  // first): bounds the loads in flight, and the registers holding them, independently of E.  A
-  // chunk's diagonal entries are loaded first and applied last (to the element's own value, read
-  // back from lds), so their global-load latency runs under the chunk's flips.
   constexpr int C = E < 4 ? E : 4;
 #pragma unroll
   for (int ib = 0; ib < E; ib += C) {
@@ -74,24 +105,7 @@ __device__ __forceinline__ void apply_inplace(T (&v)[E], T *lds, const T *diag, 
       dg[i - ib] = ld_at(diag, tid_off(sizeof(T)) + static_cast<uint32_t>(i * kBT * sizeof(T)));
       v[i] = static_cast<T>(0);
     }
-#pragma nounroll
-    for (int t = 0; t < nplain; ++t) {
-      const uint32_t xm = flips[t].xmask;
-      const T c = static_cast<T>(flips[t].coef);
-#pragma unroll
-      for (int i = ib; i < ib + C; ++i) v[i] += c * lds[(threadIdx.x + i * kBT) ^ xm];
-    }
-#pragma nounroll
-    for (int t = nplain; t < nflip; ++t) {
-      const uint32_t xm = flips[t].xmask;
-      const uint32_t zm = flips[t].zmask;
-      const T c = static_cast<T>(flips[t].coef);
-#pragma unroll
-      for (int i = ib; i < ib + C; ++i) {
-        const uint32_t src = (threadIdx.x + i * kBT) ^ xm;
-        v[i] += ((__popc(src & zm) & 1) ? -c : c) * lds[src];
-      }
-    }
+    chunk_flips<T, E, C>(v, lds, flips, nplain, nflip, ib);
 #pragma unroll
     for (int i = ib; i < ib + C; ++i) v[i] += dg[i - ib] * lds[threadIdx.x + i * kBT];
   }
@@ -157,6 +171,38 @@ struct Held {
     else st_at(g, boff, x);
   }
 };
+
+// One evolution step T_(k+1) = (2 / e) H T_k - T_(k-1) (Sec. II.B): v holds T_k on entry and
+// T_(k+1) on exit, A holds T_(k-1) on entry and T_k on exit.  The apply of apply_inplace with the
+// combination done per chunk, so that the chunk's T_(k-1) loads (global when A lives in the column
+// scratch) run under its flips together with the diagonal loads.
+template <int E>
+__device__ __forceinline__ void evolve_step(double (&v)[E], double *lds, const double *diag, ConstFlipTable flips,
+                                            int nplain, int nflip, uint32_t D, Held<E> &A, double two_inv_e) {
+  stage_column<double, E>(v, lds, D);
+  if (E == 1 && threadIdx.x >= D) return;
+  constexpr int C = E < 4 ? E : 4;
+#pragma unroll
+  for (int ib = 0; ib < E; ib += C) {
+    double dg[C], pa[C];
+#pragma unroll
+    for (int i = ib; i < ib + C; ++i) {
+      const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
+      dg[i - ib] = ld_at(diag, bo);
+      pa[i - ib] = A.get(i, bo);
+      v[i] = 0.0;
+    }
+    chunk_flips<double, E, C>(v, lds, flips, nplain, nflip, ib);
+#pragma unroll
+    for (int i = ib; i < ib + C; ++i) {
+      const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
+      const double x = lds[threadIdx.x + i * kBT];
+      const double hv = v[i] + dg[i - ib] * x;
+      A.set(i, bo, x);
+      v[i] = two_inv_e * hv - pa[i - ib];
+    }
+  }
+}
 
 template <int E>
 __device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable flips, ConstInts ks, unsigned char *smem,
@@ -269,16 +315,7 @@ __device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable fli
   const int64_t kmax = c.n_samples > 0 ? ks[c.n_samples - 1] : 1;
   const double two_inv_e = 2.0 * c.inv_e;
   for (int64_t k = 1; k < kmax; ++k) {
-    apply_inplace<double, E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D);  // lds keeps T_k
-    if (active) {
-#pragma unroll
-      for (int i = 0; i < E; ++i) {
-        const uint32_t bo = tid_off(8u) + static_cast<uint32_t>(i * kBT * 8);
-        const double nb = two_inv_e * v[i] - A.get(i, bo);
-        A.set(i, bo, ld_at(lds64, bo));
-        v[i] = nb;
-      }
-    }
+    evolve_step<E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D, A, two_inv_e);
     sample_at<E>(c, ks, next, k + 1, v, D, red);
   }
 }
