@@ -62,8 +62,17 @@ __global__ __launch_bounds__(256) void k_symv(const double *A, int64_t ld, int n
   const int lane = threadIdx.x & 63;
   if (row >= m || beta == 0.0) return;
   const double *a = A + static_cast<int64_t>(k + 1 + row) * ld + k + 1;
-  double s = 0.0;
-  for (int j = lane; j < m; j += 64) s += a[j] * v[j];
+  // four independent 64-wide strips in flight per wave
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = lane;
+  for (; j + 192 < m; j += 256) {
+    s0 += a[j] * v[j];
+    s1 += a[j + 64] * v[j + 64];
+    s2 += a[j + 128] * v[j + 128];
+    s3 += a[j + 192] * v[j + 192];
+  }
+  for (; j < m; j += 64) s0 += a[j] * v[j];
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) p[row] = beta * s;
