@@ -233,7 +233,8 @@ dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, dou
 
 /* The same decomposition for `count` matrices in one launch, one workgroup per matrix (App. C's
  * two eigen-decompositions for many small subspace problems, the batched-realisation path):
- * Householder tridiagonalisation, implicit symmetric QR with a Wilkinson shift, Householder Q.
+ * Householder tridiagonalisation, the tridiagonal's eigenvalues by bisection, implicit symmetric
+ * QR shifted by the nearest of those not yet deflated (else Wilkinson's shift), Householder Q.
  * n[i] (host): 1 <= n[i] <= 2048.  A[i] (host array of device pointers): symmetric n[i] x n[i],
  * row-major, ld n[i], destroyed.  w[i] (host array of host pointers): n[i] eigenvalues ascending.
  * Z[i] (host array of device pointers, entries may be NULL): n[i] x n[i], row j = eigenvector j.
