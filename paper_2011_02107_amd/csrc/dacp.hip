@@ -2193,7 +2193,23 @@ class EigRendezvous {
     hipEvent_t ready = nullptr;
     dacp_status st = DACP_OK;
   };
+  // Runs the round (the lock held) and always ends it, so that no waiting thread is left behind.
   void run_locked(dacp_ctx ctx) {
+    dacp_status st = DACP_OK;
+    try {
+      st = launch_round(ctx);
+    } catch (...) {
+      st = set_err(ctx, DACP_E_NOMEM, "batched eigensolver: host allocation failed");
+    }
+    for (Arrival *a : arrived_) {
+      a->st = st;
+      if (st != DACP_OK && a->ctx != ctx) a->ctx->err = ctx->err;
+    }
+    arrived_.clear();
+    ++generation_;
+    cv_.notify_all();
+  }
+  dacp_status launch_round(dacp_ctx ctx) {
     std::vector<int> n;
     std::vector<double *> A, zr, q, w;
     for (Arrival *a : arrived_)
@@ -2216,17 +2232,18 @@ class EigRendezvous {
           const hipError_t e = hipStreamWaitEvent(stream_, a->ready, 0);
           if (e != hipSuccess) st = hip_err(ctx, e, "batched eigensolver: wait");
         }
-      if (st == DACP_OK)
-        st = dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(), zr.data(), q.data(), w.data());
+      if (st == DACP_OK) {
+        try {
+          st = dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(), zr.data(), q.data(),
+                                    w.data());
+        } catch (...) {
+          ctx->stream = own;
+          throw;
+        }
+      }
       ctx->stream = own;
     }
-    for (Arrival *a : arrived_) {
-      a->st = st;
-      if (st != DACP_OK && a->ctx != ctx) a->ctx->err = ctx->err;
-    }
-    arrived_.clear();
-    ++generation_;
-    cv_.notify_all();
+    return st;
   }
   std::mutex mu_;
   std::condition_variable cv_;
@@ -2398,6 +2415,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     DACP_HIP(ctx, hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   }
   EigRendezvous rendezvous(nw, ctx->device);
+  std::vector<char> has_left(nw, 0);  // the worker has left the rendezvous
   // Each thread finishes its realisations r = w, w + nw, ...: with the batched eigensolver, stage by
   // stage (projection; eig(S) for all of them in the shared launch; U and H~; eig(H~) likewise;
   // Ritz vectors and acceptance), else one realisation after another.
@@ -2416,6 +2434,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
         vb[r].release();
       }
       rendezvous.leave(wc);
+      has_left[w] = 1;
       return;
     }
     struct Fin {
@@ -2502,6 +2521,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
           if (alive(r)) fail(r, st);
     }
     rendezvous.leave(wc);
+    has_left[w] = 1;
     // B, Ritz vectors and acceptance
     for (size_t i = 0; i < mine.size(); ++i) {
       const int r = mine[i];
@@ -2525,9 +2545,22 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
       vb[r].release();
     }
   };
+  // A host exception in a worker (an allocation) fails its realisations; the thread still leaves
+  // the rendezvous so that the others are not held up.
+  auto guarded = [&](int w) {
+    try {
+      worker(w);
+    } catch (...) {
+      for (int r = w; r < count; r += nw) {
+        wst[r] = DACP_E_NOMEM;
+        werr[r] = "batched finish: host allocation failed";
+      }
+      if (!has_left[w]) rendezvous.leave(&wctx[w]);
+    }
+  };
   std::vector<std::thread> threads;
-  for (int w = 1; w < nw; ++w) threads.emplace_back(worker, w);
-  worker(0);
+  for (int w = 1; w < nw; ++w) threads.emplace_back(guarded, w);
+  guarded(0);
   for (auto &t : threads) t.join();
   for (int w = 0; w < nw; ++w) {
     if (wctx[w].red) (void)hipFree(wctx[w].red);
