@@ -94,6 +94,8 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "rec_hi_w"    fused recurrence: adjacent rows per high-bit tile (0 = automatic: enough
  *                 for 128-byte runs; else 1, 2, 4 or 8)
  *   "rec_threads" fused recurrence: threads per workgroup, 512 or 1024 (default 1024)
+ *   "rec_graph"   evolution below 2^19 rows: runs of this many steps without a sample replay one
+ *                 captured hipGraph (even, up to 256; default 0 = launch every step)
  *   "rec_persist" fused recurrence: 0 = one workgroup per tile (default); n = 1..8 persistent
  *                 workgroups per compute unit that prefetch their next tile
  *   "project_whole" projection: 1 = P = V^T (H V) as one GEMM when the block H V (D x m FP64)

@@ -759,6 +759,40 @@ struct EvolStats {
   int group = 0;
 };
 
+// A captured run of launches, replayed with one hipGraphLaunch.  capture(n, launch) records
+// launch(j, stream) for j = 0 .. n-1 on a private stream; any failure leaves no graph (failed set)
+// and the caller launches one by one.  Only kernel launches are recorded.
+struct GraphRun {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool failed = false;
+  template <typename F>
+  void capture(int n, F launch) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      failed = true;
+      return;
+    }
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    for (int j = 0; ok && j < n; ++j) ok = launch(j, cs) == hipSuccess;
+    hipGraph_t g = nullptr;
+    const bool ended = hipStreamEndCapture(cs, &g) == hipSuccess;
+    if (ok && ended && g && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess) {
+      graph = g;
+    } else {
+      if (g) (void)hipGraphDestroy(g);
+      exec = nullptr;
+      failed = true;
+      (void)hipGetLastError();
+    }
+    (void)hipStreamDestroy(cs);
+  }
+  ~GraphRun() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *V,
                       int64_t ldv, int *m_out, EvolStats *stats) {
   const int64_t D = h->D;
@@ -793,6 +827,11 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
     auto store_of = [&](int64_t k) -> double * {
       auto it = panel_of.find(k);
       return it == panel_of.end() ? nullptr : V + static_cast<int64_t>(it->second) * b + g0;
+    };
+    // whether a sample falls on T_k1 .. T_k2
+    auto panel_in = [&](int64_t k1, int64_t k2) {
+      auto it = panel_of.lower_bound(k1);
+      return it != panel_of.end() && it->first <= k2;
     };
     dacp_status st =
         step<double>(ctx, h, gw, A, gw, B, gw, inv_e, nullptr, 0, 0.0, nullptr, 0, 0.0, store_of(1), ldv, 2);
@@ -841,27 +880,51 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
       ra.threads = ctx->rec_threads;
       ra.grid = ctx->rec_persist * ctx->num_cus;
       ra.p = Pp;
-      for (int64_t k = 1; k < kmax; ++k) {
-        // produce T_{k+1} from T_k (B) and the partial; T_{k+1} overwrites T_{k-1} (A)
-        ra.tcur = B;
-        ra.tnew = A;
-        ra.st = store_of(k + 1);
-        const bool hi_turn = (k % 2) == 1;
-        if (hi_turn) {
+      // one step: T_{k+1} from T_k (tcur) and the partial; T_{k+1} overwrites T_{k-1} (tnew)
+      auto launch_step = [&](int64_t k, double *tcur, double *tnew, double *stv, hipStream_t s) -> hipError_t {
+        ra.tcur = tcur;
+        ra.tnew = tnew;
+        ra.st = stv;
+        if ((k % 2) == 1) {
           ra.flips = so.hi;
           ra.nflip = so.nhi;
           ra.nplain = so.nhi_plain;
           ra.ntiles = (1 << lo_bits) / hw;
           ra.xcd_remap = ((ctx->rec_xcd & 2) && ra.ntiles % 8 == 0) ? 1 : 0;
-          DACP_HIP(ctx, dacp::launch_rec_hi<double>(ra, ctx->stream));
-        } else {
-          ra.flips = so.lo;
-          ra.nflip = so.nlo;
-          ra.nplain = so.nlo_plain;
-          ra.ntiles = static_cast<int>(D >> lo_bits);
-          ra.xcd_remap = ((ctx->rec_xcd & 1) && ra.ntiles % 8 == 0) ? 1 : 0;
-          DACP_HIP(ctx, dacp::launch_rec_lo<double>(ra, ctx->stream));
+          return dacp::launch_rec_hi<double>(ra, s);
         }
+        ra.flips = so.lo;
+        ra.nflip = so.nlo;
+        ra.nplain = so.nlo_plain;
+        ra.ntiles = static_cast<int>(D >> lo_bits);
+        ra.xcd_remap = ((ctx->rec_xcd & 1) && ra.ntiles % 8 == 0) ? 1 : 0;
+        return dacp::launch_rec_lo<double>(ra, s);
+      };
+      // Below 2^19 rows a launch is a few microseconds and its issue cost shows, so runs of
+      // rec_graph steps without a sample (a high/low period starting on a high step, the buffers
+      // then in their starting roles) replay one captured graph.
+      GraphRun graph;
+      const int gsteps = (D < (int64_t(1) << 19) && kmax > 4 * ctx->rec_graph) ? ctx->rec_graph : 0;
+      for (int64_t k = 1; k < kmax;) {
+        if (gsteps > 0 && (k % 2) == 1 && k + gsteps <= kmax && !panel_in(k + 1, k + gsteps) &&
+            A == ba.as<double>()) {
+          if (!graph.exec && !graph.failed) {
+            DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the first steps set the kernels' attributes
+            graph.capture(gsteps, [&](int64_t j, hipStream_t cs) {
+              double *tc = (j % 2 == 0) ? bb.as<double>() : ba.as<double>();
+              double *tn = (j % 2 == 0) ? ba.as<double>() : bb.as<double>();
+              return launch_step(k + j, tc, tn, nullptr, cs);
+            });
+          }
+          if (graph.exec) {
+            DACP_HIP(ctx, hipGraphLaunch(graph.exec, ctx->stream));
+            launches += gsteps;
+            k += gsteps;  // an even count: A and B are back in their roles
+            continue;
+          }
+        }
+        DACP_HIP(ctx, launch_step(k, B, A, store_of(k + 1), ctx->stream));
+        ++k;
         ++launches;
         std::swap(A, B);
         if (verbose() && k % report_every == 0) {
@@ -870,6 +933,7 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
                static_cast<long long>(k), static_cast<long long>(kmax));
         }
       }
+      if (graph.exec) DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // before the graph is released
       continue;
     }
     for (int64_t k = 1; k < kmax; ++k) {
@@ -1394,6 +1458,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->rec_persist = value;
     return DACP_OK;
   }
+  if (k == "rec_graph") {
+    if (value < 0 || value > 256 || (value & 1)) return set_err(ctx, DACP_E_INVALID, "rec_graph: even, 0..256");
+    ctx->rec_graph = value;
+    return DACP_OK;
+  }
   if (k == "rec_tile") {
     if (!pow2 || value < 1024 || value > 8192) return set_err(ctx, DACP_E_INVALID, "rec_tile: power of two in [1024, 8192]");
     ctx->rec_tile_elems = value;
@@ -1422,6 +1491,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "rec_threads") *value = ctx->rec_threads;
   else if (k == "rec_tile") *value = ctx->rec_tile_elems;
   else if (k == "rec_persist") *value = ctx->rec_persist;
+  else if (k == "rec_graph") *value = ctx->rec_graph;
   else if (k == "rec_xcd") *value = ctx->rec_xcd;
   else if (k == "project_whole") *value = ctx->project_whole;
   else if (k == "project_splitk") *value = ctx->project_splitk;
@@ -2726,10 +2796,13 @@ dacp_status dacp_autotune(dacp_ctx ctx, dacp_ham h, int b, int steps, int *best_
     int group, threads, tile, hi_w;
   };
   std::vector<Cand> cands;
+  // smaller tiles only where the launch would otherwise leave compute units idle (below 2^19 rows)
   for (int g = 1; g <= std::min(b, 16); g *= 2)
     for (int th : {512, 1024})
-      for (int tile : {4096, 8192})
+      for (int tile : {1024, 2048, 4096, 8192}) {
+        if (tile < 4096 && D >= (int64_t(1) << 19)) continue;
         for (int w : {0, 1, 2}) cands.push_back({g, th, tile, w});
+      }
   const int saved_threads = ctx->rec_threads, saved_tile = ctx->rec_tile_elems, saved_w = ctx->rec_hi_w;
   // unit start columns; E_b = sum |c| >= ||H||; a_r = pi / steps puts the first sample pair at k = steps
   DevBuf psi, V;

@@ -301,6 +301,7 @@ struct dacp_ctx_s {
   int rec_threads = 1024;      // fused recurrence: threads per workgroup (512 or 1024)
   int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
+  int rec_graph = 0;           // evolution: steps per captured graph below 2^19 rows (0 = no graphs)
   int batch_eig = 1;           // batched realisations: dense eigen-decompositions in batched launches
   int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)
   int project_splitk = 1;      // projection: upper-triangle split-K products when the output has few tiles

@@ -389,6 +389,30 @@ def test_basis_fused_layouts_match_oracle(ctx, g, threads, hi_w, rec_tile, persi
     assert np.abs(host(V) - ref).max() < 1e-15 * max(ks) + 1e-12
 
 
+def test_basis_graph_replay_matches_step_launches(ctx):
+    """Below 2^19 rows, runs of sample-free evolution steps replay a captured hipGraph (rec_graph
+    steps each): the basis equals, bit for bit, the one launched step by step, and the oracle."""
+    L, b, n = 16, 8, 2
+    terms = _signed_flip_terms(L, 5)
+    eb = 1.05 * hamiltonian.sum_abs_coeff(terms)
+    a = 0.02 * eb
+    psi = np.random.default_rng(13).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0)
+    ref, ks = chebyshev.chebyshev_basis(lambda X: hamiltonian.apply_h(L, terms, X), psi, eb, a, n)
+    assert max(ks) > 4 * 32  # long enough for graph runs between the samples
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    V0 = torch.zeros((1 << L, b * (2 * n + 1)), dtype=torch.float64, device=DEV)
+    V1 = torch.zeros_like(V0)
+    B.dacp_basis(ctx, ham, to_dev(psi), V0, eb, a, n, group=8)
+    try:
+        ctx.tune("rec_graph", 32)
+        B.dacp_basis(ctx, ham, to_dev(psi), V1, eb, a, n, group=8)
+    finally:
+        ctx.tune("rec_graph", 0)
+    assert torch.equal(V0, V1)
+    assert np.abs(host(V1) - ref).max() < 1e-15 * max(ks) + 1e-12
+
+
 def test_basis_detects_bound_below_norm(ctx):
     L = 8
     terms = inputs.ising_chain(L)
