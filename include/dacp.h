@@ -299,6 +299,18 @@ void dacp_default_opts(dacp_opts *opts);
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report);
 
+/* dacp_central_eigs that also returns the eigenvectors: the Ritz vectors phi = A b of the N
+ * returned values (Sec. II.C: the basis A times the subspace solution), each scaled to unit norm.
+ *   vecs_out  device, D x N block, row stride ldvec >= N: vecs_out[s * ldvec + i] is component s
+ *             of the vector of eigs_out[i].  Written only when the call returns DACP_OK.
+ * Forming them is one extra FP64 GEMM of D x N x m after the acceptance.  A vector's angle to the
+ * exact eigenvector is at most err_i' / gap, with err_i' its residual norm and gap the distance of
+ * its value to the rest of the spectrum, so vectors of near-degenerate levels are only
+ * determined as a subspace.  Returns DACP_E_INVALID for a null vecs_out or ldvec < N. */
+dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
+                                  double *err_out, double *vecs_out, int64_t ldvec, int *n_out,
+                                  dacp_report *report);
+
 /* dacp_central_eigs for `count` independent realisations (disorder samples, possibly of
  * different L, every L <= 14) with the same N and options.  Bounds, densities and windows are
  * set per realisation; then ONE persistent launch runs the filter and the evolution of every
@@ -323,7 +335,8 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
 
 /* Autotuner of the evolution recurrence for this Hamiltonian and block width b: times `steps`
  * evolution steps of one column group for every group width (powers of two up to min(b, 16)),
- * workgroup size (512, 1024), fused tile (4096, 8192 elements) and high-tile row count
+ * workgroup size (512, 1024), fused tile (4096, 8192 elements; also 1024 and 2048 below 2^19
+ * rows) and high-tile row count
  * (automatic, 1, 2), at the real state length, and keeps the fastest in ctx (the "group",
  * "rec_threads", "rec_tile", "rec_hi_w" knobs).  best_group and best_us_per_column_step (host,
  * may be NULL) get the winner's group width and its time per column and step. */

@@ -146,6 +146,10 @@ SIGNATURES = {
     ),
     "dacp_default_opts": (None, [ctypes.POINTER(Opts)]),
     "dacp_central_eigs": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)]),
+    "dacp_central_eigpairs": (
+        ctypes.c_int,
+        [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _vp, _i64, _ip, ctypes.POINTER(Report)],
+    ),
     "dacp_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _ip, _dp]),
     "dacp_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "dacp_mlp_free": (None, [_vp]),
@@ -383,6 +387,25 @@ def dacp_central_eigs(ctx, ham, N, opts=None, raise_on_window=True):
     n_out = ctypes.c_int()
     rep = Report()
     st = ctx.lib.dacp_central_eigs(ctx.handle, ham.handle, int(N), ctypes.byref(opts), _f64(eigs), _f64(errs), ctypes.byref(n_out), ctypes.byref(rep))
+    if st != 0 and (raise_on_window or st != -5):
+        ctx.check(st)
+    n = n_out.value if st == 0 else 0
+    return eigs[:n], errs[:n], rep.as_dict(), st
+
+
+def dacp_central_eigpairs(ctx, ham, N, vecs, opts=None, raise_on_window=True):
+    """dacp_central_eigs that also writes the unit eigenvectors into the device tensor vecs
+    (2^L x ldvec FP64, ldvec >= N; column i belongs to eigs[i]).  Returns as dacp_central_eigs."""
+    if opts is None:
+        opts = default_opts()
+    if vecs.dim() != 2 or vecs.shape[0] != 1 << ham.L or vecs.shape[1] < N or str(vecs.dtype) != "torch.float64":
+        raise ValueError("vecs must be a float64 2^L x ldvec tensor with ldvec >= N")
+    eigs = np.zeros(N)
+    errs = np.zeros(N)
+    n_out = ctypes.c_int()
+    rep = Report()
+    st = ctx.lib.dacp_central_eigpairs(ctx.handle, ham.handle, int(N), ctypes.byref(opts), _f64(eigs), _f64(errs),
+                                       _ptr(vecs), int(vecs.shape[1]), ctypes.byref(n_out), ctypes.byref(rep))
     if st != 0 and (raise_on_window or st != -5):
         ctx.check(st)
     n = n_out.value if st == 0 else 0

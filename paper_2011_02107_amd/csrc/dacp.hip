@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <functional>
+#include <tuple>
 #include <map>
 #include <mutex>
 #include <set>
@@ -1769,9 +1770,12 @@ Plan make_plan(const dacp_opts &o, int64_t D, int N, double e_b, const std::vect
 // Acceptance (Sec. II.C residual check) of one realisation: Ritz vectors V B for the candidates by
 // |theta|, their residuals, the quadratic residual bound and the contiguous core.  theta ascending
 // (r values), bc the rows of B^T (r x m).
+// vecs_out (device, may be null): row s of the D x N block at vecs_out + s * ldvec gets component
+// s of the unit Ritz vector of each returned value, in the order of eigs_out.
 dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, double tol, double norm_est,
                          const double *V, int m, int r, const std::vector<double> &theta, const DevBuf &bc,
-                         dacp_report &rep, double *eigs_out, double *err_out, int &accepted) {
+                         dacp_report &rep, double *eigs_out, double *err_out, int &accepted,
+                         double *vecs_out = nullptr, int64_t ldvec = 0) {
   const int64_t D = h->D;
   hipStream_t s = ctx->stream;
   dacp_status st;
@@ -1783,7 +1787,7 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
     return ai < aj || (ai == aj && theta[i] < theta[j]);
   });
   const int n_sel = std::min(r, N + std::max(64, N / 8));
-  std::vector<double> rnorm(n_sel, INFINITY);
+  std::vector<double> rnorm(n_sel, INFINITY), phin2(n_sel, 1.0);
   {
     const int cw = std::min(n_sel, 512);
     DevBuf bsel, phi, hphi, dth, dperm;
@@ -1814,7 +1818,10 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
                                        dacp::coldots_blocks(D, 2 * w), ctx->red_out, s));
       DACP_TRY(to_host(ctx, out.data(), ctx->red_out, sizeof(double) * 2 * w));
       DACP_HIP(ctx, hipStreamSynchronize(s));
-      for (int i = 0; i < w; ++i) rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
+      for (int i = 0; i < w; ++i) {
+        rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
+        phin2[c0 + i] = out[2 * i + 1];
+      }
     }
   }
   // Acceptance.  The Ritz residual r_j is orthogonal to the whole search space, which holds the
@@ -1894,12 +1901,38 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
   vlog("acceptance done: %.1f ms, %d accepted of %d candidates", rep.t_accept_ms, core, n_sel);
   accepted = core;
   if (core >= N) {
-    std::vector<std::pair<double, double>> sel;
-    for (int i = 0; i < N; ++i) sel.push_back({theta[order[core_idx[i]]], est[core_idx[i]]});
+    std::vector<std::tuple<double, double, int>> sel;  // (theta, estimate, position in order)
+    for (int i = 0; i < N; ++i) sel.push_back({theta[order[core_idx[i]]], est[core_idx[i]], core_idx[i]});
     std::sort(sel.begin(), sel.end());
     for (int i = 0; i < N; ++i) {
-      eigs_out[i] = sel[i].first;
-      if (err_out) err_out[i] = sel[i].second;
+      eigs_out[i] = std::get<0>(sel[i]);
+      if (err_out) err_out[i] = std::get<1>(sel[i]);
+    }
+    if (vecs_out) {
+      // Phi = V B_sel again for the returned values only, each column of B_sel scaled by
+      // 1 / ||V b_j|| (the Ritz vectors are orthonormal only up to the S cut-off's rounding).
+      const int cw = std::min(N, 512);
+      DevBuf bsel, dperm, dscale;
+      DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
+      DACP_HIP(ctx, dperm.alloc(sizeof(int) * cw));
+      DACP_HIP(ctx, dscale.alloc(sizeof(double) * cw));
+      for (int c0 = 0; c0 < N; c0 += cw) {
+        const int w = std::min(cw, N - c0);
+        std::vector<int> pr(w);
+        std::vector<double> sc(w);
+        for (int i = 0; i < w; ++i) {
+          const int q = std::get<2>(sel[c0 + i]);
+          pr[i] = order[q];
+          sc[i] = 1.0 / std::sqrt(phin2[q]);
+        }
+        DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
+        DACP_TRY(to_device(ctx, dscale.p, sc.data(), sizeof(double) * w));
+        DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(),
+                                               dscale.as<double>(), w, m, s));
+        DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, V, m, bsel.as<double>(), m, 0.0, vecs_out + c0, ldvec, 0,
+                                         s));
+        DACP_HIP(ctx, hipStreamSynchronize(s));  // the host staging of the next chunk reuses dperm / dscale
+      }
     }
   }
   return DACP_OK;
@@ -1907,7 +1940,8 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
 
 dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
                          double norm_est, const double *V, int m, dacp_report &rep, double *eigs_out, double *err_out,
-                         int &accepted, const EigFn *eig = nullptr) {
+                         int &accepted, const EigFn *eig = nullptr, double *vecs_out = nullptr,
+                         int64_t ldvec = 0) {
   // projection (Sec. II.C)
   double t0 = now_ms();
   dacp_status st;
@@ -1932,16 +1966,16 @@ dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, do
   rep.t_gep_ms = now_ms() - t0;
   vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
 
-  return accept_stage(ctx, h, N, a, n_w, tol, norm_est, V, m, r, theta, bc, rep, eigs_out, err_out, accepted);
+  return accept_stage(ctx, h, N, a, n_w, tol, norm_est, V, m, r, theta, bc, rep, eigs_out, err_out, accepted,
+                      vecs_out, ldvec);
 }
 
-}  // namespace
-
-dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_in, double *eigs_out,
-                              double *err_out, int *n_out, dacp_report *report) {
+dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_in, double *eigs_out,
+                         double *err_out, double *vecs_out, int64_t ldvec, int *n_out, dacp_report *report) {
   if (!ctx || !h || !eigs_out) return DACP_E_INVALID;
   const int64_t D = h->D;
   if (N < 1 || N > D) return set_err(ctx, DACP_E_INVALID, "central_eigs: need 1 <= N <= 2^L");
+  if (vecs_out && ldvec < N) return set_err(ctx, DACP_E_INVALID, "central_eigpairs: need ldvec >= N");
   dacp_opts o;
   if (opts_in) o = *opts_in;
   else dacp_default_opts(&o);
@@ -2028,7 +2062,8 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
     rep.evol_group = es.group;
     vlog("evolution done: %.1f ms (%lld launches)", rep.t_evol_ms, static_cast<long long>(es.launches));
 
-    st = finish_basis(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, rep, eigs_out, err_out, accepted);
+    st = finish_basis(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, rep, eigs_out, err_out, accepted,
+                      nullptr, vecs_out, ldvec);
     if (st) return st;
     if (accepted >= N) {
       if (n_out) *n_out = N;
@@ -2044,6 +2079,20 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
   if (report) *report = rep;
   return set_err(ctx, DACP_E_WINDOW,
                  "only " + std::to_string(accepted) + " eigenvalues accepted near 0; widen the window");
+}
+
+}  // namespace
+
+dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
+                              double *err_out, int *n_out, dacp_report *report) {
+  return central_eigs(ctx, h, N, opts, eigs_out, err_out, nullptr, 0, n_out, report);
+}
+
+dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
+                                  double *err_out, double *vecs_out, int64_t ldvec, int *n_out,
+                                  dacp_report *report) {
+  if (!vecs_out) return ctx ? set_err(ctx, DACP_E_INVALID, "central_eigpairs: null vecs_out") : DACP_E_INVALID;
+  return central_eigs(ctx, h, N, opts, eigs_out, err_out, vecs_out, ldvec, n_out, report);
 }
 
 

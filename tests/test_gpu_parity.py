@@ -673,6 +673,74 @@ def test_central_eigs_jw_twin_L14(ctx):
     _check_central(eigs, ref, norm, N)
 
 
+def _check_eigvecs(X, eigs, errs, Hd, norm, a):
+    """Unit vectors whose Rayleigh quotient is the returned value, whose residual r = H x - theta x
+    obeys the acceptance rule (estimate min(||r||, ||r||^2 / eta) <= 1e-10 ||H|| with eta <= a, so
+    ||r|| <= sqrt(1e-10 ||H|| a)), and whose angle to the dense eigenvector of the nearest level is
+    at most ||r|| / delta, delta = distance from theta to every other level (the sin-theta bound of
+    a Ritz pair).
+
+    Rounding: x = V b with b = U y, U = S's eigenvectors over sqrt(eigenvalues) >= sqrt(1e-12), so
+    the FP64 product cancels by up to ~1e6 and x carries relative errors up to ~1e-10: the norm and
+    angle checks allow 1e-9 absolute; the Rayleigh quotient is second order in them."""
+    lam, Phi = np.linalg.eigh(Hd)
+    N = len(eigs)
+    nrm2 = np.einsum("si,si->i", X, X)
+    assert np.abs(np.sqrt(nrm2) - 1.0).max() < 1e-9
+    assert np.abs(np.einsum("si,si->i", X, Hd @ X) / nrm2 - eigs).max() <= 1e-12 * norm
+    rn = np.linalg.norm(Hd @ X - X * eigs[None, :], axis=0)
+    assert np.all(errs <= rn * (1 + 1e-6) + 1e-13 * norm)  # the estimate never exceeds ||r||
+    assert rn.max() <= 1.01 * math.sqrt(1.01e-10 * norm * a) + 1e-13 * norm
+    sin_max = 0.0
+    for i in range(N):
+        k = int(np.argmin(np.abs(lam - eigs[i])))
+        others = np.delete(lam, k)
+        delta = np.abs(others - eigs[i]).min()
+        perp = X[:, i] - Phi[:, k] * (Phi[:, k] @ X[:, i])
+        sin_t = np.linalg.norm(perp)
+        assert sin_t <= rn[i] / delta * 1.01 + 1e-9, (i, sin_t, rn[i], delta)
+        sin_max = max(sin_max, sin_t)
+    # orthogonality follows from the angles: |x_i . x_j| <= sin_i + sin_j for distinct levels
+    G = X.T @ X
+    np.fill_diagonal(G, 0.0)
+    assert np.abs(G).max() <= 2 * sin_max + 1e-9
+    return sin_max
+
+
+def test_central_eigpairs_vectors_against_dense_eigenvectors(ctx):
+    """Eigenvector output (Sec. II.C Ritz vectors) of the L = 10 spin glass and the L = 11 chain:
+    the values equal dacp_central_eigs', the vectors land in the requested columns of a padded
+    block and satisfy the Ritz-pair angle bound against the dense eigenvectors."""
+    for L, N, terms, ld in ((10, 100, inputs.spin_glass(10, 3), 103), (11, 64, inputs.ising_chain(11), 64)):
+        Hd = hamiltonian.dense_h(L, terms)
+        ref, norm = central.central_eigenvalues(L, terms, N)
+        ham = B.dacp_build_hamiltonian(ctx, L, terms)
+        opts = B.default_opts(b=4)
+        e0, r0, _, _ = B.dacp_central_eigs(ctx, ham, N, opts)
+        vecs = torch.full((1 << L, ld), float("nan"), dtype=torch.float64, device=DEV)
+        eigs, errs, rep, st = B.dacp_central_eigpairs(ctx, ham, N, vecs, opts)
+        _check_central(eigs, ref, norm, N)
+        assert np.array_equal(eigs, e0) and np.array_equal(errs, r0)
+        Xp = host(vecs)
+        assert np.isnan(Xp[:, N:]).all()  # the padding columns are left alone
+        _check_eigvecs(Xp[:, :N], eigs, errs, Hd, norm, rep["a"])
+
+
+def test_central_eigpairs_rejects_bad_stride(ctx):
+    L, N = 10, 20
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L))
+    vecs = torch.zeros((1 << L, N), dtype=torch.float64, device=DEV)
+    opts = B.default_opts(b=4)
+    eigs = np.zeros(N)
+    n_out = B.ctypes.c_int()
+    st = ctx.lib.dacp_central_eigpairs(ctx.handle, ham.handle, N, B.ctypes.byref(opts), B._f64(eigs), None,
+                                       B._ptr(vecs), N - 1, B.ctypes.byref(n_out), None)
+    assert st == -1
+    st = ctx.lib.dacp_central_eigpairs(ctx.handle, ham.handle, N, B.ctypes.byref(opts), B._f64(eigs), None, None,
+                                       N, B.ctypes.byref(n_out), None)
+    assert st == -1
+
+
 def test_central_eigs_jw_twin_L20_full_size(ctx):
     """Full size, in the benchmark's tuned configuration (D = 2^20, N = 5000, b = 64, FP32 filter with
     an FP64 tail, basis ratio 1.2): the integrable twin (hz = 0) of the benchmark chain against the
