@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="chain_L20_N5000",
-                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "fp32_tail_table"])
+                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "fp32_tail_table",
+                                                          "stage_sweep_L15"])
     ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
     ap.add_argument("--seed", type=int, default=None, help="start-block seed (default: the library's)")
@@ -294,6 +295,42 @@ def fp32_tail_table(args):
                       "rows": rows, "norm": norm}), flush=True)
 
 
+def stage_sweep_L15(args):
+    """Stage times against the number of central eigenvalues R at L = 15 (the timing analysis of
+    Sec. IV: filter time ~ 1/R, evolution time ~ R^0, subspace diagonalisation ~ R^3), for the
+    chaotic chain and a spin-glass shard, plain FP64 options, b = 16.  Each row is one call after an
+    untimed warm-up call; the slopes are least-squares fits of log T against log R."""
+    import numpy as np
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    ctx = B.Context(0)
+    L = 15
+    Rs = (30, 100, 300, 1000, 3000)
+    out = {"metric": "stage times vs number of eigenvalues R (L=15, plain FP64, b=16)", "L": L, "models": {}}
+    for name, terms in (("chain", inputs.ising_chain(L)), ("glass", inputs.spin_glass(L, 0))):
+        ham = B.dacp_build_hamiltonian(ctx, L, terms)
+        o = B.default_opts(b=16, kfac=18.0, window_ratio=2.2, precision=B.DACP_F64)
+        B.dacp_central_eigs(ctx, ham, 300, o, raise_on_window=False)  # warm-up
+        rows = []
+        for R in Rs:
+            eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, R, o, raise_on_window=False)
+            rows.append({"R": R, "status": st, "K": rep["K"], "m": rep["m"], "evol_steps": rep["evol_steps"],
+                         "t_filter_ms": rep["t_filter_ms"], "t_evol_ms": rep["t_evol_ms"],
+                         "t_project_ms": rep["t_project_ms"], "t_gep_ms": rep["t_gep_ms"],
+                         "t_accept_ms": rep["t_accept_ms"], "t_total_ms": rep["t_total_ms"]})
+            print(f"# {name} R={R}: status {st}, total {rep['t_total_ms']:.1f} ms", file=sys.stderr, flush=True)
+        ok = [r for r in rows if r["status"] == 0]
+        slopes = {}
+        if len(ok) >= 3:
+            lr = np.log([r["R"] for r in ok])
+            for key in ("t_filter_ms", "t_evol_ms", "t_gep_ms", "evol_steps"):
+                slopes[key] = float(np.polyfit(lr, np.log([max(r[key], 1e-9) for r in ok]), 1)[0])
+        out["models"][name] = {"rows": rows, "loglog_slopes": slopes}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -310,6 +347,8 @@ def main():
         return glass18_learned(args)
     if args.workload == "fp32_tail_table":
         return fp32_tail_table(args)
+    if args.workload == "stage_sweep_L15":
+        return stage_sweep_L15(args)
     import numpy as np
     import torch
 
