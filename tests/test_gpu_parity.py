@@ -741,6 +741,31 @@ def test_central_eigpairs_rejects_bad_stride(ctx):
     assert st == -1
 
 
+def test_central_eigs_paper_tfim_L14_against_jordan_wigner(ctx):
+    """The paper's random transverse-field chain, (1/4) sum J X X + (1/2) sum Gamma Z with
+    J ~ U[-10/sqrt(L), 10/sqrt(L)] and Gamma ~ U[0, 1] (Sec. III), against its Jordan-Wigner
+    spectrum (x and z exchanged: couplings J/4, fields Gamma/2)."""
+    L, N = 14, 300
+    terms = inputs.paper_tfim(L, 2)
+    Jb = np.array([t["coeff"] for t in terms if t["op_b"] == 1])
+    g = np.array([t["coeff"] for t in terms if t["op_b"] == 0])
+    ref, norm = central.central_eigenvalues_jw(Jb, g, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=16))
+    _check_central(eigs, ref, norm, N)
+
+
+def test_central_eigs_paper_spin_glass_shard_L12(ctx):
+    """The paper's spin-glass shard, sum_{i<j} J_ij X_i X_j + sum Gamma_i Z_i with the same
+    distributions (Sec. III), against the dense oracle."""
+    L, N = 12, 200
+    terms = inputs.paper_sgs(L, 5)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=8))
+    _check_central(eigs, ref, norm, N)
+
+
 def test_central_eigs_jw_twin_L20_full_size(ctx):
     """Full size, in the benchmark's tuned configuration (D = 2^20, N = 5000, b = 64, FP32 filter with
     an FP64 tail, basis ratio 1.2): the integrable twin (hz = 0) of the benchmark chain against the
