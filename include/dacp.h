@@ -333,6 +333,15 @@ dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_op
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports);
 
+/* Level statistics of a computed spectrum (the paper's motivation, Sec. I): the gap ratios
+ * r_i = min(s_i, s_{i+1}) / max(s_i, s_{i+1}) of consecutive spacings s_i = eigs[i+1] - eigs[i].
+ * Host code, no device or context needed.
+ *   eigs[n]       host, ascending (n >= 3), e.g. the output of dacp_central_eigs
+ *   r_out[n - 2]  host, may be NULL; NaN where both spacings are zero (three equal levels)
+ *   mean_out      host, may be NULL; mean of the finite ratios (NaN if there is none)
+ * Returns DACP_E_INVALID for n < 3, a null eigs, or values not ascending (or NaN). */
+dacp_status dacp_spacing_ratios(const double *eigs, int n, double *r_out, double *mean_out);
+
 /* Autotuner of the evolution recurrence for this Hamiltonian and block width b: times `steps`
  * evolution steps of one column group for every group width (powers of two up to min(b, 16)),
  * workgroup size (512, 1024), fused tile (4096, 8192 elements; also 1024 and 2048 below 2^19

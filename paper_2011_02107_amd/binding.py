@@ -150,6 +150,7 @@ SIGNATURES = {
         ctypes.c_int,
         [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _vp, _i64, _ip, ctypes.POINTER(Report)],
     ),
+    "dacp_spacing_ratios": (ctypes.c_int, [_dp, ctypes.c_int, _dp, _dp]),
     "dacp_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _ip, _dp]),
     "dacp_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "dacp_mlp_free": (None, [_vp]),
@@ -410,6 +411,17 @@ def dacp_central_eigpairs(ctx, ham, N, vecs, opts=None, raise_on_window=True):
         ctx.check(st)
     n = n_out.value if st == 0 else 0
     return eigs[:n], errs[:n], rep.as_dict(), st
+
+
+def dacp_spacing_ratios(eigs):
+    """(gap ratios [n-2], their mean) of ascending levels; host code, no device needed."""
+    e = np.ascontiguousarray(eigs, dtype=np.float64)
+    r = np.zeros(max(len(e) - 2, 0))
+    mean = ctypes.c_double()
+    st = load_library().dacp_spacing_ratios(_f64(e), int(len(e)), _f64(r), ctypes.byref(mean))
+    if st != 0:
+        raise ValueError("dacp_spacing_ratios: need n >= 3 ascending levels")
+    return r, mean.value
 
 
 def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True):

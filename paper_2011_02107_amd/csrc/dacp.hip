@@ -2715,6 +2715,26 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   return DACP_OK;
 }
 
+dacp_status dacp_spacing_ratios(const double *eigs, int n, double *r_out, double *mean_out) {
+  if (!eigs || n < 3) return DACP_E_INVALID;
+  for (int i = 0; i + 1 < n; ++i)
+    if (!(eigs[i + 1] >= eigs[i])) return DACP_E_INVALID;  // also rejects NaN
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (int i = 0; i + 2 < n; ++i) {
+    const double s0 = eigs[i + 1] - eigs[i], s1 = eigs[i + 2] - eigs[i + 1];
+    const double hi = std::max(s0, s1);
+    const double r = hi > 0.0 ? std::min(s0, s1) / hi : NAN;
+    if (r_out) r_out[i] = r;
+    if (hi > 0.0) {
+      sum += r;
+      ++cnt;
+    }
+  }
+  if (mean_out) *mean_out = cnt ? sum / static_cast<double>(cnt) : NAN;
+  return DACP_OK;
+}
+
 dacp_status dacp_window_features(dacp_ham h, double *f) {
   if (!h || !f) return DACP_E_INVALID;
   const double sig2 = h->sum_sq;

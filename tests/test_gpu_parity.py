@@ -21,7 +21,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import central, chebyshev, hamiltonian, jordan_wigner, philox, spectral, subspace  # noqa: E402
+from oracle import central, chebyshev, hamiltonian, jordan_wigner, levels, philox, spectral, subspace  # noqa: E402
 from oracle import _native  # noqa: E402
 from paper_2011_02107_amd import binding as B  # noqa: E402
 from paper_2011_02107_amd import inputs  # noqa: E402
@@ -753,6 +753,12 @@ def test_central_eigs_paper_tfim_L14_against_jordan_wigner(ctx):
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=16))
     _check_central(eigs, ref, norm, N)
+    # gap ratios of the computed levels: each level is within 1e-10 ||H||, so each spacing within
+    # 2e-10 ||H|| and each ratio within (1 + r) 2e-10 ||H|| / max(s_i, s_i+1) of the exact one
+    r, _ = B.dacp_spacing_ratios(eigs)
+    r_ref, _ = levels.spacing_ratios(ref)
+    s = np.diff(ref)
+    assert np.all(np.abs(r - r_ref) <= 4.4e-10 * norm / np.maximum(s[:-1], s[1:]) + 1e-12)
 
 
 def test_central_eigs_paper_spin_glass_shard_L12(ctx):

@@ -40,3 +40,27 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.dacp_create(0, None, None) == -1
     assert lib.dacp_last_error(None).decode() == "null context"
     lib.dacp_destroy(None)  # a no-op
+
+
+def test_spacing_ratios_through_the_abi_match_the_oracle():
+    """Host entry point, no device: ratios equal the oracle's bit for bit, NaN where both spacings
+    vanish, and bad input is rejected with a status."""
+    import numpy as np
+
+    from oracle import levels
+
+    rng = np.random.default_rng(3)
+    E = np.sort(rng.standard_normal(5000))
+    E = np.concatenate([E, [E[-1] + 1.0] * 3])  # three equal levels at the end
+    r, mean = binding.dacp_spacing_ratios(E)
+    r_ref, mean_ref = levels.spacing_ratios(E)
+    assert np.array_equal(np.isnan(r), np.isnan(r_ref)) and np.isnan(r[-1])
+    fin = ~np.isnan(r_ref)
+    assert np.array_equal(r[fin], r_ref[fin])
+    assert abs(mean - mean_ref) <= 1e-15
+    lib = binding.load_library()
+    bad = np.array([0.0, 2.0, 1.0])
+    assert lib.dacp_spacing_ratios(bad.ctypes.data_as(binding._dp), 3, None, None) == -1
+    assert lib.dacp_spacing_ratios(bad.ctypes.data_as(binding._dp), 2, None, None) == -1
+    nan = np.array([0.0, np.nan, 1.0])
+    assert lib.dacp_spacing_ratios(nan.ctypes.data_as(binding._dp), 3, None, None) == -1

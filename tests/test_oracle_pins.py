@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import _native, central, chebyshev, hamiltonian, jordan_wigner, philox, spectral, subspace
+from oracle import _native, central, chebyshev, hamiltonian, jordan_wigner, levels, philox, spectral, subspace
 from paper_2011_02107_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -471,3 +471,37 @@ def test_mlp_adam_first_step_is_signed_lr():
     g = np.array([0.3, -2.0, 1e-3, -5e-4])
     th, m, v = mlp.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01, eps=0.0)
     assert np.allclose(th, -0.01 * np.sign(g), rtol=1e-12)
+
+
+# ------------------------------------------------------------------ level statistics
+
+
+def test_spacing_ratios_worked_example():
+    """Levels 0, 1, 3, 4, 4, 4: spacings 1, 2, 1, 0, 0 give ratios 1/2, 1/2, 0 and no ratio for
+    the two zero spacings."""
+    r, mean = levels.spacing_ratios([0.0, 1.0, 3.0, 4.0, 4.0, 4.0])
+    assert np.array_equal(r[:3], [0.5, 0.5, 0.0]) and np.isnan(r[3])
+    assert mean == pytest.approx(1.0 / 3.0, abs=1e-15)
+    with pytest.raises(ValueError):
+        levels.spacing_ratios([0.0, 2.0, 1.0])
+
+
+def test_spacing_ratios_poisson_closed_form():
+    """Uncorrelated levels (i.i.d. uniform): the ratio has density 2 / (1 + r)^2 on [0, 1], so its
+    mean is 2 ln 2 - 1 and P(r < 0.1) = 2 (1 - 1/1.1).  2e5 levels: standard error ~7e-4."""
+    E = np.sort(np.random.default_rng(0).uniform(0.0, 1.0, 200_000))
+    r, mean = levels.spacing_ratios(E)
+    assert abs(mean - (2 * np.log(2) - 1)) < 4e-3
+    assert abs(np.mean(r < 0.1) - 2 * (1 - 1 / 1.1)) < 5e-3
+
+
+def test_spacing_ratios_goe_level_repulsion():
+    """Bulk levels of a GOE matrix (eigenvalues from numpy's LAPACK driver) repel: the mean ratio is
+    about 0.53 (Atas et al. 2013), far above the Poisson 0.386, and small ratios are rare."""
+    rng = np.random.default_rng(1)
+    n = 1200
+    A = rng.standard_normal((n, n))
+    w = np.linalg.eigvalsh((A + A.T) / 2)
+    r, mean = levels.spacing_ratios(w[n // 4: 3 * n // 4])
+    assert abs(mean - 0.5307) < 0.03
+    assert np.mean(r < 0.1) < 0.05
