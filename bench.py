@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--block", type=int, default=0, help="start-block width b (default: the workload's)")
     ap.add_argument("--max-retries", type=int, default=None, help="wider-window retries (default: the library's)")
+    ap.add_argument("--eigvecs", action="store_true",
+                    help="time dacp_central_eigpairs (eigenvalues and unit eigenvectors) instead of dacp_central_eigs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--profile-gemm", action="store_true",
@@ -371,14 +373,21 @@ def main():
     small = B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8))
     B.dacp_central_eigs(ctx, small, 20, B.default_opts(b=4), raise_on_window=False)
     small.close()
+    vecs = torch.empty((1 << L, N), dtype=torch.float64, device="cuda:0") if args.eigvecs else None
+
+    def call():
+        if vecs is not None:
+            return B.dacp_central_eigpairs(ctx, ham, N, vecs, opts)
+        return B.dacp_central_eigs(ctx, ham, N, opts)
+
     for _ in range(args.warmup):
-        B.dacp_central_eigs(ctx, ham, N, opts)
+        call()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
     n_ok = 0
     for _ in range(args.steps):
-        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
+        eigs, errs, rep, st = call()
         reps.append(rep)
         n_ok += len(eigs)
     torch.cuda.synchronize()
@@ -416,6 +425,7 @@ def main():
             "L": L,
             "N": N,
             "mode": args.mode,
+            "eigenvectors": bool(args.eigvecs),
             "b": rep["b"],
             "group": g,
             "K": rep["K"],
