@@ -40,8 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="chain_L20_N5000",
-                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "fp32_tail_table",
-                                                          "stage_sweep_L15"])
+                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "stage_sweep_L15"])
     ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
     ap.add_argument("--seed", type=int, default=None, help="start-block seed (default: the library's)")
@@ -268,35 +267,6 @@ def glass18_learned(args):
         "data": "synthetic"}), flush=True)
 
 
-def fp32_tail_table(args):
-    """Error of the FP32 filter + FP64 tail against the dense FP64 oracle, per tail fraction
-    (spin glass L = 12, N = 200, b = 8, kfac 12)."""
-    import numpy as np
-
-    from oracle import central
-    from paper_2011_02107_amd import binding as B
-    from paper_2011_02107_amd import inputs
-
-    ctx = B.Context(0)
-    L, N = 12, 200
-    terms = inputs.spin_glass(L, 0)
-    ref, norm = central.central_eigenvalues(L, terms, N)
-    ham = B.dacp_build_hamiltonian(ctx, L, terms)
-    rows = []
-    for prec, frac in ((B.DACP_F64, 1.0), (B.DACP_F32, 0.0), (B.DACP_F32, 0.05), (B.DACP_F32, 0.1),
-                       (B.DACP_F32, 0.2), (B.DACP_F32, 0.3)):
-        o = B.default_opts(b=8, kfac=12.0, precision=prec, fp64_tail_frac=frac, max_retries=0)
-        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o, raise_on_window=False)
-        row = {"filter": "f64" if prec == B.DACP_F64 else "f32", "fp64_tail_frac": frac, "status": st,
-               "accepted_core": rep["n_accepted"], "of_candidates": rep["n_candidates"]}
-        if st == 0:
-            d = np.abs(np.sort(eigs) - ref) / norm
-            row.update({"max_rel_err": float(d.max()), "median_rel_err": float(np.median(d))})
-        rows.append(row)
-    print(json.dumps({"metric": "FP32 filter + FP64 tail vs dense FP64 oracle (glass L=12, N=200)",
-                      "rows": rows, "norm": norm}), flush=True)
-
-
 def stage_sweep_L15(args):
     """Stage times against the number of central eigenvalues R at L = 15 (the timing analysis of
     Sec. IV: filter time ~ 1/R, evolution time ~ R^0, subspace diagonalisation ~ R^3), for the
@@ -347,8 +317,6 @@ def main():
         return batch96(args)
     if args.workload == "glass_L18_N3000_learned":
         return glass18_learned(args)
-    if args.workload == "fp32_tail_table":
-        return fp32_tail_table(args)
     if args.workload == "stage_sweep_L15":
         return stage_sweep_L15(args)
     import numpy as np

@@ -787,6 +787,58 @@ def test_central_eigs_jw_twin_L20_full_size(ctx):
     assert np.all(errs <= 1e-10 * norm)
 
 
+def test_central_eigs_paper_tfim_L19_full_size(ctx):
+    """The paper's error experiment on its Ising model (Sec. III, the L = 19 panel of its relative-
+    error figure) with our own disorder seed: 5000 central levels of the random transverse-field
+    chain at L = 19 in the benchmark's tuned configuration, against the exact Jordan-Wigner
+    spectrum.  Its levels cluster (integrable model): the closest pair among the 5000 is 2.7e-9
+    apart, 3.5x the 1e-10 ||H|| tolerance.  Prints the paper's measure, the count of values with
+    relative error eta = |E - E_exact| / |E_exact| below 1e-6."""
+    import time
+
+    L, N = 19, 5000
+    terms = inputs.paper_tfim(L, 0)
+    Jb = np.array([t["coeff"] for t in terms if t["op_b"] == 1])
+    g = np.array([t["coeff"] for t in terms if t["op_b"] == 0])
+    ref, norm = central.central_eigenvalues_jw(Jb, g, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    opts = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
+                          fp64_tail_frac=0.3)
+    t0 = time.perf_counter()
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
+    dt = time.perf_counter() - t0
+    _check_central(eigs, ref, norm, N)
+    assert np.all(errs <= 1e-10 * norm)
+    err = np.abs(eigs - ref)
+    eta = err / np.abs(ref)
+    print(f"paper TFIM L=19 N=5000: {dt:.1f} s, max |dE|/||H|| {err.max() / norm:.2e}, "
+          f"eta < 1e-6 for {int(np.sum(eta < 1e-6))} of {N}, max eta {eta.max():.2e}, m {rep['m']}, "
+          f"rank {rep['rank']}, K {rep['K']}, evolution steps {rep['evol_steps']}, retries {rep['retries']}")
+
+
+def test_fp32_tail_error_table(ctx):
+    """Error of the FP32 filter with an FP64 tail against the dense FP64 oracle, per tail fraction
+    (spin glass L = 12, N = 200, b = 8, kfac 12, no retries).  FP64 and tails of 0.2 and 0.3 must
+    reach N with the full accuracy; shorter tails may fall short (printed, not asserted)."""
+    L, N = 12, 200
+    terms = inputs.spin_glass(L, 0)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    for prec, frac in ((B.DACP_F64, 1.0), (B.DACP_F32, 0.0), (B.DACP_F32, 0.05), (B.DACP_F32, 0.1),
+                       (B.DACP_F32, 0.2), (B.DACP_F32, 0.3)):
+        o = B.default_opts(b=8, kfac=12.0, precision=prec, fp64_tail_frac=frac, max_retries=0)
+        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o, raise_on_window=False)
+        line = (f"{'f64' if prec == B.DACP_F64 else 'f32'} tail {frac}: status {st}, core {rep['n_accepted']} "
+                f"of {rep['n_candidates']}")
+        if st == 0:
+            d = np.abs(np.sort(eigs) - ref) / norm
+            line += f", max {d.max():.1e}, median {np.median(d):.1e} (of ||H|| = {norm:.2f})"
+        print(line)
+        if prec == B.DACP_F64 or frac >= 0.2:
+            assert st == 0
+            _check_central(eigs, ref, norm, N)
+
+
 # ------------------------------------------------------------------ batched realisations
 
 
