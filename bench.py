@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="chain_L20_N5000",
-                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "stage_sweep_L15"])
+                    choices=sorted(WORKLOADS) + ["glass_batch96_N200", "glass_L18_N3000_learned", "stage_sweep_L15",
+                                                          "scaling_paper_models"])
     ap.add_argument("--mode", default="tuned", choices=["plain", "tuned"])
     ap.add_argument("--kfac", type=float, default=None)
     ap.add_argument("--seed", type=int, default=None, help="start-block seed (default: the library's)")
@@ -303,6 +304,56 @@ def stage_sweep_L15(args):
     print(json.dumps(out), flush=True)
 
 
+def scaling_paper_models(args):
+    """Time against system size for the paper's two models with its distributions (Sec. III: the
+    random transverse-field chain and the all-to-all spin-glass shard, J ~ U[-10/sqrt(L), 10/sqrt(L)],
+    Gamma ~ U[0, 1]), N = 5000 central values, L = 15 .. 18, tuned options with the evolution
+    autotuned per shape (untimed, as in the headline).  alpha is the
+    least-squares slope of log T against L (T = T0 exp(alpha L), the paper's scaling constant),
+    for the filter + evolution time and for the whole call."""
+    import numpy as np
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    ctx = B.Context(0)
+    N = 5000
+    Ls = (15, 16, 17, 18)
+    small = B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8))
+    B.dacp_central_eigs(ctx, small, 20, B.default_opts(b=4), raise_on_window=False)  # load the kernels
+    small.close()
+    out = {"metric": "time vs L, N=5000, paper models (tuned options)", "N": N, "models": {}}
+    for name, build in (("ising", inputs.paper_tfim), ("glass", inputs.paper_sgs)):
+        rows = []
+        for L in Ls:
+            ham = B.dacp_build_hamiltonian(ctx, L, build(L, 0))
+            t0 = time.perf_counter()
+            g, us = B.dacp_autotune(ctx, ham, b=64, steps=64)  # as in the headline's tuned mode, untimed
+            t_tune = time.perf_counter() - t0
+            o = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
+                               fp64_tail_frac=0.3)
+            eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o, raise_on_window=False)
+            rows.append({"L": L, "status": st, "accepted": len(eigs), "K": rep["K"], "m": rep["m"],
+                         "evol_steps": rep["evol_steps"], "t_filter_ms": rep["t_filter_ms"],
+                         "t_evol_ms": rep["t_evol_ms"], "t_project_ms": rep["t_project_ms"],
+                         "t_gep_ms": rep["t_gep_ms"], "t_total_ms": rep["t_total_ms"],
+                         "autotune": {"group": g, "rec_threads": ctx.tune_get("rec_threads"),
+                                      "rec_tile": ctx.tune_get("rec_tile"), "rec_hi_w": ctx.tune_get("rec_hi_w"),
+                                      "us_per_column_step": us, "s": t_tune}})
+            ham.close()
+            print(f"# {name} L={L}: status {st}, total {rep['t_total_ms']:.0f} ms, evolution {rep['t_evol_ms']:.0f} ms",
+                  file=sys.stderr, flush=True)
+        ok = [r for r in rows if r["status"] == 0]
+        fit = {}
+        if len(ok) >= 2:
+            Lv = [r["L"] for r in ok]
+            fit["alpha_filter_plus_evolution"] = float(np.polyfit(Lv, np.log([r["t_filter_ms"] + r["t_evol_ms"]
+                                                                              for r in ok]), 1)[0])
+            fit["alpha_total"] = float(np.polyfit(Lv, np.log([r["t_total_ms"] for r in ok]), 1)[0])
+        out["models"][name] = {"rows": rows, **fit}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -319,6 +370,8 @@ def main():
         return glass18_learned(args)
     if args.workload == "stage_sweep_L15":
         return stage_sweep_L15(args)
+    if args.workload == "scaling_paper_models":
+        return scaling_paper_models(args)
     import numpy as np
     import torch
 
