@@ -303,9 +303,9 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
  * returned values (Sec. II.C: the basis A times the subspace solution), each scaled to unit norm.
  *   vecs_out  device, D x N block, row stride ldvec >= N: vecs_out[s * ldvec + i] is component s
  *             of the vector of eigs_out[i].  Written only when the call returns DACP_OK.
- * Forming them is one extra FP64 GEMM of D x N x m after the acceptance.  A vector's angle to the
- * exact eigenvector is at most err_i' / gap, with err_i' its residual norm and gap the distance of
- * its value to the rest of the spectrum, so vectors of near-degenerate levels are only
+ * Forming them is one extra FP64 GEMM of D x N x m after the acceptance.  The angle between
+ * phi_i and the exact eigenvector is at most ||H phi_i - theta_i phi_i|| / gap_i, gap_i being the
+ * distance from theta_i to every other eigenvalue, so vectors of near-degenerate levels are only
  * determined as a subspace.  Returns DACP_E_INVALID for a null vecs_out or ldvec < N. */
 dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                                   double *err_out, double *vecs_out, int64_t ldvec, int *n_out,
