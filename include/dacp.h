@@ -333,6 +333,22 @@ dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_op
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports);
 
+/* The parameters dacp_central_eigs picks for one attempt (Sec. II.A, II.B, III), host code with no
+ * device or context: the window holds N_w = min(D, ceil(window_ratio' N)) estimated levels, with
+ * window_ratio' = window_ratio * 1.5^attempt; a_r = a / E_b from the density's Chebyshev moments
+ * (or opts->a); K = ceil(kfac / a_r); the block width b; n = ceil((basis_ratio N_w / b - 1) / 2)
+ * evolution samples per start state, m = b (2n + 1); sampled orders k_j = 2 floor(j pi / (2 a_r)).
+ *   D, N, e_bound  state length, wanted values, spectral bound E_b > 0
+ *   mu[n_mu]       host, density moments as from dacp_dos_moments (unused when opts->a > 0)
+ *   opts           host, may be NULL (defaults); attempt = 0 for the first window
+ *   fout[3]        host: N_w, a_r, a
+ *   iout[4]        host: K, b, n, m
+ *   k_samples      host, may be NULL: the first min(n, max_samples) sampled orders
+ * Returns DACP_E_INVALID for D < 1, N outside [1, D], E_b <= 0, attempt < 0, null outputs, or
+ * missing moments. */
+dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_mu, const dacp_opts *opts,
+                      int attempt, double *fout, int *iout, int64_t *k_samples, int max_samples);
+
 /* Level statistics of a computed spectrum (the paper's motivation, Sec. I): the gap ratios
  * r_i = min(s_i, s_{i+1}) / max(s_i, s_{i+1}) of consecutive spacings s_i = eigs[i+1] - eigs[i].
  * Host code, no device or context needed.

@@ -151,6 +151,11 @@ SIGNATURES = {
         [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _vp, _i64, _ip, ctypes.POINTER(Report)],
     ),
     "dacp_spacing_ratios": (ctypes.c_int, [_dp, ctypes.c_int, _dp, _dp]),
+    "dacp_plan": (
+        ctypes.c_int,
+        [_i64, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int, ctypes.POINTER(Opts), ctypes.c_int, _dp, _ip,
+         ctypes.POINTER(_i64), ctypes.c_int],
+    ),
     "dacp_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _ip, _dp]),
     "dacp_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "dacp_mlp_free": (None, [_vp]),
@@ -411,6 +416,26 @@ def dacp_central_eigpairs(ctx, ham, N, vecs, opts=None, raise_on_window=True):
         ctx.check(st)
     n = n_out.value if st == 0 else 0
     return eigs[:n], errs[:n], rep.as_dict(), st
+
+
+def dacp_plan(D, N, e_bound, mu=None, opts=None, attempt=0, max_samples=1 << 16):
+    """Parameters of one attempt (host code): dict with n_w, a_r, a, K, b, n, m and the sampled
+    orders k_samples (the first max_samples of them)."""
+    if opts is None:
+        opts = default_opts()
+    m = np.ascontiguousarray(mu if mu is not None else np.zeros(0), dtype=np.float64)
+    fout = np.zeros(3)
+    iout = np.zeros(4, dtype=np.int32)
+    ks = np.zeros(max_samples, dtype=np.int64)
+    st = load_library().dacp_plan(int(D), int(N), float(e_bound), _f64(m) if len(m) else None, int(len(m)),
+                                  ctypes.byref(opts), int(attempt), _f64(fout),
+                                  iout.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  ks.ctypes.data_as(ctypes.POINTER(_i64)), int(max_samples))
+    if st != 0:
+        raise ValueError(f"dacp_plan: invalid arguments (status {st})")
+    n = int(iout[2])
+    return {"n_w": fout[0], "a_r": fout[1], "a": fout[2], "K": int(iout[0]), "b": int(iout[1]), "n": n,
+            "m": int(iout[3]), "k_samples": ks[:min(n, max_samples)].copy()}
 
 
 def dacp_spacing_ratios(eigs):

@@ -2088,6 +2088,33 @@ dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *
   return central_eigs(ctx, h, N, opts, eigs_out, err_out, nullptr, 0, n_out, report);
 }
 
+dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_mu, const dacp_opts *opts_in,
+                      int attempt, double *fout, int *iout, int64_t *k_samples, int max_samples) {
+  if (D < 1 || N < 1 || N > D || !(e_bound > 0.0) || attempt < 0 || !fout || !iout) return DACP_E_INVALID;
+  dacp_opts o;
+  if (opts_in) o = *opts_in;
+  else dacp_default_opts(&o);
+  if (!(o.a > 0.0) && (!mu || n_mu < 1)) return DACP_E_INVALID;
+  std::vector<double> m;
+  if (!(o.a > 0.0)) m.assign(mu, mu + n_mu);
+  // the same widening as dacp_central_eigs applies before each retry
+  double window_ratio = o.window_ratio > 0.0 ? o.window_ratio : 2.2;
+  for (int i = 0; i < attempt; ++i) window_ratio *= 1.5;
+  const Plan p = make_plan(o, D, N, e_bound, m, window_ratio, attempt);
+  fout[0] = p.n_w;
+  fout[1] = p.a_r;
+  fout[2] = p.a;
+  iout[0] = p.K;
+  iout[1] = p.b;
+  iout[2] = p.n;
+  iout[3] = p.m;
+  if (k_samples && max_samples > 0) {
+    const std::vector<int64_t> ks = sample_orders(p.a_r, p.n);
+    for (int i = 0; i < std::min(max_samples, p.n); ++i) k_samples[i] = ks[i];
+  }
+  return DACP_OK;
+}
+
 dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                                   double *err_out, double *vecs_out, int64_t ldvec, int *n_out,
                                   dacp_report *report) {

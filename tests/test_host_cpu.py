@@ -64,3 +64,48 @@ def test_spacing_ratios_through_the_abi_match_the_oracle():
     assert lib.dacp_spacing_ratios(bad.ctypes.data_as(binding._dp), 2, None, None) == -1
     nan = np.array([0.0, np.nan, 1.0])
     assert lib.dacp_spacing_ratios(nan.ctypes.data_as(binding._dp), 3, None, None) == -1
+
+
+def test_plan_matches_the_oracle_parameter_rules():
+    """The host parameter selection (window, filter order, basis size, sampled orders; Sec. II.A,
+    II.B, III) through the C ABI, without a device, against the oracle's window bisection over its
+    KPM count, its filter order and its sampled orders."""
+    import math
+
+    import numpy as np
+
+    from oracle import chebyshev, hamiltonian, spectral
+    from paper_2011_02107_amd import inputs
+
+    L, N = 10, 100
+    D = 1 << L
+    terms = inputs.ising_chain(L)
+    e_b = hamiltonian.sum_abs_coeff(terms)  # a valid bound (>= ||H||)
+    R = inputs.gaussian_block(D, 8, 4)
+    mu = spectral.kpm_moments(lambda X: hamiltonian.apply_h(L, terms, X), R, e_b, 128)
+    for attempt, opts in ((0, binding.default_opts(b=4)), (1, binding.default_opts(b=4)),
+                          (0, binding.default_opts(b=0, basis_ratio=1.2, kfac=12.0))):
+        p = binding.dacp_plan(D, N, e_b, mu, opts, attempt=attempt)
+        wr = 2.2  # the count is decided in FP64 on both sides (2.2 * 100 rounds up to 220.00000000000003)
+        for _ in range(attempt):
+            wr *= 1.5
+        n_w = min(D, math.ceil(wr * N))
+        assert p["n_w"] == n_w
+        ref = spectral.window_for_count(mu, D, n_w)
+        assert abs(p["a_r"] - ref) <= 1e-12
+        assert spectral.kpm_count(mu, D, p["a_r"]) >= n_w * (1 - 1e-12)
+        assert p["a"] == p["a_r"] * e_b
+        assert p["K"] == chebyshev.filter_order(e_b, p["a"], opts.kfac)
+        b, n, m = p["b"], p["n"], p["m"]
+        assert m == b * (2 * n + 1) and m >= opts.basis_ratio * n_w
+        assert n == 1 or b * (2 * n - 1) < opts.basis_ratio * n_w  # the smallest such n
+        assert list(p["k_samples"]) == chebyshev.sample_orders(p["a_r"], n)
+    # a fixed window skips the moments
+    p = binding.dacp_plan(D, N, e_b, None, binding.default_opts(b=4, a=0.5))
+    assert p["a_r"] == 0.5 / e_b and p["K"] == chebyshev.filter_order(e_b, p["a"], 18.0)
+    with pytest.raises(ValueError):
+        binding.dacp_plan(D, N, e_b, None, binding.default_opts(b=4))  # no moments, no window
+    with pytest.raises(ValueError):
+        binding.dacp_plan(D, D + 1, e_b, mu)
+    with pytest.raises(ValueError):
+        binding.dacp_plan(D, N, 0.0, mu)
