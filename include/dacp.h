@@ -349,6 +349,26 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
 dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_mu, const dacp_opts *opts,
                       int attempt, double *fout, int *iout, int64_t *k_samples, int max_samples);
 
+/* The acceptance rule of dacp_central_eigs (Sec. II.C residual check, with the quadratic residual
+ * bound), host code with no device or context.  Candidates are the first n_sel Ritz values in the
+ * order of (|theta|, theta).  A candidate starts accepted when its residual is at most
+ * 1e-4 norm_est, and is a "ghost" when its residual exceeds ten mean level spacings 20 a / n_w.
+ * Its estimate is min(||r||, ||r||^2 / eta), eta being the distance to the window edge a or to the
+ * nearest Ritz value that is neither accepted nor a ghost.  Candidates whose estimate exceeds tol
+ * are dropped until nothing changes (at most 8 rounds).  The core is then the run of accepted
+ * candidates with |theta| <= a, walking outward from 0, skipping ghosts and stopping at the first
+ * other rejection.
+ *   theta[r]        host, ascending Ritz values
+ *   rnorm[n_sel]    host, residual norms in the (|theta|, theta) order
+ *   core_out        host: the core's size
+ *   core_pos[n_sel] host, may be NULL: the core's positions in that order
+ *   est_out[n_sel]  host, may be NULL: estimates (infinite where a candidate never started accepted)
+ *   n_ghost_out     host, may be NULL: the number of ghosts
+ * Returns DACP_E_INVALID for n_sel outside [0, r], unsorted theta, a <= 0, n_w <= 0 or null inputs. */
+dacp_status dacp_accept_rule(int r, const double *theta, int n_sel, const double *rnorm, double a, double n_w,
+                             double tol, double norm_est, int *core_out, int *core_pos, double *est_out,
+                             int *n_ghost_out);
+
 /* Level statistics of a computed spectrum (the paper's motivation, Sec. I): the gap ratios
  * r_i = min(s_i, s_{i+1}) / max(s_i, s_{i+1}) of consecutive spacings s_i = eigs[i+1] - eigs[i].
  * Host code, no device or context needed.

@@ -151,6 +151,11 @@ SIGNATURES = {
         [_vp, _vp, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _vp, _i64, _ip, ctypes.POINTER(Report)],
     ),
     "dacp_spacing_ratios": (ctypes.c_int, [_dp, ctypes.c_int, _dp, _dp]),
+    "dacp_accept_rule": (
+        ctypes.c_int,
+        [ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+         _ip, _ip, _dp, _ip],
+    ),
     "dacp_plan": (
         ctypes.c_int,
         [_i64, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_int, ctypes.POINTER(Opts), ctypes.c_int, _dp, _ip,
@@ -436,6 +441,22 @@ def dacp_plan(D, N, e_bound, mu=None, opts=None, attempt=0, max_samples=1 << 16)
     n = int(iout[2])
     return {"n_w": fout[0], "a_r": fout[1], "a": fout[2], "K": int(iout[0]), "b": int(iout[1]), "n": n,
             "m": int(iout[3]), "k_samples": ks[:min(n, max_samples)].copy()}
+
+
+def dacp_accept_rule(theta, rnorm, a, n_w, tol, norm_est):
+    """(core positions in the (|theta|, theta) order, estimates, ghost count); host code."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    rn = np.ascontiguousarray(rnorm, dtype=np.float64)
+    core = ctypes.c_int()
+    pos = np.zeros(max(len(rn), 1), dtype=np.int32)
+    est = np.zeros(max(len(rn), 1))
+    ng = ctypes.c_int()
+    st = load_library().dacp_accept_rule(int(len(th)), _f64(th), int(len(rn)), _f64(rn), float(a), float(n_w),
+                                         float(tol), float(norm_est), ctypes.byref(core),
+                                         pos.ctypes.data_as(_ip), _f64(est), ctypes.byref(ng))
+    if st != 0:
+        raise ValueError(f"dacp_accept_rule: invalid arguments (status {st})")
+    return pos[:core.value].copy(), est[:len(rn)].copy(), ng.value
 
 
 def dacp_spacing_ratios(eigs):

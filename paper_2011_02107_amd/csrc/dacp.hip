@@ -1770,6 +1770,86 @@ Plan make_plan(const dacp_opts &o, int64_t D, int N, double e_b, const std::vect
 // Acceptance (Sec. II.C residual check) of one realisation: Ritz vectors V B for the candidates by
 // |theta|, their residuals, the quadratic residual bound and the contiguous core.  theta ascending
 // (r values), bc the rows of B^T (r x m).
+// The acceptance rule on the host.  theta: the r Ritz values, ascending; order: positions in
+// theta sorted by (|theta|, theta); rnorm[q]: residual norm of the Ritz vector of theta[order[q]]
+// for the first n_sel positions.  The Ritz residual is orthogonal to the whole search space, which
+// holds the converged neighbours of theta_j, so the quadratic residual bound |theta_j - lambda_j|
+// <= ||r_j||^2 / eta_j uses eta_j = distance from theta_j to the part of the spectrum the subspace
+// does not resolve: the nearest unaccepted Ritz value, or the window edge (levels beyond a are not
+// represented).  Start from the candidates whose residual is below a generous cap, iterate to a
+// fixed point, then keep the contiguous accepted core around 0 (walk outward in |theta|, stop at
+// the first rejection).  The estimate is min(||r||, ||r||^2 / eta).
+//
+// A Ritz value whose residual exceeds ten mean level spacings of the window approximates no
+// eigenvalue near it (a "ghost" built from weakly represented directions of the overcomplete
+// basis): it is left out of eta and does not stop the core.  Central levels carry the largest
+// filter amplitude, so a true level there is never that poorly represented.
+struct AcceptResult {
+  std::vector<char> ok, ghost;  // per Ritz value
+  std::vector<double> est;      // per position q < n_sel (INFINITY where never accepted)
+  std::vector<int> core_idx;    // positions q of the contiguous core, walking outward
+  double max_est = 0.0;
+  int n_ghost = 0;
+};
+
+AcceptResult accept_rule(const std::vector<double> &theta, const std::vector<int> &order, int n_sel,
+                         const std::vector<double> &rnorm, double a, double n_w, double tol, double norm_est) {
+  const int r = static_cast<int>(theta.size());
+  AcceptResult res;
+  std::vector<char> &ok = res.ok, &ghost = res.ghost;
+  ok.assign(r, 0);
+  ghost.assign(r, 0);
+  const double cap = 1e-4 * norm_est;
+  const double ghost_thr = 10.0 * (2.0 * a / n_w);
+  for (int i = 0; i < n_sel; ++i) {
+    ok[order[i]] = rnorm[i] <= cap;
+    ghost[order[i]] = rnorm[i] > ghost_thr;
+  }
+  for (int i = 0; i < n_sel; ++i) res.n_ghost += ghost[order[i]];
+  std::vector<double> &est = res.est;
+  est.assign(n_sel, INFINITY);
+  for (int iter = 0; iter < 8; ++iter) {
+    std::vector<double> unc;  // sorted Ritz values not (or no longer) accepted, ghosts excluded
+    for (int i = 0; i < r; ++i)
+      if (!ok[i] && !ghost[i]) unc.push_back(theta[i]);
+    bool changed = false;
+    for (int q = 0; q < n_sel; ++q) {
+      const int j = order[q];
+      if (!ok[j]) continue;
+      double eta = a - std::fabs(theta[j]);
+      auto it = std::lower_bound(unc.begin(), unc.end(), theta[j]);
+      if (it != unc.end()) eta = std::min(eta, *it - theta[j]);
+      if (it != unc.begin()) eta = std::min(eta, theta[j] - *(it - 1));
+      est[q] = (eta > 0.0) ? std::min(rnorm[q], rnorm[q] * rnorm[q] / eta) : rnorm[q];
+      if (!(est[q] <= tol)) {
+        ok[j] = 0;
+        changed = true;
+      }
+    }
+    if (!changed) break;
+  }
+  // walk outward in |theta|: ghosts are skipped, the first other rejection ends the core
+  for (int q = 0; q < n_sel && std::fabs(theta[order[q]]) <= a; ++q) {
+    const int j = order[q];
+    if (ghost[j]) continue;
+    if (!ok[j]) break;
+    res.max_est = std::max(res.max_est, est[q]);
+    res.core_idx.push_back(q);
+  }
+  return res;
+}
+
+// Positions of theta sorted by (|theta|, theta).
+std::vector<int> central_order(const std::vector<double> &theta) {
+  std::vector<int> order(theta.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+    const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
+    return ai < aj || (ai == aj && theta[i] < theta[j]);
+  });
+  return order;
+}
+
 // vecs_out (device, may be null): row s of the D x N block at vecs_out + s * ldvec gets component
 // s of the unit Ritz vector of each returned value, in the order of eigs_out.
 dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, double tol, double norm_est,
@@ -1780,12 +1860,7 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
   hipStream_t s = ctx->stream;
   dacp_status st;
   double t0 = now_ms();
-  std::vector<int> order(r);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
-    const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
-    return ai < aj || (ai == aj && theta[i] < theta[j]);
-  });
+  const std::vector<int> order = central_order(theta);
   const int n_sel = std::min(r, N + std::max(64, N / 8));
   std::vector<double> rnorm(n_sel, INFINITY), phin2(n_sel, 1.0);
   {
@@ -1824,58 +1899,13 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
       }
     }
   }
-  // Acceptance.  The Ritz residual r_j is orthogonal to the whole search space, which holds the
-  // converged neighbours of theta_j, so the quadratic residual bound |theta_j - lambda_j| <=
-  // ||r_j||^2 / eta_j uses eta_j = distance from theta_j to the part of the spectrum the subspace does
-  // not resolve: the nearest unaccepted Ritz value, or the window edge (levels beyond a are not
-  // represented).  Start from the candidates whose residual is below a generous cap, iterate to a
-  // fixed point, then keep the contiguous accepted core around 0 (walk outward in |theta|, stop at
-  // the first rejection).  The estimate reported is min(||r||, ||r||^2 / eta).
-  //
-  // A Ritz value whose residual exceeds ten mean level spacings of the window approximates no
-  // eigenvalue near it (a "ghost" built from weakly represented directions of the overcomplete
-  // basis): it is left out of eta and does not stop the core.  Central levels carry the largest
-  // filter amplitude, so a true level there is never that poorly represented.
-  std::vector<char> ok(r, 0), ghost(r, 0);
-  const double cap = 1e-4 * norm_est;
-  const double ghost_thr = 10.0 * (2.0 * a / n_w);
-  for (int i = 0; i < n_sel; ++i) {
-    ok[order[i]] = rnorm[i] <= cap;
-    ghost[order[i]] = rnorm[i] > ghost_thr;
-  }
-  int n_ghost = 0;
-  for (int i = 0; i < n_sel; ++i) n_ghost += ghost[order[i]];
-  std::vector<double> est(n_sel, INFINITY);
-  for (int iter = 0; iter < 8; ++iter) {
-    std::vector<double> unc;  // sorted Ritz values not (or no longer) accepted, ghosts excluded
-    for (int i = 0; i < r; ++i)
-      if (!ok[i] && !ghost[i]) unc.push_back(theta[i]);
-    bool changed = false;
-    for (int q = 0; q < n_sel; ++q) {
-      const int j = order[q];
-      if (!ok[j]) continue;
-      double eta = a - std::fabs(theta[j]);
-      auto it = std::lower_bound(unc.begin(), unc.end(), theta[j]);
-      if (it != unc.end()) eta = std::min(eta, *it - theta[j]);
-      if (it != unc.begin()) eta = std::min(eta, theta[j] - *(it - 1));
-      est[q] = (eta > 0.0) ? std::min(rnorm[q], rnorm[q] * rnorm[q] / eta) : rnorm[q];
-      if (!(est[q] <= tol)) {
-        ok[j] = 0;
-        changed = true;
-      }
-    }
-    if (!changed) break;
-  }
-  // walk outward in |theta|: ghosts are skipped, the first other rejection ends the core
-  std::vector<int> core_idx;  // positions q (into order) of the accepted core
-  double max_est = 0.0;
-  for (int q = 0; q < n_sel && std::fabs(theta[order[q]]) <= a; ++q) {
-    const int j = order[q];
-    if (ghost[j]) continue;
-    if (!ok[j]) break;
-    max_est = std::max(max_est, est[q]);
-    core_idx.push_back(q);
-  }
+  // acceptance (the rule is described at accept_rule)
+  const AcceptResult ar = accept_rule(theta, order, n_sel, rnorm, a, n_w, tol, norm_est);
+  const std::vector<char> &ok = ar.ok, &ghost = ar.ghost;
+  const std::vector<double> &est = ar.est;
+  const std::vector<int> &core_idx = ar.core_idx;
+  const double max_est = ar.max_est;
+  const int n_ghost = ar.n_ghost;
   const int core = static_cast<int>(core_idx.size());
   if (verbose()) {
     int shown = 0;
@@ -2112,6 +2142,24 @@ dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_
     const std::vector<int64_t> ks = sample_orders(p.a_r, p.n);
     for (int i = 0; i < std::min(max_samples, p.n); ++i) k_samples[i] = ks[i];
   }
+  return DACP_OK;
+}
+
+dacp_status dacp_accept_rule(int r, const double *theta, int n_sel, const double *rnorm, double a, double n_w,
+                             double tol, double norm_est, int *core_out, int *core_pos, double *est_out,
+                             int *n_ghost_out) {
+  if (r < 0 || n_sel < 0 || n_sel > r || (r > 0 && !theta) || (n_sel > 0 && !rnorm) || !core_out ||
+      !(a > 0.0) || !(n_w > 0.0))
+    return DACP_E_INVALID;
+  const std::vector<double> th(theta, theta + r);
+  for (int i = 0; i + 1 < r; ++i)
+    if (!(th[i + 1] >= th[i])) return DACP_E_INVALID;
+  const std::vector<double> rn(rnorm, rnorm + n_sel);
+  const AcceptResult res = accept_rule(th, central_order(th), n_sel, rn, a, n_w, tol, norm_est);
+  *core_out = static_cast<int>(res.core_idx.size());
+  if (core_pos) std::copy(res.core_idx.begin(), res.core_idx.end(), core_pos);
+  if (est_out) std::copy(res.est.begin(), res.est.end(), est_out);
+  if (n_ghost_out) *n_ghost_out = res.n_ghost;
   return DACP_OK;
 }
 

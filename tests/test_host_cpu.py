@@ -109,3 +109,31 @@ def test_plan_matches_the_oracle_parameter_rules():
         binding.dacp_plan(D, D + 1, e_b, mu)
     with pytest.raises(ValueError):
         binding.dacp_plan(D, N, 0.0, mu)
+
+
+def test_accept_rule_through_the_abi_matches_the_oracle():
+    """The library's acceptance rule (host code, no device) against the oracle's plain version on
+    random Ritz values and residuals with ghosts, cascades and values beyond the window: the same
+    core, the same estimates bit for bit, the same ghost count."""
+    import numpy as np
+
+    from oracle import acceptance
+
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        r = int(rng.integers(1, 300))
+        theta = np.sort(rng.uniform(-1.0, 1.0, r))
+        if trial % 5 == 0 and r > 3:
+            theta[r // 2] = theta[r // 2 - 1]  # a repeated value
+        n_sel = int(rng.integers(0, r + 1))
+        rn = 10.0 ** rng.uniform(-14, -3, n_sel)
+        rn[rng.uniform(size=n_sel) < 0.05] = 50.0  # ghosts
+        a, n_w, tol = float(rng.uniform(0.2, 0.9)), float(rng.uniform(20, 400)), 10.0 ** rng.uniform(-11, -7)
+        pos, est, ng = binding.dacp_accept_rule(theta, rn, a, n_w, tol, 1.0)
+        core_ref, est_ref, ng_ref = acceptance.accept(theta, rn, a, n_w, tol, 1.0)
+        assert list(pos) == core_ref and ng == ng_ref
+        assert np.array_equal(est, np.array(est_ref, dtype=np.float64))
+    with pytest.raises(ValueError):
+        binding.dacp_accept_rule([0.2, 0.1], [1e-12], 0.5, 10.0, 1e-10, 1.0)  # unsorted
+    with pytest.raises(ValueError):
+        binding.dacp_accept_rule([0.1, 0.2], [1e-12] * 3, 0.5, 10.0, 1e-10, 1.0)  # n_sel > r

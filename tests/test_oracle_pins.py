@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import _native, central, chebyshev, hamiltonian, jordan_wigner, levels, philox, spectral, subspace
+from oracle import _native, acceptance, central, chebyshev, hamiltonian, jordan_wigner, levels, philox, spectral, subspace
 from paper_2011_02107_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -505,3 +505,27 @@ def test_spacing_ratios_goe_level_repulsion():
     r, mean = levels.spacing_ratios(w[n // 4: 3 * n // 4])
     assert abs(mean - 0.5307) < 0.03
     assert np.mean(r < 0.1) < 0.05
+
+
+# ------------------------------------------------------------------ acceptance rule
+
+
+def test_acceptance_worked_cases():
+    """Hand-checked cases of the acceptance rule (quadratic residual bound, ghosts, contiguous core)."""
+    theta = [-0.3, -0.1, 0.05, 0.2, 0.6]  # (|theta|, theta) order: 0.05, -0.1, 0.2, -0.3, 0.6
+    a, n_w, tol = 0.5, 4.0, 1e-10  # ghost threshold 10 * 2a / n_w = 2.5; start cap 1e-4
+    # all converged: the core is the four values inside a; eta is the distance to the edge
+    core, est, ng = acceptance.accept(theta, [1e-12] * 5, a, n_w, tol, 1.0)
+    assert core == [0, 1, 2, 3] and ng == 0
+    assert est[0] == pytest.approx(1e-24 / 0.45, rel=1e-15)
+    assert est[4] == 1e-12  # beyond the window: eta <= 0, the plain residual
+    # -0.1 unconverged: it ends the core and bounds its neighbour's eta (0.05 - (-0.1))
+    core, est, ng = acceptance.accept(theta, [1e-12, 1e-3, 1e-12, 1e-12, 1e-12], a, n_w, tol, 1.0)
+    assert core == [0] and est[0] == pytest.approx(1e-24 / 0.15, rel=1e-14) and math.isinf(est[1])
+    # -0.1 a ghost: skipped by the core and left out of eta
+    core, est, ng = acceptance.accept(theta, [1e-12, 3.0, 1e-12, 1e-12, 1e-12], a, n_w, tol, 1.0)
+    assert core == [0, 2, 3] and ng == 1 and est[0] == pytest.approx(1e-24 / 0.45, rel=1e-15)
+    # cascade: 0.002 fails (4e-10 / 0.498 > tol), then 0 fails against it (1e-12 / 0.002 = 5e-10)
+    core, est, ng = acceptance.accept([0.0, 0.002, 0.3], [1e-6, 2e-5, 1e-12], 0.5, 4.0, 1e-10, 1.0)
+    assert core == [] and est[0] == pytest.approx(5e-10, rel=1e-12)
+    assert est[2] == pytest.approx(1e-24 / 0.2, rel=1e-12)
