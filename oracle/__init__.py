@@ -16,4 +16,6 @@ Modules:
   philox         -- Philox4x32-10 + Box-Muller start states
   central        -- the plain definition: dense full diagonalisation + selection
   mlp            -- the learned window's regression network: forward, backward, Adam
+  acceptance     -- the acceptance rule for computed Ritz pairs (quadratic residual bound)
+  levels         -- gap ratios of consecutive level spacings
 """
