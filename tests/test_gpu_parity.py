@@ -726,6 +726,34 @@ def test_central_eigpairs_vectors_against_dense_eigenvectors(ctx):
         _check_eigvecs(Xp[:, :N], eigs, errs, Hd, norm, rep["a"])
 
 
+def test_central_eigpairs_chain_L16_properties(ctx):
+    """At L = 16, N = 1000 (no dense oracle), in the benchmark's tuned options: the returned vectors,
+    checked with the oracle's CPU matrix-free apply, are unit and mutually orthogonal up to the
+    S cut-off's rounding, their Rayleigh quotients are the returned values and their residuals obey
+    the acceptance rule's bound ||r|| <= sqrt(1e-10 ||H|| a) (||H|| <= sum |c|)."""
+    L, N = 16, 1000
+    terms = inputs.ising_chain(L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    opts = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
+                          fp64_tail_frac=0.3)
+    vecs = torch.empty((1 << L, N), dtype=torch.float64, device=DEV)
+    eigs, errs, rep, st = B.dacp_central_eigpairs(ctx, ham, N, vecs, opts)
+    assert len(eigs) == N and np.all(np.diff(eigs) >= 0)
+    X = host(vecs)
+    del vecs
+    bound = hamiltonian.sum_abs_coeff(terms)
+    HX = hamiltonian.apply_h(L, terms, X)
+    nrm2 = np.einsum("si,si->i", X, X)
+    assert np.abs(np.sqrt(nrm2) - 1.0).max() < 1e-9
+    G = X.T @ X
+    np.fill_diagonal(G, 0.0)
+    assert np.abs(G).max() < 1e-8
+    assert np.abs(np.einsum("si,si->i", X, HX) / nrm2 - eigs).max() <= 1e-12 * bound
+    rn = np.linalg.norm(HX - X * eigs[None, :], axis=0)
+    assert rn.max() <= 1.01 * math.sqrt(1.01e-10 * bound * rep["a"]) + 1e-13 * bound
+    assert np.all(errs <= rn * (1 + 1e-6) + 1e-13 * bound)
+
+
 def test_central_eigpairs_rejects_bad_stride(ctx):
     L, N = 10, 20
     ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L))
