@@ -12,6 +12,8 @@ import os
 import sys
 import time
 
+T_PROCESS_START = time.perf_counter()
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -54,7 +56,13 @@ def parse():
     ap.add_argument("--eigvecs", action="store_true",
                     help="time dacp_central_eigpairs (eigenvalues and unit eigenvectors) instead of dacp_central_eigs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--cpu-sample-s", type=float, default=12.0,
+                    help="seconds of oracle applies timed for the CPU baseline (at least one apply)")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="wall-time budget of the whole run from process start, seconds: at most one warm-up "
+                         "call, then as many timed calls as fit (up to --steps), one plain FP64 call and the CPU "
+                         "baseline; the JSON line reports the number of calls actually timed")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison call (tuned mode)")
     ap.add_argument("--profile-gemm", action="store_true",
                     help="run only the Gram product C = V^T V (V of 2^20 x 4096, FP64 MFMA) three times and "
                          "print one JSON line (for MFMA counter runs)")
@@ -91,11 +99,45 @@ def opts_for(args, wl):
     return o
 
 
-def cpu_baseline(wl, rep, steps):
-    """The oracle's matrix-free apply timed on a bounded sample of the same
-    workload (`steps` applies on the L, b block), scaled to the run's total
-    apply count (2K filter + evolution steps x column groups); projection and
-    the subspace solve are not counted (so the CPU figure is optimistic)."""
+def progress(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def host_info():
+    """Host cores, CPU model and memory of the machine the benchmark runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem_gb = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model, "mem_gb": mem_gb}
+
+
+def cpu_baseline(wl, rep, sample_s, threads):
+    """The oracle's matrix-free apply (numpy, FP64) on the workload's L x b block, spread over
+    `threads` host threads by column slices (numpy releases the interpreter lock inside its array
+    operations), repeated for about `sample_s` seconds and scaled to the run's total apply count
+    (2K filter applies + the evolution steps).  Projection and the subspace solve are
+    not counted, so the CPU figure is optimistic."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     from oracle import hamiltonian
@@ -104,19 +146,36 @@ def cpu_baseline(wl, rep, steps):
     L, b = wl["L"], rep["b"]
     terms = inputs.ising_chain(L)
     X = np.random.default_rng(0).standard_normal((1 << L, b))
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        X = hamiltonian.apply_h(L, terms, X) / 40.0
-    dt = (time.perf_counter() - t0) / steps
+    threads = max(1, min(threads, b))
+    bounds = [(b * t // threads, b * (t + 1) // threads) for t in range(threads)]
+
+    def one(c):
+        c0, c1 = c
+        return hamiltonian.apply_h(L, terms, X[:, c0:c1])
+
+    n = 0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        t0 = time.perf_counter()
+        while True:
+            parts = list(ex.map(one, bounds))
+            n += 1
+            if time.perf_counter() - t0 >= sample_s or n >= 64:
+                break
+        dt = (time.perf_counter() - t0) / n
+    del parts
+    # evol_steps counts the steps of one column group; every group takes as many, so the evolution
+    # is evol_steps applies of the whole b-column block, as one oracle apply here
     applies = 2 * rep["K"] + rep["evol_steps"]
     total_s = applies * dt
     return {
         "value": wl["N"] / total_s,
         "unit": "eigenvalues/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{steps} oracle matrix-free applies (numpy, L={L}, b={b}) at {dt:.2f} s each, "
-        f"scaled to {applies} applies of the run; projection and subspace solve excluded",
+        "sample": f"{n} oracle matrix-free applies (numpy FP64, L={L}, b={b} split over {threads} threads by "
+        f"columns) at {dt:.3f} s each, scaled to the run's {applies} applies of all b columns "
+        f"(2K filter + evolution steps); projection and subspace solve excluded",
+        "host": host_info(),
     }
 
 
@@ -401,18 +460,41 @@ def main():
             return B.dacp_central_eigpairs(ctx, ham, N, vecs, opts)
         return B.dacp_central_eigs(ctx, ham, N, opts)
 
-    for _ in range(args.warmup):
+    def elapsed():
+        return time.perf_counter() - T_PROCESS_START
+
+    # Wall budget.  One call at L = 20 takes about a minute, so `--steps` and `--warmup` are caps:
+    # at most one untimed warm-up call, then timed calls while the next one still fits, keeping
+    # room for the plain FP64 call (about 1.4 tuned calls) and the CPU baseline.
+    t_call = None
+    for i in range(min(args.warmup, 1)):
+        progress(f"warm-up call {i + 1} at {elapsed():.0f} s")
+        t0 = time.perf_counter()
         call()
+        t_call = time.perf_counter() - t0
+        progress(f"warm-up call done: {t_call:.1f} s")
+    want_plain = args.mode == "tuned" and not args.no_plain
+    cpu_s = 0.0 if args.no_cpu_baseline else args.cpu_sample_s + 15.0
+
+    def reserve(tc):
+        return (1.5 * tc if want_plain else 0.0) + cpu_s + 10.0
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
     n_ok = 0
-    for _ in range(args.steps):
+    while len(reps) < max(1, args.steps):
         eigs, errs, rep, st = call()
         reps.append(rep)
         n_ok += len(eigs)
+        tc = (time.perf_counter() - t0) / len(reps)
+        progress(f"timed call {len(reps)}: {len(eigs)} values, {tc:.1f} s per call so far, elapsed {elapsed():.0f} s")
+        if elapsed() + tc + reserve(tc) > args.budget_s:
+            break
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    steps_timed = len(reps)
+    t_call = dt / steps_timed
     rep = reps[-1]
     D = 1 << L
     g = rep["evol_group"]
@@ -432,9 +514,9 @@ def main():
         "value": n_ok / dt,
         "unit": "eigenvalues/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
+        "steps": steps_timed,
+        "warmup": min(args.warmup, 1),
+        "ms_per_step": dt * 1e3 / steps_timed,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -483,8 +565,31 @@ def main():
         counted = groups * (fb["fp32"] * (K - k64) + fb["fp64"] * k64)
         out["filter_counted"] = {"bytes": counted, "GBps": counted / (rep["t_filter_ms"] * 1e-3) / 1e9,
                                  "bytes_per_order_per_group": fb}
+    out["budget"] = {"requested_steps": args.steps, "requested_warmup": args.warmup, "budget_s": args.budget_s}
+    if want_plain:
+        if elapsed() + 1.5 * t_call + cpu_s < args.budget_s:
+            progress(f"plain FP64 call at {elapsed():.0f} s")
+            plain_args = argparse.Namespace(**{**vars(args), "mode": "plain"})
+            popts = opts_for(plain_args, wl)
+            t0 = time.perf_counter()
+            pe, _, prep, pst = B.dacp_central_eigs(ctx, ham, N, popts)
+            tp = time.perf_counter() - t0
+            out["plain"] = {
+                "value": len(pe) / tp, "unit": "eigenvalues/s", "s": tp, "dtype": "f64",
+                "options": "FP64 filter, kfac 18, window 2.2, basis 1.5, no autotune of the options",
+                "K": prep["K"], "m": prep["m"], "rank": prep["rank"], "evol_steps": prep["evol_steps"],
+                "stages_ms": {k: prep[k] for k in ("t_bound_ms", "t_filter_ms", "t_evol_ms", "t_project_ms",
+                                                   "t_gep_ms", "t_accept_ms", "t_total_ms")},
+                "tuned_over_plain": (n_ok / dt) / (len(pe) / tp),
+                "max_abs_diff_to_tuned": float(np.abs(np.sort(pe) - np.sort(eigs)).max()),
+            }
+            progress(f"plain call done: {tp:.1f} s")
+        else:
+            out["plain"] = {"skipped": f"no room in the {args.budget_s:.0f} s budget"}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, rep, args.cpu_sample_steps)
+        progress(f"CPU baseline at {elapsed():.0f} s")
+        out["cpu_baseline"] = cpu_baseline(wl, rep, args.cpu_sample_s, min(16, host_info()["usable_cpus"] or 1))
+    out["wall_s"] = elapsed()
     print(json.dumps(out), flush=True)
 
 

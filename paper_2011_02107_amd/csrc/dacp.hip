@@ -116,10 +116,15 @@ hipError_t pool_alloc(size_t nbytes, hipStream_t s, int device, void **p, size_t
       const CachedBlock b = it->second;
       bc.blocks.erase(it);
       bc.cached -= c;
+      // The wait is queued before the event goes back to `spare`, with the lock held: a
+      // pool_free on another thread can take the event from `spare` and record it on its own
+      // stream only after this wait has captured the freeing stream's point.  (Queued after the
+      // unlock, the wait could see that later record and hand the block out while its previous
+      // stream still uses it; the record and the wait would also touch one event from two
+      // threads at once.)
+      const hipError_t e = hipStreamWaitEvent(s, b.ready, 0);
       bc.spare.push_back(b.ready);
       lk.unlock();
-      // the wait takes the event's state now; the event may be recorded again afterwards
-      const hipError_t e = hipStreamWaitEvent(s, b.ready, 0);
       if (e != hipSuccess) {
         (void)hipFree(b.p);  // synchronises the device, so its last use is over
         return e;
@@ -189,17 +194,20 @@ dacp_status hip_err(dacp_ctx ctx, hipError_t e, const char *what) {
   return set_err(ctx, st, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Both copies are queued on the context's own stream and waited for there: a blocking copy on
+// the null stream would also order against every other blocking stream of the device, which
+// serialises host threads that each drive a stream of their own.
 dacp_status to_host(dacp_ctx ctx, void *host, const void *dev, size_t bytes) {
   if (bytes == 0) return DACP_OK;
+  DACP_HIP(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
   DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  DACP_HIP(ctx, hipMemcpy(host, dev, bytes, hipMemcpyDeviceToHost));
   return DACP_OK;
 }
 
 dacp_status to_device(dacp_ctx ctx, void *dev, const void *host, size_t bytes) {
   if (bytes == 0) return DACP_OK;
-  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  DACP_HIP(ctx, hipMemcpy(dev, host, bytes, hipMemcpyHostToDevice));
+  DACP_HIP(ctx, hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // `host` may be released on return
   return DACP_OK;
 }
 

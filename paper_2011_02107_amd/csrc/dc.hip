@@ -206,10 +206,13 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
   // eigenvectors, component m of the second half's.
   std::vector<double> z(n);
   {
+    // both strided columns gathered into the merge's own z buffer, then one copy to the host
     std::vector<double> col(n);
-    DACP_TRY(to_host_2d(ctx, col.data(), W.Z + static_cast<int64_t>(lo) * W.n + (m - 1), W.n, n1, 1));
-    DACP_TRY(to_host_2d(ctx, col.data() + n1, W.Z + static_cast<int64_t>(m) * W.n + m, W.n, n - n1, 1));
-    DACP_HIP(ctx, hipStreamSynchronize(st));
+    DACP_HIP(ctx, launch_copy_cols(W.Z + static_cast<int64_t>(lo) * W.n + (m - 1), W.n, W.dz.as<double>(), 1, n1, 1,
+                                   st));
+    DACP_HIP(ctx, launch_copy_cols(W.Z + static_cast<int64_t>(m) * W.n + m, W.n, W.dz.as<double>() + n1, 1, n - n1, 1,
+                                   st));
+    DACP_TRY(to_host(ctx, col.data(), W.dz.p, static_cast<size_t>(n) * sizeof(double)));
     for (int i = 0; i < n1; ++i) z[i] = sgn * col[i];
     for (int i = n1; i < n; ++i) z[i] = col[i];
   }
