@@ -281,7 +281,7 @@ typedef struct {
   double evol_kernel_ms;    /* HIP-event time of the evolution launches only        */
   double max_err_est;       /* largest accepted error estimate                      */
   int evol_group;           /* column-group width the evolution ran with            */
-  int n_ghost;              /* candidates with residual above ten level spacings    */
+  int n_ghost;              /* candidates whose residual reaches the window edge   */
   int model_used;           /* dacp_central_eigs_learned: 1 = bound and window from the network */
   int model_fallback;       /* 1 = the network's window failed and Lanczos / KPM redid the call */
 } dacp_report;
@@ -290,12 +290,11 @@ typedef struct {
 void dacp_default_opts(dacp_opts *opts);
 
 /* The N eigenvalues of H nearest 0, ascending (host eigs_out[N]); err_out
- * (host, may be NULL) gets the residual error estimate of each:
- * min(||r||, ||r||^2 / eta) with r = H phi - theta phi for the Ritz vector phi
- * and eta the distance from theta to the nearest unaccepted Ritz value or to
- * the window edge (quadratic residual bound; the residual is orthogonal to the
- * converged neighbours, which lie in the search space); n_out gets N on success
- * or, on DACP_E_WINDOW, the number accepted.  report may be NULL. */
+ * (host, may be NULL) gets the residual error estimate of each (the estimate of
+ * dacp_accept_rule: the residual norm, or the block quadratic residual bound of a
+ * cluster of neighbouring Ritz values over its distance to the rest of the
+ * spectrum, whichever is smaller); n_out gets N on success or, on DACP_E_WINDOW,
+ * the number accepted.  report may be NULL. */
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report);
 
@@ -349,25 +348,29 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
 dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_mu, const dacp_opts *opts,
                       int attempt, double *fout, int *iout, int64_t *k_samples, int max_samples);
 
-/* The acceptance rule of dacp_central_eigs (Sec. II.C residual check, with the quadratic residual
- * bound), host code with no device or context.  Candidates are the first n_sel Ritz values in the
- * order of (|theta|, theta).  A candidate starts accepted when its residual is at most
- * 1e-4 norm_est, and is a "ghost" when its residual exceeds ten mean level spacings 20 a / n_w.
- * Its estimate is min(||r||, ||r||^2 / eta), eta being the distance to the window edge a or to the
- * nearest Ritz value that is neither accepted nor a ghost.  Candidates whose estimate exceeds tol
- * are dropped until nothing changes (at most 8 rounds).  The core is then the run of accepted
- * candidates with |theta| <= a, walking outward from 0, skipping ghosts and stopping at the first
- * other rejection.
+/* The acceptance rule of dacp_central_eigs (Sec. II.C: the residual of a Ritz pair bounds its error;
+ * here with the quadratic form of that bound), host code with no device or context.  Candidates are
+ * the first n_sel Ritz values in the order of (|theta|, theta).
+ *   - A candidate is a "ghost" when its residual is at least a - |theta|: a unit vector made only of
+ *     eigenvectors outside the window [-a, a] has at least that residual, so a ghost may approximate
+ *     no level.  Below it, Weyl's bound places a level within the residual of theta, inside [-a, a].
+ *   - Estimate: the smaller of ||r|| and the block quadratic residual bound sum_C ||r||^2 / delta_C,
+ *     minimised over every run C of at most 8 consecutive non-ghost candidates (in ascending theta)
+ *     that contains the candidate; delta_C is the distance from C to the nearest non-ghost Ritz value
+ *     outside C (less that value's own residual when it is a candidate) or to the window edge.
+ *     Accepted: estimate <= tol.
+ *   - The core walks the candidates outward in |theta| while |theta| <= a; the first ghost or
+ *     unaccepted candidate ends it.
  *   theta[r]        host, ascending Ritz values
- *   rnorm[n_sel]    host, residual norms in the (|theta|, theta) order
+ *   rnorm[n_sel]    host, residual norms of the unit Ritz vectors, in the (|theta|, theta) order
+ *   a, tol          window half-width (> 0) and accepted error (>= 0)
  *   core_out        host: the core's size
  *   core_pos[n_sel] host, may be NULL: the core's positions in that order
- *   est_out[n_sel]  host, may be NULL: estimates (infinite where a candidate never started accepted)
+ *   est_out[n_sel]  host, may be NULL: estimates (infinite for a ghost)
  *   n_ghost_out     host, may be NULL: the number of ghosts
- * Returns DACP_E_INVALID for n_sel outside [0, r], unsorted theta, a <= 0, n_w <= 0 or null inputs. */
-dacp_status dacp_accept_rule(int r, const double *theta, int n_sel, const double *rnorm, double a, double n_w,
-                             double tol, double norm_est, int *core_out, int *core_pos, double *est_out,
-                             int *n_ghost_out);
+ * Returns DACP_E_INVALID for n_sel outside [0, r], unsorted theta, a <= 0, tol < 0 or null inputs. */
+dacp_status dacp_accept_rule(int r, const double *theta, int n_sel, const double *rnorm, double a, double tol,
+                             int *core_out, int *core_pos, double *est_out, int *n_ghost_out);
 
 /* Level statistics of a computed spectrum (the paper's motivation, Sec. I): the gap ratios
  * r_i = min(s_i, s_{i+1}) / max(s_i, s_{i+1}) of consecutive spacings s_i = eigs[i+1] - eigs[i].

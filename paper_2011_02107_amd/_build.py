@@ -8,6 +8,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdacp.so")
 SOURCES = ["kernels.hip", "gemm.hip", "eig.hip", "dc.hip", "batch.hip", "beig.hip", "mlp.hip", "dacp.hip"]
+# host-only sources (no device code): compiled by the host C++ compiler
+HOST_SOURCES = ["host_rules.cpp"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 FLAGS = [
     "-O3",
     "-std=c++17",
@@ -28,8 +31,12 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
 
     def compile_one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        if src.endswith(".cpp"):
+            obj = os.path.join(BUILD, src.replace(".cpp", ".host.o"))
+            cmd = [os.environ.get("CXX", "g++"), *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        else:
+            obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+            cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -38,7 +45,7 @@ def build(verbose=False):
         return obj
 
     with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+        objs = list(ex.map(compile_one, SOURCES + HOST_SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -153,8 +153,7 @@ SIGNATURES = {
     "dacp_spacing_ratios": (ctypes.c_int, [_dp, ctypes.c_int, _dp, _dp]),
     "dacp_accept_rule": (
         ctypes.c_int,
-        [ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-         _ip, _ip, _dp, _ip],
+        [ctypes.c_int, _dp, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, _ip, _ip, _dp, _ip],
     ),
     "dacp_plan": (
         ctypes.c_int,
@@ -443,7 +442,7 @@ def dacp_plan(D, N, e_bound, mu=None, opts=None, attempt=0, max_samples=1 << 16)
             "m": int(iout[3]), "k_samples": ks[:min(n, max_samples)].copy()}
 
 
-def dacp_accept_rule(theta, rnorm, a, n_w, tol, norm_est):
+def dacp_accept_rule(theta, rnorm, a, tol):
     """(core positions in the (|theta|, theta) order, estimates, ghost count); host code."""
     th = np.ascontiguousarray(theta, dtype=np.float64)
     rn = np.ascontiguousarray(rnorm, dtype=np.float64)
@@ -451,9 +450,8 @@ def dacp_accept_rule(theta, rnorm, a, n_w, tol, norm_est):
     pos = np.zeros(max(len(rn), 1), dtype=np.int32)
     est = np.zeros(max(len(rn), 1))
     ng = ctypes.c_int()
-    st = load_library().dacp_accept_rule(int(len(th)), _f64(th), int(len(rn)), _f64(rn), float(a), float(n_w),
-                                         float(tol), float(norm_est), ctypes.byref(core),
-                                         pos.ctypes.data_as(_ip), _f64(est), ctypes.byref(ng))
+    st = load_library().dacp_accept_rule(int(len(th)), _f64(th), int(len(rn)), _f64(rn), float(a), float(tol),
+                                         ctypes.byref(core), pos.ctypes.data_as(_ip), _f64(est), ctypes.byref(ng))
     if st != 0:
         raise ValueError(f"dacp_accept_rule: invalid arguments (status {st})")
     return pos[:core.value].copy(), est[:len(rn)].copy(), ng.value

@@ -12,6 +12,7 @@
 #include <functional>
 #include <tuple>
 #include <map>
+#include <new>
 #include <mutex>
 #include <set>
 #include <numeric>
@@ -20,6 +21,8 @@
 #include <utility>
 #include <vector>
 
+#include "block_cache.h"
+#include "host_rules.h"
 #include "internal.h"
 
 using dacp::DevBuf;
@@ -29,6 +32,14 @@ using dacp::to_device;
 using dacp::to_host;
 using dacp::BatchCol;
 using dacp::BatchSpec;
+using dacp::rules::AcceptResult;
+using dacp::rules::Plan;
+using dacp::rules::accept_rule;
+using dacp::rules::central_order;
+using dacp::rules::kpm_count;
+using dacp::rules::make_plan;
+using dacp::rules::sample_orders;
+using dacp::rules::window_for_count;
 
 namespace dacp {
 
@@ -70,29 +81,31 @@ AllocState &alloc_state_tl() {
 }
 
 namespace {
-struct CachedBlock {
-  void *p;
-  hipEvent_t ready;  // recorded on the freeing stream
+// The HIP runtime calls of the block cache (block_cache.h).
+struct HipRt {
+  using Stream = hipStream_t;
+  using Event = hipEvent_t;
+  using Err = hipError_t;
+  static constexpr hipError_t ok = hipSuccess;
+  static constexpr hipError_t oom = hipErrorOutOfMemory;
+  hipError_t malloc(void **p, size_t n) {
+    const hipError_t e = hipMalloc(p, n);
+    if (e == hipErrorOutOfMemory) (void)hipGetLastError();  // clear it before the retry
+    return e;
+  }
+  void free(void *p) { (void)hipFree(p); }
+  hipError_t event_create(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableTiming); }
+  hipError_t record(hipEvent_t e, hipStream_t s) { return hipEventRecord(e, s); }
+  hipError_t wait(hipStream_t s, hipEvent_t e) { return hipStreamWaitEvent(s, e, 0); }
 };
 
-struct BlockCache {
-  std::mutex mu;
-  std::multimap<size_t, CachedBlock> blocks;  // by size class
-  std::vector<hipEvent_t> spare;              // events not attached to a block
-  size_t cached = 0;
-};
-
-BlockCache &block_cache(int device) {
-  static BlockCache caches[64];
+BlockCacheT<HipRt> &block_cache(int device) {
+  static BlockCacheT<HipRt> *caches = [] {
+    auto *c = static_cast<BlockCacheT<HipRt> *>(::operator new(64 * sizeof(BlockCacheT<HipRt>)));
+    for (int d = 0; d < 64; ++d) new (&c[d]) BlockCacheT<HipRt>(kBlockCacheBytes);
+    return c;
+  }();
   return caches[device & 63];
-}
-
-// Size class: n rounded up to a multiple of a quarter of its leading power of two (256 B at least).
-size_t size_class(size_t n) {
-  size_t top = 256;
-  while (top * 2 <= n) top *= 2;
-  const size_t step = std::max<size_t>(256, top / 4);
-  return (n + step - 1) / step * step;
 }
 }  // namespace
 
@@ -106,82 +119,13 @@ AllocStream::AllocStream(hipStream_t s, int device) : prev(alloc_state_tl()) {
 AllocStream::~AllocStream() { alloc_state_tl() = prev; }
 
 hipError_t pool_alloc(size_t nbytes, hipStream_t s, int device, void **p, size_t *cls) {
-  const size_t c = size_class(nbytes);
-  *cls = c;
-  BlockCache &bc = block_cache(device);
-  {
-    std::unique_lock<std::mutex> lk(bc.mu);
-    auto it = bc.blocks.find(c);
-    if (it != bc.blocks.end()) {
-      const CachedBlock b = it->second;
-      bc.blocks.erase(it);
-      bc.cached -= c;
-      // The wait is queued before the event goes back to `spare`, with the lock held: a
-      // pool_free on another thread can take the event from `spare` and record it on its own
-      // stream only after this wait has captured the freeing stream's point.  (Queued after the
-      // unlock, the wait could see that later record and hand the block out while its previous
-      // stream still uses it; the record and the wait would also touch one event from two
-      // threads at once.)
-      const hipError_t e = hipStreamWaitEvent(s, b.ready, 0);
-      bc.spare.push_back(b.ready);
-      lk.unlock();
-      if (e != hipSuccess) {
-        (void)hipFree(b.p);  // synchronises the device, so its last use is over
-        return e;
-      }
-      *p = b.p;
-      return hipSuccess;
-    }
-  }
-  hipError_t e = hipMalloc(p, c);
-  if (e == hipErrorOutOfMemory) {
-    // hand every cached block of the device back to the runtime, then try once more
-    std::vector<void *> held;
-    {
-      std::lock_guard<std::mutex> lk(bc.mu);
-      for (const auto &kv : bc.blocks) {
-        held.push_back(kv.second.p);
-        bc.spare.push_back(kv.second.ready);
-      }
-      bc.blocks.clear();
-      bc.cached = 0;
-    }
-    if (!held.empty()) {
-      (void)hipGetLastError();
-      for (void *q : held) (void)hipFree(q);
-      e = hipMalloc(p, c);
-    }
-  }
-  return e;
+  HipRt rt;
+  return block_cache(device).alloc(rt, nbytes, s, p, cls);
 }
 
 void pool_free(void *p, size_t cls, int device, hipStream_t s) {
-  BlockCache &bc = block_cache(device);
-  hipEvent_t ev = nullptr;
-  bool keep;
-  {
-    std::lock_guard<std::mutex> lk(bc.mu);
-    keep = bc.cached + cls <= kBlockCacheBytes;
-    if (keep) {
-      bc.cached += cls;  // reserved until the block is filed below or released
-      if (!bc.spare.empty()) {
-        ev = bc.spare.back();
-        bc.spare.pop_back();
-      }
-    }
-  }
-  if (keep && !ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-  if (keep && ev && hipEventRecord(ev, s) == hipSuccess) {
-    std::lock_guard<std::mutex> lk(bc.mu);
-    bc.blocks.insert({cls, CachedBlock{p, ev}});
-    return;
-  }
-  {
-    std::lock_guard<std::mutex> lk(bc.mu);
-    if (keep) bc.cached -= cls;
-    if (ev) bc.spare.push_back(ev);
-  }
-  (void)hipFree(p);
+  HipRt rt;
+  block_cache(device).release(rt, p, cls, s);
 }
 
 dacp_status set_err(dacp_ctx ctx, dacp_status st, const std::string &msg) {
@@ -756,12 +700,6 @@ dacp_status run_filter(dacp_ctx ctx, dacp_ham h, const dacp_filter_params *p, co
 }
 
 // ------------------------------------------------------------- basis core
-std::vector<int64_t> sample_orders(double a_r, int n) {
-  std::vector<int64_t> ks(n);
-  for (int m = 1; m <= n; ++m) ks[m - 1] = 2 * static_cast<int64_t>(std::floor(m * M_PI / (2.0 * a_r)));
-  return ks;
-}
-
 struct EvolStats {
   int64_t steps = 0, launches = 0;
   double kernel_ms = 0.0;
@@ -1326,30 +1264,6 @@ dacp_status run_moments(dacp_ctx ctx, dacp_ham h, double e_bound, int M, int nve
   return DACP_OK;
 }
 
-// Estimated levels in [-a_r E_b, a_r E_b] from Jackson-damped moments (closed-form integrals).
-double kpm_count(const std::vector<double> &mu, int64_t D, double a_r) {
-  const int M = static_cast<int>(mu.size());
-  const double q = M_PI / (M + 1);
-  const double th = std::acos(a_r);
-  double total = 0.0;
-  for (int k = 0; k < M; ++k) {
-    const double g = ((M - k + 1) * std::cos(q * k) + std::sin(q * k) / std::tan(q)) / (M + 1);
-    if (k == 0) total += g * mu[0] * (M_PI - 2.0 * th) / M_PI;
-    else total += 2.0 * g * mu[k] * (std::sin(k * (M_PI - th)) - std::sin(k * th)) / (k * M_PI);
-  }
-  return static_cast<double>(D) * total;
-}
-
-double window_for_count(const std::vector<double> &mu, int64_t D, double count) {
-  double lo = 0.0, hi = 1.0;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (kpm_count(mu, D, mid) >= count) hi = mid;
-    else lo = mid;
-  }
-  return hi;
-}
-
 }  // namespace
 
 // =====================================================================  ABI
@@ -1722,142 +1636,7 @@ dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N
   return DACP_OK;
 }
 
-void dacp_default_opts(dacp_opts *o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->b = 0;
-  o->group = 0;
-  o->kfac = 18.0;
-  o->window_ratio = 2.2;
-  o->basis_ratio = 1.5;
-  o->eps = 1e-12;
-  o->tol_rel = 1e-10;
-  o->lanczos_steps = 80;
-  o->kpm_moments = 256;
-  o->kpm_vectors = 8;
-  o->e_bound = 0.0;
-  o->a = 0.0;
-  o->precision = DACP_F64;
-  o->fp64_tail_frac = 0.2;
-  o->seed = 0;
-  o->max_retries = 1;
-}
-
 namespace {
-// Window, orders and basis size of one attempt (Sec. II.A, II.B, III; readings in the header).
-struct Plan {
-  double n_w, a_r, a;
-  int K, b, n, m;
-};
-
-Plan make_plan(const dacp_opts &o, int64_t D, int N, double e_b, const std::vector<double> &mu, double window_ratio,
-               int attempt) {
-  Plan p;
-  p.n_w = std::min(static_cast<double>(D), std::ceil(window_ratio * N));
-  double a_r = (o.a > 0.0 && attempt == 0) ? o.a / e_b
-                                           : window_for_count(mu.empty() ? std::vector<double>{1.0} : mu, D, p.n_w);
-  if (o.a > 0.0 && attempt > 0) a_r = std::min(0.95, (o.a / e_b) * std::pow(1.5, attempt));
-  p.a_r = std::min(a_r, 0.95);
-  p.a = p.a_r * e_b;
-  const double kfac = o.kfac > 0.0 ? o.kfac : 18.0;
-  p.K = static_cast<int>(std::ceil(kfac / p.a_r));
-  p.b = o.b;
-  if (p.b <= 0) {
-    p.b = 4;
-    while (p.b < 64 && p.b * 16 <= p.n_w) p.b *= 2;
-  }
-  const double basis_ratio = o.basis_ratio > 0.0 ? o.basis_ratio : 1.5;
-  p.n = std::max(1, static_cast<int>(std::ceil((basis_ratio * p.n_w / p.b - 1.0) / 2.0)));
-  p.m = p.b * (2 * p.n + 1);
-  return p;
-}
-
-// Projection (Sec. II.C), subspace solve (App. C) and acceptance (Sec. II.C residual check) for
-// one realisation whose basis V (D x m, row stride m) is built.  `accepted` gets the size of the
-// contiguous accepted core; when it reaches N the N values and their estimates are written.
-// Acceptance (Sec. II.C residual check) of one realisation: Ritz vectors V B for the candidates by
-// |theta|, their residuals, the quadratic residual bound and the contiguous core.  theta ascending
-// (r values), bc the rows of B^T (r x m).
-// The acceptance rule on the host.  theta: the r Ritz values, ascending; order: positions in
-// theta sorted by (|theta|, theta); rnorm[q]: residual norm of the Ritz vector of theta[order[q]]
-// for the first n_sel positions.  The Ritz residual is orthogonal to the whole search space, which
-// holds the converged neighbours of theta_j, so the quadratic residual bound |theta_j - lambda_j|
-// <= ||r_j||^2 / eta_j uses eta_j = distance from theta_j to the part of the spectrum the subspace
-// does not resolve: the nearest unaccepted Ritz value, or the window edge (levels beyond a are not
-// represented).  Start from the candidates whose residual is below a generous cap, iterate to a
-// fixed point, then keep the contiguous accepted core around 0 (walk outward in |theta|, stop at
-// the first rejection).  The estimate is min(||r||, ||r||^2 / eta).
-//
-// A Ritz value whose residual exceeds ten mean level spacings of the window approximates no
-// eigenvalue near it (a "ghost" built from weakly represented directions of the overcomplete
-// basis): it is left out of eta and does not stop the core.  Central levels carry the largest
-// filter amplitude, so a true level there is never that poorly represented.
-struct AcceptResult {
-  std::vector<char> ok, ghost;  // per Ritz value
-  std::vector<double> est;      // per position q < n_sel (INFINITY where never accepted)
-  std::vector<int> core_idx;    // positions q of the contiguous core, walking outward
-  double max_est = 0.0;
-  int n_ghost = 0;
-};
-
-AcceptResult accept_rule(const std::vector<double> &theta, const std::vector<int> &order, int n_sel,
-                         const std::vector<double> &rnorm, double a, double n_w, double tol, double norm_est) {
-  const int r = static_cast<int>(theta.size());
-  AcceptResult res;
-  std::vector<char> &ok = res.ok, &ghost = res.ghost;
-  ok.assign(r, 0);
-  ghost.assign(r, 0);
-  const double cap = 1e-4 * norm_est;
-  const double ghost_thr = 10.0 * (2.0 * a / n_w);
-  for (int i = 0; i < n_sel; ++i) {
-    ok[order[i]] = rnorm[i] <= cap;
-    ghost[order[i]] = rnorm[i] > ghost_thr;
-  }
-  for (int i = 0; i < n_sel; ++i) res.n_ghost += ghost[order[i]];
-  std::vector<double> &est = res.est;
-  est.assign(n_sel, INFINITY);
-  for (int iter = 0; iter < 8; ++iter) {
-    std::vector<double> unc;  // sorted Ritz values not (or no longer) accepted, ghosts excluded
-    for (int i = 0; i < r; ++i)
-      if (!ok[i] && !ghost[i]) unc.push_back(theta[i]);
-    bool changed = false;
-    for (int q = 0; q < n_sel; ++q) {
-      const int j = order[q];
-      if (!ok[j]) continue;
-      double eta = a - std::fabs(theta[j]);
-      auto it = std::lower_bound(unc.begin(), unc.end(), theta[j]);
-      if (it != unc.end()) eta = std::min(eta, *it - theta[j]);
-      if (it != unc.begin()) eta = std::min(eta, theta[j] - *(it - 1));
-      est[q] = (eta > 0.0) ? std::min(rnorm[q], rnorm[q] * rnorm[q] / eta) : rnorm[q];
-      if (!(est[q] <= tol)) {
-        ok[j] = 0;
-        changed = true;
-      }
-    }
-    if (!changed) break;
-  }
-  // walk outward in |theta|: ghosts are skipped, the first other rejection ends the core
-  for (int q = 0; q < n_sel && std::fabs(theta[order[q]]) <= a; ++q) {
-    const int j = order[q];
-    if (ghost[j]) continue;
-    if (!ok[j]) break;
-    res.max_est = std::max(res.max_est, est[q]);
-    res.core_idx.push_back(q);
-  }
-  return res;
-}
-
-// Positions of theta sorted by (|theta|, theta).
-std::vector<int> central_order(const std::vector<double> &theta) {
-  std::vector<int> order(theta.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
-    const double ai = std::fabs(theta[i]), aj = std::fabs(theta[j]);
-    return ai < aj || (ai == aj && theta[i] < theta[j]);
-  });
-  return order;
-}
-
 // vecs_out (device, may be null): row s of the D x N block at vecs_out + s * ldvec gets component
 // s of the unit Ritz vector of each returned value, in the order of eigs_out.
 dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, double tol, double norm_est,
@@ -1908,7 +1687,7 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
     }
   }
   // acceptance (the rule is described at accept_rule)
-  const AcceptResult ar = accept_rule(theta, order, n_sel, rnorm, a, n_w, tol, norm_est);
+  const AcceptResult ar = accept_rule(theta, order, n_sel, rnorm, a, tol);
   const std::vector<char> &ok = ar.ok, &ghost = ar.ghost;
   const std::vector<double> &est = ar.est;
   const std::vector<int> &core_idx = ar.core_idx;
@@ -2124,51 +1903,6 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
 dacp_status dacp_central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
                               double *err_out, int *n_out, dacp_report *report) {
   return central_eigs(ctx, h, N, opts, eigs_out, err_out, nullptr, 0, n_out, report);
-}
-
-dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_mu, const dacp_opts *opts_in,
-                      int attempt, double *fout, int *iout, int64_t *k_samples, int max_samples) {
-  if (D < 1 || N < 1 || N > D || !(e_bound > 0.0) || attempt < 0 || !fout || !iout) return DACP_E_INVALID;
-  dacp_opts o;
-  if (opts_in) o = *opts_in;
-  else dacp_default_opts(&o);
-  if (!(o.a > 0.0) && (!mu || n_mu < 1)) return DACP_E_INVALID;
-  std::vector<double> m;
-  if (!(o.a > 0.0)) m.assign(mu, mu + n_mu);
-  // the same widening as dacp_central_eigs applies before each retry
-  double window_ratio = o.window_ratio > 0.0 ? o.window_ratio : 2.2;
-  for (int i = 0; i < attempt; ++i) window_ratio *= 1.5;
-  const Plan p = make_plan(o, D, N, e_bound, m, window_ratio, attempt);
-  fout[0] = p.n_w;
-  fout[1] = p.a_r;
-  fout[2] = p.a;
-  iout[0] = p.K;
-  iout[1] = p.b;
-  iout[2] = p.n;
-  iout[3] = p.m;
-  if (k_samples && max_samples > 0) {
-    const std::vector<int64_t> ks = sample_orders(p.a_r, p.n);
-    for (int i = 0; i < std::min(max_samples, p.n); ++i) k_samples[i] = ks[i];
-  }
-  return DACP_OK;
-}
-
-dacp_status dacp_accept_rule(int r, const double *theta, int n_sel, const double *rnorm, double a, double n_w,
-                             double tol, double norm_est, int *core_out, int *core_pos, double *est_out,
-                             int *n_ghost_out) {
-  if (r < 0 || n_sel < 0 || n_sel > r || (r > 0 && !theta) || (n_sel > 0 && !rnorm) || !core_out ||
-      !(a > 0.0) || !(n_w > 0.0))
-    return DACP_E_INVALID;
-  const std::vector<double> th(theta, theta + r);
-  for (int i = 0; i + 1 < r; ++i)
-    if (!(th[i + 1] >= th[i])) return DACP_E_INVALID;
-  const std::vector<double> rn(rnorm, rnorm + n_sel);
-  const AcceptResult res = accept_rule(th, central_order(th), n_sel, rn, a, n_w, tol, norm_est);
-  *core_out = static_cast<int>(res.core_idx.size());
-  if (core_pos) std::copy(res.core_idx.begin(), res.core_idx.end(), core_pos);
-  if (est_out) std::copy(res.est.begin(), res.est.end(), est_out);
-  if (n_ghost_out) *n_ghost_out = res.n_ghost;
-  return DACP_OK;
 }
 
 dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts, double *eigs_out,
@@ -2795,26 +2529,6 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     if (reports) reports[r] = rep[r];
   }
   if (worst != DACP_OK) return set_err(ctx, worst, "batched: some realisations fell short of N accepted eigenvalues");
-  return DACP_OK;
-}
-
-dacp_status dacp_spacing_ratios(const double *eigs, int n, double *r_out, double *mean_out) {
-  if (!eigs || n < 3) return DACP_E_INVALID;
-  for (int i = 0; i + 1 < n; ++i)
-    if (!(eigs[i + 1] >= eigs[i])) return DACP_E_INVALID;  // also rejects NaN
-  double sum = 0.0;
-  int64_t cnt = 0;
-  for (int i = 0; i + 2 < n; ++i) {
-    const double s0 = eigs[i + 1] - eigs[i], s1 = eigs[i + 2] - eigs[i + 1];
-    const double hi = std::max(s0, s1);
-    const double r = hi > 0.0 ? std::min(s0, s1) / hi : NAN;
-    if (r_out) r_out[i] = r;
-    if (hi > 0.0) {
-      sum += r;
-      ++cnt;
-    }
-  }
-  if (mean_out) *mean_out = cnt ? sum / static_cast<double>(cnt) : NAN;
   return DACP_OK;
 }
 

@@ -14,6 +14,7 @@
 #include <numeric>
 #include <vector>
 
+#include "host_rules.h"
 #include "internal.h"
 
 namespace dacp {
@@ -223,51 +224,12 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
   zn = std::sqrt(zn);
   for (double &v : z) v /= zn;
   rho *= zn * zn;
-  // sort by eigenvalue
-  std::vector<int> perm(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return dv[a] < dv[b]; });
-  std::vector<double> ds(n), zs(n);
-  std::vector<int> rowid(n);  // absolute eigenvector row of each sorted entry
-  for (int i = 0; i < n; ++i) {
-    ds[i] = dv[perm[i]];
-    zs[i] = z[perm[i]];
-    rowid[i] = lo + perm[i];
-  }
-  // deflation
-  const double eps = 2.220446049250313e-16;
-  double dmax = 0.0;
-  for (double v : ds) dmax = std::max(dmax, std::fabs(v));
-  const double tol = 8.0 * eps * std::max(dmax, rho);
-  std::vector<char> defl(n, 0);
-  std::vector<int> rot_pq;
-  std::vector<double> rot_cs;
-  int pj = -1;
-  for (int j = 0; j < n; ++j) {
-    if (rho * std::fabs(zs[j]) <= tol) {
-      defl[j] = 1;
-      continue;
-    }
-    if (pj >= 0) {
-      const double s0 = zs[pj], c0 = zs[j];
-      const double t = std::hypot(c0, s0);
-      const double c = c0 / t, s = s0 / t;
-      if (std::fabs((ds[j] - ds[pj]) * c * s) <= tol) {
-        // rotate the pair so that z_pj = 0: rows pj' = c pj - s j, j' = s pj + c j
-        rot_pq.push_back(rowid[pj]);
-        rot_pq.push_back(rowid[j]);
-        rot_cs.push_back(c);
-        rot_cs.push_back(s);
-        zs[j] = t;
-        zs[pj] = 0.0;
-        const double dp = ds[pj] * c * c + ds[j] * s * s;
-        ds[j] = ds[pj] * s * s + ds[j] * c * c;
-        ds[pj] = dp;
-        defl[pj] = 1;
-      }
-    }
-    pj = j;
-  }
+  // sort, deflate and list the secular problem (host bookkeeping, host_rules.cpp)
+  rules::DcDeflation df = rules::dc_deflate(dv, z, rho, lo);
+  const std::vector<double> &ds = df.ds, &zs = df.zs;
+  const std::vector<int> &rowid = df.rowid, &rot_pq = df.rot_pq, &nd = df.nd;
+  const std::vector<double> &rot_cs = df.rot_cs;
+  const std::vector<char> &defl = df.defl;
   if (!rot_pq.empty()) {
     const int nr = static_cast<int>(rot_cs.size() / 2);
     DACP_TRY(to_device(ctx, W.dpq.p, rot_pq.data(), rot_pq.size() * sizeof(int)));
@@ -277,18 +239,9 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
     DACP_HIP(ctx, hipGetLastError());
   }
   // non-deflated problem
-  std::vector<int> nd;
-  for (int j = 0; j < n; ++j)
-    if (!defl[j]) nd.push_back(j);
   const int k = static_cast<int>(nd.size());
-  std::vector<double> lam_out(n);
-  std::vector<int> new_rows_src;  // for the final ordering
   // final eigenvalue list: (value, kind, index) kind 0 = deflated (rowid), 1 = secular root (nd index)
-  struct Ent {
-    double v;
-    int kind, idx;
-  };
-  std::vector<Ent> ents;
+  std::vector<rules::DcEntry> ents;
   for (int j = 0; j < n; ++j)
     if (defl[j]) ents.push_back({ds[j], 0, rowid[j]});
   if (k > 0) {
@@ -328,20 +281,11 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
       ents.push_back({v, 1, q});
     }
   }
-  std::stable_sort(ents.begin(), ents.end(), [](const Ent &a, const Ent &b) { return a.v < b.v; });
   // place rows: deflated rows are copied (they may currently sit anywhere in the block), roots
   // come from dB; stage everything through dA (n x n of the block) then copy to rows lo..hi
-  std::vector<int> src_defl, dst_defl, src_root, dst_root;
-  for (int t = 0; t < n; ++t) {
-    if (ents[t].kind == 0) {
-      src_defl.push_back(ents[t].idx);
-      dst_defl.push_back(t);
-    } else {
-      src_root.push_back(ents[t].idx);
-      dst_root.push_back(t);
-    }
-    W.w[lo + t] = ents[t].v;
-  }
+  const rules::DcPlacement pl = rules::dc_place(std::move(ents), k);
+  const std::vector<int> &src_defl = pl.src_defl, &dst_defl = pl.dst_defl;
+  for (int t = 0; t < n; ++t) W.w[lo + t] = pl.w[t];
   // deflated: gather Z rows -> dA rows dst
   DevBuf tmp_idx;
   if (!src_defl.empty()) {
@@ -361,11 +305,9 @@ dacp_status merge(DcWork &W, int lo, int m, int hi, double beta) {
     DACP_HIP(ctx, hipGetLastError());
     DACP_HIP(ctx, hipStreamSynchronize(st));
   }
-  std::vector<int> dst_of_q(k);  // read by an async copy: lives until the stream sync below
-  if (!src_root.empty()) {
-    // dB row q (root q) -> dA row dst; src_root[t] = q
-    for (size_t t = 0; t < src_root.size(); ++t) dst_of_q[src_root[t]] = dst_root[t];
-    DACP_TRY(to_device(ctx, W.drows.p, dst_of_q.data(), k * sizeof(int)));
+  if (k > 0) {
+    // dB row q (root q) -> dA row dst_of_root[q]
+    DACP_TRY(to_device(ctx, W.drows.p, pl.dst_of_root.data(), k * sizeof(int)));
     hipLaunchKernelGGL(k_scatter_block, dim3(nblk(static_cast<int64_t>(k) * n, 256)), dim3(256), 0, st,
                        W.dB.as<double>(), (int64_t)n, W.drows.as<int>(), 0, k, n, W.dA.as<double>(), (int64_t)n);
     DACP_HIP(ctx, hipGetLastError());

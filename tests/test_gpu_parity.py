@@ -635,10 +635,16 @@ def test_rayleigh_ritz_parity(ctx):
 # ------------------------------------------------------------------ end to end
 
 
-def _check_central(got, ref, norm, N):
+def _check_central(got, ref, norm, N, errs=None):
+    """Counts, order and values against the oracle; with `errs`, every returned error estimate must
+    bound the true error (up to the rounding of the value itself, 64 eps ||H||)."""
     assert len(got) == N
     assert np.all(np.diff(got) >= 0)
-    assert np.abs(np.sort(got) - ref).max() <= 1e-10 * norm
+    err = np.abs(np.sort(got) - ref)
+    assert err.max() <= 1e-10 * norm
+    if errs is not None:
+        below = err > np.asarray(errs) + 64 * 2.220446049250313e-16 * norm
+        assert not below.any(), f"{int(below.sum())} estimates below the true error (max {err.max():.2e})"
 
 
 def test_central_eigs_chain_L10(ctx):
@@ -650,7 +656,7 @@ def test_central_eigs_chain_L10(ctx):
     for seed in (0, 1, 2):
         opts = B.default_opts(b=4, seed=seed)
         eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
-        _check_central(eigs, ref, norm, N)
+        _check_central(eigs, ref, norm, N, errs=errs)
         assert np.all(errs <= 1e-10 * norm)
 
 
@@ -660,7 +666,7 @@ def test_central_eigs_spin_glass_L12(ctx):
     ref, norm = central.central_eigenvalues(L, terms, N)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=8))
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
 
 
 def test_central_eigs_jw_twin_L14(ctx):
@@ -670,7 +676,7 @@ def test_central_eigs_jw_twin_L14(ctx):
     ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=16))
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
 
 
 def _check_eigvecs(X, eigs, errs, Hd, norm, a):
@@ -719,7 +725,7 @@ def test_central_eigpairs_vectors_against_dense_eigenvectors(ctx):
         e0, r0, _, _ = B.dacp_central_eigs(ctx, ham, N, opts)
         vecs = torch.full((1 << L, ld), float("nan"), dtype=torch.float64, device=DEV)
         eigs, errs, rep, st = B.dacp_central_eigpairs(ctx, ham, N, vecs, opts)
-        _check_central(eigs, ref, norm, N)
+        _check_central(eigs, ref, norm, N, errs=errs)
         assert np.array_equal(eigs, e0) and np.array_equal(errs, r0)
         Xp = host(vecs)
         assert np.isnan(Xp[:, N:]).all()  # the padding columns are left alone
@@ -780,7 +786,7 @@ def test_central_eigs_paper_tfim_L14_against_jordan_wigner(ctx):
     ref, norm = central.central_eigenvalues_jw(Jb, g, N)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=16))
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
     # gap ratios of the computed levels: each level is within 1e-10 ||H||, so each spacing within
     # 2e-10 ||H|| and each ratio within (1 + r) 2e-10 ||H|| / max(s_i, s_i+1) of the exact one
     r, _ = B.dacp_spacing_ratios(eigs)
@@ -797,7 +803,7 @@ def test_central_eigs_paper_spin_glass_shard_L12(ctx):
     ref, norm = central.central_eigenvalues(L, terms, N)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=8))
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
 
 
 def test_central_eigs_jw_twin_L20_full_size(ctx):
@@ -811,7 +817,7 @@ def test_central_eigs_jw_twin_L20_full_size(ctx):
     opts = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
                           fp64_tail_frac=0.3)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
     assert np.all(errs <= 1e-10 * norm)
 
 
@@ -835,7 +841,7 @@ def test_central_eigs_paper_tfim_L19_full_size(ctx):
     t0 = time.perf_counter()
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
     dt = time.perf_counter() - t0
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
     assert np.all(errs <= 1e-10 * norm)
     err = np.abs(eigs - ref)
     eta = err / np.abs(ref)
@@ -864,7 +870,7 @@ def test_fp32_tail_error_table(ctx):
         print(line)
         if prec == B.DACP_F64 or frac >= 0.2:
             assert st == 0
-            _check_central(eigs, ref, norm, N)
+            _check_central(eigs, ref, norm, N, errs=errs)
 
 
 # ------------------------------------------------------------------ batched realisations
@@ -884,7 +890,7 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
         eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
         assert st == 0 and np.all(n_out == N)
         for r, (ref, norm) in enumerate(refs):
-            _check_central(eigs[r], ref, norm, N)
+            _check_central(eigs[r], ref, norm, N, errs=errs[r])
             assert np.all(errs[r] <= 1e-10 * norm)
             # the batched Lanczos bound equals the single-realisation one up to reduction order
             eb, _, _ = B.dacp_spectral_bound(ctx, hams[r], steps=80, seed=0x5BD1E995)
@@ -951,9 +957,9 @@ def test_central_eigs_batched_L14_and_L12(ctx):
     ham2 = B.dacp_build_hamiltonian(ctx, L2, terms2)
     eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, [ham1, ham2, ham1], N, B.default_opts(b=8))
     assert st == 0 and np.all(n_out == N)
-    _check_central(eigs[0], ref1, norm1, N)
-    _check_central(eigs[2], ref1, norm1, N)
-    _check_central(eigs[1], ref2, norm2, N)
+    _check_central(eigs[0], ref1, norm1, N, errs=errs[0])
+    _check_central(eigs[2], ref1, norm1, N, errs=errs[2])
+    _check_central(eigs[1], ref2, norm2, N, errs=errs[1])
 
 
 def test_central_eigs_batched_rejects_large_L(ctx):
@@ -1066,7 +1072,7 @@ def test_central_eigs_learned_matches_dense_oracle(ctx):
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs_learned(ctx, ham, net, N, bound_margin=0.05, opts=B.default_opts(b=8))
     assert rep["model_used"] == 1
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
 
 
 def test_central_eigs_learned_falls_back_on_a_bad_model(ctx):
@@ -1083,7 +1089,7 @@ def test_central_eigs_learned_falls_back_on_a_bad_model(ctx):
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
     eigs, errs, rep, st = B.dacp_central_eigs_learned(ctx, ham, net, N, bound_margin=0.0, opts=B.default_opts(b=8))
     assert rep["model_used"] == 1 and rep["model_fallback"] == 1
-    _check_central(eigs, ref, norm, N)
+    _check_central(eigs, ref, norm, N, errs=errs)
 
 
 def test_autotune_keeps_a_working_configuration(ctx):

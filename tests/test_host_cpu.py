@@ -125,15 +125,19 @@ def test_accept_rule_through_the_abi_matches_the_oracle():
         theta = np.sort(rng.uniform(-1.0, 1.0, r))
         if trial % 5 == 0 and r > 3:
             theta[r // 2] = theta[r // 2 - 1]  # a repeated value
+        if trial % 7 == 0 and r > 10:
+            theta[r // 3: r // 3 + 4] = theta[r // 3] + 1e-9 * np.arange(4)  # a near-degenerate cluster
         n_sel = int(rng.integers(0, r + 1))
         rn = 10.0 ** rng.uniform(-14, -3, n_sel)
         rn[rng.uniform(size=n_sel) < 0.05] = 50.0  # ghosts
-        a, n_w, tol = float(rng.uniform(0.2, 0.9)), float(rng.uniform(20, 400)), 10.0 ** rng.uniform(-11, -7)
-        pos, est, ng = binding.dacp_accept_rule(theta, rn, a, n_w, tol, 1.0)
-        core_ref, est_ref, ng_ref = acceptance.accept(theta, rn, a, n_w, tol, 1.0)
+        a, tol = float(rng.uniform(0.2, 0.9)), 10.0 ** rng.uniform(-11, -7)
+        pos, est, ng = binding.dacp_accept_rule(theta, rn, a, tol)
+        core_ref, est_ref, ng_ref = acceptance.accept(theta, rn, a, tol)
         assert list(pos) == core_ref and ng == ng_ref
         assert np.array_equal(est, np.array(est_ref, dtype=np.float64))
     with pytest.raises(ValueError):
-        binding.dacp_accept_rule([0.2, 0.1], [1e-12], 0.5, 10.0, 1e-10, 1.0)  # unsorted
+        binding.dacp_accept_rule([0.2, 0.1], [1e-12], 0.5, 1e-10)  # unsorted
     with pytest.raises(ValueError):
-        binding.dacp_accept_rule([0.1, 0.2], [1e-12] * 3, 0.5, 10.0, 1e-10, 1.0)  # n_sel > r
+        binding.dacp_accept_rule([0.1, 0.2], [1e-12] * 3, 0.5, 1e-10)  # n_sel > r
+    with pytest.raises(ValueError):
+        binding.dacp_accept_rule([0.1, 0.2], [1e-12], 0.0, 1e-10)  # a <= 0

@@ -511,21 +511,29 @@ def test_spacing_ratios_goe_level_repulsion():
 
 
 def test_acceptance_worked_cases():
-    """Hand-checked cases of the acceptance rule (quadratic residual bound, ghosts, contiguous core)."""
+    """Hand-checked cases of the acceptance rule (block quadratic residual bound, ghosts, core)."""
     theta = [-0.3, -0.1, 0.05, 0.2, 0.6]  # (|theta|, theta) order: 0.05, -0.1, 0.2, -0.3, 0.6
-    a, n_w, tol = 0.5, 4.0, 1e-10  # ghost threshold 10 * 2a / n_w = 2.5; start cap 1e-4
-    # all converged: the core is the four values inside a; eta is the distance to the edge
-    core, est, ng = acceptance.accept(theta, [1e-12] * 5, a, n_w, tol, 1.0)
+    a, tol = 0.5, 1e-10
+    # all converged: the core is the four values inside a; 0.6 lies beyond the window (a ghost,
+    # since a - |theta| < 0); the best cluster of 0.05 is itself, 0.15 - 1e-12 from its neighbours
+    core, est, ng = acceptance.accept(theta, [1e-12] * 5, a, tol)
+    assert core == [0, 1, 2, 3] and ng == 1 and math.isinf(est[4])
+    assert est[0] == pytest.approx(1e-24 / (0.15 - 1e-12), rel=1e-15)
+    # -0.1 unconverged: it ends the core, and its residual moves it towards its neighbour 0.05
+    core, est, ng = acceptance.accept(theta, [1e-12, 1e-3, 1e-12, 1e-12, 1e-12], a, tol)
+    assert core == [0] and est[0] == pytest.approx(1e-24 / (0.15 - 1e-3), rel=1e-14)
+    # its best cluster is all four values: their distance to the window edge, 0.2
+    assert est[1] == pytest.approx(1e-6 / 0.2, rel=1e-10)
+    # -0.1 a ghost (residual 3 >= a - 0.1): it represents no level and ends the core
+    core, est, ng = acceptance.accept(theta, [1e-12, 3.0, 1e-12, 1e-12, 1e-12], a, tol)
+    assert core == [0] and ng == 2 and math.isinf(est[1])
+    assert est[0] == pytest.approx(1e-24 / (0.15 - 1e-12), rel=1e-15)
+    # a near-degenerate pair 1e-9 apart with residuals 1e-8: alone, each is closer to its twin than
+    # the twin's residual (no bound); the cluster {-0.2, 0, 1e-9} is 0.3 - 1e-9 - 1e-12 from 0.3
+    theta = [-0.2, 0.0, 1e-9, 0.3]
+    core, est, ng = acceptance.accept(theta, [1e-8, 1e-8, 1e-12, 1e-12], a, tol)
     assert core == [0, 1, 2, 3] and ng == 0
-    assert est[0] == pytest.approx(1e-24 / 0.45, rel=1e-15)
-    assert est[4] == 1e-12  # beyond the window: eta <= 0, the plain residual
-    # -0.1 unconverged: it ends the core and bounds its neighbour's eta (0.05 - (-0.1))
-    core, est, ng = acceptance.accept(theta, [1e-12, 1e-3, 1e-12, 1e-12, 1e-12], a, n_w, tol, 1.0)
-    assert core == [0] and est[0] == pytest.approx(1e-24 / 0.15, rel=1e-14) and math.isinf(est[1])
-    # -0.1 a ghost: skipped by the core and left out of eta
-    core, est, ng = acceptance.accept(theta, [1e-12, 3.0, 1e-12, 1e-12, 1e-12], a, n_w, tol, 1.0)
-    assert core == [0, 2, 3] and ng == 1 and est[0] == pytest.approx(1e-24 / 0.45, rel=1e-15)
-    # cascade: 0.002 fails (4e-10 / 0.498 > tol), then 0 fails against it (1e-12 / 0.002 = 5e-10)
-    core, est, ng = acceptance.accept([0.0, 0.002, 0.3], [1e-6, 2e-5, 1e-12], 0.5, 4.0, 1e-10, 1.0)
-    assert core == [] and est[0] == pytest.approx(5e-10, rel=1e-12)
-    assert est[2] == pytest.approx(1e-24 / 0.2, rel=1e-12)
+    assert est[0] == pytest.approx((1e-24 + 2e-16) / (0.3 - 1e-9 - 1e-12), rel=1e-12)
+    # the same pair with residuals 1e-5: the cluster bound 2e-10 / 0.3 exceeds tol
+    core, est, ng = acceptance.accept(theta, [1e-5, 1e-5, 1e-12, 1e-12], a, tol)
+    assert core == [] and est[0] > tol
