@@ -284,6 +284,9 @@ typedef struct {
   int n_ghost;              /* candidates whose residual reaches the window edge   */
   int model_used;           /* dacp_central_eigs_learned: 1 = bound and window from the network */
   int model_fallback;       /* 1 = the network's window failed and Lanczos / KPM redid the call */
+  int n_clusters_at_b;      /* returned runs of >= b values, each within 2 tol of the next: a level
+                               of multiplicity b; b start states resolve at most b copies of one
+                               level (Sec. III, block filter), so its multiplicity may be larger */
 } dacp_report;
 
 /* Fill `opts` with the defaults listed above. */

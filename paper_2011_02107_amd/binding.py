@@ -106,6 +106,7 @@ class Report(ctypes.Structure):
         ("n_ghost", ctypes.c_int),
         ("model_used", ctypes.c_int),
         ("model_fallback", ctypes.c_int),
+        ("n_clusters_at_b", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -400,7 +401,9 @@ def dacp_central_eigs(ctx, ham, N, opts=None, raise_on_window=True):
     if st != 0 and (raise_on_window or st != -5):
         ctx.check(st)
     n = n_out.value if st == 0 else 0
-    return eigs[:n], errs[:n], rep.as_dict(), st
+    d = rep.as_dict()
+    d["n_out"] = n_out.value  # on DACP_E_WINDOW: the number accepted
+    return eigs[:n], errs[:n], d, st
 
 
 def dacp_central_eigpairs(ctx, ham, N, vecs, opts=None, raise_on_window=True):

@@ -1725,6 +1725,7 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
       eigs_out[i] = std::get<0>(sel[i]);
       if (err_out) err_out[i] = std::get<1>(sel[i]);
     }
+    rep.n_clusters_at_b = dacp::rules::clusters_at_width(eigs_out, N, tol, rep.b);
     if (vecs_out) {
       // Phi = V B_sel again for the returned values only, each column of B_sel scaled by
       // 1 / ||V b_j|| (the Ritz vectors are orthonormal only up to the S cut-off's rounding).

@@ -137,6 +137,19 @@ AcceptResult accept_rule(const std::vector<double> &theta, const std::vector<int
   return res;
 }
 
+int clusters_at_width(const double *eigs, int n, double tol, int b) {
+  int count = 0, run = 1;
+  for (int i = 1; i <= n; ++i) {
+    if (i < n && eigs[i] - eigs[i - 1] <= 2.0 * tol) {
+      ++run;
+      continue;
+    }
+    if (run >= b && b >= 1 && n > 0) ++count;
+    run = 1;
+  }
+  return count;
+}
+
 DcDeflation dc_deflate(const std::vector<double> &dv, const std::vector<double> &z, double rho, int lo) {
   const int n = static_cast<int>(dv.size());
   DcDeflation out;

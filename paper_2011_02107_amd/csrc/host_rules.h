@@ -66,6 +66,10 @@ constexpr int kAcceptMaxCluster = 8;
 AcceptResult accept_rule(const std::vector<double> &theta, const std::vector<int> &order, int n_sel,
                          const std::vector<double> &rnorm, double a, double tol);
 
+// Number of runs of at least b consecutive values of the ascending list eigs[n] in which each
+// value lies within 2 tol of the next (levels of multiplicity b at the accepted accuracy).
+int clusters_at_width(const double *eigs, int n, double tol, int b);
+
 // Divide-and-conquer merge bookkeeping (host side of the rank-one update): sort the two halves'
 // eigenvalues, deflate tiny z components and close pairs (Givens rotations that zero one z of
 // the pair), and list the non-deflated problem.
