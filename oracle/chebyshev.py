@@ -14,6 +14,13 @@ Evolution (Sec. II.B, Eq. G2): G = H / E_max, a_r = a / E_max; the basis
 k_m = floor(m pi / a_r), m = 1..n, read here as the even number
 2 floor(m pi / (2 a_r)) as App. C allows.
 
+Moment mode (App. C, Eq. shift): the basis states are never stored.  With the
+product identity T_x T_y = (T_{x+y} + T_{|x-y|})/2 the overlap S and the projected
+H follow from the b x b moment matrices mu_k = psi_E^T T_k(G) psi_E alone, recorded
+during an evolution to twice the last sampled order.  Sums of sampled orders must
+themselves be recorded orders, which fixes the samples on a uniform grid
+k_m = m Delta, Delta = 2 floor(pi / (2 a_r)) (even, as App. C assumes).
+
 Every function takes the operator as a callable `apply(X) -> H X` on (D, b)
 blocks, so the same code runs on the dense and the matrix-free oracle H.
 """
@@ -116,3 +123,67 @@ def chebyshev_basis(apply, psi_e, e_max, a, n):
         cols.append(panels[km - 1])
         cols.append(panels[km])
     return np.concatenate(cols, axis=1), ks
+
+
+def uniform_sample_orders(a_r, n):
+    """Moment mode: (Delta, [k_1 .. k_n]) with k_m = m Delta, Delta = 2 floor(pi / (2 a_r))."""
+    delta = 2 * int(math.floor(math.pi / (2.0 * a_r)))
+    return delta, [m * delta for m in range(1, n + 1)]
+
+
+def panel_orders(ks):
+    """Orders of the basis panels (App. C, Eq. set2): [0, k_1 - 1, k_1, ..., k_n - 1, k_n]."""
+    return [0] + [k for km in ks for k in (km - 1, km)]
+
+
+def basis_on_orders(apply, psi_e, e_max, orders):
+    """Explicit panels T_x(G) psi_E for the given orders (any order list), G = H / E_max."""
+    psi_e = np.asarray(psi_e, dtype=np.float64)
+    want = set(orders)
+    panels = {}
+    t_prev = psi_e.copy()
+    if 0 in want:
+        panels[0] = t_prev.copy()
+    t_cur = apply(psi_e) / e_max
+    if 1 in want:
+        panels[1] = t_cur.copy()
+    for k in range(2, max(orders) + 1):
+        t_prev, t_cur = t_cur, 2.0 * apply(t_cur) / e_max - t_prev
+        if k in want:
+            panels[k] = t_cur.copy()
+    return np.concatenate([panels[x] for x in orders], axis=1)
+
+
+def chebyshev_moments(apply, psi_e, e_max, kmax):
+    """mu[k] = psi_E^T T_k(G) psi_E (b x b), k = 0 .. kmax, by the three-term recurrence."""
+    psi_e = np.asarray(psi_e, dtype=np.float64)
+    b = psi_e.shape[1]
+    mu = np.zeros((kmax + 1, b, b))
+    t_prev = psi_e.copy()
+    mu[0] = psi_e.T @ t_prev
+    if kmax == 0:
+        return mu
+    t_cur = apply(psi_e) / e_max
+    mu[1] = psi_e.T @ t_cur
+    for k in range(2, kmax + 1):
+        t_prev, t_cur = t_cur, 2.0 * apply(t_cur) / e_max - t_prev
+        mu[k] = psi_e.T @ t_cur
+    return mu
+
+
+def moment_projection(mu, orders, e_max):
+    """S = A^T A and P = A^T H A of the panels T_x(G) psi_E, x in `orders`, from the moments alone
+    (App. C, Eq. shift): block (p, q) of S is (mu_{x+y} + mu_{|x-y|}) / 2; with H = E_max T_1(G)
+    and T_1 T_y = (T_{y+1} + T_{|y-1|}) / 2, block (p, q) of P is
+    E_max (mu_{x+y+1} + mu_{|x-y-1|} + mu_{x+|y-1|} + mu_{|x-|y-1||}) / 4."""
+    b = mu.shape[1]
+    npan = len(orders)
+    S = np.zeros((npan * b, npan * b))
+    P = np.zeros_like(S)
+    for p, x in enumerate(orders):
+        for q, y in enumerate(orders):
+            ym = abs(y - 1)
+            S[p * b:(p + 1) * b, q * b:(q + 1) * b] = 0.5 * (mu[x + y] + mu[abs(x - y)])
+            P[p * b:(p + 1) * b, q * b:(q + 1) * b] = 0.25 * e_max * (
+                mu[x + y + 1] + mu[abs(x - y - 1)] + mu[x + ym] + mu[abs(x - ym)])
+    return S, P

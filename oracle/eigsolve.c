@@ -127,13 +127,18 @@ int orc_tridiagonalize(int n, double *a, double *d, double *e, double *q) {
 int orc_tridiag_ql(int n, double *d, double *e, double *z) {
   if (n <= 0) return 0;
   e[n - 1] = 0.0;
+  /* An off-diagonal element is negligible once it is below eps times the scale of the matrix seen
+   * so far, the running maximum of |d_l| + |e_l| (the Wilkinson-Reinsch test).  A test against
+   * the two neighbouring diagonal entries alone never deflates a cluster of eigenvalues at zero,
+   * as in the singular overlap matrix of the projected problem. */
+  double tst1 = 0.0;
   for (int l = 0; l < n; ++l) {
     int iter = 0;
     int mm;
+    tst1 = fmax(tst1, fabs(d[l]) + fabs(e[l]));
     for (;;) {
       for (mm = l; mm < n - 1; ++mm) {
-        const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
-        if (fabs(e[mm]) <= 1e-300 || fabs(e[mm]) <= 2.220446049250313e-16 * dd) break;
+        if (fabs(e[mm]) <= 2.220446049250313e-16 * tst1) break;
       }
       if (mm == l) break;
       if (++iter > 60) return -1;

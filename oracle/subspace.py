@@ -42,6 +42,20 @@ def residual_norms(apply, V, B, theta):
     return np.linalg.norm(R, axis=0), np.linalg.norm(Phi, axis=0)
 
 
+def rayleigh_quotients(apply, V, B, theta):
+    """For the computed Ritz vectors phi = V b_j: their Rayleigh quotients phi^T H phi / phi^T phi
+    and the residual norms ||H phi - theta phi|| / ||phi|| about the projected problem's values
+    (Sec. II.C).  The Rayleigh quotient of phi is the Ritz value in exact arithmetic; computed
+    directly from phi it does not carry the rounding of the ill-conditioned projected problem, and
+    its own residual is at most the one returned."""
+    Phi = V @ B
+    HPhi = apply(Phi)
+    nx = np.einsum("ij,ij->j", Phi, Phi)
+    rq = np.einsum("ij,ij->j", Phi, HPhi) / nx
+    rn = np.linalg.norm(HPhi - Phi * theta[None, :], axis=0) / np.sqrt(nx)
+    return rq, rn
+
+
 def neighbour_gaps(theta):
     """Distance of each Ritz value to its nearest other Ritz value."""
     theta = np.asarray(theta)

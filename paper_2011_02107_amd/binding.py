@@ -75,6 +75,7 @@ class Opts(ctypes.Structure):
         ("fp64_tail_frac", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("max_retries", ctypes.c_int),
+        ("moment_mode", ctypes.c_int),
     ]
 
 
@@ -140,6 +141,7 @@ SIGNATURES = {
     "dacp_project": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i64, _vp, _vp, _i64]),
     "dacp_rayleigh_ritz": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, ctypes.c_double, _dp, _vp, _ip]),
     "dacp_syev": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _dp, _vp]),
+    "dacp_basis_moments": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(BasisParams), _vp, _vp, _vp, _i64, _ip]),
     "dacp_syev_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "dacp_gemm": (
         ctypes.c_int,
@@ -333,6 +335,17 @@ def dacp_basis(ctx, ham, psi_e, V, e_bound, a, n, group=0):
     p = BasisParams(float(e_bound), float(a), int(n), b, int(group))
     m = ctypes.c_int()
     ctx.check(ctx.lib.dacp_basis(ctx.handle, ham.handle, ctypes.byref(p), _ptr(psi_e), _ptr(V), int(V.shape[1]), ctypes.byref(m)))
+    return m.value
+
+
+def dacp_basis_moments(ctx, ham, psi_e, S, P, e_bound, a, n, group=0):
+    """Moment mode: S and P (device m x m tensors) of the uniform-grid Chebyshev basis from moments,
+    without storing it; returns m = b (2n + 1)."""
+    b = int(psi_e.shape[1])
+    p = BasisParams(float(e_bound), float(a), int(n), b, int(group))
+    m = ctypes.c_int()
+    ctx.check(ctx.lib.dacp_basis_moments(ctx.handle, ham.handle, ctypes.byref(p), _ptr(psi_e), _ptr(S), _ptr(P),
+                                         int(S.shape[1]), ctypes.byref(m)))
     return m.value
 
 

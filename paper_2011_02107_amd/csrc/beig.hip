@@ -523,48 +523,98 @@ hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n,
   }
 }
 
+namespace {
+
+__global__ void k_fill_int(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Device buffers of one batched solve besides A, Zr and Q: per-matrix w and beta (2 n doubles
+// each), convergence flags, the problem table, and the sort permutation of the finish.
+struct BatchEigWork {
+  double *wb = nullptr;            // sum 2 n[i] doubles
+  int *stat = nullptr;             // count ints
+  BatchEigProblem *probs = nullptr;  // count entries
+};
+
+// First half on given buffers (no allocation): one launch over the matrices; w[i] (host) gets the
+// eigenvalues in the unsorted order of the rows of Zr[i].
+dacp_status batch_syev_raw_on(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
+                              double *const *Q, double *const *w, const BatchEigWork &wk) {
+  hipStream_t st = ctx->stream;
+  int max_n = 0;
+  size_t total = 0;
+  std::vector<size_t> off(count);
+  for (int i = 0; i < count; ++i) {
+    max_n = std::max(max_n, n[i]);
+    off[i] = total;
+    total += 2 * static_cast<size_t>(n[i]);  // w, beta
+  }
+  // flags cleared by a kernel (a memset node would misbehave inside a caller's captured graph)
+  hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, st, wk.stat, count, 0);
+  DACP_HIP(ctx, hipGetLastError());
+  std::vector<BatchEigProblem> probs(count);
+  for (int i = 0; i < count; ++i) {
+    double *base = wk.wb + off[i];
+    probs[i].A = A[i];
+    probs[i].Zr = Zr[i];
+    probs[i].Q = Q[i];
+    probs[i].w = base;
+    probs[i].beta = base + n[i];
+    probs[i].status = wk.stat + i;
+    probs[i].n = n[i];
+  }
+  DACP_TRY(to_device(ctx, wk.probs, probs.data(), sizeof(BatchEigProblem) * count));
+  DACP_HIP(ctx, launch_batch_syev(wk.probs, count, max_n, st));
+  std::vector<int> status(count);
+  DACP_TRY(to_host(ctx, status.data(), wk.stat, sizeof(int) * count));
+  for (int i = 0; i < count; ++i)
+    if (status[i] != 0) return set_err(ctx, DACP_E_CONVERGENCE, "batch_syev: QR iteration did not converge");
+  std::vector<double> all(total);
+  DACP_TRY(to_host(ctx, all.data(), wk.wb, total * sizeof(double)));
+  for (int i = 0; i < count; ++i) std::copy(all.begin() + off[i], all.begin() + off[i] + n[i], w[i]);
+  return DACP_OK;
+}
+
+// Second half for one matrix on a given permutation buffer dperm (n ints, no allocation).
+dacp_status batch_syev_finish_on(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr,
+                                 const double *Q, double *w_out, double *Zrows, int *dperm) {
+  hipStream_t st = ctx->stream;
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return w_raw[a] < w_raw[b]; });
+  for (int j = 0; j < n; ++j) w_out[j] = w_raw[perm[j]];
+  if (!Zrows) return DACP_OK;
+  DACP_TRY(to_device(ctx, dperm, perm.data(), sizeof(int) * n));
+  DACP_HIP(ctx, launch_dgemm(0, 1, n, n, n, 1.0, Zr, n, Q, n, 0.0, A, n, 0, st));
+  DACP_HIP(ctx, launch_gather_rows(A, n, Zrows, n, dperm, nullptr, n, n, st));
+  DACP_HIP(ctx, hipStreamSynchronize(st));  // dperm may be reused on return
+  return DACP_OK;
+}
+
+}  // namespace
+
 // Host side, first half: one launch over `count` matrices A[i] (device, n[i] x n[i], ld n[i],
 // destroyed); Zr[i], Q[i] (device, n x n) receive the tridiagonal's eigenvectors (rows, unsorted)
 // and the Householder product, w[i] (host) the eigenvalues in the same unsorted order.
 dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
                            double *const *Q, double *const *w) {
   if (count <= 0) return DACP_OK;
-  hipStream_t st = ctx->stream;
-  int max_n = 0;
   size_t total = 0;
-  std::vector<size_t> off(count);
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > kBatchEigMaxN) return set_err(ctx, DACP_E_INVALID, "batch_syev: 1 <= n <= 2048");
-    max_n = std::max(max_n, n[i]);
-    off[i] = total;
-    total += 2 * static_cast<size_t>(n[i]);  // w, beta
+    total += 2 * static_cast<size_t>(n[i]);
   }
   DevBuf work, dprobs, dstat;
   DACP_HIP(ctx, work.alloc(total * sizeof(double)));
   DACP_HIP(ctx, dstat.alloc(sizeof(int) * count));
-  DACP_HIP(ctx, hipMemsetAsync(dstat.p, 0, sizeof(int) * count, st));
-  std::vector<BatchEigProblem> probs(count);
-  for (int i = 0; i < count; ++i) {
-    double *base = work.as<double>() + off[i];
-    probs[i].A = A[i];
-    probs[i].Zr = Zr[i];
-    probs[i].Q = Q[i];
-    probs[i].w = base;
-    probs[i].beta = base + n[i];
-    probs[i].status = dstat.as<int>() + i;
-    probs[i].n = n[i];
-  }
   DACP_HIP(ctx, dprobs.alloc(sizeof(BatchEigProblem) * count));
-  DACP_TRY(to_device(ctx, dprobs.p, probs.data(), sizeof(BatchEigProblem) * count));
-  DACP_HIP(ctx, launch_batch_syev(dprobs.as<BatchEigProblem>(), count, max_n, st));
-  std::vector<int> status(count);
-  DACP_TRY(to_host(ctx, status.data(), dstat.p, sizeof(int) * count));
-  for (int i = 0; i < count; ++i)
-    if (status[i] != 0) return set_err(ctx, DACP_E_CONVERGENCE, "batch_syev: QR iteration did not converge");
-  std::vector<double> all(total);
-  DACP_TRY(to_host(ctx, all.data(), work.p, total * sizeof(double)));
-  for (int i = 0; i < count; ++i) std::copy(all.begin() + off[i], all.begin() + off[i] + n[i], w[i]);
-  return DACP_OK;
+  BatchEigWork wk;
+  wk.wb = work.as<double>();
+  wk.stat = dstat.as<int>();
+  wk.probs = dprobs.as<BatchEigProblem>();
+  return batch_syev_raw_on(ctx, count, n, A, Zr, Q, w, wk);
 }
 
 // Second half, for one matrix on the caller's stream: eigenvalues ascending into w_out and, if
@@ -572,19 +622,9 @@ dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const 
 // the rows of Y in ascending order of the eigenvalues.
 dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr, const double *Q,
                               double *w_out, double *Zrows) {
-  hipStream_t st = ctx->stream;
-  std::vector<int> perm(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return w_raw[a] < w_raw[b]; });
-  for (int j = 0; j < n; ++j) w_out[j] = w_raw[perm[j]];
-  if (!Zrows) return DACP_OK;
   DevBuf dperm;
-  DACP_HIP(ctx, dperm.alloc(sizeof(int) * n));
-  DACP_TRY(to_device(ctx, dperm.p, perm.data(), sizeof(int) * n));
-  DACP_HIP(ctx, launch_dgemm(0, 1, n, n, n, 1.0, Zr, n, Q, n, 0.0, A, n, 0, st));
-  DACP_HIP(ctx, launch_gather_rows(A, n, Zrows, n, dperm.as<int>(), nullptr, n, n, st));
-  DACP_HIP(ctx, hipStreamSynchronize(st));  // dperm is released on return
-  return DACP_OK;
+  if (Zrows) DACP_HIP(ctx, dperm.alloc(sizeof(int) * n));
+  return batch_syev_finish_on(ctx, n, w_raw, A, Zr, Q, w_out, Zrows, dperm.as<int>());
 }
 
 // Both halves: eigen-decompositions of `count` symmetric matrices A[i] (device, n[i] x n[i], ld n[i],
@@ -599,12 +639,12 @@ dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, 
     off[i] = total;
     total += 2 * static_cast<size_t>(n[i]) * n[i];
   }
-  DevBuf scratch;
-  DACP_HIP(ctx, scratch.alloc(total * sizeof(double)));
+  DevBuf scratch_zq;
+  DACP_HIP(ctx, scratch_zq.alloc(total * sizeof(double)));
   std::vector<double *> zr(count), q(count), wr(count);
   std::vector<std::vector<double>> wraw(count);
   for (int i = 0; i < count; ++i) {
-    zr[i] = scratch.as<double>() + off[i];
+    zr[i] = scratch_zq.as<double>() + off[i];
     q[i] = zr[i] + static_cast<size_t>(n[i]) * n[i];
     wraw[i].resize(n[i]);
     wr[i] = wraw[i].data();

@@ -740,6 +740,140 @@ struct GraphRun {
   }
 };
 
+// Chebyshev evolution T_{k+1}(G) = 2 G T_k - T_{k-1} (Sec. II.B) of one column group from T_0 (in
+// A, D x gw, row stride gw) up to T_kmax, G = H inv_e.  A, B and P are D x gw buffers.
+//   store_of(k)       device pointer (row stride ldst) that the kernel writing T_k also fills with an
+//                     FP64 copy of it, or null
+//   visit(k, T_k)     called once T_k is complete (D x gw, stride gw) for every k with want(k); it may
+//                     queue work on the context stream that reads T_k (queued before T_k's buffer is
+//                     reused)
+//   events(k1, k2)    whether a store or a visit falls on k1..k2 (such steps are not replayed from a
+//                     captured graph)
+dacp_status evolve_group(dacp_ctx ctx, dacp_ham h, double inv_e, int64_t kmax, int gw, double *A, double *B,
+                         double *Pp, const std::function<double *(int64_t)> &store_of, int64_t ldst,
+                         const std::function<bool(int64_t)> &want,
+                         const std::function<dacp_status(int64_t, const double *)> &visit,
+                         const std::function<bool(int64_t, int64_t)> &events, int64_t &launches) {
+  const int64_t D = h->D;
+  double *const A0 = A;
+  if (want(0)) DACP_TRY(visit(0, A));
+  if (kmax < 1) return DACP_OK;
+  dacp_status st = step<double>(ctx, h, gw, A, gw, B, gw, inv_e, nullptr, 0, 0.0, nullptr, 0, 0.0, store_of(1), ldst, 2);
+  if (st) return st;
+  ++launches;
+  if (want(1)) DACP_TRY(visit(1, B));
+  const int64_t report_every = std::max<int64_t>(1, kmax / 8);
+  int lo_bits = 0, hw = 1;
+  if (kmax > 1 && fused_plan(ctx, h, gw, lo_bits, hw, 8)) {
+    // P_2 = (2/E)(D + Lo) T_1 - T_0 by the low-bit pass, then alternate high / low fused kernels.
+    st = split_order(ctx, h, lo_bits);
+    if (st) return st;
+    const auto &so = h->split[lo_bits];
+    {
+      StepArgs<double> sa;
+      std::memset(&sa, 0, sizeof(sa));
+      sa.x = B;
+      sa.ldx = gw;
+      sa.y = Pp;
+      sa.ldy = gw;
+      sa.z = A;
+      sa.ldz = gw;
+      sa.alpha = 2.0 * inv_e;
+      sa.gamma = -1.0;
+      sa.diag = h->d64;
+      sa.flips = so.lo;
+      sa.nflip = so.nlo;
+      sa.nlow = so.nlo;
+      sa.nhigh = so.nlo;
+      sa.b = gw;
+      sa.log2R = lo_bits;
+      sa.ntiles = static_cast<int>(D >> lo_bits);
+      DACP_HIP(ctx, dacp::launch_step_lo<double>(sa, ctx->stream, 2));
+    }
+    dacp::RecArgs<double> ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.ld = gw;
+    ra.ldst = ldst;
+    ra.a_fin = ra.a_start = 2.0 * inv_e;
+    ra.b_cur = -1.0;
+    ra.diag = h->d64;
+    ra.b = gw;
+    ra.lo_bits = lo_bits;
+    ra.hi_bits = h->L - lo_bits;
+    ra.W = hw;
+    ra.threads = ctx->rec_threads;
+    ra.grid = ctx->rec_persist * ctx->num_cus;
+    ra.p = Pp;
+    // one step: T_{k+1} from T_k (tcur) and the partial; T_{k+1} overwrites T_{k-1} (tnew)
+    auto launch_step = [&](int64_t k, double *tcur, double *tnew, double *stv, hipStream_t s) -> hipError_t {
+      ra.tcur = tcur;
+      ra.tnew = tnew;
+      ra.st = stv;
+      if ((k % 2) == 1) {
+        ra.flips = so.hi;
+        ra.nflip = so.nhi;
+        ra.nplain = so.nhi_plain;
+        ra.ntiles = (1 << lo_bits) / hw;
+        ra.xcd_remap = ((ctx->rec_xcd & 2) && ra.ntiles % 8 == 0) ? 1 : 0;
+        return dacp::launch_rec_hi<double>(ra, s);
+      }
+      ra.flips = so.lo;
+      ra.nflip = so.nlo;
+      ra.nplain = so.nlo_plain;
+      ra.ntiles = static_cast<int>(D >> lo_bits);
+      ra.xcd_remap = ((ctx->rec_xcd & 1) && ra.ntiles % 8 == 0) ? 1 : 0;
+      return dacp::launch_rec_lo<double>(ra, s);
+    };
+    // Below 2^19 rows a launch is a few microseconds and its issue cost shows, so runs of
+    // rec_graph steps without a store or a visit (a high/low period starting on a high step, the
+    // buffers then in their starting roles) replay one captured graph.
+    GraphRun graph;
+    const int gsteps = (D < (int64_t(1) << 19) && kmax > 4 * ctx->rec_graph) ? ctx->rec_graph : 0;
+    double *const B0 = B;
+    for (int64_t k = 1; k < kmax;) {
+      if (gsteps > 0 && (k % 2) == 1 && k + gsteps <= kmax && !events(k + 1, k + gsteps) && A == A0) {
+        if (!graph.exec && !graph.failed) {
+          DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the first steps set the kernels' attributes
+          graph.capture(gsteps, [&](int64_t j, hipStream_t cs) {
+            double *tc = (j % 2 == 0) ? B0 : A0;
+            double *tn = (j % 2 == 0) ? A0 : B0;
+            return launch_step(k + j, tc, tn, nullptr, cs);
+          });
+        }
+        if (graph.exec) {
+          DACP_HIP(ctx, hipGraphLaunch(graph.exec, ctx->stream));
+          launches += gsteps;
+          k += gsteps;  // an even count: A and B are back in their roles
+          continue;
+        }
+      }
+      DACP_HIP(ctx, launch_step(k, B, A, store_of(k + 1), ctx->stream));
+      ++k;
+      ++launches;
+      std::swap(A, B);
+      if (want(k)) DACP_TRY(visit(k, B));
+      if (verbose() && k % report_every == 0) {
+        (void)hipStreamSynchronize(ctx->stream);
+        vlog("evolution: step %lld of %lld (fused)", static_cast<long long>(k), static_cast<long long>(kmax));
+      }
+    }
+    if (graph.exec) DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // before the graph is released
+    return DACP_OK;
+  }
+  for (int64_t k = 1; k < kmax; ++k) {
+    st = step<double>(ctx, h, gw, B, gw, A, gw, 2.0 * inv_e, nullptr, 0, 0.0, A, gw, -1.0, store_of(k + 1), ldst, 2);
+    if (st) return st;
+    ++launches;
+    std::swap(A, B);
+    if (want(k + 1)) DACP_TRY(visit(k + 1, B));
+    if (verbose() && (k + 1) % report_every == 0) {
+      (void)hipStreamSynchronize(ctx->stream);
+      vlog("evolution: step %lld of %lld", static_cast<long long>(k + 1), static_cast<long long>(kmax));
+    }
+  }
+  return DACP_OK;
+}
+
 dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *V,
                       int64_t ldv, int *m_out, EvolStats *stats) {
   const int64_t D = h->D;
@@ -780,120 +914,10 @@ dacp_status run_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, cons
       auto it = panel_of.lower_bound(k1);
       return it != panel_of.end() && it->first <= k2;
     };
-    dacp_status st =
-        step<double>(ctx, h, gw, A, gw, B, gw, inv_e, nullptr, 0, 0.0, nullptr, 0, 0.0, store_of(1), ldv, 2);
+    dacp_status st = evolve_group(
+        ctx, h, inv_e, kmax, gw, A, B, pbuf.as<double>(), store_of, ldv, [](int64_t) { return false; },
+        [](int64_t, const double *) { return DACP_OK; }, panel_in, launches);
     if (st) return st;
-    ++launches;
-    const int64_t report_every = std::max<int64_t>(1, kmax / 8);
-    int lo_bits = 0, hw = 1;
-    if (kmax > 1 && fused_plan(ctx, h, gw, lo_bits, hw, 8)) {
-      // P_2 = (2/E)(D + Lo) T_1 - T_0 by the low-bit pass, then alternate high / low fused kernels.
-      st = split_order(ctx, h, lo_bits);
-      if (st) return st;
-      const auto &so = h->split[lo_bits];
-      double *Pp = pbuf.as<double>();
-      {
-        StepArgs<double> sa;
-        std::memset(&sa, 0, sizeof(sa));
-        sa.x = B;
-        sa.ldx = gw;
-        sa.y = Pp;
-        sa.ldy = gw;
-        sa.z = A;
-        sa.ldz = gw;
-        sa.alpha = 2.0 * inv_e;
-        sa.gamma = -1.0;
-        sa.diag = h->d64;
-        sa.flips = so.lo;
-        sa.nflip = so.nlo;
-        sa.nlow = so.nlo;
-        sa.nhigh = so.nlo;
-        sa.b = gw;
-        sa.log2R = lo_bits;
-        sa.ntiles = static_cast<int>(D >> lo_bits);
-        DACP_HIP(ctx, dacp::launch_step_lo<double>(sa, ctx->stream, 2));
-      }
-      dacp::RecArgs<double> ra;
-      std::memset(&ra, 0, sizeof(ra));
-      ra.ld = gw;
-      ra.ldst = ldv;
-      ra.a_fin = ra.a_start = 2.0 * inv_e;
-      ra.b_cur = -1.0;
-      ra.diag = h->d64;
-      ra.b = gw;
-      ra.lo_bits = lo_bits;
-      ra.hi_bits = h->L - lo_bits;
-      ra.W = hw;
-      ra.threads = ctx->rec_threads;
-      ra.grid = ctx->rec_persist * ctx->num_cus;
-      ra.p = Pp;
-      // one step: T_{k+1} from T_k (tcur) and the partial; T_{k+1} overwrites T_{k-1} (tnew)
-      auto launch_step = [&](int64_t k, double *tcur, double *tnew, double *stv, hipStream_t s) -> hipError_t {
-        ra.tcur = tcur;
-        ra.tnew = tnew;
-        ra.st = stv;
-        if ((k % 2) == 1) {
-          ra.flips = so.hi;
-          ra.nflip = so.nhi;
-          ra.nplain = so.nhi_plain;
-          ra.ntiles = (1 << lo_bits) / hw;
-          ra.xcd_remap = ((ctx->rec_xcd & 2) && ra.ntiles % 8 == 0) ? 1 : 0;
-          return dacp::launch_rec_hi<double>(ra, s);
-        }
-        ra.flips = so.lo;
-        ra.nflip = so.nlo;
-        ra.nplain = so.nlo_plain;
-        ra.ntiles = static_cast<int>(D >> lo_bits);
-        ra.xcd_remap = ((ctx->rec_xcd & 1) && ra.ntiles % 8 == 0) ? 1 : 0;
-        return dacp::launch_rec_lo<double>(ra, s);
-      };
-      // Below 2^19 rows a launch is a few microseconds and its issue cost shows, so runs of
-      // rec_graph steps without a sample (a high/low period starting on a high step, the buffers
-      // then in their starting roles) replay one captured graph.
-      GraphRun graph;
-      const int gsteps = (D < (int64_t(1) << 19) && kmax > 4 * ctx->rec_graph) ? ctx->rec_graph : 0;
-      for (int64_t k = 1; k < kmax;) {
-        if (gsteps > 0 && (k % 2) == 1 && k + gsteps <= kmax && !panel_in(k + 1, k + gsteps) &&
-            A == ba.as<double>()) {
-          if (!graph.exec && !graph.failed) {
-            DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // the first steps set the kernels' attributes
-            graph.capture(gsteps, [&](int64_t j, hipStream_t cs) {
-              double *tc = (j % 2 == 0) ? bb.as<double>() : ba.as<double>();
-              double *tn = (j % 2 == 0) ? ba.as<double>() : bb.as<double>();
-              return launch_step(k + j, tc, tn, nullptr, cs);
-            });
-          }
-          if (graph.exec) {
-            DACP_HIP(ctx, hipGraphLaunch(graph.exec, ctx->stream));
-            launches += gsteps;
-            k += gsteps;  // an even count: A and B are back in their roles
-            continue;
-          }
-        }
-        DACP_HIP(ctx, launch_step(k, B, A, store_of(k + 1), ctx->stream));
-        ++k;
-        ++launches;
-        std::swap(A, B);
-        if (verbose() && k % report_every == 0) {
-          (void)hipStreamSynchronize(ctx->stream);
-          vlog("evolution group %d/%d: step %lld of %lld (fused)", g0 / g + 1, (b + g - 1) / g,
-               static_cast<long long>(k), static_cast<long long>(kmax));
-        }
-      }
-      if (graph.exec) DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));  // before the graph is released
-      continue;
-    }
-    for (int64_t k = 1; k < kmax; ++k) {
-      st = step<double>(ctx, h, gw, B, gw, A, gw, 2.0 * inv_e, nullptr, 0, 0.0, A, gw, -1.0, store_of(k + 1), ldv, 2);
-      if (st) return st;
-      ++launches;
-      std::swap(A, B);
-      if (verbose() && k % report_every == 0) {
-        (void)hipStreamSynchronize(ctx->stream);
-        vlog("evolution group %d/%d: step %lld of %lld", g0 / g + 1, (b + g - 1) / g, static_cast<long long>(k),
-             static_cast<long long>(kmax));
-      }
-    }
   }
   const double evol_ms = tm.stop_ms();
   // |T_k(G)| <= 1 for e_bound >= ||H||: every stored T_{k_m} column must keep norm <= ||psi_E column||.
@@ -962,6 +986,199 @@ dacp_status project_small(dacp_ctx ctx, dacp_ham h, int m, const double *V, int6
   DACP_HIP(ctx, dacp::launch_mirror_upper(out, m, ld, s));
   return DACP_OK;
 }
+
+// ------------------------------------------------------------- moment mode
+// Moment mode (App. C, Eq. shift): the panels T_x(G) psi_E are never stored.  S and P follow from
+// the b x b moments mu_k = psi_E^T T_k(G) psi_E through T_x T_y = (T_{x+y} + T_{|x-y|}) / 2 and
+// H = E_b T_1(G); the samples sit on the uniform grid k_m = m Delta, Delta = 2 floor(pi / (2 a_r)),
+// so that the needed orders x + y, |x - y| (and those one step off, for P) are recorded during an
+// evolution to 2 k_n + 1.
+struct MomentPlan {
+  int64_t delta = 0, kmax = 0;
+  std::vector<int64_t> orders;  // panel orders: 0, k_1 - 1, k_1, ..., k_n - 1, k_n
+  std::vector<int> idx_of;      // order -> moment slot, or -1 (k = 0 .. kmax)
+  int nrec = 0;
+};
+
+MomentPlan moment_plan(double a_r, int n) {
+  MomentPlan mp;
+  mp.delta = std::max<int64_t>(2, 2 * static_cast<int64_t>(std::floor(M_PI / (2.0 * a_r))));
+  mp.orders.push_back(0);
+  for (int j = 1; j <= n; ++j) {
+    mp.orders.push_back(j * mp.delta - 1);
+    mp.orders.push_back(j * mp.delta);
+  }
+  mp.kmax = 2 * n * mp.delta + 1;
+  mp.idx_of.assign(static_cast<size_t>(mp.kmax) + 1, -1);
+  std::vector<char> needed(mp.idx_of.size(), 0);
+  auto need = [&](int64_t k) { needed[k < 0 ? -k : k] = 1; };
+  for (int64_t x : mp.orders)
+    for (int64_t y : mp.orders) {
+      const int64_t ym = y >= 1 ? y - 1 : 1;
+      need(x + y);
+      need(x - y);
+      need(x + y + 1);
+      need(x - y - 1);
+      need(x + ym);
+      need(x - ym);
+    }
+  for (size_t k = 0; k < needed.size(); ++k)
+    if (needed[k]) mp.idx_of[k] = mp.nrec++;  // slots in order of k
+  return mp;
+}
+
+// Moment mode, first pass: filter output psi_e (D x b) -> S and P (device m x m, row stride ld),
+// m = b (2n + 1).  Returns DACP_E_BOUNDS when |T_{k_m}(G) psi_j| exceeds |psi_j| (E_b < ||H||).
+dacp_status run_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *S,
+                             double *P, int64_t ld, int *m_out, EvolStats *stats) {
+  const int64_t D = h->D;
+  const int b = p->b, n = p->n;
+  if (b < 1 || b > 128 || n < 1 || !(p->e_bound > 0.0) || !(p->a > 0.0) || p->a >= p->e_bound || !psi_e || !S || !P)
+    return set_err(ctx, DACP_E_INVALID, "basis_moments: need 1 <= b <= 128, n >= 1, 0 < a < e_bound, psi_e, S, P");
+  const int m = b * (2 * n + 1);
+  if (ld < m) return set_err(ctx, DACP_E_INVALID, "basis_moments: ld < b (2n + 1)");
+  const MomentPlan mp = moment_plan(p->a / p->e_bound, n);
+  int g = (p->group > 0 && p->group < b) ? p->group : recurrence_group(ctx, h, b);
+  while (g > 1 && b * g > 1024) g /= 2;  // the tall Gram kernel takes b g <= 1024 pairs
+  const double inv_e = 1.0 / p->e_bound;
+  DevBuf ba, bb, pbuf, mu, part, tmp, didx, dord;
+  DACP_HIP(ctx, ba.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, bb.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, pbuf.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, mu.alloc(static_cast<size_t>(mp.nrec) * b * b * sizeof(double)));
+  const int nblk = dacp::tall_gram_blocks(D);
+  DACP_HIP(ctx, part.alloc(static_cast<size_t>(nblk) * b * g * sizeof(double)));
+  DACP_HIP(ctx, tmp.alloc(static_cast<size_t>(b) * g * sizeof(double)));
+  Timer tm(ctx);
+  tm.start();
+  int64_t launches = 0;
+  for (int g0 = 0; g0 < b; g0 += g) {
+    const int gw = std::min(g, b - g0);
+    double *A = ba.as<double>(), *B = bb.as<double>();
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, A, gw, D, gw, ctx->stream));
+    auto want = [&](int64_t k) { return k <= mp.kmax && mp.idx_of[k] >= 0; };
+    // mu_k[:, g0 .. g0 + gw) = psi_E^T (T_k psi_E)[:, group]
+    auto visit = [&](int64_t k, const double *tk) -> dacp_status {
+      DACP_HIP(ctx, dacp::launch_tall_gram(psi_e, b, b, tk, gw, gw, D, part.as<double>(), nblk, tmp.as<double>(),
+                                           ctx->stream));
+      DACP_HIP(ctx, dacp::launch_copy_cols(tmp.as<double>(), gw,
+                                           mu.as<double>() + static_cast<int64_t>(mp.idx_of[k]) * b * b + g0, b, b,
+                                           gw, ctx->stream));
+      return DACP_OK;
+    };
+    auto events = [&](int64_t k1, int64_t k2) {
+      for (int64_t k = k1; k <= k2 && k <= mp.kmax; ++k)
+        if (mp.idx_of[k] >= 0) return true;
+      return false;
+    };
+    dacp_status st = evolve_group(
+        ctx, h, inv_e, mp.kmax, gw, A, B, pbuf.as<double>(), [](int64_t) -> double * { return nullptr; }, 0, want,
+        visit, events, launches);
+    if (st) return st;
+  }
+  const double evol_ms = tm.stop_ms();
+  // |T_k(G)| <= 1 for e_bound >= ||H||: |T_{k_j} psi|^2 = (mu_{2 k_j} + mu_0) / 2 on the diagonal
+  std::vector<double> muh(static_cast<size_t>(mp.nrec) * b * b);
+  DACP_TRY(to_host(ctx, muh.data(), mu.p, muh.size() * sizeof(double)));
+  auto mu_at = [&](int64_t k, int i, int j) { return muh[(static_cast<size_t>(mp.idx_of[k]) * b + i) * b + j]; };
+  for (int j = 1; j <= n; ++j)
+    for (int c = 0; c < b; ++c) {
+      const double n0 = mu_at(0, c, c);
+      const double nk = 0.5 * (mu_at(2 * j * mp.delta, c, c) + n0);
+      if (!std::isfinite(nk) || !std::isfinite(n0)) return set_err(ctx, DACP_E_NUMERIC, "basis_moments: non-finite moment");
+      if (nk > n0 * (1.0 + 4e-6))
+        return set_err(ctx, DACP_E_BOUNDS, "basis_moments: |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
+    }
+  DACP_HIP(ctx, didx.alloc(mp.idx_of.size() * sizeof(int)));
+  DACP_HIP(ctx, dord.alloc(mp.orders.size() * sizeof(int64_t)));
+  DACP_TRY(to_device(ctx, didx.p, mp.idx_of.data(), mp.idx_of.size() * sizeof(int)));
+  DACP_TRY(to_device(ctx, dord.p, mp.orders.data(), mp.orders.size() * sizeof(int64_t)));
+  DACP_HIP(ctx, dacp::launch_moment_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b,
+                                             static_cast<int>(mp.orders.size()), p->e_bound, S, P, ld, ctx->stream));
+  // the moments are symmetric only up to rounding: take the symmetric parts
+  DACP_HIP(ctx, dacp::launch_symmetrize(S, m, ld, ctx->stream));
+  DACP_HIP(ctx, dacp::launch_symmetrize(P, m, ld, ctx->stream));
+  DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (m_out) *m_out = m;
+  if (stats) {
+    stats->steps = mp.kmax;
+    stats->launches = launches;
+    stats->kernel_ms = evol_ms;
+    stats->group = g;
+  }
+  return DACP_OK;
+}
+
+// Moment mode, second pass: the Ritz vectors of nc candidates, Phi = A Bc (D x nc, row stride nc),
+// accumulated during an evolution to k_n without storing A.  bsel (device nc x m, row stride m):
+// row c is column c of B.  Panels are staged q_slots column groups at a time, then added with one
+// GEMM Phi += Z W^T, W (nc x K) the matching columns of bsel.
+dacp_status moment_ritz_vectors(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e,
+                                const double *bsel, int nc, double *Phi, EvolStats *stats) {
+  const int64_t D = h->D;
+  const int b = p->b, n = p->n;
+  const int m = b * (2 * n + 1);
+  const MomentPlan mp = moment_plan(p->a / p->e_bound, n);
+  std::map<int64_t, int> panel_of;  // panel order -> panel index
+  for (size_t q = 0; q < mp.orders.size(); ++q) panel_of[mp.orders[q]] = static_cast<int>(q);
+  const int64_t kmax = mp.orders.back();
+  const int g = (p->group > 0 && p->group < b) ? p->group : recurrence_group(ctx, h, b);
+  const int q_slots = 32;
+  const int kz = q_slots * g;
+  const double inv_e = 1.0 / p->e_bound;
+  DevBuf ba, bb, pbuf, zb, wb, dcols;
+  DACP_HIP(ctx, ba.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, bb.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, pbuf.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, zb.alloc(static_cast<size_t>(D) * kz * sizeof(double)));
+  DACP_HIP(ctx, wb.alloc(static_cast<size_t>(nc) * kz * sizeof(double)));
+  DACP_HIP(ctx, dcols.alloc(static_cast<size_t>(kz) * sizeof(int)));
+  DACP_HIP(ctx, hipMemsetAsync(Phi, 0, static_cast<size_t>(D) * nc * sizeof(double), ctx->stream));
+  std::vector<int> cols;  // columns of bsel (index into m) of the staged Z columns
+  int64_t launches = 0;
+  Timer tm(ctx);
+  tm.start();
+  auto flush = [&]() -> dacp_status {
+    if (cols.empty()) return DACP_OK;
+    const int K = static_cast<int>(cols.size());
+    DACP_TRY(to_device(ctx, dcols.p, cols.data(), cols.size() * sizeof(int)));
+    DACP_HIP(ctx, dacp::launch_gather_cols(bsel, m, dcols.as<int>(), nullptr, nc, K, wb.as<double>(), K, ctx->stream));
+    DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, nc, K, 1.0, zb.as<double>(), kz, wb.as<double>(), K, 1.0, Phi, nc, 0,
+                                     ctx->stream));
+    cols.clear();  // the next copies into Z and dcols are queued behind this GEMM on the same stream
+    return DACP_OK;
+  };
+  for (int g0 = 0; g0 < b; g0 += g) {
+    const int gw = std::min(g, b - g0);
+    double *A = ba.as<double>(), *B = bb.as<double>();
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, A, gw, D, gw, ctx->stream));
+    auto want = [&](int64_t k) { return panel_of.count(k) > 0; };
+    auto visit = [&](int64_t k, const double *tk) -> dacp_status {
+      if (static_cast<int>(cols.size()) + gw > kz) DACP_TRY(flush());
+      const int slot0 = static_cast<int>(cols.size());
+      DACP_HIP(ctx, dacp::launch_copy_cols(tk, gw, zb.as<double>() + slot0, kz, D, gw, ctx->stream));
+      const int pidx = panel_of[k];
+      for (int c = 0; c < gw; ++c) cols.push_back(pidx * b + g0 + c);
+      return DACP_OK;
+    };
+    auto events = [&](int64_t k1, int64_t k2) {
+      auto it = panel_of.lower_bound(k1);
+      return it != panel_of.end() && it->first <= k2;
+    };
+    dacp_status st = evolve_group(
+        ctx, h, inv_e, kmax, gw, A, B, pbuf.as<double>(), [](int64_t) -> double * { return nullptr; }, 0, want, visit,
+        events, launches);
+    if (st) return st;
+  }
+  DACP_TRY(flush());
+  if (stats) {
+    stats->steps += kmax;
+    stats->launches += launches;
+    stats->kernel_ms += tm.stop_ms();
+  }
+  return DACP_OK;
+}
+
 
 dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
                         int64_t ld) {
@@ -1590,6 +1807,12 @@ dacp_status dacp_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, con
   return run_basis(ctx, h, p, psi_e, V, ldv, m_out, nullptr);
 }
 
+dacp_status dacp_basis_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *S,
+                               double *P, int64_t ld, int *m_out) {
+  if (!ctx || !h || !p) return DACP_E_INVALID;
+  return run_moment_basis(ctx, h, p, psi_e, S, P, ld, m_out, nullptr);
+}
+
 dacp_status dacp_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
                          int64_t ld) {
   if (!ctx || !h) return DACP_E_INVALID;
@@ -1639,55 +1862,82 @@ dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N
 namespace {
 // vecs_out (device, may be null): row s of the D x N block at vecs_out + s * ldvec gets component
 // s of the unit Ritz vector of each returned value, in the order of eigs_out.
+// phi_all (device, may be null): the candidates' Ritz vectors already formed (moment mode), D x
+// n_sel0 with row stride n_sel0, column c for the c-th value in the (|theta|, theta) order; V and bc
+// are then not read.
 dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, double tol, double norm_est,
                          const double *V, int m, int r, const std::vector<double> &theta, const DevBuf &bc,
                          dacp_report &rep, double *eigs_out, double *err_out, int &accepted,
-                         double *vecs_out = nullptr, int64_t ldvec = 0) {
+                         double *vecs_out = nullptr, int64_t ldvec = 0, const double *phi_all = nullptr) {
   const int64_t D = h->D;
   hipStream_t s = ctx->stream;
   dacp_status st;
   double t0 = now_ms();
-  const std::vector<int> order = central_order(theta);
-  const int n_sel = std::min(r, N + std::max(64, N / 8));
-  std::vector<double> rnorm(n_sel, INFINITY), phin2(n_sel, 1.0);
+  const std::vector<int> order0 = central_order(theta);
+  const int n_sel0 = std::min(r, N + std::max(64, N / 8));
+  // per Ritz value (index into theta): residual norm of the unit Ritz vector, squared norm of the
+  // computed vector V b_j, and its Rayleigh quotient (NaN where not a candidate)
+  std::vector<double> rho(r, NAN), phin2(r, 1.0), rq(theta);
   {
-    const int cw = std::min(n_sel, 512);
+    const int cw = std::min(n_sel0, 512);
     DevBuf bsel, phi, hphi, dth, dperm;
-    DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
+    if (!phi_all) DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
     DACP_HIP(ctx, phi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
     DACP_HIP(ctx, hphi.alloc(static_cast<size_t>(D) * cw * sizeof(double)));
     DACP_HIP(ctx, dth.alloc(sizeof(double) * cw));
     DACP_HIP(ctx, dperm.alloc(sizeof(int) * cw));
     const int nblk = dacp::coldots_blocks(D, 2 * cw);
-    st = ensure_red(ctx, static_cast<size_t>(nblk) * 2 * cw, 2 * cw);
+    st = ensure_red(ctx, static_cast<size_t>(nblk) * 3 * cw, 3 * cw);
     if (st) return st;
-    std::vector<double> out(2 * cw);
-    for (int c0 = 0; c0 < n_sel; c0 += cw) {
-      const int w = std::min(cw, n_sel - c0);
-      std::vector<int> pr(order.begin() + c0, order.begin() + c0 + w);
+    std::vector<double> out(3 * cw);
+    for (int c0 = 0; c0 < n_sel0; c0 += cw) {
+      const int w = std::min(cw, n_sel0 - c0);
+      std::vector<int> pr(order0.begin() + c0, order0.begin() + c0 + w);
       std::vector<double> th(w);
       for (int i = 0; i < w; ++i) th[i] = theta[pr[i]];
-      DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
       DACP_TRY(to_device(ctx, dth.p, th.data(), sizeof(double) * w));
-      DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, w, m,
-                                             s));
-      // Phi = V B_sel  (D x w)
-      DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, V, m, bsel.as<double>(), m, 0.0,
-                                       phi.as<double>(), w, 0, s));
+      if (phi_all) {
+        DACP_HIP(ctx, dacp::launch_copy_cols(phi_all + c0, n_sel0, phi.as<double>(), w, D, w, s));
+      } else {
+        DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
+        DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, w,
+                                               m, s));
+        // Phi = V B_sel  (D x w)
+        DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, V, m, bsel.as<double>(), m, 0.0, phi.as<double>(), w, 0,
+                                         s));
+      }
       st = step<double>(ctx, h, w, phi.as<double>(), w, hphi.as<double>(), w, 1.0);
       if (st) return st;
       DACP_HIP(ctx, dacp::launch_resid(phi.as<double>(), hphi.as<double>(), w, dth.as<double>(), D, w, ctx->red,
                                        dacp::coldots_blocks(D, 2 * w), ctx->red_out, s));
-      DACP_TRY(to_host(ctx, out.data(), ctx->red_out, sizeof(double) * 2 * w));
-      DACP_HIP(ctx, hipStreamSynchronize(s));
+      DACP_TRY(to_host(ctx, out.data(), ctx->red_out, sizeof(double) * 3 * w));
       for (int i = 0; i < w; ++i) {
-        rnorm[c0 + i] = std::sqrt(out[2 * i] / out[2 * i + 1]);
-        phin2[c0 + i] = out[2 * i + 1];
+        const int j = pr[i];
+        // r = H x - theta x with x = V b_j.  The Rayleigh quotient of the computed x is
+        // theta + x.r / x.x; the residual taken about it is no larger than ||r|| / ||x||.
+        rho[j] = std::sqrt(out[3 * i] / out[3 * i + 1]);
+        phin2[j] = out[3 * i + 1];
+        rq[j] = theta[j] + out[3 * i + 2] / out[3 * i + 1];
       }
     }
   }
+  // The Ritz values of the projected problem carry the rounding of App. C's ill-conditioned
+  // overlap matrix; the Rayleigh quotients of the computed Ritz vectors do not, and the residual
+  // bounds hold for them.  The candidates therefore take their Rayleigh quotients, and the rule
+  // runs on the re-sorted values; the candidates are the leading positions of the new (|theta|,
+  // theta) order up to the first value that is not one.
+  std::vector<int> srt(r);
+  std::iota(srt.begin(), srt.end(), 0);
+  std::stable_sort(srt.begin(), srt.end(), [&](int x, int y) { return rq[x] < rq[y]; });
+  std::vector<double> ths(r);
+  for (int i = 0; i < r; ++i) ths[i] = rq[srt[i]];
+  const std::vector<int> order = central_order(ths);
+  int n_sel = 0;
+  while (n_sel < r && !std::isnan(rho[srt[order[n_sel]]])) ++n_sel;
+  std::vector<double> rnorm(n_sel);
+  for (int q = 0; q < n_sel; ++q) rnorm[q] = rho[srt[order[q]]];
   // acceptance (the rule is described at accept_rule)
-  const AcceptResult ar = accept_rule(theta, order, n_sel, rnorm, a, tol);
+  const AcceptResult ar = accept_rule(ths, order, n_sel, rnorm, a, tol);
   const std::vector<char> &ok = ar.ok, &ghost = ar.ghost;
   const std::vector<double> &est = ar.est;
   const std::vector<int> &core_idx = ar.core_idx;
@@ -1699,17 +1949,16 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
     for (int q = 0; q < n_sel && shown < 6; ++q) {
       if (ok[order[q]] || ghost[order[q]]) continue;
       const int j = order[q];
-      const double gl = j > 0 ? theta[j] - theta[j - 1] : INFINITY;
-      const double gr = j + 1 < r ? theta[j + 1] - theta[j] : INFINITY;
+      const double gl = j > 0 ? ths[j] - ths[j - 1] : INFINITY;
+      const double gr = j + 1 < r ? ths[j + 1] - ths[j] : INFINITY;
       vlog("rejected #%d (|theta| rank %d): theta=%.10g r=%.3g est=%.3g gaps=(%.3g, %.3g) tol=%.3g", shown, q,
-           theta[j], rnorm[q], est[q], gl, gr, tol);
+           ths[j], rnorm[q], est[q], gl, gr, tol);
       ++shown;
     }
     int n_ok = 0;
     for (int q = 0; q < n_sel; ++q) n_ok += ok[order[q]] ? 1 : 0;
     vlog("accepted (any position) %d of %d candidates; ghosts %d; contiguous core %d", n_ok, n_sel, n_ghost, core);
   }
-  accepted = core;
   rep.n_candidates = n_sel;
   rep.n_accepted = core;
   rep.max_err_est = max_est;
@@ -1718,8 +1967,11 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
   vlog("acceptance done: %.1f ms, %d accepted of %d candidates", rep.t_accept_ms, core, n_sel);
   accepted = core;
   if (core >= N) {
-    std::vector<std::tuple<double, double, int>> sel;  // (theta, estimate, position in order)
-    for (int i = 0; i < N; ++i) sel.push_back({theta[order[core_idx[i]]], est[core_idx[i]], core_idx[i]});
+    std::vector<std::tuple<double, double, int>> sel;  // (value, estimate, Ritz index into theta and B)
+    for (int i = 0; i < N; ++i) {
+      const int q = core_idx[i];
+      sel.push_back({ths[order[q]], est[q], srt[order[q]]});
+    }
     std::sort(sel.begin(), sel.end());
     for (int i = 0; i < N; ++i) {
       eigs_out[i] = std::get<0>(sel[i]);
@@ -1731,24 +1983,31 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
       // 1 / ||V b_j|| (the Ritz vectors are orthonormal only up to the S cut-off's rounding).
       const int cw = std::min(N, 512);
       DevBuf bsel, dperm, dscale;
-      DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
+      if (!phi_all) DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(cw) * m * sizeof(double)));
       DACP_HIP(ctx, dperm.alloc(sizeof(int) * cw));
       DACP_HIP(ctx, dscale.alloc(sizeof(double) * cw));
+      std::vector<int> pos0(r, -1);  // Ritz index -> candidate column of phi_all
+      for (int c = 0; c < n_sel0; ++c) pos0[order0[c]] = c;
       for (int c0 = 0; c0 < N; c0 += cw) {
         const int w = std::min(cw, N - c0);
         std::vector<int> pr(w);
         std::vector<double> sc(w);
         for (int i = 0; i < w; ++i) {
-          const int q = std::get<2>(sel[c0 + i]);
-          pr[i] = order[q];
-          sc[i] = 1.0 / std::sqrt(phin2[q]);
+          const int j = std::get<2>(sel[c0 + i]);
+          pr[i] = phi_all ? pos0[j] : j;
+          sc[i] = 1.0 / std::sqrt(phin2[j]);
         }
         DACP_TRY(to_device(ctx, dperm.p, pr.data(), sizeof(int) * w));
         DACP_TRY(to_device(ctx, dscale.p, sc.data(), sizeof(double) * w));
-        DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(),
-                                               dscale.as<double>(), w, m, s));
-        DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, V, m, bsel.as<double>(), m, 0.0, vecs_out + c0, ldvec, 0,
-                                         s));
+        if (phi_all) {
+          DACP_HIP(ctx, dacp::launch_gather_cols(phi_all, n_sel0, dperm.as<int>(), dscale.as<double>(), D, w,
+                                                 vecs_out + c0, ldvec, s));
+        } else {
+          DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(),
+                                                 dscale.as<double>(), w, m, s));
+          DACP_HIP(ctx, dacp::launch_dgemm(0, 1, D, w, m, 1.0, V, m, bsel.as<double>(), m, 0.0, vecs_out + c0, ldvec,
+                                           0, s));
+        }
         DACP_HIP(ctx, hipStreamSynchronize(s));  // the host staging of the next chunk reuses dperm / dscale
       }
     }
@@ -1786,6 +2045,65 @@ dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, do
 
   return accept_stage(ctx, h, N, a, n_w, tol, norm_est, V, m, r, theta, bc, rep, eigs_out, err_out, accepted,
                       vecs_out, ldvec);
+}
+
+// One attempt in moment mode (App. C, Eq. shift), after the filter: moments during an evolution to
+// 2 k_n + 1 and S, P from them; the subspace solve; the candidates' Ritz vectors from a second
+// evolution to k_n (no basis stored); then the acceptance on those vectors.  The evolution times
+// of both passes go to t_evol_ms (S and P come out of the first), t_project_ms stays 0.
+dacp_status moment_attempt(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, const dacp_basis_params &bp,
+                           double a, double n_w, double tol, double norm_est, DevBuf &psi, dacp_report &rep,
+                           double *eigs_out, double *err_out, int &accepted, double *vecs_out, int64_t ldvec) {
+  const int64_t D = h->D;
+  const int m = bp.b * (2 * bp.n + 1);
+  double t0 = now_ms();
+  EvolStats es;
+  std::vector<double> theta;
+  DevBuf bc;
+  int r = 0;
+  {
+    DevBuf sb, pb;
+    DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+    DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+    int m_got = 0;
+    DACP_TRY(run_moment_basis(ctx, h, &bp, psi.as<double>(), sb.as<double>(), pb.as<double>(), m, &m_got, &es));
+    rep.t_evol_ms = now_ms() - t0;
+    vlog("moment evolution done: %.1f ms (%lld steps)", rep.t_evol_ms, static_cast<long long>(es.steps));
+    t0 = now_ms();
+    DACP_TRY(run_rr(ctx, m, sb.as<double>(), pb.as<double>(), m, o.eps > 0.0 ? o.eps : 1e-12, theta, &bc, &r));
+  }
+  rep.rank = r;
+  rep.t_gep_ms = now_ms() - t0;
+  rep.t_project_ms = 0.0;
+  vlog("subspace solve done: %.1f ms, rank %d", rep.t_gep_ms, r);
+  // candidates (the same set accept_stage takes) and their Ritz vectors by a second evolution
+  const std::vector<int> order0 = central_order(theta);
+  const int n_sel0 = std::min(r, N + std::max(64, N / 8));
+  size_t free_b = 0, total_b = 0;
+  DACP_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
+  const double need = static_cast<double>(D) * n_sel0 * 8.0;
+  if (need > 0.9 * static_cast<double>(free_b))
+    return set_err(ctx, DACP_E_NOMEM, "moment mode: the candidates' Ritz vectors (D x " + std::to_string(n_sel0) +
+                                          " FP64) do not fit in free device memory");
+  t0 = now_ms();
+  DevBuf bsel, phi, dperm;
+  DACP_HIP(ctx, bsel.alloc(static_cast<size_t>(n_sel0) * m * sizeof(double)));
+  DACP_HIP(ctx, dperm.alloc(sizeof(int) * std::max(1, n_sel0)));
+  DACP_TRY(to_device(ctx, dperm.p, order0.data(), sizeof(int) * n_sel0));
+  DACP_HIP(ctx, dacp::launch_gather_rows(bc.as<double>(), m, bsel.as<double>(), m, dperm.as<int>(), nullptr, n_sel0, m,
+                                         ctx->stream));
+  DACP_HIP(ctx, phi.alloc(static_cast<size_t>(D) * n_sel0 * sizeof(double)));
+  DACP_TRY(moment_ritz_vectors(ctx, h, &bp, psi.as<double>(), bsel.as<double>(), n_sel0, phi.as<double>(), &es));
+  bsel.release();
+  psi.release();
+  rep.t_evol_ms += now_ms() - t0;
+  rep.evol_steps = es.steps;
+  rep.evol_launches = es.launches;
+  rep.evol_kernel_ms = es.kernel_ms;
+  rep.evol_group = es.group;
+  vlog("Ritz vectors by the second evolution: %.1f ms", now_ms() - t0);
+  return accept_stage(ctx, h, N, a, n_w, tol, norm_est, nullptr, m, r, theta, bc, rep, eigs_out, err_out, accepted,
+                      vecs_out, ldvec, phi.as<double>());
 }
 
 dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_in, double *eigs_out,
@@ -1858,16 +2176,31 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
     rep.t_filter_ms = now_ms() - t0;
     vlog("filter done: %.1f ms", rep.t_filter_ms);
 
-    // evolution basis (Sec. II.B, App. B/C)
-    t0 = now_ms();
-    DevBuf vbuf;
-    DACP_HIP(ctx, vbuf.alloc(static_cast<size_t>(D) * m * sizeof(double)));
     dacp_basis_params bp;
     bp.e_bound = e_b;
     bp.a = a;
     bp.n = n;
     bp.b = b;
     bp.group = o.group;
+    if (o.moment_mode) {
+      st = moment_attempt(ctx, h, N, o, bp, a, n_w, tol, norm_est, psi, rep, eigs_out, err_out, accepted, vecs_out,
+                          ldvec);
+      if (st) return st;
+      if (accepted >= N) {
+        if (n_out) *n_out = N;
+        rep.t_total_ms = now_ms() - t_start;
+        if (report) *report = rep;
+        return DACP_OK;
+      }
+      if (attempt >= o.max_retries) break;
+      window_ratio *= 1.5;
+      continue;
+    }
+
+    // evolution basis (Sec. II.B, App. B/C)
+    t0 = now_ms();
+    DevBuf vbuf;
+    DACP_HIP(ctx, vbuf.alloc(static_cast<size_t>(D) * m * sizeof(double)));
     EvolStats es;
     int m_got = 0;
     st = run_basis(ctx, h, &bp, psi.as<double>(), vbuf.as<double>(), m, &m_got, &es);

@@ -183,9 +183,22 @@ hipError_t launch_convert_f32_to_f64(const float *x, int64_t ldx, double *y, int
                                      hipStream_t s);
 hipError_t launch_philox_gauss(double *out, int64_t D, int b, uint64_t seed, hipStream_t s);
 hipError_t launch_axpby(double *y, const double *x, double a, double bcoef, int64_t n, hipStream_t s);
-// residual: out[2j] = ||hx_j - theta_j x_j||^2 partials, out[2j+1] = ||x_j||^2 partials (2-stage).
+// residual: with r_j = hx_j - theta_j x_j, out[3j] = ||r_j||^2, out[3j+1] = ||x_j||^2,
+// out[3j+2] = x_j . r_j (two stages; partial holds nblk * 3 b doubles).
 hipError_t launch_resid(const double *x, const double *hx, int64_t ld, const double *theta, int64_t D, int b,
                         double *partial, int nblk, double *out, hipStream_t s);
+
+// Moment mode (App. C, Eq. shift; kernels.hip).  out (bx x gy, contiguous) = X^T Y for X (D x bx)
+// and Y (D x gy), bx gy <= 1024; partial holds nblk bx gy doubles, nblk = tall_gram_blocks(D).
+int tall_gram_blocks(int64_t D);
+hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *Y, int64_t ldy, int gy, int64_t D,
+                            double *partial, int nblk, double *out, hipStream_t s);
+// S and P (m x m, m = npan b) of the panels of orders orders[p] from the moment slots (see kernels.hip).
+hipError_t launch_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
+                                  double e_b, double *S, double *P, int64_t ld, hipStream_t s);
+// dst[r][c] = src[r][cols[c]] * scale[c] for r < D, c < w (scale may be null).
+hipError_t launch_gather_cols(const double *src, int64_t lds, const int *cols, const double *scale, int64_t D, int w,
+                              double *dst, int64_t ldd, hipStream_t s);
 
 // FP64 MFMA GEMM (gemm.hip).  C = alpha op(A) op(B) + beta C, row-major.
 // upper: only output tiles with tile_row <= tile_col (symmetric results).

@@ -963,7 +963,7 @@ hipError_t launch_coldots(const void *x, int64_t ldx, const void *y, int64_t ldy
 
 __global__ __launch_bounds__(256) void k_resid(const double *x, const double *hx, int64_t ld, const double *theta,
                                                int64_t D, int b, double *partial) {
-  __shared__ double sm[2][256];
+  __shared__ double sm[3][256];
   const int cpt = b < 256 ? b : 256;
   const int rstride = 256 / cpt;
   const int tid = threadIdx.x;
@@ -975,7 +975,7 @@ __global__ __launch_bounds__(256) void k_resid(const double *x, const double *hx
   if (rend > D) rend = D;
   for (int jc = 0; jc < b; jc += cpt) {
     const int j = jc + j0;
-    double ar = 0.0, ax = 0.0;
+    double ar = 0.0, ax = 0.0, axr = 0.0;
     if (r0 < rstride && j < b) {
       const double th = theta[j];
       for (int64_t r = rbeg + r0; r < rend; r += rstride) {
@@ -983,19 +983,24 @@ __global__ __launch_bounds__(256) void k_resid(const double *x, const double *hx
         const double rv = hx[r * ld + j] - th * xv;
         ar += rv * rv;
         ax += xv * xv;
+        axr += xv * rv;
       }
     }
     sm[0][tid] = ar;
     sm[1][tid] = ax;
+    sm[2][tid] = axr;
     __syncthreads();
     if (r0 == 0 && j < b) {
-      double s0 = 0.0, s1 = 0.0;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int q = 0; q < rstride; ++q) {
         s0 += sm[0][q * cpt + j0];
         s1 += sm[1][q * cpt + j0];
+        s2 += sm[2][q * cpt + j0];
       }
-      partial[static_cast<int64_t>(blockIdx.x) * 2 * b + 2 * j] = s0;
-      partial[static_cast<int64_t>(blockIdx.x) * 2 * b + 2 * j + 1] = s1;
+      double *o = partial + static_cast<int64_t>(blockIdx.x) * 3 * b + 3 * j;
+      o[0] = s0;
+      o[1] = s1;
+      o[2] = s2;
     }
     __syncthreads();
   }
@@ -1004,7 +1009,115 @@ __global__ __launch_bounds__(256) void k_resid(const double *x, const double *hx
 hipError_t launch_resid(const double *x, const double *hx, int64_t ld, const double *theta, int64_t D, int b,
                         double *partial, int nblk, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_resid, dim3(nblk), dim3(256), 0, s, x, hx, ld, theta, D, b, partial);
-  hipLaunchKernelGGL(k_reduce_partials, dim3((2 * b + 255) / 256), dim3(256), 0, s, partial, nblk, 2 * b, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((3 * b + 255) / 256), dim3(256), 0, s, partial, nblk, 3 * b, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Moment mode (App. C, Eq. shift).
+// ---------------------------------------------------------------------------
+// Tall Gram block X^T Y of X (D x bx, row stride ldx) and Y (D x gy, stride ldy): each workgroup
+// sums a range of rows into partial[blk][i gy + j]; rows are staged 32 at a time through LDS with
+// coalesced loads, and each thread accumulates its (i, j) pairs over them in row order.
+constexpr int kGramRows = 32;
+__global__ __launch_bounds__(256) void k_tall_gram(const double *X, int64_t ldx, int bx, const double *Y, int64_t ldy,
+                                                   int gy, int64_t D, double *partial) {
+  extern __shared__ double gsm[];
+  double *xs = gsm;                    // kGramRows x bx
+  double *ys = gsm + kGramRows * bx;   // kGramRows x gy
+  const int npair = bx * gy;
+  const int64_t rows_per = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t rbeg = static_cast<int64_t>(blockIdx.x) * rows_per;
+  const int64_t rend = rbeg + rows_per < D ? rbeg + rows_per : D;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // pairs tid, tid + 256, ... (npair <= 1024)
+  for (int64_t r0 = rbeg; r0 < rend; r0 += kGramRows) {
+    const int nr = static_cast<int>(rend - r0 < kGramRows ? rend - r0 : kGramRows);
+    for (int e = threadIdx.x; e < nr * bx; e += 256) {
+      const int rr = e / bx, c = e - rr * bx;
+      xs[e] = X[(r0 + rr) * ldx + c];
+    }
+    for (int e = threadIdx.x; e < nr * gy; e += 256) {
+      const int rr = e / gy, c = e - rr * gy;
+      ys[e] = Y[(r0 + rr) * ldy + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int pr = threadIdx.x + q * 256;
+      if (pr < npair) {
+        const int i = pr / gy, j = pr - (pr / gy) * gy;
+        double a = acc[q];
+        for (int rr = 0; rr < nr; ++rr) a += xs[rr * bx + i] * ys[rr * gy + j];
+        acc[q] = a;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int pr = threadIdx.x + q * 256;
+    if (pr < npair) partial[static_cast<int64_t>(blockIdx.x) * npair + pr] = acc[q];
+  }
+}
+
+int tall_gram_blocks(int64_t D) {
+  int64_t nb = D / 1024;
+  if (nb < 1) nb = 1;
+  if (nb > 1024) nb = 1024;
+  return static_cast<int>(nb);
+}
+
+hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *Y, int64_t ldy, int gy, int64_t D,
+                            double *partial, int nblk, double *out, hipStream_t s) {
+  if (bx < 1 || gy < 1 || bx * gy > 1024) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * kGramRows * (bx + gy);
+  hipLaunchKernelGGL(k_tall_gram, dim3(nblk), dim3(256), lds, s, X, ldx, bx, Y, ldy, gy, D, partial);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((bx * gy + 255) / 256), dim3(256), 0, s, partial, nblk, bx * gy, out);
+  return hipGetLastError();
+}
+
+// S and P (m x m, m = npan b, row stride ld) of the panels T_x(G) psi_E, x = orders[p], from the
+// recorded moments mu (slot idx_of[k], b x b row-major per slot): block (p, q) of S is
+// (mu_{x+y} + mu_{|x-y|}) / 2 and block (p, q) of P is
+// e_b (mu_{x+y+1} + mu_{|x-y-1|} + mu_{x+|y-1|} + mu_{|x-|y-1||}) / 4 (H = e_b T_1(G)).
+__global__ void k_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int m,
+                                  double e_b, double *S, double *P, int64_t ld) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(m) * m) return;
+  const int row = static_cast<int>(e / m), col = static_cast<int>(e - static_cast<int64_t>(row) * m);
+  const int p = row / b, i = row - p * b, q = col / b, j = col - q * b;
+  const int64_t x = orders[p], y = orders[q];
+  const int64_t ym = y >= 1 ? y - 1 : 1;
+  auto at = [&](int64_t k) { return mu[static_cast<int64_t>(idx_of[k < 0 ? -k : k]) * b * b + i * b + j]; };
+  S[row * ld + col] = 0.5 * (at(x + y) + at(x - y));
+  P[row * ld + col] = 0.25 * e_b * (at(x + y + 1) + at(x - y - 1) + at(x + ym) + at(x - ym));
+}
+
+hipError_t launch_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
+                                  double e_b, double *S, double *P, int64_t ld, hipStream_t s) {
+  const int m = b * npan;
+  const int64_t n = static_cast<int64_t>(m) * m;
+  hipLaunchKernelGGL(k_moment_assemble, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, mu, idx_of,
+                     orders, b, m, e_b, S, P, ld);
+  return hipGetLastError();
+}
+
+// dst[r][c] = src[r][cols[c]] * scale[c] (scale may be null).
+__global__ void k_gather_cols(const double *src, int64_t lds, const int *cols, const double *scale, int64_t D, int w,
+                              double *dst, int64_t ldd) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= D * w) return;
+  const int64_t r = e / w;
+  const int c = static_cast<int>(e - r * w);
+  const double v = src[r * lds + cols[c]];
+  dst[r * ldd + c] = scale ? v * scale[c] : v;
+}
+
+hipError_t launch_gather_cols(const double *src, int64_t lds, const int *cols, const double *scale, int64_t D, int w,
+                              double *dst, int64_t ldd, hipStream_t s) {
+  const int64_t n = D * w;
+  hipLaunchKernelGGL(k_gather_cols, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, src, lds, cols,
+                     scale, D, w, dst, ldd);
   return hipGetLastError();
 }
 

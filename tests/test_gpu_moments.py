@@ -1,0 +1,145 @@
+"""Moment mode (App. C, Eq. shift) of the HIP path against the oracle (MI355X).
+
+  * dacp_basis_moments: S and P of the uniform-grid basis assembled from the b x b Chebyshev moments
+    against the oracle's moment assembly and against the explicit A^T A, A^T H A of the same panels
+    (small grids, a grid whose step is 2, and the fused split kernels at L = 16).
+    Tolerance: each moment is a sum over D terms of products of unit-scale values, so like the
+    explicit projection 1e-13 D relative to max |S| (and max |P|).
+  * dacp_central_eigs with opts.moment_mode = 1 (no stored basis; the candidates' Ritz vectors from a
+    second evolution) against the dense oracle and Jordan-Wigner, and its eigenvectors against the
+    dense eigenvectors.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import central, chebyshev, hamiltonian, subspace  # noqa: E402
+from paper_2011_02107_amd import binding as B  # noqa: E402
+from paper_2011_02107_amd import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+EPS = 2.220446049250313e-16
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("L,b,a_r,n,terms_of", [
+    (8, 4, 0.2, 3, lambda L: inputs.ising_chain(L)),
+    (9, 8, 0.9, 4, lambda L: inputs.spin_glass(L, 2)),      # grid step 2: recorded orders overlap
+    (10, 3, 0.05, 2, lambda L: inputs.spin_glass(L, 4)),    # b not a power of two
+])
+def test_basis_moments_match_the_oracle(ctx, L, b, a_r, n, terms_of):
+    terms = terms_of(L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    e_b = 1.01 * hamiltonian.sum_abs_coeff(terms)
+    psi = np.random.default_rng(L).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0, keepdims=True)
+    m = b * (2 * n + 1)
+    S = torch.zeros((m, m + 3), dtype=torch.float64, device=DEV)
+    P = torch.zeros((m, m + 3), dtype=torch.float64, device=DEV)
+    got_m = B.dacp_basis_moments(ctx, ham, torch.as_tensor(psi, device=DEV), S, P, e_b, a_r * e_b, n)
+    assert got_m == m
+    Sg, Pg = _host(S)[:, :m], _host(P)[:, :m]
+    apply = lambda X: hamiltonian.apply_h(L, terms, X)
+    delta, ks = chebyshev.uniform_sample_orders(a_r, n)
+    orders = chebyshev.panel_orders(ks)
+    mu = chebyshev.chebyshev_moments(apply, psi, e_b, 2 * ks[-1] + 1)
+    So, Po = chebyshev.moment_projection(mu, orders, e_b)
+    V = chebyshev.basis_on_orders(apply, psi, e_b, orders)
+    Se, Pe = subspace.project(apply, V)
+    D = 1 << L
+    for got, ref in ((Sg, So), (Pg, Po), (Sg, Se), (Pg, Pe)):
+        assert np.abs(got - ref).max() <= 1e-13 * D * np.abs(ref).max()
+    assert np.array_equal(Sg, Sg.T) and np.array_equal(Pg, Pg.T)
+
+
+def test_basis_moments_fused_kernels_L16(ctx):
+    """At L = 16 the evolution runs the fused split kernels; moments against the oracle's."""
+    L, b, a_r, n = 16, 8, 0.3, 2
+    terms = inputs.ising_chain(L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    e_b = 1.01 * hamiltonian.sum_abs_coeff(terms)
+    psi = np.random.default_rng(7).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0, keepdims=True)
+    m = b * (2 * n + 1)
+    S = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    P = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    B.dacp_basis_moments(ctx, ham, torch.as_tensor(psi, device=DEV), S, P, e_b, a_r * e_b, n)
+    apply = lambda X: hamiltonian.apply_h(L, terms, X)
+    delta, ks = chebyshev.uniform_sample_orders(a_r, n)
+    mu = chebyshev.chebyshev_moments(apply, psi, e_b, 2 * ks[-1] + 1)
+    So, Po = chebyshev.moment_projection(mu, chebyshev.panel_orders(ks), e_b)
+    D = 1 << L
+    assert np.abs(_host(S) - So).max() <= 1e-13 * D * np.abs(So).max()
+    assert np.abs(_host(P) - Po).max() <= 1e-13 * D * np.abs(Po).max()
+
+
+def _check(got, errs, ref, norm, N, label):
+    assert len(got) == N, label
+    err = np.abs(np.sort(got) - ref)
+    assert err.max() <= 1e-10 * norm, f"{label}: {err.max():.2e}"
+    assert not (err > np.asarray(errs) + 64 * EPS * norm).any(), f"{label}: estimate below the true error"
+
+
+@pytest.mark.parametrize("label,L,terms,N,b", [
+    ("chain L10", 10, inputs.ising_chain(10), 100, 4),
+    ("glass L12", 12, inputs.spin_glass(12, 0), 200, 8),
+])
+def test_central_eigs_moment_mode_against_dense_oracle(ctx, label, L, terms, N, b):
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=b, moment_mode=1))
+    _check(eigs, errs, ref, norm, N, label)
+    e2, _, rep2, _ = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=b))
+    print(f"{label}: moment mode m {rep['m']} rank {rep['rank']} core {rep['n_accepted']} evolution steps "
+          f"{rep['evol_steps']} (stored basis: rank {rep2['rank']} core {rep2['n_accepted']} steps {rep2['evol_steps']})")
+
+
+def test_central_eigs_moment_mode_jw_twin_L16(ctx):
+    """The integrable chain at L = 16, N = 1000, b = 64, FP32 filter + FP64 tail, in moment mode:
+    every value against the exact Jordan-Wigner spectrum."""
+    L, N = 16, 1000
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L, hz=0.0))
+    ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
+    o = B.default_opts(b=64, kfac=12.0, basis_ratio=1.2, precision=B.DACP_F32, fp64_tail_frac=0.3, moment_mode=1)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o)
+    _check(eigs, errs, ref, norm, N, "JW twin L16 moment mode")
+
+
+def test_central_eigpairs_moment_mode_vectors(ctx):
+    """Eigenvectors in moment mode (formed by the second evolution): unit, Rayleigh quotient equal to
+    the value, angle to the dense eigenvector within ||r|| / gap."""
+    L, N = 10, 60
+    terms = inputs.spin_glass(L, 3)
+    Hd = hamiltonian.dense_h(L, terms)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    vecs = torch.zeros((1 << L, N), dtype=torch.float64, device=DEV)
+    eigs, errs, rep, st = B.dacp_central_eigpairs(ctx, ham, N, vecs, B.default_opts(b=4, moment_mode=1))
+    _check(eigs, errs, ref, norm, N, "eigpairs moment mode")
+    X = _host(vecs)
+    nrm = np.linalg.norm(X, axis=0)
+    assert np.abs(nrm - 1.0).max() < 1e-9
+    rq = np.einsum("si,si->i", X, Hd @ X)
+    assert np.abs(rq - eigs).max() <= 1e-12 * norm
+    lam, Phi = np.linalg.eigh(Hd)
+    rn = np.linalg.norm(Hd @ X - X * eigs[None, :], axis=0)
+    for i in range(N):
+        k = int(np.argmin(np.abs(lam - eigs[i])))
+        delta = np.abs(np.delete(lam, k) - eigs[i]).min()
+        sin_t = np.linalg.norm(X[:, i] - Phi[:, k] * (Phi[:, k] @ X[:, i]))
+        assert sin_t <= rn[i] / delta * 1.01 + 1e-9

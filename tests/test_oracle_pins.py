@@ -303,6 +303,33 @@ def test_overlap_from_moments_product_identity():
             assert abs(P[i, j] - 0.5 * (mom_h[x + y] + mom_h[abs(x - y)])) < 1e-8
 
 
+def test_moment_projection_matches_explicit_basis_on_the_uniform_grid():
+    """Moment mode (App. C): S and P assembled from the b x b moments mu_k = psi^T T_k(G) psi by
+    the product identity equal the explicit A^T A and A^T H A of the panels on the same uniform
+    grid k_m = m Delta, within the recurrence's rounding; the recorded orders reach 2 k_n + 1."""
+    L = 7
+    terms = inputs.spin_glass(L, 5)
+    apply = lambda X: hamiltonian.apply_h(L, terms, X)
+    lam = central.full_spectrum_dense(L, terms)
+    e_max = 1.01 * np.abs(lam).max()
+    psi = np.random.default_rng(4).standard_normal((1 << L, 3))
+    psi /= np.linalg.norm(psi, axis=0, keepdims=True)
+    delta, ks = chebyshev.uniform_sample_orders(0.3, 4)
+    assert delta % 2 == 0 and ks == [delta * m for m in range(1, 5)]
+    orders = chebyshev.panel_orders(ks)
+    V = chebyshev.basis_on_orders(apply, psi, e_max, orders)
+    S_ex, P_ex = subspace.project(apply, V)
+    mu = chebyshev.chebyshev_moments(apply, psi, e_max, 2 * ks[-1] + 1)
+    S, P = chebyshev.moment_projection(mu, orders, e_max)
+    assert np.abs(S - S_ex).max() < 1e-11 * np.abs(S_ex).max()
+    assert np.abs(P - P_ex).max() < 1e-11 * np.abs(P_ex).max() * 10
+    # moments of exact eigenvectors are diagonal with entries T_k(lambda / E_max)
+    w, Z = _native.jacobi(hamiltonian.dense_h(L, terms), vectors=True)
+    mu_e = chebyshev.chebyshev_moments(apply, Z[:, :2], e_max, 9)
+    for k in (0, 3, 9):
+        assert np.allclose(mu_e[k], np.diag(chebyshev.cheb_scalar(k, w[:2] / e_max)), atol=1e-10)
+
+
 # ---------------------------------------------------------------- subspace diagonalisation
 
 
