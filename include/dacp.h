@@ -259,6 +259,22 @@ dacp_status dacp_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, dou
 dacp_status dacp_syev_batched(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
                               double *const *Z);
 
+/* dacp_syev_batched that allocates nothing, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and errors as dacp_syev_batched (same kernels).  Every device buffer besides A[i] and
+ * Z[i] -- the tridiagonal's eigenvectors, the Householder product, w and beta per matrix, the
+ * convergence flags, the problem table and the sort permutation -- lives in one fixed workspace of
+ * 128 MiB per device, held from the library's first use on that device until the process ends.  A
+ * request fits when 2 sum n[i]^2 + 2 sum n[i] doubles plus small tables fit in it (for example 16
+ * matrices of n = 1000, or one of n = 2048); a larger one returns DACP_E_INVALID with the sizes in
+ * the message, before any device work.  Every call on one device shares that device's workspace
+ * and leaves its contents behind (the flags are cleared at the start of each call): calls that
+ * overlap on one device, from any context or thread, race and must be serialised by the caller.
+ * No hipMalloc, hipFree or allocating library routine is called; host copies of the problem table
+ * and the results still synchronise the context's stream. */
+dacp_status dacp_syev_batched_noalloc(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                                      double *const *Z);
+
 /* C = alpha op(A) op(B) + beta C in FP64 on the matrix cores (row-major;
  * op(A) is M x K: A stored M x K when transA = 0, K x M when transA = 1;
  * op(B) is K x N: B stored K x N when transB = 0, N x K when transB = 1). */

@@ -143,6 +143,7 @@ SIGNATURES = {
     "dacp_syev": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _dp, _vp]),
     "dacp_basis_moments": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(BasisParams), _vp, _vp, _vp, _i64, _ip]),
     "dacp_syev_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "dacp_syev_batched_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "dacp_gemm": (
         ctypes.c_int,
         [_vp, ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _vp, _i64, ctypes.c_double, _vp, _i64],
@@ -369,16 +370,18 @@ def dacp_syev(ctx, A, Z=None):
     return w
 
 
-def dacp_syev_batched(ctx, As, Zs=None):
+def dacp_syev_batched(ctx, As, Zs=None, noalloc=False):
     """Eigen-decompositions of square device matrices `As` (destroyed) in one launch; returns the
-    list of ascending eigenvalue arrays.  Zs: matching device matrices for the eigenvectors (rows)."""
+    list of ascending eigenvalue arrays.  Zs: matching device matrices for the eigenvectors (rows).
+    noalloc: call dacp_syev_batched_noalloc (fixed per-device workspace, no device allocation)."""
     count = len(As)
     ns = (ctypes.c_int * count)(*[int(a.shape[0]) for a in As])
     ws = [np.zeros(int(a.shape[0])) for a in As]
     a_ptrs = (_vp * count)(*[_ptr(a) for a in As])
     w_ptrs = (_vp * count)(*[w.ctypes.data_as(_vp) for w in ws])
     z_ptrs = (_vp * count)(*[(_ptr(z) if z is not None else None) for z in (Zs or [None] * count)])
-    ctx.check(ctx.lib.dacp_syev_batched(ctx.handle, count, ns, a_ptrs, w_ptrs, z_ptrs))
+    fn = ctx.lib.dacp_syev_batched_noalloc if noalloc else ctx.lib.dacp_syev_batched
+    ctx.check(fn(ctx.handle, count, ns, a_ptrs, w_ptrs, z_ptrs))
     return ws
 
 

@@ -16,7 +16,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -652,6 +654,95 @@ dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, 
   DACP_TRY(batch_syev_raw(ctx, count, n, A, zr.data(), q.data(), wr.data()));
   for (int i = 0; i < count; ++i)
     DACP_TRY(batch_syev_finish(ctx, n[i], wr[i], A[i], zr[i], q[i], w[i], Zrows[i]));
+  return DACP_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free form
+//
+// The workspace of dacp_syev_batched_noalloc: one array per device, of a fixed size, held from the
+// module's load until the process ends.  In host code `scratch` names a host-side stand-in, not the
+// device array: host code uses only the address that hipGetSymbolAddress returns for the device
+// that is current (kept per device below).  Every call on one device shares the array.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+bool g_scratch_done[64] = {};
+hipError_t g_scratch_err[64] = {};
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the current device's copy
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = (e == hipSuccess) ? ptr : nullptr;
+    g_scratch_done[device] = true;
+  }
+  return g_scratch_err[device];
+}
+
+size_t batch_syev_noalloc_bytes(int count, const int *n) {
+  size_t wb = 0, zq = 0;
+  int max_n = 0;
+  for (int i = 0; i < count; ++i) {
+    wb += 2 * static_cast<size_t>(n[i]);
+    zq += 2 * static_cast<size_t>(n[i]) * n[i];
+    max_n = std::max(max_n, n[i]);
+  }
+  return round256(sizeof(int) * count) + round256(sizeof(BatchEigProblem) * count) + round256(wb * sizeof(double)) +
+         round256(zq * sizeof(double)) + round256(sizeof(int) * max_n);
+}
+
+dacp_status batch_syev_noalloc(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                               double *const *Zrows) {
+  if (count <= 0) return DACP_OK;
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 1 || n[i] > kBatchEigMaxN) return set_err(ctx, DACP_E_INVALID, "batch_syev: 1 <= n <= 2048");
+  const size_t need = batch_syev_noalloc_bytes(count, n);
+  if (need > kNoAllocScratchBytes)
+    return set_err(ctx, DACP_E_INVALID,
+                   "syev_batched_noalloc: the matrices need " + std::to_string(need) +
+                       " bytes of workspace; the fixed workspace holds " + std::to_string(kNoAllocScratchBytes));
+  const hipError_t e = noalloc_scratch_init(ctx->device);
+  if (e != hipSuccess) return hip_err(ctx, e, "syev_batched_noalloc: hipGetSymbolAddress(scratch)");
+  unsigned char *base = static_cast<unsigned char *>(g_scratch_ptr[ctx->device]);
+  size_t wb = 0, zq = 0;
+  int max_n = 0;
+  for (int i = 0; i < count; ++i) {
+    wb += 2 * static_cast<size_t>(n[i]);
+    zq += 2 * static_cast<size_t>(n[i]) * n[i];
+    max_n = std::max(max_n, n[i]);
+  }
+  BatchEigWork wk;
+  size_t at = 0;
+  wk.stat = reinterpret_cast<int *>(base + at);
+  at += round256(sizeof(int) * count);
+  wk.probs = reinterpret_cast<BatchEigProblem *>(base + at);
+  at += round256(sizeof(BatchEigProblem) * count);
+  wk.wb = reinterpret_cast<double *>(base + at);
+  at += round256(wb * sizeof(double));
+  double *zqb = reinterpret_cast<double *>(base + at);
+  at += round256(zq * sizeof(double));
+  int *dperm = reinterpret_cast<int *>(base + at);
+  std::vector<double *> zr(count), q(count), wr(count);
+  std::vector<std::vector<double>> wraw(count);
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    zr[i] = zqb + off;
+    q[i] = zr[i] + static_cast<size_t>(n[i]) * n[i];
+    off += 2 * static_cast<size_t>(n[i]) * n[i];
+    wraw[i].resize(n[i]);
+    wr[i] = wraw[i].data();
+  }
+  DACP_TRY(batch_syev_raw_on(ctx, count, n, A, zr.data(), q.data(), wr.data(), wk));
+  for (int i = 0; i < count; ++i)
+    DACP_TRY(batch_syev_finish_on(ctx, n[i], wr[i], A[i], zr[i], q[i], w[i], Zrows[i], dperm));
   return DACP_OK;
 }
 

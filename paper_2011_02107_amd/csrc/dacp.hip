@@ -1502,6 +1502,9 @@ dacp_status dacp_create(int device, void *hip_stream, dacp_ctx *out) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
+  // the device's copy of the allocation-free workspace, resolved once per device with it current;
+  // a failure is reported by the entry point that needs it
+  (void)dacp::noalloc_scratch_init(device);
   *out = c;
   return DACP_OK;
 }
@@ -1849,6 +1852,16 @@ dacp_status dacp_syev_batched(dacp_ctx ctx, int count, const int *n, double *con
     if (n[i] < 1 || n[i] > dacp::kBatchEigMaxN || !A[i] || !w[i])
       return set_err(ctx, DACP_E_INVALID, "syev_batched: need 1 <= n <= 2048 and A, w for every matrix");
   return dacp::batch_syev(ctx, count, n, A, w, Z);
+}
+
+dacp_status dacp_syev_batched_noalloc(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                                      double *const *Z) {
+  if (!ctx || count < 0 || (count > 0 && (!n || !A || !w || !Z)))
+    return set_err(ctx, DACP_E_INVALID, "syev_batched_noalloc: args");
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 1 || n[i] > dacp::kBatchEigMaxN || !A[i] || !w[i])
+      return set_err(ctx, DACP_E_INVALID, "syev_batched_noalloc: need 1 <= n <= 2048 and A, w for every matrix");
+  return dacp::batch_syev_noalloc(ctx, count, n, A, w, Z);
 }
 
 dacp_status dacp_gemm(dacp_ctx ctx, int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,

@@ -378,6 +378,15 @@ dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const 
                            double *const *Q, double *const *w);
 dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr, const double *Q,
                               double *w_out, double *Zrows);
+// The allocation-free form (dacp_syev_batched_noalloc): every device buffer besides A and Zrows comes
+// from one fixed device array of kNoAllocScratchBytes per device (beig.hip).  noalloc_scratch_init
+// resolves that device's address once (call it with the device current); batch_syev_noalloc_bytes
+// is the workspace a request needs.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+hipError_t noalloc_scratch_init(int device);
+size_t batch_syev_noalloc_bytes(int count, const int *n);
+dacp_status batch_syev_noalloc(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
+                               double *const *Zrows);
 bool host_tridiag_eig(const double *diag, const double *off, int n, double *w, double *Z);
 dacp_status dc_tridiag(dacp_ctx ctx, int n, const double *d, const double *e, double *w, double *Z);
 }  // namespace dacp
