@@ -74,31 +74,48 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int64_t M, int64_t N, int64_t 
   __shared__ __attribute__((aligned(16))) double As[2][BM][KS];
   __shared__ __attribute__((aligned(16))) double Bs[2][BN][KS];
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so workgroup
-  // b = 8 q + x runs on XCD x.  Each XCD takes whole 8 x 8 blocks of output tiles (super-block
-  // s = 8 (q / 64) + x, tile q % 64 inside it): the tiles resident on one XCD at a time share 8 row
-  // panels of op(A) and 8 column panels of op(B) in its L2.  Upper mode enumerates the super-blocks
-  // with block row <= block column and idles the tiles below the diagonal.
+  // b = 8 q + x runs on XCD x.  Each XCD takes rounds of 64 output tiles (round
+  // s = 8 (q / 64) + x, tile q % 64 inside it), one round resident at a time: mostly whole 8 x 8
+  // blocks of tiles, which share 8 row panels of op(A) and 8 column panels of op(B) in its L2.
+  // Upper mode takes the blocks strictly above the diagonal first, then the upper triangles of the
+  // diagonal blocks (36 tiles each) packed 64 tiles to a round, so no round idles 28 of its
+  // workgroups on the tiles below the diagonal.
   const int tmc = static_cast<int>((M + BM - 1) / BM);
   const int sbm = (tmc + 7) / 8, sbn = (ntn + 7) / 8;
   const int bid = blockIdx.x;
   const int slot = bid >> 3, x = bid & 7;
   int sb = (slot >> 6) * 8 + x;
   const int t64 = slot & 63;
-  int si, sj;
+  int tm, tn;
   if (upper) {
-    si = 0;
-    while (si < sbm && sb >= sbn - si) {
-      sb -= sbn - si;
-      ++si;
+    const int nfull = sbn * (sbn - 1) / 2;
+    if (sb < nfull) {
+      int si = 0;
+      while (sb >= sbn - 1 - si) {
+        sb -= sbn - 1 - si;
+        ++si;
+      }
+      const int sj = si + 1 + sb;
+      tm = si * 8 + (t64 >> 3);
+      tn = sj * 8 + (t64 & 7);
+    } else {
+      const int d = (sb - nfull) * 64 + t64;  // tile d of the diagonal blocks' upper triangles
+      if (d >= 36 * sbn) return;
+      const int blk = d / 36;
+      int w = d - blk * 36, r = 0;
+      while (w >= 8 - r) {
+        w -= 8 - r;
+        ++r;
+      }
+      tm = blk * 8 + r;
+      tn = blk * 8 + r + w;
     }
-    if (si >= sbm) return;
-    sj = si + sb;
   } else {
     if (sb >= sbm * sbn) return;
-    si = sb / sbn;
-    sj = sb - si * sbn;
+    const int si = sb / sbn, sj = sb - si * sbn;
+    tm = si * 8 + (t64 >> 3);
+    tn = sj * 8 + (t64 & 7);
   }
-  const int tm = si * 8 + (t64 >> 3), tn = sj * 8 + (t64 & 7);
   if (tm >= tmc || tn >= ntn || (upper && tm > tn)) return;
   const int64_t m0 = static_cast<int64_t>(tm) * BM;
   const int64_t n0 = static_cast<int64_t>(tn) * BN;
@@ -197,9 +214,10 @@ hipError_t launch_dgemm_impl(int transA, int transB, int64_t M, int64_t N, int64
   if (splits < 1 || (splits > 1 && !work)) return hipErrorInvalidValue;
   if (upper && M != N) return hipErrorInvalidValue;
   const int64_t kchunk = splits == 1 ? K : ((K + splits - 1) / splits + BK - 1) / BK * BK;
-  // super-blocks of 8 x 8 tiles, dealt 8 at a time (one per XCD), 64 workgroups each
+  // rounds of 64 tiles (8 x 8 blocks, or packed diagonal-block triangles in upper mode), dealt 8 at
+  // a time (one per XCD), 64 workgroups each
   const int64_t sbm = (tmc + 7) / 8, sbn = (tnc + 7) / 8;
-  const int64_t nsb = upper ? sbn * (sbn + 1) / 2 : sbm * sbn;
+  const int64_t nsb = upper ? sbn * (sbn - 1) / 2 + (36 * sbn + 63) / 64 : sbm * sbn;
   const int64_t nblocks = 8 * 64 * ((nsb + 7) / 8);
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid(static_cast<unsigned>(nblocks), 1, static_cast<unsigned>(splits)), block(256);
