@@ -428,6 +428,17 @@ dacp_status dacp_spacing_ratios(const double *eigs, int n, double *r_out, double
  * may be NULL) get the winner's group width and its time per column and step. */
 dacp_status dacp_autotune(dacp_ctx ctx, dacp_ham h, int b, int steps, int *best_group, double *best_us_per_column_step);
 
+/* Autotuner of the batched schedule: runs dacp_central_eigs_batched on a sample of the realisations
+ * (every sample_every-th one, plus the first of each L present) for each candidate window ratio
+ * (2.2, 2.5, 2.8), basis ratio (1.3, 1.5) and filter factor kfac (12, 18), with no window retry,
+ * and keeps the fastest candidate whose every sampled realisation reached N on its first window.
+ * A wider window costs larger subspace problems but avoids redoing realisations whose certified
+ * core falls short; kfac trades filter length against the core.  best (host) gets opts_in (may be
+ * NULL: defaults) with those three fields replaced; best_s (host, may be NULL) the sample's time.
+ * Returns DACP_E_WINDOW if no candidate reached N everywhere. */
+dacp_status dacp_autotune_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
+                                  int sample_every, dacp_opts *best, double *best_s);
+
 /* ------------------------------------------------------- learned window */
 
 /* A small regression network (multilayer perceptron: `layers` tanh hidden layers of width
@@ -477,6 +488,17 @@ dacp_status dacp_window_labels(dacp_ctx ctx, int count, const dacp_ham *hams, co
 dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, double bound_margin, int N,
                                       const dacp_opts *opts, double *eigs_out, double *err_out, int *n_out,
                                       dacp_report *report);
+
+/* dacp_central_eigs_batched with every realisation's bound and window predicted by `model` (one
+ * forward pass over all realisations, the formulas of dacp_central_eigs_learned) instead of the
+ * batched Lanczos / KPM launches.  Tolerances are relative to each predicted bound / (1 +
+ * bound_margin).  A realisation whose predicted bound proves below ||H|| (the evolution's norm
+ * guard) or whose accepted core falls short of N is redone alone with the Lanczos / KPM estimates
+ * (reports[r].model_fallback = 1).  reports[r].t_bound_ms is the prediction time.  Arguments,
+ * outputs and errors otherwise as dacp_central_eigs_batched. */
+dacp_status dacp_central_eigs_batched_learned(dacp_ctx ctx, int count, const dacp_ham *hams, dacp_mlp model,
+                                              double bound_margin, int N, const dacp_opts *opts, double *eigs_out,
+                                              double *err_out, int *n_out, dacp_report *reports);
 
 #ifdef __cplusplus
 }

@@ -184,6 +184,16 @@ SIGNATURES = {
         ctypes.c_int,
         [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip, ctypes.POINTER(Report)],
     ),
+    "dacp_autotune_batched": (
+        ctypes.c_int,
+        [_vp, ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(Opts), ctypes.c_int, ctypes.POINTER(Opts),
+         _dp],
+    ),
+    "dacp_central_eigs_batched_learned": (
+        ctypes.c_int,
+        [_vp, ctypes.c_int, ctypes.POINTER(_vp), _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Opts), _dp, _dp, _ip,
+         ctypes.POINTER(Report)],
+    ),
 }
 
 _lib = None
@@ -487,8 +497,9 @@ def dacp_spacing_ratios(eigs):
     return r, mean.value
 
 
-def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True):
-    """Returns (eigs [count, N], errs [count, N], n_out [count], list of report dicts, status)."""
+def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True, model=None, bound_margin=0.05):
+    """Returns (eigs [count, N], errs [count, N], n_out [count], list of report dicts, status).
+    model: a trained Mlp -> dacp_central_eigs_batched_learned with that bound margin."""
     if opts is None:
         opts = default_opts()
     count = len(hams)
@@ -497,12 +508,31 @@ def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True):
     n_out = np.zeros(count, dtype=np.int32)
     reps = (Report * count)()
     handles = (_vp * count)(*[h.handle for h in hams])
-    st = ctx.lib.dacp_central_eigs_batched(
-        ctx.handle, count, handles, int(N), ctypes.byref(opts), _f64(eigs), _f64(errs),
-        n_out.ctypes.data_as(_ip), reps)
+    if model is not None:
+        st = ctx.lib.dacp_central_eigs_batched_learned(
+            ctx.handle, count, handles, model.handle, float(bound_margin), int(N), ctypes.byref(opts), _f64(eigs),
+            _f64(errs), n_out.ctypes.data_as(_ip), reps)
+    else:
+        st = ctx.lib.dacp_central_eigs_batched(
+            ctx.handle, count, handles, int(N), ctypes.byref(opts), _f64(eigs), _f64(errs),
+            n_out.ctypes.data_as(_ip), reps)
     if st != 0 and (raise_on_window or st != -5):
         ctx.check(st)
     return eigs, errs, n_out, [r.as_dict() for r in reps], st
+
+
+def dacp_autotune_batched(ctx, hams, N, opts=None, sample_every=8):
+    """Fastest (window ratio, basis ratio, kfac) that reaches N on the first window on a sample of the
+    realisations; returns (tuned Opts, sample time in s)."""
+    if opts is None:
+        opts = default_opts()
+    count = len(hams)
+    handles = (_vp * count)(*[h.handle for h in hams])
+    best = Opts()
+    t = ctypes.c_double()
+    ctx.check(ctx.lib.dacp_autotune_batched(ctx.handle, count, handles, int(N), ctypes.byref(opts), int(sample_every),
+                                            ctypes.byref(best), ctypes.byref(t)))
+    return best, t.value
 
 
 WINDOW_FEATURES = 8

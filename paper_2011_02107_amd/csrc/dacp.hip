@@ -2537,8 +2537,20 @@ class EigRendezvous {
   long generation_ = 0;
 };
 
-dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
-                                      double *eigs_out, double *err_out, int *n_out, dacp_report *reports) {
+namespace {
+// Per-realisation bounds and windows given by the caller (the learned window): e_b[r] and a[r]
+// replace the Lanczos bound and the density estimate; tolerances are taken relative to
+// e_b[r] / (1 + margin).  A realisation whose bound proves too low (the evolution's norm guard) or
+// whose core falls short is redone alone with the Lanczos / KPM estimates (model_fallback = 1).
+struct BatchWindows {
+  const double *e_b;
+  const double *a;
+  double margin;
+};
+
+dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
+                                 double *eigs_out, double *err_out, int *n_out, dacp_report *reports,
+                                 const BatchWindows *given) {
   if (!ctx || count < 1 || !hams || !eigs_out || !n_out)
     return set_err(ctx, DACP_E_INVALID, "batched: need ctx, count >= 1, hams, eigs_out, n_out");
   int max_L = 0;
@@ -2576,12 +2588,22 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   std::vector<std::vector<double>> mus(count);
   {
     const double tb = now_ms();
-    DACP_TRY(batched_estimates(ctx, count, hams, o, max_L, e_bs, norm_est, mus));
+    if (given) {
+      for (int r = 0; r < count; ++r) {
+        e_bs[r] = given->e_b[r];
+        norm_est[r] = e_bs[r] / (1.0 + given->margin);
+      }
+    } else {
+      DACP_TRY(batched_estimates(ctx, count, hams, o, max_L, e_bs, norm_est, mus));
+    }
     const double t_spec = now_ms() - tb;
     vlog("batched bounds and densities of %d realisations: %.1f ms", count, t_spec);
     const double tp = now_ms();
-    dacp::host_parallel(count, ctx->batch_workers,
-                  [&](int r) { plans[r] = make_plan(o, hams[r]->D, N, e_bs[r], mus[r], window_ratio, 0); });
+    dacp::host_parallel(count, ctx->batch_workers, [&](int r) {
+      dacp_opts orr = o;
+      if (given) orr.a = given->a[r];
+      plans[r] = make_plan(orr, hams[r]->D, N, e_bs[r], mus[r], window_ratio, 0);
+    });
     for (int r = 0; r < count; ++r) {
       std::memset(&rep[r], 0, sizeof(dacp_report));
       tol[r] = o.tol_rel * norm_est[r];
@@ -2672,10 +2694,16 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   const double t_batch = now_ms() - tb0;
   vlog("batched filter + evolution: %d columns of %d realisations in %.1f ms", static_cast<int>(cols.size()), count,
        t_batch);
+  std::vector<char> redo(count, 0);  // given windows only: realisations redone with Lanczos / KPM
   for (int r = 0; r < count; ++r) {
     psi[r].release();
     scr[r].release();
     rep[r].t_evol_ms = t_batch;
+    if (flag[r] && given) {
+      redo[r] = 1;
+      vb[r].release();
+      continue;
+    }
     if (flag[r])
       return set_err(ctx, DACP_E_BOUNDS, "batched: realisation " + std::to_string(r) +
                                              ": |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
@@ -2709,6 +2737,7 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     const double eps = o.eps > 0.0 ? o.eps : 1e-12;
     if (!ctx->batch_eig) {
       for (int r = w; r < count; r += nw) {
+        if (redo[r]) continue;
         const Plan &pl = plans[r];
         wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
                               eigs_out + static_cast<int64_t>(r) * N,
@@ -2727,7 +2756,8 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
       double t0 = 0.0;
     };
     std::vector<int> mine;
-    for (int r = w; r < count; r += nw) mine.push_back(r);
+    for (int r = w; r < count; r += nw)
+      if (!redo[r]) mine.push_back(r);
     std::vector<Fin> F(mine.size());
     auto fail = [&](int r, dacp_status st) {
       wst[r] = st;
@@ -2853,22 +2883,54 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
   for (int r = 0; r < count; ++r)
     if (wst[r]) return set_err(ctx, wst[r], "batched: realisation " + std::to_string(r) + ": " + werr[r]);
 
-  // realisations whose core fell short: the single-realisation path with a wider window
+  // Realisations whose core fell short are redone together in one more batched call with a 1.5x
+  // wider window (up to opts.max_retries times); with given windows, the short ones and those whose
+  // bound proved too low are redone with the Lanczos / KPM estimates (the method's own estimators
+  // are the fallback) and the same window ratio.
   dacp_status worst = DACP_OK;
+  std::vector<int> again;
   for (int r = 0; r < count; ++r) {
     n_out[r] = acc[r] >= N ? N : acc[r];
-    if (acc[r] >= N) continue;
+    if (acc[r] >= N && !redo[r]) {
+      if (given) rep[r].model_used = 1;
+      continue;
+    }
+    again.push_back(r);
+  }
+  if (!again.empty() && (given || o.max_retries > 0)) {
+    const int na = static_cast<int>(again.size());
+    std::vector<dacp_ham> sub(na);
+    for (int i = 0; i < na; ++i) sub[i] = hams[again[i]];
     dacp_opts o2 = o;
-    o2.window_ratio = window_ratio * 1.5;
-    dacp_report r2;
-    int got = 0;
-    const dacp_status st = dacp_central_eigs(ctx, hams[r], N, &o2, eigs_out + static_cast<int64_t>(r) * N,
-                                             err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, &got, &r2);
-    r2.retries += 1;
-    r2.t_bound_ms += rep[r].t_bound_ms;
-    rep[r] = r2;
-    n_out[r] = got;
-    if (st != DACP_OK && worst == DACP_OK) worst = st;
+    if (!given) {
+      o2.window_ratio = window_ratio * 1.5;
+      o2.max_retries = o.max_retries - 1;
+    }
+    std::vector<double> e2(static_cast<size_t>(na) * N), r2e(err_out ? static_cast<size_t>(na) * N : 0);
+    std::vector<int> n2(na, 0);
+    std::vector<dacp_report> rp2(na);
+    vlog("batched: %d realisations redone (%s)", na, given ? "Lanczos / KPM fallback" : "wider window");
+    worst = central_eigs_batched(ctx, na, sub.data(), N, &o2, e2.data(), err_out ? r2e.data() : nullptr, n2.data(),
+                                 rp2.data(), nullptr);
+    if (worst != DACP_OK && worst != DACP_E_WINDOW) return worst;
+    for (int i = 0; i < na; ++i) {
+      const int r = again[i];
+      std::copy(e2.begin() + static_cast<int64_t>(i) * N, e2.begin() + static_cast<int64_t>(i + 1) * N,
+                eigs_out + static_cast<int64_t>(r) * N);
+      if (err_out)
+        std::copy(r2e.begin() + static_cast<int64_t>(i) * N, r2e.begin() + static_cast<int64_t>(i + 1) * N,
+                  err_out + static_cast<int64_t>(r) * N);
+      rp2[i].retries += 1;
+      rp2[i].t_bound_ms += rep[r].t_bound_ms;
+      if (given) {
+        rp2[i].model_used = 1;
+        rp2[i].model_fallback = 1;
+      }
+      rep[r] = rp2[i];
+      n_out[r] = n2[i];
+    }
+  } else if (!again.empty()) {
+    worst = DACP_E_WINDOW;
   }
   const double total = now_ms() - t_start;
   for (int r = 0; r < count; ++r) {
@@ -2876,6 +2938,62 @@ dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *h
     if (reports) reports[r] = rep[r];
   }
   if (worst != DACP_OK) return set_err(ctx, worst, "batched: some realisations fell short of N accepted eigenvalues");
+  return DACP_OK;
+}
+}  // namespace
+
+dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
+                                      double *eigs_out, double *err_out, int *n_out, dacp_report *reports) {
+  return central_eigs_batched(ctx, count, hams, N, opts_in, eigs_out, err_out, n_out, reports, nullptr);
+}
+
+dacp_status dacp_autotune_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
+                                  int sample_every, dacp_opts *best, double *best_s) {
+  if (!ctx || count < 1 || !hams || !best || sample_every < 1)
+    return set_err(ctx, DACP_E_INVALID, "autotune_batched: need ctx, count >= 1, hams, best, sample_every >= 1");
+  dacp_opts o;
+  if (opts_in) o = *opts_in;
+  else dacp_default_opts(&o);
+  // a sample of the realisations, always including one of every L present (the largest L sets the
+  // length of the shared launch)
+  std::vector<dacp_ham> smp;
+  std::set<int> Ls;
+  for (int r = 0; r < count; ++r) {
+    if (!hams[r]) return set_err(ctx, DACP_E_INVALID, "autotune_batched: null Hamiltonian");
+    const bool first_of_L = Ls.insert(hams[r]->L).second;
+    if (first_of_L || r % sample_every == 0) smp.push_back(hams[r]);
+  }
+  const int ns = static_cast<int>(smp.size());
+  std::vector<double> e(static_cast<size_t>(ns) * N);
+  std::vector<int> n_out(ns);
+  std::vector<dacp_report> rp(ns);
+  double best_t = INFINITY;
+  bool found = false;
+  for (double wr : {2.2, 2.5, 2.8})
+    for (double br : {1.3, 1.5})
+      for (double kf : {12.0, 18.0}) {
+        dacp_opts c = o;
+        c.window_ratio = wr;
+        c.basis_ratio = br;
+        c.kfac = kf;
+        c.max_retries = 0;  // a candidate must reach N on its first window
+        const double t0 = now_ms();
+        const dacp_status st = central_eigs_batched(ctx, ns, smp.data(), N, &c, e.data(), nullptr, n_out.data(),
+                                                    rp.data(), nullptr);
+        const double t = now_ms() - t0;
+        vlog("autotune_batched: window %.1f basis %.1f kfac %.0f: status %d, %.1f ms", wr, br, kf,
+             static_cast<int>(st), t);
+        if (st == DACP_E_WINDOW) continue;
+        if (st != DACP_OK) return st;
+        if (t < best_t) {
+          best_t = t;
+          *best = c;
+          best->max_retries = o.max_retries;
+          found = true;
+        }
+      }
+  if (!found) return set_err(ctx, DACP_E_WINDOW, "autotune_batched: no candidate reached N on its first window");
+  if (best_s) *best_s = best_t * 1e-3;
   return DACP_OK;
 }
 
@@ -2999,6 +3117,45 @@ dacp_status dacp_central_eigs_learned(dacp_ctx ctx, dacp_ham h, dacp_mlp model, 
   }
   if (n_out) *n_out = got;
   if (report) *report = r1;
+  return st;
+}
+
+dacp_status dacp_central_eigs_batched_learned(dacp_ctx ctx, int count, const dacp_ham *hams, dacp_mlp model,
+                                              double bound_margin, int N, const dacp_opts *opts_in, double *eigs_out,
+                                              double *err_out, int *n_out, dacp_report *reports) {
+  if (!ctx || count < 1 || !hams || !model || !eigs_out || !n_out || !(bound_margin >= 0.0))
+    return set_err(ctx, DACP_E_INVALID, "batched_learned: need ctx, count >= 1, hams, model, eigs_out, n_out, margin >= 0");
+  dacp_opts o;
+  if (opts_in) o = *opts_in;
+  else dacp_default_opts(&o);
+  const double t0 = now_ms();
+  std::vector<double> f(static_cast<size_t>(count) * DACP_WINDOW_FEATURES), y(2 * static_cast<size_t>(count));
+  for (int r = 0; r < count; ++r) {
+    if (!hams[r] || dacp_window_features(hams[r], f.data() + static_cast<size_t>(r) * DACP_WINDOW_FEATURES) != DACP_OK)
+      return set_err(ctx, DACP_E_INVALID, "batched_learned: features of realisation " + std::to_string(r));
+  }
+  DACP_TRY(dacp_mlp_predict(ctx, model, count, f.data(), y.data()));
+  std::vector<double> e_b(count), a(count);
+  for (int r = 0; r < count; ++r) {
+    const dacp_ham h = hams[r];
+    const double sig = std::sqrt(h->sum_sq);
+    const double D = static_cast<double>(h->D);
+    e_b[r] = std::min((1.0 + bound_margin) * sig * std::sqrt(2.0 * h->L * M_LN2) * std::exp(y[2 * r]), h->sum_abs);
+    const double rho0 = D * std::exp(y[2 * r + 1]) / (std::sqrt(2.0 * M_PI) * sig);
+    const double n_w = std::min(D, std::ceil((o.window_ratio > 0.0 ? o.window_ratio : 2.2) * N));
+    a[r] = std::min(0.95 * e_b[r], n_w / (2.0 * rho0));
+    if (!(std::isfinite(e_b[r]) && std::isfinite(a[r]) && a[r] > 0.0 && e_b[r] > a[r]))
+      return set_err(ctx, DACP_E_NUMERIC, "batched_learned: prediction for realisation " + std::to_string(r));
+  }
+  const double t_pred = now_ms() - t0;
+  vlog("batched learned windows of %d realisations: %.2f ms", count, t_pred);
+  BatchWindows bw{e_b.data(), a.data(), bound_margin};
+  dacp_opts o2 = o;
+  o2.tol_rel = o.tol_rel;  // relative to e_b / (1 + margin), see BatchWindows
+  const dacp_status st = central_eigs_batched(ctx, count, hams, N, &o2, eigs_out, err_out, n_out, reports, &bw);
+  if (reports)
+    for (int r = 0; r < count; ++r)
+      if (!reports[r].model_fallback) reports[r].t_bound_ms = t_pred;
   return st;
 }
 

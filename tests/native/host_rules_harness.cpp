@@ -113,6 +113,31 @@ void spacing(std::mt19937_64 &rng) {
   check(dacp_spacing_ratios(bad, 2, nullptr, nullptr) == DACP_E_INVALID, "ratios: n < 3");
 }
 
+void clusters(std::mt19937_64 &rng) {
+  std::uniform_real_distribution<double> u(0.0, 1.0);
+  for (int t = 0; t < 2000; ++t) {
+    const int n = static_cast<int>(rng() % 60);
+    std::vector<double> e;
+    while (static_cast<int>(e.size()) < n) {
+      const double v = u(rng);
+      const int rep = 1 + static_cast<int>(rng() % 6);
+      for (int k = 0; k < rep && static_cast<int>(e.size()) < n; ++k) e.push_back(v + 1e-13 * k);
+    }
+    std::sort(e.begin(), e.end());
+    const int b = 1 + static_cast<int>(rng() % 6);
+    const double tol = 1e-12;
+    // brute force: maximal runs with consecutive gaps <= 2 tol, counted when at least b long
+    int want = 0;
+    for (int i = 0; i < n;) {
+      int j = i + 1;
+      while (j < n && e[j] - e[j - 1] <= 2.0 * tol) ++j;
+      if (j - i >= b) ++want;
+      i = j;
+    }
+    check(dacp::rules::clusters_at_width(e.data(), n, tol, b) == want, "clusters_at_width", t);
+  }
+}
+
 void deflation(std::mt19937_64 &rng) {
   std::uniform_real_distribution<double> u(0.0, 1.0);
   for (int t = 0; t < 2000; ++t) {
@@ -161,6 +186,7 @@ int main() {
   plans(rng);
   acceptance(rng);
   spacing(rng);
+  clusters(rng);
   deflation(rng);
   std::printf("host rules harness: %d failures\n", g_fail);
   return g_fail == 0 ? 0 : 1;

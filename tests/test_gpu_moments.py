@@ -143,3 +143,27 @@ def test_central_eigpairs_moment_mode_vectors(ctx):
         delta = np.abs(np.delete(lam, k) - eigs[i]).min()
         sin_t = np.linalg.norm(X[:, i] - Phi[:, k] * (Phi[:, k] @ X[:, i]))
         assert sin_t <= rn[i] / delta * 1.01 + 1e-9
+
+
+def test_central_eigs_moment_mode_jw_twin_L18_N5000(ctx):
+    """The integrable chain at L = 18 (D = 262144), N = 5000, in the benchmark's tuned options and in
+    moment mode (three evolution passes' worth of steps, no stored basis), every value against the
+    exact Jordan-Wigner spectrum; the stored-basis mode on the same input for comparison."""
+    import time
+
+    L, N = 18, 5000
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L, hz=0.0))
+    ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
+    o = B.default_opts(b=64, kfac=12.0, basis_ratio=1.2, precision=B.DACP_F32, fp64_tail_frac=0.3, moment_mode=1)
+    t0 = time.perf_counter()
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o)
+    t_mom = time.perf_counter() - t0
+    _check(eigs, errs, ref, norm, N, "JW twin L18 moment mode")
+    o.moment_mode = 0
+    t0 = time.perf_counter()
+    e2, errs2, rep2, _ = B.dacp_central_eigs(ctx, ham, N, o)
+    t_exp = time.perf_counter() - t0
+    _check(e2, errs2, ref, norm, N, "JW twin L18 stored basis")
+    print(f"L=18 N=5000: moment mode {t_mom:.1f} s (evolution steps {rep['evol_steps']}, rank {rep['rank']}), "
+          f"stored basis {t_exp:.1f} s (steps {rep2['evol_steps']}, rank {rep2['rank']}); "
+          f"max error {np.abs(eigs - ref).max() / norm:.1e} / {np.abs(e2 - ref).max() / norm:.1e} of ||H||")
