@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--profile-gemm", action="store_true",
                     help="run only the Gram product C = V^T V (V of 2^20 x 4096, FP64 MFMA) three times and "
                          "print one JSON line (for MFMA counter runs)")
+    ap.add_argument("--profile-project", type=int, default=0, metavar="M",
+                    help="run only the projection S = V^T V, P = V^T (H V) of the L = 20 chain on a seeded V of "
+                         "2^20 x M columns, twice, and print one JSON line (for MFMA counter runs at the "
+                         "benchmark's basis size)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="run only a device copy of known size and a short evolution at the workload's shape "
                          "(for hardware-counter runs), print one JSON line and exit")
@@ -245,6 +249,38 @@ def profile_gemm(args):
         rates.append(2.0 * D * m * m / (time.perf_counter() - t0) / 1e12)
     print(json.dumps({"gemm": "C = V^T V", "D": D, "m": m, "flops_per_call": 2 * D * m * m,
                       "tflops": rates, "peak_tflops": 78.6}), flush=True)
+
+
+def profile_project(args):
+    """The projection of the benchmark (Sec. II.C, Eq. (9)) at its real shape: S = V^T V and
+    P = V^T (H V) of the L = 20 chain for a seeded Gaussian V of D = 2^20 rows and m columns, two
+    calls of dacp_project.  S and P are upper-triangle products of D m (m + 1) flops each."""
+    import torch
+
+    from paper_2011_02107_amd import binding as B
+    from paper_2011_02107_amd import inputs
+
+    ctx = B.Context(0)
+    L, m = 20, args.profile_project
+    D = 1 << L
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L))
+    g = torch.Generator(device="cuda").manual_seed(5)
+    V = torch.empty(D, m, dtype=torch.float64, device="cuda")
+    for c0 in range(0, m, 1024):  # fill in slabs: one randn of the whole block would double the peak
+        c1 = min(m, c0 + 1024)
+        V[:, c0:c1] = torch.randn(D, c1 - c0, dtype=torch.float64, device="cuda", generator=g)
+    torch.cuda.empty_cache()  # hand the slab back: the library allocates H V beside V when it fits
+    S = torch.empty(m, m, dtype=torch.float64, device="cuda")
+    P = torch.empty(m, m, dtype=torch.float64, device="cuda")
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.dacp_project(ctx, ham, V, S, P)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    print(json.dumps({"projection": "S = V^T V, P = V^T (H V)", "L": L, "D": D, "m": m,
+                      "flops_per_product": D * m * (m + 1), "s_per_call": times, "peak_tflops": 78.6}), flush=True)
 
 
 def train_window_model(ctx, Ls=(10, 11, 12, 13, 14), per_L=48, seed0=5000):
@@ -472,6 +508,8 @@ def main():
         return profile_kernels(args)
     if args.profile_gemm:
         return profile_gemm(args)
+    if args.profile_project:
+        return profile_project(args)
     if args.workload == "glass_batch96_N200":
         return batch96(args)
     if args.workload == "glass_L18_N3000_learned":

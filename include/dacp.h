@@ -109,6 +109,11 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *   "batch_workers" host threads finishing the realisations of dacp_central_eigs_batched (1..64, default 16)
  *   "batch_eig"   dacp_central_eigs_batched: 1 = the finishing threads' dense eigen-decompositions are
  *                 collected and solved in batched launches (default), 0 = one solver per problem
+ *   "beig_pipe"   batched eigensolver: 1 = on unreduced blocks of 48 rows or more, the QR sweeps
+ *                 of a batch take their shifts at its start and are chased in lockstep, one lane
+ *                 per sweep (default); 0 = one sweep after another
+ *   "beig_sweeps" batched eigensolver: at most this many QR sweeps per batch, 1..8 (default 6;
+ *                 fewer where the rotation buffers would not fit the LDS)
  *   "group"       evolution column-group width when L >= 15 (power of two, default 8)
  *   "filter_group_f64", "filter_group_f32"
  *                 filter column-group width when L >= 15 for the FP64 / FP32 recurrence

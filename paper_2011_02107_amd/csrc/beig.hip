@@ -5,13 +5,19 @@
 //      each step's rank-2 update is applied in the next step's pass over the trailing block);
 //   2. every eigenvalue of the tridiagonal by bisection, one per thread, for the QR shifts;
 //   3. implicit symmetric QR on (d, e), shifted by the nearest eigenvalue not yet deflated (else
-//      Wilkinson's shift), in batches of up to S sweeps: thread 0 chases the bulges of batch b+1
+//      Wilkinson's shift), in batches of up to S sweeps: wave 0 chases the bulges of batch b+1
 //      (the chase carries its running values in registers) while waves 1.. apply the Givens
 //      rotations of batch b to the rows of Zr (rows = eigenvectors of the tridiagonal, starting
-//      from I), one column per thread, all S sweeps in one pass down the column;
-//   4. Q = H_0 H_1 ... H_(n-3) formed explicitly, one thread per column, by the applying waves
-//      while thread 0 chases (the columns of Q need no barrier between Householder steps).
-// The host then sorts the eigenvalues and forms the eigenvectors of A as rows of Zr Q^T.
+//      from I), one column per thread, all S sweeps in one pass down the column.  On a large
+//      unreduced block the S sweeps of a batch take S shifts chosen at its start and run in
+//      lockstep, lane s of wave 0 chasing sweep s a fixed number of rotations behind lane s-1;
+//      small blocks, and the batch after a pipelined one that deflated nothing, chase one sweep
+//      after another on lane 0 with the shift taken after each.
+// Two more launches over every matrix then turn the rows of Zr into eigenvectors of A, Zr Q^T with
+// Q = H_0 H_1 ... H_(n-3), never forming Q: k_wy_prep writes each block of kWY reflectors in
+// compact WY form (the masked rows V and the triangular T), k_wy_apply applies the blocks to Zr
+// from the right, last block first, RB rows of Zr per workgroup held in LDS (rows are
+// independent).  The host sorts the eigenvalues and gathers the rows in that order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,9 +38,13 @@ constexpr int kBWaves = kBT / 64;
 constexpr int kApplyThreads = kBT - 64;  // waves 1.. apply rotations while wave 0 chases
 constexpr int kPrefetch = 8;             // rows of a column loaded ahead of their rotations
 constexpr int kRowBatch = 16;            // rows of a column in flight in the BLAS-2 passes
-constexpr int kQBatch = 8;               // the same while forming Q beside the rotations
 constexpr int kFuseBatch = 8;            // the same in the fused update-and-product pass
 constexpr size_t kLdsMax = 160 * 1024;
+constexpr int kPipeLag = 5;     // rotations between consecutive sweeps of a pipelined batch
+constexpr int kPipeMin = 48;    // smallest unreduced block chased as a pipelined batch
+constexpr int kShiftSlots = 8;  // LDS slots for a pipelined batch's shifts (S <= 8)
+constexpr int kWY = 64;         // reflectors per compact-WY block of the back-transformation
+constexpr int kRB = 8;          // rows of Zr per workgroup of the back-transformation
 
 // Sum over the workgroup, the same value returned to every thread (fixed order: lanes by
 // butterfly, then the waves in index order).  red holds kBWaves doubles.
@@ -154,12 +164,13 @@ __device__ int nearest_unused(const double *lam, const double *used, int n, doub
   return (x - lam[l] <= lam[r] - x) ? l : r;
 }
 
-// Per-matrix state of the QR phase, held by thread 0.
+// Per-matrix state of the QR phase, held by lane 0 of wave 0.
 struct QrState {
   int q;
   long iters, max_iters;
   bool failed;
-  double small;  // off-diagonals at most this (eps times a bound on the norm) count as zero
+  double small;     // off-diagonals at most this (eps times a bound on the norm) count as zero
+  bool pipe_prev;   // the previous batch was pipelined
 };
 
 // Thread 0: up to S sweeps (deflating from the bottom between them) into batch buffer `cs`
@@ -201,6 +212,162 @@ __device__ void chase_batch(QrState &st, double *d, double *e, int n, const doub
     ++cnt;
   }
   mt[0] = cnt;
+}
+
+// Lane 0: the decisions of one batch.  Batch header mt = {count, p_0.., q_0.., pipelined}.
+// Without pipelining, on a block of fewer than kPipeMin rows, or when the previous pipelined batch
+// left nothing to deflate, this is chase_batch (the sweeps run here, one after another).
+// Otherwise it deflates at the bottom, finds the unreduced block [p, q] and picks S shifts: the
+// first as in chase_batch, the others the eigenvalues not yet deflated nearest to it (exact shifts
+// of the block when they belong to it, ordinary shifts otherwise); the sweeps run in
+// chase_pipelined.
+template <int S>
+__device__ void plan_batch(QrState &st, double *d, double *e, int n, const double *lam, double *used, double *cs,
+                           int *mt, double *shifts, bool pipe) {
+  const double eps = 2.220446049250313e-16;
+  mt[1 + 2 * S] = 0;
+  if (!pipe) {
+    chase_batch<S>(st, d, e, n, lam, used, cs, mt);
+    return;
+  }
+  int deflated = 0;
+  while (st.q > 0 && fabs(e[st.q - 1]) <= fmax(st.small, eps * (fabs(d[st.q - 1]) + fabs(d[st.q])))) {
+    e[st.q - 1] = 0.0;
+    const int j = nearest_unused(lam, used, n, d[st.q]);
+    if (j >= 0) used[j] = 1.0;
+    --st.q;
+    ++deflated;
+  }
+  if (st.q == 0 || st.failed) {
+    mt[0] = 0;
+    return;
+  }
+  const int q = st.q;
+  int p = q - 1;
+  while (p > 0 && !(fabs(e[p - 1]) <= fmax(st.small, eps * (fabs(d[p - 1]) + fabs(d[p]))))) --p;
+  if (q - p + 1 < kPipeMin || (st.pipe_prev && deflated == 0)) {
+    st.pipe_prev = false;
+    chase_batch<S>(st, d, e, n, lam, used, cs, mt);
+    return;
+  }
+  if (p > 0) e[p - 1] = 0.0;
+  if (st.iters + S > st.max_iters) {
+    st.failed = true;
+    mt[0] = 0;
+    return;
+  }
+  st.iters += S;
+  const double a = d[q - 1], bb = e[q - 1], cq = d[q];
+  const double delta = 0.5 * (a - cq);
+  const double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * hypot(delta, bb);
+  double mu = (den != 0.0) ? cq - bb * bb / den : cq;
+  int taken[S];
+  int cnt = 0;
+  const int j0 = nearest_unused(lam, used, n, mu);
+  if (j0 >= 0 && fabs(lam[j0] - mu) <= 2.0 * fabs(bb)) {
+    mu = lam[j0];
+    taken[cnt] = j0;
+  } else {
+    taken[cnt] = -1;
+  }
+  shifts[cnt++] = mu;
+  // the unused eigenvalues nearest mu, outward from its position in the ascending list
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) / 2;
+    if (lam[mid] < mu) lo = mid + 1;
+    else hi = mid;
+  }
+  int l = lo - 1, r = lo;
+  auto skip = [&](int i) {
+    if (used[i] != 0.0) return true;
+    for (int t = 0; t < cnt; ++t)
+      if (taken[t] == i) return true;
+    return false;
+  };
+  while (cnt < S) {
+    while (l >= 0 && skip(l)) --l;
+    while (r < n && skip(r)) ++r;
+    int pick;
+    if (l < 0 && r >= n) break;
+    if (l < 0) pick = r;
+    else if (r >= n) pick = l;
+    else pick = (mu - lam[l] <= lam[r] - mu) ? l : r;
+    taken[cnt] = pick;
+    shifts[cnt++] = lam[pick];
+  }
+  mt[0] = cnt;
+  for (int s = 0; s < S; ++s) {
+    mt[1 + s] = p;
+    mt[1 + S + s] = q;
+  }
+  mt[1 + 2 * S] = 1;
+  st.pipe_prev = true;
+}
+
+// All lanes of wave 0: the sweeps of a pipelined batch (header mt, shifts from plan_batch).  Lane
+// s chases sweep s with shift s, kPipeLag rotations behind lane s-1, through the same rotations
+// as qr_sweep.  Lane s reads d[k+3] and e[k+3] at its rotation k; lane s-1 wrote them at its
+// rotations k+3 and k+4, in earlier steps of the loop (kPipeLag >= 5), and lane s+1 reads what
+// lane s writes at rotation k (e[k-1], d[k]) two or more steps later.  The LDS operations of one
+// wave are carried out in order; the empty asm keeps the compiler from moving loads or stores
+// across a step.  The result is that of the S sweeps applied one after another.
+template <int S>
+__device__ void chase_pipelined(double *d, double *e, int n, double *cs, const int *mt, const double *shifts,
+                                int lane) {
+  const int cnt = mt[0], p = mt[1], q = mt[1 + S];
+  const bool mine = lane < cnt;
+  const double mu = mine ? shifts[lane] : 0.0;
+  double *myc = cs + static_cast<size_t>(mine ? lane : 0) * 2 * n;
+  const int T = (q - p) + kPipeLag * (cnt - 1);
+  double dk = 0.0, ek = 0.0, dn = 0.0, en = 0.0, dn2 = 0.0, en2 = 0.0, x = 0.0, z = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const int k = p + t - kPipeLag * lane;
+    if (mine && k >= p && k < q) {
+      if (k == p) {
+        dk = d[p];
+        ek = e[p];
+        dn = d[p + 1];
+        en = e[p + 1];
+        dn2 = d[p + 2];
+        en2 = e[p + 2];
+        x = dk - mu;
+        z = ek;
+      }
+      const double dn3 = d[k + 3], en3 = e[k + 3];
+      double c, sn;
+      givens_fast(x, z, c, sn);
+      if (k > p) e[k - 1] = c * x - sn * z;
+      const double c2 = c * c, s2 = sn * sn, csn = c * sn;
+      d[k] = c2 * dk - 2.0 * csn * ek + s2 * dn;
+      const double ndk1 = s2 * dk + 2.0 * csn * ek + c2 * dn;
+      const double xn = csn * (dk - dn) + (c2 - s2) * ek;
+      if (k == q - 1) {
+        d[q] = ndk1;
+        e[q - 1] = xn;
+      }
+      myc[2 * (k - p)] = c;
+      myc[2 * (k - p) + 1] = sn;
+      x = xn;
+      z = -sn * en;
+      dk = ndk1;
+      ek = c * en;
+      dn = dn2;
+      en = en2;
+      dn2 = dn3;
+      en2 = en3;
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
+// Wave 0: one batch (lane 0 decides; a pipelined batch is then chased by the whole wave).
+template <int S>
+__device__ void chase_wave(QrState &st, double *d, double *e, int n, const double *lam, double *used, double *cs,
+                           int *mt, double *shifts, int lane, bool pipe) {
+  if (lane == 0) plan_batch<S>(st, d, e, n, lam, used, cs, mt, shifts, pipe);
+  asm volatile("" ::: "memory");
+  if (mt[1 + 2 * S]) chase_pipelined<S>(d, e, n, cs, mt, shifts, lane);
 }
 
 // One column of Zr through the batch's sweeps in one pass.  Rotation k of sweep s acts on rows
@@ -268,58 +435,24 @@ __device__ void apply_batch(double *Zr, int n, int col, const double *cs, const 
   }
 }
 
-// Householder step k of forming Q = H_0 H_1 ... H_(n-3) (applied from k = n-3 down to 0 onto I)
-// on the columns of Q that applying thread `a` owns: Q[k+1.., col] -= beta v (v^T Q[k+1.., col]),
-// v from row k of the reduced A.  H_k touches rows and columns k+1.. only, so columns <= k stay
-// those of I.  Every column is independent of the others, so the steps need no barrier.
-__device__ void house_cols(double *Q, const double *A, const double *betas, int n, int k, int a) {
-  const double beta = betas[k];
-  if (beta == 0.0) return;
-  const int m = n - k - 1;
-  const double *v = A + static_cast<int64_t>(k) * n + k + 1;
-  for (int col = a; col < n; col += kApplyThreads) {
-    if (col <= k) continue;
-    double *qc = Q + static_cast<int64_t>(k + 1) * n + col;
-    double t = 0.0;
-    int r = 0;
-    for (; r + kQBatch <= m; r += kQBatch) {
-      double q[kQBatch];
-#pragma unroll
-      for (int u = 0; u < kQBatch; ++u) q[u] = qc[static_cast<int64_t>(r + u) * n];
-#pragma unroll
-      for (int u = 0; u < kQBatch; ++u) t += v[r + u] * q[u];
-    }
-    for (; r < m; ++r) t += v[r] * qc[static_cast<int64_t>(r) * n];
-    t *= beta;
-    for (r = 0; r + kQBatch <= m; r += kQBatch) {
-      double q[kQBatch];
-#pragma unroll
-      for (int u = 0; u < kQBatch; ++u) q[u] = qc[static_cast<int64_t>(r + u) * n];
-#pragma unroll
-      for (int u = 0; u < kQBatch; ++u) qc[static_cast<int64_t>(r + u) * n] = q[u] - t * v[r + u];
-    }
-    for (; r < m; ++r) qc[static_cast<int64_t>(r) * n] -= t * v[r];
-  }
-}
-
-// LDS: v, w, d, e (n each), the reduction slots, two batch buffers of S x n Givens pairs, two
-// batch headers of 1 + 2S ints and the count of finished chases.
+// LDS: v, w, d, e (n each), the reduction slots, the shift slots, two batch buffers of S x n
+// Givens pairs, two batch headers of 2 + 2S ints and the count of finished chases.  pipe = 1
+// enables the pipelined batches.
 template <int S>
-__global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs) {
+__global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs, int pipe) {
   extern __shared__ double sm[];
   const BatchEigProblem pb = probs[blockIdx.x];
   const int n = pb.n;
   double *vsh = sm, *wsh = sm + n, *d = sm + 2 * n, *e = sm + 3 * n, *red = sm + 4 * n;
-  double *csb = red + kBWaves;
+  double *shifts = red + kBWaves;
+  double *csb = shifts + kShiftSlots;
   int *meta = reinterpret_cast<int *>(csb + 4 * static_cast<size_t>(S) * n);
-  const int tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double *A = pb.A;
-  double *betas = pb.beta;
   if (n == 1) {
     if (tid == 0) {
       pb.w[0] = A[0];
       pb.Zr[0] = 1.0;
-      pb.Q[0] = 1.0;
       *pb.status = 0;
     }
     return;
@@ -355,8 +488,8 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     if (tid == 0) {
       d[k] = rowk[k];
       e[k] = alpha;
-      betas[k] = beta;
-      rowk[k + 1] = v0;  // row k keeps v for forming Q
+      rowk[k] = beta;    // row k keeps beta and v for the back-transformation
+      rowk[k + 1] = v0;
     }
     // step k-1's update of A22 and p = beta A22 v as column sums (A22 is symmetric): one thread
     // per column, kRowBatch rows loaded before any is stored
@@ -446,22 +579,14 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     tnorm = fmax(fabs(glo), fabs(ghi));
   }
   __syncthreads();
-  // ---- 3. implicit symmetric QR, batch b+1 chased while batch b is applied; the applying
-  // threads fill the time the chase takes with the Householder steps that form Q (4.), which
-  // depend on phase 1 only, polling the count of finished chases between steps
-  const int hdr = 1 + 2 * S;
-  volatile int *chased = meta + 2 * hdr;
+  // ---- 3. implicit symmetric QR, batch b+1 chased while batch b is applied
+  const int hdr = 2 + 2 * S;
   const int a = tid - 64;  // applying thread index (waves 1..)
-  int hk = n - 3;          // next Householder step of this thread's Q columns (wave-uniform)
-  if (wave != 0)
-    for (int col = a; col < n; col += kApplyThreads)
-      for (int r = 0; r < n; ++r) pb.Q[static_cast<int64_t>(r) * n + col] = (r == col) ? 1.0 : 0.0;
   // deflation: an off-diagonal below eps (|d_k| + |d_k+1|) or below eps times the norm bound (a
   // backward error of that size; eigenvalues near zero then need no relative accuracy)
-  QrState qs{n - 1, 0, 40L * n + 100, false, 2.220446049250313e-16 * tnorm};  // thread 0's
-  if (tid == 0) {
-    chase_batch<S>(qs, d, e, n, vsh, wsh, csb, meta);
-    *chased = 0;
+  QrState qs{n - 1, 0, 40L * n + 100, false, 2.220446049250313e-16 * tnorm, false};  // lane 0's
+  if (wave == 0) {
+    chase_wave<S>(qs, d, e, n, vsh, wsh, csb, meta, shifts, lane, pipe != 0);
   }
   __syncthreads();
   for (int it = 0;; ++it) {
@@ -470,58 +595,167 @@ __global__ __launch_bounds__(kBT) void k_batch_syev(const BatchEigProblem *probs
     if (wave == 0) {
       // the chase is one dependent chain: let its wave issue ahead of the applying waves
       __builtin_amdgcn_s_setprio(3);
-      if (tid == 0) {
-        chase_batch<S>(qs, d, e, n, vsh, wsh, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr);
-        *chased = it + 1;
-      }
+      chase_wave<S>(qs, d, e, n, vsh, wsh, csb + static_cast<size_t>(cur ^ 1) * 2 * S * n, meta + (cur ^ 1) * hdr,
+                    shifts, lane, pipe != 0);
       __builtin_amdgcn_s_setprio(0);
     } else {
       for (int col = a; col < n; col += kApplyThreads)
         apply_batch<S>(pb.Zr, n, col, csb + static_cast<size_t>(cur) * 2 * S * n, meta + cur * hdr);
-      while (hk >= 0 && *chased <= it) house_cols(pb.Q, A, betas, n, hk--, a);
     }
     __syncthreads();
   }
   if (tid == 0) *pb.status = qs.failed ? 1 : 0;
   for (int i = tid; i < n; i += kBT) pb.w[i] = d[i];
-  // ---- 4. the Householder steps not yet taken
-  if (wave != 0)
-    while (hk >= 0) house_cols(pb.Q, A, betas, n, hk--, a);
+}
+
+// Work item of the back-transformation launches: matrix `prob`, reflector block or first row `at`.
+struct WyItem {
+  int prob, at;
+};
+
+// Compact-WY factors of the reflectors H_k = I - beta_k v_k v_k^T that k_batch_syev left in the rows
+// of A (row k: beta_k at column k, v_k at columns k+1..), one workgroup per block of kWY reflectors
+// k0 = item.at ..: writes the block's rows of V (row k = v_k, zero at columns <= k; V = the
+// matrix's work, n x n) and T (kb x kb, row-major, ld kb, at work + n^2 + (k0 / kWY) kWY^2) with
+// H_k0 ... H_(k0+kb-1) = I - V^T T V in this row layout: T_jj = beta_j and
+// T[0:j, j] = -beta_j T[0:j, 0:j] G[0:j, j], G = the Gram matrix of the v's.
+__global__ __launch_bounds__(256) void k_wy_prep(const BatchEigProblem *probs, const WyItem *items) {
+  __shared__ double G[kWY][kWY + 1];
+  __shared__ double Ts[kWY][kWY + 1];
+  __shared__ double bet[kWY];
+  const WyItem it = items[blockIdx.x];
+  const BatchEigProblem pb = probs[it.prob];
+  const double *A = pb.A;
+  const int n = pb.n;
+  double *V = pb.work, *T = pb.work + static_cast<int64_t>(n) * n;
+  const int tid = threadIdx.x;
+  const int k0 = it.at, nref = n - 2;
+  const int kb = min(kWY, nref - k0);
+  for (int64_t e = tid; e < static_cast<int64_t>(kb) * n; e += blockDim.x) {
+    const int r = static_cast<int>(e / n), c = static_cast<int>(e - static_cast<int64_t>(r) * n);
+    const int k = k0 + r;
+    V[static_cast<int64_t>(k) * n + c] = (c > k) ? A[static_cast<int64_t>(k) * n + c] : 0.0;
+  }
+  if (tid < kb) bet[tid] = A[static_cast<int64_t>(k0 + tid) * n + k0 + tid];
+  for (int e = tid; e < kb * kb; e += blockDim.x) {
+    const int q = e / kb, j = e - q * kb;
+    if (q > j) continue;
+    const double *vq = A + static_cast<int64_t>(k0 + q) * n, *vj = A + static_cast<int64_t>(k0 + j) * n;
+    double acc = 0.0;
+    for (int c = k0 + j + 1; c < n; ++c) acc += vq[c] * vj[c];
+    G[q][j] = acc;
+    G[j][q] = acc;
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    if (tid < j) {
+      double acc = 0.0;
+      for (int q = tid; q < j; ++q) acc += Ts[tid][q] * G[q][j];
+      Ts[tid][j] = -bet[j] * acc;
+    } else if (tid == j) {
+      Ts[j][j] = bet[j];
+    } else if (tid < kb) {
+      Ts[tid][j] = 0.0;
+    }
+    __syncthreads();
+  }
+  double *Tb = T + static_cast<int64_t>(k0 / kWY) * kWY * kWY;
+  for (int e = tid; e < kb * kb; e += blockDim.x) Tb[e] = Ts[e / kb][e % kb];
+}
+
+// Rows item.at .. item.at + kRB - 1 of Zr <- Zr Q^T = Zr P_B^T ... P_0^T, P_j = I - V_j^T T_j V_j
+// (k_wy_prep): the last block first, Z <- Z - ((Z V_j^T) T_j^T) V_j on the columns after k0 (V_j is
+// zero on the others).  The rows stay in LDS (dynamic: kRB x n doubles) through every block.
+__global__ __launch_bounds__(256) void k_wy_apply(const BatchEigProblem *probs, const WyItem *items) {
+  extern __shared__ double zs[];
+  __shared__ double w1[kRB][kWY], w2[kRB][kWY];
+  const WyItem it = items[blockIdx.x];
+  const BatchEigProblem pb = probs[it.prob];
+  const int n = pb.n, nref = n - 2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rows = min(kRB, n - it.at);
+  double *Z = pb.Zr + static_cast<int64_t>(it.at) * n;
+  const double *V = pb.work, *T = pb.work + static_cast<int64_t>(n) * n;
+  for (int e = tid; e < rows * n; e += blockDim.x) zs[e] = Z[e];
+  __syncthreads();
+  const int nblk = (nref + kWY - 1) / kWY;
+  for (int j = nblk - 1; j >= 0; --j) {
+    const int k0 = j * kWY, kb = min(kWY, nref - k0), c0 = k0 + 1;
+    const double *Vj = V + static_cast<int64_t>(k0) * n;
+    const double *Tj = T + static_cast<int64_t>(j) * kWY * kWY;
+    // w1 = Z V_j^T: one (row, reflector) pair per wave at a time, lanes along the columns
+    for (int pq = wave; pq < rows * kb; pq += 4) {
+      const int r = pq / kb, q = pq - r * kb;
+      const double *vq = Vj + static_cast<int64_t>(q) * n;
+      const double *zr = zs + r * n;
+      double acc = 0.0;
+      for (int c = c0 + lane; c < n; c += 64) acc += zr[c] * vq[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0) w1[r][q] = acc;
+    }
+    __syncthreads();
+    // w2 = w1 T_j^T
+    for (int e = tid; e < rows * kb; e += blockDim.x) {
+      const int r = e / kb, i = e - r * kb;
+      double acc = 0.0;
+      for (int q = 0; q < kb; ++q) acc += w1[r][q] * Tj[i * kb + q];
+      w2[r][i] = acc;
+    }
+    __syncthreads();
+    // Z -= w2 V_j on the columns after k0: one column per thread, every row of the item
+    for (int c = c0 + tid; c < n; c += blockDim.x) {
+      double acc[kRB];
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) acc[r] = 0.0;
+      for (int i = 0; i < kb; ++i) {
+        const double v = Vj[static_cast<int64_t>(i) * n + c];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) acc[r] += w2[r][i] * v;
+      }
+      for (int r = 0; r < rows; ++r) zs[r * n + c] -= acc[r];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < rows * n; e += blockDim.x) Z[e] = zs[e];
 }
 
 }  // namespace
 
 size_t batch_syev_lds_for(int max_n, int S) {
-  return (4 * static_cast<size_t>(max_n) + kBWaves + 4 * static_cast<size_t>(S) * max_n) * sizeof(double) +
-         (2 * (1 + 2 * static_cast<size_t>(S)) + 1) * sizeof(int);
+  return (4 * static_cast<size_t>(max_n) + kBWaves + kShiftSlots + 4 * static_cast<size_t>(S) * max_n) *
+             sizeof(double) +
+         (2 * (2 + 2 * static_cast<size_t>(S)) + 1) * sizeof(int);
 }
 
-// Sweeps per batch: the most of 4, 2, 1 whose two Givens buffers fit the LDS beside the rest.
-int batch_syev_sweeps(int max_n) {
-  for (int S : {4, 2})
-    if (batch_syev_lds_for(max_n, S) <= kLdsMax) return S;
+// Sweeps per batch: the most of 8, 6, 4, 2, 1, at most max_sweeps, whose two Givens buffers fit
+// the LDS beside the rest.
+int batch_syev_sweeps(int max_n, int max_sweeps) {
+  for (int S : {8, 6, 4, 2})
+    if (S <= max_sweeps && batch_syev_lds_for(max_n, S) <= kLdsMax) return S;
   return 1;
 }
 
-size_t batch_syev_lds(int max_n) { return batch_syev_lds_for(max_n, batch_syev_sweeps(max_n)); }
-
 template <int S>
-static hipError_t launch_batch_syev_s(const BatchEigProblem *probs, int count, int max_n, hipStream_t s) {
+static hipError_t launch_batch_syev_s(const BatchEigProblem *probs, int count, int max_n, int pipe, hipStream_t s) {
   const size_t lds = batch_syev_lds_for(max_n, S);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_syev<S>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_syev<S>, dim3(count), dim3(kBT), lds, s, probs);
+  hipLaunchKernelGGL(k_batch_syev<S>, dim3(count), dim3(kBT), lds, s, probs, pipe);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s) {
+hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s, int pipe,
+                             int max_sweeps) {
   if (count <= 0) return hipSuccess;
-  if (max_n < 1 || max_n > kBatchEigMaxN) return hipErrorInvalidValue;
-  switch (batch_syev_sweeps(max_n)) {
-    case 4: return launch_batch_syev_s<4>(probs, count, max_n, s);
-    case 2: return launch_batch_syev_s<2>(probs, count, max_n, s);
-    default: return launch_batch_syev_s<1>(probs, count, max_n, s);
+  if (max_n < 1 || max_n > kBatchEigMaxN || pipe < 0 || pipe > 1 || max_sweeps < 1) return hipErrorInvalidValue;
+  switch (batch_syev_sweeps(max_n, max_sweeps)) {
+    case 8: return launch_batch_syev_s<8>(probs, count, max_n, pipe, s);
+    case 6: return launch_batch_syev_s<6>(probs, count, max_n, pipe, s);
+    case 4: return launch_batch_syev_s<4>(probs, count, max_n, pipe, s);
+    case 2: return launch_batch_syev_s<2>(probs, count, max_n, pipe, s);
+    default: return launch_batch_syev_s<1>(probs, count, max_n, pipe, s);
   }
 }
 
@@ -532,10 +766,11 @@ __global__ void k_fill_int(int *p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-// Device buffers of one batched solve besides A, Zr and Q: per-matrix w and beta (2 n doubles
-// each), convergence flags, the problem table, and the sort permutation of the finish.
+// Device buffers of one batched solve besides A and Zr: per-matrix w (n doubles each),
+// convergence flags and the problem table.
 struct BatchEigWork {
-  double *wb = nullptr;            // sum 2 n[i] doubles
+  WyItem *items = nullptr;         // batch_syev_items(count, n) entries
+  double *wb = nullptr;            // sum n[i] doubles
   int *stat = nullptr;             // count ints
   BatchEigProblem *probs = nullptr;  // count entries
 };
@@ -543,7 +778,7 @@ struct BatchEigWork {
 // First half on given buffers (no allocation): one launch over the matrices; w[i] (host) gets the
 // eigenvalues in the unsorted order of the rows of Zr[i].
 dacp_status batch_syev_raw_on(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
-                              double *const *Q, double *const *w, const BatchEigWork &wk) {
+                              double *const *work, double *const *w, const BatchEigWork &wk) {
   hipStream_t st = ctx->stream;
   int max_n = 0;
   size_t total = 0;
@@ -551,7 +786,7 @@ dacp_status batch_syev_raw_on(dacp_ctx ctx, int count, const int *n, double *con
   for (int i = 0; i < count; ++i) {
     max_n = std::max(max_n, n[i]);
     off[i] = total;
-    total += 2 * static_cast<size_t>(n[i]);  // w, beta
+    total += static_cast<size_t>(n[i]);
   }
   // flags cleared by a kernel (a memset node would misbehave inside a caller's captured graph)
   hipLaunchKernelGGL(k_fill_int, dim3((count + 255) / 256), dim3(256), 0, st, wk.stat, count, 0);
@@ -561,14 +796,35 @@ dacp_status batch_syev_raw_on(dacp_ctx ctx, int count, const int *n, double *con
     double *base = wk.wb + off[i];
     probs[i].A = A[i];
     probs[i].Zr = Zr[i];
-    probs[i].Q = Q[i];
+    probs[i].work = work ? work[i] : nullptr;
     probs[i].w = base;
-    probs[i].beta = base + n[i];
     probs[i].status = wk.stat + i;
     probs[i].n = n[i];
   }
   DACP_TRY(to_device(ctx, wk.probs, probs.data(), sizeof(BatchEigProblem) * count));
-  DACP_HIP(ctx, launch_batch_syev(wk.probs, count, max_n, st));
+  DACP_HIP(ctx, launch_batch_syev(wk.probs, count, max_n, st, ctx->beig_pipe, ctx->beig_sweeps));
+  if (work) {
+    // eigenvectors of A: Zr <- Zr Q^T for every matrix, two launches
+    std::vector<WyItem> prep, apply;
+    for (int i = 0; i < count; ++i) {
+      for (int k0 = 0; k0 < n[i] - 2; k0 += kWY) prep.push_back({i, k0});
+      if (n[i] > 2)
+        for (int r0 = 0; r0 < n[i]; r0 += kRB) apply.push_back({i, r0});
+    }
+    if (!prep.empty()) {
+      std::vector<WyItem> all(prep);
+      all.insert(all.end(), apply.begin(), apply.end());
+      DACP_TRY(to_device(ctx, wk.items, all.data(), sizeof(WyItem) * all.size()));
+      hipLaunchKernelGGL(k_wy_prep, dim3(static_cast<unsigned>(prep.size())), dim3(256), 0, st, wk.probs, wk.items);
+      DACP_HIP(ctx, hipGetLastError());
+      const size_t lds = static_cast<size_t>(kRB) * max_n * sizeof(double);
+      DACP_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void *>(k_wy_apply),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+      hipLaunchKernelGGL(k_wy_apply, dim3(static_cast<unsigned>(apply.size())), dim3(256), lds, st, wk.probs,
+                         wk.items + prep.size());
+      DACP_HIP(ctx, hipGetLastError());
+    }
+  }
   std::vector<int> status(count);
   DACP_TRY(to_host(ctx, status.data(), wk.stat, sizeof(int) * count));
   for (int i = 0; i < count; ++i)
@@ -579,9 +835,10 @@ dacp_status batch_syev_raw_on(dacp_ctx ctx, int count, const int *n, double *con
   return DACP_OK;
 }
 
-// Second half for one matrix on a given permutation buffer dperm (n ints, no allocation).
-dacp_status batch_syev_finish_on(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr,
-                                 const double *Q, double *w_out, double *Zrows, int *dperm) {
+// Second half for one matrix on a given permutation buffer dperm (n ints, no allocation): the
+// eigenvalues in ascending order, and the rows of Zr (already Zr Q^T) in that order.
+dacp_status batch_syev_finish_on(dacp_ctx ctx, int n, const double *w_raw, const double *Zr, double *w_out,
+                                 double *Zrows, int *dperm) {
   hipStream_t st = ctx->stream;
   std::vector<int> perm(n);
   std::iota(perm.begin(), perm.end(), 0);
@@ -589,44 +846,57 @@ dacp_status batch_syev_finish_on(dacp_ctx ctx, int n, const double *w_raw, doubl
   for (int j = 0; j < n; ++j) w_out[j] = w_raw[perm[j]];
   if (!Zrows) return DACP_OK;
   DACP_TRY(to_device(ctx, dperm, perm.data(), sizeof(int) * n));
-  DACP_HIP(ctx, launch_dgemm(0, 1, n, n, n, 1.0, Zr, n, Q, n, 0.0, A, n, 0, st));
-  DACP_HIP(ctx, launch_gather_rows(A, n, Zrows, n, dperm, nullptr, n, n, st));
+  DACP_HIP(ctx, launch_gather_rows(Zr, n, Zrows, n, dperm, nullptr, n, n, st));
   DACP_HIP(ctx, hipStreamSynchronize(st));  // dperm may be reused on return
   return DACP_OK;
 }
 
 }  // namespace
 
-// Host side, first half: one launch over `count` matrices A[i] (device, n[i] x n[i], ld n[i],
-// destroyed); Zr[i], Q[i] (device, n x n) receive the tridiagonal's eigenvectors (rows, unsorted)
-// and the Householder product, w[i] (host) the eigenvalues in the same unsorted order.
+size_t batch_syev_work_doubles(int n) {
+  const size_t nblk = n > 2 ? (static_cast<size_t>(n) - 2 + kWY - 1) / kWY : 0;
+  return static_cast<size_t>(n) * n + nblk * kWY * kWY;
+}
+
+size_t batch_syev_items(int count, const int *n) {
+  size_t k = 0;
+  for (int i = 0; i < count; ++i)
+    if (n[i] > 2) k += (static_cast<size_t>(n[i]) - 2 + kWY - 1) / kWY + (static_cast<size_t>(n[i]) + kRB - 1) / kRB;
+  return std::max<size_t>(k, 1);
+}
+
+// Host side, first half: launches over `count` matrices A[i] (device, n[i] x n[i], ld n[i],
+// destroyed); w[i] (host) receives the eigenvalues, unsorted; Zr[i] (device, n x n) the eigenvectors
+// of A[i] as rows in the same order when work[i] (device, batch_syev_work_doubles(n[i]) doubles) is
+// given (work null: Zr holds the tridiagonal's eigenvectors only).
 dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
-                           double *const *Q, double *const *w) {
+                           double *const *work, double *const *w) {
   if (count <= 0) return DACP_OK;
   size_t total = 0;
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > kBatchEigMaxN) return set_err(ctx, DACP_E_INVALID, "batch_syev: 1 <= n <= 2048");
-    total += 2 * static_cast<size_t>(n[i]);
+    total += static_cast<size_t>(n[i]);
   }
-  DevBuf work, dprobs, dstat;
-  DACP_HIP(ctx, work.alloc(total * sizeof(double)));
+  DevBuf wbuf, dprobs, dstat, ditems;
+  DACP_HIP(ctx, wbuf.alloc(total * sizeof(double)));
   DACP_HIP(ctx, dstat.alloc(sizeof(int) * count));
   DACP_HIP(ctx, dprobs.alloc(sizeof(BatchEigProblem) * count));
+  DACP_HIP(ctx, ditems.alloc(sizeof(WyItem) * batch_syev_items(count, n)));
   BatchEigWork wk;
-  wk.wb = work.as<double>();
+  wk.wb = wbuf.as<double>();
   wk.stat = dstat.as<int>();
   wk.probs = dprobs.as<BatchEigProblem>();
-  return batch_syev_raw_on(ctx, count, n, A, Zr, Q, w, wk);
+  wk.items = ditems.as<WyItem>();
+  return batch_syev_raw_on(ctx, count, n, A, Zr, work, w, wk);
 }
 
 // Second half, for one matrix on the caller's stream: eigenvalues ascending into w_out and, if
-// Zrows is set, the eigenvectors of A as its rows: Y = Zr Q^T (written over the destroyed A), then
-// the rows of Y in ascending order of the eigenvalues.
-dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr, const double *Q,
-                              double *w_out, double *Zrows) {
+// Zrows is set, the rows of Zr (eigenvectors of A from batch_syev_raw with work) in that order.
+dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, const double *Zr, double *w_out,
+                              double *Zrows) {
   DevBuf dperm;
   if (Zrows) DACP_HIP(ctx, dperm.alloc(sizeof(int) * n));
-  return batch_syev_finish_on(ctx, n, w_raw, A, Zr, Q, w_out, Zrows, dperm.as<int>());
+  return batch_syev_finish_on(ctx, n, w_raw, Zr, w_out, Zrows, dperm.as<int>());
 }
 
 // Both halves: eigen-decompositions of `count` symmetric matrices A[i] (device, n[i] x n[i], ld n[i],
@@ -639,21 +909,29 @@ dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, 
   for (int i = 0; i < count; ++i) {
     if (n[i] < 1 || n[i] > kBatchEigMaxN) return set_err(ctx, DACP_E_INVALID, "batch_syev: 1 <= n <= 2048");
     off[i] = total;
-    total += 2 * static_cast<size_t>(n[i]) * n[i];
+    total += static_cast<size_t>(n[i]) * n[i];
   }
-  DevBuf scratch_zq;
-  DACP_HIP(ctx, scratch_zq.alloc(total * sizeof(double)));
-  std::vector<double *> zr(count), q(count), wr(count);
+  bool vectors = false;
+  size_t wtotal = 0;
+  std::vector<size_t> woff(count);
+  for (int i = 0; i < count; ++i) {
+    vectors = vectors || Zrows[i] != nullptr;
+    woff[i] = wtotal;
+    wtotal += batch_syev_work_doubles(n[i]);
+  }
+  DevBuf scratch_z, scratch_w;
+  DACP_HIP(ctx, scratch_z.alloc(total * sizeof(double)));
+  if (vectors) DACP_HIP(ctx, scratch_w.alloc(wtotal * sizeof(double)));
+  std::vector<double *> zr(count), wk(count), wr(count);
   std::vector<std::vector<double>> wraw(count);
   for (int i = 0; i < count; ++i) {
-    zr[i] = scratch_zq.as<double>() + off[i];
-    q[i] = zr[i] + static_cast<size_t>(n[i]) * n[i];
+    zr[i] = scratch_z.as<double>() + off[i];
+    wk[i] = vectors ? scratch_w.as<double>() + woff[i] : nullptr;
     wraw[i].resize(n[i]);
     wr[i] = wraw[i].data();
   }
-  DACP_TRY(batch_syev_raw(ctx, count, n, A, zr.data(), q.data(), wr.data()));
-  for (int i = 0; i < count; ++i)
-    DACP_TRY(batch_syev_finish(ctx, n[i], wr[i], A[i], zr[i], q[i], w[i], Zrows[i]));
+  DACP_TRY(batch_syev_raw(ctx, count, n, A, zr.data(), vectors ? wk.data() : nullptr, wr.data()));
+  for (int i = 0; i < count; ++i) DACP_TRY(batch_syev_finish(ctx, n[i], wr[i], zr[i], w[i], Zrows[i]));
   return DACP_OK;
 }
 
@@ -688,15 +966,18 @@ hipError_t noalloc_scratch_init(int device) {
 }
 
 size_t batch_syev_noalloc_bytes(int count, const int *n) {
-  size_t wb = 0, zq = 0;
+  size_t wb = 0, z = 0;
   int max_n = 0;
   for (int i = 0; i < count; ++i) {
-    wb += 2 * static_cast<size_t>(n[i]);
-    zq += 2 * static_cast<size_t>(n[i]) * n[i];
+    wb += static_cast<size_t>(n[i]);
+    z += static_cast<size_t>(n[i]) * n[i];
     max_n = std::max(max_n, n[i]);
   }
+  size_t wk = 0;
+  for (int i = 0; i < count; ++i) wk += batch_syev_work_doubles(n[i]);
   return round256(sizeof(int) * count) + round256(sizeof(BatchEigProblem) * count) + round256(wb * sizeof(double)) +
-         round256(zq * sizeof(double)) + round256(sizeof(int) * max_n);
+         round256(z * sizeof(double)) + round256(wk * sizeof(double)) +
+         round256(sizeof(WyItem) * batch_syev_items(count, n)) + round256(sizeof(int) * max_n);
 }
 
 dacp_status batch_syev_noalloc(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
@@ -712,11 +993,11 @@ dacp_status batch_syev_noalloc(dacp_ctx ctx, int count, const int *n, double *co
   const hipError_t e = noalloc_scratch_init(ctx->device);
   if (e != hipSuccess) return hip_err(ctx, e, "syev_batched_noalloc: hipGetSymbolAddress(scratch)");
   unsigned char *base = static_cast<unsigned char *>(g_scratch_ptr[ctx->device]);
-  size_t wb = 0, zq = 0;
+  size_t wb = 0, z = 0;
   int max_n = 0;
   for (int i = 0; i < count; ++i) {
-    wb += 2 * static_cast<size_t>(n[i]);
-    zq += 2 * static_cast<size_t>(n[i]) * n[i];
+    wb += static_cast<size_t>(n[i]);
+    z += static_cast<size_t>(n[i]) * n[i];
     max_n = std::max(max_n, n[i]);
   }
   BatchEigWork wk;
@@ -727,22 +1008,28 @@ dacp_status batch_syev_noalloc(dacp_ctx ctx, int count, const int *n, double *co
   at += round256(sizeof(BatchEigProblem) * count);
   wk.wb = reinterpret_cast<double *>(base + at);
   at += round256(wb * sizeof(double));
-  double *zqb = reinterpret_cast<double *>(base + at);
-  at += round256(zq * sizeof(double));
+  double *zb = reinterpret_cast<double *>(base + at);
+  at += round256(z * sizeof(double));
+  double *workb = reinterpret_cast<double *>(base + at);
+  size_t wk_total = 0;
+  for (int i = 0; i < count; ++i) wk_total += batch_syev_work_doubles(n[i]);
+  at += round256(wk_total * sizeof(double));
+  wk.items = reinterpret_cast<WyItem *>(base + at);
+  at += round256(sizeof(WyItem) * batch_syev_items(count, n));
   int *dperm = reinterpret_cast<int *>(base + at);
-  std::vector<double *> zr(count), q(count), wr(count);
+  std::vector<double *> zr(count), work(count), wr(count);
   std::vector<std::vector<double>> wraw(count);
-  size_t off = 0;
+  size_t off = 0, woff = 0;
   for (int i = 0; i < count; ++i) {
-    zr[i] = zqb + off;
-    q[i] = zr[i] + static_cast<size_t>(n[i]) * n[i];
-    off += 2 * static_cast<size_t>(n[i]) * n[i];
+    zr[i] = zb + off;
+    off += static_cast<size_t>(n[i]) * n[i];
+    work[i] = workb + woff;
+    woff += batch_syev_work_doubles(n[i]);
     wraw[i].resize(n[i]);
     wr[i] = wraw[i].data();
   }
-  DACP_TRY(batch_syev_raw_on(ctx, count, n, A, zr.data(), q.data(), wr.data(), wk));
-  for (int i = 0; i < count; ++i)
-    DACP_TRY(batch_syev_finish_on(ctx, n[i], wr[i], A[i], zr[i], q[i], w[i], Zrows[i], dperm));
+  DACP_TRY(batch_syev_raw_on(ctx, count, n, A, zr.data(), work.data(), wr.data(), wk));
+  for (int i = 0; i < count; ++i) DACP_TRY(batch_syev_finish_on(ctx, n[i], wr[i], zr[i], w[i], Zrows[i], dperm));
   return DACP_OK;
 }
 

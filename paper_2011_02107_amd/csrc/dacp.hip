@@ -1576,6 +1576,16 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->batch_eig = value;
     return DACP_OK;
   }
+  if (k == "beig_pipe") {
+    if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "beig_pipe: 0 or 1");
+    ctx->beig_pipe = value;
+    return DACP_OK;
+  }
+  if (k == "beig_sweeps") {
+    if (value < 1 || value > 8) return set_err(ctx, DACP_E_INVALID, "beig_sweeps: 1..8");
+    ctx->beig_sweeps = value;
+    return DACP_OK;
+  }
   if (k == "blocked") {
     if (value < 0) return set_err(ctx, DACP_E_INVALID, "blocked: size >= 0 (0 = never)");
     ctx->blocked_min_n = value;
@@ -1640,6 +1650,8 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "project_splitk") *value = ctx->project_splitk;
   else if (k == "blocked") *value = ctx->blocked_min_n;
   else if (k == "batch_eig") *value = ctx->batch_eig;
+  else if (k == "beig_pipe") *value = ctx->beig_pipe;
+  else if (k == "beig_sweeps") *value = ctx->beig_sweeps;
   else if (k == "batch_workers") *value = ctx->batch_workers;
   else return set_err(ctx, DACP_E_INVALID, "unknown tuning key " + k);
   return DACP_OK;
@@ -2424,19 +2436,19 @@ class EigRendezvous {
     for (const Req &r : reqs) {
       if (r.n <= dacp::kBatchEigMaxN) {
         me.reqs.push_back(r);
-        scratch += 2 * static_cast<size_t>(r.n) * r.n;
+        scratch += static_cast<size_t>(r.n) * r.n + dacp::batch_syev_work_doubles(r.n);
       } else if (big == DACP_OK) {
         big = dacp::gpu_syev(ctx, r.n, r.A, r.n, r.w, r.Z);
       }
     }
     dacp::DevBuf zq;
-    hipError_t e = zq.alloc(scratch * sizeof(double));
+    hipError_t e = zq.alloc(std::max<size_t>(scratch, 1) * sizeof(double));
     size_t off = 0;
     for (const Req &r : me.reqs) {
       me.zr.push_back(e == hipSuccess ? zq.as<double>() + off : nullptr);
-      me.q.push_back(e == hipSuccess ? zq.as<double>() + off + static_cast<size_t>(r.n) * r.n : nullptr);
+      me.work.push_back(e == hipSuccess ? zq.as<double>() + off + static_cast<size_t>(r.n) * r.n : nullptr);
       me.wraw.emplace_back(r.n);
-      off += 2 * static_cast<size_t>(r.n) * r.n;
+      off += static_cast<size_t>(r.n) * r.n + dacp::batch_syev_work_doubles(r.n);
     }
     hipEvent_t ev = nullptr;
     if (e == hipSuccess && !stream_) e = hipErrorInvalidResourceHandle;
@@ -2456,7 +2468,7 @@ class EigRendezvous {
     if (me.st != DACP_OK) return me.st;
     for (size_t i = 0; i < me.reqs.size(); ++i) {
       const Req &r = me.reqs[i];
-      DACP_TRY(dacp::batch_syev_finish(ctx, r.n, me.wraw[i].data(), r.A, me.zr[i], me.q[i], r.w, r.Z));
+      DACP_TRY(dacp::batch_syev_finish(ctx, r.n, me.wraw[i].data(), me.zr[i], r.w, r.Z));
     }
     return big;
   }
@@ -2471,7 +2483,7 @@ class EigRendezvous {
   struct Arrival {
     dacp_ctx ctx = nullptr;
     std::vector<Req> reqs;
-    std::vector<double *> zr, q;
+    std::vector<double *> zr, work;
     std::vector<std::vector<double>> wraw;
     hipEvent_t ready = nullptr;
     dacp_status st = DACP_OK;
@@ -2494,13 +2506,13 @@ class EigRendezvous {
   }
   dacp_status launch_round(dacp_ctx ctx) {
     std::vector<int> n;
-    std::vector<double *> A, zr, q, w;
+    std::vector<double *> A, zr, work, w;
     for (Arrival *a : arrived_)
       for (size_t i = 0; i < a->reqs.size(); ++i) {
         n.push_back(a->reqs[i].n);
         A.push_back(a->reqs[i].A);
         zr.push_back(a->zr[i]);
-        q.push_back(a->q[i]);
+        work.push_back(a->work[i]);
         w.push_back(a->wraw[i].data());
       }
     dacp_status st = DACP_OK;
@@ -2517,7 +2529,7 @@ class EigRendezvous {
         }
       if (st == DACP_OK) {
         try {
-          st = dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(), zr.data(), q.data(),
+          st = dacp::batch_syev_raw(ctx, static_cast<int>(n.size()), n.data(), A.data(), zr.data(), work.data(),
                                     w.data());
         } catch (...) {
           ctx->stream = own;

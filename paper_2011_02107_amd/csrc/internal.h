@@ -142,20 +142,22 @@ struct BatchSpec {
 };
 hipError_t launch_batch_spectral(const BatchSpec *specs, int n, int max_L, hipStream_t s);
 
-// One problem of the batched dense eigensolver (beig.hip): A (n x n, ld n) is destroyed; Zr gets
-// the tridiagonal's eigenvectors as rows (unsorted), Q the Householder product, w the eigenvalues
-// (unsorted, w[j] pairs with row j of Zr); beta holds n reflector scalars; status 0 = converged.
+// One problem of the batched dense eigensolver (beig.hip): A (n x n, ld n) is destroyed and keeps
+// the Householder reflectors (row k: beta_k at column k, v_k at columns k+1..); Zr gets the
+// tridiagonal's eigenvectors as rows (unsorted), w the eigenvalues (unsorted, w[j] pairs with row j
+// of Zr); status 0 = converged.
 struct BatchEigProblem {
   double *A;
   double *Zr;
-  double *Q;
+  double *work;  // batch_syev_work_doubles(n) doubles for the back-transformation, or null
   double *w;
-  double *beta;
   int *status;
   int n;
 };
 constexpr int kBatchEigMaxN = 2048;
-hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s);
+// pipe = 1: pipelined multishift batches on large blocks; max_sweeps caps the sweeps per batch.
+hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s, int pipe,
+                             int max_sweeps);
 
 // Launch helpers (kernels.hip).
 template <typename T>
@@ -316,6 +318,8 @@ struct dacp_ctx_s {
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
   int rec_graph = 0;           // evolution: steps per captured graph below 2^19 rows (0 = no graphs)
   int batch_eig = 1;           // batched realisations: dense eigen-decompositions in batched launches
+  int beig_pipe = 1;           // batched eigensolver: pipelined multishift QR batches on large blocks
+  int beig_sweeps = 6;         // batched eigensolver: at most this many QR sweeps per batch (1..8)
   int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)
   int project_splitk = 1;      // projection: upper-triangle split-K products when the output has few tiles
   int rec_xcd = 2;             // fused recurrence: XCD-contiguous tile order, bit 0 low pass, bit 1 high pass
@@ -372,12 +376,15 @@ dacp_status gpu_syev(dacp_ctx ctx, int n, double *A, int64_t ld, double *w, doub
 // in one launch; w[i] (host) ascending; Zrows[i] (device, n x n, may be null) row j = eigenvector j.
 dacp_status batch_syev(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *w,
                        double *const *Zrows);
-// Its two halves: the launch (Zr, Q device n x n scratch per matrix; w host, unsorted) and, per
-// matrix on the caller's stream, the sort and Zrows = rows of Zr Q^T in ascending order (A reused).
+// Its two halves: the launches (Zr device n x n scratch per matrix, which receives the eigenvectors
+// of A as unsorted rows when work[i] gives batch_syev_work_doubles(n) device doubles; w host,
+// unsorted) and, per matrix on the caller's stream, the sort and the gather of Zr's rows into Zrows
+// in ascending order.
 dacp_status batch_syev_raw(dacp_ctx ctx, int count, const int *n, double *const *A, double *const *Zr,
-                           double *const *Q, double *const *w);
-dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, double *A, const double *Zr, const double *Q,
-                              double *w_out, double *Zrows);
+                           double *const *work, double *const *w);
+dacp_status batch_syev_finish(dacp_ctx ctx, int n, const double *w_raw, const double *Zr, double *w_out,
+                              double *Zrows);
+size_t batch_syev_work_doubles(int n);
 // The allocation-free form (dacp_syev_batched_noalloc): every device buffer besides A and Zrows comes
 // from one fixed device array of kNoAllocScratchBytes per device (beig.hip).  noalloc_scratch_init
 // resolves that device's address once (call it with the device current); batch_syev_noalloc_bytes
