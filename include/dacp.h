@@ -360,8 +360,9 @@ dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_op
  * being applied in LDS, the recurrence terms in registers) and writes only the sampled panels
  * of its basis (Sec. II.A, II.B on many small problems at once).  Projection, subspace solve
  * and acceptance follow per realisation, spread over host worker threads with their own
- * streams.  A realisation whose accepted core falls short is redone alone with a 1.5x wider
- * window.
+ * streams.  The realisations whose accepted core falls short are redone together, in one more
+ * batched call, with a 1.5x wider window, a basis ratio 0.2 higher and new start blocks (up to
+ * opts.max_retries times).
  *   hams[count]              Hamiltonian handles (distinct or repeated)
  *   eigs_out[count * N]      host; row r = the N values of realisation r, ascending
  *   err_out[count * N]       host, may be NULL; error estimates as for dacp_central_eigs
@@ -371,7 +372,7 @@ dacp_status dacp_central_eigpairs(dacp_ctx ctx, dacp_ham h, int N, const dacp_op
  * Device buffers of the call come from a per-device block cache that keeps freed blocks (up to
  * 32 GB) for later calls until the process ends; reuse is ordered by events on the streams.
  * Returns DACP_E_INVALID for L > 14, DACP_E_BOUNDS if a bound is below ||H||, DACP_E_WINDOW
- * if some realisation stays short after its retry (the others are still filled in). */
+ * if some realisation stays short after its retries (the others are still filled in). */
 dacp_status dacp_central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts,
                                       double *eigs_out, double *err_out, int *n_out, dacp_report *reports);
 

@@ -2896,7 +2896,8 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
     if (wst[r]) return set_err(ctx, wst[r], "batched: realisation " + std::to_string(r) + ": " + werr[r]);
 
   // Realisations whose core fell short are redone together in one more batched call with a 1.5x
-  // wider window (up to opts.max_retries times); with given windows, the short ones and those whose
+  // wider window, a basis ratio 0.2 higher and new start blocks (up to opts.max_retries times);
+  // with given windows, the short ones and those whose
   // bound proved too low are redone with the Lanczos / KPM estimates (the method's own estimators
   // are the fallback) and the same window ratio.
   dacp_status worst = DACP_OK;
@@ -2915,7 +2916,11 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
     for (int i = 0; i < na; ++i) sub[i] = hams[again[i]];
     dacp_opts o2 = o;
     if (!given) {
+      // a wider window, a denser basis (a core usually ends at a pair of close levels left with
+      // large residuals: more basis vectors per level resolve it) and new start blocks
       o2.window_ratio = window_ratio * 1.5;
+      o2.basis_ratio = (o.basis_ratio > 0.0 ? o.basis_ratio : 1.5) + 0.2;
+      o2.seed = o.seed + 0xD1B54A32D192ED03ULL;
       o2.max_retries = o.max_retries - 1;
     }
     std::vector<double> e2(static_cast<size_t>(na) * N), r2e(err_out ? static_cast<size_t>(na) * N : 0);

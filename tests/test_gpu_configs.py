@@ -7,7 +7,8 @@
   * The 96-realisation spin-glass set (32 each at L = 12, 13, 14, N = 200) in one batched call,
     every L = 12 and L = 13 realisation and the first three at L = 14 against dense-oracle fixtures
     (tests/golden/glass_batch96_L*.txt, written by tests/golden/make_fixtures.py), and the same set
-    with the per-problem eigensolver on the finishing threads.
+    with the per-problem eigensolver on the finishing threads; the schedule dacp_autotune_batched
+    picks for that set, against the same fixtures.
   * Failure paths, each forced from the host so that every kernel exits normally: a window too
     narrow for N (DACP_E_WINDOW with the accepted count), a NaN start block (DACP_E_NUMERIC), a
     non-finite coupling (DACP_E_INVALID), and a level multiplicity above the block width (copies
@@ -153,6 +154,32 @@ def test_batch96_per_problem_eigensolver(ctx):
         check_against(e0[i], r0[i], ref, norm, N, f"per-problem realisation {i}")
     for i in range(len(hams)):
         assert np.abs(e0[i] - e1[i]).max() <= 1e-10 * reps0[i]["e_bound"], i
+
+
+def test_autotune_batched_schedule_against_dense_fixtures(ctx):
+    """dacp_autotune_batched on the 96-realisation set, sampling every eighth realisation (the first
+    of each L among them): the schedule it returns is one of its grid's, keeps the caller's other
+    options, and reaches N on the sample at its first window; the whole set with that schedule
+    (retries allowed) matches every fixture."""
+    sets, hams = _batch96(ctx)
+    fx = _fixtures()
+    N = 200
+    opts = B.default_opts(b=8, precision=B.DACP_F32, fp64_tail_frac=0.3)
+    best, t = B.dacp_autotune_batched(ctx, hams, N, opts, sample_every=8)
+    assert best.window_ratio in (2.2, 2.5, 2.8) and best.basis_ratio in (1.3, 1.5) and best.kfac in (12.0, 18.0)
+    assert best.max_retries == opts.max_retries and best.b == opts.b and best.precision == opts.precision
+    assert 0.0 < t < 60.0
+    first = type(best).from_buffer_copy(best)
+    first.max_retries = 0
+    sample = [h for i, h in enumerate(hams) if i % 8 == 0]
+    _, _, n_s, _, st_s = B.dacp_central_eigs_batched(ctx, sample, N, first, raise_on_window=False)
+    assert st_s == 0 and np.all(n_s == N)
+    eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, best)
+    assert st == 0 and np.all(n_out == N)
+    for i, (seed, L, norm, ref) in fx.items():
+        check_against(eigs[i], errs[i], ref, norm, N, f"autotuned schedule, realisation {i}")
+    print(f"autotuned schedule: window {best.window_ratio}, basis {best.basis_ratio}, kfac {best.kfac}; "
+          f"sample call {t:.3f} s; retried {sum(r['retries'] > 0 for r in reps)} of {len(hams)}")
 
 
 # ------------------------------------------------------------------ failure paths

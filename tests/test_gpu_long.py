@@ -1,0 +1,59 @@
+"""Full-size runs too long for the regular GPU suite (about ten minutes each on one MI355X); they
+run only when the environment variable DACP_LONG is set.
+
+  * Moment mode at L = 21 (D = 2^21), N = 5000, on the integrable chain (h_z = 0), every value
+    against the exact Jordan-Wigner spectrum: App. C's product identity with no stored basis, so
+    the memory held is the candidates' Ritz vectors (D x 1.1 N) and a few recurrence blocks,
+    independent of m D.  The stored-basis mode would need V and H V of D x m FP64 each (263 GB
+    apiece at m = 15680), more than one GPU holds.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import central  # noqa: E402
+from paper_2011_02107_amd import binding as B  # noqa: E402
+from paper_2011_02107_amd import inputs  # noqa: E402
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not os.environ.get("DACP_LONG"), reason="about ten minutes; set DACP_LONG=1")]
+
+EPS = 2.220446049250313e-16
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = B.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def test_moment_mode_jw_twin_L21_N5000(ctx):
+    L, N = 21, 5000
+    ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L, hz=0.0))
+    o = B.default_opts(b=64, kfac=12.0, window_ratio=2.6, basis_ratio=1.2, precision=B.DACP_F32,
+                       fp64_tail_frac=0.3, moment_mode=1)
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    t0 = time.perf_counter()
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o)
+    dt = time.perf_counter() - t0
+    free1, _ = torch.cuda.mem_get_info()
+    assert st == 0 and len(eigs) == N
+    err = np.abs(np.sort(eigs) - ref)
+    assert err.max() <= 1e-10 * norm
+    assert not (err > np.asarray(errs) + 64 * EPS * norm).any()
+    m = rep["m"]
+    held = (free0 - free1) / 2**30
+    print(f"L=21 N=5000 moment mode: {dt:.1f} s, m {m}, rank {rep['rank']}, evolution steps {rep['evol_steps']}, "
+          f"stages {{filter {rep['t_filter_ms'] / 1e3:.1f}, evolution {rep['t_evol_ms'] / 1e3:.1f}, "
+          f"projection {rep['t_project_ms'] / 1e3:.1f}, GEP {rep['t_gep_ms'] / 1e3:.1f}, "
+          f"acceptance {rep['t_accept_ms'] / 1e3:.1f}}} s; max error {err.max() / norm:.1e} of ||H||; "
+          f"device memory held after the call (library block cache) {held:.1f} GiB of {total / 2**30:.0f}; "
+          f"a stored basis would need {2 * (1 << L) * m * 8 / 2**30:.0f} GiB for V and H V", flush=True)
