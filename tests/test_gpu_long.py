@@ -37,6 +37,9 @@ def test_moment_mode_jw_twin_L21_N5000(ctx):
     L, N = 21, 5000
     ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
     ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L, hz=0.0))
+    # the evolution kernels' shape for this size (at L = 21 the fused recurrence needs 4-column
+    # groups: an 8-column high tile would exceed 64 KB of LDS)
+    group, us = B.dacp_autotune(ctx, ham, b=64, steps=64)
     o = B.default_opts(b=64, kfac=12.0, window_ratio=2.6, basis_ratio=1.2, precision=B.DACP_F32,
                        fp64_tail_frac=0.3, moment_mode=1)
     torch.cuda.synchronize()
@@ -52,6 +55,7 @@ def test_moment_mode_jw_twin_L21_N5000(ctx):
     m = rep["m"]
     held = (free0 - free1) / 2**30
     print(f"L=21 N=5000 moment mode: {dt:.1f} s, m {m}, rank {rep['rank']}, evolution steps {rep['evol_steps']}, "
+          f"group {group} ({us:.3f} us per column step), "
           f"stages {{filter {rep['t_filter_ms'] / 1e3:.1f}, evolution {rep['t_evol_ms'] / 1e3:.1f}, "
           f"projection {rep['t_project_ms'] / 1e3:.1f}, GEP {rep['t_gep_ms'] / 1e3:.1f}, "
           f"acceptance {rep['t_accept_ms'] / 1e3:.1f}}} s; max error {err.max() / norm:.1e} of ||H||; "
