@@ -1,4 +1,4 @@
-"""Full-size runs too long for the regular GPU suite (about ten minutes each on one MI355X); they
+"""Full-size runs too long for the regular GPU suite (10 to 20 minutes each on one MI355X); they
 run only when the environment variable DACP_LONG is set.
 
   * Moment mode at L = 21 (D = 2^21), N = 5000, on the integrable chain (h_z = 0), every value
@@ -20,7 +20,7 @@ from paper_2011_02107_amd import binding as B  # noqa: E402
 from paper_2011_02107_amd import inputs  # noqa: E402
 
 pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(not os.environ.get("DACP_LONG"), reason="about ten minutes; set DACP_LONG=1")]
+              pytest.mark.skipif(not os.environ.get("DACP_LONG"), reason="10 to 20 minutes; set DACP_LONG=1")]
 
 EPS = 2.220446049250313e-16
 
