@@ -108,7 +108,10 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *                 tiles dealt round-robin in launch order (default 2: high pass only)
  *   "batch_workers" host threads finishing the realisations of dacp_central_eigs_batched (1..64, default 16)
  *   "batch_eig"   dacp_central_eigs_batched: 1 = the finishing threads' dense eigen-decompositions are
- *                 collected and solved in batched launches (default), 0 = one solver per problem
+ *                 collected and solved in batched launches when the call has more than 8
+ *                 realisations (default; smaller calls, such as a retry round, solve each problem
+ *                 on its thread's stream), 2 = batched launches always, 0 = one solver per
+ *                 problem always
  *   "beig_pipe"   batched eigensolver: 1 = on unreduced blocks of 48 rows or more, the QR sweeps
  *                 of a batch take their shifts at its start and are chased in lockstep, one lane
  *                 per sweep (default); 0 = one sweep after another

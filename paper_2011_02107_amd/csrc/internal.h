@@ -155,6 +155,9 @@ struct BatchEigProblem {
   int n;
 };
 constexpr int kBatchEigMaxN = 2048;
+// dacp_central_eigs_batched calls with at most this many realisations use the per-problem
+// eigensolver on the finishing threads' streams instead of the batched launch.
+constexpr int kBatchEigMinCount = 8;
 // pipe = 1: pipelined multishift batches on large blocks; max_sweeps caps the sweeps per batch.
 hipError_t launch_batch_syev(const BatchEigProblem *probs, int count, int max_n, hipStream_t s, int pipe,
                              int max_sweeps);
@@ -317,7 +320,8 @@ struct dacp_ctx_s {
   int rec_tile_elems = 8192;   // fused recurrence: largest tile, elements
   int rec_persist = 0;         // fused recurrence: persistent workgroups per CU (0 = one per tile)
   int rec_graph = 0;           // evolution: steps per captured graph below 2^19 rows (0 = no graphs)
-  int batch_eig = 1;           // batched realisations: dense eigen-decompositions in batched launches
+  int batch_eig = 1;           // batched realisations' eigensolver: 1 = batched launches when the call has more
+                               // than kBatchEigMinCount realisations, 2 = always, 0 = never
   int beig_pipe = 1;           // batched eigensolver: pipelined multishift QR batches on large blocks
   int beig_sweeps = 6;         // batched eigensolver: at most this many QR sweeps per batch (1..8)
   int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)

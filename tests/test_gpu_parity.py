@@ -876,8 +876,11 @@ def test_fp32_tail_error_table(ctx):
 # ------------------------------------------------------------------ batched realisations
 
 
-def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
-    """Realisations of different L in one persistent launch, each against its dense oracle."""
+@pytest.mark.parametrize("batch_eig", [1, 2], ids=["eigensolver_auto", "batched_eigensolver"])
+def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx, batch_eig):
+    """Realisations of different L in one persistent launch, each against its dense oracle; with
+    the default eigensolver choice (five realisations: the per-problem solver) and with the
+    batched eigensolver forced."""
     N = 40
     specs = [(8, 1), (10, 2), (9, 3), (10, 4), (8, 5)]
     hams, refs = [], []
@@ -887,7 +890,11 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
         hams.append(B.dacp_build_hamiltonian(ctx, L, terms))
     for precision in (B.DACP_F64, B.DACP_F32):
         opts = B.default_opts(b=8, precision=precision, fp64_tail_frac=0.3)
-        eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+        try:
+            ctx.tune("batch_eig", batch_eig)
+            eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+        finally:
+            ctx.tune("batch_eig", 1)
         assert st == 0 and np.all(n_out == N)
         for r, (ref, norm) in enumerate(refs):
             _check_central(eigs[r], ref, norm, N, errs=errs[r])
@@ -899,7 +906,8 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx):
 
 def test_central_eigs_batched_per_problem_eigensolver(ctx):
     """The batched path with the finishing threads' eigen-decompositions solved one by one (knob
-    batch_eig = 0) gives the same eigenvalues as the batched eigensolver path, both at the oracle."""
+    batch_eig = 0) gives the same eigenvalues as with the batched eigensolver forced
+    (batch_eig = 2), both at the oracle."""
     N = 40
     specs = [(8, 11), (10, 12), (9, 13)]
     hams, refs = [], []
@@ -908,8 +916,9 @@ def test_central_eigs_batched_per_problem_eigensolver(ctx):
         refs.append(central.central_eigenvalues(L, terms, N))
         hams.append(B.dacp_build_hamiltonian(ctx, L, terms))
     opts = B.default_opts(b=8)
-    e1, _, n1, _, st1 = B.dacp_central_eigs_batched(ctx, hams, N, opts)
     try:
+        ctx.tune("batch_eig", 2)
+        e1, _, n1, _, st1 = B.dacp_central_eigs_batched(ctx, hams, N, opts)
         ctx.tune("batch_eig", 0)
         e0, _, n0, _, st0 = B.dacp_central_eigs_batched(ctx, hams, N, opts)
     finally:
