@@ -90,11 +90,11 @@ def opts_for(args, wl):
     else:
         # basis 1.2 N_w: at 1.1 - 1.15 a cluster of near-degenerate levels somewhere in the core can
         # stay unresolved (residuals ~5e-7) on some start blocks and force a retry with a wider window.
-        # Window 2.6 N: the quadratic residual bound accepts the central 4851 of 5000 at L = 20 with a
-        # 2.2 N window (the values near |theta| = 0.44 a carry too large a residual) and all 5625
-        # candidates with 2.6 N, so the first attempt succeeds (61 s vs 67 s per attempt, a retry
-        # with the 1.5x window would take 80 s more)
-        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.6, basis_ratio=1.2, precision=B.DACP_F32,
+        # Window 2.4 N: at L = 20 the quadratic residual bound's core ends near |theta| = 0.44 a
+        # (4851 values with a 2.2 N window, 5234 with 2.4 N, 5469 with 2.5 N, all 5625 candidates
+        # with 2.6 N), so 2.4 N is the narrowest window that holds N = 5000 on the first attempt
+        # (63.8 s; a retry with the 1.5x window would take about 80 s more)
+        o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.4, basis_ratio=1.2, precision=B.DACP_F32,
                            fp64_tail_frac=0.3, group=args.group)
     if args.block:
         o.b = args.block
@@ -503,10 +503,12 @@ def scaling_paper_models(args):
             t0 = time.perf_counter()
             g, us = B.dacp_autotune(ctx, ham, b=64, steps=64)  # as in the headline's tuned mode, untimed
             t_tune = time.perf_counter() - t0
+            # tuned options with the 2.2 N window (wider first windows do not help here: at L = 15,
+            # N = 5000 is 15 % of the spectrum and a 2.6 N window, retried at 3.9 N, falls short)
             o = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
                                fp64_tail_frac=0.3)
             eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o, raise_on_window=False)
-            rows.append({"L": L, "status": st, "accepted": len(eigs), "K": rep["K"], "m": rep["m"],
+            rows.append({"L": L, "status": st, "accepted": len(eigs), "retries": rep["retries"], "K": rep["K"], "m": rep["m"],
                          "evol_steps": rep["evol_steps"], "t_filter_ms": rep["t_filter_ms"],
                          "t_evol_ms": rep["t_evol_ms"], "t_project_ms": rep["t_project_ms"],
                          "t_gep_ms": rep["t_gep_ms"], "t_total_ms": rep["t_total_ms"],
