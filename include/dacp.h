@@ -145,6 +145,10 @@ void dacp_free_hamiltonian(dacp_ham h);
 /* Host query: number of spins, sum |c| (triangle bound on ||H||), sum c^2
  * (= tr H^2 / D), number of off-diagonal flip groups. */
 dacp_status dacp_ham_info(dacp_ham h, int *L, double *sum_abs, double *sum_sq, int *n_flip_groups);
+/* Host query: *flip_sym = 1 when H commutes with the global spin flip prod_i sigma^x_i (every
+ * merged Pauli string has an even number of Z and Y factors; dacp_opts.sectors then splits the
+ * start columns between its two eigenspaces), else 0. */
+dacp_status dacp_ham_flip_symmetry(dacp_ham h, int *flip_sym);
 
 /* y = H x on [D][b] blocks (device), dtype DACP_F64 or DACP_F32 for both x and
  * y, row strides ldx, ldy >= b.  x and y must not overlap.  This is the
@@ -313,6 +317,12 @@ typedef struct {
                        /* and P from moments, no stored basis; the candidates' Ritz vectors */
                        /* from a second evolution (D x (N + max(64, N/8)) FP64 on device)   */
                        /* for the residual acceptance.  0 (default): the basis is stored  */
+  int sectors;         /* 1: when H commutes with the global spin flip                  */
+                       /* P = prod_i sigma^x_i (every Pauli string has an even number of */
+                       /* Z and Y factors), half the start columns are projected onto   */
+                       /* P = +1 and half onto P = -1; H keeps each column in its sector */
+                       /* and every Ritz vector is an eigenvector of P (b >= 2).         */
+                       /* 0 (default): plain Gaussian start columns                       */
 } dacp_opts;
 
 typedef struct {

@@ -76,6 +76,7 @@ class Opts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("max_retries", ctypes.c_int),
         ("moment_mode", ctypes.c_int),
+        ("sectors", ctypes.c_int),
     ]
 
 
@@ -132,6 +133,7 @@ SIGNATURES = {
     "dacp_build_hamiltonian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "dacp_free_hamiltonian": (None, [_vp]),
     "dacp_ham_info": (ctypes.c_int, [_vp, _ip, _dp, _dp, _ip]),
+    "dacp_ham_flip_symmetry": (ctypes.c_int, [_vp, _ip]),
     "dacp_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _i64, _vp, _i64]),
     "dacp_spectral_bound": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_uint64, ctypes.c_double, _dp, _dp, _dp]),
     "dacp_dos_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_uint64, _dp]),
@@ -287,6 +289,12 @@ class Hamiltonian:
         nf = ctypes.c_int()
         self.ctx.check(self.ctx.lib.dacp_ham_info(self.handle, ctypes.byref(L), ctypes.byref(sa), ctypes.byref(sq), ctypes.byref(nf)))
         return {"L": L.value, "sum_abs": sa.value, "sum_sq": sq.value, "n_flip_groups": nf.value}
+
+    def flip_symmetry(self):
+        """True when H commutes with the global spin flip prod_i sigma^x_i."""
+        f = ctypes.c_int()
+        self.ctx.check(self.ctx.lib.dacp_ham_flip_symmetry(self.handle, ctypes.byref(f)))
+        return bool(f.value)
 
     def close(self):
         if self.handle:

@@ -1724,6 +1724,12 @@ dacp_status dacp_build_hamiltonian(dacp_ctx ctx, int L, int n_terms, const dacp_
     h->max_abs = std::max(h->max_abs, std::fabs(kv.second));
     ++h->n_strings;
   }
+  // a Pauli string commutes with prod_i sigma^x_i when it has an even number of Z and Y factors
+  h->flip_sym = true;
+  for (uint32_t zm : dz)
+    if (__builtin_popcount(zm) % 2) h->flip_sym = false;
+  for (const FlipEntry &f : h->flips_host)
+    if (__builtin_popcount(f.zmask) % 2) h->flip_sym = false;
   std::stable_sort(h->flips_host.begin(), h->flips_host.end(),
                    [](const FlipEntry &a, const FlipEntry &b) { return a.xmask < b.xmask; });
   if (h->flips_host.size() > static_cast<size_t>(dacp::kMaxFlips)) {
@@ -1781,6 +1787,12 @@ dacp_status dacp_ham_info(dacp_ham h, int *L, double *sum_abs, double *sum_sq, i
   if (sum_abs) *sum_abs = h->sum_abs;
   if (sum_sq) *sum_sq = h->sum_sq;
   if (n_flip_groups) *n_flip_groups = static_cast<int>(h->flips_host.size());
+  return DACP_OK;
+}
+
+dacp_status dacp_ham_flip_symmetry(dacp_ham h, int *flip_sym) {
+  if (!h || !flip_sym) return DACP_E_INVALID;
+  *flip_sym = h->flip_sym ? 1 : 0;
   return DACP_OK;
 }
 
@@ -2196,8 +2208,16 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
     fp.precision = o.precision;
     fp.fp64_tail = static_cast<int>(std::ceil(o.fp64_tail_frac * K));
     fp.seed = o.seed + static_cast<uint64_t>(attempt) * 0x9E3779B97F4A7C15ULL;
-    st = run_filter(ctx, h, &fp, nullptr, psi.as<double>());
+    DevBuf start;
+    if (o.sectors && h->flip_sym && b >= 2) {
+      // start columns split between the two eigenspaces of the global spin flip, which H keeps
+      DACP_HIP(ctx, start.alloc(static_cast<size_t>(D) * b * sizeof(double)));
+      DACP_HIP(ctx, dacp::launch_philox_gauss(start.as<double>(), D, b, fp.seed, ctx->stream));
+      DACP_HIP(ctx, dacp::launch_parity_split(start.as<double>(), D, b, (b + 1) / 2, ctx->stream));
+    }
+    st = run_filter(ctx, h, &fp, start.p ? start.as<double>() : nullptr, psi.as<double>());
     if (st) return st;
+    start.release();
     rep.t_filter_ms = now_ms() - t0;
     vlog("filter done: %.1f ms", rep.t_filter_ms);
 
@@ -2647,6 +2667,8 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
     DACP_HIP(ctx, psi[r].alloc(static_cast<size_t>(D) * pl.b * sizeof(double)));
     DACP_HIP(ctx, dacp::launch_philox_gauss(psi[r].as<double>(), D, pl.b, o.seed + static_cast<uint64_t>(r) * 0x9E3779B97F4A7C15ULL,
                                             ctx->stream));
+    if (o.sectors && h->flip_sym && pl.b >= 2)
+      DACP_HIP(ctx, dacp::launch_parity_split(psi[r].as<double>(), D, pl.b, (pl.b + 1) / 2, ctx->stream));
     DACP_HIP(ctx, vb[r].alloc(static_cast<size_t>(D) * pl.m * sizeof(double)));
     if (static_cast<double>(D) * pl.m * 8.0 >= 4294967296.0)
       return set_err(ctx, DACP_E_INVALID, "batched: basis of realisation " + std::to_string(r) + " exceeds 4 GiB");

@@ -245,6 +245,7 @@ void dacp_default_opts(dacp_opts *o) {
   o->fp64_tail_frac = 0.2;
   o->seed = 0;
   o->max_retries = 1;
+  o->sectors = 0;
 }
 
 dacp_status dacp_plan(int64_t D, int N, double e_bound, const double *mu, int n_mu, const dacp_opts *opts_in,

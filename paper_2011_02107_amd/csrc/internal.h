@@ -187,6 +187,9 @@ hipError_t launch_convert_f64_to_f32(const double *x, int64_t ldx, float *y, int
 hipError_t launch_convert_f32_to_f64(const float *x, int64_t ldx, double *y, int64_t ldy, int64_t D, int b,
                                      hipStream_t s);
 hipError_t launch_philox_gauss(double *out, int64_t D, int b, uint64_t seed, hipStream_t s);
+// Columns j < b_even of the [D][b] block <- psi + P psi, the others psi - P psi, P the global spin
+// flip (s -> s ^ (D - 1)).
+hipError_t launch_parity_split(double *psi, int64_t D, int b, int b_even, hipStream_t s);
 hipError_t launch_axpby(double *y, const double *x, double a, double bcoef, int64_t n, hipStream_t s);
 // residual: with r_j = hx_j - theta_j x_j, out[3j] = ||r_j||^2, out[3j+1] = ||x_j||^2,
 // out[3j+2] = x_j . r_j (two stages; partial holds nblk * 3 b doubles).
@@ -345,6 +348,7 @@ struct dacp_ham_s {
   // coupling statistics of the merged Pauli strings (features of the learned window)
   double w_diag = 0.0, w_zz = 0.0, w_flip1 = 0.0, max_abs = 0.0;
   int n_strings = 0;
+  bool flip_sym = false;  // H commutes with the global spin flip prod_i sigma^x_i
   double *d64 = nullptr;  // diagonal of H, FP64
   float *d32 = nullptr;   // same in FP32
   dacp::FlipEntry *flips = nullptr;

@@ -1212,6 +1212,32 @@ __global__ void k_philox_gauss(double *out, int64_t D, int b, uint32_t k0, uint3
   out[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
 }
 
+// Projects the columns of a [D][b] block onto the eigenspaces of the global spin flip
+// P = prod_i sigma^x_i, (P psi)(s) = psi(s ^ (D - 1)): columns j < b_even become psi + P psi, the
+// others psi - P psi.  One thread per pair (s, s ^ (D - 1)), s < D / 2, and column.
+__global__ void k_parity_split(double *psi, int64_t D, int b, int b_even) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= (D / 2) * b) return;
+  const int64_t s = e / b;
+  const int j = static_cast<int>(e - s * b);
+  const int64_t p = s ^ (D - 1);
+  const double x = psi[s * b + j], y = psi[p * b + j];
+  if (j < b_even) {
+    psi[s * b + j] = x + y;
+    psi[p * b + j] = x + y;
+  } else {
+    psi[s * b + j] = x - y;
+    psi[p * b + j] = y - x;
+  }
+}
+
+hipError_t launch_parity_split(double *psi, int64_t D, int b, int b_even, hipStream_t s) {
+  if (D < 2 || b < 1 || b_even < 0 || b_even > b) return hipErrorInvalidValue;
+  const int64_t n = (D / 2) * b;
+  hipLaunchKernelGGL(k_parity_split, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, psi, D, b, b_even);
+  return hipGetLastError();
+}
+
 hipError_t launch_philox_gauss(double *out, int64_t D, int b, uint64_t seed, hipStream_t s) {
   const int64_t n = D * b;
   hipLaunchKernelGGL(k_philox_gauss, dim3((n + 255) / 256), dim3(256), 0, s, out, D, b,

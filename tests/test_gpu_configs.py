@@ -273,3 +273,32 @@ def test_multiplicity_above_block_width_falls_short_and_is_flagged(ctx):
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=8))
     check_against(eigs, errs, ref, norm, N, "b = 8")
     assert rep["n_clusters_at_b"] == 0
+
+
+# ------------------------------------------------------------------ symmetry sectors
+
+
+def test_flip_symmetry_sectors_against_dense_oracle(ctx):
+    """The global spin flip P = prod_i sigma^x_i commutes with the spin glass and with the
+    integrable chain, not with the chain's Z field.  With sectors on (the default) the start
+    columns are split between P = +1 and P = -1: the values match the dense oracle as with plain
+    Gaussian columns, and every returned eigenvector is an eigenvector of P (<phi, P phi> = +-1)."""
+    assert B.dacp_build_hamiltonian(ctx, 8, inputs.spin_glass(8, 0)).flip_symmetry()
+    assert B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8, hz=0.0)).flip_symmetry()
+    assert not B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8)).flip_symmetry()
+    L, N = 11, 150
+    terms = inputs.spin_glass(L, 3)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    D = 1 << L
+    for sectors in (1, 0):
+        opts = B.default_opts(b=8, sectors=sectors)
+        vecs = torch.empty((D, N), dtype=torch.float64, device=DEV)
+        eigs, errs, rep, st = B.dacp_central_eigpairs(ctx, ham, N, vecs, opts)
+        check_against(eigs, errs, ref, norm, N, f"sectors {sectors}")
+        if sectors:
+            X = vecs.cpu().numpy()
+            flip = np.arange(D) ^ (D - 1)
+            par = np.einsum("ij,ij->j", X, X[flip]) / np.einsum("ij,ij->j", X, X)
+            assert np.all(np.abs(np.abs(par) - 1.0) < 1e-8), np.abs(np.abs(par) - 1.0).max()
+            assert (par > 0).sum() > 0 and (par < 0).sum() > 0
