@@ -120,13 +120,13 @@ def _fixtures():
 
 
 def test_batch96_every_L12_L13_realisation_against_dense_fixtures(ctx):
-    """The benchmark's batched call (96 realisations, FP32 filter + FP64 tail, b = 8, N = 200): all
+    """The benchmark's batched call (96 realisations, FP32 filter + FP64 tail, b = 16, N = 200): all
     reach N, and every realisation with a dense-oracle fixture (all 64 at L = 12 and 13, three at
     L = 14) matches it value by value, its estimates bounding the true errors."""
     sets, hams = _batch96(ctx)
     fx = _fixtures()
     N = 200
-    opts = B.default_opts(b=8, precision=B.DACP_F32, fp64_tail_frac=0.3)
+    opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3)
     eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
     assert st == 0 and np.all(n_out == N)
     assert sum(1 for i in fx if sets[i][0] in (12, 13)) == 64
@@ -164,7 +164,7 @@ def test_autotune_batched_schedule_against_dense_fixtures(ctx):
     sets, hams = _batch96(ctx)
     fx = _fixtures()
     N = 200
-    opts = B.default_opts(b=8, precision=B.DACP_F32, fp64_tail_frac=0.3)
+    opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3)
     best, t = B.dacp_autotune_batched(ctx, hams, N, opts, sample_every=8)
     assert best.window_ratio in (2.2, 2.5, 2.8) and best.basis_ratio in (1.3, 1.5) and best.kfac in (12.0, 18.0)
     assert best.max_retries == opts.max_retries and best.b == opts.b and best.precision == opts.precision
