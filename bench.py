@@ -325,7 +325,7 @@ def batch96(args):
     hams = [B.dacp_build_hamiltonian(ctx, L, t) for (L, _, t) in sets]
     N = 200
     # b = 16 start columns: with 8, close pairs of levels are left unresolved more often and more
-    # realisations need the retry round (autotuned schedule: 0.65 s per call against 0.76 s)
+    # realisations need the retry round (autotuned schedule: 0.63 s per call against 0.76 s)
     opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3)
     if args.kfac:
         opts.kfac = args.kfac
@@ -349,10 +349,10 @@ def batch96(args):
             times.append(time.perf_counter() - t0)
         return float(np.median(times)), last
 
-    # one-time schedule autotune (window, basis and filter order) on every eighth realisation, not
-    # part of the timed calls
+    # one-time schedule autotune (window, basis and filter order) on the whole set, retry rounds
+    # included, not part of the timed calls
     t0 = time.perf_counter()
-    tuned, t_sample = B.dacp_autotune_batched(ctx, hams, N, opts, sample_every=8)
+    tuned, t_sample = B.dacp_autotune_batched(ctx, hams, N, opts, sample_every=1)
     tuning_s = time.perf_counter() - t0
     B.dacp_central_eigs_batched(ctx, hams, N, tuned)  # the tuned shapes' buffers into the block cache
     options = {"kfac": tuned.kfac, "basis_ratio": tuned.basis_ratio, "window_ratio": tuned.window_ratio,

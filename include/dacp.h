@@ -448,12 +448,13 @@ dacp_status dacp_spacing_ratios(const double *eigs, int n, double *r_out, double
 dacp_status dacp_autotune(dacp_ctx ctx, dacp_ham h, int b, int steps, int *best_group, double *best_us_per_column_step);
 
 /* Autotuner of the batched schedule: runs dacp_central_eigs_batched on a sample of the realisations
- * (every sample_every-th one, plus the first of each L present) for each candidate window ratio
- * (2.2, 2.5, 2.8), basis ratio (1.3, 1.5) and filter factor kfac (12, 18), with no window retry,
- * and keeps the fastest candidate whose every sampled realisation reached N on its first window.
- * A wider window costs larger subspace problems but avoids redoing realisations whose certified
- * core falls short; kfac trades filter length against the core.  best (host) gets opts_in (may be
- * NULL: defaults) with those three fields replaced; best_s (host, may be NULL) the sample's time.
+ * (every sample_every-th one, plus the first of each L present; sample_every = 1 times the whole
+ * set) for each candidate window ratio (2.2, 2.5, 2.8), basis ratio (1.3, 1.5) and filter factor
+ * kfac (12, 18), with the caller's window retries (opts_in->max_retries), and keeps the fastest
+ * candidate whose every sampled realisation reached N.  A wider window costs larger subspace
+ * problems but redoes fewer realisations whose certified core falls short; kfac trades filter
+ * length against the core.  best (host) gets opts_in (may be NULL: defaults) with those three
+ * fields replaced; best_s (host, may be NULL) the sample's time with that schedule.
  * Returns DACP_E_WINDOW if no candidate reached N everywhere. */
 dacp_status dacp_autotune_batched(dacp_ctx ctx, int count, const dacp_ham *hams, int N, const dacp_opts *opts_in,
                                   int sample_every, dacp_opts *best, double *best_s);

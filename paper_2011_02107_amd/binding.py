@@ -530,8 +530,8 @@ def dacp_central_eigs_batched(ctx, hams, N, opts=None, raise_on_window=True, mod
 
 
 def dacp_autotune_batched(ctx, hams, N, opts=None, sample_every=8):
-    """Fastest (window ratio, basis ratio, kfac) that reaches N on the first window on a sample of the
-    realisations; returns (tuned Opts, sample time in s)."""
+    """Fastest (window ratio, basis ratio, kfac) on a sample of the realisations (sample_every = 1:
+    all of them), window retries as in opts included; returns (tuned Opts, sample time in s)."""
     if opts is None:
         opts = default_opts()
     count = len(hams)

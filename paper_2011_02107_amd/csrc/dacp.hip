@@ -3019,7 +3019,6 @@ dacp_status dacp_autotune_batched(dacp_ctx ctx, int count, const dacp_ham *hams,
         c.window_ratio = wr;
         c.basis_ratio = br;
         c.kfac = kf;
-        c.max_retries = 0;  // a candidate must reach N on its first window
         const double t0 = now_ms();
         const dacp_status st = central_eigs_batched(ctx, ns, smp.data(), N, &c, e.data(), nullptr, n_out.data(),
                                                     rp.data(), nullptr);
@@ -3031,11 +3030,10 @@ dacp_status dacp_autotune_batched(dacp_ctx ctx, int count, const dacp_ham *hams,
         if (t < best_t) {
           best_t = t;
           *best = c;
-          best->max_retries = o.max_retries;
           found = true;
         }
       }
-  if (!found) return set_err(ctx, DACP_E_WINDOW, "autotune_batched: no candidate reached N on its first window");
+  if (!found) return set_err(ctx, DACP_E_WINDOW, "autotune_batched: no candidate reached N");
   if (best_s) *best_s = best_t * 1e-3;
   return DACP_OK;
 }
