@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--max-retries", type=int, default=None, help="wider-window retries (default: the library's)")
     ap.add_argument("--moments", action="store_true",
                     help="moment mode (App. C product identity): S and P from moments, no stored basis")
+    ap.add_argument("--moment-mode", type=int, default=None, choices=[0, 1, 2],
+                    help="opts.moment_mode: 0 S = V^T V and P = V^T (H V) of the stored basis, 1 moment mode, "
+                         "2 stored basis with S and P from the anchor panels' moments (default: the mode's)")
     ap.add_argument("--eigvecs", action="store_true",
                     help="time dacp_central_eigpairs (eigenvalues and unit eigenvectors) instead of dacp_central_eigs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,8 +97,10 @@ def opts_for(args, wl):
         # (4851 values with a 2.2 N window, 5234 with 2.4 N, 5469 with 2.5 N, all 5625 candidates
         # with 2.6 N), so 2.4 N is the narrowest window that holds N = 5000 on the first attempt
         # (63.8 s; a retry with the 1.5x window would take about 80 s more)
+        # S and P from the anchor panels' moments (moment_mode 2): the same core as V^T V and V^T (H V)
+        # at L = 20 (5234 values at the 2.4 N window, rank 10962), 0.6 s against 8.4 s for the products
         o = B.default_opts(b=wl["b"], kfac=12.0, window_ratio=2.4, basis_ratio=1.2, precision=B.DACP_F32,
-                           fp64_tail_frac=0.3, group=args.group)
+                           fp64_tail_frac=0.3, group=args.group, moment_mode=2)
     if args.block:
         o.b = args.block
     if args.max_retries is not None:
@@ -112,6 +117,8 @@ def opts_for(args, wl):
         o.fp64_tail_frac = args.tail
     if args.moments:
         o.moment_mode = 1
+    if args.moment_mode is not None:
+        o.moment_mode = args.moment_mode
     return o
 
 
@@ -649,7 +656,7 @@ def main():
             "N": N,
             "mode": args.mode,
             "eigenvectors": bool(args.eigvecs),
-            "moment_mode": bool(args.moments),
+            "moment_mode": int(opts.moment_mode),
             "b": rep["b"],
             "group": g,
             "K": rep["K"],

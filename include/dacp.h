@@ -237,6 +237,24 @@ dacp_status dacp_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, con
 dacp_status dacp_basis_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *S,
                                double *P, int64_t ld, int *m_out);
 
+/* Stored basis with the moment projection (App. C, Eq. shift): the panels of the uniform grid of
+ * dacp_basis_moments are stored in V (device, row-major D x ldv, ldv >= m = b (2n + 1), panel p in
+ * columns [p b, p b + b)).  S and P come from b x b moments given by the Gram products of seven
+ * anchor panels (orders 0, 1, 2, k_n - 2, k_n - 1, k_n, k_n + 1) and of their images under H with
+ * the stored panels: for an anchor of order A and a panel of order x,
+ *   (T_A psi)^T (T_x psi) = (mu_{A+x} + mu_{|A-x|}) / 2,              mu_k = psi^T T_k(G) psi,
+ *   (H T_A psi)^T (T_x psi) = e_bound (nu_{A+x} + nu_{|A-x|}) / 2,    nu_k = psi^T G T_k(G) psi,
+ * so each moment follows from one block and a moment found before it; then
+ *   S block (p, q) = (mu_{x+y} + mu_{|x-y|}) / 2,  P block (p, q) = e_bound (nu_{x+y} + nu_{|x-y|}) / 2.
+ * The evolution runs to k_n + 1; the Gram products are 2 D (14 b) m flops, in place of the 2 D m^2
+ * of V^T V and V^T (H V).  psi_e: device [D][b] FP64, 1 <= b <= 128.  S, P: device m x m, row
+ * stride ld >= m, both triangles written (symmetric parts).  m_out (host, may be NULL) gets m.
+ * Memory besides V, S and P: three D x g FP64 blocks, the anchors and their images (D x 14b FP64)
+ * and the Gram products.  Errors as dacp_basis (DACP_E_BOUNDS when |T_{k_m}(G) psi| exceeds |psi|,
+ * DACP_E_NUMERIC for a non-finite state or moment). */
+dacp_status dacp_basis_stored_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e,
+                                      double *V, int64_t ldv, double *S, double *P, int64_t ld, int *m_out);
+
 /* ------------------------------------------------------------ projection */
 
 /* S = V^T V and P = V^T (H V) (Sec. II.C, Eq. gep) for the first m columns
@@ -316,7 +334,11 @@ typedef struct {
   int moment_mode;     /* 1: moment mode (App. C, Eq. shift; see dacp_basis_moments): S  */
                        /* and P from moments, no stored basis; the candidates' Ritz vectors */
                        /* from a second evolution (D x (N + max(64, N/8)) FP64 on device)   */
-                       /* for the residual acceptance.  0 (default): the basis is stored  */
+                       /* for the residual acceptance.  2: the uniform-grid basis stored, S */
+                       /* and P from the anchors' moments (dacp_basis_stored_moments), the  */
+                       /* Ritz vectors from V as in 0.  0 (default): the basis is stored  */
+                       /* and S = V^T V, P = V^T (H V) are formed.  The batched calls     */
+                       /* ignore this field.                                              */
   int sectors;         /* 1: when H commutes with the global spin flip                  */
                        /* P = prod_i sigma^x_i (every Pauli string has an even number of */
                        /* Z and Y factors), half the start columns are projected onto   */

@@ -144,6 +144,10 @@ SIGNATURES = {
     "dacp_rayleigh_ritz": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i64, ctypes.c_double, _dp, _vp, _ip]),
     "dacp_syev": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _dp, _vp]),
     "dacp_basis_moments": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(BasisParams), _vp, _vp, _vp, _i64, _ip]),
+    "dacp_basis_stored_moments": (
+        ctypes.c_int,
+        [_vp, _vp, ctypes.POINTER(BasisParams), _vp, _vp, _i64, _vp, _vp, _i64, _ip],
+    ),
     "dacp_syev_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "dacp_syev_batched_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "dacp_gemm": (
@@ -365,6 +369,17 @@ def dacp_basis_moments(ctx, ham, psi_e, S, P, e_bound, a, n, group=0):
     m = ctypes.c_int()
     ctx.check(ctx.lib.dacp_basis_moments(ctx.handle, ham.handle, ctypes.byref(p), _ptr(psi_e), _ptr(S), _ptr(P),
                                          int(S.shape[1]), ctypes.byref(m)))
+    return m.value
+
+
+def dacp_basis_stored_moments(ctx, ham, psi_e, V, S, P, e_bound, a, n, group=0):
+    """Uniform-grid basis stored in V (device D x ldv tensor) and S, P (device m x m tensors) from the
+    moments of its anchor panels; returns m = b (2n + 1)."""
+    b = int(psi_e.shape[1])
+    p = BasisParams(float(e_bound), float(a), int(n), b, int(group))
+    m = ctypes.c_int()
+    ctx.check(ctx.lib.dacp_basis_stored_moments(ctx.handle, ham.handle, ctypes.byref(p), _ptr(psi_e), _ptr(V),
+                                                int(V.shape[1]), _ptr(S), _ptr(P), int(S.shape[1]), ctypes.byref(m)))
     return m.value
 
 

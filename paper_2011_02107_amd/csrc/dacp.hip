@@ -12,6 +12,7 @@
 #include <functional>
 #include <tuple>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <mutex>
 #include <set>
@@ -1179,6 +1180,229 @@ dacp_status moment_ritz_vectors(dacp_ctx ctx, dacp_ham h, const dacp_basis_param
   return DACP_OK;
 }
 
+// Stored basis with moment projection (App. C, Eq. shift): the panels of the uniform grid are
+// stored in V as by the evolution basis, and S and P are assembled from b x b moments, but the moments
+// come from Gram products of a few anchor panels with V instead of an evolution to 2 k_n + 1.  For
+// an anchor T_A psi and a panel T_x psi (G = H / e_bound),
+//   (T_A psi)^T (T_x psi)   = (mu_{A+x} + mu_{|A-x|}) / 2,  mu_k = psi^T T_k(G) psi,
+//   (H T_A psi)^T (T_x psi) = e_bound (nu_{A+x} + nu_{|A-x|}) / 2,  nu_k = psi^T G T_k(G) psi,
+// so a moment follows from one such block and the moment at the other order.  The anchors are the
+// orders 0, 1, 2 and k_n - 2 .. k_n + 1 (k_n the last sample): those next to 0 give every moment up to
+// about k_n, those next to k_n the ones beyond.  Then S block (p, q) = (mu_{x+y} + mu_{|x-y|}) / 2 and
+// P block (p, q) = e_bound (nu_{x+y} + nu_{|x-y|}) / 2.  P is taken from nu rather than from mu one
+// order off (T_1 T_k = (T_{k+1} + T_{k-1}) / 2): the window's states have |G| <= a_r, so P is a_r
+// times smaller than the moments, and differences of neighbouring mu would lose that factor of the
+// recurrence's rounding.  The Gram products cost 2 D (14 b) m flops against 2 D m^2 for V^T V and
+// V^T (H V).
+dacp_status run_stored_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e,
+                                    double *V, int64_t ldv, double *S, double *P, int64_t ld, int *m_out,
+                                    EvolStats *stats, double *gram_ms) {
+  const int64_t D = h->D;
+  const int b = p->b, n = p->n;
+  if (b < 1 || b > 128 || n < 1 || !(p->e_bound > 0.0) || !(p->a > 0.0) || p->a >= p->e_bound || !psi_e || !V ||
+      !S || !P)
+    return set_err(ctx, DACP_E_INVALID,
+                   "basis_stored_moments: need 1 <= b <= 128, n >= 1, 0 < a < e_bound, psi_e, V, S, P");
+  const int m = b * (2 * n + 1);
+  if (ldv < m || ld < m) return set_err(ctx, DACP_E_INVALID, "basis_stored_moments: ldv or ld < b (2n + 1)");
+  hipStream_t s = ctx->stream;
+  const MomentPlan mp = moment_plan(p->a / p->e_bound, n);
+  const int npan = static_cast<int>(mp.orders.size());
+  std::map<int64_t, int> panel_of;  // panel order -> panel index
+  for (int q = 0; q < npan; ++q) panel_of[mp.orders[q]] = q;
+  const int64_t kn = mp.orders.back();
+  std::map<int64_t, int> anchor_of;  // anchor order -> anchor slot
+  for (int64_t k : {int64_t(0), int64_t(1), int64_t(2), kn - 2, kn - 1, kn, kn + 1})
+    if (k >= 0) anchor_of.emplace(k, 0);
+  std::vector<int64_t> anchors;
+  for (auto &kv : anchor_of) {
+    kv.second = static_cast<int>(anchors.size());
+    anchors.push_back(kv.first);
+  }
+  const int na = static_cast<int>(anchors.size());
+  const int ma = na * b;  // anchor block width
+  const int g = (p->group > 0 && p->group < b) ? p->group : recurrence_group(ctx, h, b);
+  const double inv_e = 1.0 / p->e_bound;
+  DevBuf ba, bb, pbuf, abuf, nrm;
+  DACP_HIP(ctx, ba.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, bb.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, pbuf.alloc(static_cast<size_t>(D) * g * sizeof(double)));
+  DACP_HIP(ctx, abuf.alloc(static_cast<size_t>(D) * 2 * ma * sizeof(double)));  // anchors | their H images
+  DACP_HIP(ctx, nrm.alloc(static_cast<size_t>(n) * b * sizeof(double)));
+  Timer tm(ctx);
+  tm.start();
+  int64_t launches = 0;
+  for (int g0 = 0; g0 < b; g0 += g) {
+    const int gw = std::min(g, b - g0);
+    double *A = ba.as<double>(), *B = bb.as<double>();
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, A, gw, D, gw, s));
+    DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, V + g0, ldv, D, gw, s));
+    auto store_of = [&](int64_t k) -> double * {
+      auto it = panel_of.find(k);
+      return (k == 0 || it == panel_of.end()) ? nullptr : V + static_cast<int64_t>(it->second) * b + g0;
+    };
+    auto want = [&](int64_t k) { return anchor_of.count(k) > 0; };
+    auto visit = [&](int64_t k, const double *tk) -> dacp_status {
+      DACP_HIP(ctx, dacp::launch_copy_cols(tk, gw, abuf.as<double>() + static_cast<int64_t>(anchor_of[k]) * b + g0,
+                                           2 * ma, D, gw, s));
+      return DACP_OK;
+    };
+    auto events = [&](int64_t k1, int64_t k2) {
+      auto it = panel_of.lower_bound(k1);
+      if (it != panel_of.end() && it->first <= k2) return true;
+      auto ia = anchor_of.lower_bound(k1);
+      return ia != anchor_of.end() && ia->first <= k2;
+    };
+    dacp_status st =
+        evolve_group(ctx, h, inv_e, kn + 1, gw, A, B, pbuf.as<double>(), store_of, ldv, want, visit, events, launches);
+    if (st) return st;
+  }
+  const double evol_ms = tm.stop_ms();
+  // |T_k(G)| <= 1 for e_bound >= ||H||: every stored T_{k_j} column must keep norm <= ||psi_E column||
+  std::vector<double> n0(b), nk(static_cast<size_t>(n) * b);
+  DACP_TRY(coldots_host(ctx, psi_e, b, psi_e, b, DACP_F64, D, b, n0.data()));
+  for (int j = 1; j <= n; ++j)
+    DACP_TRY(coldots_dev(ctx, V + static_cast<int64_t>(2 * j) * b, ldv, V + static_cast<int64_t>(2 * j) * b, ldv,
+                         DACP_F64, D, b, nrm.as<double>() + static_cast<size_t>(j - 1) * b));
+  DACP_TRY(to_host(ctx, nk.data(), nrm.p, sizeof(double) * nk.size()));
+  DACP_HIP(ctx, hipStreamSynchronize(s));
+  for (size_t i = 0; i < nk.size(); ++i) {
+    if (!std::isfinite(nk[i])) return set_err(ctx, DACP_E_NUMERIC, "basis_stored_moments: non-finite evolved state");
+    if (nk[i] > n0[i % b] * (1.0 + 2e-6))
+      return set_err(ctx, DACP_E_BOUNDS, "basis_stored_moments: |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
+  }
+  // images of the anchors under H, beside them
+  const double tg0 = now_ms();
+  for (int c0 = 0; c0 < ma; c0 += 64)
+    DACP_TRY(step<double>(ctx, h, std::min(64, ma - c0), abuf.as<double>() + c0, 2 * ma, abuf.as<double>() + ma + c0,
+                          2 * ma, 1.0));
+  // Gram of the anchors and their images with the panels, (2 na b) x m: block (i, q) =
+  // (T_{anchors[i]} psi)^T (T_{orders[q]} psi), block (na + i, q) = (H T_{anchors[i]} psi)^T (T_{orders[q]} psi)
+  const int mg = 2 * ma;
+  std::vector<double> gm(static_cast<size_t>(mg) * m);
+  {
+    DevBuf gd, work;
+    DACP_HIP(ctx, gd.alloc(gm.size() * sizeof(double)));
+    const int64_t tiles = static_cast<int64_t>((mg + 127) / 128) * ((m + 127) / 128);
+    const int sp = static_cast<int>(std::min<int64_t>(
+        {16, std::max<int64_t>(1, (4 * ctx->num_cus + tiles - 1) / tiles), std::max<int64_t>(1, D / 4096)}));
+    if (sp > 1) {
+      DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * mg * m * sizeof(double)));
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, mg, m, D, 1.0, abuf.as<double>(), mg, V, ldv, 0.0, gd.as<double>(),
+                                              m, 0, sp, work.as<double>(), s));
+    } else {
+      DACP_HIP(ctx, dacp::launch_dgemm(1, 0, mg, m, D, 1.0, abuf.as<double>(), mg, V, ldv, 0.0, gd.as<double>(), m, 0,
+                                       s));
+    }
+    DACP_TRY(to_host(ctx, gm.data(), gd.p, gm.size() * sizeof(double)));
+    DACP_HIP(ctx, hipStreamSynchronize(s));
+  }
+  abuf.release();
+  // the orders S and P read: x + y and |x - y| over the panel orders, one slot each
+  std::vector<int> slot_of(static_cast<size_t>(2 * kn) + 1, -1);
+  int nslot = 0;
+  for (int64_t x : mp.orders)
+    for (int64_t y : mp.orders)
+      for (int64_t k : {x + y, x >= y ? x - y : y - x})
+        if (slot_of[k] < 0) slot_of[k] = nslot++;
+  // Which pair gives which moment: sweep the (anchor, panel) pairs until nothing new follows; a
+  // moment is derived once, from the first pair that reaches it.  mu and nu share the rules.
+  struct Rule {
+    int ai, q;
+    int64_t other;  // the moment subtracted (-1: the block is the moment itself)
+  };
+  std::unordered_map<int64_t, int> rule_of;  // order -> index into rules
+  std::vector<std::pair<int64_t, Rule>> rules;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int ai = 0; ai < na; ++ai)
+      for (int q = 0; q < npan; ++q) {
+        const int64_t sum = anchors[ai] + mp.orders[q];
+        const int64_t dif = anchors[ai] >= mp.orders[q] ? anchors[ai] - mp.orders[q] : mp.orders[q] - anchors[ai];
+        const bool hs = rule_of.count(sum) > 0, hd = rule_of.count(dif) > 0;
+        int64_t k = -1, other = -1;
+        if (sum == dif) {
+          if (!hs) k = sum;
+        } else if (hd && !hs) {
+          k = sum;
+          other = dif;
+        } else if (hs && !hd) {
+          k = dif;
+          other = sum;
+        }
+        if (k < 0) continue;
+        rule_of[k] = static_cast<int>(rules.size());
+        rules.push_back({k, Rule{ai, q, other}});
+        changed = true;
+      }
+  }
+  // the moments the assembly reads, and the ones they are derived from
+  std::vector<char> used(rules.size(), 0);
+  for (int64_t k = 0; k <= 2 * kn; ++k) {
+    if (slot_of[k] < 0) continue;
+    auto it = rule_of.find(k);
+    if (it == rule_of.end())
+      return set_err(ctx, DACP_E_INVALID, "basis_stored_moments: moment " + std::to_string(k) + " not reachable");
+    for (int r = it->second; r >= 0 && !used[r];) {
+      used[r] = 1;
+      const int64_t o = rules[r].second.other;
+      r = o < 0 ? -1 : rule_of.at(o);
+    }
+  }
+  // evaluate in the order found (a rule's other moment was derived before it); mu from the anchor
+  // rows, nu from the image rows scaled by 1 / e_bound
+  const size_t bb2 = static_cast<size_t>(b) * b;
+  std::vector<double> muh(static_cast<size_t>(nslot) * bb2), nuh(muh.size());
+  for (int part = 0; part < 2; ++part) {
+    std::unordered_map<int64_t, std::vector<double>> mom;
+    std::vector<double> &out = part == 0 ? muh : nuh;
+    const double sc = part == 0 ? 1.0 : 1.0 / p->e_bound;
+    for (size_t r = 0; r < rules.size(); ++r) {
+      if (!used[r]) continue;
+      const int64_t k = rules[r].first;
+      const Rule &ru = rules[r].second;
+      std::vector<double> mk(bb2);
+      const std::vector<double> *ot = ru.other < 0 ? nullptr : &mom.at(ru.other);
+      const size_t row0 = static_cast<size_t>(part * na + ru.ai) * b;
+      for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+          const double gij = sc * gm[(row0 + i) * m + static_cast<size_t>(ru.q) * b + j];
+          mk[static_cast<size_t>(i) * b + j] = ot ? 2.0 * gij - (*ot)[static_cast<size_t>(i) * b + j] : gij;
+        }
+      if (k <= 2 * kn && slot_of[k] >= 0)
+        std::copy(mk.begin(), mk.end(), out.begin() + static_cast<size_t>(slot_of[k]) * bb2);
+      mom.emplace(k, std::move(mk));
+    }
+  }
+  for (size_t i = 0; i < muh.size(); ++i)
+    if (!std::isfinite(muh[i]) || !std::isfinite(nuh[i]))
+      return set_err(ctx, DACP_E_NUMERIC, "basis_stored_moments: non-finite moment");
+  DevBuf mu, nu, didx, dord;
+  DACP_HIP(ctx, mu.alloc(muh.size() * sizeof(double)));
+  DACP_HIP(ctx, nu.alloc(nuh.size() * sizeof(double)));
+  DACP_HIP(ctx, didx.alloc(slot_of.size() * sizeof(int)));
+  DACP_HIP(ctx, dord.alloc(mp.orders.size() * sizeof(int64_t)));
+  DACP_TRY(to_device(ctx, mu.p, muh.data(), muh.size() * sizeof(double)));
+  DACP_TRY(to_device(ctx, nu.p, nuh.data(), nuh.size() * sizeof(double)));
+  DACP_TRY(to_device(ctx, didx.p, slot_of.data(), slot_of.size() * sizeof(int)));
+  DACP_TRY(to_device(ctx, dord.p, mp.orders.data(), mp.orders.size() * sizeof(int64_t)));
+  DACP_HIP(ctx, dacp::launch_gram_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, 1.0, S, ld, s));
+  DACP_HIP(ctx, dacp::launch_gram_assemble(nu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, p->e_bound, P,
+                                           ld, s));
+  DACP_HIP(ctx, dacp::launch_symmetrize(S, m, ld, s));
+  DACP_HIP(ctx, dacp::launch_symmetrize(P, m, ld, s));
+  DACP_HIP(ctx, hipStreamSynchronize(s));
+  if (gram_ms) *gram_ms = now_ms() - tg0;
+  if (m_out) *m_out = m;
+  if (stats) {
+    stats->steps = kn + 1;
+    stats->launches = launches;
+    stats->kernel_ms = evol_ms;
+    stats->group = g;
+  }
+  return DACP_OK;
+}
+
 
 dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
                         int64_t ld) {
@@ -1840,6 +2064,12 @@ dacp_status dacp_basis_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params
   return run_moment_basis(ctx, h, p, psi_e, S, P, ld, m_out, nullptr);
 }
 
+dacp_status dacp_basis_stored_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e,
+                                      double *V, int64_t ldv, double *S, double *P, int64_t ld, int *m_out) {
+  if (!ctx || !h || !p) return DACP_E_INVALID;
+  return run_stored_moment_basis(ctx, h, p, psi_e, V, ldv, S, P, ld, m_out, nullptr, nullptr);
+}
+
 dacp_status dacp_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
                          int64_t ld) {
   if (!ctx || !h) return DACP_E_INVALID;
@@ -2052,6 +2282,11 @@ dacp_status accept_stage(dacp_ctx ctx, dacp_ham h, int N, double a, double n_w, 
   return DACP_OK;
 }
 
+dacp_status finish_projected(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
+                             double norm_est, const double *V, int m, DevBuf &sb, DevBuf &pb, dacp_report &rep,
+                             double *eigs_out, double *err_out, int &accepted, const EigFn *eig, double *vecs_out,
+                             int64_t ldvec);
+
 dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
                          double norm_est, const double *V, int m, dacp_report &rep, double *eigs_out, double *err_out,
                          int &accepted, const EigFn *eig = nullptr, double *vecs_out = nullptr,
@@ -2066,9 +2301,19 @@ dacp_status finish_basis(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, do
   if (st) return st;
   rep.t_project_ms = now_ms() - t0;
   vlog("projection done: %.1f ms", rep.t_project_ms);
+  return finish_projected(ctx, h, N, o, a, n_w, tol, norm_est, V, m, sb, pb, rep, eigs_out, err_out, accepted, eig,
+                          vecs_out, ldvec);
+}
 
+// The subspace solve of S and P (released once reduced) and the acceptance on the Ritz vectors V b_j
+// of the stored basis.
+dacp_status finish_projected(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, double a, double n_w, double tol,
+                             double norm_est, const double *V, int m, DevBuf &sb, DevBuf &pb, dacp_report &rep,
+                             double *eigs_out, double *err_out, int &accepted, const EigFn *eig, double *vecs_out,
+                             int64_t ldvec) {
   // generalised eigenproblem (App. C)
-  t0 = now_ms();
+  double t0 = now_ms();
+  dacp_status st;
   std::vector<double> theta;
   DevBuf bc;
   int r = 0;
@@ -2152,6 +2397,7 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
   dacp_opts o;
   if (opts_in) o = *opts_in;
   else dacp_default_opts(&o);
+  if (o.moment_mode < 0 || o.moment_mode > 2) return set_err(ctx, DACP_E_INVALID, "central_eigs: moment_mode is 0, 1 or 2");
   dacp_report rep;
   std::memset(&rep, 0, sizeof(rep));
   const double t_start = now_ms();
@@ -2227,7 +2473,7 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
     bp.n = n;
     bp.b = b;
     bp.group = o.group;
-    if (o.moment_mode) {
+    if (o.moment_mode == 1) {
       st = moment_attempt(ctx, h, N, o, bp, a, n_w, tol, norm_est, psi, rep, eigs_out, err_out, accepted, vecs_out,
                           ldvec);
       if (st) return st;
@@ -2248,19 +2494,42 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
     DACP_HIP(ctx, vbuf.alloc(static_cast<size_t>(D) * m * sizeof(double)));
     EvolStats es;
     int m_got = 0;
-    st = run_basis(ctx, h, &bp, psi.as<double>(), vbuf.as<double>(), m, &m_got, &es);
-    if (st) return st;
-    psi.release();
-    rep.t_evol_ms = now_ms() - t0;
-    rep.evol_steps = es.steps;
-    rep.evol_launches = es.launches;
-    rep.evol_kernel_ms = es.kernel_ms;
-    rep.evol_group = es.group;
-    vlog("evolution done: %.1f ms (%lld launches)", rep.t_evol_ms, static_cast<long long>(es.launches));
+    if (o.moment_mode == 2) {
+      // the uniform-grid basis stored, S and P from the anchors' moments (no V^T V, V^T H V)
+      DevBuf sb, pb;
+      DACP_HIP(ctx, sb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+      DACP_HIP(ctx, pb.alloc(static_cast<size_t>(m) * m * sizeof(double)));
+      double gram_ms = 0.0;
+      st = run_stored_moment_basis(ctx, h, &bp, psi.as<double>(), vbuf.as<double>(), m, sb.as<double>(),
+                                   pb.as<double>(), m, &m_got, &es, &gram_ms);
+      if (st) return st;
+      psi.release();
+      rep.t_evol_ms = now_ms() - t0 - gram_ms;
+      rep.t_project_ms = gram_ms;
+      rep.evol_steps = es.steps;
+      rep.evol_launches = es.launches;
+      rep.evol_kernel_ms = es.kernel_ms;
+      rep.evol_group = es.group;
+      vlog("evolution done: %.1f ms (%lld launches); moments and S, P: %.1f ms", rep.t_evol_ms,
+           static_cast<long long>(es.launches), gram_ms);
+      st = finish_projected(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, sb, pb, rep, eigs_out, err_out,
+                            accepted, nullptr, vecs_out, ldvec);
+      if (st) return st;
+    } else {
+      st = run_basis(ctx, h, &bp, psi.as<double>(), vbuf.as<double>(), m, &m_got, &es);
+      if (st) return st;
+      psi.release();
+      rep.t_evol_ms = now_ms() - t0;
+      rep.evol_steps = es.steps;
+      rep.evol_launches = es.launches;
+      rep.evol_kernel_ms = es.kernel_ms;
+      rep.evol_group = es.group;
+      vlog("evolution done: %.1f ms (%lld launches)", rep.t_evol_ms, static_cast<long long>(es.launches));
 
-    st = finish_basis(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, rep, eigs_out, err_out, accepted,
-                      nullptr, vecs_out, ldvec);
-    if (st) return st;
+      st = finish_basis(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, rep, eigs_out, err_out, accepted,
+                        nullptr, vecs_out, ldvec);
+      if (st) return st;
+    }
     if (accepted >= N) {
       if (n_out) *n_out = N;
       rep.t_total_ms = now_ms() - t_start;

@@ -204,6 +204,9 @@ hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *
 // S and P (m x m, m = npan b) of the panels of orders orders[p] from the moment slots (see kernels.hip).
 hipError_t launch_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
                                   double e_b, double *S, double *P, int64_t ld, hipStream_t s);
+// out (m x m, m = npan b) block (p, q) = scale (M_{x+y} + M_{|x-y|}) / 2 from the moment slots.
+hipError_t launch_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
+                                double scale, double *out, int64_t ld, hipStream_t s);
 // dst[r][c] = src[r][cols[c]] * scale[c] for r < D, c < w (scale may be null).
 hipError_t launch_gather_cols(const double *src, int64_t lds, const int *cols, const double *scale, int64_t D, int w,
                               double *dst, int64_t ldd, hipStream_t s);

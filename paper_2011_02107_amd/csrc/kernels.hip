@@ -1102,6 +1102,30 @@ hipError_t launch_moment_assemble(const double *mu, const int *idx_of, const int
   return hipGetLastError();
 }
 
+// out block (p, q) = scale (M_{x+y} + M_{|x-y|}) / 2, x, y the orders of panels p, q, M_k the b x b
+// moment in slot idx_of[k] of mu (the product identity T_x T_y = (T_{x+y} + T_{|x-y|}) / 2).
+__global__ void k_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int m, double scale,
+                                double *out, int64_t ld) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(m) * m) return;
+  const int row = static_cast<int>(e / m), col = static_cast<int>(e - static_cast<int64_t>(row) * m);
+  const int p = row / b, i = row - p * b, q = col / b, j = col - q * b;
+  const int64_t x = orders[p], y = orders[q];
+  const int64_t d = x >= y ? x - y : y - x;
+  const double ms = mu[static_cast<int64_t>(idx_of[x + y]) * b * b + i * b + j];
+  const double md = mu[static_cast<int64_t>(idx_of[d]) * b * b + i * b + j];
+  out[row * ld + col] = 0.5 * scale * (ms + md);
+}
+
+hipError_t launch_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
+                                double scale, double *out, int64_t ld, hipStream_t s) {
+  const int m = b * npan;
+  const int64_t n = static_cast<int64_t>(m) * m;
+  hipLaunchKernelGGL(k_gram_assemble, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, mu, idx_of,
+                     orders, b, m, scale, out, ld);
+  return hipGetLastError();
+}
+
 // dst[r][c] = src[r][cols[c]] * scale[c] (scale may be null).
 __global__ void k_gather_cols(const double *src, int64_t lds, const int *cols, const double *scale, int64_t D, int w,
                               double *dst, int64_t ldd) {

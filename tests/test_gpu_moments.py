@@ -8,6 +8,10 @@
   * dacp_central_eigs with opts.moment_mode = 1 (no stored basis; the candidates' Ritz vectors from a
     second evolution) against the dense oracle and Jordan-Wigner, and its eigenvectors against the
     dense eigenvectors.
+  * dacp_basis_stored_moments: the stored uniform-grid panels against the oracle's Chebyshev basis
+    on the same orders, S and P (moments derived from the anchor panels' Gram products) against the
+    oracle's moment assembly and the explicit projection; dacp_central_eigs with opts.moment_mode = 2
+    against the dense oracle and Jordan-Wigner.
 """
 import numpy as np
 import pytest
@@ -88,6 +92,63 @@ def test_basis_moments_fused_kernels_L16(ctx):
     assert np.abs(_host(P) - Po).max() <= 1e-13 * D * np.abs(Po).max()
 
 
+@pytest.mark.parametrize("L,b,a_r,n,terms_of", [
+    (8, 4, 0.2, 3, lambda L: inputs.ising_chain(L)),
+    (9, 8, 0.9, 4, lambda L: inputs.spin_glass(L, 2)),      # grid step 2: anchors and panels overlap
+    (10, 3, 0.05, 2, lambda L: inputs.spin_glass(L, 4)),    # b not a power of two
+    (11, 5, 0.7, 1, lambda L: inputs.ising_chain(L)),       # one sample pair: k_n - 2 is below k_1 - 1
+    (16, 8, 0.3, 2, lambda L: inputs.ising_chain(L)),       # fused split kernels, split-K Gram
+])
+def test_basis_stored_moments_match_the_oracle(ctx, L, b, a_r, n, terms_of):
+    terms = terms_of(L)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    e_b = 1.01 * hamiltonian.sum_abs_coeff(terms)
+    psi = np.random.default_rng(L + 100).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0, keepdims=True)
+    m = b * (2 * n + 1)
+    D = 1 << L
+    V = torch.zeros((D, m + 2), dtype=torch.float64, device=DEV)
+    S = torch.zeros((m, m + 3), dtype=torch.float64, device=DEV)
+    P = torch.zeros((m, m + 3), dtype=torch.float64, device=DEV)
+    got_m = B.dacp_basis_stored_moments(ctx, ham, torch.as_tensor(psi, device=DEV), V, S, P, e_b, a_r * e_b, n)
+    assert got_m == m
+    Vg, Sg, Pg = _host(V)[:, :m], _host(S)[:, :m], _host(P)[:, :m]
+    apply = lambda X: hamiltonian.apply_h(L, terms, X)
+    delta, ks = chebyshev.uniform_sample_orders(a_r, n)
+    orders = chebyshev.panel_orders(ks)
+    Vo = chebyshev.basis_on_orders(apply, psi, e_b, orders)
+    assert np.abs(Vg - Vo).max() < 1e-15 * max(ks) + 1e-12
+    mu = chebyshev.chebyshev_moments(apply, psi, e_b, 2 * ks[-1] + 1)
+    So, Po = chebyshev.moment_projection(mu, orders, e_b)
+    Se, Pe = subspace.project(apply, Vo)
+    for got, ref in ((Sg, So), (Pg, Po), (Sg, Se), (Pg, Pe)):
+        assert np.abs(got - ref).max() <= 1e-13 * D * np.abs(ref).max()
+    assert np.array_equal(Sg, Sg.T) and np.array_equal(Pg, Pg.T)
+
+
+def test_basis_stored_moments_match_the_explicit_projection_L16(ctx):
+    """Moment assembly against the library's own V^T V and V^T (H V) of the stored panels, at a grid
+    of 41 panels on the fused kernels (the explicit products read the same V)."""
+    L, b, a_r, n = 16, 8, 0.05, 20
+    terms = inputs.spin_glass(L, 3)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    e_b = 1.01 * hamiltonian.sum_abs_coeff(terms)
+    psi = np.random.default_rng(3).standard_normal((1 << L, b))
+    psi /= np.linalg.norm(psi, axis=0, keepdims=True)
+    m = b * (2 * n + 1)
+    V = torch.zeros((1 << L, m), dtype=torch.float64, device=DEV)
+    S = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    P = torch.zeros((m, m), dtype=torch.float64, device=DEV)
+    B.dacp_basis_stored_moments(ctx, ham, torch.as_tensor(psi, device=DEV), V, S, P, e_b, a_r * e_b, n)
+    Se = torch.zeros_like(S)
+    Pe = torch.zeros_like(P)
+    B.dacp_project(ctx, ham, V, Se, Pe)
+    Sg, Pg, Se, Pe = _host(S), _host(P), _host(Se), _host(Pe)
+    # both sides are rounded sums over D terms; the moments also carry the recurrence's rounding
+    assert np.abs(Sg - Se).max() <= 1e-12 * np.abs(Se).max()
+    assert np.abs(Pg - Pe).max() <= 1e-12 * np.abs(Pe).max()
+
+
 def _check(got, errs, ref, norm, N, label):
     assert len(got) == N, label
     err = np.abs(np.sort(got) - ref)
@@ -107,6 +168,35 @@ def test_central_eigs_moment_mode_against_dense_oracle(ctx, label, L, terms, N, 
     e2, _, rep2, _ = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=b))
     print(f"{label}: moment mode m {rep['m']} rank {rep['rank']} core {rep['n_accepted']} evolution steps "
           f"{rep['evol_steps']} (stored basis: rank {rep2['rank']} core {rep2['n_accepted']} steps {rep2['evol_steps']})")
+
+
+@pytest.mark.parametrize("label,L,terms,N,b", [
+    ("chain L10", 10, inputs.ising_chain(10), 100, 4),
+    ("glass L12", 12, inputs.spin_glass(12, 0), 200, 8),
+    ("glass L13", 13, inputs.spin_glass(13, 5), 300, 16),
+])
+def test_central_eigs_stored_moments_against_dense_oracle(ctx, label, L, terms, N, b):
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=b, moment_mode=2))
+    _check(eigs, errs, ref, norm, N, label)
+
+
+def test_central_eigs_stored_moments_jw_twin_L16(ctx):
+    """The integrable chain at L = 16, N = 1000, b = 64, FP32 filter + FP64 tail, stored basis with the
+    moment projection: every value against the exact Jordan-Wigner spectrum."""
+    L, N = 16, 1000
+    ham = B.dacp_build_hamiltonian(ctx, L, inputs.ising_chain(L, hz=0.0))
+    ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
+    o = B.default_opts(b=64, kfac=12.0, basis_ratio=1.2, precision=B.DACP_F32, fp64_tail_frac=0.3, moment_mode=2)
+    eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o)
+    _check(eigs, errs, ref, norm, N, "JW twin L16 stored moments")
+
+
+def test_central_eigs_moment_mode_rejects_unknown_value(ctx):
+    ham = B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8))
+    with pytest.raises(B.DacpError):
+        B.dacp_central_eigs(ctx, ham, 10, B.default_opts(b=4, moment_mode=3))
 
 
 def test_central_eigs_moment_mode_jw_twin_L16(ctx):
@@ -148,7 +238,8 @@ def test_central_eigpairs_moment_mode_vectors(ctx):
 def test_central_eigs_moment_mode_jw_twin_L18_N5000(ctx):
     """The integrable chain at L = 18 (D = 262144), N = 5000, in the benchmark's tuned options and in
     moment mode (three evolution passes' worth of steps, no stored basis), every value against the
-    exact Jordan-Wigner spectrum; the stored-basis mode on the same input for comparison."""
+    exact Jordan-Wigner spectrum; the stored basis with explicit products and with the moment
+    projection on the same input too."""
     import time
 
     L, N = 18, 5000
@@ -164,6 +255,12 @@ def test_central_eigs_moment_mode_jw_twin_L18_N5000(ctx):
     e2, errs2, rep2, _ = B.dacp_central_eigs(ctx, ham, N, o)
     t_exp = time.perf_counter() - t0
     _check(e2, errs2, ref, norm, N, "JW twin L18 stored basis")
+    o.moment_mode = 2
+    t0 = time.perf_counter()
+    e3, errs3, rep3, _ = B.dacp_central_eigs(ctx, ham, N, o)
+    t_sm = time.perf_counter() - t0
+    _check(e3, errs3, ref, norm, N, "JW twin L18 stored basis, moment projection")
     print(f"L=18 N=5000: moment mode {t_mom:.1f} s (evolution steps {rep['evol_steps']}, rank {rep['rank']}), "
-          f"stored basis {t_exp:.1f} s (steps {rep2['evol_steps']}, rank {rep2['rank']}); "
-          f"max error {np.abs(eigs - ref).max() / norm:.1e} / {np.abs(e2 - ref).max() / norm:.1e} of ||H||")
+          f"stored basis {t_exp:.1f} s (steps {rep2['evol_steps']}, rank {rep2['rank']}), with the moment "
+          f"projection {t_sm:.1f} s (rank {rep3['rank']}); max error {np.abs(eigs - ref).max() / norm:.1e} / "
+          f"{np.abs(e2 - ref).max() / norm:.1e} / {np.abs(e3 - ref).max() / norm:.1e} of ||H||")

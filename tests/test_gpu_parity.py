@@ -806,16 +806,18 @@ def test_central_eigs_paper_spin_glass_shard_L12(ctx):
     _check_central(eigs, ref, norm, N, errs=errs)
 
 
-def test_central_eigs_jw_twin_L20_full_size(ctx):
+@pytest.mark.parametrize("moment_mode", [0, 2])
+def test_central_eigs_jw_twin_L20_full_size(ctx, moment_mode):
     """Full size, in the benchmark's tuned configuration (D = 2^20, N = 5000, b = 64, FP32 filter with
-    an FP64 tail, basis ratio 1.2): the integrable twin (hz = 0) of the benchmark chain against the
-    exact Jordan-Wigner spectrum, every one of the N values."""
+    an FP64 tail, window 2.4 N, basis ratio 1.2), with S and P as explicit products (0) and from the
+    anchor panels' moments (2, the benchmark's): the integrable twin (hz = 0) of the benchmark chain
+    against the exact Jordan-Wigner spectrum, every one of the N values."""
     L, N = 20, 5000
     terms = inputs.ising_chain(L, hz=0.0)
     ref, norm = central.central_eigenvalues_jw(np.ones(L - 1), 1.05 * np.ones(L), N)
     ham = B.dacp_build_hamiltonian(ctx, L, terms)
-    opts = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
-                          fp64_tail_frac=0.3)
+    opts = B.default_opts(b=64, kfac=12.0, window_ratio=2.4, basis_ratio=1.2, precision=B.DACP_F32,
+                          fp64_tail_frac=0.3, moment_mode=moment_mode)
     eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, opts)
     _check_central(eigs, ref, norm, N, errs=errs)
     assert np.all(errs <= 1e-10 * norm)
