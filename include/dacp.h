@@ -226,14 +226,16 @@ dacp_status dacp_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, con
  * sit on the uniform grid k_m = m Delta, Delta = 2 floor(pi / (2 a_r)) (a_r = a / e_bound), so that
  * sums of sampled orders are sampled too; the panels are
  *   panel 0 = psi_E, panel 2m-1 = T_{k_m - 1}(G) psi_E, panel 2m = T_{k_m}(G) psi_E, m = 1..n.
- * The evolution runs to 2 k_n + 1 and records the b x b moments mu_k = psi_E^T T_k(G) psi_E at every
- * order the product identity T_x T_y = (T_{x+y} + T_{|x-y|}) / 2 needs; then, with H = e_bound T_1(G),
+ * The evolution runs to 2 k_n and records the b x b moments mu_k = psi_E^T T_k(G) psi_E and
+ * nu_k = psi_E^T G T_k(G) psi_E at every order x + y, |x - y| of two panel orders; then, with the
+ * product identity T_x T_y = (T_{x+y} + T_{|x-y|}) / 2 and H = e_bound G,
  *   S block (p, q) = (mu_{x+y} + mu_{|x-y|}) / 2,
- *   P block (p, q) = e_bound (mu_{x+y+1} + mu_{|x-y-1|} + mu_{x+|y-1|} + mu_{|x-|y-1||}) / 4,
+ *   P block (p, q) = e_bound (nu_{x+y} + nu_{|x-y|}) / 2,
  * x, y the orders of panels p, q.  psi_e: device [D][b] FP64, 1 <= b <= 128.  S, P: device m x m,
  * row stride ld >= m = b (2n + 1), both triangles written (symmetric parts of the assembled
- * blocks).  m_out (host, may be NULL) gets m.  Memory besides S and P: three D x g FP64 blocks and
- * the moments.  Errors as dacp_basis (DACP_E_BOUNDS when |T_{k_m}(G) psi| exceeds |psi|). */
+ * blocks).  m_out (host, may be NULL) gets m.  Memory besides S and P: three D x g FP64 blocks,
+ * G psi_E (D x b) and the moments.  Errors as dacp_basis (DACP_E_BOUNDS when |T_{k_m}(G) psi|
+ * exceeds |psi|). */
 dacp_status dacp_basis_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e, double *S,
                                double *P, int64_t ld, int *m_out);
 

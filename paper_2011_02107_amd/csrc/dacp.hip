@@ -990,15 +990,17 @@ dacp_status project_small(dacp_ctx ctx, dacp_ham h, int m, const double *V, int6
 
 // ------------------------------------------------------------- moment mode
 // Moment mode (App. C, Eq. shift): the panels T_x(G) psi_E are never stored.  S and P follow from
-// the b x b moments mu_k = psi_E^T T_k(G) psi_E through T_x T_y = (T_{x+y} + T_{|x-y|}) / 2 and
-// H = E_b T_1(G); the samples sit on the uniform grid k_m = m Delta, Delta = 2 floor(pi / (2 a_r)),
-// so that the needed orders x + y, |x - y| (and those one step off, for P) are recorded during an
-// evolution to 2 k_n + 1.
+// the b x b moments mu_k = psi_E^T T_k(G) psi_E and nu_k = psi_E^T G T_k(G) psi_E through
+// T_x T_y = (T_{x+y} + T_{|x-y|}) / 2 and H = e_bound G:
+//   S block (p, q) = (mu_{x+y} + mu_{|x-y|}) / 2,  P block (p, q) = e_bound (nu_{x+y} + nu_{|x-y|}) / 2.
+// The samples sit on the uniform grid k_m = m Delta, Delta = 2 floor(pi / (2 a_r)), so that the
+// orders x + y and |x - y| are recorded during an evolution to 2 k_n.  P is taken from nu rather
+// than from mu one order off (G T_k = (T_{k+1} + T_{k-1}) / 2): the window's states have |G| <= a_r,
+// so P is a_r times smaller than the moments, and differences of neighbouring mu would lose that
+// factor of the recurrence's rounding.
 struct MomentPlan {
-  int64_t delta = 0, kmax = 0;
+  int64_t delta = 0;
   std::vector<int64_t> orders;  // panel orders: 0, k_1 - 1, k_1, ..., k_n - 1, k_n
-  std::vector<int> idx_of;      // order -> moment slot, or -1 (k = 0 .. kmax)
-  int nrec = 0;
 };
 
 MomentPlan moment_plan(double a_r, int n) {
@@ -1009,23 +1011,19 @@ MomentPlan moment_plan(double a_r, int n) {
     mp.orders.push_back(j * mp.delta - 1);
     mp.orders.push_back(j * mp.delta);
   }
-  mp.kmax = 2 * n * mp.delta + 1;
-  mp.idx_of.assign(static_cast<size_t>(mp.kmax) + 1, -1);
-  std::vector<char> needed(mp.idx_of.size(), 0);
-  auto need = [&](int64_t k) { needed[k < 0 ? -k : k] = 1; };
-  for (int64_t x : mp.orders)
-    for (int64_t y : mp.orders) {
-      const int64_t ym = y >= 1 ? y - 1 : 1;
-      need(x + y);
-      need(x - y);
-      need(x + y + 1);
-      need(x - y - 1);
-      need(x + ym);
-      need(x - ym);
-    }
-  for (size_t k = 0; k < needed.size(); ++k)
-    if (needed[k]) mp.idx_of[k] = mp.nrec++;  // slots in order of k
   return mp;
+}
+
+// Slot of every order x + y and |x - y| over the panel orders (-1 elsewhere, k = 0 .. 2 k_n), in
+// order of first appearance; nslot gets the count.
+std::vector<int> moment_slots(const std::vector<int64_t> &orders, int &nslot) {
+  std::vector<int> slot_of(static_cast<size_t>(2 * orders.back()) + 1, -1);
+  nslot = 0;
+  for (int64_t x : orders)
+    for (int64_t y : orders)
+      for (int64_t k : {x + y, x >= y ? x - y : y - x})
+        if (slot_of[k] < 0) slot_of[k] = nslot++;
+  return slot_of;
 }
 
 // Moment mode, first pass: filter output psi_e (D x b) -> S and P (device m x m, row stride ld),
@@ -1039,17 +1037,25 @@ dacp_status run_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *
   const int m = b * (2 * n + 1);
   if (ld < m) return set_err(ctx, DACP_E_INVALID, "basis_moments: ld < b (2n + 1)");
   const MomentPlan mp = moment_plan(p->a / p->e_bound, n);
+  const int64_t kmax = 2 * mp.orders.back();
+  int nslot = 0;
+  const std::vector<int> slot_of = moment_slots(mp.orders, nslot);
   int g = (p->group > 0 && p->group < b) ? p->group : recurrence_group(ctx, h, b);
   while (g > 1 && b * g > 1024) g /= 2;  // the tall Gram kernel takes b g <= 1024 pairs
   const double inv_e = 1.0 / p->e_bound;
-  DevBuf ba, bb, pbuf, mu, part, tmp, didx, dord;
+  DevBuf ba, bb, pbuf, gpsi, mu, nu, part, tmp, didx, dord;
   DACP_HIP(ctx, ba.alloc(static_cast<size_t>(D) * g * sizeof(double)));
   DACP_HIP(ctx, bb.alloc(static_cast<size_t>(D) * g * sizeof(double)));
   DACP_HIP(ctx, pbuf.alloc(static_cast<size_t>(D) * g * sizeof(double)));
-  DACP_HIP(ctx, mu.alloc(static_cast<size_t>(mp.nrec) * b * b * sizeof(double)));
+  DACP_HIP(ctx, gpsi.alloc(static_cast<size_t>(D) * b * sizeof(double)));
+  DACP_HIP(ctx, mu.alloc(static_cast<size_t>(nslot) * b * b * sizeof(double)));
+  DACP_HIP(ctx, nu.alloc(static_cast<size_t>(nslot) * b * b * sizeof(double)));
   const int nblk = dacp::tall_gram_blocks(D);
   DACP_HIP(ctx, part.alloc(static_cast<size_t>(nblk) * b * g * sizeof(double)));
   DACP_HIP(ctx, tmp.alloc(static_cast<size_t>(b) * g * sizeof(double)));
+  // G psi_E, the left factor of nu
+  for (int c0 = 0; c0 < b; c0 += 64)
+    DACP_TRY(step<double>(ctx, h, std::min(64, b - c0), psi_e + c0, b, gpsi.as<double>() + c0, b, inv_e));
   Timer tm(ctx);
   tm.start();
   int64_t launches = 0;
@@ -1057,31 +1063,33 @@ dacp_status run_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *
     const int gw = std::min(g, b - g0);
     double *A = ba.as<double>(), *B = bb.as<double>();
     DACP_HIP(ctx, dacp::launch_copy_cols(psi_e + g0, b, A, gw, D, gw, ctx->stream));
-    auto want = [&](int64_t k) { return k <= mp.kmax && mp.idx_of[k] >= 0; };
-    // mu_k[:, g0 .. g0 + gw) = psi_E^T (T_k psi_E)[:, group]
+    auto want = [&](int64_t k) { return k <= kmax && slot_of[k] >= 0; };
+    // mu_k[:, g0 .. g0 + gw) = psi_E^T (T_k psi_E)[:, group], nu_k likewise with (G psi_E)^T
     auto visit = [&](int64_t k, const double *tk) -> dacp_status {
+      const int64_t off = static_cast<int64_t>(slot_of[k]) * b * b + g0;
       DACP_HIP(ctx, dacp::launch_tall_gram(psi_e, b, b, tk, gw, gw, D, part.as<double>(), nblk, tmp.as<double>(),
                                            ctx->stream));
-      DACP_HIP(ctx, dacp::launch_copy_cols(tmp.as<double>(), gw,
-                                           mu.as<double>() + static_cast<int64_t>(mp.idx_of[k]) * b * b + g0, b, b,
-                                           gw, ctx->stream));
+      DACP_HIP(ctx, dacp::launch_copy_cols(tmp.as<double>(), gw, mu.as<double>() + off, b, b, gw, ctx->stream));
+      DACP_HIP(ctx, dacp::launch_tall_gram(gpsi.as<double>(), b, b, tk, gw, gw, D, part.as<double>(), nblk,
+                                           tmp.as<double>(), ctx->stream));
+      DACP_HIP(ctx, dacp::launch_copy_cols(tmp.as<double>(), gw, nu.as<double>() + off, b, b, gw, ctx->stream));
       return DACP_OK;
     };
     auto events = [&](int64_t k1, int64_t k2) {
-      for (int64_t k = k1; k <= k2 && k <= mp.kmax; ++k)
-        if (mp.idx_of[k] >= 0) return true;
+      for (int64_t k = k1; k <= k2 && k <= kmax; ++k)
+        if (slot_of[k] >= 0) return true;
       return false;
     };
     dacp_status st = evolve_group(
-        ctx, h, inv_e, mp.kmax, gw, A, B, pbuf.as<double>(), [](int64_t) -> double * { return nullptr; }, 0, want,
+        ctx, h, inv_e, kmax, gw, A, B, pbuf.as<double>(), [](int64_t) -> double * { return nullptr; }, 0, want,
         visit, events, launches);
     if (st) return st;
   }
   const double evol_ms = tm.stop_ms();
   // |T_k(G)| <= 1 for e_bound >= ||H||: |T_{k_j} psi|^2 = (mu_{2 k_j} + mu_0) / 2 on the diagonal
-  std::vector<double> muh(static_cast<size_t>(mp.nrec) * b * b);
+  std::vector<double> muh(static_cast<size_t>(nslot) * b * b);
   DACP_TRY(to_host(ctx, muh.data(), mu.p, muh.size() * sizeof(double)));
-  auto mu_at = [&](int64_t k, int i, int j) { return muh[(static_cast<size_t>(mp.idx_of[k]) * b + i) * b + j]; };
+  auto mu_at = [&](int64_t k, int i, int j) { return muh[(static_cast<size_t>(slot_of[k]) * b + i) * b + j]; };
   for (int j = 1; j <= n; ++j)
     for (int c = 0; c < b; ++c) {
       const double n0 = mu_at(0, c, c);
@@ -1090,19 +1098,22 @@ dacp_status run_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *
       if (nk > n0 * (1.0 + 4e-6))
         return set_err(ctx, DACP_E_BOUNDS, "basis_moments: |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
     }
-  DACP_HIP(ctx, didx.alloc(mp.idx_of.size() * sizeof(int)));
+  DACP_HIP(ctx, didx.alloc(slot_of.size() * sizeof(int)));
   DACP_HIP(ctx, dord.alloc(mp.orders.size() * sizeof(int64_t)));
-  DACP_TRY(to_device(ctx, didx.p, mp.idx_of.data(), mp.idx_of.size() * sizeof(int)));
+  DACP_TRY(to_device(ctx, didx.p, slot_of.data(), slot_of.size() * sizeof(int)));
   DACP_TRY(to_device(ctx, dord.p, mp.orders.data(), mp.orders.size() * sizeof(int64_t)));
-  DACP_HIP(ctx, dacp::launch_moment_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b,
-                                             static_cast<int>(mp.orders.size()), p->e_bound, S, P, ld, ctx->stream));
+  const int npan = static_cast<int>(mp.orders.size());
+  DACP_HIP(ctx, dacp::launch_gram_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, 1.0, S, ld,
+                                           ctx->stream));
+  DACP_HIP(ctx, dacp::launch_gram_assemble(nu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, p->e_bound, P,
+                                           ld, ctx->stream));
   // the moments are symmetric only up to rounding: take the symmetric parts
   DACP_HIP(ctx, dacp::launch_symmetrize(S, m, ld, ctx->stream));
   DACP_HIP(ctx, dacp::launch_symmetrize(P, m, ld, ctx->stream));
   DACP_HIP(ctx, hipStreamSynchronize(ctx->stream));
   if (m_out) *m_out = m;
   if (stats) {
-    stats->steps = mp.kmax;
+    stats->steps = kmax;
     stats->launches = launches;
     stats->kernel_ms = evol_ms;
     stats->group = g;
@@ -1299,12 +1310,8 @@ dacp_status run_stored_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_p
   }
   abuf.release();
   // the orders S and P read: x + y and |x - y| over the panel orders, one slot each
-  std::vector<int> slot_of(static_cast<size_t>(2 * kn) + 1, -1);
   int nslot = 0;
-  for (int64_t x : mp.orders)
-    for (int64_t y : mp.orders)
-      for (int64_t k : {x + y, x >= y ? x - y : y - x})
-        if (slot_of[k] < 0) slot_of[k] = nslot++;
+  const std::vector<int> slot_of = moment_slots(mp.orders, nslot);
   // Which pair gives which moment: sweep the (anchor, panel) pairs until nothing new follows; a
   // moment is derived once, from the first pair that reaches it.  mu and nu share the rules.
   struct Rule {

@@ -201,9 +201,6 @@ hipError_t launch_resid(const double *x, const double *hx, int64_t ld, const dou
 int tall_gram_blocks(int64_t D);
 hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *Y, int64_t ldy, int gy, int64_t D,
                             double *partial, int nblk, double *out, hipStream_t s);
-// S and P (m x m, m = npan b) of the panels of orders orders[p] from the moment slots (see kernels.hip).
-hipError_t launch_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
-                                  double e_b, double *S, double *P, int64_t ld, hipStream_t s);
 // out (m x m, m = npan b) block (p, q) = scale (M_{x+y} + M_{|x-y|}) / 2 from the moment slots.
 hipError_t launch_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
                                 double scale, double *out, int64_t ld, hipStream_t s);

@@ -1076,32 +1076,6 @@ hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *
   return hipGetLastError();
 }
 
-// S and P (m x m, m = npan b, row stride ld) of the panels T_x(G) psi_E, x = orders[p], from the
-// recorded moments mu (slot idx_of[k], b x b row-major per slot): block (p, q) of S is
-// (mu_{x+y} + mu_{|x-y|}) / 2 and block (p, q) of P is
-// e_b (mu_{x+y+1} + mu_{|x-y-1|} + mu_{x+|y-1|} + mu_{|x-|y-1||}) / 4 (H = e_b T_1(G)).
-__global__ void k_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int m,
-                                  double e_b, double *S, double *P, int64_t ld) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(m) * m) return;
-  const int row = static_cast<int>(e / m), col = static_cast<int>(e - static_cast<int64_t>(row) * m);
-  const int p = row / b, i = row - p * b, q = col / b, j = col - q * b;
-  const int64_t x = orders[p], y = orders[q];
-  const int64_t ym = y >= 1 ? y - 1 : 1;
-  auto at = [&](int64_t k) { return mu[static_cast<int64_t>(idx_of[k < 0 ? -k : k]) * b * b + i * b + j]; };
-  S[row * ld + col] = 0.5 * (at(x + y) + at(x - y));
-  P[row * ld + col] = 0.25 * e_b * (at(x + y + 1) + at(x - y - 1) + at(x + ym) + at(x - ym));
-}
-
-hipError_t launch_moment_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
-                                  double e_b, double *S, double *P, int64_t ld, hipStream_t s) {
-  const int m = b * npan;
-  const int64_t n = static_cast<int64_t>(m) * m;
-  hipLaunchKernelGGL(k_moment_assemble, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, mu, idx_of,
-                     orders, b, m, e_b, S, P, ld);
-  return hipGetLastError();
-}
-
 // out block (p, q) = scale (M_{x+y} + M_{|x-y|}) / 2, x, y the orders of panels p, q, M_k the b x b
 // moment in slot idx_of[k] of mu (the product identity T_x T_y = (T_{x+y} + T_{|x-y|}) / 2).
 __global__ void k_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int m, double scale,
