@@ -332,8 +332,12 @@ def batch96(args):
     hams = [B.dacp_build_hamiltonian(ctx, L, t) for (L, _, t) in sets]
     N = 200
     # b = 16 start columns: with 8, close pairs of levels are left unresolved more often and more
-    # realisations need the retry round (autotuned schedule: 0.63 s per call against 0.76 s)
-    opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3)
+    # realisations need the retry round (autotuned schedule: 0.63 s per call against 0.76 s).
+    # S and P from the anchor panels' moments (moment_mode 2): 0.50 s per call against 0.63 s with
+    # the explicit products
+    opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3, moment_mode=2)
+    if args.moment_mode is not None:
+        opts.moment_mode = args.moment_mode
     if args.kfac:
         opts.kfac = args.kfac
     if args.basis_ratio:
@@ -363,7 +367,8 @@ def batch96(args):
     tuning_s = time.perf_counter() - t0
     B.dacp_central_eigs_batched(ctx, hams, N, tuned)  # the tuned shapes' buffers into the block cache
     options = {"kfac": tuned.kfac, "basis_ratio": tuned.basis_ratio, "window_ratio": tuned.window_ratio,
-               "b": tuned.b, "autotuned": True, "tuning_s": tuning_s, "tuning_sample_call_s": t_sample}
+               "b": tuned.b, "moment_mode": tuned.moment_mode, "autotuned": True, "tuning_s": tuning_s,
+               "tuning_sample_call_s": t_sample}
     if args.batched_only:
         dt, (eigs, errs, n_out, reps, st) = timed(None, tuned)
         options["retried"] = int(sum(r["retries"] > 0 for r in reps))

@@ -340,7 +340,7 @@ typedef struct {
                        /* and P from the anchors' moments (dacp_basis_stored_moments), the  */
                        /* Ritz vectors from V as in 0.  0 (default): the basis is stored  */
                        /* and S = V^T V, P = V^T (H V) are formed.  The batched calls     */
-                       /* ignore this field.                                              */
+                       /* store every basis and take 2 as here, 1 as 0.                   */
   int sectors;         /* 1: when H commutes with the global spin flip                  */
                        /* P = prod_i sigma^x_i (every Pauli string has an even number of */
                        /* Z and Y factors), half the start columns are projected onto   */

@@ -156,6 +156,15 @@ __device__ __forceinline__ void sample_at(const BatchCol &c, ConstInts ks, int &
   }
 }
 
+// Store T_kk into the anchor slot when kk is the next anchor order (the moment projection).
+template <int E>
+__device__ __forceinline__ void anchor_at(const BatchCol &c, ConstInts ka, int &next, int64_t kk, const double (&T)[E],
+                                          uint32_t D) {
+  if (next >= c.n_anchor || ka[next] != kk) return;
+  store_panel<E>(c.A, c.lda, static_cast<int64_t>(next) * c.b, T, D);
+  ++next;
+}
+
 // A recurrence term held per thread: in registers when a thread holds <= 8 elements (g is then
 // never used and may be null), otherwise in a 2^L-double slice of the column's global scratch,
 // read back only by the thread that wrote it (L2 resident).
@@ -205,8 +214,8 @@ __device__ __forceinline__ void evolve_step(double (&v)[E], double *lds, const d
 }
 
 template <int E>
-__device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable flips, ConstInts ks, unsigned char *smem,
-                                           double *red) {
+__device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable flips, ConstInts ks, ConstInts ka,
+                                           unsigned char *smem, double *red) {
   const uint32_t D = 1u << c.L;
   double *lds64 = reinterpret_cast<double *>(smem);
   float *lds32 = reinterpret_cast<float *>(smem);
@@ -303,7 +312,8 @@ __device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable fli
 
   // ---- evolution: A = T_(k-1), v = T_k
   store_panel<E>(c.V, c.ldv, 0, v, D);
-  int next = 0;
+  int next = 0, next_a = 0;
+  anchor_at<E>(c, ka, next_a, 0, v, D);
   if (active) {
 #pragma unroll
     for (int i = 0; i < E; ++i) A.set(i, tid_off(8u) + static_cast<uint32_t>(i * kBT * 8), v[i]);
@@ -312,11 +322,14 @@ __device__ __forceinline__ void run_column(const BatchCol &c, ConstFlipTable fli
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] *= c.inv_e;
   sample_at<E>(c, ks, next, 1, v, D, red);
-  const int64_t kmax = c.n_samples > 0 ? ks[c.n_samples - 1] : 1;
+  anchor_at<E>(c, ka, next_a, 1, v, D);
+  int64_t kmax = c.n_samples > 0 ? ks[c.n_samples - 1] : 1;
+  if (c.n_anchor > 0 && ka[c.n_anchor - 1] > kmax) kmax = ka[c.n_anchor - 1];
   const double two_inv_e = 2.0 * c.inv_e;
   for (int64_t k = 1; k < kmax; ++k) {
     evolve_step<E>(v, lds64, c.d64, flips, c.nplain, c.nflip, D, A, two_inv_e);
     sample_at<E>(c, ks, next, k + 1, v, D, red);
+    anchor_at<E>(c, ka, next_a, k + 1, v, D);
   }
 }
 
@@ -334,8 +347,11 @@ __global__ __launch_bounds__(kBT) void k_batch_chebyshev(const BatchCol *cols_g)
   c.ks = cc->ks;
   c.bound_flag = cc->bound_flag;
   c.scratch = cc->scratch;
+  c.A = cc->A;
+  c.ka = cc->ka;
   c.ld_psi = cc->ld_psi;
   c.ldv = cc->ldv;
+  c.lda = cc->lda;
   c.f_alpha = cc->f_alpha;
   c.f_beta = cc->f_beta;
   c.f_gamma = cc->f_gamma;
@@ -349,14 +365,16 @@ __global__ __launch_bounds__(kBT) void k_batch_chebyshev(const BatchCol *cols_g)
   c.n32 = cc->n32;
   c.n_samples = cc->n_samples;
   c.b = cc->b;
+  c.n_anchor = cc->n_anchor;
   const ConstFlipTable flips = (ConstFlipTable)c.flips;
   const ConstInts ks = (ConstInts)c.ks;
+  const ConstInts ka = (ConstInts)c.ka;
   switch (c.L) {  // elements per thread: 2^L / 1024, at least 1
-    case 14: run_column<16>(c, flips, ks, smem_raw, red); break;
-    case 13: run_column<8>(c, flips, ks, smem_raw, red); break;
-    case 12: run_column<4>(c, flips, ks, smem_raw, red); break;
-    case 11: run_column<2>(c, flips, ks, smem_raw, red); break;
-    default: run_column<1>(c, flips, ks, smem_raw, red); break;
+    case 14: run_column<16>(c, flips, ks, ka, smem_raw, red); break;
+    case 13: run_column<8>(c, flips, ks, ka, smem_raw, red); break;
+    case 12: run_column<4>(c, flips, ks, ka, smem_raw, red); break;
+    case 11: run_column<2>(c, flips, ks, ka, smem_raw, red); break;
+    default: run_column<1>(c, flips, ks, ka, smem_raw, red); break;
   }
 }
 

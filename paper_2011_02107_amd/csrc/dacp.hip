@@ -1205,6 +1205,148 @@ dacp_status moment_ritz_vectors(dacp_ctx ctx, dacp_ham h, const dacp_basis_param
 // times smaller than the moments, and differences of neighbouring mu would lose that factor of the
 // recurrence's rounding.  The Gram products cost 2 D (14 b) m flops against 2 D m^2 for V^T V and
 // V^T (H V).
+// Anchor orders of the moment projection on the uniform grid whose last sample is k_n: 0, 1, 2 and
+// k_n - 2 .. k_n + 1, ascending and distinct.
+std::vector<int64_t> anchor_orders(int64_t kn) {
+  std::set<int64_t> a;
+  for (int64_t k : {int64_t(0), int64_t(1), int64_t(2), kn - 2, kn - 1, kn, kn + 1})
+    if (k >= 0) a.insert(k);
+  return std::vector<int64_t>(a.begin(), a.end());
+}
+
+// S and P (device m x m, row stride ld) of the panels of orders `orders` stored in V (device D x m,
+// row stride ldv) from the anchors: abuf (device D x 2 na b, row stride 2 na b) holds T_A psi of
+// anchor i = 0 .. na-1 in columns [i b, i b + b); its right half receives their images under H.
+// gram_ms (may be null) gets the wall time of the whole step.
+dacp_status anchor_projection(dacp_ctx ctx, dacp_ham h, const std::vector<int64_t> &orders,
+                              const std::vector<int64_t> &anchors, double *abuf, const double *V, int64_t ldv, int b,
+                              double e_bound, double *S, double *P, int64_t ld, double *gram_ms) {
+  const int64_t D = h->D;
+  hipStream_t s = ctx->stream;
+  const int npan = static_cast<int>(orders.size());
+  const int m = b * npan;
+  const int na = static_cast<int>(anchors.size());
+  const int ma = na * b;
+  const int64_t kn = orders.back();
+  // images of the anchors under H, beside them
+  const double tg0 = now_ms();
+  for (int c0 = 0; c0 < ma; c0 += 64)
+    DACP_TRY(step<double>(ctx, h, std::min(64, ma - c0), abuf + c0, 2 * ma, abuf + ma + c0, 2 * ma, 1.0));
+  // Gram of the anchors and their images with the panels, (2 na b) x m: block (i, q) =
+  // (T_{anchors[i]} psi)^T (T_{orders[q]} psi), block (na + i, q) = (H T_{anchors[i]} psi)^T (T_{orders[q]} psi)
+  const int mg = 2 * ma;
+  std::vector<double> gm(static_cast<size_t>(mg) * m);
+  {
+    DevBuf gd, work;
+    DACP_HIP(ctx, gd.alloc(gm.size() * sizeof(double)));
+    const int64_t tiles = static_cast<int64_t>((mg + 127) / 128) * ((m + 127) / 128);
+    const int sp = static_cast<int>(std::min<int64_t>(
+        {16, std::max<int64_t>(1, (4 * ctx->num_cus + tiles - 1) / tiles), std::max<int64_t>(1, D / 4096)}));
+    if (sp > 1) {
+      DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * mg * m * sizeof(double)));
+      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, mg, m, D, 1.0, abuf, mg, V, ldv, 0.0, gd.as<double>(), m, 0, sp,
+                                              work.as<double>(), s));
+    } else {
+      DACP_HIP(ctx, dacp::launch_dgemm(1, 0, mg, m, D, 1.0, abuf, mg, V, ldv, 0.0, gd.as<double>(), m, 0,
+                                       s));
+    }
+    DACP_TRY(to_host(ctx, gm.data(), gd.p, gm.size() * sizeof(double)));
+    DACP_HIP(ctx, hipStreamSynchronize(s));
+  }
+  // the orders S and P read: x + y and |x - y| over the panel orders, one slot each
+  int nslot = 0;
+  const std::vector<int> slot_of = moment_slots(orders, nslot);
+  // Which pair gives which moment: sweep the (anchor, panel) pairs until nothing new follows; a
+  // moment is derived once, from the first pair that reaches it.  mu and nu share the rules.
+  struct Rule {
+    int ai, q;
+    int64_t other;  // the moment subtracted (-1: the block is the moment itself)
+  };
+  std::unordered_map<int64_t, int> rule_of;  // order -> index into rules
+  std::vector<std::pair<int64_t, Rule>> rules;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int ai = 0; ai < na; ++ai)
+      for (int q = 0; q < npan; ++q) {
+        const int64_t sum = anchors[ai] + orders[q];
+        const int64_t dif = anchors[ai] >= orders[q] ? anchors[ai] - orders[q] : orders[q] - anchors[ai];
+        const bool hs = rule_of.count(sum) > 0, hd = rule_of.count(dif) > 0;
+        int64_t k = -1, other = -1;
+        if (sum == dif) {
+          if (!hs) k = sum;
+        } else if (hd && !hs) {
+          k = sum;
+          other = dif;
+        } else if (hs && !hd) {
+          k = dif;
+          other = sum;
+        }
+        if (k < 0) continue;
+        rule_of[k] = static_cast<int>(rules.size());
+        rules.push_back({k, Rule{ai, q, other}});
+        changed = true;
+      }
+  }
+  // the moments the assembly reads, and the ones they are derived from
+  std::vector<char> used(rules.size(), 0);
+  for (int64_t k = 0; k <= 2 * kn; ++k) {
+    if (slot_of[k] < 0) continue;
+    auto it = rule_of.find(k);
+    if (it == rule_of.end())
+      return set_err(ctx, DACP_E_INVALID, "basis_stored_moments: moment " + std::to_string(k) + " not reachable");
+    for (int r = it->second; r >= 0 && !used[r];) {
+      used[r] = 1;
+      const int64_t o = rules[r].second.other;
+      r = o < 0 ? -1 : rule_of.at(o);
+    }
+  }
+  // evaluate in the order found (a rule's other moment was derived before it); mu from the anchor
+  // rows, nu from the image rows scaled by 1 / e_bound
+  const size_t bb2 = static_cast<size_t>(b) * b;
+  std::vector<double> muh(static_cast<size_t>(nslot) * bb2), nuh(muh.size());
+  for (int part = 0; part < 2; ++part) {
+    std::unordered_map<int64_t, std::vector<double>> mom;
+    std::vector<double> &out = part == 0 ? muh : nuh;
+    const double sc = part == 0 ? 1.0 : 1.0 / e_bound;
+    for (size_t r = 0; r < rules.size(); ++r) {
+      if (!used[r]) continue;
+      const int64_t k = rules[r].first;
+      const Rule &ru = rules[r].second;
+      std::vector<double> mk(bb2);
+      const std::vector<double> *ot = ru.other < 0 ? nullptr : &mom.at(ru.other);
+      const size_t row0 = static_cast<size_t>(part * na + ru.ai) * b;
+      for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+          const double gij = sc * gm[(row0 + i) * m + static_cast<size_t>(ru.q) * b + j];
+          mk[static_cast<size_t>(i) * b + j] = ot ? 2.0 * gij - (*ot)[static_cast<size_t>(i) * b + j] : gij;
+        }
+      if (k <= 2 * kn && slot_of[k] >= 0)
+        std::copy(mk.begin(), mk.end(), out.begin() + static_cast<size_t>(slot_of[k]) * bb2);
+      mom.emplace(k, std::move(mk));
+    }
+  }
+  for (size_t i = 0; i < muh.size(); ++i)
+    if (!std::isfinite(muh[i]) || !std::isfinite(nuh[i]))
+      return set_err(ctx, DACP_E_NUMERIC, "basis_stored_moments: non-finite moment");
+  DevBuf mu, nu, didx, dord;
+  DACP_HIP(ctx, mu.alloc(muh.size() * sizeof(double)));
+  DACP_HIP(ctx, nu.alloc(nuh.size() * sizeof(double)));
+  DACP_HIP(ctx, didx.alloc(slot_of.size() * sizeof(int)));
+  DACP_HIP(ctx, dord.alloc(orders.size() * sizeof(int64_t)));
+  DACP_TRY(to_device(ctx, mu.p, muh.data(), muh.size() * sizeof(double)));
+  DACP_TRY(to_device(ctx, nu.p, nuh.data(), nuh.size() * sizeof(double)));
+  DACP_TRY(to_device(ctx, didx.p, slot_of.data(), slot_of.size() * sizeof(int)));
+  DACP_TRY(to_device(ctx, dord.p, orders.data(), orders.size() * sizeof(int64_t)));
+  DACP_HIP(ctx, dacp::launch_gram_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, 1.0, S, ld, s));
+  DACP_HIP(ctx, dacp::launch_gram_assemble(nu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, e_bound, P,
+                                           ld, s));
+  DACP_HIP(ctx, dacp::launch_symmetrize(S, m, ld, s));
+  DACP_HIP(ctx, dacp::launch_symmetrize(P, m, ld, s));
+  DACP_HIP(ctx, hipStreamSynchronize(s));
+  if (gram_ms) *gram_ms = now_ms() - tg0;
+  return DACP_OK;
+}
+
 dacp_status run_stored_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e,
                                     double *V, int64_t ldv, double *S, double *P, int64_t ld, int *m_out,
                                     EvolStats *stats, double *gram_ms) {
@@ -1222,14 +1364,9 @@ dacp_status run_stored_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_p
   std::map<int64_t, int> panel_of;  // panel order -> panel index
   for (int q = 0; q < npan; ++q) panel_of[mp.orders[q]] = q;
   const int64_t kn = mp.orders.back();
+  const std::vector<int64_t> anchors = anchor_orders(kn);
   std::map<int64_t, int> anchor_of;  // anchor order -> anchor slot
-  for (int64_t k : {int64_t(0), int64_t(1), int64_t(2), kn - 2, kn - 1, kn, kn + 1})
-    if (k >= 0) anchor_of.emplace(k, 0);
-  std::vector<int64_t> anchors;
-  for (auto &kv : anchor_of) {
-    kv.second = static_cast<int>(anchors.size());
-    anchors.push_back(kv.first);
-  }
+  for (size_t i = 0; i < anchors.size(); ++i) anchor_of[anchors[i]] = static_cast<int>(i);
   const int na = static_cast<int>(anchors.size());
   const int ma = na * b;  // anchor block width
   const int g = (p->group > 0 && p->group < b) ? p->group : recurrence_group(ctx, h, b);
@@ -1282,124 +1419,7 @@ dacp_status run_stored_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_p
     if (nk[i] > n0[i % b] * (1.0 + 2e-6))
       return set_err(ctx, DACP_E_BOUNDS, "basis_stored_moments: |T_k(H/e_bound)| grew above 1; e_bound is below ||H||");
   }
-  // images of the anchors under H, beside them
-  const double tg0 = now_ms();
-  for (int c0 = 0; c0 < ma; c0 += 64)
-    DACP_TRY(step<double>(ctx, h, std::min(64, ma - c0), abuf.as<double>() + c0, 2 * ma, abuf.as<double>() + ma + c0,
-                          2 * ma, 1.0));
-  // Gram of the anchors and their images with the panels, (2 na b) x m: block (i, q) =
-  // (T_{anchors[i]} psi)^T (T_{orders[q]} psi), block (na + i, q) = (H T_{anchors[i]} psi)^T (T_{orders[q]} psi)
-  const int mg = 2 * ma;
-  std::vector<double> gm(static_cast<size_t>(mg) * m);
-  {
-    DevBuf gd, work;
-    DACP_HIP(ctx, gd.alloc(gm.size() * sizeof(double)));
-    const int64_t tiles = static_cast<int64_t>((mg + 127) / 128) * ((m + 127) / 128);
-    const int sp = static_cast<int>(std::min<int64_t>(
-        {16, std::max<int64_t>(1, (4 * ctx->num_cus + tiles - 1) / tiles), std::max<int64_t>(1, D / 4096)}));
-    if (sp > 1) {
-      DACP_HIP(ctx, work.alloc(static_cast<size_t>(sp) * mg * m * sizeof(double)));
-      DACP_HIP(ctx, dacp::launch_dgemm_splitk(1, 0, mg, m, D, 1.0, abuf.as<double>(), mg, V, ldv, 0.0, gd.as<double>(),
-                                              m, 0, sp, work.as<double>(), s));
-    } else {
-      DACP_HIP(ctx, dacp::launch_dgemm(1, 0, mg, m, D, 1.0, abuf.as<double>(), mg, V, ldv, 0.0, gd.as<double>(), m, 0,
-                                       s));
-    }
-    DACP_TRY(to_host(ctx, gm.data(), gd.p, gm.size() * sizeof(double)));
-    DACP_HIP(ctx, hipStreamSynchronize(s));
-  }
-  abuf.release();
-  // the orders S and P read: x + y and |x - y| over the panel orders, one slot each
-  int nslot = 0;
-  const std::vector<int> slot_of = moment_slots(mp.orders, nslot);
-  // Which pair gives which moment: sweep the (anchor, panel) pairs until nothing new follows; a
-  // moment is derived once, from the first pair that reaches it.  mu and nu share the rules.
-  struct Rule {
-    int ai, q;
-    int64_t other;  // the moment subtracted (-1: the block is the moment itself)
-  };
-  std::unordered_map<int64_t, int> rule_of;  // order -> index into rules
-  std::vector<std::pair<int64_t, Rule>> rules;
-  for (bool changed = true; changed;) {
-    changed = false;
-    for (int ai = 0; ai < na; ++ai)
-      for (int q = 0; q < npan; ++q) {
-        const int64_t sum = anchors[ai] + mp.orders[q];
-        const int64_t dif = anchors[ai] >= mp.orders[q] ? anchors[ai] - mp.orders[q] : mp.orders[q] - anchors[ai];
-        const bool hs = rule_of.count(sum) > 0, hd = rule_of.count(dif) > 0;
-        int64_t k = -1, other = -1;
-        if (sum == dif) {
-          if (!hs) k = sum;
-        } else if (hd && !hs) {
-          k = sum;
-          other = dif;
-        } else if (hs && !hd) {
-          k = dif;
-          other = sum;
-        }
-        if (k < 0) continue;
-        rule_of[k] = static_cast<int>(rules.size());
-        rules.push_back({k, Rule{ai, q, other}});
-        changed = true;
-      }
-  }
-  // the moments the assembly reads, and the ones they are derived from
-  std::vector<char> used(rules.size(), 0);
-  for (int64_t k = 0; k <= 2 * kn; ++k) {
-    if (slot_of[k] < 0) continue;
-    auto it = rule_of.find(k);
-    if (it == rule_of.end())
-      return set_err(ctx, DACP_E_INVALID, "basis_stored_moments: moment " + std::to_string(k) + " not reachable");
-    for (int r = it->second; r >= 0 && !used[r];) {
-      used[r] = 1;
-      const int64_t o = rules[r].second.other;
-      r = o < 0 ? -1 : rule_of.at(o);
-    }
-  }
-  // evaluate in the order found (a rule's other moment was derived before it); mu from the anchor
-  // rows, nu from the image rows scaled by 1 / e_bound
-  const size_t bb2 = static_cast<size_t>(b) * b;
-  std::vector<double> muh(static_cast<size_t>(nslot) * bb2), nuh(muh.size());
-  for (int part = 0; part < 2; ++part) {
-    std::unordered_map<int64_t, std::vector<double>> mom;
-    std::vector<double> &out = part == 0 ? muh : nuh;
-    const double sc = part == 0 ? 1.0 : 1.0 / p->e_bound;
-    for (size_t r = 0; r < rules.size(); ++r) {
-      if (!used[r]) continue;
-      const int64_t k = rules[r].first;
-      const Rule &ru = rules[r].second;
-      std::vector<double> mk(bb2);
-      const std::vector<double> *ot = ru.other < 0 ? nullptr : &mom.at(ru.other);
-      const size_t row0 = static_cast<size_t>(part * na + ru.ai) * b;
-      for (int i = 0; i < b; ++i)
-        for (int j = 0; j < b; ++j) {
-          const double gij = sc * gm[(row0 + i) * m + static_cast<size_t>(ru.q) * b + j];
-          mk[static_cast<size_t>(i) * b + j] = ot ? 2.0 * gij - (*ot)[static_cast<size_t>(i) * b + j] : gij;
-        }
-      if (k <= 2 * kn && slot_of[k] >= 0)
-        std::copy(mk.begin(), mk.end(), out.begin() + static_cast<size_t>(slot_of[k]) * bb2);
-      mom.emplace(k, std::move(mk));
-    }
-  }
-  for (size_t i = 0; i < muh.size(); ++i)
-    if (!std::isfinite(muh[i]) || !std::isfinite(nuh[i]))
-      return set_err(ctx, DACP_E_NUMERIC, "basis_stored_moments: non-finite moment");
-  DevBuf mu, nu, didx, dord;
-  DACP_HIP(ctx, mu.alloc(muh.size() * sizeof(double)));
-  DACP_HIP(ctx, nu.alloc(nuh.size() * sizeof(double)));
-  DACP_HIP(ctx, didx.alloc(slot_of.size() * sizeof(int)));
-  DACP_HIP(ctx, dord.alloc(mp.orders.size() * sizeof(int64_t)));
-  DACP_TRY(to_device(ctx, mu.p, muh.data(), muh.size() * sizeof(double)));
-  DACP_TRY(to_device(ctx, nu.p, nuh.data(), nuh.size() * sizeof(double)));
-  DACP_TRY(to_device(ctx, didx.p, slot_of.data(), slot_of.size() * sizeof(int)));
-  DACP_TRY(to_device(ctx, dord.p, mp.orders.data(), mp.orders.size() * sizeof(int64_t)));
-  DACP_HIP(ctx, dacp::launch_gram_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, 1.0, S, ld, s));
-  DACP_HIP(ctx, dacp::launch_gram_assemble(nu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, p->e_bound, P,
-                                           ld, s));
-  DACP_HIP(ctx, dacp::launch_symmetrize(S, m, ld, s));
-  DACP_HIP(ctx, dacp::launch_symmetrize(P, m, ld, s));
-  DACP_HIP(ctx, hipStreamSynchronize(s));
-  if (gram_ms) *gram_ms = now_ms() - tg0;
+  DACP_TRY(anchor_projection(ctx, h, mp.orders, anchors, abuf.as<double>(), V, ldv, b, p->e_bound, S, P, ld, gram_ms));
   if (m_out) *m_out = m;
   if (stats) {
     stats->steps = kn + 1;
@@ -1409,7 +1429,6 @@ dacp_status run_stored_moment_basis(dacp_ctx ctx, dacp_ham h, const dacp_basis_p
   }
   return DACP_OK;
 }
-
 
 dacp_status run_project(dacp_ctx ctx, dacp_ham h, int m, const double *V, int64_t ldv, double *S, double *P,
                         int64_t ld) {
@@ -2886,6 +2905,7 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
   dacp_opts o;
   if (opts_in) o = *opts_in;
   else dacp_default_opts(&o);
+  if (o.moment_mode < 0 || o.moment_mode > 2) return set_err(ctx, DACP_E_INVALID, "batched: moment_mode is 0, 1 or 2");
   const double t_start = now_ms();
   const double window_ratio = o.window_ratio > 0.0 ? o.window_ratio : 2.2;
   std::vector<dacp_report> rep(count);
@@ -2931,7 +2951,10 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
   const double t_setup = now_ms();
 
   // start blocks, bases and the column table of the persistent launch
-  std::vector<DevBuf> psi(count), vb(count), ksd(count), scr(count);
+  std::vector<DevBuf> psi(count), vb(count), ksd(count), scr(count), ab(count), kad(count);
+  // moment projection (moment_mode 2): panel orders on the uniform grid and the anchor orders
+  const bool anchored = o.moment_mode == 2;
+  std::vector<std::vector<int64_t>> orders_of(count), anchors_of(count);
   DevBuf flags;
   DACP_HIP(ctx, flags.alloc(sizeof(int) * count));
   DACP_HIP(ctx, hipMemsetAsync(flags.p, 0, sizeof(int) * count, ctx->stream));
@@ -2951,7 +2974,19 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
     if (h->L == 14) DACP_HIP(ctx, scr[r].alloc(static_cast<size_t>(2 * D) * pl.b * sizeof(double)));
     DACP_TRY(split_order(ctx, h, h->L));  // every flip in one list, sign-free flips first
     const auto &so = h->split[h->L];
-    const std::vector<int64_t> ks64 = sample_orders(pl.a_r, pl.n);
+    std::vector<int64_t> ks64;
+    if (anchored) {
+      const MomentPlan mp = moment_plan(pl.a_r, pl.n);
+      for (int j = 1; j <= pl.n; ++j) ks64.push_back(mp.orders[2 * j]);
+      orders_of[r] = mp.orders;
+      anchors_of[r] = anchor_orders(mp.orders.back());
+      const std::vector<int> ka(anchors_of[r].begin(), anchors_of[r].end());
+      DACP_HIP(ctx, kad[r].alloc(sizeof(int) * ka.size()));
+      DACP_TRY(to_device(ctx, kad[r].p, ka.data(), sizeof(int) * ka.size()));
+      DACP_HIP(ctx, ab[r].alloc(static_cast<size_t>(D) * 2 * ka.size() * pl.b * sizeof(double)));
+    } else {
+      ks64 = sample_orders(pl.a_r, pl.n);
+    }
     std::vector<int> ks(ks64.begin(), ks64.end());
     DACP_HIP(ctx, ksd[r].alloc(sizeof(int) * ks.size()));
     DACP_TRY(to_device(ctx, ksd[r].p, ks.data(), sizeof(int) * ks.size()));
@@ -2975,6 +3010,12 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
       c.ldv = pl.m;
       c.ks = ksd[r].as<int>();
       c.n_samples = pl.n;
+      if (anchored) {
+        c.n_anchor = static_cast<int>(anchors_of[r].size());
+        c.lda = 2 * c.n_anchor * pl.b;
+        c.A = ab[r].as<double>() + j;
+        c.ka = kad[r].as<int>();
+      }
       c.bound_flag = flags.as<int>() + r;
       c.f_alpha = 2.0 / (e_0 * rho);
       c.f_beta = -2.0 * e_c / (e_0 * rho);
@@ -3053,9 +3094,26 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
       for (int r = w; r < count; r += nw) {
         if (redo[r]) continue;
         const Plan &pl = plans[r];
-        wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
-                              eigs_out + static_cast<int64_t>(r) * N,
-                              err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
+        double *eo = eigs_out + static_cast<int64_t>(r) * N;
+        double *ee = err_out ? err_out + static_cast<int64_t>(r) * N : nullptr;
+        if (anchored) {
+          const double t0 = now_ms();
+          DevBuf sb, pb;
+          hipError_t e = sb.alloc(static_cast<size_t>(pl.m) * pl.m * sizeof(double));
+          if (e == hipSuccess) e = pb.alloc(static_cast<size_t>(pl.m) * pl.m * sizeof(double));
+          wst[r] = e != hipSuccess ? hip_err(wc, e, "batched finish: allocation")
+                                   : anchor_projection(wc, hams[r], orders_of[r], anchors_of[r], ab[r].as<double>(),
+                                                       vb[r].as<double>(), pl.m, pl.b, e_bs[r], sb.as<double>(),
+                                                       pb.as<double>(), pl.m, nullptr);
+          ab[r].release();
+          rep[r].t_project_ms = now_ms() - t0;
+          if (wst[r] == DACP_OK)
+            wst[r] = finish_projected(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m,
+                                      sb, pb, rep[r], eo, ee, acc[r], nullptr, nullptr, 0);
+        } else {
+          wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
+                                eo, ee, acc[r]);
+        }
         if (wst[r]) werr[r] = wc->err;
         vb[r].release();
       }
@@ -3092,7 +3150,11 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
         fail(r, hip_err(wc, e, "batched finish: allocation"));
         continue;
       }
-      dacp_status st = run_project(wc, hams[r], m, vb[r].as<double>(), m, f.sb.as<double>(), f.pb.as<double>(), m);
+      dacp_status st =
+          anchored ? anchor_projection(wc, hams[r], orders_of[r], anchors_of[r], ab[r].as<double>(), vb[r].as<double>(),
+                                       m, plans[r].b, e_bs[r], f.sb.as<double>(), f.pb.as<double>(), m, nullptr)
+                   : run_project(wc, hams[r], m, vb[r].as<double>(), m, f.sb.as<double>(), f.pb.as<double>(), m);
+      ab[r].release();
       if (st == DACP_OK) {
         e = dacp::launch_copy_cols(f.sb.as<double>(), m, f.awork.as<double>(), m, m, m, wc->stream);
         if (e != hipSuccess) st = hip_err(wc, e, "batched finish: copy");

@@ -120,11 +120,13 @@ struct BatchCol {
   const int *ks;           // sample orders k_1 < ... < k_n (device)
   int *bound_flag;         // set to 1 when |T_k(G) psi_E| > 1 is seen (bound below ||H||)
   double *scratch;         // 2 x 2^L doubles owned by this column (older recurrence terms at L = 14)
-  int64_t ld_psi, ldv;
+  double *A;               // anchors (moment projection) shifted to this column: anchor i at A[s * lda + i * b]
+  const int *ka;           // anchor orders, ascending (device; n_anchor of them, 0 = none)
+  int64_t ld_psi, ldv, lda;
   double f_alpha, f_beta, f_gamma;  // damped filter step coefficients
   double f_first_a, f_first_b;      // first order: T^_1 = a H (H psi) + b psi
   double inv_e;                     // 1 / E_b
-  int L, nflip, nplain, K, n32, n_samples, b;  // flips[0, nplain) have z-mask 0
+  int L, nflip, nplain, K, n32, n_samples, b, n_anchor;  // flips[0, nplain) have z-mask 0
 };
 hipError_t launch_batch_chebyshev(const BatchCol *cols, int ncols, int max_L, hipStream_t s);
 

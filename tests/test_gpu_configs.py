@@ -119,14 +119,16 @@ def _fixtures():
     return fx
 
 
-def test_batch96_every_L12_L13_realisation_against_dense_fixtures(ctx):
-    """The benchmark's batched call (96 realisations, FP32 filter + FP64 tail, b = 16, N = 200): all
-    reach N, and every realisation with a dense-oracle fixture (all 64 at L = 12 and 13, three at
-    L = 14) matches it value by value, its estimates bounding the true errors."""
+@pytest.mark.parametrize("moment_mode", [0, 2], ids=["explicit_products", "moment_projection"])
+def test_batch96_every_L12_L13_realisation_against_dense_fixtures(ctx, moment_mode):
+    """The benchmark's batched call (96 realisations, FP32 filter + FP64 tail, b = 16, N = 200), with
+    S and P as explicit products and from the anchor panels' moments: all reach N, and every
+    realisation with a dense-oracle fixture (all 64 at L = 12 and 13, three at L = 14) matches it
+    value by value, its estimates bounding the true errors."""
     sets, hams = _batch96(ctx)
     fx = _fixtures()
     N = 200
-    opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3)
+    opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3, moment_mode=moment_mode)
     eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
     assert st == 0 and np.all(n_out == N)
     assert sum(1 for i in fx if sets[i][0] in (12, 13)) == 64

@@ -878,11 +878,13 @@ def test_fp32_tail_error_table(ctx):
 # ------------------------------------------------------------------ batched realisations
 
 
+@pytest.mark.parametrize("moment_mode", [0, 2], ids=["explicit_products", "moment_projection"])
 @pytest.mark.parametrize("batch_eig", [1, 2], ids=["eigensolver_auto", "batched_eigensolver"])
-def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx, batch_eig):
+def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx, batch_eig, moment_mode):
     """Realisations of different L in one persistent launch, each against its dense oracle; with
     the default eigensolver choice (five realisations: the per-problem solver) and with the
-    batched eigensolver forced."""
+    batched eigensolver forced; S and P as explicit products and from the anchor panels' moments
+    (the kernel then samples the uniform grid and stores the anchors)."""
     N = 40
     specs = [(8, 1), (10, 2), (9, 3), (10, 4), (8, 5)]
     hams, refs = [], []
@@ -891,7 +893,7 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx, batch_eig):
         refs.append(central.central_eigenvalues(L, terms, N))
         hams.append(B.dacp_build_hamiltonian(ctx, L, terms))
     for precision in (B.DACP_F64, B.DACP_F32):
-        opts = B.default_opts(b=8, precision=precision, fp64_tail_frac=0.3)
+        opts = B.default_opts(b=8, precision=precision, fp64_tail_frac=0.3, moment_mode=moment_mode)
         try:
             ctx.tune("batch_eig", batch_eig)
             eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
