@@ -338,6 +338,8 @@ def batch96(args):
     opts = B.default_opts(b=16, precision=B.DACP_F32, fp64_tail_frac=0.3, moment_mode=2)
     if args.moment_mode is not None:
         opts.moment_mode = args.moment_mode
+    if args.block:
+        opts.b = args.block
     if args.kfac:
         opts.kfac = args.kfac
     if args.basis_ratio:
