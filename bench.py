@@ -496,8 +496,9 @@ def stage_sweep_L15(args):
 def scaling_paper_models(args):
     """Time against system size for the paper's two models with its distributions (Sec. III: the
     random transverse-field chain and the all-to-all spin-glass shard, J ~ U[-10/sqrt(L), 10/sqrt(L)],
-    Gamma ~ U[0, 1]), N = 5000 central values, L = 15 .. 18, tuned options with the evolution
-    autotuned per shape (untimed, as in the headline).  alpha is the
+    Gamma ~ U[0, 1]), N = 5000 central values, L = 15 .. 18, tuned options (S and P as explicit
+    products unless --moment-mode says otherwise) with the evolution autotuned per shape (untimed,
+    as in the headline).  alpha is the
     least-squares slope of log T against L (T = T0 exp(alpha L), the paper's scaling constant),
     for the filter + evolution time and for the whole call."""
     import numpy as np
@@ -511,7 +512,8 @@ def scaling_paper_models(args):
     small = B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8))
     B.dacp_central_eigs(ctx, small, 20, B.default_opts(b=4), raise_on_window=False)  # load the kernels
     small.close()
-    out = {"metric": "time vs L, N=5000, paper models (tuned options)", "N": N, "models": {}}
+    out = {"metric": "time vs L, N=5000, paper models (tuned options)", "N": N,
+           "moment_mode": args.moment_mode or 0, "models": {}}
     for name, build in (("ising", inputs.paper_tfim), ("glass", inputs.paper_sgs)):
         rows = []
         for L in Ls:
@@ -522,7 +524,7 @@ def scaling_paper_models(args):
             # tuned options with the 2.2 N window (wider first windows do not help here: at L = 15,
             # N = 5000 is 15 % of the spectrum and a 2.6 N window, retried at 3.9 N, falls short)
             o = B.default_opts(b=64, kfac=12.0, window_ratio=2.2, basis_ratio=1.2, precision=B.DACP_F32,
-                               fp64_tail_frac=0.3)
+                               fp64_tail_frac=0.3, moment_mode=args.moment_mode or 0)
             eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, o, raise_on_window=False)
             rows.append({"L": L, "status": st, "accepted": len(eigs), "retries": rep["retries"], "K": rep["K"], "m": rep["m"],
                          "evol_steps": rep["evol_steps"], "t_filter_ms": rep["t_filter_ms"],

@@ -112,6 +112,10 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *                 realisations (default; smaller calls, such as a retry round, solve each problem
  *                 on its thread's stream), 2 = batched launches always, 0 = one solver per
  *                 problem always
+ *   "moment_explicit" dacp_central_eigs with moment_mode 2: 1 = when the certified core falls
+ *                 short of N, S and P of the same stored basis are formed explicitly and solved
+ *                 again before the window is widened (default); 2 = always after the moment
+ *                 solve; 0 = never
  *   "beig_pipe"   batched eigensolver: 1 = on unreduced blocks of 48 rows or more, the QR sweeps
  *                 of a batch take their shifts at its start and are chased in lockstep, one lane
  *                 per sweep (default); 0 = one sweep after another
@@ -125,7 +129,8 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *                 n >= value (default 3500, at least 256; 0 = never)
  *   "dc"          dense eigensolver: eigenvectors by divide and conquer for n >= value
  *                 (default 96; 0 = always implicit QR with replayed rotations)
- * Results agree for every setting up to the rounding order of each element's sum.
+ * Results agree for every setting up to the rounding order of each element's sum ("moment_explicit":
+ * within the values' certified error estimates, since S and P are formed differently).
  * Returns DACP_E_INVALID for an unknown key or a value out of range. */
 dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value);
 /* Current value of a tuning knob (same keys as dacp_tune); value: host. */
@@ -338,7 +343,9 @@ typedef struct {
                        /* from a second evolution (D x (N + max(64, N/8)) FP64 on device)   */
                        /* for the residual acceptance.  2: the uniform-grid basis stored, S */
                        /* and P from the anchors' moments (dacp_basis_stored_moments), the  */
-                       /* Ritz vectors from V as in 0.  0 (default): the basis is stored  */
+                       /* Ritz vectors from V as in 0; if the certified core falls short   */
+                       /* of N, S and P of the same basis are then formed explicitly and   */
+                       /* solved again before any retry.  0 (default): the basis is stored */
                        /* and S = V^T V, P = V^T (H V) are formed.  The batched calls     */
                        /* store every basis and take 2 as here, 1 as 0.                   */
   int sectors;         /* 1: when H commutes with the global spin flip                  */

@@ -1826,6 +1826,11 @@ dacp_status dacp_tune(dacp_ctx ctx, const char *key, int value) {
     ctx->batch_eig = value;
     return DACP_OK;
   }
+  if (k == "moment_explicit") {
+    if (value < 0 || value > 2) return set_err(ctx, DACP_E_INVALID, "moment_explicit: 0, 1 or 2");
+    ctx->moment_explicit = value;
+    return DACP_OK;
+  }
   if (k == "beig_pipe") {
     if (value != 0 && value != 1) return set_err(ctx, DACP_E_INVALID, "beig_pipe: 0 or 1");
     ctx->beig_pipe = value;
@@ -1900,6 +1905,7 @@ dacp_status dacp_tune_get(dacp_ctx ctx, const char *key, int *value) {
   else if (k == "project_splitk") *value = ctx->project_splitk;
   else if (k == "blocked") *value = ctx->blocked_min_n;
   else if (k == "batch_eig") *value = ctx->batch_eig;
+  else if (k == "moment_explicit") *value = ctx->moment_explicit;
   else if (k == "beig_pipe") *value = ctx->beig_pipe;
   else if (k == "beig_sweeps") *value = ctx->beig_sweeps;
   else if (k == "batch_workers") *value = ctx->batch_workers;
@@ -2541,6 +2547,21 @@ dacp_status central_eigs(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts *opts_
       st = finish_projected(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, sb, pb, rep, eigs_out, err_out,
                             accepted, nullptr, vecs_out, ldvec);
       if (st) return st;
+      if (ctx->moment_explicit == 2 || (ctx->moment_explicit == 1 && accepted < N)) {
+        // The moments' rounding is not that of a Gram matrix of the stored panels, so a direction
+        // at S's cut-off can be kept that the explicit products would drop, and its Ritz value
+        // may end the core early.  Before widening the window, project the same basis explicitly.
+        vlog("moment projection: core %d of %d; explicit products of the same basis", accepted, N);
+        const int acc_moments = accepted;
+        const double t_proj = rep.t_project_ms, t_gep = rep.t_gep_ms, t_acc = rep.t_accept_ms;
+        st = finish_basis(ctx, h, N, o, a, n_w, tol, norm_est, vbuf.as<double>(), m, rep, eigs_out, err_out, accepted,
+                          nullptr, vecs_out, ldvec);
+        if (st) return st;
+        vlog("explicit products: core %d (moments: %d)", accepted, acc_moments);
+        rep.t_project_ms += t_proj;
+        rep.t_gep_ms += t_gep;
+        rep.t_accept_ms += t_acc;
+      }
     } else {
       st = run_basis(ctx, h, &bp, psi.as<double>(), vbuf.as<double>(), m, &m_got, &es);
       if (st) return st;

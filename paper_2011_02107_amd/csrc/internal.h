@@ -327,6 +327,8 @@ struct dacp_ctx_s {
   int rec_graph = 0;           // evolution: steps per captured graph below 2^19 rows (0 = no graphs)
   int batch_eig = 1;           // batched realisations' eigensolver: 1 = batched launches when the call has more
                                // than kBatchEigMinCount realisations, 2 = always, 0 = never
+  int moment_explicit = 1;     // moment projection (moment_mode 2): explicit S, P of the same basis when the core
+                               // falls short of N (1), always (2), never (0)
   int beig_pipe = 1;           // batched eigensolver: pipelined multishift QR batches on large blocks
   int beig_sweeps = 6;         // batched eigensolver: at most this many QR sweeps per batch (1..8)
   int project_whole = 1;       // projection: P in one GEMM when H V fits beside V (0 = column chunks)

@@ -193,6 +193,23 @@ def test_central_eigs_stored_moments_jw_twin_L16(ctx):
     _check(eigs, errs, ref, norm, N, "JW twin L16 stored moments")
 
 
+@pytest.mark.parametrize("explicit", [0, 2])
+def test_central_eigs_stored_moments_explicit_products_switch(ctx, explicit):
+    """moment_mode 2 with the explicit products of the same stored basis forced after the moment
+    solve (the path taken when the moment solve's core falls short of N) and switched off: both
+    against the dense oracle."""
+    L, N = 12, 200
+    terms = inputs.spin_glass(12, 7)
+    ref, norm = central.central_eigenvalues(L, terms, N)
+    ham = B.dacp_build_hamiltonian(ctx, L, terms)
+    try:
+        ctx.tune("moment_explicit", explicit)
+        eigs, errs, rep, st = B.dacp_central_eigs(ctx, ham, N, B.default_opts(b=8, moment_mode=2))
+    finally:
+        ctx.tune("moment_explicit", 1)
+    _check(eigs, errs, ref, norm, N, f"glass L12 moment_explicit {explicit}")
+
+
 def test_central_eigs_moment_mode_rejects_unknown_value(ctx):
     ham = B.dacp_build_hamiltonian(ctx, 8, inputs.ising_chain(8))
     with pytest.raises(B.DacpError):
