@@ -112,10 +112,11 @@ dacp_status dacp_set_tile(dacp_ctx ctx, int tile_elems);
  *                 realisations (default; smaller calls, such as a retry round, solve each problem
  *                 on its thread's stream), 2 = batched launches always, 0 = one solver per
  *                 problem always
- *   "moment_explicit" dacp_central_eigs with moment_mode 2: 1 = when the certified core falls
- *                 short of N, S and P of the same stored basis are formed explicitly and solved
- *                 again before the window is widened (default); 2 = always after the moment
- *                 solve; 0 = never
+ *   "moment_explicit" dacp_central_eigs and the batched calls with moment_mode 2: 1 = when the
+ *                 certified core falls short of N, S and P of the same stored basis are formed
+ *                 explicitly and solved again (by the per-problem eigensolver in a batched call)
+ *                 before the window is widened (default); 2 = always after the moment solve;
+ *                 0 = never
  *   "beig_pipe"   batched eigensolver: 1 = on unreduced blocks of 48 rows or more, the QR sweeps
  *                 of a batch take their shifts at its start and are chased in lockstep, one lane
  *                 per sweep (default); 0 = one sweep after another

@@ -3131,6 +3131,10 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
           if (wst[r] == DACP_OK)
             wst[r] = finish_projected(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m,
                                       sb, pb, rep[r], eo, ee, acc[r], nullptr, nullptr, 0);
+          // as in the single call: the explicit products of the same basis before any retry round
+          if (wst[r] == DACP_OK && (ctx->moment_explicit == 2 || (ctx->moment_explicit == 1 && acc[r] < N)))
+            wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m,
+                                  rep[r], eo, ee, acc[r]);
         } else {
           wst[r] = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
                                 eo, ee, acc[r]);
@@ -3247,6 +3251,15 @@ dacp_status central_eigs_batched(dacp_ctx ctx, int count, const dacp_ham *hams, 
           f.uc.release();
           st = accept_stage(wc, hams[r], N, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, f.rank,
                             f.theta, f.bc, rep[r], eigs_out + static_cast<int64_t>(r) * N,
+                            err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
+        }
+        // as in the single call: with the moment projection, the explicit products of the same
+        // basis (solved on this thread's stream) before any retry round
+        if (st == DACP_OK && anchored &&
+            (ctx->moment_explicit == 2 || (ctx->moment_explicit == 1 && acc[r] < N))) {
+          for (DevBuf *b : {&f.sb, &f.pb, &f.awork, &f.zs, &f.uc, &f.ht, &f.yc, &f.bc}) b->release();
+          st = finish_basis(wc, hams[r], N, o, pl.a, pl.n_w, tol[r], norm_est[r], vb[r].as<double>(), pl.m, rep[r],
+                            eigs_out + static_cast<int64_t>(r) * N,
                             err_out ? err_out + static_cast<int64_t>(r) * N : nullptr, acc[r]);
         }
         if (st) fail(r, st);

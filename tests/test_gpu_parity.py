@@ -908,6 +908,31 @@ def test_central_eigs_batched_mixed_L_matches_dense_oracle(ctx, batch_eig, momen
             assert abs(reps[r]["e_bound"] - eb) <= 1e-9 * eb
 
 
+@pytest.mark.parametrize("batch_eig", [0, 2], ids=["per_problem_eigensolver", "batched_eigensolver"])
+def test_central_eigs_batched_moment_projection_explicit_switch(ctx, batch_eig):
+    """Batched calls with the moment projection and the explicit products of each stored basis
+    forced after the moment solve (moment_explicit = 2: the path a realisation takes when its
+    moment-solve core falls short of N), against the dense oracle."""
+    N = 40
+    specs = [(8, 21), (10, 22), (9, 23)]
+    hams, refs = [], []
+    for L, seed in specs:
+        terms = inputs.spin_glass(L, seed)
+        refs.append(central.central_eigenvalues(L, terms, N))
+        hams.append(B.dacp_build_hamiltonian(ctx, L, terms))
+    opts = B.default_opts(b=8, moment_mode=2)
+    try:
+        ctx.tune("batch_eig", batch_eig)
+        ctx.tune("moment_explicit", 2)
+        eigs, errs, n_out, reps, st = B.dacp_central_eigs_batched(ctx, hams, N, opts)
+    finally:
+        ctx.tune("batch_eig", 1)
+        ctx.tune("moment_explicit", 1)
+    assert st == 0 and np.all(n_out == N)
+    for r, (ref, norm) in enumerate(refs):
+        _check_central(eigs[r], ref, norm, N, errs=errs[r])
+
+
 def test_central_eigs_batched_per_problem_eigensolver(ctx):
     """The batched path with the finishing threads' eigen-decompositions solved one by one (knob
     batch_eig = 0) gives the same eigenvalues as with the batched eigensolver forced
