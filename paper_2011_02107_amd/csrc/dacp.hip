@@ -1235,10 +1235,10 @@ dacp_status anchor_projection(dacp_ctx ctx, dacp_ham h, const std::vector<int64_
   // Gram of the anchors and their images with the panels, (2 na b) x m: block (i, q) =
   // (T_{anchors[i]} psi)^T (T_{orders[q]} psi), block (na + i, q) = (H T_{anchors[i]} psi)^T (T_{orders[q]} psi)
   const int mg = 2 * ma;
-  std::vector<double> gm(static_cast<size_t>(mg) * m);
+  DevBuf gd;
+  DACP_HIP(ctx, gd.alloc(static_cast<size_t>(mg) * m * sizeof(double)));
   {
-    DevBuf gd, work;
-    DACP_HIP(ctx, gd.alloc(gm.size() * sizeof(double)));
+    DevBuf work;
     const int64_t tiles = static_cast<int64_t>((mg + 127) / 128) * ((m + 127) / 128);
     const int sp = static_cast<int>(std::min<int64_t>(
         {16, std::max<int64_t>(1, (4 * ctx->num_cus + tiles - 1) / tiles), std::max<int64_t>(1, D / 4096)}));
@@ -1250,8 +1250,6 @@ dacp_status anchor_projection(dacp_ctx ctx, dacp_ham h, const std::vector<int64_
       DACP_HIP(ctx, dacp::launch_dgemm(1, 0, mg, m, D, 1.0, abuf, mg, V, ldv, 0.0, gd.as<double>(), m, 0,
                                        s));
     }
-    DACP_TRY(to_host(ctx, gm.data(), gd.p, gm.size() * sizeof(double)));
-    DACP_HIP(ctx, hipStreamSynchronize(s));
   }
   // the orders S and P read: x + y and |x - y| over the panel orders, one slot each
   int nslot = 0;
@@ -1300,46 +1298,42 @@ dacp_status anchor_projection(dacp_ctx ctx, dacp_ham h, const std::vector<int64_
       r = o < 0 ? -1 : rule_of.at(o);
     }
   }
-  // evaluate in the order found (a rule's other moment was derived before it); mu from the anchor
-  // rows, nu from the image rows scaled by 1 / e_bound
-  const size_t bb2 = static_cast<size_t>(b) * b;
-  std::vector<double> muh(static_cast<size_t>(nslot) * bb2), nuh(muh.size());
-  for (int part = 0; part < 2; ++part) {
-    std::unordered_map<int64_t, std::vector<double>> mom;
-    std::vector<double> &out = part == 0 ? muh : nuh;
-    const double sc = part == 0 ? 1.0 : 1.0 / e_bound;
-    for (size_t r = 0; r < rules.size(); ++r) {
-      if (!used[r]) continue;
-      const int64_t k = rules[r].first;
-      const Rule &ru = rules[r].second;
-      std::vector<double> mk(bb2);
-      const std::vector<double> *ot = ru.other < 0 ? nullptr : &mom.at(ru.other);
-      const size_t row0 = static_cast<size_t>(part * na + ru.ai) * b;
-      for (int i = 0; i < b; ++i)
-        for (int j = 0; j < b; ++j) {
-          const double gij = sc * gm[(row0 + i) * m + static_cast<size_t>(ru.q) * b + j];
-          mk[static_cast<size_t>(i) * b + j] = ot ? 2.0 * gij - (*ot)[static_cast<size_t>(i) * b + j] : gij;
-        }
-      if (k <= 2 * kn && slot_of[k] >= 0)
-        std::copy(mk.begin(), mk.end(), out.begin() + static_cast<size_t>(slot_of[k]) * bb2);
-      mom.emplace(k, std::move(mk));
-    }
+  // the used rules in the order found (a rule's other moment comes before it), renumbered, and the
+  // block each order the assembly reads takes
+  std::vector<int> cidx(rules.size(), -1), table;
+  int nc = 0;
+  for (size_t r = 0; r < rules.size(); ++r) {
+    if (!used[r]) continue;
+    cidx[r] = nc++;
+    const Rule &ru = rules[r].second;
+    table.push_back(ru.ai);
+    table.push_back(ru.q);
+    table.push_back(ru.other < 0 ? -1 : cidx[rule_of.at(ru.other)]);
   }
-  for (size_t i = 0; i < muh.size(); ++i)
-    if (!std::isfinite(muh[i]) || !std::isfinite(nuh[i]))
-      return set_err(ctx, DACP_E_NUMERIC, "basis_stored_moments: non-finite moment");
-  DevBuf mu, nu, didx, dord;
-  DACP_HIP(ctx, mu.alloc(muh.size() * sizeof(double)));
-  DACP_HIP(ctx, nu.alloc(nuh.size() * sizeof(double)));
-  DACP_HIP(ctx, didx.alloc(slot_of.size() * sizeof(int)));
+  std::vector<int> block_of(slot_of.size(), -1);
+  for (size_t k = 0; k < slot_of.size(); ++k)
+    if (slot_of[k] >= 0) block_of[k] = cidx[rule_of.at(static_cast<int64_t>(k))];
+  // the moments on the device: mu from the anchor rows, nu from the image rows scaled by 1 / e_bound
+  const size_t bb2 = static_cast<size_t>(b) * b;
+  DevBuf mom, drules, dblk, dord, dbad;
+  DACP_HIP(ctx, mom.alloc(2 * static_cast<size_t>(nc) * bb2 * sizeof(double)));
+  DACP_HIP(ctx, drules.alloc(table.size() * sizeof(int)));
+  DACP_HIP(ctx, dblk.alloc(block_of.size() * sizeof(int)));
   DACP_HIP(ctx, dord.alloc(orders.size() * sizeof(int64_t)));
-  DACP_TRY(to_device(ctx, mu.p, muh.data(), muh.size() * sizeof(double)));
-  DACP_TRY(to_device(ctx, nu.p, nuh.data(), nuh.size() * sizeof(double)));
-  DACP_TRY(to_device(ctx, didx.p, slot_of.data(), slot_of.size() * sizeof(int)));
+  DACP_HIP(ctx, dbad.alloc(sizeof(int)));
+  DACP_TRY(to_device(ctx, drules.p, table.data(), table.size() * sizeof(int)));
+  DACP_TRY(to_device(ctx, dblk.p, block_of.data(), block_of.size() * sizeof(int)));
   DACP_TRY(to_device(ctx, dord.p, orders.data(), orders.size() * sizeof(int64_t)));
-  DACP_HIP(ctx, dacp::launch_gram_assemble(mu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, 1.0, S, ld, s));
-  DACP_HIP(ctx, dacp::launch_gram_assemble(nu.as<double>(), didx.as<int>(), dord.as<int64_t>(), b, npan, e_bound, P,
-                                           ld, s));
+  const int zero = 0;
+  DACP_TRY(to_device(ctx, dbad.p, &zero, sizeof(int)));
+  DACP_HIP(ctx, dacp::launch_moment_chain(gd.as<double>(), m, b, na, drules.as<int>(), nc, 1.0, 1.0 / e_bound,
+                                          mom.as<double>(), dbad.as<int>(), s));
+  int bad = 0;
+  DACP_TRY(to_host(ctx, &bad, dbad.p, sizeof(int)));
+  if (bad) return set_err(ctx, DACP_E_NUMERIC, "basis_stored_moments: non-finite moment");
+  const double *mu = mom.as<double>(), *nu = mu + static_cast<size_t>(nc) * bb2;
+  DACP_HIP(ctx, dacp::launch_gram_assemble(mu, dblk.as<int>(), dord.as<int64_t>(), b, npan, 1.0, S, ld, s));
+  DACP_HIP(ctx, dacp::launch_gram_assemble(nu, dblk.as<int>(), dord.as<int64_t>(), b, npan, e_bound, P, ld, s));
   DACP_HIP(ctx, dacp::launch_symmetrize(S, m, ld, s));
   DACP_HIP(ctx, dacp::launch_symmetrize(P, m, ld, s));
   DACP_HIP(ctx, hipStreamSynchronize(s));

@@ -203,6 +203,10 @@ hipError_t launch_resid(const double *x, const double *hx, int64_t ld, const dou
 int tall_gram_blocks(int64_t D);
 hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *Y, int64_t ldy, int gy, int64_t D,
                             double *partial, int nblk, double *out, hipStream_t s);
+// The anchors' moments on the device (kernels.hip): M (2 x nrules b x b blocks, mu then nu) from the
+// Gram product G ((2 na b) x m) by the derivation rules (ai, q, other; other = -1 or an earlier rule).
+hipError_t launch_moment_chain(const double *G, int64_t m, int b, int na, const int *rules, int nrules, double scale0,
+                               double scale1, double *M, int *bad, hipStream_t s);
 // out (m x m, m = npan b) block (p, q) = scale (M_{x+y} + M_{|x-y|}) / 2 from the moment slots.
 hipError_t launch_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int npan,
                                 double scale, double *out, int64_t ld, hipStream_t s);

@@ -1076,6 +1076,38 @@ hipError_t launch_tall_gram(const double *X, int64_t ldx, int bx, const double *
   return hipGetLastError();
 }
 
+// Moments from the anchors' Gram products (see anchor_projection): thread (part, i, j) walks the
+// derivation rules in order; rule c takes block (part na + ai, q) of the Gram product G (row-major,
+// row stride m) scaled by scale[part], and gives M_c[i][j] = s G[.][.] (other < 0) or
+// 2 s G[.][.] - M_other[i][j].  A thread reads only the entries it wrote itself.  bad is set to 1
+// when a moment is not finite.
+__global__ void k_moment_chain(const double *G, int64_t m, int b, int na, const int *rules, int nrules, double scale0,
+                               double scale1, double *M, int *bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int bb = b * b;
+  if (t >= 2 * bb) return;
+  const int part = t / bb, i = (t - part * bb) / b, j = t - part * bb - i * b;
+  const double sc = part == 0 ? scale0 : scale1;
+  double *Mp = M + static_cast<int64_t>(part) * nrules * bb;
+  bool finite = true;
+  for (int c = 0; c < nrules; ++c) {
+    const int ai = rules[3 * c], q = rules[3 * c + 1], o = rules[3 * c + 2];
+    const double g = sc * G[static_cast<int64_t>((part * na + ai) * b + i) * m + static_cast<int64_t>(q) * b + j];
+    const double v = o < 0 ? g : 2.0 * g - Mp[static_cast<int64_t>(o) * bb + i * b + j];
+    Mp[static_cast<int64_t>(c) * bb + i * b + j] = v;
+    finite = finite && isfinite(v);
+  }
+  if (!finite) *bad = 1;
+}
+
+hipError_t launch_moment_chain(const double *G, int64_t m, int b, int na, const int *rules, int nrules, double scale0,
+                               double scale1, double *M, int *bad, hipStream_t s) {
+  const int n = 2 * b * b;
+  hipLaunchKernelGGL(k_moment_chain, dim3((n + 255) / 256), dim3(256), 0, s, G, m, b, na, rules, nrules, scale0,
+                     scale1, M, bad);
+  return hipGetLastError();
+}
+
 // out block (p, q) = scale (M_{x+y} + M_{|x-y|}) / 2, x, y the orders of panels p, q, M_k the b x b
 // moment in slot idx_of[k] of mu (the product identity T_x T_y = (T_{x+y} + T_{|x-y|}) / 2).
 __global__ void k_gram_assemble(const double *mu, const int *idx_of, const int64_t *orders, int b, int m, double scale,
