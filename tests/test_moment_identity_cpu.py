@@ -16,6 +16,7 @@ import pytest
 from oracle import chebyshev, hamiltonian, subspace
 from paper_2011_02107_amd import inputs
 
+
 def _anchors(kn):
     return sorted({k for k in (0, 1, 2, kn - 2, kn - 1, kn, kn + 1) if k >= 0})
 
