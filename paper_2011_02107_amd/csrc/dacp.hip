@@ -1193,7 +1193,7 @@ dacp_status moment_ritz_vectors(dacp_ctx ctx, dacp_ham h, const dacp_basis_param
 
 // Stored basis with moment projection (App. C, Eq. shift): the panels of the uniform grid are
 // stored in V as by the evolution basis, and S and P are assembled from b x b moments, but the moments
-// come from Gram products of a few anchor panels with V instead of an evolution to 2 k_n + 1.  For
+// come from Gram products of a few anchor panels with V instead of an evolution to 2 k_n.  For
 // an anchor T_A psi and a panel T_x psi (G = H / e_bound),
 //   (T_A psi)^T (T_x psi)   = (mu_{A+x} + mu_{|A-x|}) / 2,  mu_k = psi^T T_k(G) psi,
 //   (H T_A psi)^T (T_x psi) = e_bound (nu_{A+x} + nu_{|A-x|}) / 2,  nu_k = psi^T G T_k(G) psi,
@@ -2356,7 +2356,7 @@ dacp_status finish_projected(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o
 }
 
 // One attempt in moment mode (App. C, Eq. shift), after the filter: moments during an evolution to
-// 2 k_n + 1 and S, P from them; the subspace solve; the candidates' Ritz vectors from a second
+// 2 k_n and S, P from them; the subspace solve; the candidates' Ritz vectors from a second
 // evolution to k_n (no basis stored); then the acceptance on those vectors.  The evolution times
 // of both passes go to t_evol_ms (S and P come out of the first), t_project_ms stays 0.
 dacp_status moment_attempt(dacp_ctx ctx, dacp_ham h, int N, const dacp_opts &o, const dacp_basis_params &bp,
