@@ -36,6 +36,7 @@ using dacp::BatchSpec;
 using dacp::rules::AcceptResult;
 using dacp::rules::Plan;
 using dacp::rules::accept_rule;
+using dacp::rules::anchor_orders;
 using dacp::rules::central_order;
 using dacp::rules::kpm_count;
 using dacp::rules::make_plan;
@@ -1205,15 +1206,6 @@ dacp_status moment_ritz_vectors(dacp_ctx ctx, dacp_ham h, const dacp_basis_param
 // times smaller than the moments, and differences of neighbouring mu would lose that factor of the
 // recurrence's rounding.  The Gram products cost 2 D (14 b) m flops against 2 D m^2 for V^T V and
 // V^T (H V).
-// Anchor orders of the moment projection on the uniform grid whose last sample is k_n: 0, 1, 2 and
-// k_n - 2 .. k_n + 1, ascending and distinct.
-std::vector<int64_t> anchor_orders(int64_t kn) {
-  std::set<int64_t> a;
-  for (int64_t k : {int64_t(0), int64_t(1), int64_t(2), kn - 2, kn - 1, kn, kn + 1})
-    if (k >= 0) a.insert(k);
-  return std::vector<int64_t>(a.begin(), a.end());
-}
-
 // S and P (device m x m, row stride ld) of the panels of orders `orders` stored in V (device D x m,
 // row stride ldv) from the anchors: abuf (device D x 2 na b, row stride 2 na b) holds T_A psi of
 // anchor i = 0 .. na-1 in columns [i b, i b + b); its right half receives their images under H.
@@ -1227,7 +1219,6 @@ dacp_status anchor_projection(dacp_ctx ctx, dacp_ham h, const std::vector<int64_
   const int m = b * npan;
   const int na = static_cast<int>(anchors.size());
   const int ma = na * b;
-  const int64_t kn = orders.back();
   // images of the anchors under H, beside them
   const double tg0 = now_ms();
   for (int c0 = 0; c0 < ma; c0 += 64)
@@ -1251,68 +1242,12 @@ dacp_status anchor_projection(dacp_ctx ctx, dacp_ham h, const std::vector<int64_
                                        s));
     }
   }
-  // the orders S and P read: x + y and |x - y| over the panel orders, one slot each
-  int nslot = 0;
-  const std::vector<int> slot_of = moment_slots(orders, nslot);
-  // Which pair gives which moment: sweep the (anchor, panel) pairs until nothing new follows; a
-  // moment is derived once, from the first pair that reaches it.  mu and nu share the rules.
-  struct Rule {
-    int ai, q;
-    int64_t other;  // the moment subtracted (-1: the block is the moment itself)
-  };
-  std::unordered_map<int64_t, int> rule_of;  // order -> index into rules
-  std::vector<std::pair<int64_t, Rule>> rules;
-  for (bool changed = true; changed;) {
-    changed = false;
-    for (int ai = 0; ai < na; ++ai)
-      for (int q = 0; q < npan; ++q) {
-        const int64_t sum = anchors[ai] + orders[q];
-        const int64_t dif = anchors[ai] >= orders[q] ? anchors[ai] - orders[q] : orders[q] - anchors[ai];
-        const bool hs = rule_of.count(sum) > 0, hd = rule_of.count(dif) > 0;
-        int64_t k = -1, other = -1;
-        if (sum == dif) {
-          if (!hs) k = sum;
-        } else if (hd && !hs) {
-          k = sum;
-          other = dif;
-        } else if (hs && !hd) {
-          k = dif;
-          other = sum;
-        }
-        if (k < 0) continue;
-        rule_of[k] = static_cast<int>(rules.size());
-        rules.push_back({k, Rule{ai, q, other}});
-        changed = true;
-      }
-  }
-  // the moments the assembly reads, and the ones they are derived from
-  std::vector<char> used(rules.size(), 0);
-  for (int64_t k = 0; k <= 2 * kn; ++k) {
-    if (slot_of[k] < 0) continue;
-    auto it = rule_of.find(k);
-    if (it == rule_of.end())
-      return set_err(ctx, DACP_E_INVALID, "basis_stored_moments: moment " + std::to_string(k) + " not reachable");
-    for (int r = it->second; r >= 0 && !used[r];) {
-      used[r] = 1;
-      const int64_t o = rules[r].second.other;
-      r = o < 0 ? -1 : rule_of.at(o);
-    }
-  }
-  // the used rules in the order found (a rule's other moment comes before it), renumbered, and the
-  // block each order the assembly reads takes
-  std::vector<int> cidx(rules.size(), -1), table;
-  int nc = 0;
-  for (size_t r = 0; r < rules.size(); ++r) {
-    if (!used[r]) continue;
-    cidx[r] = nc++;
-    const Rule &ru = rules[r].second;
-    table.push_back(ru.ai);
-    table.push_back(ru.q);
-    table.push_back(ru.other < 0 ? -1 : cidx[rule_of.at(ru.other)]);
-  }
-  std::vector<int> block_of(slot_of.size(), -1);
-  for (size_t k = 0; k < slot_of.size(); ++k)
-    if (slot_of[k] >= 0) block_of[k] = cidx[rule_of.at(static_cast<int64_t>(k))];
+  // the chain of Gram blocks that gives every moment S and P read (host rule, integers only)
+  const dacp::rules::MomentChain ch = dacp::rules::moment_chain(orders, anchors);
+  if (ch.missing >= 0)
+    return set_err(ctx, DACP_E_INVALID, "basis_stored_moments: moment " + std::to_string(ch.missing) + " not reachable");
+  const std::vector<int> &table = ch.table, &block_of = ch.block_of;
+  const int nc = static_cast<int>(ch.order.size());
   // the moments on the device: mu from the anchor rows, nu from the image rows scaled by 1 / e_bound
   const size_t bb2 = static_cast<size_t>(b) * b;
   DevBuf mom, drules, dblk, dord, dbad;

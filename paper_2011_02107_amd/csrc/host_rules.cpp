@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <unordered_map>
 
 namespace dacp {
 namespace rules {
@@ -197,6 +198,80 @@ DcDeflation dc_deflate(const std::vector<double> &dv, const std::vector<double> 
   }
   for (int j = 0; j < n; ++j)
     if (!out.defl[j]) out.nd.push_back(j);
+  return out;
+}
+
+std::vector<int64_t> anchor_orders(int64_t kn) {
+  std::vector<int64_t> a;
+  for (int64_t k : {int64_t(0), int64_t(1), int64_t(2), kn - 2, kn - 1, kn, kn + 1})
+    if (k >= 0) a.push_back(k);
+  std::sort(a.begin(), a.end());
+  a.erase(std::unique(a.begin(), a.end()), a.end());
+  return a;
+}
+
+MomentChain moment_chain(const std::vector<int64_t> &orders, const std::vector<int64_t> &anchors) {
+  MomentChain out;
+  const int64_t kn = orders.back();
+  const int na = static_cast<int>(anchors.size()), npan = static_cast<int>(orders.size());
+  struct Rule {
+    int ai, q;
+    int64_t k, other;  // the moment given; the one subtracted (-1: none)
+  };
+  std::unordered_map<int64_t, int> rule_of;  // order -> index into rules
+  std::vector<Rule> rules;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (int ai = 0; ai < na; ++ai)
+      for (int q = 0; q < npan; ++q) {
+        const int64_t sum = anchors[ai] + orders[q];
+        const int64_t dif = anchors[ai] >= orders[q] ? anchors[ai] - orders[q] : orders[q] - anchors[ai];
+        const bool hs = rule_of.count(sum) > 0, hd = rule_of.count(dif) > 0;
+        int64_t k = -1, other = -1;
+        if (sum == dif) {
+          if (!hs) k = sum;
+        } else if (hd && !hs) {
+          k = sum;
+          other = dif;
+        } else if (hs && !hd) {
+          k = dif;
+          other = sum;
+        }
+        if (k < 0) continue;
+        rule_of[k] = static_cast<int>(rules.size());
+        rules.push_back({ai, q, k, other});
+        changed = true;
+      }
+  }
+  // the orders the assembly reads, and the rules they are derived from
+  std::vector<char> needed(static_cast<size_t>(2 * kn) + 1, 0), used(rules.size(), 0);
+  for (int64_t x : orders)
+    for (int64_t y : orders) needed[x + y] = needed[x >= y ? x - y : y - x] = 1;
+  for (int64_t k = 0; k <= 2 * kn; ++k) {
+    if (!needed[k]) continue;
+    auto it = rule_of.find(k);
+    if (it == rule_of.end()) {
+      out.missing = k;
+      return out;
+    }
+    for (int r = it->second; r >= 0 && !used[r];) {
+      used[r] = 1;
+      r = rules[r].other < 0 ? -1 : rule_of.at(rules[r].other);
+    }
+  }
+  std::vector<int> cidx(rules.size(), -1);
+  int nc = 0;
+  for (size_t r = 0; r < rules.size(); ++r) {
+    if (!used[r]) continue;
+    cidx[r] = nc++;
+    out.table.push_back(rules[r].ai);
+    out.table.push_back(rules[r].q);
+    out.table.push_back(rules[r].other < 0 ? -1 : cidx[rule_of.at(rules[r].other)]);
+    out.order.push_back(rules[r].k);
+  }
+  out.block_of.assign(needed.size(), -1);
+  for (size_t k = 0; k < needed.size(); ++k)
+    if (needed[k]) out.block_of[k] = cidx[rule_of.at(static_cast<int64_t>(k))];
   return out;
 }
 

@@ -103,5 +103,23 @@ struct DcPlacement {
 };
 DcPlacement dc_place(std::vector<DcEntry> ents, int k);
 
+// Moment projection from a stored basis (App. C, Eq. shift): with T_A T_x = (T_{A+x} + T_{|A-x|}) / 2,
+// the Gram block of an anchor panel of order A with a stored panel of order x gives the moment at
+// one of A + x, |A - x| once the moment at the other is known (both at once when A or x is 0).
+// Anchor orders for the uniform grid whose last sample is kn: 0, 1, 2, kn - 2 .. kn + 1, ascending
+// and distinct.
+std::vector<int64_t> anchor_orders(int64_t kn);
+// The derivation chain for panel orders `orders` (orders[0] = 0, last = kn): sweeping the (anchor,
+// panel) pairs until nothing new follows, each moment is derived once, from the first pair that
+// reaches it; only the rules that the orders x + y, |x - y| of two panel orders need (and those
+// they are derived from) are kept, in the order found, so a rule's other moment comes before it.
+struct MomentChain {
+  std::vector<int> table;           // per kept rule: anchor index, panel index, earlier rule or -1
+  std::vector<int64_t> order;       // per kept rule: the order of the moment it gives
+  std::vector<int> block_of;        // order k = 0 .. 2 kn: the kept rule giving moment k, or -1
+  int64_t missing = -1;             // an order the assembly needs that the anchors do not reach
+};
+MomentChain moment_chain(const std::vector<int64_t> &orders, const std::vector<int64_t> &anchors);
+
 }  // namespace rules
 }  // namespace dacp

@@ -1,6 +1,7 @@
 // Host-side harness of the library's host-only entry points and rules
-// (paper_2011_02107_amd/csrc/host_rules.cpp): dacp_plan, dacp_accept_rule, dacp_spacing_ratios and
-// the divide-and-conquer merge bookkeeping, on random and edge-case inputs.  Built with
+// (paper_2011_02107_amd/csrc/host_rules.cpp): dacp_plan, dacp_accept_rule, dacp_spacing_ratios, the
+// divide-and-conquer merge bookkeeping and the moment projection's derivation chain, on random and
+// edge-case inputs.  Built with
 // -fsanitize=address,undefined: any out-of-bounds access, use after free, overflow or other
 // undefined behaviour aborts the run.  The checks here are invariants of each output (sizes,
 // ranges, orderings, permutations); the values themselves are compared with the oracle elsewhere.
@@ -181,6 +182,57 @@ void deflation(std::mt19937_64 &rng) {
 }
 }  // namespace
 
+// The moment projection's derivation chain: for uniform grids of every even step to 80 and up to 40
+// sample pairs, every order x + y, |x - y| of two panel orders is reached; every kept rule's anchor
+// and panel give the order it claims (as A + x or |A - x|), with its subtracted moment, when there
+// is one, the other of the two and given by an earlier rule; orders not read get no rule.
+void moment_chains() {
+  for (int delta = 2; delta <= 80; delta += 2)
+    for (int n = 1; n <= 40; ++n) {
+      std::vector<int64_t> orders{0};
+      for (int j = 1; j <= n; ++j) {
+        orders.push_back(int64_t(j) * delta - 1);
+        orders.push_back(int64_t(j) * delta);
+      }
+      const int64_t kn = orders.back();
+      const std::vector<int64_t> anchors = dacp::rules::anchor_orders(kn);
+      check(std::is_sorted(anchors.begin(), anchors.end()) && anchors.front() == 0 && anchors.back() == kn + 1,
+            "anchor orders", n);
+      const dacp::rules::MomentChain ch = dacp::rules::moment_chain(orders, anchors);
+      check(ch.missing < 0, "moment chain: an order is not reached", delta * 100 + n);
+      const int nc = static_cast<int>(ch.order.size());
+      check(ch.table.size() == static_cast<size_t>(3 * nc), "moment chain: table size", nc);
+      check(ch.block_of.size() == static_cast<size_t>(2 * kn + 1), "moment chain: block map size", n);
+      for (int c = 0; c < nc; ++c) {
+        const int ai = ch.table[3 * c], q = ch.table[3 * c + 1], o = ch.table[3 * c + 2];
+        if (ai < 0 || ai >= static_cast<int>(anchors.size()) || q < 0 || q >= static_cast<int>(orders.size()) ||
+            o >= c) {
+          check(false, "moment chain: rule out of range", c);
+          continue;
+        }
+        const int64_t sum = anchors[ai] + orders[q];
+        const int64_t dif = anchors[ai] >= orders[q] ? anchors[ai] - orders[q] : orders[q] - anchors[ai];
+        const int64_t k = ch.order[c];
+        if (o < 0) {
+          check(sum == dif && k == sum, "moment chain: direct rule", c);
+        } else {
+          const int64_t ko = ch.order[o];
+          check((k == sum && ko == dif) || (k == dif && ko == sum), "moment chain: derived rule", c);
+        }
+      }
+      std::vector<char> needed(static_cast<size_t>(2 * kn) + 1, 0);
+      for (int64_t x : orders)
+        for (int64_t y : orders) needed[x + y] = needed[x >= y ? x - y : y - x] = 1;
+      for (int64_t k = 0; k <= 2 * kn; ++k) {
+        const int blk = ch.block_of[k];
+        if (needed[k])
+          check(blk >= 0 && blk < nc && ch.order[blk] == k, "moment chain: needed order's block", k);
+        else
+          check(blk == -1, "moment chain: unneeded order has a block", k);
+      }
+    }
+}
+
 int main() {
   std::mt19937_64 rng(20111);
   plans(rng);
@@ -188,6 +240,7 @@ int main() {
   spacing(rng);
   clusters(rng);
   deflation(rng);
+  moment_chains();
   std::printf("host rules harness: %d failures\n", g_fail);
   return g_fail == 0 ? 0 : 1;
 }
