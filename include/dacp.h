@@ -257,8 +257,8 @@ dacp_status dacp_basis_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params
  * The evolution runs to k_n + 1; the Gram products are 2 D (14 b) m flops, in place of the 2 D m^2
  * of V^T V and V^T (H V).  psi_e: device [D][b] FP64, 1 <= b <= 128.  S, P: device m x m, row
  * stride ld >= m, both triangles written (symmetric parts).  m_out (host, may be NULL) gets m.
- * Memory besides V, S and P: three D x g FP64 blocks, the anchors and their images (D x 14b FP64)
- * and the Gram products.  Errors as dacp_basis (DACP_E_BOUNDS when |T_{k_m}(G) psi| exceeds |psi|,
+ * Memory besides V, S and P: three D x g FP64 blocks, the anchors and their images (D x 14b FP64),
+ * their Gram product with V (14b x m FP64) and the derived moments (at most 2 (2 k_n + 1) b^2 FP64).  Errors as dacp_basis (DACP_E_BOUNDS when |T_{k_m}(G) psi| exceeds |psi|,
  * DACP_E_NUMERIC for a non-finite state or moment). */
 dacp_status dacp_basis_stored_moments(dacp_ctx ctx, dacp_ham h, const dacp_basis_params *p, const double *psi_e,
                                       double *V, int64_t ldv, double *S, double *P, int64_t ld, int *m_out);
